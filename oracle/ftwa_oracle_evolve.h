@@ -1,0 +1,189 @@
+/*
+ * ftwa_oracle_evolve.h -- body of the oracle's equation of motion and
+ * Runge-Kutta loop, included twice by ftwa_oracle.c (ORC_REAL = double, then
+ * float).  Test infrastructure only; see ftwa_oracle.c.
+ *
+ * A trajectory is rho[spin][i][j] (full N x N complex, interleaved re/im).
+ */
+#define ORC_CAT2(a, b) a##b
+#define ORC_CAT(a, b) ORC_CAT2(a, b)
+#define ORC_NAME(base) ORC_CAT(base, ORC_SUFFIX)
+
+/*
+ * Right-hand side of the fTWA equation of motion, Sec. III, Eq. (5), with
+ * j_ij = t on bonds and u_ij = U delta_ij (Sec. II):
+ *
+ *   d rho_ij,s / dt = i [ t ( sum_{k in nb(j)} rho_ik,s - sum_{k in nb(i)} rho_kj,s )
+ *                         + U ( rho_ii,sbar - rho_jj,sbar ) rho_ij,s ]
+ *
+ * (the 1/2 of (rho_kk + 1/2) cancels between the two u terms).  Evaluation
+ * order: each neighbour sum starts from the first (smallest) neighbour and
+ * adds the others in ascending order; g = t*(col - row); then
+ * a = U*(d_i - d_j) is applied with one fma per component; f = i*g.
+ */
+void ORC_NAME(oracle_rhs)(int N, const int32_t* nbr, const uint8_t* deg,
+                          ORC_REAL t, ORC_REAL U, const ORC_REAL* rho, ORC_REAL* f)
+{
+    const size_t NN2 = (size_t)N * N * 2;
+    for (int s = 0; s < 2; ++s) {
+        const ORC_REAL* R = rho + s * NN2;
+        const ORC_REAL* Rbar = rho + (1 - s) * NN2;
+        ORC_REAL* F = f + s * NN2;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                ORC_REAL col_re = 0, col_im = 0, row_re = 0, row_im = 0;
+                for (int n = 0; n < deg[j]; ++n) {
+                    int k = nbr[j * ORC_MAXDEG + n];
+                    if (n == 0) {
+                        col_re = R[2 * (i * N + k)];
+                        col_im = R[2 * (i * N + k) + 1];
+                    } else {
+                        col_re = col_re + R[2 * (i * N + k)];
+                        col_im = col_im + R[2 * (i * N + k) + 1];
+                    }
+                }
+                for (int n = 0; n < deg[i]; ++n) {
+                    int k = nbr[i * ORC_MAXDEG + n];
+                    if (n == 0) {
+                        row_re = R[2 * (k * N + j)];
+                        row_im = R[2 * (k * N + j) + 1];
+                    } else {
+                        row_re = row_re + R[2 * (k * N + j)];
+                        row_im = row_im + R[2 * (k * N + j) + 1];
+                    }
+                }
+                ORC_REAL g_re = t * (col_re - row_re);
+                ORC_REAL g_im = t * (col_im - row_im);
+                ORC_REAL a = U * (Rbar[2 * (i * N + i)] - Rbar[2 * (j * N + j)]);
+                g_re = ORC_FMA(a, R[2 * (i * N + j)], g_re);
+                g_im = ORC_FMA(a, R[2 * (i * N + j) + 1], g_im);
+                F[2 * (i * N + j)] = -g_im; /* f = i * g */
+                F[2 * (i * N + j) + 1] = g_re;
+            }
+    }
+}
+
+/*
+ * Per-trajectory quantities conserved by the exact flow (used as checks):
+ *   inv[0], inv[1]: trace of rho_up, rho_down;
+ *   inv[2]: Weyl Hamiltonian, Appendix A.3, Eq. (A9):
+ *           H_W = - sum_{ij s} j_ij rho_ij,s + U sum_i (rho_ii,up + 1/2)(rho_ii,dn + 1/2);
+ *   inv[3], inv[4]: squared Frobenius norm of rho_up, rho_down.
+ * Accumulated in FP64 in plain row-major order.
+ */
+static void ORC_NAME(invariants)(int N, const int32_t* nbr, const uint8_t* deg,
+                                 double t, double U, const ORC_REAL* rho, double* inv)
+{
+    const size_t NN2 = (size_t)N * N * 2;
+    double hop = 0.0, inter = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        const ORC_REAL* R = rho + s * NN2;
+        double tr = 0.0, fro = 0.0;
+        for (int i = 0; i < N; ++i) {
+            tr += (double)R[2 * (i * N + i)];
+            for (int j = 0; j < N; ++j) {
+                double re = (double)R[2 * (i * N + j)], im = (double)R[2 * (i * N + j) + 1];
+                fro += re * re + im * im;
+            }
+            for (int n = 0; n < deg[i]; ++n) {
+                int k = nbr[i * ORC_MAXDEG + n];
+                hop += (double)R[2 * (i * N + k)];
+            }
+        }
+        inv[s] = tr;
+        inv[3 + s] = fro;
+    }
+    for (int i = 0; i < N; ++i)
+        inter += ((double)rho[2 * (i * N + i)] + 0.5) * ((double)rho[NN2 + 2 * (i * N + i)] + 0.5);
+    inv[2] = -t * hop + U * inter;
+}
+
+/*
+ * Classical fourth-order Runge-Kutta for every trajectory (the paper does not
+ * name its integrator).  With h = dt:
+ *   k1 = f(y);  Y2 = y + (h/2) k1;  k2 = f(Y2);  Y3 = y + (h/2) k2;
+ *   k3 = f(Y3); Y4 = y + h k3;      k4 = f(Y4);
+ *   y <- y + (h/6) (k1 + 2 k2 + 2 k3 + k4).
+ * Evaluation order: Y = fma(c, k, y); acc = k1; acc = fma(2, k2, acc);
+ * acc = fma(2, k3, acc); acc = acc + k4; y = fma(h/6, acc, y).
+ * The coefficients h/2, h, h/6 are formed in FP64 and rounded once to the
+ * working precision.
+ *
+ * rho: [M][2][N][N] complex FP64 in/out (rounded to the working precision on
+ * entry).  Records are taken at steps 0, record_every, 2 record_every, ...:
+ *   X[r][m][s*N + i] = rho_ii,s (FP64), inv[r][m][0..4] (see invariants).
+ */
+int ORC_NAME(oracle_evolve)(int N, const int32_t* nbr, const uint8_t* deg,
+                            double t, double U, double dt, int64_t n_steps,
+                            int record_every, int64_t M, double* rho_io,
+                            double* X, double* inv)
+{
+    if (N <= 0 || M < 0 || n_steps < 0 || record_every <= 0) return -1;
+    const size_t E = (size_t)2 * N * N * 2; /* reals per trajectory */
+    const int64_t n_rec = n_steps / record_every + 1;
+    const int D = 2 * N;
+    const ORC_REAL tw = (ORC_REAL)t, Uw = (ORC_REAL)U;
+    const ORC_REAL c_half = (ORC_REAL)(0.5 * dt), c_full = (ORC_REAL)dt;
+    const ORC_REAL c_sixth = (ORC_REAL)(dt / 6.0), two = (ORC_REAL)2;
+    int failed = 0;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        ORC_REAL* y = (ORC_REAL*)malloc(sizeof(ORC_REAL) * E);
+        ORC_REAL* Y = (ORC_REAL*)malloc(sizeof(ORC_REAL) * E);
+        ORC_REAL* k = (ORC_REAL*)malloc(sizeof(ORC_REAL) * E);
+        ORC_REAL* acc = (ORC_REAL*)malloc(sizeof(ORC_REAL) * E);
+        if (!y || !Y || !k || !acc) {
+            failed = 1;
+        } else {
+            double* src = rho_io + (size_t)m * E;
+            for (size_t e = 0; e < E; ++e) y[e] = (ORC_REAL)src[e];
+            int64_t r = 0;
+            for (int64_t step = 0; step <= n_steps; ++step) {
+                if (step % record_every == 0) {
+                    if (X)
+                        for (int s = 0; s < 2; ++s)
+                            for (int i = 0; i < N; ++i)
+                                X[((size_t)r * M + m) * D + s * N + i] =
+                                    (double)y[s * N * N * 2 + 2 * (i * N + i)];
+                    if (inv)
+                        ORC_NAME(invariants)(N, nbr, deg, t, U, y,
+                                             inv + ((size_t)r * M + m) * 5);
+                    ++r;
+                }
+                if (step == n_steps) break;
+                /* stage 1 */
+                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, y, k);
+                for (size_t e = 0; e < E; ++e) {
+                    acc[e] = k[e];
+                    Y[e] = ORC_FMA(c_half, k[e], y[e]);
+                }
+                /* stage 2 */
+                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, Y, k);
+                for (size_t e = 0; e < E; ++e) {
+                    acc[e] = ORC_FMA(two, k[e], acc[e]);
+                    Y[e] = ORC_FMA(c_half, k[e], y[e]);
+                }
+                /* stage 3 */
+                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, Y, k);
+                for (size_t e = 0; e < E; ++e) {
+                    acc[e] = ORC_FMA(two, k[e], acc[e]);
+                    Y[e] = ORC_FMA(c_full, k[e], y[e]);
+                }
+                /* stage 4 */
+                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, Y, k);
+                for (size_t e = 0; e < E; ++e) {
+                    acc[e] = acc[e] + k[e];
+                    y[e] = ORC_FMA(c_sixth, acc[e], y[e]);
+                }
+            }
+            (void)n_rec;
+            for (size_t e = 0; e < E; ++e) src[e] = (double)y[e];
+        }
+        free(y); free(Y); free(k); free(acc);
+    }
+    return failed ? -2 : 0;
+}
+
+#undef ORC_NAME
+#undef ORC_CAT
+#undef ORC_CAT2
