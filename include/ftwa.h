@@ -1,0 +1,249 @@
+/*
+ * ftwa.h -- C ABI of libftwa, the MI355X (gfx950) implementation of the
+ * fermionic Truncated Wigner Approximation (fTWA) hot path for the
+ * Fermi-Hubbard model on honeycomb (graphene) lattices.
+ *
+ * Paper: F. Rousse, O. Eriksson, M. Ogren, "Correlated quantum dynamics of
+ * graphene", arXiv:2212.04352.  The library computes, on the GPU:
+ *   1. Gaussian initial phase-space points rho(0) around a Fock state
+ *      (Sec. III, Eq. (6));
+ *   2. trajectories of the fTWA equation of motion (Sec. III, Eq. (5)) with
+ *      nearest-neighbour hopping t and on-site U (Sec. II, Eq. (1)),
+ *      integrated with the classical fourth-order Runge-Kutta method;
+ *   3. FP64 ensemble moments of the diagonal variables, giving the site
+ *      occupations (Eq. (4)), connected density-density correlations and g2
+ *      (Eq. (8)).
+ *
+ * General rules for every entry point:
+ *   - Return value: FTWA_OK (0) or a negative ftwa_status.  Nothing throws
+ *     across the ABI.  ftwa_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - Arguments are validated on the host before any device work is queued;
+ *     on an argument error nothing is launched and outputs are untouched.
+ *   - "device" pointers are HIP device allocations owned by the caller; the
+ *     library never frees them.  "host" pointers are ordinary memory.
+ *   - Device work is queued asynchronously on `stream` (a hipStream_t; NULL
+ *     means the default stream) of the current HIP device.  The caller
+ *     synchronises before reading outputs.
+ *   - The library allocates device memory only for a lattice's small index
+ *     tables (once per lattice and device, freed by ftwa_free_lattice).
+ *     Scratch memory comes from the caller through `workspace`.
+ *
+ * Data layout of the phase-space state ("packed layout"):
+ *   For N sites, one spin block is Hermitian, so only its upper triangle
+ *   i <= j is stored: P = N(N+1)/2 complex elements, element (i, j) at
+ *   p(i, j) = i*N - i*(i-1)/2 + (j - i).  The trajectory index is innermost:
+ *     rho[((s * P + p(i, j)) * n_traj + m)]   (s = 0 up, 1 down)
+ *   each entry a complex number stored as (re, im) -- two doubles for
+ *   FTWA_F64, two floats for FTWA_F32.  Diagonal entries are real (im = 0).
+ *   rho_ji = conj(rho_ij) is implied.
+ */
+#ifndef FTWA_H
+#define FTWA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FTWA_OK = 0,
+    FTWA_EINVAL = -1,      /* invalid argument (detected on the host)          */
+    FTWA_ENOMEM = -2,      /* host or device allocation failed                 */
+    FTWA_EHIP = -3,        /* a HIP runtime call or kernel launch failed       */
+    FTWA_ENOTSUP = -4,     /* valid request this build does not support        */
+    FTWA_ENONFINITE = -5,  /* a trajectory became non-finite (NaN or Inf)      */
+    FTWA_ETIMEOUT = -6     /* a cooperative kernel gave up waiting (bounded)   */
+} ftwa_status;
+
+typedef enum {
+    FTWA_TORUS = 0,          /* a x b honeycomb unit cells, periodic; N = 2ab  */
+    FTWA_ARMCHAIR_RECT = 1,  /* a x b brick-wall rectangle, degree-<2 sites
+                                trimmed (10 x 20 gives the 198-site flake)     */
+    FTWA_HEX_ZIGZAG = 2      /* zigzag hexagonal flake of a rings, N = 6 a^2  */
+} ftwa_lattice_kind;
+
+typedef enum { FTWA_F64 = 0, FTWA_F32 = 1 } ftwa_dtype;
+
+typedef enum {
+    FTWA_START_NEEL = 0,     /* up electrons on sublattice A, down on B        */
+    FTWA_START_RANDOM = 1    /* seeded random half filling, one electron/site */
+} ftwa_start;
+
+typedef struct ftwa_lattice_s* ftwa_lattice;
+
+/* ---------------------------------------------------------------- lattice */
+
+/*
+ * ftwa_build_lattice -- nearest-neighbour honeycomb graph with uniform
+ * hopping t_hop on every bond (Sec. II: j_ij = J for neighbours, u_ij = U
+ * delta_ij).  Geometries (the paper's own exist only in its figures):
+ *   FTWA_TORUS (a, b >= 2): site 2*(x*b + y) + s; A(x,y) is bonded to
+ *     B(x,y), B(x-1,y), B(x,y-1), indices modulo a and b.
+ *   FTWA_ARMCHAIR_RECT (a rows, b columns, both >= 2): sites (r, c);
+ *     bonds (r,c)-(r,c+1) and, when r + c is even, (r,c)-(r+1,c); sites of
+ *     degree < 2 are removed repeatedly; survivors numbered row by row.
+ *   FTWA_HEX_ZIGZAG (a >= 1 rings, b ignored): hexagons within hex distance
+ *     a-1 of a centre hexagon on the same brick wall, sites numbered by
+ *     (row, column).
+ * Sublattice of site (r, c) is (r + c) mod 2 (torus: s).  Neighbour lists
+ * are ascending.  N must be <= 255 (the kernels index sites in 8 bits).
+ * out: receives a handle owned by the caller, released with
+ * ftwa_free_lattice.  Errors: FTWA_EINVAL for bad sizes or N > 255.
+ */
+ftwa_status ftwa_build_lattice(ftwa_lattice_kind kind, int a, int b, double t_hop,
+                               ftwa_lattice* out);
+
+/*
+ * ftwa_build_lattice_bonds -- any graph of degree <= 3 from an explicit bond
+ * list (host arrays): bonds[2*k], bonds[2*k+1] are the sites of bond k,
+ * sublattice[i] in {0, 1} (only used by FTWA_START_NEEL).  Duplicate bonds,
+ * self bonds, degree > 3 or N > 255 give FTWA_EINVAL.
+ */
+ftwa_status ftwa_build_lattice_bonds(int n_sites, int n_bonds, const int32_t* bonds,
+                                     const uint8_t* sublattice, double t_hop,
+                                     ftwa_lattice* out);
+
+/*
+ * ftwa_lattice_info -- read-only views of the host tables: nbr[N][3]
+ * (ascending, padded with -1), deg[N], sublattice[N].  The pointers stay
+ * valid until ftwa_free_lattice.  Any output pointer may be NULL.
+ */
+ftwa_status ftwa_lattice_info(ftwa_lattice lat, int* n_sites, int* n_bonds,
+                              const int32_t** nbr, const uint8_t** deg,
+                              const uint8_t** sublattice);
+
+/* ftwa_free_lattice -- releases host and device tables; NULL is a no-op. */
+void ftwa_free_lattice(ftwa_lattice lat);
+
+/*
+ * ftwa_fock_start -- initial occupations of a Fock state with one electron on
+ * every site (Sec. IV.A), written to host n0_host[2][N] (0.0 or 1.0).
+ * FTWA_START_RANDOM: Fisher-Yates permutation of the sites, swap partner of
+ * position i drawn as floor(a (i+1) / 2^53) from the 53-bit integer a of
+ * Philox4x32-10 counter (i, instance, 0, 1), key = seed; the first N/2 sites
+ * of the permutation get an up electron.  Requires even N.
+ */
+ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
+                            uint32_t instance, double* n0_host);
+
+/* ---------------------------------------------------------------- problem */
+
+/*
+ * One problem instance.  All pointers are device pointers owned by the
+ * caller; N = number of sites of `lat`, D = 2N,
+ * n_rec = n_steps / record_every + 1 records (steps 0, record_every, ...).
+ *   n0   [2][N] FP64     initial occupations n_{i s}(0) (may be fractional)
+ *   rho  packed layout (see top of file), n_traj trajectories, in/out
+ *   S1   [n_rec][D] FP64              sum_m x_m[a],       x_m[s*N+i] = rho_ii,s
+ *   S2   [n_rec][D(D+1)/2] FP64       sum_m x_m[a] x_m[b], a <= b, packed as
+ *                                     a*D - a*(a-1)/2 + (b-a)
+ *   inv  [n_rec][4] FP64 or NULL      per record, maximum over trajectories of
+ *        |tr rho_s(t) - tr rho_s(0)| (max over s), |H_W(t) - H_W(0)| (Weyl
+ *        Hamiltonian, Appendix A.3), | |rho|_F^2(t) - |rho|_F^2(0) | (max over
+ *        s), and the count of non-finite trajectories.
+ * Trajectory m of the instance has global index traj_offset + m; it keys the
+ * random numbers, so any trajectory range reproduces the same trajectories.
+ * `instance` enters the random-number counter (distinct streams per instance
+ * of a batch).
+ */
+typedef struct {
+    ftwa_lattice lat;
+    double U;
+    int64_t n_traj;
+    int64_t traj_offset;
+    uint32_t instance;
+    const double* n0;
+    void* rho;
+    double* S1;
+    double* S2;
+    double* inv;
+} ftwa_instance;
+
+/*
+ * ftwa_sample -- writes rho(0) of every trajectory of every instance
+ * (Eq. (6)): rho_ii = n_i - 1/2; for i < j,
+ *   rho_ij = xi_ij sqrt((n_i + n_j - 2 n_i n_j) / 2),
+ * xi complex normal (E|xi|^2 = 1, E xi^2 = 0) by Box-Muller from two 53-bit
+ * uniforms of Philox4x32-10 with counter
+ *   (i*N - i(i+1)/2 + j-i-1, instance<<1 | s, traj_offset + m, 0), key = seed:
+ *   u1 = (a+1) 2^-53, u2 = b 2^-53, xi = sqrt(-ln u1) exp(2 pi i u2).
+ * The noise is drawn in FP64; FTWA_F32 stores the FP64 values rounded.
+ */
+ftwa_status ftwa_sample(const ftwa_instance* inst, int n_inst, uint64_t seed,
+                        ftwa_dtype dtype, void* stream);
+
+/* Tuning of ftwa_evolve; pass NULL for the automatic choice. */
+typedef enum {
+    FTWA_PATH_AUTO = 0,
+    FTWA_PATH_STREAM = 1,    /* state in HBM, one launch per Runge-Kutta stage */
+    FTWA_PATH_RESIDENT = 2   /* state held on chip for the whole horizon       */
+} ftwa_path;
+
+typedef struct {
+    ftwa_path path;
+    int traj_chunk;          /* trajectories per pass (0 = automatic)         */
+} ftwa_tuning;
+
+/*
+ * ftwa_evolve_workspace_size -- bytes of device scratch ftwa_evolve needs for
+ * these arguments (written to *bytes).
+ */
+ftwa_status ftwa_evolve_workspace_size(const ftwa_instance* inst, int n_inst,
+                                       int64_t n_steps, int record_every,
+                                       ftwa_dtype dtype, const ftwa_tuning* tune,
+                                       size_t* bytes);
+
+/*
+ * ftwa_evolve -- integrates every trajectory of every instance for n_steps
+ * steps of size dt with classical RK4 applied to Eq. (5):
+ *   d rho_ij,s/dt = i [ t (sum_{k in nb(j)} rho_ik,s - sum_{k in nb(i)} rho_kj,s)
+ *                       + U (rho_ii,sbar - rho_jj,sbar) rho_ij,s ],
+ * overwriting rho with rho(n_steps dt), and fills S1/S2 (zeroed first) and
+ * inv (if not NULL) at every record.  Arithmetic (FP32 or FP64 per dtype)
+ * follows a fixed order -- neighbour sums in ascending order,
+ * g = t (col - row), one fma per component for the U term, f = i g,
+ * stage inputs fma(c, k, y), acc = k1, fma(2, k2, acc), fma(2, k3, acc),
+ * acc + k4, y = fma(dt/6, acc, y) -- so results do not depend on the kernel
+ * path, the tiling or the batch composition.  S1/S2 are always FP64.
+ * workspace: device scratch of at least ftwa_evolve_workspace_size bytes.
+ * Errors: FTWA_EINVAL (sizes, NULL pointers, workspace too small),
+ * FTWA_ENONFINITE if a trajectory became non-finite (reported after the
+ * run; inv counts them), FTWA_EHIP on launch failure.
+ */
+ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
+                        int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * ftwa_observables -- ensemble observables from the moments of M
+ * trajectories (device pointers), plug-in estimators with divisor M:
+ *   n_out [n_rec][D]      n_a = S1_a/M + 1/2                          (Eq. (4))
+ *   C_out [n_rec][D][D]   C_ab = S2_ab/M - (S1_a/M)(S1_b/M)
+ *   g2_out[n_rec][D][D]   (S2_ab/M + (S1_a+S1_b)/(2M) + 1/4)
+ *                         / ((S1_a/M + 1/2)(S1_b/M + 1/2))            (Eq. (8))
+ * with a = s*N + i.  The a = b entries of C and g2 are Weyl-symbol
+ * variances, not same-site observables.  C_out and g2_out may be NULL.
+ */
+ftwa_status ftwa_observables(int n_sites, int64_t M, int n_rec, const double* S1,
+                             const double* S2, double* n_out, double* C_out,
+                             double* g2_out, void* stream);
+
+/*
+ * ftwa_unpack -- expands packed rho (n_traj trajectories) into full matrices
+ * out[m][s][i][j] (complex, same precision as dtype), filling i > j with
+ * conjugates.  Device pointers.
+ */
+ftwa_status ftwa_unpack(int n_sites, int64_t n_traj, ftwa_dtype dtype, const void* rho,
+                        void* out, void* stream);
+
+/* ftwa_last_error -- message for the calling thread's last non-OK status. */
+const char* ftwa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTWA_H */

@@ -1,0 +1,136 @@
+"""MI355X (gfx950) fTWA hot path: Gaussian sampling of the one-body phase-space
+matrix around a Fock state, RK4 trajectories of the fTWA equation of motion on
+honeycomb lattices, and FP64 ensemble moments -> occupations, connected
+density-density correlations and g2.
+
+Paper: Rousse, Eriksson, Ogren, "Correlated quantum dynamics of graphene",
+arXiv:2212.04352 (Sec. III, Eqs. (4)-(6) and (8)).
+
+All computation runs in the HIP library libftwa.so (include/ftwa.h); this
+package marshals torch tensors (device memory, streams) into it.  Importing
+works without a GPU; calls that queue device work need one.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+from ._binding import (DTYPE, FtwaError, ftwa_build_lattice, ftwa_build_lattice_bonds,  # noqa: F401
+                       ftwa_evolve, ftwa_evolve_workspace_size, ftwa_fock_start, ftwa_free_lattice,
+                       ftwa_lattice_info, ftwa_last_error, ftwa_observables, ftwa_sample,
+                       ftwa_unpack, load)
+
+
+def packed_count(N: int) -> int:
+    return N * (N + 1) // 2
+
+
+def n_records(n_steps: int, record_every: int) -> int:
+    return n_steps // record_every + 1
+
+
+class Lattice:
+    """Owns an ftwa_lattice handle."""
+
+    def __init__(self, kind: str, a: int, b: int = 0, t: float = 1.0, *, bonds=None,
+                 sublattice=None, n_sites: int = 0):
+        if kind == "custom":
+            self.handle = ftwa_build_lattice_bonds(n_sites, bonds, sublattice, t)
+        else:
+            self.handle = ftwa_build_lattice(kind, a, b, t)
+        self.kind, self.a, self.b, self.t = kind, a, b, float(t)
+        self.N, self.n_bonds, self.nbr, self.deg, self.sub = ftwa_lattice_info(self.handle)
+
+    def fock_start(self, kind: str = "neel", seed: int = 0, instance: int = 0):
+        return ftwa_fock_start(self.handle, kind, seed, instance)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            ftwa_free_lattice(h)
+            self.handle = None
+
+
+@dataclass
+class Problem:
+    """Device buffers of one instance (torch tensors on the current GPU)."""
+    lat: Lattice
+    U: float
+    n_traj: int
+    dtype: str
+    n0: object
+    rho: object
+    S1: object = None
+    S2: object = None
+    traj_offset: int = 0
+    instance: int = 0
+
+    @classmethod
+    def allocate(cls, lat: Lattice, U: float, n_traj: int, n0, dtype: str = "f64",
+                 traj_offset: int = 0, instance: int = 0, device=None):
+        import torch
+        cdt = torch.complex128 if dtype == "f64" else torch.complex64
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        n0_t = torch.as_tensor(n0, dtype=torch.float64).reshape(2, lat.N).to(dev).contiguous()
+        rho = torch.empty((2, packed_count(lat.N), n_traj), dtype=cdt, device=dev)
+        return cls(lat, float(U), int(n_traj), dtype, n0_t, rho, traj_offset=traj_offset,
+                   instance=instance)
+
+    def desc(self):
+        return {"lat": self.lat.handle, "U": self.U, "n_traj": self.n_traj,
+                "traj_offset": self.traj_offset, "instance": self.instance, "n0": self.n0,
+                "rho": self.rho, "S1": self.S1, "S2": self.S2}
+
+    def ensure_moments(self, n_rec: int):
+        import torch
+        D = 2 * self.lat.N
+        if self.S1 is None or self.S1.shape[0] != n_rec:
+            self.S1 = torch.empty((n_rec, D), dtype=torch.float64, device=self.rho.device)
+            self.S2 = torch.empty((n_rec, D * (D + 1) // 2), dtype=torch.float64,
+                                  device=self.rho.device)
+
+
+def sample(problems, seed: int, stream=None) -> None:
+    problems = problems if isinstance(problems, (list, tuple)) else [problems]
+    dt = problems[0].dtype
+    ftwa_sample([p.desc() for p in problems], seed, dt, stream)
+
+
+def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str = "auto",
+           traj_chunk: int = 0, workspace=None, stream=None):
+    """Runs ftwa_evolve; allocates the workspace as a torch tensor unless given."""
+    import torch
+    problems = problems if isinstance(problems, (list, tuple)) else [problems]
+    dtype = problems[0].dtype
+    n_rec = n_records(n_steps, record_every)
+    for p in problems:
+        p.ensure_moments(n_rec)
+    descs = [p.desc() for p in problems]
+    nbytes = ftwa_evolve_workspace_size(descs, n_steps, record_every, dtype, path, traj_chunk)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=problems[0].rho.device)
+    ftwa_evolve(descs, dt, n_steps, record_every, dtype, workspace, path, traj_chunk, stream)
+    return workspace
+
+
+def observables(problem: Problem, n_total: int = None, stream=None):
+    """(n [n_rec, 2N], C [n_rec, 2N, 2N], g2 [n_rec, 2N, 2N]) on the device."""
+    import torch
+    N = problem.lat.N
+    D = 2 * N
+    n_rec = problem.S1.shape[0]
+    M = problem.n_traj if n_total is None else n_total
+    dev = problem.S1.device
+    n = torch.empty((n_rec, D), dtype=torch.float64, device=dev)
+    C = torch.empty((n_rec, D, D), dtype=torch.float64, device=dev)
+    g2 = torch.empty((n_rec, D, D), dtype=torch.float64, device=dev)
+    ftwa_observables(N, M, n_rec, problem.S1, problem.S2, n, C, g2, stream)
+    return n, C, g2
+
+
+def unpack(problem: Problem, stream=None):
+    """Full matrices [n_traj, 2, N, N] complex of the packed state."""
+    import torch
+    N = problem.lat.N
+    out = torch.empty((problem.n_traj, 2, N, N), dtype=problem.rho.dtype, device=problem.rho.device)
+    ftwa_unpack(N, problem.n_traj, problem.dtype, problem.rho, out, stream)
+    return out

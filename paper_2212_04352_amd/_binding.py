@@ -1,0 +1,210 @@
+"""ctypes binding of libftwa (include/ftwa.h): the same entry points under the
+same names, marshalling torch tensors (device memory) and the current HIP
+stream into the C ABI.  No arithmetic happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libftwa.so")
+
+FTWA_OK = 0
+STATUS = {0: "FTWA_OK", -1: "FTWA_EINVAL", -2: "FTWA_ENOMEM", -3: "FTWA_EHIP",
+          -4: "FTWA_ENOTSUP", -5: "FTWA_ENONFINITE", -6: "FTWA_ETIMEOUT"}
+KIND = {"torus": 0, "armchair": 1, "hex": 2}
+DTYPE = {"f64": 0, "f32": 1}
+START = {"neel": 0, "random": 1}
+PATH = {"auto": 0, "stream": 1, "resident": 2}
+
+# Every symbol include/ftwa.h declares.
+EXPORTS = (
+    "ftwa_build_lattice", "ftwa_build_lattice_bonds", "ftwa_lattice_info", "ftwa_free_lattice",
+    "ftwa_fock_start", "ftwa_sample", "ftwa_evolve_workspace_size", "ftwa_evolve",
+    "ftwa_observables", "ftwa_unpack", "ftwa_last_error",
+)
+
+
+class FtwaError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [
+        ("lat", ctypes.c_void_p),
+        ("U", ctypes.c_double),
+        ("n_traj", ctypes.c_int64),
+        ("traj_offset", ctypes.c_int64),
+        ("instance", ctypes.c_uint32),
+        ("n0", ctypes.c_void_p),
+        ("rho", ctypes.c_void_p),
+        ("S1", ctypes.c_void_p),
+        ("S2", ctypes.c_void_p),
+        ("inv", ctypes.c_void_p),
+    ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int), ("traj_chunk", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the in-tree libftwa.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2212_04352_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_double)
+    P = ctypes.POINTER
+    sig = {
+        "ftwa_build_lattice": ([i32, i32, i32, dbl, P(vp)], i32),
+        "ftwa_build_lattice_bonds": ([i32, i32, vp, vp, dbl, P(vp)], i32),
+        "ftwa_lattice_info": ([vp, P(i32), P(i32), P(vp), P(vp), P(vp)], i32),
+        "ftwa_free_lattice": ([vp], None),
+        "ftwa_fock_start": ([vp, i32, u64, u32, vp], i32),
+        "ftwa_sample": ([P(Instance), i32, u64, i32, vp], i32),
+        "ftwa_evolve_workspace_size": ([P(Instance), i32, i64, i32, i32, P(Tuning),
+                                        P(ctypes.c_size_t)], i32),
+        "ftwa_evolve": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp, ctypes.c_size_t,
+                         vp], i32),
+        "ftwa_observables": ([i32, i64, i32, vp, vp, vp, vp, vp, vp], i32),
+        "ftwa_unpack": ([i32, i64, i32, vp, vp, vp], i32),
+        "ftwa_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str) -> None:
+    if status != FTWA_OK:
+        msg = load().ftwa_last_error().decode(errors="replace")
+        raise FtwaError(status, where, msg)
+
+
+def _stream(stream):
+    """hipStream_t of a torch stream (current stream of the current device if None)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ entry points
+def ftwa_build_lattice(kind: str, a: int, b: int, t_hop: float = 1.0) -> int:
+    out = ctypes.c_void_p()
+    check(load().ftwa_build_lattice(KIND[kind], int(a), int(b), float(t_hop), ctypes.byref(out)),
+          "ftwa_build_lattice")
+    return out.value
+
+
+def ftwa_build_lattice_bonds(n_sites: int, bonds, sublattice, t_hop: float = 1.0) -> int:
+    import numpy as np
+    b = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1))
+    s = np.ascontiguousarray(np.asarray(sublattice, dtype=np.uint8))
+    out = ctypes.c_void_p()
+    check(load().ftwa_build_lattice_bonds(int(n_sites), len(b) // 2, b.ctypes.data, s.ctypes.data,
+                                          float(t_hop), ctypes.byref(out)),
+          "ftwa_build_lattice_bonds")
+    return out.value
+
+
+def ftwa_lattice_info(lat: int):
+    """Returns (N, n_bonds, nbr [N,3] int32, deg [N] uint8, sub [N] uint8) as numpy copies."""
+    import numpy as np
+    n, nb = ctypes.c_int(), ctypes.c_int()
+    p_nbr, p_deg, p_sub = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    check(load().ftwa_lattice_info(lat, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(p_nbr),
+                                   ctypes.byref(p_deg), ctypes.byref(p_sub)), "ftwa_lattice_info")
+    N = n.value
+    nbr = np.ctypeslib.as_array(ctypes.cast(p_nbr, ctypes.POINTER(ctypes.c_int32)), (N * 3,))
+    deg = np.ctypeslib.as_array(ctypes.cast(p_deg, ctypes.POINTER(ctypes.c_uint8)), (N,))
+    sub = np.ctypeslib.as_array(ctypes.cast(p_sub, ctypes.POINTER(ctypes.c_uint8)), (N,))
+    return N, nb.value, nbr.reshape(N, 3).copy(), deg.copy(), sub.copy()
+
+
+def ftwa_free_lattice(lat: int) -> None:
+    load().ftwa_free_lattice(lat)
+
+
+def ftwa_fock_start(lat: int, kind: str = "neel", seed: int = 0, instance: int = 0):
+    """Host array n0[2, N] (numpy float64)."""
+    import numpy as np
+    N = ftwa_lattice_info(lat)[0]
+    n0 = np.zeros(2 * N, dtype=np.float64)
+    check(load().ftwa_fock_start(lat, START[kind], ctypes.c_uint64(seed), instance, n0.ctypes.data),
+          "ftwa_fock_start")
+    return n0.reshape(2, N)
+
+
+def _instances(insts):
+    arr = (Instance * len(insts))()
+    for k, d in enumerate(insts):
+        arr[k] = Instance(d["lat"], float(d["U"]), int(d["n_traj"]), int(d.get("traj_offset", 0)),
+                          int(d.get("instance", 0)), _ptr(d["n0"]), _ptr(d["rho"]),
+                          _ptr(d.get("S1")), _ptr(d.get("S2")), _ptr(d.get("inv")))
+    return arr
+
+
+def _tuning(path: str = "auto", traj_chunk: int = 0):
+    return Tuning(PATH[path], int(traj_chunk))
+
+
+def ftwa_sample(insts, seed: int, dtype: str, stream=None) -> None:
+    arr = _instances(insts)
+    check(load().ftwa_sample(arr, len(insts), ctypes.c_uint64(seed), DTYPE[dtype], _stream(stream)),
+          "ftwa_sample")
+
+
+def ftwa_evolve_workspace_size(insts, n_steps: int, record_every: int, dtype: str,
+                               path: str = "auto", traj_chunk: int = 0) -> int:
+    arr = _instances(insts)
+    out = ctypes.c_size_t()
+    tune = _tuning(path, traj_chunk)
+    check(load().ftwa_evolve_workspace_size(arr, len(insts), int(n_steps), int(record_every),
+                                            DTYPE[dtype], ctypes.byref(tune), ctypes.byref(out)),
+          "ftwa_evolve_workspace_size")
+    return out.value
+
+
+def ftwa_evolve(insts, dt: float, n_steps: int, record_every: int, dtype: str, workspace,
+                path: str = "auto", traj_chunk: int = 0, stream=None) -> None:
+    arr = _instances(insts)
+    tune = _tuning(path, traj_chunk)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    check(load().ftwa_evolve(arr, len(insts), float(dt), int(n_steps), int(record_every),
+                             DTYPE[dtype], ctypes.byref(tune), _ptr(workspace), nbytes,
+                             _stream(stream)), "ftwa_evolve")
+
+
+def ftwa_observables(n_sites: int, M: int, n_rec: int, S1, S2, n_out, C_out=None, g2_out=None,
+                     stream=None) -> None:
+    check(load().ftwa_observables(int(n_sites), int(M), int(n_rec), _ptr(S1), _ptr(S2),
+                                  _ptr(n_out), _ptr(C_out), _ptr(g2_out), _stream(stream)),
+          "ftwa_observables")
+
+
+def ftwa_unpack(n_sites: int, n_traj: int, dtype: str, rho, out, stream=None) -> None:
+    check(load().ftwa_unpack(int(n_sites), int(n_traj), DTYPE[dtype], _ptr(rho), _ptr(out),
+                             _stream(stream)), "ftwa_unpack")
+
+
+def ftwa_last_error() -> str:
+    return load().ftwa_last_error().decode(errors="replace")

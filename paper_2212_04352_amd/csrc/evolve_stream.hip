@@ -1,0 +1,220 @@
+// evolve_stream.hip -- "stream" path of the fTWA time integration: the state
+// lives in HBM in the packed, trajectory-innermost layout and every stage of
+// the classical Runge-Kutta step is one kernel launch over all elements of a
+// chunk of trajectories.
+//
+// Equation of motion: Eq. (5) of arXiv:2212.04352 with j_ij = t on bonds and
+// u_ij = U delta_ij:
+//   f_ij = i [ t (sum_{k in nb(j)} rho_ik - sum_{k in nb(i)} rho_kj) + U (d_i - d_j) rho_ij ],
+// d = diagonal of the other spin block.  A wave owns 64 consecutive
+// trajectories and walks a run of packed elements; (i, j) and all neighbour
+// indices are therefore wave-uniform (scalar registers) and every load is one
+// coalesced 512 B (FP32) or 1 KiB (FP64) row segment.  Elements i > j are read
+// as conjugates of the stored upper triangle.
+#include "device_common.h"
+#include "ftwa_internal.h"
+
+namespace ftwa {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kElemsPerWave = 16;
+
+template <typename T> struct StageArgs {
+    int N;
+    int64_t P;
+    int64_t Mc;
+    cplx_t<T>* y;
+    int64_t ldy;
+    const cplx_t<T>* yin;  // stage input
+    int64_t ldin;
+    cplx_t<T>* yout;       // next stage input (stages 1-3)
+    cplx_t<T>* acc;        // Runge-Kutta accumulator, stride Mc
+    const int32_t* nb;     // [N][4]
+    T t, U, c;             // c: this stage's coefficient (h/2, h/2, h, h/6)
+    int64_t n_elem_chunks; // ceil(2P / kElemsPerWave)
+    int64_t n_work;        // n_traj_blocks * n_elem_chunks waves
+    int64_t blocks_per_xcd;
+};
+
+__device__ __forceinline__ int64_t prow(int N, int i) {
+    return (int64_t)i * N - (int64_t)i * (i - 1) / 2;
+}
+
+// Element (a, b) of one spin block of the stage input for trajectory m,
+// read from the stored upper triangle (conjugated when a > b).
+template <typename T>
+__device__ __forceinline__ cplx_t<T> load_elem(const cplx_t<T>* base, int64_t ld, int N, int a,
+                                               int b, int64_t m) {
+    if (a <= b) return base[(prow(N, a) + (b - a)) * ld + m];
+    return conj(base[(prow(N, b) + (a - b)) * ld + m]);
+}
+
+template <typename T, int STAGE>
+__global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A) {
+    // XCD-aware numbering: blocks are dealt round-robin to the 8 XCDs, so
+    // consecutive virtual blocks (neighbouring elements of the same
+    // trajectories) are made to run on the same XCD and share its L2.
+    const int64_t xcd = blockIdx.x % 8;
+    const int64_t slot = blockIdx.x / 8;
+    const int64_t vblock = xcd * A.blocks_per_xcd + slot;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int lane = threadIdx.x % 64;
+    const int64_t w = vblock * kWavesPerBlock + wave;
+    if (w >= A.n_work) return;
+    const int64_t tb = w / A.n_elem_chunks;
+    const int64_t chunk = w - tb * A.n_elem_chunks;
+    const int64_t m_raw = tb * 64 + lane;
+    const bool active = m_raw < A.Mc;
+    const int64_t m = active ? m_raw : A.Mc - 1;  // inactive lanes load in bounds, never store
+    const int N = A.N;
+    const int64_t P = A.P;
+    const int64_t q0 = chunk * kElemsPerWave;
+    const int64_t q1 = q0 + kElemsPerWave < 2 * P ? q0 + kElemsPerWave : 2 * P;
+    for (int64_t q = q0; q < q1; ++q) {
+        const int s = q >= P ? 1 : 0;
+        const int64_t p = q - s * P;
+        // recover (i, j) of packed element p: rows are contiguous runs
+        int i = 0;
+        {
+            // row i satisfies prow(i) <= p < prow(i+1); N <= 255 so a short search
+            int lo = 0, hi = N - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (prow(N, mid) <= p) lo = mid; else hi = mid - 1;
+            }
+            i = lo;
+        }
+        const int j = (int)(p - prow(N, i)) + i;
+        const cplx_t<T>* Ys = A.yin + (int64_t)s * P * A.ldin;
+        const cplx_t<T>* Yo = A.yin + (int64_t)(1 - s) * P * A.ldin;
+        // col = sum_{k in nb(j)} rho_ik, ascending k
+        const int dj = A.nb[j * 4 + 3];
+        cplx_t<T> col, row;
+        col.x = col.y = 0;
+        row.x = row.y = 0;
+        for (int n = 0; n < dj; ++n) {
+            const int k = A.nb[j * 4 + n];
+            const cplx_t<T> v = load_elem<T>(Ys, A.ldin, N, i, k, m);
+            col = n == 0 ? v : cadd(col, v);
+        }
+        // row = sum_{k in nb(i)} rho_kj, ascending k
+        const int di = A.nb[i * 4 + 3];
+        for (int n = 0; n < di; ++n) {
+            const int k = A.nb[i * 4 + n];
+            const cplx_t<T> v = load_elem<T>(Ys, A.ldin, N, k, j, m);
+            row = n == 0 ? v : cadd(row, v);
+        }
+        const int64_t ep = (prow(N, i) + (j - i));
+        const cplx_t<T> own = Ys[ep * A.ldin + m];
+        const T d_i = Yo[prow(N, i) * A.ldin + m].x;
+        const T d_j = Yo[prow(N, j) * A.ldin + m].x;
+        const T a = A.U * (d_i - d_j);
+        const cplx_t<T> k = rhs_element<T>(col, row, own, A.t, a);
+        const int64_t e_ws = ((int64_t)s * P + ep) * A.Mc + m;  // workspace index
+        const int64_t e_y = ((int64_t)s * P + ep) * A.ldy + m;   // state index
+        if (STAGE == 1) {
+            // Y_1 = y, so `own` is y itself
+            if (active) {
+                A.acc[e_ws] = k;
+                cplx_t<T> nx;
+                nx.x = fma_rn<T>(A.c, k.x, own.x);
+                nx.y = fma_rn<T>(A.c, k.y, own.y);
+                A.yout[e_ws] = nx;
+            }
+        } else if (STAGE == 2 || STAGE == 3) {
+            if (active) {
+                cplx_t<T> ac = A.acc[e_ws];
+                ac.x = fma_rn<T>((T)2, k.x, ac.x);
+                ac.y = fma_rn<T>((T)2, k.y, ac.y);
+                A.acc[e_ws] = ac;
+                const cplx_t<T> yv = A.y[e_y];
+                cplx_t<T> nx;
+                nx.x = fma_rn<T>(A.c, k.x, yv.x);
+                nx.y = fma_rn<T>(A.c, k.y, yv.y);
+                A.yout[e_ws] = nx;
+            }
+        } else {
+            if (active) {
+                cplx_t<T> ac = A.acc[e_ws];
+                ac.x = ac.x + k.x;
+                ac.y = ac.y + k.y;
+                cplx_t<T> yv = A.y[e_y];
+                yv.x = fma_rn<T>(A.c, ac.x, yv.x);
+                yv.y = fma_rn<T>(A.c, ac.y, yv.y);
+                A.y[e_y] = yv;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void record_diag_kernel(int N, int64_t P, int64_t Mc,
+                                                          const cplx_t<T>* __restrict__ y,
+                                                          int64_t ldy, double* __restrict__ X) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Mc) return;
+    const int a = blockIdx.y;  // s * N + i
+    const int s = a >= N ? 1 : 0;
+    const int i = a - s * N;
+    const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
+    X[(int64_t)a * Mc + m] = (double)y[((int64_t)s * P + p) * ldy + m].x;
+}
+
+template <typename T>
+ftwa_status step_impl(const StreamChunk& c, const DeviceTables& tab, hipStream_t stream) {
+    StageArgs<T> A;
+    A.N = c.N;
+    A.P = c.P;
+    A.Mc = c.Mc;
+    A.y = static_cast<cplx_t<T>*>(c.y);
+    A.ldy = c.ldy;
+    A.acc = static_cast<cplx_t<T>*>(c.acc);
+    A.nb = tab.nb;
+    A.t = (T)c.t;
+    A.U = (T)c.U;
+    A.n_elem_chunks = (2 * c.P + kElemsPerWave - 1) / kElemsPerWave;
+    const int64_t n_tb = (c.Mc + 63) / 64;
+    A.n_work = n_tb * A.n_elem_chunks;
+    const int64_t n_blocks = (A.n_work + kWavesPerBlock - 1) / kWavesPerBlock;
+    A.blocks_per_xcd = (n_blocks + 7) / 8;
+    const dim3 grid((unsigned)(A.blocks_per_xcd * 8)), block(64 * kWavesPerBlock);
+    cplx_t<T>* ya = static_cast<cplx_t<T>*>(c.ya);
+    cplx_t<T>* yb = static_cast<cplx_t<T>*>(c.yb);
+    const T c_half = (T)(0.5 * c.dt), c_full = (T)c.dt, c_sixth = (T)(c.dt / 6.0);
+
+    A.yin = A.y; A.ldin = c.ldy; A.yout = ya; A.c = c_half;
+    hipLaunchKernelGGL((rk4_stage_stream<T, 1>), grid, block, 0, stream, A);
+    A.yin = ya; A.ldin = c.Mc; A.yout = yb; A.c = c_half;
+    hipLaunchKernelGGL((rk4_stage_stream<T, 2>), grid, block, 0, stream, A);
+    A.yin = yb; A.ldin = c.Mc; A.yout = ya; A.c = c_full;
+    hipLaunchKernelGGL((rk4_stage_stream<T, 3>), grid, block, 0, stream, A);
+    A.yin = ya; A.ldin = c.Mc; A.yout = nullptr; A.c = c_sixth;
+    hipLaunchKernelGGL((rk4_stage_stream<T, 4>), grid, block, 0, stream, A);
+    FTWA_LAUNCH_CHECK("rk4_stage_stream");
+    return FTWA_OK;
+}
+
+}  // namespace
+
+ftwa_status stream_step(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
+                        hipStream_t stream) {
+    return dtype == FTWA_F64 ? step_impl<double>(c, tab, stream) : step_impl<float>(c, tab, stream);
+}
+
+ftwa_status record_diag(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
+                        double* X, hipStream_t stream) {
+    (void)tab;
+    const dim3 grid((unsigned)((c.Mc + 255) / 256), (unsigned)(2 * c.N)), block(256);
+    if (dtype == FTWA_F64)
+        hipLaunchKernelGGL(record_diag_kernel<double>, grid, block, 0, stream, c.N, c.P, c.Mc,
+                           static_cast<const double2*>(c.y), c.ldy, X);
+    else
+        hipLaunchKernelGGL(record_diag_kernel<float>, grid, block, 0, stream, c.N, c.P, c.Mc,
+                           static_cast<const float2*>(c.y), c.ldy, X);
+    FTWA_LAUNCH_CHECK("record_diag_kernel");
+    return FTWA_OK;
+}
+
+}  // namespace ftwa

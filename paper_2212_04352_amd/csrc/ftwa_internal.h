@@ -1,0 +1,102 @@
+// ftwa_internal.h -- shared declarations of the libftwa host code and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ftwa.h"
+
+namespace ftwa {
+
+constexpr int kMaxDeg = 3;
+constexpr int kMaxSites = 255;
+
+// Index tables of a lattice on one device (uploaded once, owned by the handle).
+struct DeviceTables {
+    int32_t* nb = nullptr;     // [N][4]: three neighbours (ascending, -1 padded), degree
+    int32_t* off = nullptr;    // [N]: packed row start i*N - i*(i-1)/2
+    uint32_t* elem = nullptr;  // [P]: packed element p -> i | j << 16
+};
+
+}  // namespace ftwa
+
+struct ftwa_lattice_s {
+    int N = 0;
+    int n_bonds = 0;
+    double t = 1.0;
+    std::vector<int32_t> nbr;   // [N][3], ascending, padded with -1
+    std::vector<uint8_t> deg;   // [N]
+    std::vector<uint8_t> sub;   // [N]
+    std::mutex mu;
+    std::map<int, ftwa::DeviceTables> dev;  // by HIP device ordinal
+};
+
+namespace ftwa {
+
+// Packed Hermitian storage of one spin block.
+inline int64_t packed_count(int N) { return (int64_t)N * (N + 1) / 2; }
+inline int64_t packed_row(int N, int i) { return (int64_t)i * N - (int64_t)i * (i - 1) / 2; }
+inline int64_t n_records(int64_t n_steps, int record_every) { return n_steps / record_every + 1; }
+inline int64_t s2_count(int D) { return (int64_t)D * (D + 1) / 2; }
+
+// Error reporting (thread-local message, see ftwa_last_error).
+ftwa_status fail(ftwa_status st, const std::string& msg);
+ftwa_status hip_fail(hipError_t e, const char* what);
+
+#define FTWA_HIP_TRY(expr)                                                  \
+    do {                                                                    \
+        hipError_t _e = (expr);                                             \
+        if (_e != hipSuccess) return ::ftwa::hip_fail(_e, #expr);           \
+    } while (0)
+
+#define FTWA_LAUNCH_CHECK(what)                                             \
+    do {                                                                    \
+        hipError_t _e = hipGetLastError();                                  \
+        if (_e != hipSuccess) return ::ftwa::hip_fail(_e, what);            \
+    } while (0)
+
+// Uploads (once per device) and returns the lattice's device tables.
+ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
+
+// ---------------------------------------------------------------- launches
+// Sampling of rho(0) for one instance (sample.hip).
+ftwa_status launch_sample(const ftwa_instance& in, const DeviceTables& tab, uint64_t seed,
+                          ftwa_dtype dtype, hipStream_t stream);
+
+// Copies of the diagonal variables into the record buffer X[a][m] (FP64).
+struct RecordView {
+    double* X;        // [D][Mc] for one record
+    int64_t ldx;      // = Mc
+};
+
+// Stream path (evolve_stream.hip).
+struct StreamChunk {
+    int N;
+    int64_t P;
+    int64_t Mc;          // trajectories in this chunk
+    void* y;             // instance rho, already offset by the chunk's first trajectory
+    int64_t ldy;         // stride of y between packed elements (= instance n_traj)
+    void* acc;           // workspace state copies, stride Mc
+    void* ya;
+    void* yb;
+    double t, U, dt;
+};
+ftwa_status stream_step(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
+                        hipStream_t stream);
+ftwa_status record_diag(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
+                        double* X, hipStream_t stream);
+
+// Moments of the records of one chunk: S1[r] += sum_m X[r][a][m],
+// S2[r][ab] += sum_m X[r][a][m] X[r][b][m] (fixed summation order).
+size_t moments_workspace_bytes(int D, int64_t Mc, int64_t n_rec);
+ftwa_status moments_accumulate(int D, int64_t Mc, int64_t n_rec, const double* X,
+                               double* S1, double* S2, void* scratch, hipStream_t stream);
+
+ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream);
+
+}  // namespace ftwa

@@ -1,0 +1,312 @@
+// lattice.cpp -- honeycomb lattices (Sec. II of arXiv:2212.04352: hopping
+// j_ij = t between nearest neighbours of a graphene lattice) and Fock starts
+// (Sec. IV.A: every site holds one electron of either spin).  Host code.
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <set>
+#include <utility>
+
+#include "ftwa_internal.h"
+#include "philox.h"
+
+namespace ftwa {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+using Site = std::pair<int, int>;  // (row, column) on the brick wall
+
+// Brick-wall honeycomb: every site has a left and a right neighbour in its
+// row and one vertical neighbour, above when row + column is even.
+bool vertical_up(int r, int c) { return ((r + c) % 2 + 2) % 2 == 0; }
+
+// Builds a lattice from a set of brick-wall sites, numbered in the set's
+// (row, column) order, with every brick-wall bond between two members.
+ftwa_lattice from_brick_sites(const std::set<Site>& sites, double t) {
+    std::map<Site, int> index;
+    for (const Site& s : sites) index.emplace(s, (int)index.size());
+    const int N = (int)index.size();
+    std::vector<std::vector<int>> adj(N);
+    int bonds = 0;
+    for (const auto& [s, i] : index) {
+        const Site right{s.first, s.second + 1};
+        auto it = index.find(right);
+        if (it != index.end()) { adj[i].push_back(it->second); adj[it->second].push_back(i); ++bonds; }
+        if (vertical_up(s.first, s.second)) {
+            auto up = index.find(Site{s.first + 1, s.second});
+            if (up != index.end()) { adj[i].push_back(up->second); adj[up->second].push_back(i); ++bonds; }
+        }
+    }
+    auto* lat = new ftwa_lattice_s;
+    lat->N = N;
+    lat->n_bonds = bonds;
+    lat->t = t;
+    lat->nbr.assign((size_t)N * kMaxDeg, -1);
+    lat->deg.assign(N, 0);
+    lat->sub.assign(N, 0);
+    for (const auto& [s, i] : index) {
+        auto& a = adj[i];
+        std::sort(a.begin(), a.end());
+        if (a.size() > (size_t)kMaxDeg) { delete lat; return nullptr; }
+        for (size_t k = 0; k < a.size(); ++k) lat->nbr[(size_t)i * kMaxDeg + k] = a[k];
+        lat->deg[i] = (uint8_t)a.size();
+        lat->sub[i] = (uint8_t)(((s.first + s.second) % 2 + 2) % 2);
+    }
+    return lat;
+}
+
+int brick_degree(const std::set<Site>& alive, const Site& s) {
+    int d = 0;
+    if (alive.count({s.first, s.second - 1})) ++d;
+    if (alive.count({s.first, s.second + 1})) ++d;
+    if (vertical_up(s.first, s.second) ? alive.count({s.first + 1, s.second})
+                                       : alive.count({s.first - 1, s.second}))
+        ++d;
+    return d;
+}
+
+ftwa_lattice build_torus(int L1, int L2, double t) {
+    auto* lat = new ftwa_lattice_s;
+    const int N = 2 * L1 * L2;
+    lat->N = N;
+    lat->t = t;
+    std::vector<std::set<int>> adj(N);
+    auto site = [&](int x, int y, int b) { return 2 * (x * L2 + y) + b; };
+    for (int x = 0; x < L1; ++x)
+        for (int y = 0; y < L2; ++y) {
+            const int A = site(x, y, 0);
+            const int partners[3] = {site(x, y, 1), site((x + L1 - 1) % L1, y, 1),
+                                     site(x, (y + L2 - 1) % L2, 1)};
+            for (int B : partners) { adj[A].insert(B); adj[B].insert(A); }
+        }
+    lat->nbr.assign((size_t)N * kMaxDeg, -1);
+    lat->deg.assign(N, 0);
+    lat->sub.assign(N, 0);
+    int twice_bonds = 0;
+    for (int i = 0; i < N; ++i) {
+        int k = 0;
+        for (int j : adj[i]) lat->nbr[(size_t)i * kMaxDeg + k++] = j;  // std::set is ascending
+        lat->deg[i] = (uint8_t)k;
+        lat->sub[i] = (uint8_t)(i & 1);
+        twice_bonds += k;
+    }
+    lat->n_bonds = twice_bonds / 2;
+    return lat;
+}
+
+ftwa_lattice build_armchair(int R, int C, double t) {
+    std::set<Site> alive;
+    for (int r = 0; r < R; ++r)
+        for (int c = 0; c < C; ++c) alive.insert({r, c});
+    // remove dangling sites (degree < 2) until none is left
+    std::deque<Site> queue(alive.begin(), alive.end());
+    while (!queue.empty()) {
+        Site s = queue.front();
+        queue.pop_front();
+        if (!alive.count(s) || brick_degree(alive, s) >= 2) continue;
+        alive.erase(s);
+        const Site around[4] = {{s.first, s.second - 1}, {s.first, s.second + 1},
+                                {s.first + 1, s.second}, {s.first - 1, s.second}};
+        for (const Site& n : around)
+            if (alive.count(n)) queue.push_back(n);
+    }
+    return alive.empty() ? nullptr : from_brick_sites(alive, t);
+}
+
+ftwa_lattice build_hex_flake(int rings, double t) {
+    // hexagon with axial coordinates (q, w) has lower-left brick-wall site
+    // (row w, column 2q + w) and spans rows w..w+1, columns 2q+w..2q+w+2
+    std::set<Site> sites;
+    const int R = rings - 1;
+    for (int q = -R; q <= R; ++q)
+        for (int w = -R; w <= R; ++w) {
+            const int s = -q - w;
+            if (std::max({std::abs(q), std::abs(w), std::abs(s)}) > R) continue;
+            for (int dr = 0; dr <= 1; ++dr)
+                for (int dc = 0; dc <= 2; ++dc) sites.insert({w + dr, 2 * q + w + dc});
+        }
+    return from_brick_sites(sites, t);
+}
+
+}  // namespace
+
+ftwa_status fail(ftwa_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+ftwa_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return FTWA_EHIP;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
+}  // namespace ftwa
+
+using namespace ftwa;
+
+extern "C" {
+
+const char* ftwa_last_error(void) { return ftwa::last_error(); }
+
+ftwa_status ftwa_build_lattice(ftwa_lattice_kind kind, int a, int b, double t_hop,
+                               ftwa_lattice* out) {
+    if (!out) return fail(FTWA_EINVAL, "ftwa_build_lattice: out is NULL");
+    *out = nullptr;
+    ftwa_lattice lat = nullptr;
+    switch (kind) {
+        case FTWA_TORUS:
+            if (a < 2 || b < 2) return fail(FTWA_EINVAL, "torus needs a, b >= 2");
+            if (2LL * a * b > kMaxSites) return fail(FTWA_EINVAL, "more than 255 sites");
+            lat = build_torus(a, b, t_hop);
+            break;
+        case FTWA_ARMCHAIR_RECT:
+            if (a < 2 || b < 2) return fail(FTWA_EINVAL, "rectangle needs a, b >= 2");
+            if ((long long)a * b > 4 * kMaxSites) return fail(FTWA_EINVAL, "rectangle too large");
+            lat = build_armchair(a, b, t_hop);
+            break;
+        case FTWA_HEX_ZIGZAG:
+            if (a < 1 || 6LL * a * a > kMaxSites) return fail(FTWA_EINVAL, "hex flake rings out of range");
+            lat = build_hex_flake(a, t_hop);
+            break;
+        default:
+            return fail(FTWA_EINVAL, "unknown lattice kind");
+    }
+    if (!lat) return fail(FTWA_EINVAL, "lattice construction failed");
+    if (lat->N > kMaxSites || lat->N < 1) {
+        delete lat;
+        return fail(FTWA_EINVAL, "lattice has more than 255 sites");
+    }
+    *out = lat;
+    return FTWA_OK;
+}
+
+ftwa_status ftwa_build_lattice_bonds(int n_sites, int n_bonds, const int32_t* bonds,
+                                     const uint8_t* sublattice, double t_hop,
+                                     ftwa_lattice* out) {
+    if (!out) return fail(FTWA_EINVAL, "ftwa_build_lattice_bonds: out is NULL");
+    *out = nullptr;
+    if (n_sites < 1 || n_sites > kMaxSites) return fail(FTWA_EINVAL, "n_sites out of range");
+    if (n_bonds < 0 || (n_bonds > 0 && !bonds)) return fail(FTWA_EINVAL, "bad bond list");
+    std::vector<std::set<int>> adj(n_sites);
+    for (int k = 0; k < n_bonds; ++k) {
+        int u = bonds[2 * k], v = bonds[2 * k + 1];
+        if (u < 0 || v < 0 || u >= n_sites || v >= n_sites || u == v)
+            return fail(FTWA_EINVAL, "bond endpoint out of range or self bond");
+        if (adj[u].count(v)) return fail(FTWA_EINVAL, "duplicate bond");
+        adj[u].insert(v);
+        adj[v].insert(u);
+        if (adj[u].size() > (size_t)kMaxDeg || adj[v].size() > (size_t)kMaxDeg)
+            return fail(FTWA_EINVAL, "site degree above 3");
+    }
+    auto* lat = new ftwa_lattice_s;
+    lat->N = n_sites;
+    lat->n_bonds = n_bonds;
+    lat->t = t_hop;
+    lat->nbr.assign((size_t)n_sites * kMaxDeg, -1);
+    lat->deg.assign(n_sites, 0);
+    lat->sub.assign(n_sites, 0);
+    for (int i = 0; i < n_sites; ++i) {
+        int k = 0;
+        for (int j : adj[i]) lat->nbr[(size_t)i * kMaxDeg + k++] = j;
+        lat->deg[i] = (uint8_t)k;
+        lat->sub[i] = sublattice ? (uint8_t)(sublattice[i] & 1) : 0;
+    }
+    *out = lat;
+    return FTWA_OK;
+}
+
+ftwa_status ftwa_lattice_info(ftwa_lattice lat, int* n_sites, int* n_bonds, const int32_t** nbr,
+                              const uint8_t** deg, const uint8_t** sublattice) {
+    if (!lat) return fail(FTWA_EINVAL, "ftwa_lattice_info: NULL lattice");
+    if (n_sites) *n_sites = lat->N;
+    if (n_bonds) *n_bonds = lat->n_bonds;
+    if (nbr) *nbr = lat->nbr.data();
+    if (deg) *deg = lat->deg.data();
+    if (sublattice) *sublattice = lat->sub.data();
+    return FTWA_OK;
+}
+
+void ftwa_free_lattice(ftwa_lattice lat) {
+    if (!lat) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (auto& [dev, tab] : lat->dev) {
+        if (hipSetDevice(dev) != hipSuccess) continue;
+        (void)hipFree(tab.nb);
+        (void)hipFree(tab.off);
+        (void)hipFree(tab.elem);
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+    delete lat;
+}
+
+ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed, uint32_t instance,
+                            double* n0_host) {
+    if (!lat || !n0_host) return fail(FTWA_EINVAL, "ftwa_fock_start: NULL argument");
+    const int N = lat->N;
+    if (kind == FTWA_START_NEEL) {
+        for (int i = 0; i < N; ++i) {
+            n0_host[i] = lat->sub[i] ? 0.0 : 1.0;
+            n0_host[N + i] = lat->sub[i] ? 1.0 : 0.0;
+        }
+        return FTWA_OK;
+    }
+    if (kind != FTWA_START_RANDOM) return fail(FTWA_EINVAL, "unknown start kind");
+    if (N % 2) return fail(FTWA_EINVAL, "random half filling needs an even number of sites");
+    std::vector<int> order(N);
+    for (int i = 0; i < N; ++i) order[i] = i;
+    for (int i = N - 1; i > 0; --i) {
+        const PhiloxBlock x = philox4x32_10({(uint32_t)i, instance, 0u, 1u}, seed);
+        const uint64_t a = x.bits53_first();
+        const int j = (int)(((unsigned __int128)a * (unsigned)(i + 1)) >> 53);
+        std::swap(order[i], order[j]);
+    }
+    for (int k = 0; k < N; ++k) {
+        const bool up = k < N / 2;
+        n0_host[order[k]] = up ? 1.0 : 0.0;
+        n0_host[N + order[k]] = up ? 0.0 : 1.0;
+    }
+    return FTWA_OK;
+}
+
+}  // extern "C"
+
+namespace ftwa {
+
+ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
+    int dev = 0;
+    FTWA_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(lat->mu);
+    auto it = lat->dev.find(dev);
+    if (it != lat->dev.end()) {
+        *out = it->second;
+        return FTWA_OK;
+    }
+    const int N = lat->N;
+    const int64_t P = packed_count(N);
+    std::vector<int32_t> nb((size_t)N * 4), off(N);
+    std::vector<uint32_t> elem((size_t)P);
+    for (int i = 0; i < N; ++i) {
+        for (int k = 0; k < kMaxDeg; ++k) nb[(size_t)i * 4 + k] = lat->nbr[(size_t)i * kMaxDeg + k];
+        nb[(size_t)i * 4 + 3] = lat->deg[i];
+        off[i] = (int32_t)packed_row(N, i);
+        for (int j = i; j < N; ++j) elem[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)i | ((uint32_t)j << 16);
+    }
+    DeviceTables tab;
+    FTWA_HIP_TRY(hipMalloc(&tab.nb, nb.size() * sizeof(int32_t)));
+    FTWA_HIP_TRY(hipMalloc(&tab.off, off.size() * sizeof(int32_t)));
+    FTWA_HIP_TRY(hipMalloc(&tab.elem, elem.size() * sizeof(uint32_t)));
+    FTWA_HIP_TRY(hipMemcpy(tab.nb, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    FTWA_HIP_TRY(hipMemcpy(tab.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    FTWA_HIP_TRY(hipMemcpy(tab.elem, elem.data(), elem.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    lat->dev[dev] = tab;
+    *out = tab;
+    return FTWA_OK;
+}
+
+}  // namespace ftwa

@@ -1,0 +1,143 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI).
+
+Tolerances: integer work (lattices, Fock starts, Philox words) is bit-exact;
+the FP64 and FP32 time evolutions follow the same operation order as the
+oracle and are required to match it exactly (bitwise on rho); sampled rho(0)
+differs only through the device's log/cos/sin (a few ulp); FP64 moments and
+observables match to 1e-12 relative (summation order differs).
+"""
+import numpy as np
+import pytest
+
+from tests._util import pack, unpack, unpack_s2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ft():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_04352_amd as ft
+    ft.load()
+    return ft
+
+
+def _problem(ft, kind, a, b, U, M, start="neel", seed=1, dtype="f64", traj_offset=0, t=1.0):
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = lat.fock_start(start, seed)
+    return lat, n0, ft.Problem.allocate(lat, U, M, n0, dtype, traj_offset=traj_offset)
+
+
+def _to_host(x):
+    import torch
+    torch.cuda.synchronize()
+    return x.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,a,b,M,start,off", [("torus", 2, 3, 300, "neel", 0),
+                                                 ("torus", 3, 9, 65, "random", 7),
+                                                 ("armchair", 10, 20, 17, "neel", 1000)])
+def test_sample_matches_oracle(ft, orc, kind, a, b, M, start, off):
+    seed = 0x2212043520000001
+    lat, n0, prob = _problem(ft, kind, a, b, 3.3, M, start, seed, traj_offset=off)
+    ft.sample(prob, seed)
+    got = unpack(_to_host(prob.rho), lat.N)
+    ref = orc.sample(orc.Lattice(kind, a, b), n0, seed, M, traj_offset=off)
+    # exact zero pattern and exact diagonal; off-diagonal within a few ulp
+    assert np.array_equal(got == 0, ref == 0)
+    assert np.array_equal(np.diagonal(got, axis1=2, axis2=3), np.diagonal(ref, axis1=2, axis2=3))
+    assert np.max(np.abs(got - ref)) <= 8 * np.finfo(np.float64).eps * np.max(np.abs(ref))
+    # FP32 storage is the FP64 value rounded once
+    _, _, p32 = _problem(ft, kind, a, b, 3.3, M, start, seed, dtype="f32", traj_offset=off)
+    ft.sample(p32, seed)
+    got32 = unpack(_to_host(p32.rho), lat.N)
+    assert np.max(np.abs(got32 - ref.astype(np.complex64))) <= 2 * np.finfo(np.float32).eps * 8
+
+
+def _evolve_parity(ft, orc, kind, a, b, U, M, n_steps, dt, re, dtype, start="random", seed=3,
+                   chunk=0, path="stream"):
+    import torch
+    olat = orc.Lattice(kind, a, b)
+    n0 = orc.fock_start(olat, start, seed)
+    rho0 = orc.sample(olat, n0, seed, M)
+    lat = ft.Lattice(kind, a, b)
+    prob = ft.Problem.allocate(lat, U, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    ft.evolve(prob, dt, n_steps, re, path=path, traj_chunk=chunk)
+    y_ref, X_ref, _ = orc.evolve(olat, U, rho0, dt, n_steps, re, precision=dtype)
+    got = unpack(_to_host(prob.rho), lat.N)
+    S1, S2 = _to_host(prob.S1), _to_host(prob.S2)
+    return got, y_ref.astype(cdt), S1, S2, X_ref
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kind,a,b,U,M,steps,chunk", [
+    ("torus", 2, 3, 3.3, 130, 200, 0),       # 12 sites, ragged trajectory count
+    ("torus", 2, 3, 0.0, 64, 50, 0),         # free fermions
+    ("torus", 3, 9, 3.3, 70, 60, 32),        # 54 sites, several chunks with a ragged tail
+    ("hex", 2, 0, 1.7, 33, 40, 0),           # degree-2 edge sites
+    ("armchair", 10, 20, 3.3, 20, 12, 0),    # 198-site flake
+])
+def test_evolve_stream_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, U, M, steps, chunk):
+    got, ref, S1, S2, X = _evolve_parity(ft, orc, kind, a, b, U, M, steps, 0.01, 10, dtype,
+                                         chunk=chunk)
+    assert np.array_equal(got, ref), np.max(np.abs(got - ref))
+    S1r, S2r = orc.moments(X)
+    assert np.allclose(S1, S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(S2, S2r, rtol=1e-12, atol=1e-12)
+
+
+def test_observables_match_oracle(ft, orc):
+    import torch
+    got, ref, S1, S2, X = _evolve_parity(ft, orc, "torus", 2, 3, 3.3, 200, 100, 0.01, 10, "f64")
+    S1r, S2r = orc.moments(X)
+    N = 12
+    n_r, C_r, g2_r = orc.observables(N, 200, S1r, S2r)
+    D = 2 * N
+    n = torch.empty((S1.shape[0], D), dtype=torch.float64, device="cuda")
+    C = torch.empty((S1.shape[0], D, D), dtype=torch.float64, device="cuda")
+    g2 = torch.empty_like(C)
+    ft.ftwa_observables(N, 200, S1.shape[0], torch.from_numpy(S1).cuda(),
+                        torch.from_numpy(S2).cuda(), n, C, g2)
+    assert np.allclose(_to_host(n), n_r, rtol=0, atol=1e-13)
+    assert np.allclose(_to_host(C), C_r, rtol=0, atol=1e-12)
+    assert np.allclose(_to_host(g2), g2_r, rtol=1e-11, atol=1e-12)
+    assert np.allclose(unpack_s2(S2, D), unpack_s2(S2r, D), rtol=1e-12, atol=1e-13)
+
+
+def test_full_pipeline_small_torus(ft, orc):
+    """GPU sample -> evolve -> observables against the oracle's own pipeline on
+    the 12-site torus workload (Neel start, U/t = 3.3, dt = 0.01 to T = 10,
+    256 of its trajectories).  rho(0) differs by a few ulp (device
+    log/cos/sin), which the dynamics amplifies by at most ~1e4 at this size."""
+    import torch
+    from workloads import SMALL_TORUS as W
+    M = 256
+    lat, n0, prob = _problem(ft, W.kind, W.a, W.b, W.U, M, W.start, W.seed)
+    ft.sample(prob, W.seed)
+    ft.evolve(prob, W.dt, W.n_steps, W.record_every)
+    n, C, g2 = ft.observables(prob)
+    olat = orc.Lattice(W.kind, W.a, W.b)
+    rho0 = orc.sample(olat, n0, W.seed, M)
+    _, X, _ = orc.evolve(olat, W.U, rho0, W.dt, W.n_steps, W.record_every)
+    S1r, S2r = orc.moments(X)
+    n_r, C_r, g2_r = orc.observables(lat.N, M, S1r, S2r)
+    assert np.max(np.abs(_to_host(n) - n_r)) < 1e-9
+    assert np.max(np.abs(_to_host(C) - C_r)) < 1e-9
+    assert np.max(np.abs(_to_host(g2) - g2_r)) < 1e-8
+    del torch
+
+
+def test_errors_are_reported(ft):
+    import torch
+    lat, n0, prob = _problem(ft, "torus", 2, 3, 1.0, 4)
+    ft.sample(prob, 1)
+    d = prob.desc()
+    d["S1"] = torch.empty(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ft.FtwaError):
+        ft.ftwa_evolve([d], 0.01, 10, 0, "f64", None)  # record_every < 1
+    with pytest.raises(ft.FtwaError):
+        ft.ftwa_evolve([d], 0.01, 10, 1, "f64", None)  # workspace missing
