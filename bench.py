@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the fTWA hot path on one MI355X.
+
+Metric: trajectory x RK4-steps per second on the 198-site honeycomb flake
+(10 x 20 brick wall with its two dangling corners trimmed), Neel start,
+U/t = 3.3, 32768 trajectories, dt = 0.005/t to T = 20/t (4000 RK4 steps),
+records every 10 steps; FP32 trajectories with FP64 ensemble moments, next to
+the FP64 run on identical samples and the observable error between them.
+
+One benchmark step is one pass of the whole hot path over the batch:
+sampling of rho(0) (Eq. (6) of arXiv:2212.04352), RK4 integration of Eq. (5)
+for every trajectory with FP64 moments at every record, and the observables
+(Eq. (4), Eq. (8)).  Inputs are generated on the device (nothing crosses
+PCIe in the timed region).  Warm-up steps run first; then exactly --steps
+steps are timed between device synchronisations.
+
+Prints one JSON line.  `--gpus` above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--traj", type=int, default=None, help="override the trajectory count")
+    ap.add_argument("--horizon-steps", type=int, default=None,
+                    help="override the number of RK4 steps (default: the full horizon)")
+    ap.add_argument("--path", default="auto", choices=["auto", "stream", "resident"])
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="RK4 steps of the FP64 comparison run (default: full horizon)")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-traj", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2212_04352_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str, dtype: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    rec = data.get(f"{kernel}:{dtype}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_pass(ft, torch, W, lat, n0, dtype, M, n_steps, path, seed, workspace):
+    """One pass of the hot path; returns (problem, workspace, timing)."""
+    prob = ft.Problem.allocate(lat, W.U, M, n0, dtype)
+    ft.sample(prob, seed)
+    timing = ft.new_timing()
+    workspace = ft.evolve(prob, W.dt, n_steps, W.record_every, path=path, workspace=workspace,
+                          timing=timing)
+    obs = ft.observables(prob)
+    return prob, workspace, timing, obs
+
+
+def cpu_baseline(W, n_traj, n_steps):
+    import numpy as np
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_num_threads(threads)
+    lat = oracle.Lattice(W.kind, W.a, W.b)
+    n0 = oracle.fock_start(lat, W.start, W.seed)
+    rho0 = oracle.sample(lat, n0, W.seed, n_traj)
+    t0 = time.perf_counter()
+    oracle.evolve(lat, W.U, rho0, W.dt, n_steps, W.record_every, precision="f64")
+    dt = time.perf_counter() - t0
+    del np
+    return {"value": n_traj * n_steps / dt, "unit": "trajectory*RK4-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_traj} trajectories x {n_steps} RK4 steps of the same workload, "
+                      f"FP64, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2212_04352_amd as ft
+    from workloads import FLAKE_198 as W
+
+    torch.cuda.set_device(0)
+    M = args.traj or W.n_traj
+    n_steps = args.horizon_steps or W.n_steps
+    lat = ft.Lattice(W.kind, W.a, W.b, W.t_hop)
+    n0 = lat.fock_start(W.start, W.seed)
+    N = lat.N
+
+    # ---------------------------------------------------------------- FP32 (headline)
+    ws = None
+    for _ in range(args.warmup):
+        prob, ws, _, _ = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, args.path, W.seed, ws)
+        del prob
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    launches = 0
+    work = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prob32, ws, timing, obs32 = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, args.path,
+                                             W.seed, ws)
+        kernel_ms += timing["ms"].value
+        launches += timing["launches"].value
+        work += timing["work"].value
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = M * n_steps * args.steps / elapsed
+    bytes_per_ts_f32 = 2 * (2 * N * N) * 4
+    avg_ms = kernel_ms / max(launches, 1)
+    work_per_launch = work / max(launches, 1)
+    achieved = bytes_per_ts_f32 * work_per_launch / (avg_ms * 1e-3) / 1e9
+    kernel_name = "rk4_stage_stream" if args.path in ("stream", "auto") else "rk4_resident"
+    traffic = counter_traffic(kernel_name, "f32")
+    result = {
+        "metric": "trajectory*RK4-steps/s at N=198, FP32 vs FP64 plain, at stated obs. error",
+        "value": value,
+        "unit": "trajectory*RK4-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Philox Gaussian samples around a Neel Fock state)",
+        "config": {"workload": W.name, "lattice": "armchair 10x20 trimmed, N=198", "U": W.U,
+                   "trajectories": M, "dt": W.dt, "rk4_steps": n_steps,
+                   "record_every": W.record_every, "moments": "f64", "path": args.path},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kernel_name, "kernel_avg_ms": avg_ms,
+                     "algorithmic_bytes_per_traj_step": bytes_per_ts_f32,
+                     "traj_steps_per_launch": work_per_launch},
+    }
+    del ws
+
+    # ---------------------------------------------------------------- FP64 on identical samples
+    if not args.no_fp64:
+        steps64 = args.fp64_steps or n_steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob64, ws64, timing64, obs64 = run_pass(ft, torch, W, lat, n0, "f64", M, steps64,
+                                                 args.path, W.seed, None)
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t0
+        v64 = M * steps64 / el64
+        n32, C32, _ = obs32
+        n64, C64, _ = obs64
+        R = n64.shape[0]
+        dn = (n32[:R] - n64).abs().amax(dim=1).cpu().numpy()
+        dC = (C32[:R] - C64).abs().amax(dim=(1, 2)).cpu().numpy()
+        times = [r * W.record_every * W.dt for r in range(R)]
+
+        def upto(arr, tmax):
+            sel = [a for a, t in zip(arr, times) if t <= tmax + 1e-9]
+            return float(max(sel)) if sel else None
+
+        result["fp64"] = {"value": v64, "rk4_steps": steps64,
+                          "kernel_avg_ms": timing64["ms"].value / max(timing64["launches"].value, 1)}
+        result["fp32_over_fp64"] = value / v64
+        result["obs_error_fp32_vs_fp64"] = {
+            "max_abs_dn": {"t<=5": upto(dn, 5), "t<=8": upto(dn, 8), "t<=10": upto(dn, 10),
+                           "t<=20": upto(dn, 20)},
+            "max_abs_dC": {"t<=5": upto(dC, 5), "t<=8": upto(dC, 8), "t<=10": upto(dC, 10),
+                           "t<=20": upto(dC, 20)},
+        }
+        del prob64, ws64
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(W, args.cpu_traj, args.cpu_steps)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,16 @@ typedef enum {
 typedef struct {
     ftwa_path path;
     int traj_chunk;          /* trajectories per pass (0 = automatic)         */
+    /* Optional timing of the dominant kernel (the Runge-Kutta kernel of the
+       chosen path): when kernel_ms is not NULL, every launch of that kernel is
+       bracketed by HIP events on `stream`, ftwa_evolve waits for the stream
+       before returning, and writes the summed duration in milliseconds to
+       *kernel_ms, the number of launches to *kernel_launches (if not NULL)
+       and the trajectory-steps those launches advanced to *kernel_work (if
+       not NULL; a stage launch counts 1/4 step per trajectory). */
+    double* kernel_ms;
+    int64_t* kernel_launches;
+    double* kernel_work;
 } ftwa_tuning;
 
 /*

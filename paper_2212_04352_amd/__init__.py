@@ -17,7 +17,7 @@ from dataclasses import dataclass
 from ._binding import (DTYPE, FtwaError, ftwa_build_lattice, ftwa_build_lattice_bonds,  # noqa: F401
                        ftwa_evolve, ftwa_evolve_workspace_size, ftwa_fock_start, ftwa_free_lattice,
                        ftwa_lattice_info, ftwa_last_error, ftwa_observables, ftwa_sample,
-                       ftwa_unpack, load)
+                       ftwa_unpack, load, new_timing)
 
 
 def packed_count(N: int) -> int:
@@ -96,7 +96,7 @@ def sample(problems, seed: int, stream=None) -> None:
 
 
 def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str = "auto",
-           traj_chunk: int = 0, workspace=None, stream=None):
+           traj_chunk: int = 0, workspace=None, stream=None, timing=None):
     """Runs ftwa_evolve; allocates the workspace as a torch tensor unless given."""
     import torch
     problems = problems if isinstance(problems, (list, tuple)) else [problems]
@@ -108,7 +108,8 @@ def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str 
     nbytes = ftwa_evolve_workspace_size(descs, n_steps, record_every, dtype, path, traj_chunk)
     if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=problems[0].rho.device)
-    ftwa_evolve(descs, dt, n_steps, record_every, dtype, workspace, path, traj_chunk, stream)
+    ftwa_evolve(descs, dt, n_steps, record_every, dtype, workspace, path, traj_chunk, stream,
+                timing)
     return workspace
 
 

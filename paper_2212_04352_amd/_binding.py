@@ -48,7 +48,10 @@ class Instance(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("path", ctypes.c_int), ("traj_chunk", ctypes.c_int)]
+    _fields_ = [("path", ctypes.c_int), ("traj_chunk", ctypes.c_int),
+                ("kernel_ms", ctypes.POINTER(ctypes.c_double)),
+                ("kernel_launches", ctypes.POINTER(ctypes.c_int64)),
+                ("kernel_work", ctypes.POINTER(ctypes.c_double))]
 
 
 _lib = None
@@ -163,8 +166,18 @@ def _instances(insts):
     return arr
 
 
-def _tuning(path: str = "auto", traj_chunk: int = 0):
-    return Tuning(PATH[path], int(traj_chunk))
+def _tuning(path: str = "auto", traj_chunk: int = 0, timing=None):
+    t = Tuning(PATH[path], int(traj_chunk), None, None, None)
+    if timing is not None:
+        t.kernel_ms = ctypes.pointer(timing["ms"])
+        t.kernel_launches = ctypes.pointer(timing["launches"])
+        t.kernel_work = ctypes.pointer(timing["work"])
+    return t
+
+
+def new_timing():
+    """Holder for the dominant-kernel timing that ftwa_evolve can report."""
+    return {"ms": ctypes.c_double(0.0), "launches": ctypes.c_int64(0), "work": ctypes.c_double(0.0)}
 
 
 def ftwa_sample(insts, seed: int, dtype: str, stream=None) -> None:
@@ -185,9 +198,9 @@ def ftwa_evolve_workspace_size(insts, n_steps: int, record_every: int, dtype: st
 
 
 def ftwa_evolve(insts, dt: float, n_steps: int, record_every: int, dtype: str, workspace,
-                path: str = "auto", traj_chunk: int = 0, stream=None) -> None:
+                path: str = "auto", traj_chunk: int = 0, stream=None, timing=None) -> None:
     arr = _instances(insts)
-    tune = _tuning(path, traj_chunk)
+    tune = _tuning(path, traj_chunk, timing)
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     check(load().ftwa_evolve(arr, len(insts), float(dt), int(n_steps), int(record_every),
                              DTYPE[dtype], ctypes.byref(tune), _ptr(workspace), nbytes,

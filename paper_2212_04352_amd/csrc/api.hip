@@ -121,6 +121,45 @@ __global__ __launch_bounds__(256) void unpack_kernel(int N, int64_t n_traj, cons
 
 }  // namespace
 
+KernelTimer::~KernelTimer() {
+    for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+}
+
+ftwa_status KernelTimer::begin(hipStream_t s) {
+    if (!enabled_) return FTWA_OK;
+    hipEvent_t e;
+    FTWA_HIP_TRY(hipEventCreate(&e));
+    events_.push_back(e);
+    FTWA_HIP_TRY(hipEventRecord(e, s));
+    return FTWA_OK;
+}
+
+ftwa_status KernelTimer::end(hipStream_t s, int64_t launches, double work) {
+    if (!enabled_) return FTWA_OK;
+    hipEvent_t e;
+    FTWA_HIP_TRY(hipEventCreate(&e));
+    events_.push_back(e);
+    FTWA_HIP_TRY(hipEventRecord(e, s));
+    launches_ += launches;
+    work_ += work;
+    return FTWA_OK;
+}
+
+ftwa_status KernelTimer::finish(double* ms, int64_t* launches, double* work) {
+    if (!enabled_) return FTWA_OK;
+    double total = 0.0;
+    if (!events_.empty()) FTWA_HIP_TRY(hipEventSynchronize(events_.back()));
+    for (size_t k = 0; k + 1 < events_.size(); k += 2) {
+        float dt = 0.f;
+        FTWA_HIP_TRY(hipEventElapsedTime(&dt, events_[k], events_[k + 1]));
+        total += dt;
+    }
+    if (ms) *ms = total;
+    if (launches) *launches = launches_;
+    if (work) *work = work_;
+    return FTWA_OK;
+}
+
 }  // namespace ftwa
 
 using namespace ftwa;
@@ -167,6 +206,7 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         if (inst[k].inv) return fail(FTWA_ENOTSUP, "invariant output not built yet");
     hipStream_t stream = (hipStream_t)stream_;
     char* ws = static_cast<char*>(workspace);
+    KernelTimer timer(tune && tune->kernel_ms);
     for (int k = 0; k < n_inst; ++k) {
         const ftwa_instance& in = inst[k];
         DeviceTables tab;
@@ -192,8 +232,16 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             c.U = in.U;
             c.dt = dt;
             if ((st = record_diag(c, tab, dtype, X, stream)) != FTWA_OK) return st;
+            int64_t open_steps = 0;
             for (int64_t step = 1; step <= n_steps; ++step) {
+                if (open_steps == 0 && (st = timer.begin(stream)) != FTWA_OK) return st;
                 if ((st = stream_step(c, tab, dtype, stream)) != FTWA_OK) return st;
+                ++open_steps;
+                if (step % record_every == 0 || step == n_steps) {
+                    if ((st = timer.end(stream, 4 * open_steps, (double)open_steps * Mc)) != FTWA_OK)
+                        return st;
+                    open_steps = 0;
+                }
                 if (step % record_every == 0)
                     if ((st = record_diag(c, tab, dtype, X + (step / record_every) * D * Mc,
                                           stream)) != FTWA_OK)
@@ -204,6 +252,9 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 return st;
         }
     }
+    if (tune && tune->kernel_ms)
+        if ((st = timer.finish(tune->kernel_ms, tune->kernel_launches, tune->kernel_work)) != FTWA_OK)
+            return st;
     return FTWA_OK;
 }
 

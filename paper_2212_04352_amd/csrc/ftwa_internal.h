@@ -99,4 +99,22 @@ ftwa_status moments_accumulate(int D, int64_t Mc, int64_t n_rec, const double* X
 
 ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream);
 
+// Brackets launches of the dominant kernel with HIP events on one stream and
+// sums their durations (optional, see ftwa_tuning::kernel_ms).
+class KernelTimer {
+public:
+    explicit KernelTimer(bool enabled) : enabled_(enabled) {}
+    ~KernelTimer();
+    bool enabled() const { return enabled_; }
+    ftwa_status begin(hipStream_t s);
+    ftwa_status end(hipStream_t s, int64_t launches, double work);
+    ftwa_status finish(double* ms, int64_t* launches, double* work);
+
+private:
+    bool enabled_;
+    std::vector<hipEvent_t> events_;
+    int64_t launches_ = 0;
+    double work_ = 0.0;
+};
+
 }  // namespace ftwa
