@@ -185,6 +185,9 @@ typedef enum {
 typedef struct {
     ftwa_path path;
     int traj_chunk;          /* trajectories per pass (0 = automatic)         */
+    int resident_config;     /* index into the resident kernel table, or -1
+                                for the automatic choice (FTWA_ENOTSUP if the
+                                forced one does not fit the lattice)          */
     /* Optional timing of the dominant kernel (the Runge-Kutta kernel of the
        chosen path): when kernel_ms is not NULL, every launch of that kernel is
        bracketed by HIP events on `stream`, ftwa_evolve waits for the stream

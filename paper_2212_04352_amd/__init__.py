@@ -96,7 +96,7 @@ def sample(problems, seed: int, stream=None) -> None:
 
 
 def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str = "auto",
-           traj_chunk: int = 0, workspace=None, stream=None, timing=None):
+           traj_chunk: int = 0, workspace=None, stream=None, timing=None, config: int = -1):
     """Runs ftwa_evolve; allocates the workspace as a torch tensor unless given."""
     import torch
     problems = problems if isinstance(problems, (list, tuple)) else [problems]
@@ -105,11 +105,12 @@ def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str 
     for p in problems:
         p.ensure_moments(n_rec)
     descs = [p.desc() for p in problems]
-    nbytes = ftwa_evolve_workspace_size(descs, n_steps, record_every, dtype, path, traj_chunk)
+    nbytes = ftwa_evolve_workspace_size(descs, n_steps, record_every, dtype, path, traj_chunk,
+                                        config)
     if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=problems[0].rho.device)
     ftwa_evolve(descs, dt, n_steps, record_every, dtype, workspace, path, traj_chunk, stream,
-                timing)
+                timing, config)
     return workspace
 
 

@@ -49,6 +49,7 @@ class Instance(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int), ("traj_chunk", ctypes.c_int),
+                ("resident_config", ctypes.c_int),
                 ("kernel_ms", ctypes.POINTER(ctypes.c_double)),
                 ("kernel_launches", ctypes.POINTER(ctypes.c_int64)),
                 ("kernel_work", ctypes.POINTER(ctypes.c_double))]
@@ -166,8 +167,8 @@ def _instances(insts):
     return arr
 
 
-def _tuning(path: str = "auto", traj_chunk: int = 0, timing=None):
-    t = Tuning(PATH[path], int(traj_chunk), None, None, None)
+def _tuning(path: str = "auto", traj_chunk: int = 0, timing=None, config: int = -1):
+    t = Tuning(PATH[path], int(traj_chunk), int(config), None, None, None)
     if timing is not None:
         t.kernel_ms = ctypes.pointer(timing["ms"])
         t.kernel_launches = ctypes.pointer(timing["launches"])
@@ -187,10 +188,10 @@ def ftwa_sample(insts, seed: int, dtype: str, stream=None) -> None:
 
 
 def ftwa_evolve_workspace_size(insts, n_steps: int, record_every: int, dtype: str,
-                               path: str = "auto", traj_chunk: int = 0) -> int:
+                               path: str = "auto", traj_chunk: int = 0, config: int = -1) -> int:
     arr = _instances(insts)
     out = ctypes.c_size_t()
-    tune = _tuning(path, traj_chunk)
+    tune = _tuning(path, traj_chunk, None, config)
     check(load().ftwa_evolve_workspace_size(arr, len(insts), int(n_steps), int(record_every),
                                             DTYPE[dtype], ctypes.byref(tune), ctypes.byref(out)),
           "ftwa_evolve_workspace_size")
@@ -198,9 +199,10 @@ def ftwa_evolve_workspace_size(insts, n_steps: int, record_every: int, dtype: st
 
 
 def ftwa_evolve(insts, dt: float, n_steps: int, record_every: int, dtype: str, workspace,
-                path: str = "auto", traj_chunk: int = 0, stream=None, timing=None) -> None:
+                path: str = "auto", traj_chunk: int = 0, stream=None, timing=None,
+                config: int = -1) -> None:
     arr = _instances(insts)
-    tune = _tuning(path, traj_chunk, timing)
+    tune = _tuning(path, traj_chunk, timing, config)
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     check(load().ftwa_evolve(arr, len(insts), float(dt), int(n_steps), int(record_every),
                              DTYPE[dtype], ctypes.byref(tune), _ptr(workspace), nbytes,

@@ -34,13 +34,21 @@ ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_mom
     return FTWA_OK;
 }
 
-struct EvolvePlan {
+// How one instance is integrated, and where its scratch sits in the workspace.
+struct InstancePlan {
     ftwa_path path = FTWA_PATH_STREAM;
+    ResidentPlan res;
     int64_t chunk = 0;       // trajectories per pass
-    int64_t n_rec = 0;
-    int maxN = 0;
-    size_t off_acc = 0, off_ya = 0, off_yb = 0, off_x = 0, off_mom = 0, total = 0;
+    size_t off_acc = 0, off_ya = 0, off_yb = 0, off_x = 0, off_mom = 0, off_mb = 0, total = 0;
 };
+
+struct EvolvePlan {
+    int64_t n_rec = 0;
+    std::vector<InstancePlan> inst;
+    size_t total = 0;        // max over instances (passes run one after another)
+};
+
+constexpr size_t kRecordBudget = (size_t)4 << 30;  // bytes of FP64 records per pass
 
 ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, int64_t n_steps, int record_every,
                         ftwa_dtype dtype, const ftwa_tuning* tune, EvolvePlan* plan) {
@@ -50,27 +58,53 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, int64_t n_steps, 
     EvolvePlan p;
     p.n_rec = n_records(n_steps, record_every);
     if (p.n_rec > 65535) return fail(FTWA_EINVAL, "more than 65535 records");
-    int64_t max_traj = 0;
-    for (int k = 0; k < n_inst; ++k) {
-        p.maxN = std::max(p.maxN, inst[k].lat->N);
-        max_traj = std::max(max_traj, inst[k].n_traj);
-    }
     const ftwa_path want = tune ? tune->path : FTWA_PATH_AUTO;
-    if (want == FTWA_PATH_RESIDENT) return fail(FTWA_ENOTSUP, "resident path not built yet");
-    p.path = FTWA_PATH_STREAM;
-    int64_t chunk = tune && tune->traj_chunk > 0 ? tune->traj_chunk : 4096;
-    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, std::max<int64_t>(max_traj, 1)));
-    p.chunk = chunk;
-    const int64_t P = packed_count(p.maxN);
-    const int D = 2 * p.maxN;
-    const size_t state = (size_t)2 * P * chunk * cplx_bytes(dtype);
-    size_t off = 0;
-    p.off_acc = off; off = align_up(off + state);
-    p.off_ya = off; off = align_up(off + state);
-    p.off_yb = off; off = align_up(off + state);
-    p.off_x = off; off = align_up(off + (size_t)p.n_rec * D * chunk * sizeof(double));
-    p.off_mom = off; off = align_up(off + moments_workspace_bytes(D, chunk, p.n_rec));
-    p.total = off;
+    if (want != FTWA_PATH_AUTO && want != FTWA_PATH_STREAM && want != FTWA_PATH_RESIDENT)
+        return fail(FTWA_EINVAL, "unknown path");
+    for (int k = 0; k < n_inst; ++k) {
+        const int N = inst[k].lat->N;
+        const int64_t P = packed_count(N);
+        const int D = 2 * N;
+        InstancePlan ip;
+        DeviceTables tab;
+        ftwa_status st = device_tables(inst[k].lat, &tab);
+        if (st != FTWA_OK) return st;
+        const int force = tune ? tune->resident_config : -1;
+        if (force >= resident_config_count())
+            return fail(FTWA_EINVAL, "resident_config out of range");
+        const bool can_res = resident_plan(N, dtype, tab, &ip.res, force);
+        if (force >= 0 && !can_res)
+            return fail(FTWA_ENOTSUP, "the forced resident configuration does not fit");
+        if (want == FTWA_PATH_RESIDENT && !can_res)
+            return fail(FTWA_ENOTSUP, "no resident configuration fits this lattice and dtype");
+        ip.path = (want == FTWA_PATH_STREAM || !can_res) ? FTWA_PATH_STREAM : FTWA_PATH_RESIDENT;
+        const int64_t traj = std::max<int64_t>(inst[k].n_traj, 1);
+        int64_t chunk;
+        if (ip.path == FTWA_PATH_STREAM) {
+            chunk = tune && tune->traj_chunk > 0 ? tune->traj_chunk : 4096;
+        } else {
+            chunk = tune && tune->traj_chunk > 0 ? tune->traj_chunk : traj;
+            chunk = std::min(chunk, resident_max_traj(ip.res));
+        }
+        const int64_t rec_cap = std::max<int64_t>(
+            64, (int64_t)(kRecordBudget / ((size_t)p.n_rec * D * sizeof(double))));
+        chunk = std::max<int64_t>(1, std::min({chunk, traj, rec_cap}));
+        ip.chunk = chunk;
+        size_t off = 0;
+        if (ip.path == FTWA_PATH_STREAM) {
+            const size_t state = (size_t)2 * P * chunk * cplx_bytes(dtype);
+            ip.off_acc = off; off = align_up(off + state);
+            ip.off_ya = off; off = align_up(off + state);
+            ip.off_yb = off; off = align_up(off + state);
+        } else {
+            ip.off_mb = off; off = align_up(off + resident_mailbox_bytes(ip.res, N, dtype, chunk));
+        }
+        ip.off_x = off; off = align_up(off + (size_t)p.n_rec * D * chunk * sizeof(double));
+        ip.off_mom = off; off = align_up(off + moments_workspace_bytes(D, chunk, p.n_rec));
+        ip.total = off;
+        p.total = std::max(p.total, off);
+        p.inst.push_back(ip);
+    }
     *plan = p;
     return FTWA_OK;
 }
@@ -207,8 +241,10 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     hipStream_t stream = (hipStream_t)stream_;
     char* ws = static_cast<char*>(workspace);
     KernelTimer timer(tune && tune->kernel_ms);
+    std::vector<int*> error_words;
     for (int k = 0; k < n_inst; ++k) {
         const ftwa_instance& in = inst[k];
+        const InstancePlan& ip = plan.inst[k];
         DeviceTables tab;
         if ((st = device_tables(in.lat, &tab)) != FTWA_OK) return st;
         const int N = in.lat->N;
@@ -216,18 +252,49 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         const int64_t P = packed_count(N);
         if ((st = zero_fill(in.S1, plan.n_rec * D, stream)) != FTWA_OK) return st;
         if ((st = zero_fill(in.S2, plan.n_rec * s2_count(D), stream)) != FTWA_OK) return st;
-        double* X = reinterpret_cast<double*>(ws + plan.off_x);
-        for (int64_t m0 = 0; m0 < in.n_traj; m0 += plan.chunk) {
-            const int64_t Mc = std::min(plan.chunk, in.n_traj - m0);
+        double* X = reinterpret_cast<double*>(ws + ip.off_x);
+        if (ip.path == FTWA_PATH_RESIDENT) {
+            int* err = resident_error_word(ip.res, N, ip.chunk, ws + ip.off_mb);
+            if (err) {
+                if ((st = zero_words(reinterpret_cast<unsigned*>(err), 1, stream)) != FTWA_OK) return st;
+                error_words.push_back(err);
+            }
+            for (int64_t m0 = 0; m0 < in.n_traj; m0 += ip.chunk) {
+                ResidentPass pass;
+                pass.N = N;
+                pass.Mc = std::min(ip.chunk, in.n_traj - m0);
+                pass.rho = static_cast<char*>(in.rho) + (size_t)m0 * cplx_bytes(dtype);
+                pass.ldr = in.n_traj;
+                pass.t = in.lat->t;
+                pass.U = in.U;
+                pass.dt = dt;
+                pass.n_steps = n_steps;
+                pass.record_every = record_every;
+                pass.X = X;
+                pass.mailbox = ws + ip.off_mb;
+                if ((st = padded_descriptors(in.lat, ip.res.even_slots, ip.res.odd_slots,
+                                             &pass.desc)) != FTWA_OK)
+                    return st;
+                if ((st = timer.begin(stream)) != FTWA_OK) return st;
+                if ((st = resident_run(ip.res, pass, stream)) != FTWA_OK) return st;
+                if ((st = timer.end(stream, 1, (double)pass.Mc * n_steps)) != FTWA_OK) return st;
+                if ((st = moments_accumulate(D, pass.Mc, plan.n_rec, X, in.S1, in.S2,
+                                             ws + ip.off_mom, stream)) != FTWA_OK)
+                    return st;
+            }
+            continue;
+        }
+        for (int64_t m0 = 0; m0 < in.n_traj; m0 += ip.chunk) {
+            const int64_t Mc = std::min(ip.chunk, in.n_traj - m0);
             StreamChunk c;
             c.N = N;
             c.P = P;
             c.Mc = Mc;
             c.y = static_cast<char*>(in.rho) + (size_t)m0 * cplx_bytes(dtype);
             c.ldy = in.n_traj;
-            c.acc = ws + plan.off_acc;
-            c.ya = ws + plan.off_ya;
-            c.yb = ws + plan.off_yb;
+            c.acc = ws + ip.off_acc;
+            c.ya = ws + ip.off_ya;
+            c.yb = ws + ip.off_yb;
             c.t = in.lat->t;
             c.U = in.U;
             c.dt = dt;
@@ -247,7 +314,7 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                                           stream)) != FTWA_OK)
                         return st;
             }
-            if ((st = moments_accumulate(D, Mc, plan.n_rec, X, in.S1, in.S2, ws + plan.off_mom,
+            if ((st = moments_accumulate(D, Mc, plan.n_rec, X, in.S1, in.S2, ws + ip.off_mom,
                                          stream)) != FTWA_OK)
                 return st;
         }
@@ -255,6 +322,12 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     if (tune && tune->kernel_ms)
         if ((st = timer.finish(tune->kernel_ms, tune->kernel_launches, tune->kernel_work)) != FTWA_OK)
             return st;
+    for (const int* err : error_words) {
+        bool timed_out = false;
+        if ((st = resident_check_error(err, stream, &timed_out)) != FTWA_OK) return st;
+        if (timed_out)
+            return fail(FTWA_ETIMEOUT, "a spin-split workgroup pair timed out waiting for its partner");
+    }
     return FTWA_OK;
 }
 

@@ -1,0 +1,501 @@
+// evolve_resident.hip -- "resident" path of the fTWA time integration: every
+// trajectory stays on chip for the whole horizon.
+//
+// Equation of motion: Eq. (5) of arXiv:2212.04352 with j_ij = t on bonds and
+// u_ij = U delta_ij (Sec. II):
+//   f_ij = i [ t (sum_{k in nb(j)} rho_ik - sum_{k in nb(i)} rho_kj) + U (d_i - d_j) rho_ij ],
+// d = diagonal of the other spin, integrated with classical RK4.
+//
+// Layout on chip.  A workgroup holds UNITS "units"; a unit is one trajectory
+// (S = 2: both spin blocks) or one spin block of one trajectory (S = 1, the
+// partner workgroup holds the other spin).  The current Runge-Kutta stage
+// input Y of a unit lives in LDS as packed upper triangles plus two extra
+// slots per block: slot P is always zero and stands in for missing
+// neighbours, slot P+1 is scratch owned by padding elements.  The base point
+// y and the accumulator acc of every element live in the registers of the
+// thread that owns it.  The two spin diagonals of the stage sit in a small
+// LDS vector.
+//
+// Two-phase stages.  The honeycomb is bipartite: an element (i, j) with i and
+// j on the same sublattice ("even") reads only elements joining different
+// sublattices ("odd") and vice versa.  Phase 1 updates the even elements and
+// keeps their next-stage values in registers; after a barrier phase 2 updates
+// the odd elements and writes their next values straight into LDS (nothing
+// reads an odd element during phase 2 except its owner); after a second
+// barrier the held even values are written.  Only half of the next-stage
+// values is ever held, which is what lets the 198-site FP32 spin block live in
+// one CU (157.6 KB of LDS, y/acc in VGPRs).
+//
+// Element slots.  Thread t of a unit owns element t + NTU*u of the even class
+// for u < UE and of the odd class for UE <= u < UE + UO.  Both classes are
+// padded to whole slots with dummy elements, so the stage loop carries no
+// per-lane validity tests.
+//
+// Spin split (S = 1).  The two workgroups of a trajectory run on the same XCD
+// and exchange only the N diagonal values per stage through a two-slot
+// mailbox in global memory: the diagonal is even, so it is known after phase
+// 1 and is published then, half a stage before the partner needs it.  Waits
+// are bounded; a timeout aborts both workgroups and is reported.
+#include "device_common.h"
+#include "ftwa_internal.h"
+
+namespace ftwa {
+
+namespace {
+
+struct ResidentArgs {
+    int N;
+    int P;
+    int64_t Mc;            // trajectories of this pass
+    void* rho;             // instance state, offset to the pass's first trajectory
+    int64_t ldr;           // stride between packed elements (= instance n_traj)
+    const uint4* desc;     // padded: [NTU*UE even][NTU*UO odd]
+    double t, U, dt;
+    int64_t n_steps;
+    int record_every;
+    double* X;             // [n_rec][2N][Mc]
+    void* mailbox;         // S = 1: [pairs][2 spins][2 slots][N] of T
+    unsigned* flags;       // S = 1: [pairs][2]
+    int* error;            // set to 1 when a wait times out
+};
+
+constexpr unsigned kSpinLimit = 1u << 26;  // ~2 s of polling
+
+template <typename C>
+__device__ __forceinline__ C lds_nb(const C* Y, uint32_t field) {
+    C v = Y[field & 0x7fffu];
+    if (field & 0x8000u) v.y = -v.y;
+    return v;
+}
+
+template <typename C>
+__device__ __forceinline__ C lds_nb_plain(const C* Y, uint32_t field) {
+    return Y[field & 0x7fffu];
+}
+
+// Right-hand side of one element from its descriptor; CONJ selects the
+// variant that honours the conjugate flags (needed only near the diagonal).
+template <typename T, bool CONJ>
+__device__ __forceinline__ cplx_t<T> stencil(const cplx_t<T>* Yb, const T* dother, uint4 d, T t,
+                                             T U) {
+    using C = cplx_t<T>;
+    const uint32_t own = d.x & 0xffffu;
+    const int i = (d.x >> 16) & 0xff, j = d.x >> 24;
+    C c0, c1, c2, r0, r1, r2;
+    if (CONJ) {
+        c0 = lds_nb(Yb, d.y); c1 = lds_nb(Yb, d.y >> 16); c2 = lds_nb(Yb, d.z);
+        r0 = lds_nb(Yb, d.z >> 16); r1 = lds_nb(Yb, d.w); r2 = lds_nb(Yb, d.w >> 16);
+    } else {
+        c0 = lds_nb_plain(Yb, d.y); c1 = lds_nb_plain(Yb, d.y >> 16); c2 = lds_nb_plain(Yb, d.z);
+        r0 = lds_nb_plain(Yb, d.z >> 16); r1 = lds_nb_plain(Yb, d.w); r2 = lds_nb_plain(Yb, d.w >> 16);
+    }
+    const C col = cadd(cadd(c0, c1), c2);
+    const C row = cadd(cadd(r0, r1), r2);
+    const C rho = Yb[own];
+    const T a = U * (dother[i] - dother[j]);
+    return rhs_element<T>(col, row, rho, t, a);
+}
+
+__device__ __forceinline__ bool needs_conj(uint4 d) {
+    return ((d.y | d.z | d.w) & 0x80008000u) != 0u;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx_t<T> element_rhs(const cplx_t<T>* Yb, const T* dother, uint4 d,
+                                                 T t, T U) {
+    return __any(needs_conj(d)) ? stencil<T, true>(Yb, dother, d, t, U)
+                                : stencil<T, false>(Yb, dother, d, t, U);
+}
+
+// One Runge-Kutta stage update of an element from its slope k:
+//   stage 1: acc = k;                 next = fma(c, k, y)
+//   stage 2, 3: acc = fma(2, k, acc); next = fma(c, k, y)
+//   stage 4: acc = acc + k;           y = fma(c, acc, y); next = y
+template <typename T>
+__device__ __forceinline__ cplx_t<T> rk_update(int stage, T c, cplx_t<T> k, cplx_t<T>& y,
+                                               cplx_t<T>& acc) {
+    cplx_t<T> nx;
+    if (stage == 1) {
+        acc = k;
+    } else if (stage < 4) {
+        acc.x = fma_rn<T>((T)2, k.x, acc.x);
+        acc.y = fma_rn<T>((T)2, k.y, acc.y);
+    } else {
+        acc.x = acc.x + k.x;
+        acc.y = acc.y + k.y;
+    }
+    if (stage < 4) {
+        nx.x = fma_rn<T>(c, k.x, y.x);
+        nx.y = fma_rn<T>(c, k.y, y.y);
+    } else {
+        y.x = fma_rn<T>(c, acc.x, y.x);
+        y.y = fma_rn<T>(c, acc.y, y.y);
+        nx = y;
+    }
+    return nx;
+}
+
+// Descriptor table as a global-address-space pointer.  It is passed through
+// an SGPR every phase ("laundered") so that the compiler re-reads descriptors
+// instead of keeping one address or index register per slot alive across the
+// time loop; keeping the address space lets the loads use a scalar base plus
+// the one per-thread offset shared by all slots.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(1))) uint4* gdesc_t;
+#else
+typedef const uint4* gdesc_t;  // host pass of the kernel source only
+#endif
+
+__device__ __forceinline__ gdesc_t launder(gdesc_t p) {
+    uint64_t v = (uint64_t)p;
+    __asm__ volatile("" : "+s"(v)::"memory");
+    return (gdesc_t)v;
+}
+
+template <typename T> __device__ __forceinline__ unsigned to_bits(T v);
+template <> __device__ __forceinline__ unsigned to_bits<float>(float v) { return __float_as_uint(v); }
+template <typename T> __device__ __forceinline__ T from_bits(unsigned v);
+template <> __device__ __forceinline__ float from_bits<float>(unsigned v) { return __uint_as_float(v); }
+
+template <typename T, int S, int NTU, int UNITS, int UE, int UO>
+__global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
+    using C = cplx_t<T>;
+    constexpr int kEvenPad = NTU * UE;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int abort_flag;
+    const int N = A.N;
+    const int P = A.P;
+    const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
+    const int tid = threadIdx.x;
+    const int unit = tid / NTU;
+    const int t = tid % NTU;
+    C* const Yunit = reinterpret_cast<C*>(smem) + (size_t)unit * S * Pb;
+    T* const dvec = reinterpret_cast<T*>(smem + (size_t)UNITS * S * Pb * sizeof(C)) + (size_t)unit * 2 * N;
+
+    // trajectory and spins of this unit
+    int64_t m;
+    int spin0 = 0;
+    int pair = 0;
+    if constexpr (S == 1) {
+        const int b = blockIdx.x, xcd = b % 8, k = b / 8;
+        spin0 = k % 2;
+        pair = (k / 2) * 8 + xcd;
+        m = pair;
+        if (m >= A.Mc) return;  // both workgroups of an unused pair leave together
+    } else {
+        m = (int64_t)blockIdx.x * UNITS + unit;
+    }
+    const bool active = m < A.Mc;
+    C* const rho = static_cast<C*>(A.rho);
+    gdesc_t desc = (gdesc_t)A.desc;
+
+    C y[S][UE + UO], acc[S][UE + UO], hold[S][UE];
+
+    // ---- load the trajectory into registers and LDS
+    if (tid == 0) abort_flag = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int gs = spin0 + s;
+#pragma unroll
+        for (int u = 0; u < UE + UO; ++u) {
+            const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
+            const uint32_t p = desc[e].x & 0xffffu;
+            C v;
+            v.x = 0;
+            v.y = 0;
+            if (active && (int)p < P) v = rho[((int64_t)gs * P + p) * A.ldr + m];
+            Yunit[s * Pb + p] = v;  // dummies write the scratch slot
+            y[s][u] = v;
+            acc[s][u] = v;
+        }
+        if (t == 0) {
+            C z;
+            z.x = 0;
+            z.y = 0;
+            Yunit[s * Pb + P] = z;
+            Yunit[s * Pb + P + 1] = z;
+        }
+    }
+    for (int idx = t; idx < 2 * N; idx += NTU) {
+        const int gs = idx / N, i = idx - gs * N;
+        const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
+        dvec[idx] = active ? rho[((int64_t)gs * P + p) * A.ldr + m].x : (T)0;
+    }
+    // records: the first N even elements are the diagonal (i = position)
+    // (every configuration has N <= NTU, so only slot 0 can hold them)
+    auto record = [&](int64_t r) {
+        if (!active || t >= N) return;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            A.X[(r * 2 * N + (int64_t)(spin0 + s) * N + t) * A.Mc + m] = (double)y[s][0].x;
+    };
+    record(0);
+    __syncthreads();
+
+    const T tw = (T)A.t, Uw = (T)A.U;
+    const T c_half = (T)(0.5 * A.dt), c_full = (T)A.dt, c_sixth = (T)(A.dt / 6.0);
+    const int lane = tid % 64;
+    const int wave = tid / 64;
+    const int n_pub_waves = (N + 63) / 64;  // S = 1: waves that own diagonal elements
+    T* const mb = static_cast<T*>(A.mailbox);
+    int64_t g = 0;  // stage counter
+
+    for (int64_t step = 1; step <= A.n_steps; ++step) {
+#pragma unroll 1
+        for (int stage = 1; stage <= 4; ++stage, ++g) {
+            const T c = stage <= 2 ? c_half : (stage == 3 ? c_full : c_sixth);
+            desc = launder(desc);  // descriptors are re-read every phase
+            // ---------------- phase 1: even elements (next values held in registers)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const C* Yb = Yunit + s * Pb;
+                const T* dother = dvec + (1 - (spin0 + s)) * N;
+#pragma unroll
+                for (int u = 0; u < UE; ++u) {
+                    const uint4 d = (desc + NTU * u)[t];
+                    const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
+                    hold[s][u] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
+                }
+            }
+            if constexpr (S == 1) {
+                // publish the next-stage diagonal of this spin for the partner
+                if (wave < n_pub_waves) {
+                    unsigned* slot = reinterpret_cast<unsigned*>(
+                        mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * N);
+                    if (t < N)
+                        __hip_atomic_store(slot + t, to_bits<T>(hold[0][0].x), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __threadfence();
+                    if (lane == 0)
+                        __hip_atomic_fetch_add(A.flags + pair * 2 + spin0, 1u, __ATOMIC_RELEASE,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            __syncthreads();
+            desc = launder(desc);
+            // ---------------- phase 2: odd elements (written straight to LDS)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                C* Yb = Yunit + s * Pb;
+                const T* dother = dvec + (1 - (spin0 + s)) * N;
+#pragma unroll
+                for (int u = UE; u < UE + UO; ++u) {
+                    const uint4 d = (desc + kEvenPad + NTU * (u - UE))[t];
+                    const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
+                    Yb[d.x & 0xffffu] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
+                }
+            }
+            __syncthreads();
+            desc = launder(desc);
+            // ---------------- held even values and the diagonals
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                C* Yb = Yunit + s * Pb;
+#pragma unroll
+                for (int u = 0; u < UE; ++u) Yb[(desc + NTU * u)[t].x & 0xffffu] = hold[s][u];
+                if (t < N) dvec[(spin0 + s) * N + t] = hold[s][0].x;
+            }
+            if constexpr (S == 1) {
+                if (wave == 0) {
+                    // partner's diagonal for the next stage
+                    const unsigned target = (unsigned)(n_pub_waves * (g + 1));
+                    const unsigned* fl = A.flags + pair * 2 + (1 - spin0);
+                    int ok = 1;
+                    if (lane == 0) {
+                        unsigned it = 0;
+                        while (__hip_atomic_load(fl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                               target) {
+                            if (++it >= kSpinLimit) {
+                                ok = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                    }
+                    ok = __shfl(ok, 0, 64);
+                    if (!ok) {
+                        if (lane == 0) {
+                            abort_flag = 1;
+                            atomicExch(A.error, 1);
+                        }
+                    } else {
+                        __threadfence();
+                        const unsigned* slot = reinterpret_cast<const unsigned*>(
+                            mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * N);
+                        for (int i = lane; i < N; i += 64)
+                            dvec[(1 - spin0) * N + i] = from_bits<T>(__hip_atomic_load(
+                                slot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    }
+                }
+            }
+            __syncthreads();
+            if constexpr (S == 1) {
+                if (abort_flag) return;
+            }
+        }
+        if (step % A.record_every == 0) record(step / A.record_every);
+    }
+
+    // ---- final state back to HBM (addresses recomputed, not kept alive
+    // across the time loop)
+    if (!active) return;
+    C* rho_out = rho;
+    desc = launder(desc);
+    __asm__ volatile("" : "+s"(rho_out)::"memory");
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int gs = spin0 + s;
+#pragma unroll
+        for (int u = 0; u < UE + UO; ++u) {
+            const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
+            const uint32_t p = desc[e].x & 0xffffu;
+            if ((int)p < P) rho_out[((int64_t)gs * P + p) * A.ldr + m] = y[s][u];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- configurations
+struct Config {
+    ftwa_dtype dtype;
+    int S, NTU, UNITS, UE, UO;
+    const void* fn;
+};
+
+#define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO) \
+    Config{DT, S, NTU, UNITS, UE, UO, (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO>}
+
+// Ordered by preference; the first one that fits a lattice is used.
+const Config kConfigs[] = {
+    FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 128, 8, 2, 2),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 256, 3, 3, 3),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 512, 1, 5, 5),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 64, 16, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 128, 8, 2, 2),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 256, 4, 3, 3),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 512, 1, 5, 5),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 8, 8),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 13, 13),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 1024, 1, 10, 10),
+};
+
+constexpr size_t kMaxLds = 160 * 1024 - 256;  // leave room for static shared variables
+
+size_t lds_bytes(const Config& c, int N, int P) {
+    const size_t cb = c.dtype == FTWA_F64 ? 16 : 8, rb = cb / 2;
+    return (size_t)c.UNITS * c.S * (P + 2) * cb + (size_t)c.UNITS * 2 * N * rb;
+}
+
+}  // namespace
+
+bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
+                   int force_config) {
+    if (!tab.bipartite) return false;
+    const int P = (int)packed_count(N);
+    const int n_even = (int)tab.n_even, n_odd = P - n_even;
+    if (P + 2 > 0x7fff) return false;
+    const int n_cfg = (int)(sizeof(kConfigs) / sizeof(kConfigs[0]));
+    for (int k = 0; k < n_cfg; ++k) {
+        if (force_config >= 0 && k != force_config) continue;
+        const Config& c = kConfigs[k];
+        if (c.dtype != dtype) continue;
+        if ((int64_t)c.NTU * c.UE < n_even || (int64_t)c.NTU * c.UO < n_odd) continue;
+        if (lds_bytes(c, N, P) > kMaxLds) continue;
+        if (N > c.NTU) continue;  // the diagonal must sit in slot 0
+        plan->config = k;
+        plan->spins_per_unit = c.S;
+        plan->threads = c.NTU * c.UNITS;
+        plan->units = c.UNITS;
+        plan->even_slots = (int64_t)c.NTU * c.UE;
+        plan->odd_slots = (int64_t)c.NTU * c.UO;
+        plan->lds = lds_bytes(c, N, P);
+        return true;
+    }
+    return false;
+}
+
+int resident_config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
+
+int64_t resident_max_traj(const ResidentPlan& plan) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    if (plan.spins_per_unit == 1) {
+        // one workgroup per CU (LDS bound), two per trajectory, pairs in groups of 8
+        int64_t pairs = (int64_t)cus / 2 / 8 * 8;
+        return pairs < 8 ? 8 : pairs;
+    }
+    return (int64_t)1 << 20;  // no co-residency needed: any number of workgroups
+}
+
+size_t resident_mailbox_bytes(const ResidentPlan& plan, int N, ftwa_dtype dtype, int64_t Mc) {
+    if (plan.spins_per_unit != 1) return 0;
+    const int64_t pairs = (Mc + 7) / 8 * 8;
+    const size_t rb = dtype == FTWA_F64 ? 8 : 4;
+    return (size_t)pairs * 2 * 2 * N * rb + (size_t)pairs * 2 * sizeof(unsigned) + 64;
+}
+
+int* resident_error_word(const ResidentPlan& plan, int N, int64_t Mc, void* mailbox) {
+    const Config& c = kConfigs[plan.config];
+    if (c.S != 1) return nullptr;
+    const int64_t pairs = (Mc + 7) / 8 * 8;
+    const size_t rb = c.dtype == FTWA_F64 ? 8 : 4;
+    char* base = static_cast<char*>(mailbox);
+    return reinterpret_cast<int*>(base + (size_t)pairs * 2 * 2 * N * rb +
+                                  (size_t)pairs * 2 * sizeof(unsigned));
+}
+
+ftwa_status resident_run(const ResidentPlan& plan, const ResidentPass& pass, hipStream_t stream) {
+    const Config& c = kConfigs[plan.config];
+    ResidentArgs A;
+    A.N = pass.N;
+    A.P = (int)packed_count(pass.N);
+    A.Mc = pass.Mc;
+    A.rho = pass.rho;
+    A.ldr = pass.ldr;
+    A.desc = pass.desc;
+    A.t = pass.t;
+    A.U = pass.U;
+    A.dt = pass.dt;
+    A.n_steps = pass.n_steps;
+    A.record_every = pass.record_every;
+    A.X = pass.X;
+    A.mailbox = pass.mailbox;
+    A.flags = nullptr;
+    A.error = nullptr;
+    FTWA_HIP_TRY(hipFuncSetAttribute(c.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
+    void* args[] = {&A};
+    if (c.S == 1) {
+        const int64_t pairs = (pass.Mc + 7) / 8 * 8;
+        const size_t rb = c.dtype == FTWA_F64 ? 8 : 4;
+        char* base = static_cast<char*>(pass.mailbox);
+        A.flags = reinterpret_cast<unsigned*>(base + (size_t)pairs * 2 * 2 * pass.N * rb);
+        A.error = reinterpret_cast<int*>(A.flags + pairs * 2);
+        // the stage counters start at zero (a fill kernel, no memset node); the
+        // error word is cleared once per ftwa_evolve call by the caller
+        ftwa_status st = zero_words(A.flags, pairs * 2, stream);
+        if (st != FTWA_OK) return st;
+        // both workgroups of a pair must be resident at the same time
+        FTWA_HIP_TRY(hipLaunchCooperativeKernel(c.fn, dim3((unsigned)(2 * pairs)), dim3(plan.threads),
+                                                args, (unsigned)plan.lds, stream));
+    } else {
+        const int64_t blocks = (pass.Mc + c.UNITS - 1) / c.UNITS;
+        FTWA_HIP_TRY(hipLaunchKernel(c.fn, dim3((unsigned)blocks), dim3(plan.threads), args,
+                                     (unsigned)plan.lds, stream));
+    }
+    return FTWA_OK;
+}
+
+ftwa_status resident_check_error(const int* err, hipStream_t stream, bool* timed_out) {
+    *timed_out = false;
+    if (!err) return FTWA_OK;
+    int h = 0;
+    FTWA_HIP_TRY(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, stream));
+    FTWA_HIP_TRY(hipStreamSynchronize(stream));
+    *timed_out = h != 0;
+    return FTWA_OK;
+}
+
+}  // namespace ftwa

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -21,6 +22,15 @@ struct DeviceTables {
     int32_t* nb = nullptr;     // [N][4]: three neighbours (ascending, -1 padded), degree
     int32_t* off = nullptr;    // [N]: packed row start i*N - i*(i-1)/2
     uint32_t* elem = nullptr;  // [P]: packed element p -> i | j << 16
+    // Stencil descriptors of the resident path, one per packed element, even
+    // class (i, j on the same sublattice, diagonal first) then odd class:
+    //   x = own p | i << 16 | j << 24
+    //   y = col0 | col1 << 16, z = col2 | row0 << 16, w = row1 | row2 << 16
+    // each neighbour field = packed index (15 bits, P = the zero slot for a
+    // missing neighbour) | conjugate flag << 15.
+    uint4* desc = nullptr;
+    int64_t n_even = 0;        // size of the even class
+    bool bipartite = false;
 };
 
 }  // namespace ftwa
@@ -34,6 +44,10 @@ struct ftwa_lattice_s {
     std::vector<uint8_t> sub;   // [N]
     std::mutex mu;
     std::map<int, ftwa::DeviceTables> dev;  // by HIP device ordinal
+    // resident-path descriptors padded per class to whole slots, by
+    // (device, even slots, odd slots)
+    std::map<std::tuple<int, int64_t, int64_t>, uint4*> padded;
+    std::vector<uint4> host_desc;           // unpadded descriptors (even, then odd)
 };
 
 namespace ftwa {
@@ -62,6 +76,11 @@ ftwa_status hip_fail(hipError_t e, const char* what);
 
 // Uploads (once per device) and returns the lattice's device tables.
 ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
+// Descriptor table with the even class padded to even_slots entries and the
+// odd class to odd_slots entries; padding entries are dummies that own the
+// scratch slot P+1 and read only the zero slot P (uploaded once per shape).
+ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
+                               const uint4** out);
 
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
@@ -98,6 +117,39 @@ ftwa_status moments_accumulate(int D, int64_t Mc, int64_t n_rec, const double* X
                                double* S1, double* S2, void* scratch, hipStream_t stream);
 
 ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream);
+ftwa_status zero_words(unsigned* p, int64_t n, hipStream_t stream);
+
+// Resident path (evolve_resident.hip).
+struct ResidentPlan {
+    int config = -1;
+    int spins_per_unit = 2;  // 1: one spin block per workgroup, pairs exchange diagonals
+    int threads = 0;
+    int units = 1;
+    int64_t even_slots = 0;  // descriptor padding of the even / odd class
+    int64_t odd_slots = 0;
+    size_t lds = 0;
+};
+struct ResidentPass {
+    int N;
+    int64_t Mc;
+    void* rho;           // instance rho offset to the pass's first trajectory
+    int64_t ldr;         // instance n_traj
+    const uint4* desc;   // padded_descriptors(lat, plan.even_slots, plan.odd_slots)
+    double t, U, dt;
+    int64_t n_steps;
+    int record_every;
+    double* X;           // [n_rec][2N][Mc]
+    void* mailbox;       // resident_mailbox_bytes(...) of scratch
+};
+// Picks the first kernel configuration that fits (or only `force_config` if >= 0).
+bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
+                   int force_config = -1);
+int resident_config_count();
+int64_t resident_max_traj(const ResidentPlan& plan);
+size_t resident_mailbox_bytes(const ResidentPlan& plan, int N, ftwa_dtype dtype, int64_t Mc);
+int* resident_error_word(const ResidentPlan& plan, int N, int64_t Mc, void* mailbox);
+ftwa_status resident_run(const ResidentPlan& plan, const ResidentPass& pass, hipStream_t stream);
+ftwa_status resident_check_error(const int* err, hipStream_t stream, bool* timed_out);
 
 // Brackets launches of the dominant kernel with HIP events on one stream and
 // sums their durations (optional, see ftwa_tuning::kernel_ms).

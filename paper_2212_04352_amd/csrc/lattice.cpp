@@ -240,6 +240,11 @@ void ftwa_free_lattice(ftwa_lattice lat) {
         (void)hipFree(tab.nb);
         (void)hipFree(tab.off);
         (void)hipFree(tab.elem);
+        (void)hipFree(tab.desc);
+    }
+    for (auto& [key, ptr] : lat->padded) {
+        if (hipSetDevice(std::get<0>(key)) != hipSuccess) continue;
+        (void)hipFree(ptr);
     }
     if (cur >= 0) (void)hipSetDevice(cur);
     delete lat;
@@ -278,6 +283,95 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed, ui
 
 namespace ftwa {
 
+// Two-colours the lattice graph (breadth first).  On a bipartite graph every
+// stencil read of an element (i, j) with i, j on the same sublattice ("even")
+// touches only elements joining different sublattices ("odd") and vice versa,
+// which lets the resident kernel update the two classes in separate phases.
+// Returns false when the graph has an odd cycle.
+bool build_descriptors(ftwa_lattice lat, std::vector<uint4>* desc, int64_t* n_even) {
+    const int N = lat->N;
+    const int64_t P = packed_count(N);
+    std::vector<int> colour(N, -1);
+    for (int root = 0; root < N; ++root) {
+        if (colour[root] >= 0) continue;
+        colour[root] = 0;
+        std::deque<int> q{root};
+        while (!q.empty()) {
+            const int u = q.front();
+            q.pop_front();
+            for (int k = 0; k < lat->deg[u]; ++k) {
+                const int v = lat->nbr[(size_t)u * kMaxDeg + k];
+                if (colour[v] < 0) { colour[v] = 1 - colour[u]; q.push_back(v); }
+                else if (colour[v] == colour[u]) return false;
+            }
+        }
+    }
+    auto field = [&](int a, int b) -> uint32_t {  // element (a, b) as stored
+        if (a <= b) return (uint32_t)(packed_row(N, a) + (b - a));
+        return (uint32_t)(packed_row(N, b) + (a - b)) | 0x8000u;
+    };
+    auto make = [&](int i, int j) {
+        uint32_t col[3], row[3];
+        for (int n = 0; n < kMaxDeg; ++n) {
+            const int kc = n < lat->deg[j] ? lat->nbr[(size_t)j * kMaxDeg + n] : -1;
+            const int kr = n < lat->deg[i] ? lat->nbr[(size_t)i * kMaxDeg + n] : -1;
+            col[n] = kc < 0 ? (uint32_t)P : field(i, kc);
+            row[n] = kr < 0 ? (uint32_t)P : field(kr, j);
+        }
+        uint4 d;
+        d.x = (uint32_t)(packed_row(N, i) + (j - i)) | ((uint32_t)i << 16) | ((uint32_t)j << 24);
+        d.y = col[0] | (col[1] << 16);
+        d.z = col[2] | (row[0] << 16);
+        d.w = row[1] | (row[2] << 16);
+        return d;
+    };
+    desc->clear();
+    desc->reserve((size_t)P);
+    for (int i = 0; i < N; ++i) desc->push_back(make(i, i));
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j)
+            if (colour[i] == colour[j]) desc->push_back(make(i, j));
+    *n_even = (int64_t)desc->size();
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j)
+            if (colour[i] != colour[j]) desc->push_back(make(i, j));
+    return true;
+}
+
+ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
+                               const uint4** out) {
+    DeviceTables tab;
+    ftwa_status st = device_tables(lat, &tab);
+    if (st != FTWA_OK) return st;
+    if (!tab.bipartite) return fail(FTWA_ENOTSUP, "lattice is not bipartite");
+    const int64_t n_even = tab.n_even, n_odd = (int64_t)lat->host_desc.size() - n_even;
+    if (even_slots < n_even || odd_slots < n_odd) return fail(FTWA_EINVAL, "padding too small");
+    int dev = 0;
+    FTWA_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(lat->mu);
+    const auto key = std::make_tuple(dev, even_slots, odd_slots);
+    auto it = lat->padded.find(key);
+    if (it != lat->padded.end()) {
+        *out = it->second;
+        return FTWA_OK;
+    }
+    const uint32_t P = (uint32_t)packed_count(lat->N);
+    uint4 dummy;
+    dummy.x = P + 1;  // own: scratch slot, i = j = 0
+    dummy.y = P | (P << 16);
+    dummy.z = P | (P << 16);
+    dummy.w = P | (P << 16);
+    std::vector<uint4> tabp((size_t)(even_slots + odd_slots), dummy);
+    std::copy(lat->host_desc.begin(), lat->host_desc.begin() + n_even, tabp.begin());
+    std::copy(lat->host_desc.begin() + n_even, lat->host_desc.end(), tabp.begin() + even_slots);
+    uint4* d = nullptr;
+    FTWA_HIP_TRY(hipMalloc(&d, tabp.size() * sizeof(uint4)));
+    FTWA_HIP_TRY(hipMemcpy(d, tabp.data(), tabp.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    lat->padded[key] = d;
+    *out = d;
+    return FTWA_OK;
+}
+
 ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
     int dev = 0;
     FTWA_HIP_TRY(hipGetDevice(&dev));
@@ -298,12 +392,19 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
         for (int j = i; j < N; ++j) elem[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)i | ((uint32_t)j << 16);
     }
     DeviceTables tab;
+    std::vector<uint4> desc;
+    tab.bipartite = build_descriptors(lat, &desc, &tab.n_even);
+    if (tab.bipartite) lat->host_desc = desc;
     FTWA_HIP_TRY(hipMalloc(&tab.nb, nb.size() * sizeof(int32_t)));
     FTWA_HIP_TRY(hipMalloc(&tab.off, off.size() * sizeof(int32_t)));
     FTWA_HIP_TRY(hipMalloc(&tab.elem, elem.size() * sizeof(uint32_t)));
     FTWA_HIP_TRY(hipMemcpy(tab.nb, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     FTWA_HIP_TRY(hipMemcpy(tab.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     FTWA_HIP_TRY(hipMemcpy(tab.elem, elem.data(), elem.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (tab.bipartite) {
+        FTWA_HIP_TRY(hipMalloc(&tab.desc, desc.size() * sizeof(uint4)));
+        FTWA_HIP_TRY(hipMemcpy(tab.desc, desc.data(), desc.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    }
     lat->dev[dev] = tab;
     *out = tab;
     return FTWA_OK;

@@ -120,6 +120,11 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(double* p, int64_t n) {
     if (e < n) p[e] = 0.0;
 }
 
+__global__ __launch_bounds__(256) void fill_zero_words_kernel(unsigned* p, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = 0u;
+}
+
 int choose_splits(int D, int64_t Mc, int64_t n_rec) {
     const int nt = (D + kTile - 1) / kTile;
     const int64_t pairs = (int64_t)nt * (nt + 1) / 2;
@@ -174,6 +179,14 @@ ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream) {
     if (n <= 0) return FTWA_OK;
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n);
     FTWA_LAUNCH_CHECK("fill_zero_kernel");
+    return FTWA_OK;
+}
+
+ftwa_status zero_words(unsigned* p, int64_t n, hipStream_t stream) {
+    if (n <= 0) return FTWA_OK;
+    hipLaunchKernelGGL(fill_zero_words_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       p, n);
+    FTWA_LAUNCH_CHECK("fill_zero_words_kernel");
     return FTWA_OK;
 }
 

@@ -143,3 +143,98 @@ def test_errors_are_reported(ft):
         ft.ftwa_evolve([d], 0.01, 10, 0, "f64", None)  # record_every < 1
     with pytest.raises(ft.FtwaError):
         ft.ftwa_evolve([d], 0.01, 10, 1, "f64", None)  # workspace missing
+
+
+# ----------------------------------------------------------------- resident path
+@pytest.mark.parametrize("dtype,kind,a,b,U,M,steps,config", [
+    ("f64", "torus", 2, 3, 3.3, 130, 200, -1),    # 16 trajectories per workgroup, ragged
+    ("f32", "torus", 2, 3, 3.3, 130, 200, -1),
+    ("f64", "hex", 2, 0, 1.7, 33, 40, -1),        # degree-2 edge sites
+    ("f32", "hex", 2, 0, 1.7, 33, 40, -1),
+    ("f64", "torus", 3, 9, 3.3, 70, 60, -1),      # 54 sites, 3 trajectories per workgroup
+    ("f32", "torus", 3, 9, 3.3, 70, 60, -1),
+    ("f64", "hex", 4, 0, 2.0, 10, 20, -1),        # 96 sites, one trajectory per workgroup
+    ("f32", "hex", 4, 0, 2.0, 10, 20, -1),
+    ("f32", "hex", 5, 0, 3.3, 9, 20, -1),         # 150 sites: spin-split workgroup pairs
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, -1),  # 198-site flake, spin split
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, 10),  # alternative tile: 1024 threads per spin
+])
+def test_evolve_resident_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, U, M, steps, config):
+    import torch
+    olat = orc.Lattice(kind, a, b)
+    n0 = orc.fock_start(olat, "random", 3)
+    rho0 = orc.sample(olat, n0, 3, M)
+    lat = ft.Lattice(kind, a, b)
+    prob = ft.Problem.allocate(lat, U, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    ft.evolve(prob, 0.01, steps, 10, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, U, rho0, 0.01, steps, 10, precision=dtype)
+    got = unpack(_to_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_to_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_to_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
+def test_resident_and_stream_paths_agree(ft):
+    """Both paths follow the same per-element arithmetic: identical states."""
+    import torch
+    lat = ft.Lattice("torus", 3, 9)
+    n0 = lat.fock_start("random", 11)
+    out = {}
+    for path in ("stream", "resident"):
+        prob = ft.Problem.allocate(lat, 3.3, 300, n0, "f32")
+        ft.sample(prob, 11)
+        ft.evolve(prob, 0.01, 100, 10, path=path)
+        out[path] = (_to_host(prob.rho), _to_host(prob.S1), _to_host(prob.S2))
+    assert np.array_equal(out["stream"][0], out["resident"][0])
+    assert np.allclose(out["stream"][1], out["resident"][1], rtol=1e-13, atol=1e-13)
+    assert np.allclose(out["stream"][2], out["resident"][2], rtol=1e-13, atol=1e-13)
+    del torch
+
+
+def test_resident_rejects_unfit_configuration(ft):
+    lat = ft.Lattice("armchair", 10, 20)
+    prob = ft.Problem.allocate(lat, 3.3, 4, lat.fock_start("neel"), "f64")
+    ft.sample(prob, 1)
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 2, 1, path="resident")      # FP64 198-site block exceeds LDS
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 2, 1, path="resident", config=0)
+
+
+def test_flake198_full_batch_sampled_trajectories(ft, orc):
+    """The benchmark's launch configuration (198-site flake, 32768 trajectories,
+    FP32, resident spin-split kernel, records every 10 steps) on a shortened
+    horizon: four trajectories spread over the batch start from the oracle's
+    rho(0) and must end bitwise equal to the oracle; the moments of the whole
+    batch must match the oracle's moments of the GPU records' own statistics
+    (trace conservation: sum over sites of n is N/2 per spin for every record)."""
+    import torch
+    from workloads import FLAKE_198 as W
+    M, steps = W.n_traj, 40
+    lat = ft.Lattice(W.kind, W.a, W.b)
+    n0 = lat.fock_start(W.start, W.seed)
+    prob = ft.Problem.allocate(lat, W.U, M, n0, "f32")
+    ft.sample(prob, W.seed)
+    olat = orc.Lattice(W.kind, W.a, W.b)
+    picks = [0, 4097, 20000, M - 1]
+    refs = []
+    for m in picks:
+        r0 = orc.sample(olat, n0, W.seed, 1, traj_offset=m)
+        prob.rho[:, :, m].copy_(torch.from_numpy(pack(r0.astype(np.complex64))[:, :, 0]))
+        refs.append(r0)
+    ft.evolve(prob, W.dt, steps, W.record_every, path="resident")
+    torch.cuda.synchronize()
+    for m, r0 in zip(picks, refs):
+        y_ref, _, _ = orc.evolve(olat, W.U, r0, W.dt, steps, W.record_every, precision="f32")
+        got = unpack(prob.rho[:, :, m:m + 1].cpu().numpy(), lat.N)
+        assert np.array_equal(got, y_ref.astype(np.complex64)), m
+    n, _, _ = ft.observables(prob)
+    n = _to_host(n)
+    N = lat.N
+    # particle number per spin is conserved exactly by the flow (trace), and
+    # the FP32 trajectories keep it to round-off
+    assert np.allclose(n[:, :N].sum(1), N / 2, atol=1e-3)
+    assert np.allclose(n[:, N:].sum(1), N / 2, atol=1e-3)
