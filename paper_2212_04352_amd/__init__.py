@@ -45,8 +45,11 @@ class Lattice:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
-            ftwa_free_lattice(h)
+        if h and ftwa_free_lattice is not None:  # module globals may be gone at exit
+            try:
+                ftwa_free_lattice(h)
+            except Exception:
+                pass
             self.handle = None
 
 

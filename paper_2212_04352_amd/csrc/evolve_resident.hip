@@ -34,8 +34,11 @@
 // Spin split (S = 1).  The two workgroups of a trajectory run on the same XCD
 // and exchange only the N diagonal values per stage through a two-slot
 // mailbox in global memory: the diagonal is even, so it is known after phase
-// 1 and is published then, half a stage before the partner needs it.  Waits
-// are bounded; a timeout aborts both workgroups and is reported.
+// 1 and is published then, half a stage before the partner needs it.  Every
+// mailbox word holds a value together with the number of the stage it belongs
+// to, written and read with single 64-bit relaxed agent-scope atomics, so no
+// fence (and no cache write-back or invalidation) is needed.  Waits are
+// bounded; a timeout aborts both workgroups and is reported.
 #include "device_common.h"
 #include "ftwa_internal.h"
 
@@ -54,8 +57,7 @@ struct ResidentArgs {
     int64_t n_steps;
     int record_every;
     double* X;             // [n_rec][2N][Mc]
-    void* mailbox;         // S = 1: [pairs][2 spins][2 slots][N] of T
-    unsigned* flags;       // S = 1: [pairs][2]
+    uint64_t* mailbox;     // S = 1: [pairs][2 spins][2 slots][N] stage-stamped words
     int* error;            // set to 1 when a wait times out
 };
 
@@ -236,8 +238,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     const T c_half = (T)(0.5 * A.dt), c_full = (T)A.dt, c_sixth = (T)(A.dt / 6.0);
     const int lane = tid % 64;
     const int wave = tid / 64;
-    const int n_pub_waves = (N + 63) / 64;  // S = 1: waves that own diagonal elements
-    T* const mb = static_cast<T*>(A.mailbox);
+    uint64_t* const mb = A.mailbox;
     int64_t g = 0;  // stage counter
 
     for (int64_t step = 1; step <= A.n_steps; ++step) {
@@ -258,17 +259,13 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 }
             }
             if constexpr (S == 1) {
-                // publish the next-stage diagonal of this spin for the partner
-                if (wave < n_pub_waves) {
-                    unsigned* slot = reinterpret_cast<unsigned*>(
-                        mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * N);
-                    if (t < N)
-                        __hip_atomic_store(slot + t, to_bits<T>(hold[0][0].x), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    __threadfence();
-                    if (lane == 0)
-                        __hip_atomic_fetch_add(A.flags + pair * 2 + spin0, 1u, __ATOMIC_RELEASE,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                // publish the next-stage diagonal of this spin for the partner:
+                // one 64-bit word per site, (stage number << 32) | value bits,
+                // written with a single relaxed agent-scope atomic store
+                if (t < N) {
+                    uint64_t* slot = mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * N;
+                    const uint64_t word = ((uint64_t)(g + 1) << 32) | to_bits<T>(hold[0][0].x);
+                    __hip_atomic_store(slot + t, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             __syncthreads();
@@ -297,34 +294,31 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             }
             if constexpr (S == 1) {
                 if (wave == 0) {
-                    // partner's diagonal for the next stage
-                    const unsigned target = (unsigned)(n_pub_waves * (g + 1));
-                    const unsigned* fl = A.flags + pair * 2 + (1 - spin0);
+                    // partner's diagonal for the next stage: poll each word until
+                    // it carries stage g+1 (bounded; two slots alternate by parity,
+                    // so a word is never overwritten before it has been read)
+                    const uint64_t* slot =
+                        mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * N;
+                    const uint32_t want = (uint32_t)(g + 1);
                     int ok = 1;
-                    if (lane == 0) {
+                    for (int i = lane; i < N; i += 64) {
+                        uint64_t w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
                         unsigned it = 0;
-                        while (__hip_atomic_load(fl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-                               target) {
+                        while ((uint32_t)(w >> 32) != want) {
                             if (++it >= kSpinLimit) {
                                 ok = 0;
                                 break;
                             }
                             __builtin_amdgcn_s_sleep(1);
+                            w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
                         }
+                        dvec[(1 - spin0) * N + i] = from_bits<T>((uint32_t)w);
                     }
-                    ok = __shfl(ok, 0, 64);
-                    if (!ok) {
-                        if (lane == 0) {
-                            abort_flag = 1;
-                            atomicExch(A.error, 1);
-                        }
-                    } else {
-                        __threadfence();
-                        const unsigned* slot = reinterpret_cast<const unsigned*>(
-                            mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * N);
-                        for (int i = lane; i < N; i += 64)
-                            dvec[(1 - spin0) * N + i] = from_bits<T>(__hip_atomic_load(
-                                slot + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (__any(!ok) && lane == 0) {
+                        abort_flag = 1;
+                        atomicExch(A.error, 1);
                     }
                 }
             }
@@ -430,21 +424,20 @@ int64_t resident_max_traj(const ResidentPlan& plan) {
     return (int64_t)1 << 20;  // no co-residency needed: any number of workgroups
 }
 
+// Spin-split scratch: the mailbox words, then the error word.
 size_t resident_mailbox_bytes(const ResidentPlan& plan, int N, ftwa_dtype dtype, int64_t Mc) {
+    (void)dtype;
     if (plan.spins_per_unit != 1) return 0;
     const int64_t pairs = (Mc + 7) / 8 * 8;
-    const size_t rb = dtype == FTWA_F64 ? 8 : 4;
-    return (size_t)pairs * 2 * 2 * N * rb + (size_t)pairs * 2 * sizeof(unsigned) + 64;
+    return (size_t)pairs * 2 * 2 * N * sizeof(uint64_t) + 64;
 }
 
 int* resident_error_word(const ResidentPlan& plan, int N, int64_t Mc, void* mailbox) {
     const Config& c = kConfigs[plan.config];
     if (c.S != 1) return nullptr;
     const int64_t pairs = (Mc + 7) / 8 * 8;
-    const size_t rb = c.dtype == FTWA_F64 ? 8 : 4;
     char* base = static_cast<char*>(mailbox);
-    return reinterpret_cast<int*>(base + (size_t)pairs * 2 * 2 * N * rb +
-                                  (size_t)pairs * 2 * sizeof(unsigned));
+    return reinterpret_cast<int*>(base + (size_t)pairs * 2 * 2 * N * sizeof(uint64_t));
 }
 
 ftwa_status resident_run(const ResidentPlan& plan, const ResidentPass& pass, hipStream_t stream) {
@@ -462,20 +455,17 @@ ftwa_status resident_run(const ResidentPlan& plan, const ResidentPass& pass, hip
     A.n_steps = pass.n_steps;
     A.record_every = pass.record_every;
     A.X = pass.X;
-    A.mailbox = pass.mailbox;
-    A.flags = nullptr;
+    A.mailbox = static_cast<uint64_t*>(pass.mailbox);
     A.error = nullptr;
     FTWA_HIP_TRY(hipFuncSetAttribute(c.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
     void* args[] = {&A};
     if (c.S == 1) {
         const int64_t pairs = (pass.Mc + 7) / 8 * 8;
-        const size_t rb = c.dtype == FTWA_F64 ? 8 : 4;
-        char* base = static_cast<char*>(pass.mailbox);
-        A.flags = reinterpret_cast<unsigned*>(base + (size_t)pairs * 2 * 2 * pass.N * rb);
-        A.error = reinterpret_cast<int*>(A.flags + pairs * 2);
-        // the stage counters start at zero (a fill kernel, no memset node); the
-        // error word is cleared once per ftwa_evolve call by the caller
-        ftwa_status st = zero_words(A.flags, pairs * 2, stream);
+        A.error = resident_error_word(plan, pass.N, pass.Mc, pass.mailbox);
+        // every word starts at stage 0, which no wait accepts (a fill kernel,
+        // no memset node); the error word is cleared once per ftwa_evolve call
+        ftwa_status st = zero_words(static_cast<unsigned*>(pass.mailbox),
+                                    pairs * 2 * 2 * pass.N * 2, stream);
         if (st != FTWA_OK) return st;
         // both workgroups of a pair must be resident at the same time
         FTWA_HIP_TRY(hipLaunchCooperativeKernel(c.fn, dim3((unsigned)(2 * pairs)), dim3(plan.threads),
