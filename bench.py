@@ -40,12 +40,17 @@ def parse():
     ap.add_argument("--horizon-steps", type=int, default=None,
                     help="override the number of RK4 steps (default: the full horizon)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "resident"])
+    ap.add_argument("--fp64-traj", type=int, default=4096,
+                    help="trajectories of the FP64 comparison (the first ones of the batch)")
     ap.add_argument("--fp64-steps", type=int, default=None,
                     help="RK4 steps of the FP64 comparison run (default: full horizon)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-traj", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-traj", type=int, default=96)
+    ap.add_argument("--cpu-steps", type=int, default=800)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a "
+                         "known-size reference dispatch for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -72,8 +77,12 @@ def counter_traffic(kernel: str, dtype: str):
     return rec.get("bytes_per_launch")
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_pass(ft, torch, W, lat, n0, dtype, M, n_steps, path, seed, workspace):
-    """One pass of the hot path; returns (problem, workspace, timing)."""
+    """One pass of the hot path; returns (problem, workspace, timing, observables)."""
     prob = ft.Problem.allocate(lat, W.U, M, n0, dtype)
     ft.sample(prob, seed)
     timing = ft.new_timing()
@@ -81,6 +90,21 @@ def run_pass(ft, torch, W, lat, n0, dtype, M, n_steps, path, seed, workspace):
                           timing=timing)
     obs = ft.observables(prob)
     return prob, workspace, timing, obs
+
+
+def resolved_path(ft, lat, dtype, path):
+    """The path ftwa_evolve takes for this lattice and dtype under `path`."""
+    if path != "auto":
+        return path
+    import torch
+    prob = ft.Problem.allocate(lat, 0.0, 1, [0.0] * (2 * lat.N), dtype)
+    try:
+        ft.evolve(prob, 0.0, 0, 1, path="resident")
+        return "resident"
+    except ft.FtwaError:
+        return "stream"
+    finally:
+        del prob, torch
 
 
 def cpu_baseline(W, n_traj, n_steps):
@@ -111,6 +135,15 @@ def main():
     from workloads import FLAKE_198 as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
     M = args.traj or W.n_traj
     n_steps = args.horizon_steps or W.n_steps
     lat = ft.Lattice(W.kind, W.a, W.b, W.t_hop)
@@ -118,29 +151,33 @@ def main():
     N = lat.N
 
     # ---------------------------------------------------------------- FP32 (headline)
+    path32 = resolved_path(ft, lat, "f32", args.path)
     ws = None
-    for _ in range(args.warmup):
-        prob, ws, _, _ = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, args.path, W.seed, ws)
+    for k in range(args.warmup):
+        log(f"warmup pass {k + 1}/{args.warmup} (f32, {path32}, {M} trajectories x {n_steps} steps)")
+        prob, ws, _, _ = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, path32, W.seed, ws)
         del prob
     torch.cuda.synchronize()
     kernel_ms = 0.0
     launches = 0
     work = 0.0
+    log(f"timing {args.steps} pass(es)")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        prob32, ws, timing, obs32 = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, args.path,
+        prob32, ws, timing, obs32 = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, path32,
                                              W.seed, ws)
         kernel_ms += timing["ms"].value
         launches += timing["launches"].value
         work += timing["work"].value
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    log(f"f32 done: {elapsed:.2f} s")
     value = M * n_steps * args.steps / elapsed
     bytes_per_ts_f32 = 2 * (2 * N * N) * 4
     avg_ms = kernel_ms / max(launches, 1)
     work_per_launch = work / max(launches, 1)
     achieved = bytes_per_ts_f32 * work_per_launch / (avg_ms * 1e-3) / 1e9
-    kernel_name = "rk4_stage_stream" if args.path in ("stream", "auto") else "rk4_resident"
+    kernel_name = "rk4_resident" if path32 == "resident" else "rk4_stage_stream"
     traffic = counter_traffic(kernel_name, "f32")
     result = {
         "metric": "trajectory*RK4-steps/s at N=198, FP32 vs FP64 plain, at stated obs. error",
@@ -157,7 +194,7 @@ def main():
         "data": "synthetic (seeded Philox Gaussian samples around a Neel Fock state)",
         "config": {"workload": W.name, "lattice": "armchair 10x20 trimmed, N=198", "U": W.U,
                    "trajectories": M, "dt": W.dt, "rk4_steps": n_steps,
-                   "record_every": W.record_every, "moments": "f64", "path": args.path},
+                   "record_every": W.record_every, "moments": "f64", "path": path32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "kernel_avg_ms": avg_ms,
@@ -168,29 +205,35 @@ def main():
 
     # ---------------------------------------------------------------- FP64 on identical samples
     if not args.no_fp64:
+        M64 = min(args.fp64_traj, M)
         steps64 = args.fp64_steps or n_steps
+        path64 = resolved_path(ft, lat, "f64", args.path)
+        log(f"f64 comparison ({path64}, first {M64} trajectories x {steps64} steps)")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        prob64, ws64, timing64, obs64 = run_pass(ft, torch, W, lat, n0, "f64", M, steps64,
-                                                 args.path, W.seed, None)
+        prob64, ws64, timing64, obs64 = run_pass(ft, torch, W, lat, n0, "f64", M64, steps64,
+                                                 path64, W.seed, None)
         torch.cuda.synchronize()
         el64 = time.perf_counter() - t0
-        v64 = M * steps64 / el64
-        n32, C32, _ = obs32
+        v64 = M64 * steps64 / el64
+        log(f"f64 done: {el64:.2f} s; f32 on the same trajectories")
+        _, _, _, obs32s = run_pass(ft, torch, W, lat, n0, "f32", M64, steps64, path32, W.seed, None)
+        n32, C32, _ = obs32s
         n64, C64, _ = obs64
-        R = n64.shape[0]
-        dn = (n32[:R] - n64).abs().amax(dim=1).cpu().numpy()
-        dC = (C32[:R] - C64).abs().amax(dim=(1, 2)).cpu().numpy()
-        times = [r * W.record_every * W.dt for r in range(R)]
+        dn = (n32 - n64).abs().amax(dim=1).cpu().numpy()
+        dC = (C32 - C64).abs().amax(dim=(1, 2)).cpu().numpy()
+        times = [r * W.record_every * W.dt for r in range(n64.shape[0])]
 
         def upto(arr, tmax):
             sel = [a for a, t in zip(arr, times) if t <= tmax + 1e-9]
             return float(max(sel)) if sel else None
 
-        result["fp64"] = {"value": v64, "rk4_steps": steps64,
+        result["fp64"] = {"value": v64, "unit": "trajectory*RK4-steps/s", "path": path64,
+                          "trajectories": M64, "rk4_steps": steps64,
                           "kernel_avg_ms": timing64["ms"].value / max(timing64["launches"].value, 1)}
         result["fp32_over_fp64"] = value / v64
         result["obs_error_fp32_vs_fp64"] = {
+            "trajectories": M64,
             "max_abs_dn": {"t<=5": upto(dn, 5), "t<=8": upto(dn, 8), "t<=10": upto(dn, 10),
                            "t<=20": upto(dn, 20)},
             "max_abs_dC": {"t<=5": upto(dC, 5), "t<=8": upto(dC, 8), "t<=10": upto(dC, 10),
@@ -199,6 +242,7 @@ def main():
         del prob64, ws64
 
     if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, {args.cpu_traj} trajectories x {args.cpu_steps} steps")
         result["cpu_baseline"] = cpu_baseline(W, args.cpu_traj, args.cpu_steps)
     print(json.dumps(result))
 
