@@ -63,9 +63,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel: str, dtype: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources (else None)."""
+def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float):
+    """HBM bytes per launch of this run from committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (calibrated against a plain copy of known size, scaled from
+    the counter run's trajectory-steps to this launch's), if the counters were
+    taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_counters.json")
     if not os.path.exists(path):
         return None
@@ -74,7 +76,7 @@ def counter_traffic(kernel: str, dtype: str):
     rec = data.get(f"{kernel}:{dtype}")
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec["bytes_per_traj_step"] * traj_steps_per_launch
 
 
 def log(msg):
@@ -178,7 +180,7 @@ def main():
     work_per_launch = work / max(launches, 1)
     achieved = bytes_per_ts_f32 * work_per_launch / (avg_ms * 1e-3) / 1e9
     kernel_name = "rk4_resident" if path32 == "resident" else "rk4_stage_stream"
-    traffic = counter_traffic(kernel_name, "f32")
+    traffic = counter_traffic(kernel_name, "f32", work_per_launch)
     result = {
         "metric": "trajectory*RK4-steps/s at N=198, FP32 vs FP64 plain, at stated obs. error",
         "value": value,
