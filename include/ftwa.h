@@ -223,8 +223,9 @@ ftwa_status ftwa_evolve_workspace_size(const ftwa_instance* inst, int n_inst,
  * path, the tiling or the batch composition.  S1/S2 are always FP64.
  * workspace: device scratch of at least ftwa_evolve_workspace_size bytes.
  * Errors: FTWA_EINVAL (sizes, NULL pointers, workspace too small),
- * FTWA_ENONFINITE if a trajectory became non-finite (reported after the
- * run; inv counts them), FTWA_EHIP on launch failure.
+ * FTWA_ENONFINITE if inv is given and a trajectory became non-finite
+ * (checked after the run; inv[r][3] counts them; this synchronises the
+ * stream), FTWA_EHIP on launch failure.
  */
 ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
                         int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,

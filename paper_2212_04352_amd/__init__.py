@@ -66,22 +66,25 @@ class Problem:
     S2: object = None
     traj_offset: int = 0
     instance: int = 0
+    track_invariants: bool = False
+    inv: object = None
 
     @classmethod
     def allocate(cls, lat: Lattice, U: float, n_traj: int, n0, dtype: str = "f64",
-                 traj_offset: int = 0, instance: int = 0, device=None):
+                 traj_offset: int = 0, instance: int = 0, device=None,
+                 track_invariants: bool = False):
         import torch
         cdt = torch.complex128 if dtype == "f64" else torch.complex64
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         n0_t = torch.as_tensor(n0, dtype=torch.float64).reshape(2, lat.N).to(dev).contiguous()
         rho = torch.empty((2, packed_count(lat.N), n_traj), dtype=cdt, device=dev)
         return cls(lat, float(U), int(n_traj), dtype, n0_t, rho, traj_offset=traj_offset,
-                   instance=instance)
+                   instance=instance, track_invariants=track_invariants)
 
     def desc(self):
         return {"lat": self.lat.handle, "U": self.U, "n_traj": self.n_traj,
                 "traj_offset": self.traj_offset, "instance": self.instance, "n0": self.n0,
-                "rho": self.rho, "S1": self.S1, "S2": self.S2}
+                "rho": self.rho, "S1": self.S1, "S2": self.S2, "inv": self.inv}
 
     def ensure_moments(self, n_rec: int):
         import torch
@@ -90,6 +93,10 @@ class Problem:
             self.S1 = torch.empty((n_rec, D), dtype=torch.float64, device=self.rho.device)
             self.S2 = torch.empty((n_rec, D * (D + 1) // 2), dtype=torch.float64,
                                   device=self.rho.device)
+        if self.track_invariants and (self.inv is None or self.inv.shape[0] != n_rec):
+            # per record: max trace drift, max Weyl-energy drift, max Frobenius
+            # drift (all vs record 0), number of non-finite trajectories
+            self.inv = torch.empty((n_rec, 4), dtype=torch.float64, device=self.rho.device)
 
 
 def sample(problems, seed: int, stream=None) -> None:

@@ -39,7 +39,8 @@ struct InstancePlan {
     ftwa_path path = FTWA_PATH_STREAM;
     ResidentPlan res;
     int64_t chunk = 0;       // trajectories per pass
-    size_t off_acc = 0, off_ya = 0, off_yb = 0, off_x = 0, off_mom = 0, off_mb = 0, total = 0;
+    size_t off_acc = 0, off_ya = 0, off_yb = 0, off_x = 0, off_mom = 0, off_mb = 0, off_inv = 0;
+    size_t total = 0;
 };
 
 struct EvolvePlan {
@@ -101,6 +102,10 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, int64_t n_steps, 
         }
         ip.off_x = off; off = align_up(off + (size_t)p.n_rec * D * chunk * sizeof(double));
         ip.off_mom = off; off = align_up(off + moments_workspace_bytes(D, chunk, p.n_rec));
+        if (inst[k].inv) {  // per-trajectory hop/frob sums of every record
+            ip.off_inv = off;
+            off = align_up(off + (size_t)p.n_rec * 4 * chunk * sizeof(double));
+        }
         ip.total = off;
         p.total = std::max(p.total, off);
         p.inst.push_back(ip);
@@ -236,8 +241,6 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         return st;
     if (workspace_bytes < plan.total || (!workspace && plan.total > 0))
         return fail(FTWA_EINVAL, "workspace smaller than ftwa_evolve_workspace_size");
-    for (int k = 0; k < n_inst; ++k)
-        if (inst[k].inv) return fail(FTWA_ENOTSUP, "invariant output not built yet");
     hipStream_t stream = (hipStream_t)stream_;
     char* ws = static_cast<char*>(workspace);
     KernelTimer timer(tune && tune->kernel_ms);
@@ -252,7 +255,16 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         const int64_t P = packed_count(N);
         if ((st = zero_fill(in.S1, plan.n_rec * D, stream)) != FTWA_OK) return st;
         if ((st = zero_fill(in.S2, plan.n_rec * s2_count(D), stream)) != FTWA_OK) return st;
+        if (in.inv && (st = zero_fill(in.inv, plan.n_rec * 4, stream)) != FTWA_OK) return st;
         double* X = reinterpret_cast<double*>(ws + ip.off_x);
+        double* parts = in.inv ? reinterpret_cast<double*>(ws + ip.off_inv) : nullptr;
+        auto finish_pass = [&](int64_t Mc) -> ftwa_status {
+            ftwa_status s2 = moments_accumulate(D, Mc, plan.n_rec, X, in.S1, in.S2,
+                                                ws + ip.off_mom, stream);
+            if (s2 != FTWA_OK || !in.inv) return s2;
+            return invariants_accumulate(N, Mc, plan.n_rec, in.lat->t, in.U, X, parts, in.inv,
+                                         stream);
+        };
         if (ip.path == FTWA_PATH_RESIDENT) {
             int* err = resident_error_word(ip.res, N, ip.chunk, ws + ip.off_mb);
             if (err) {
@@ -271,6 +283,7 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 pass.n_steps = n_steps;
                 pass.record_every = record_every;
                 pass.X = X;
+                pass.inv_parts = parts;
                 pass.mailbox = ws + ip.off_mb;
                 if ((st = padded_descriptors(in.lat, ip.res.even_slots, ip.res.odd_slots,
                                              &pass.desc)) != FTWA_OK)
@@ -278,9 +291,7 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 if ((st = timer.begin(stream)) != FTWA_OK) return st;
                 if ((st = resident_run(ip.res, pass, stream)) != FTWA_OK) return st;
                 if ((st = timer.end(stream, 1, (double)pass.Mc * n_steps)) != FTWA_OK) return st;
-                if ((st = moments_accumulate(D, pass.Mc, plan.n_rec, X, in.S1, in.S2,
-                                             ws + ip.off_mom, stream)) != FTWA_OK)
-                    return st;
+                if ((st = finish_pass(pass.Mc)) != FTWA_OK) return st;
             }
             continue;
         }
@@ -299,6 +310,7 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             c.U = in.U;
             c.dt = dt;
             if ((st = record_diag(c, tab, dtype, X, stream)) != FTWA_OK) return st;
+            if (parts && (st = record_inv(c, tab, dtype, parts, stream)) != FTWA_OK) return st;
             int64_t open_steps = 0;
             for (int64_t step = 1; step <= n_steps; ++step) {
                 if (open_steps == 0 && (st = timer.begin(stream)) != FTWA_OK) return st;
@@ -309,14 +321,15 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                         return st;
                     open_steps = 0;
                 }
-                if (step % record_every == 0)
-                    if ((st = record_diag(c, tab, dtype, X + (step / record_every) * D * Mc,
-                                          stream)) != FTWA_OK)
+                if (step % record_every == 0) {
+                    const int64_t r = step / record_every;
+                    if ((st = record_diag(c, tab, dtype, X + r * D * Mc, stream)) != FTWA_OK)
                         return st;
+                    if (parts && (st = record_inv(c, tab, dtype, parts + r * 4 * Mc, stream)) != FTWA_OK)
+                        return st;
+                }
             }
-            if ((st = moments_accumulate(D, Mc, plan.n_rec, X, in.S1, in.S2, ws + ip.off_mom,
-                                         stream)) != FTWA_OK)
-                return st;
+            if ((st = finish_pass(Mc)) != FTWA_OK) return st;
         }
     }
     if (tune && tune->kernel_ms)
@@ -327,6 +340,19 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         if ((st = resident_check_error(err, stream, &timed_out)) != FTWA_OK) return st;
         if (timed_out)
             return fail(FTWA_ETIMEOUT, "a spin-split workgroup pair timed out waiting for its partner");
+    }
+    // trajectories that became NaN or Inf are counted in inv[r][3]
+    for (int k = 0; k < n_inst; ++k) {
+        if (!inst[k].inv) continue;
+        std::vector<double> h((size_t)plan.n_rec * 4);
+        FTWA_HIP_TRY(hipMemcpyAsync(h.data(), inst[k].inv, h.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, stream));
+        FTWA_HIP_TRY(hipStreamSynchronize(stream));
+        for (int64_t r = 0; r < plan.n_rec; ++r)
+            if (h[(size_t)r * 4 + 3] > 0)
+                return fail(FTWA_ENONFINITE, "instance " + std::to_string(k) +
+                                                 ": a trajectory became non-finite by record " +
+                                                 std::to_string(r));
     }
     return FTWA_OK;
 }

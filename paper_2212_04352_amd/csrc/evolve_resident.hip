@@ -57,6 +57,7 @@ struct ResidentArgs {
     int64_t n_steps;
     int record_every;
     double* X;             // [n_rec][2N][Mc]
+    double* inv_parts;     // NULL or [n_rec][2 spins][hop, frob][Mc]
     uint64_t* mailbox;     // S = 1: [pairs][2 spins][2 slots][N] stage-stamped words
     int* error;            // set to 1 when a wait times out
 };
@@ -81,7 +82,7 @@ template <typename T, bool CONJ>
 __device__ __forceinline__ cplx_t<T> stencil(const cplx_t<T>* Yb, const T* dother, uint4 d, T t,
                                              T U) {
     using C = cplx_t<T>;
-    const uint32_t own = d.x & 0xffffu;
+    const uint32_t own = d.x & 0x7fffu;
     const int i = (d.x >> 16) & 0xff, j = d.x >> 24;
     C c0, c1, c2, r0, r1, r2;
     if (CONJ) {
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     constexpr int kEvenPad = NTU * UE;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int abort_flag;
+    __shared__ double red[(NTU * UNITS) / 64][2 * S];  // per-wave partial sums (records)
     const int N = A.N;
     const int P = A.P;
     const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
@@ -190,6 +192,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     const bool active = m < A.Mc;
     C* const rho = static_cast<C*>(A.rho);
     gdesc_t desc = (gdesc_t)A.desc;
+    const int lane = tid % 64;
+    const int wave = tid / 64;
 
     C y[S][UE + UO], acc[S][UE + UO], hold[S][UE];
 
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
         for (int u = 0; u < UE + UO; ++u) {
             const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-            const uint32_t p = desc[e].x & 0xffffu;
+            const uint32_t p = desc[e].x & 0x7fffu;
             C v;
             v.x = 0;
             v.y = 0;
@@ -226,18 +230,62 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     // records: the first N even elements are the diagonal (i = position)
     // (every configuration has N <= NTU, so only slot 0 can hold them)
     auto record = [&](int64_t r) {
-        if (!active || t >= N) return;
+        if (active && t < N) {
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            A.X[(r * 2 * N + (int64_t)(spin0 + s) * N + t) * A.Mc + m] = (double)y[s][0].x;
+            for (int s = 0; s < S; ++s)
+                A.X[(r * 2 * N + (int64_t)(spin0 + s) * N + t) * A.Mc + m] = (double)y[s][0].x;
+        }
+        if (A.inv_parts) {
+            // per-trajectory sums for the invariant checks, in FP64:
+            // hop = sum_i sum_{k in nb(i)} Re rho_ik (each bond twice),
+            // frob = sum_ij |rho_ij|^2 (off-diagonal elements twice)
+            double hop[S], frob[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                hop[s] = 0.0;
+                frob[s] = 0.0;
+#pragma unroll
+                for (int u = 0; u < UE + UO; ++u) {
+                    const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
+                    const uint32_t dx = desc[e].x;
+                    const double re = (double)y[s][u].x, im = (double)y[s][u].y;
+                    const bool diag = u < UE && e < N;
+                    frob[s] += diag ? re * re : 2.0 * (re * re + im * im);
+                    if (dx & 0x8000u) hop[s] += 2.0 * re;
+                }
+                for (int off = 32; off > 0; off /= 2) {
+                    hop[s] += __shfl_xor(hop[s], off, 64);
+                    frob[s] += __shfl_xor(frob[s], off, 64);
+                }
+            }
+            if (lane == 0)
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    red[wave][2 * s] = hop[s];
+                    red[wave][2 * s + 1] = frob[s];
+                }
+            __syncthreads();
+            if (t == 0 && active) {
+                constexpr int kWavesPerUnit = NTU / 64;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    double h = 0.0, f = 0.0;
+                    for (int w = 0; w < kWavesPerUnit; ++w) {
+                        h += red[unit * kWavesPerUnit + w][2 * s];
+                        f += red[unit * kWavesPerUnit + w][2 * s + 1];
+                    }
+                    const int64_t base = ((r * 2 + spin0 + s) * 2) * A.Mc + m;
+                    A.inv_parts[base] = h;
+                    A.inv_parts[base + A.Mc] = f;
+                }
+            }
+        }
     };
     record(0);
     __syncthreads();
 
     const T tw = (T)A.t, Uw = (T)A.U;
     const T c_half = (T)(0.5 * A.dt), c_full = (T)A.dt, c_sixth = (T)(A.dt / 6.0);
-    const int lane = tid % 64;
-    const int wave = tid / 64;
     uint64_t* const mb = A.mailbox;
     int64_t g = 0;  // stage counter
 
@@ -279,7 +327,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 for (int u = UE; u < UE + UO; ++u) {
                     const uint4 d = (desc + kEvenPad + NTU * (u - UE))[t];
                     const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
-                    Yb[d.x & 0xffffu] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
+                    Yb[d.x & 0x7fffu] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
                 }
             }
             __syncthreads();
@@ -289,7 +337,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             for (int s = 0; s < S; ++s) {
                 C* Yb = Yunit + s * Pb;
 #pragma unroll
-                for (int u = 0; u < UE; ++u) Yb[(desc + NTU * u)[t].x & 0xffffu] = hold[s][u];
+                for (int u = 0; u < UE; ++u) Yb[(desc + NTU * u)[t].x & 0x7fffu] = hold[s][u];
                 if (t < N) dvec[(spin0 + s) * N + t] = hold[s][0].x;
             }
             if constexpr (S == 1) {
@@ -342,7 +390,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
         for (int u = 0; u < UE + UO; ++u) {
             const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-            const uint32_t p = desc[e].x & 0xffffu;
+            const uint32_t p = desc[e].x & 0x7fffu;
             if ((int)p < P) rho_out[((int64_t)gs * P + p) * A.ldr + m] = y[s][u];
         }
     }
@@ -373,7 +421,7 @@ const Config kConfigs[] = {
     FTWA_RES_CFG(float, FTWA_F32, 1, 1024, 1, 10, 10),
 };
 
-constexpr size_t kMaxLds = 160 * 1024 - 256;  // leave room for static shared variables
+constexpr size_t kMaxLds = 160 * 1024 - 1024;  // leave room for static shared variables
 
 size_t lds_bytes(const Config& c, int N, int P) {
     const size_t cb = c.dtype == FTWA_F64 ? 16 : 8, rb = cb / 2;
@@ -455,6 +503,7 @@ ftwa_status resident_run(const ResidentPlan& plan, const ResidentPass& pass, hip
     A.n_steps = pass.n_steps;
     A.record_every = pass.record_every;
     A.X = pass.X;
+    A.inv_parts = pass.inv_parts;
     A.mailbox = static_cast<uint64_t*>(pass.mailbox);
     A.error = nullptr;
     FTWA_HIP_TRY(hipFuncSetAttribute(c.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));

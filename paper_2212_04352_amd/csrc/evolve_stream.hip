@@ -203,6 +203,58 @@ ftwa_status stream_step(const StreamChunk& c, const DeviceTables& tab, ftwa_dtyp
     return dtype == FTWA_F64 ? step_impl<double>(c, tab, stream) : step_impl<float>(c, tab, stream);
 }
 
+namespace {
+
+// One thread per trajectory walks every packed element of both spins (the
+// element index is uniform, so loads are coalesced over trajectories) and
+// accumulates in FP64: hop_s = sum_i sum_{k in nb(i)} Re rho_ik (each bond
+// twice) and frob_s = sum_ij |rho_ij|^2.
+template <typename T>
+__global__ __launch_bounds__(256) void record_inv_kernel(int N, int64_t P, int64_t Mc,
+                                                         const cplx_t<T>* __restrict__ y,
+                                                         int64_t ldy,
+                                                         const uint32_t* __restrict__ elem,
+                                                         const int32_t* __restrict__ nb,
+                                                         double* __restrict__ parts) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Mc) return;
+    for (int s = 0; s < 2; ++s) {
+        double hop = 0.0, frob = 0.0;
+        for (int64_t p = 0; p < P; ++p) {
+            const uint32_t ij = elem[p];
+            const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
+            const cplx_t<T> v = y[((int64_t)s * P + p) * ldy + m];
+            const double re = (double)v.x, im = (double)v.y;
+            if (i == j) {
+                frob += re * re;
+            } else {
+                frob += 2.0 * (re * re + im * im);
+                const int d = nb[i * 4 + 3];
+                bool bond = false;
+                for (int n = 0; n < d; ++n) bond = bond || nb[i * 4 + n] == j;
+                if (bond) hop += 2.0 * re;
+            }
+        }
+        parts[(s * 2) * Mc + m] = hop;
+        parts[(s * 2 + 1) * Mc + m] = frob;
+    }
+}
+
+}  // namespace
+
+ftwa_status record_inv(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
+                       double* parts, hipStream_t stream) {
+    const dim3 grid((unsigned)((c.Mc + 255) / 256)), block(256);
+    if (dtype == FTWA_F64)
+        hipLaunchKernelGGL(record_inv_kernel<double>, grid, block, 0, stream, c.N, c.P, c.Mc,
+                           static_cast<const double2*>(c.y), c.ldy, tab.elem, tab.nb, parts);
+    else
+        hipLaunchKernelGGL(record_inv_kernel<float>, grid, block, 0, stream, c.N, c.P, c.Mc,
+                           static_cast<const float2*>(c.y), c.ldy, tab.elem, tab.nb, parts);
+    FTWA_LAUNCH_CHECK("record_inv_kernel");
+    return FTWA_OK;
+}
+
 ftwa_status record_diag(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
                         double* X, hipStream_t stream) {
     (void)tab;

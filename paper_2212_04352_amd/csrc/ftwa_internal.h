@@ -24,7 +24,7 @@ struct DeviceTables {
     uint32_t* elem = nullptr;  // [P]: packed element p -> i | j << 16
     // Stencil descriptors of the resident path, one per packed element, even
     // class (i, j on the same sublattice, diagonal first) then odd class:
-    //   x = own p | i << 16 | j << 24
+    //   x = own p (15 bits) | bond flag << 15 (j is a neighbour of i) | i << 16 | j << 24
     //   y = col0 | col1 << 16, z = col2 | row0 << 16, w = row1 | row2 << 16
     // each neighbour field = packed index (15 bits, P = the zero slot for a
     // missing neighbour) | conjugate flag << 15.
@@ -109,6 +109,16 @@ ftwa_status stream_step(const StreamChunk& c, const DeviceTables& tab, ftwa_dtyp
                         hipStream_t stream);
 ftwa_status record_diag(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
                         double* X, hipStream_t stream);
+// Per-trajectory invariant sums of one record (hop and frob per spin, FP64),
+// written to parts[2 spins][2][Mc].
+ftwa_status record_inv(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
+                       double* parts, hipStream_t stream);
+// inv[r] = max/sum over the chunk's trajectories of the drifts of record r
+// from record 0 (trace, Weyl energy, Frobenius norm) and the non-finite count,
+// combined with the values already in inv (max, max, max, +).
+ftwa_status invariants_accumulate(int N, int64_t Mc, int64_t n_rec, double t, double U,
+                                  const double* X, const double* parts, double* inv,
+                                  hipStream_t stream);
 
 // Moments of the records of one chunk: S1[r] += sum_m X[r][a][m],
 // S2[r][ab] += sum_m X[r][a][m] X[r][b][m] (fixed summation order).
@@ -139,6 +149,7 @@ struct ResidentPass {
     int64_t n_steps;
     int record_every;
     double* X;           // [n_rec][2N][Mc]
+    double* inv_parts;   // NULL or [n_rec][2 spins][hop, frob][Mc]
     void* mailbox;       // resident_mailbox_bytes(...) of scratch
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).

@@ -318,8 +318,11 @@ bool build_descriptors(ftwa_lattice lat, std::vector<uint4>* desc, int64_t* n_ev
             col[n] = kc < 0 ? (uint32_t)P : field(i, kc);
             row[n] = kr < 0 ? (uint32_t)P : field(kr, j);
         }
+        bool bond = false;
+        for (int n = 0; n < lat->deg[i]; ++n) bond = bond || lat->nbr[(size_t)i * kMaxDeg + n] == j;
         uint4 d;
-        d.x = (uint32_t)(packed_row(N, i) + (j - i)) | ((uint32_t)i << 16) | ((uint32_t)j << 24);
+        d.x = (uint32_t)(packed_row(N, i) + (j - i)) | (bond ? 0x8000u : 0u) |
+              ((uint32_t)i << 16) | ((uint32_t)j << 24);
         d.y = col[0] | (col[1] << 16);
         d.z = col[2] | (row[0] << 16);
         d.w = row[1] | (row[2] << 16);

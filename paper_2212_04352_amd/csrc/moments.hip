@@ -182,6 +182,87 @@ ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream) {
     return FTWA_OK;
 }
 
+namespace {
+
+// One block per record r.  For every trajectory m of the chunk: trace of each
+// spin, the Weyl Hamiltonian of Appendix A.3 (Eq. (A9) with j_ij = t on bonds,
+// u_ij = U delta_ij),
+//   H_W = -t (hop_up + hop_dn) + U sum_i (rho_ii,up + 1/2)(rho_ii,dn + 1/2),
+// and the squared Frobenius norms, each compared with record 0.  Maxima over
+// trajectories (exact, so order-independent) and the count of trajectories
+// with a non-finite value are combined into inv[r].
+__global__ __launch_bounds__(256) void invariants_kernel(int N, int64_t Mc, double t, double U,
+                                                         const double* __restrict__ X,
+                                                         const double* __restrict__ parts,
+                                                         double* __restrict__ inv) {
+    __shared__ double red[4][256];
+    const int r = blockIdx.x;
+    const int D = 2 * N;
+    double m_tr = 0.0, m_hw = 0.0, m_fr = 0.0, bad = 0.0;
+    for (int64_t m = threadIdx.x; m < Mc; m += 256) {
+        double tr[2][2], hw[2], fr[2][2];
+        bool finite = true;
+        for (int q = 0; q < 2; ++q) {  // q = 0: record 0, q = 1: record r
+            const int64_t rr = q == 0 ? 0 : r;
+            const double* Xr = X + rr * D * Mc;
+            double inter = 0.0;
+            for (int s = 0; s < 2; ++s) {
+                double acc = 0.0;
+                for (int i = 0; i < N; ++i) acc += Xr[(int64_t)(s * N + i) * Mc + m];
+                tr[q][s] = acc;
+            }
+            for (int i = 0; i < N; ++i)
+                inter += (Xr[(int64_t)i * Mc + m] + 0.5) * (Xr[(int64_t)(N + i) * Mc + m] + 0.5);
+            const double* pr = parts + rr * 4 * Mc;
+            const double hop = pr[0 * Mc + m] + pr[2 * Mc + m];
+            hw[q] = -t * hop + U * inter;
+            fr[q][0] = pr[1 * Mc + m];
+            fr[q][1] = pr[3 * Mc + m];
+            finite = finite && isfinite(tr[q][0]) && isfinite(tr[q][1]) && isfinite(hw[q]) &&
+                     isfinite(fr[q][0]) && isfinite(fr[q][1]);
+        }
+        if (!finite) {
+            bad += 1.0;
+            continue;
+        }
+        m_tr = fmax(m_tr, fmax(fabs(tr[1][0] - tr[0][0]), fabs(tr[1][1] - tr[0][1])));
+        m_hw = fmax(m_hw, fabs(hw[1] - hw[0]));
+        m_fr = fmax(m_fr, fmax(fabs(fr[1][0] - fr[0][0]), fabs(fr[1][1] - fr[0][1])));
+    }
+    red[0][threadIdx.x] = m_tr;
+    red[1][threadIdx.x] = m_hw;
+    red[2][threadIdx.x] = m_fr;
+    red[3][threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 3; ++k)
+                red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+            red[3][threadIdx.x] += red[3][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = inv + (int64_t)r * 4;
+        o[0] = fmax(o[0], red[0][0]);
+        o[1] = fmax(o[1], red[1][0]);
+        o[2] = fmax(o[2], red[2][0]);
+        o[3] += red[3][0];
+    }
+}
+
+}  // namespace
+
+ftwa_status invariants_accumulate(int N, int64_t Mc, int64_t n_rec, double t, double U,
+                                  const double* X, const double* parts, double* inv,
+                                  hipStream_t stream) {
+    if (Mc == 0 || n_rec == 0) return FTWA_OK;
+    hipLaunchKernelGGL(invariants_kernel, dim3((unsigned)n_rec), dim3(256), 0, stream, N, Mc, t, U,
+                       X, parts, inv);
+    FTWA_LAUNCH_CHECK("invariants_kernel");
+    return FTWA_OK;
+}
+
 ftwa_status zero_words(unsigned* p, int64_t n, hipStream_t stream) {
     if (n <= 0) return FTWA_OK;
     hipLaunchKernelGGL(fill_zero_words_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
