@@ -80,6 +80,10 @@ def _load():
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_num_threads.restype = None
+    lib.oracle_evolve_tangent.argtypes = [ctypes.c_int, P(i32), P(ctypes.c_uint8), dbl, dbl, dbl,
+                                          i64, ctypes.c_int, i64, P(dbl), dbl, dbl, P(dbl),
+                                          P(dbl), P(dbl)]
+    lib.oracle_evolve_tangent.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -253,6 +257,59 @@ def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
     if rc != 0:
         raise RuntimeError(f"oracle evolve failed ({rc})")
     return y, X, inv
+
+
+def evolve_tangent(lat: Lattice, U: float, rho0: np.ndarray, dt: float, n_steps: int,
+                   record_every: int, dU: float = 0.0, dt_hop: float = 0.0, dshift=None):
+    """FP64 trajectories and their derivative along (dU, dt_hop, dshift[2][N]),
+    dshift shifting rho_ii,s(0) with the off-diagonal noise held fixed.
+    Returns (X, Xd), both [n_rec, M, 2N] diagonal records."""
+    lib = _load()
+    M = rho0.shape[0]
+    r0 = np.ascontiguousarray(rho0, dtype=np.complex128)
+    n_rec = n_records(n_steps, record_every)
+    X = np.zeros((n_rec, M, 2 * lat.N))
+    Xd = np.zeros_like(X)
+    ds = np.zeros(2 * lat.N) if dshift is None else np.ascontiguousarray(dshift, dtype=np.float64)
+    ds = ds.reshape(-1)
+    nbr = np.ascontiguousarray(lat.nbr.reshape(-1))
+    deg = np.ascontiguousarray(lat.deg)
+    dptr = ctypes.POINTER(ctypes.c_double)
+    rc = lib.oracle_evolve_tangent(lat.N, _ptr(nbr, ctypes.c_int32), _ptr(deg, ctypes.c_uint8),
+                                   lat.t, float(U), float(dt), int(n_steps), int(record_every), M,
+                                   r0.ctypes.data_as(dptr), float(dU), float(dt_hop),
+                                   ds.ctypes.data_as(dptr), X.ctypes.data_as(dptr),
+                                   Xd.ctypes.data_as(dptr))
+    if rc != 0:
+        raise RuntimeError(f"oracle tangent failed ({rc})")
+    return X, Xd
+
+
+def occupation_loss_grad(lat: Lattice, U: float, rho0: np.ndarray, dt: float, n_steps: int,
+                         record_every: int, target: np.ndarray):
+    """Loss L = sum_{r,a} (nbar_a(r) - target_a(r))^2 over the ensemble-mean
+    occupations nbar = mean_m X + 1/2 (Eq. (4)), and its gradient with respect
+    to U, t and the initial diagonal shifts [2][N], each component from one
+    tangent run (noise held fixed).  Returns (L, dU, dt, dshift[2][N])."""
+    N = lat.N
+    X, _ = evolve_tangent(lat, U, rho0, dt, n_steps, record_every)
+    nbar = X.mean(axis=1) + 0.5
+    resid = nbar - target
+    L = float(np.sum(resid * resid))
+    w = 2.0 * resid
+
+    def directional(**kw):
+        _, Xd = evolve_tangent(lat, U, rho0, dt, n_steps, record_every, **kw)
+        return float(np.sum(w * Xd.mean(axis=1)))
+
+    gU = directional(dU=1.0)
+    gt = directional(dt_hop=1.0)
+    gs = np.zeros(2 * N)
+    for a in range(2 * N):
+        e = np.zeros(2 * N)
+        e[a] = 1.0
+        gs[a] = directional(dshift=e)
+    return L, gU, gt, gs.reshape(2, N)
 
 
 def moments(X: np.ndarray):

@@ -466,3 +466,134 @@ void oracle_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/*
+ * Forward-mode derivative (tangent) of the FP64 trajectories, for the
+ * gradient of losses built on the site occupations.  Parameters: the
+ * interaction U, the hopping t, and a shift of the initial diagonal
+ * rho_ii,s(0) (the off-diagonal noise is held fixed).  The right-hand side
+ * of Eq. (5),
+ *   f_ij = i [ t (C_ij - R_ij) + U (d_i - d_j) rho_ij ],
+ *   C_ij = sum_{k in nb(j)} rho_ik,  R_ij = sum_{k in nb(i)} rho_kj,
+ *   d = diagonal of the other spin block,
+ * is differentiated term by term along (rho', U', t'):
+ *   f'_ij = i [ t' (C_ij - R_ij) + t (C'_ij - R'_ij)
+ *               + U' (d_i - d_j) rho_ij + U (d'_i - d'_j) rho_ij
+ *               + U (d_i - d_j) rho'_ij ],
+ * and carried through the classical Runge-Kutta stages by the chain rule:
+ *   k_s' = f'(Y_s, Y_s'),  Y_{s+1}' = y' + c_s k_s',
+ *   y'  <- y' + (h/6) (k1' + 2 k2' + 2 k3' + k4').
+ * Plain FP64 arithmetic in natural order (no fixed fma pattern: this is a
+ * derivative check, not a bitwise reference).
+ */
+static void tangent_rhs(int N, const int32_t* nbr, const uint8_t* deg, double t, double U,
+                        double dt_hop, double dU, const double* y, const double* yd,
+                        double* f, double* fd)
+{
+    const size_t NN2 = (size_t)N * N * 2;
+    for (int s = 0; s < 2; ++s) {
+        const double* R = y + s * NN2;
+        const double* Rd = yd + s * NN2;
+        const double* B = y + (1 - s) * NN2;
+        const double* Bd = yd + (1 - s) * NN2;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                double h_re = 0, h_im = 0, hd_re = 0, hd_im = 0;
+                for (int n = 0; n < deg[j]; ++n) {
+                    int k = nbr[j * ORC_MAXDEG + n];
+                    h_re += R[2 * (i * N + k)];
+                    h_im += R[2 * (i * N + k) + 1];
+                    hd_re += Rd[2 * (i * N + k)];
+                    hd_im += Rd[2 * (i * N + k) + 1];
+                }
+                for (int n = 0; n < deg[i]; ++n) {
+                    int k = nbr[i * ORC_MAXDEG + n];
+                    h_re -= R[2 * (k * N + j)];
+                    h_im -= R[2 * (k * N + j) + 1];
+                    hd_re -= Rd[2 * (k * N + j)];
+                    hd_im -= Rd[2 * (k * N + j) + 1];
+                }
+                const double dd = B[2 * (i * N + i)] - B[2 * (j * N + j)];
+                const double ddd = Bd[2 * (i * N + i)] - Bd[2 * (j * N + j)];
+                const double r_re = R[2 * (i * N + j)], r_im = R[2 * (i * N + j) + 1];
+                const double rd_re = Rd[2 * (i * N + j)], rd_im = Rd[2 * (i * N + j) + 1];
+                /* g = t h + U dd rho,  f = i g */
+                const double g_re = t * h_re + U * dd * r_re;
+                const double g_im = t * h_im + U * dd * r_im;
+                const double gd_re = dt_hop * h_re + t * hd_re + dU * dd * r_re +
+                                     U * ddd * r_re + U * dd * rd_re;
+                const double gd_im = dt_hop * h_im + t * hd_im + dU * dd * r_im +
+                                     U * ddd * r_im + U * dd * rd_im;
+                f[s * NN2 + 2 * (i * N + j)] = -g_im;
+                f[s * NN2 + 2 * (i * N + j) + 1] = g_re;
+                fd[s * NN2 + 2 * (i * N + j)] = -gd_im;
+                fd[s * NN2 + 2 * (i * N + j) + 1] = gd_re;
+            }
+    }
+}
+
+/*
+ * rho0: [M][2][N][N] complex FP64 (not modified); the direction is
+ * (dU, dt_hop, dshift[2][N]) with rho_ii,s(0)' = dshift[s][i].
+ * X, Xd: [n_rec][M][2N] diagonal records of rho and of its derivative.
+ */
+int oracle_evolve_tangent(int N, const int32_t* nbr, const uint8_t* deg, double t, double U,
+                          double dt, int64_t n_steps, int record_every, int64_t M,
+                          const double* rho0, double dU, double dt_hop, const double* dshift,
+                          double* X, double* Xd)
+{
+    if (N <= 0 || M < 0 || n_steps < 0 || record_every <= 0) return -1;
+    const size_t E = (size_t)2 * N * N * 2;
+    const int D = 2 * N;
+    const double ch = 0.5 * dt, cf = dt, c6 = dt / 6.0;
+    const double cs[3] = {ch, ch, cf};
+    int failed = 0;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m) {
+        double* buf = (double*)malloc(sizeof(double) * E * 8);
+        if (!buf) {
+            failed = 1;
+            continue;
+        }
+        double *y = buf, *yd = buf + E, *Y = buf + 2 * E, *Yd = buf + 3 * E;
+        double *k = buf + 4 * E, *kd = buf + 5 * E, *acc = buf + 6 * E, *accd = buf + 7 * E;
+        memcpy(y, rho0 + (size_t)m * E, sizeof(double) * E);
+        memset(yd, 0, sizeof(double) * E);
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < N; ++i) yd[s * N * N * 2 + 2 * (i * N + i)] = dshift[s * N + i];
+        int64_t r = 0;
+        for (int64_t step = 0; step <= n_steps; ++step) {
+            if (step % record_every == 0) {
+                for (int s = 0; s < 2; ++s)
+                    for (int i = 0; i < N; ++i) {
+                        const size_t o = (size_t)s * N * N * 2 + 2 * (i * N + i);
+                        X[((size_t)r * M + m) * D + s * N + i] = y[o];
+                        Xd[((size_t)r * M + m) * D + s * N + i] = yd[o];
+                    }
+                ++r;
+            }
+            if (step == n_steps) break;
+            memcpy(Y, y, sizeof(double) * E);
+            memcpy(Yd, yd, sizeof(double) * E);
+            for (int stage = 0; stage < 4; ++stage) {
+                tangent_rhs(N, nbr, deg, t, U, dt_hop, dU, Y, Yd, k, kd);
+                const double w = (stage == 0 || stage == 3) ? 1.0 : 2.0;
+                for (size_t e = 0; e < E; ++e) {
+                    acc[e] = stage == 0 ? k[e] : acc[e] + w * k[e];
+                    accd[e] = stage == 0 ? kd[e] : accd[e] + w * kd[e];
+                }
+                if (stage < 3)
+                    for (size_t e = 0; e < E; ++e) {
+                        Y[e] = y[e] + cs[stage] * k[e];
+                        Yd[e] = yd[e] + cs[stage] * kd[e];
+                    }
+            }
+            for (size_t e = 0; e < E; ++e) {
+                y[e] += c6 * acc[e];
+                yd[e] += c6 * accd[e];
+            }
+        }
+        free(buf);
+    }
+    return failed ? -2 : 0;
+}
