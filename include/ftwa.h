@@ -144,6 +144,10 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        |tr rho_s(t) - tr rho_s(0)| (max over s), |H_W(t) - H_W(0)| (Weyl
  *        Hamiltonian, Appendix A.3), | |rho|_F^2(t) - |rho|_F^2(0) | (max over
  *        s), and the count of non-finite trajectories.
+ *   n_shift [2][N] FP64 or NULL  shift of the initial diagonal: ftwa_sample
+ *        writes rho_ii,s(0) = n0[s][i] - 1/2 + n_shift[s][i] while the
+ *        off-diagonal noise amplitude uses n0 alone (the noise is held fixed
+ *        under the shift); ftwa_adjoint returns the gradient with respect to it.
  * Trajectory m of the instance has global index traj_offset + m; it keys the
  * random numbers, so any trajectory range reproduces the same trajectories.
  * `instance` enters the random-number counter (distinct streams per instance
@@ -160,11 +164,12 @@ typedef struct {
     double* S1;
     double* S2;
     double* inv;
+    const double* n_shift;
 } ftwa_instance;
 
 /*
  * ftwa_sample -- writes rho(0) of every trajectory of every instance
- * (Eq. (6)): rho_ii = n_i - 1/2; for i < j,
+ * (Eq. (6)): rho_ii = n_i - 1/2 (+ n_shift, if given); for i < j,
  *   rho_ij = xi_ij sqrt((n_i + n_j - 2 n_i n_j) / 2),
  * xi complex normal (E|xi|^2 = 1, E xi^2 = 0) by Box-Muller from two 53-bit
  * uniforms of Philox4x32-10 with counter
@@ -252,6 +257,40 @@ ftwa_status ftwa_observables(int n_sites, int64_t M, int n_rec, const double* S1
  */
 ftwa_status ftwa_unpack(int n_sites, int64_t n_traj, ftwa_dtype dtype, const void* rho,
                         void* out, void* stream);
+
+/*
+ * ftwa_adjoint_workspace_size -- bytes of device scratch ftwa_adjoint needs.
+ */
+ftwa_status ftwa_adjoint_workspace_size(const ftwa_instance* inst, int64_t n_steps,
+                                        int record_every, int ckpt_every, ftwa_dtype dtype,
+                                        int64_t traj_chunk, size_t* bytes);
+
+/*
+ * ftwa_adjoint -- gradient of a loss of the ensemble occupations
+ * nbar_a(r) = (1/n_total) sum_m rho_aa(t_r) + 1/2 (Eq. (4); a = s*N + i,
+ * t_r = r * record_every * dt) with respect to U, t and the initial diagonal
+ * shift, with the sampled noise held fixed, by the discrete adjoint of the
+ * classical Runge-Kutta map of Eq. (5) (reverse sweep over the stages,
+ * states recomputed from checkpoints every ckpt_every steps).
+ *   inst          one instance; inst->rho holds rho(0) as written by
+ *                 ftwa_sample (device, not modified); S1, S2, inv unused.
+ *   n_total       the trajectory count in the mean (>= inst->n_traj; the
+ *                 instance may be a slice of a larger ensemble).
+ *   dL_dnbar      device FP64 [n_rec][2N], n_rec = n_steps/record_every + 1.
+ *   grad          device FP64 [2 + 2N], overwritten: grad[0] = dL/dU,
+ *                 grad[1] = dL/dt, grad[2 + s*N + i] = dL/dn_shift[s][i]
+ *                 (= dL/d rho_ii,s(0)).  Accumulated in FP64 in a fixed
+ *                 order (deterministic); the adjoint state is in dtype.
+ *   traj_chunk    trajectories per pass (0 = all); smaller chunks need less
+ *                 workspace and give the same result up to the order of the
+ *                 final FP64 sums.
+ * Errors: FTWA_EINVAL (sizes, NULL pointers, workspace too small),
+ * FTWA_EHIP on launch failure.
+ */
+ftwa_status ftwa_adjoint(const ftwa_instance* inst, double dt, int64_t n_steps,
+                         int record_every, int ckpt_every, ftwa_dtype dtype, int64_t n_total,
+                         const double* dL_dnbar, double* grad, int64_t traj_chunk,
+                         void* workspace, size_t workspace_bytes, void* stream);
 
 /* ftwa_last_error -- message for the calling thread's last non-OK status. */
 const char* ftwa_last_error(void);

@@ -14,8 +14,9 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-from ._binding import (DTYPE, FtwaError, ftwa_build_lattice, ftwa_build_lattice_bonds,  # noqa: F401
-                       ftwa_evolve, ftwa_evolve_workspace_size, ftwa_fock_start, ftwa_free_lattice,
+from ._binding import (DTYPE, FtwaError, ftwa_adjoint, ftwa_adjoint_workspace_size,  # noqa: F401
+                       ftwa_build_lattice, ftwa_build_lattice_bonds, ftwa_evolve,
+                       ftwa_evolve_workspace_size, ftwa_fock_start, ftwa_free_lattice,
                        ftwa_lattice_info, ftwa_last_error, ftwa_observables, ftwa_sample,
                        ftwa_unpack, load, new_timing)
 
@@ -68,6 +69,7 @@ class Problem:
     instance: int = 0
     track_invariants: bool = False
     inv: object = None
+    n_shift: object = None   # optional [2, N] FP64 device tensor (see ftwa_instance)
 
     @classmethod
     def allocate(cls, lat: Lattice, U: float, n_traj: int, n0, dtype: str = "f64",
@@ -84,7 +86,8 @@ class Problem:
     def desc(self):
         return {"lat": self.lat.handle, "U": self.U, "n_traj": self.n_traj,
                 "traj_offset": self.traj_offset, "instance": self.instance, "n0": self.n0,
-                "rho": self.rho, "S1": self.S1, "S2": self.S2, "inv": self.inv}
+                "rho": self.rho, "S1": self.S1, "S2": self.S2, "inv": self.inv,
+                "n_shift": self.n_shift}
 
     def ensure_moments(self, n_rec: int):
         import torch
@@ -137,6 +140,26 @@ def observables(problem: Problem, n_total: int = None, stream=None):
     g2 = torch.empty((n_rec, D, D), dtype=torch.float64, device=dev)
     ftwa_observables(N, M, n_rec, problem.S1, problem.S2, n, C, g2, stream)
     return n, C, g2
+
+
+def adjoint(problem: Problem, dt: float, n_steps: int, record_every: int, ckpt_every: int,
+            dL_dnbar, n_total: int = None, traj_chunk: int = 0, workspace=None, stream=None):
+    """Gradient [2 + 2N] (dL/dU, dL/dt, dL/dn_shift[2][N]) of a loss of the
+    ensemble occupations, given dL/dnbar [n_rec, 2N] (FP64, device), by the
+    discrete adjoint of the Runge-Kutta map (ftwa_adjoint).  problem.rho must
+    hold rho(0) as sampled; it is not modified.  Returns (grad, workspace)."""
+    import torch
+    M = problem.n_traj if n_total is None else n_total
+    d = problem.desc()
+    nbytes = ftwa_adjoint_workspace_size(d, n_steps, record_every, ckpt_every, problem.dtype,
+                                         traj_chunk)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=problem.rho.device)
+    grad = torch.empty(2 + 2 * problem.lat.N, dtype=torch.float64, device=problem.rho.device)
+    dL = dL_dnbar.to(device=problem.rho.device, dtype=torch.float64).contiguous()
+    ftwa_adjoint(d, dt, n_steps, record_every, ckpt_every, problem.dtype, M, dL, grad, workspace,
+                 traj_chunk, stream)
+    return grad, workspace
 
 
 def unpack(problem: Problem, stream=None):

@@ -22,7 +22,8 @@ PATH = {"auto": 0, "stream": 1, "resident": 2}
 EXPORTS = (
     "ftwa_build_lattice", "ftwa_build_lattice_bonds", "ftwa_lattice_info", "ftwa_free_lattice",
     "ftwa_fock_start", "ftwa_sample", "ftwa_evolve_workspace_size", "ftwa_evolve",
-    "ftwa_observables", "ftwa_unpack", "ftwa_last_error",
+    "ftwa_observables", "ftwa_unpack", "ftwa_adjoint_workspace_size", "ftwa_adjoint",
+    "ftwa_last_error",
 )
 
 
@@ -44,6 +45,7 @@ class Instance(ctypes.Structure):
         ("S1", ctypes.c_void_p),
         ("S2", ctypes.c_void_p),
         ("inv", ctypes.c_void_p),
+        ("n_shift", ctypes.c_void_p),
     ]
 
 
@@ -83,6 +85,10 @@ def load() -> ctypes.CDLL:
                          vp], i32),
         "ftwa_observables": ([i32, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "ftwa_unpack": ([i32, i64, i32, vp, vp, vp], i32),
+        "ftwa_adjoint_workspace_size": ([P(Instance), i64, i32, i32, i32, i64,
+                                         P(ctypes.c_size_t)], i32),
+        "ftwa_adjoint": ([P(Instance), dbl, i64, i32, i32, i32, i64, vp, vp, i64, vp,
+                          ctypes.c_size_t, vp], i32),
         "ftwa_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -163,7 +169,8 @@ def _instances(insts):
     for k, d in enumerate(insts):
         arr[k] = Instance(d["lat"], float(d["U"]), int(d["n_traj"]), int(d.get("traj_offset", 0)),
                           int(d.get("instance", 0)), _ptr(d["n0"]), _ptr(d["rho"]),
-                          _ptr(d.get("S1")), _ptr(d.get("S2")), _ptr(d.get("inv")))
+                          _ptr(d.get("S1")), _ptr(d.get("S2")), _ptr(d.get("inv")),
+                          _ptr(d.get("n_shift")))
     return arr
 
 
@@ -219,6 +226,27 @@ def ftwa_observables(n_sites: int, M: int, n_rec: int, S1, S2, n_out, C_out=None
 def ftwa_unpack(n_sites: int, n_traj: int, dtype: str, rho, out, stream=None) -> None:
     check(load().ftwa_unpack(int(n_sites), int(n_traj), DTYPE[dtype], _ptr(rho), _ptr(out),
                              _stream(stream)), "ftwa_unpack")
+
+
+def ftwa_adjoint_workspace_size(inst, n_steps: int, record_every: int, ckpt_every: int,
+                                dtype: str, traj_chunk: int = 0) -> int:
+    arr = _instances([inst])
+    out = ctypes.c_size_t()
+    check(load().ftwa_adjoint_workspace_size(arr, int(n_steps), int(record_every),
+                                             int(ckpt_every), DTYPE[dtype], int(traj_chunk),
+                                             ctypes.byref(out)), "ftwa_adjoint_workspace_size")
+    return out.value
+
+
+def ftwa_adjoint(inst, dt: float, n_steps: int, record_every: int, ckpt_every: int, dtype: str,
+                 n_total: int, dL_dnbar, grad, workspace, traj_chunk: int = 0,
+                 stream=None) -> None:
+    arr = _instances([inst])
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    check(load().ftwa_adjoint(arr, float(dt), int(n_steps), int(record_every), int(ckpt_every),
+                              DTYPE[dtype], int(n_total), _ptr(dL_dnbar), _ptr(grad),
+                              int(traj_chunk), _ptr(workspace), nbytes, _stream(stream)),
+          "ftwa_adjoint")
 
 
 def ftwa_last_error() -> str:

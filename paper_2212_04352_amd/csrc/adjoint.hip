@@ -1,0 +1,527 @@
+// adjoint.hip -- gradient of losses of the ensemble occupations with respect
+// to U, t and the initial diagonal, by the discrete adjoint of the classical
+// Runge-Kutta map of the fTWA equation of motion (Eq. (5) of
+// arXiv:2212.04352), with the sampled noise held fixed.
+//
+// Inner product: the state of one spin block is a Hermitian matrix and
+// cotangents are taken with respect to the Frobenius inner product
+// <A, B> = Re tr(A^H B); a cotangent is then itself Hermitian and is stored
+// in the packed layout like the state.
+//
+// The right-hand side is f_s(Y) = i[Y_s, J] + i U [D_sbar, Y_s] with
+// (Y J)_ij = t sum_{k in nb(j)} Y_ik, D = diag(Re Y_sbar).  For fixed D it is
+// linear and skew with respect to <.,.>, so its transpose is minus itself:
+//   (df^T a)_s = -f_s^lin(a_s; D from Y)
+//                + on the diagonal (k,k): -2U sum_j Im(conj(a_sbar,kj) Y_sbar,kj)
+// (the second line is the dependence of f_sbar on D_s).  Parameter
+// derivatives:
+//   <a, df/dU> = -sum_ij (d_i - d_j) Im(conj(a_ij) Y_ij)
+//   <a, df/dt> = -<L(a), Y> = -sum_ij Im(conj(g_ij) Y_ij),  g = col(a) - row(a)
+// (L = hopping part at t = 1, itself skew), each off-diagonal pair counted
+// twice in the packed sums.
+//
+// Reverse sweep of one step y -> y+ with cotangent lam of y+:
+//   a4 = h/6 lam;            mu4 = df(Y4)^T a4
+//   a3 = h/3 lam + h mu4;    mu3 = df(Y3)^T a3
+//   a2 = h/3 lam + h/2 mu3;  mu2 = df(Y2)^T a2
+//   a1 = h/6 lam + h/2 mu2;  mu1 = df(y)^T a1
+//   cotangent of y = lam + mu1 + mu2 + mu3 + mu4,
+// and theta_bar += sum_s <a_s, df/dtheta(Y_s)>.  The stage inputs
+// Y2 = y + h/2 k1, Y3 = y + h/2 k2, Y4 = y + h k3 are recomputed from y with
+// the forward arithmetic; the states y of a segment are recomputed from its
+// checkpoint.  All kernels use the trajectory-innermost layout of the stream
+// path (a wave = 64 trajectories x a run of consecutive packed elements).
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+#include "ftwa_internal.h"
+
+namespace ftwa {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kElemsPerWave = 16;
+
+struct WaveGrid {
+    int64_t n_elem_chunks = 0;  // ceil(2P / kElemsPerWave)
+    int64_t n_work = 0;         // waves
+    int64_t blocks_per_xcd = 0;
+};
+
+WaveGrid make_grid(int64_t P, int64_t Mc) {
+    WaveGrid g;
+    g.n_elem_chunks = (2 * P + kElemsPerWave - 1) / kElemsPerWave;
+    g.n_work = ((Mc + 63) / 64) * g.n_elem_chunks;
+    const int64_t n_blocks = (g.n_work + kWavesPerBlock - 1) / kWavesPerBlock;
+    g.blocks_per_xcd = (n_blocks + 7) / 8;
+    return g;
+}
+
+dim3 grid_dim(const WaveGrid& g) { return dim3((unsigned)(g.blocks_per_xcd * 8)); }
+
+__device__ __forceinline__ int64_t prow(int N, int i) {
+    return (int64_t)i * N - (int64_t)i * (i - 1) / 2;
+}
+
+// (element chunk, trajectory) of this lane; consecutive virtual blocks run on
+// one XCD (blocks are dealt round-robin to the 8 XCDs).
+struct Lane {
+    int64_t chunk, m;
+    bool active, valid;
+};
+__device__ __forceinline__ Lane lane_work(const WaveGrid g, int64_t Mc) {
+    const int64_t xcd = blockIdx.x % 8;
+    const int64_t vblock = xcd * g.blocks_per_xcd + blockIdx.x / 8;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const int64_t w = vblock * kWavesPerBlock + wave;
+    Lane l;
+    l.valid = w < g.n_work;
+    const int64_t tb = l.valid ? w / g.n_elem_chunks : 0;
+    l.chunk = l.valid ? w - tb * g.n_elem_chunks : 0;
+    const int64_t m_raw = tb * 64 + threadIdx.x % 64;
+    l.active = l.valid && m_raw < Mc;
+    l.m = m_raw < Mc ? m_raw : Mc - 1;  // inactive lanes read in bounds, never write
+    return l;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx_t<T> load_el(const cplx_t<T>* X, int64_t Mc, int N, int a, int b,
+                                             int64_t m) {
+    if (a <= b) return X[(prow(N, a) + (b - a)) * Mc + m];
+    return conj(X[(prow(N, b) + (a - b)) * Mc + m]);
+}
+
+// col = sum_{k in nb(j)} X_ik and row = sum_{k in nb(i)} X_kj, ascending k
+template <typename T>
+__device__ __forceinline__ void nb_sums(const cplx_t<T>* X, int64_t Mc, int N,
+                                        const int32_t* __restrict__ nb, int i, int j, int64_t m,
+                                        cplx_t<T>& col, cplx_t<T>& row) {
+    col.x = col.y = 0;
+    row.x = row.y = 0;
+    const int dj = nb[j * 4 + 3];
+    for (int n = 0; n < dj; ++n) {
+        const cplx_t<T> v = load_el<T>(X, Mc, N, i, nb[j * 4 + n], m);
+        col = n == 0 ? v : cadd(col, v);
+    }
+    const int di = nb[i * 4 + 3];
+    for (int n = 0; n < di; ++n) {
+        const cplx_t<T> v = load_el<T>(X, Mc, N, nb[i * 4 + n], j, m);
+        row = n == 0 ? v : cadd(row, v);
+    }
+}
+
+template <typename T> struct StageInArgs {
+    int N;
+    int64_t P, Mc;
+    const int32_t* nb;
+    const uint32_t* elem;
+    T t, U, c;
+    const cplx_t<T>* yin;  // stage input Y_s
+    const cplx_t<T>* y;    // step start
+    cplx_t<T>* yout;       // Y_{s+1} = fma(c, f(Y_s), y)
+    WaveGrid g;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void stage_input_kernel(StageInArgs<T> A) {
+    const Lane l = lane_work(A.g, A.Mc);
+    if (!l.valid) return;
+    const int64_t q0 = l.chunk * kElemsPerWave;
+    const int64_t q1 = q0 + kElemsPerWave < 2 * A.P ? q0 + kElemsPerWave : 2 * A.P;
+    for (int64_t q = q0; q < q1; ++q) {
+        const int s = q >= A.P ? 1 : 0;
+        const int64_t p = q - s * A.P;
+        const uint32_t ij = A.elem[p];
+        const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
+        const cplx_t<T>* Ys = A.yin + (int64_t)s * A.P * A.Mc;
+        const cplx_t<T>* Yo = A.yin + (int64_t)(1 - s) * A.P * A.Mc;
+        cplx_t<T> col, row;
+        nb_sums<T>(Ys, A.Mc, A.N, A.nb, i, j, l.m, col, row);
+        const cplx_t<T> own = Ys[p * A.Mc + l.m];
+        const T a = A.U * (Yo[prow(A.N, i) * A.Mc + l.m].x - Yo[prow(A.N, j) * A.Mc + l.m].x);
+        const cplx_t<T> k = rhs_element<T>(col, row, own, A.t, a);
+        const int64_t e = ((int64_t)s * A.P + p) * A.Mc + l.m;
+        if (l.active) {
+            const cplx_t<T> yv = A.y[e];
+            cplx_t<T> nx;
+            nx.x = fma_rn<T>(A.c, k.x, yv.x);
+            nx.y = fma_rn<T>(A.c, k.y, yv.y);
+            A.yout[e] = nx;
+        }
+    }
+}
+
+template <typename T> struct VjpArgs {
+    int N;
+    int64_t P, Mc;
+    const int32_t* nb;
+    const uint32_t* elem;
+    T t, U;
+    const cplx_t<T>* Y;    // stage input Y_s (both spins)
+    const cplx_t<T>* a;    // cotangent a_s of k_s
+    const cplx_t<T>* lam;  // cotangent of y+ (for the next a)
+    cplx_t<T>* Lam;        // accumulating cotangent of y: Lam += mu_s
+    cplx_t<T>* a_next;     // a_{s-1} = alpha lam + beta mu_s (NULL for s = 1)
+    T alpha, beta;
+    double* partial;       // [n_elem_chunks][2][Mc]: dU, dt partial sums
+    WaveGrid g;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void vjp_kernel(VjpArgs<T> A) {
+    const Lane l = lane_work(A.g, A.Mc);
+    if (!l.valid) return;
+    const int N = A.N;
+    const int64_t Mc = A.Mc, m = l.m;
+    const int64_t q0 = l.chunk * kElemsPerWave;
+    const int64_t q1 = q0 + kElemsPerWave < 2 * A.P ? q0 + kElemsPerWave : 2 * A.P;
+    double eU = 0.0, et = 0.0;
+    for (int64_t q = q0; q < q1; ++q) {
+        const int s = q >= A.P ? 1 : 0;
+        const int64_t p = q - s * A.P;
+        const uint32_t ij = A.elem[p];
+        const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
+        const cplx_t<T>* Ys = A.Y + (int64_t)s * A.P * Mc;
+        const cplx_t<T>* Yo = A.Y + (int64_t)(1 - s) * A.P * Mc;
+        const cplx_t<T>* As = A.a + (int64_t)s * A.P * Mc;
+        cplx_t<T> col, row;
+        nb_sums<T>(As, Mc, N, A.nb, i, j, m, col, row);
+        const cplx_t<T> own_a = As[p * Mc + m];
+        const cplx_t<T> own_y = Ys[p * Mc + m];
+        const T dd = Yo[prow(N, i) * Mc + m].x - Yo[prow(N, j) * Mc + m].x;
+        const cplx_t<T> fl = rhs_element<T>(col, row, own_a, A.t, A.U * dd);
+        cplx_t<T> mu;
+        mu.x = -fl.x;
+        mu.y = -fl.y;
+        if (i == j) {
+            // dependence of the other block's equation on this diagonal
+            const cplx_t<T>* Ao = A.a + (int64_t)(1 - s) * A.P * Mc;
+            T acc = 0;
+            for (int k = 0; k < N; ++k) {
+                if (k == i) continue;
+                const cplx_t<T> av = load_el<T>(Ao, Mc, N, i, k, m);
+                const cplx_t<T> yv = load_el<T>(Yo, Mc, N, i, k, m);
+                acc = acc + (av.x * yv.y - av.y * yv.x);  // Im(conj(a) y)
+            }
+            mu.x = fma_rn<T>((T)(-2) * A.U, acc, mu.x);
+        }
+        // parameter partials in FP64
+        const double w = i == j ? 1.0 : 2.0;
+        const double im_ay = (double)own_a.x * own_y.y - (double)own_a.y * own_y.x;
+        const double gx = (double)col.x - row.x, gy = (double)col.y - row.y;
+        const double im_gy = gx * own_y.y - gy * own_y.x;
+        eU -= w * (double)dd * im_ay;
+        et -= w * im_gy;
+        const int64_t e = ((int64_t)s * A.P + p) * Mc + m;
+        if (l.active) {
+            cplx_t<T> L = A.Lam[e];
+            L.x = L.x + mu.x;
+            L.y = L.y + mu.y;
+            A.Lam[e] = L;
+            if (A.a_next) {
+                const cplx_t<T> lv = A.lam[e];
+                cplx_t<T> an;
+                an.x = fma_rn<T>(A.beta, mu.x, A.alpha * lv.x);
+                an.y = fma_rn<T>(A.beta, mu.y, A.alpha * lv.y);
+                A.a_next[e] = an;
+            }
+        }
+    }
+    if (l.active) {
+        double* pu = A.partial + (l.chunk * 2) * Mc + m;
+        pu[0] += eU;
+        pu[Mc] += et;
+    }
+}
+
+// Lam = lam, a4 = c lam (c = h/6), elementwise over both spins.
+template <typename T>
+__global__ __launch_bounds__(256) void step_init_kernel(int64_t n, const cplx_t<T>* __restrict__ lam,
+                                                        cplx_t<T>* __restrict__ Lam,
+                                                        cplx_t<T>* __restrict__ a4, T c) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const cplx_t<T> v = lam[e];
+    Lam[e] = v;
+    cplx_t<T> a;
+    a.x = c * v.x;
+    a.y = c * v.y;
+    a4[e] = a;
+}
+
+// lam_ii,s += scale * w[s*N + i] for one record (the loss's direct
+// dependence on the diagonal of y at that record).
+template <typename T>
+__global__ __launch_bounds__(256) void seed_kernel(int N, int64_t P, int64_t Mc,
+                                                   cplx_t<T>* __restrict__ lam,
+                                                   const double* __restrict__ w, double scale) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Mc) return;
+    const int a = blockIdx.y;
+    const int s = a >= N ? 1 : 0, i = a - s * N;
+    cplx_t<T>* v = lam + ((int64_t)s * P + prow(N, i)) * Mc + m;
+    v->x = v->x + (T)(scale * w[a]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void copy_state_kernel(int64_t Mc, const cplx_t<T>* __restrict__ src,
+                                                         int64_t ld_src, cplx_t<T>* __restrict__ dst,
+                                                         int64_t ld_dst) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Mc) return;
+    const int64_t e = blockIdx.y;
+    dst[e * ld_dst + m] = src[e * ld_src + m];
+}
+
+// grad[0] += sum_{chunk, m} partial[chunk][0][m], grad[1] likewise with
+// [1]; grad[2 + a] += sum_m Re lam_aa[m].  One block per output, fixed
+// order (strided per thread, then a tree): deterministic.
+template <typename T>
+__global__ __launch_bounds__(256) void final_reduce_kernel(int N, int64_t P, int64_t Mc,
+                                                           int64_t n_chunks,
+                                                           const double* __restrict__ partial,
+                                                           const cplx_t<T>* __restrict__ lam,
+                                                           double* __restrict__ grad) {
+    __shared__ double red[256];
+    const int o = blockIdx.x;
+    double acc = 0.0;
+    if (o < 2) {
+        const int64_t n = n_chunks * Mc;
+        for (int64_t x = threadIdx.x; x < n; x += 256) {
+            const int64_t c = x / Mc, m = x - c * Mc;
+            acc += partial[(c * 2 + o) * Mc + m];
+        }
+    } else {
+        const int a = o - 2;
+        const int s = a >= N ? 1 : 0, i = a - s * N;
+        const cplx_t<T>* row = lam + ((int64_t)s * P + prow(N, i)) * Mc;
+        for (int64_t m = threadIdx.x; m < Mc; m += 256) acc += (double)row[m].x;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w /= 2) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[o] += red[0];
+}
+
+struct AdjointLayout {
+    int64_t Mc = 0, n_ckpt = 0, L = 0;
+    size_t state = 0;
+    size_t off_ckpt = 0, off_seg = 0, off_w3 = 0, off_lam = 0, off_part = 0, total = 0;
+};
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+ftwa_status plan_adjoint(const ftwa_instance* inst, int64_t n_steps, int record_every,
+                         int ckpt_every, ftwa_dtype dtype, int64_t traj_chunk, AdjointLayout* out) {
+    if (!inst || !inst->lat) return fail(FTWA_EINVAL, "ftwa_adjoint: no instance or lattice");
+    if (dtype != FTWA_F64 && dtype != FTWA_F32) return fail(FTWA_EINVAL, "unknown dtype");
+    if (n_steps < 0) return fail(FTWA_EINVAL, "n_steps < 0");
+    if (record_every < 1) return fail(FTWA_EINVAL, "record_every < 1");
+    if (ckpt_every < 1) return fail(FTWA_EINVAL, "ckpt_every < 1");
+    if (inst->n_traj < 1) return fail(FTWA_EINVAL, "ftwa_adjoint: n_traj < 1");
+    if (traj_chunk < 0) return fail(FTWA_EINVAL, "traj_chunk < 0");
+    AdjointLayout a;
+    const int N = inst->lat->N;
+    const int64_t P = packed_count(N);
+    a.Mc = traj_chunk > 0 ? std::min<int64_t>(traj_chunk, inst->n_traj) : inst->n_traj;
+    a.L = std::min<int64_t>(ckpt_every, std::max<int64_t>(n_steps, 1));
+    a.n_ckpt = n_steps > 0 ? (n_steps + ckpt_every - 1) / ckpt_every : 0;
+    a.state = (size_t)2 * P * a.Mc * (dtype == FTWA_F64 ? 16 : 8);
+    const WaveGrid g = make_grid(P, a.Mc);
+    size_t off = 0;
+    a.off_ckpt = off; off = align_up(off + a.n_ckpt * a.state);
+    a.off_seg = off;  off = align_up(off + a.L * a.state);
+    a.off_w3 = off;   off = align_up(off + 3 * a.state);   // Y2, Y3, Y4 / acc, ya, yb
+    a.off_lam = off;  off = align_up(off + 4 * a.state);   // lam, Lam, a (ping-pong)
+    a.off_part = off; off = align_up(off + (size_t)g.n_elem_chunks * 2 * a.Mc * sizeof(double));
+    a.total = off;
+    *out = a;
+    return FTWA_OK;
+}
+
+template <typename T>
+ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const AdjointLayout& lay,
+                         double dt, int64_t n_steps, int record_every, int ckpt_every,
+                         int64_t n_total, const double* dL, double* grad, char* ws,
+                         hipStream_t stream) {
+    using C = cplx_t<T>;
+    const int N = in.lat->N;
+    const int64_t P = packed_count(N);
+    const int D = 2 * N;
+    const ftwa_dtype dtype = sizeof(T) == 8 ? FTWA_F64 : FTWA_F32;
+    const T h2 = (T)(0.5 * dt), h1 = (T)dt, h6 = (T)(dt / 6.0), h3 = (T)(dt / 3.0);
+    const double scale = 1.0 / (double)n_total;
+    const dim3 blk(256);
+    for (int64_t m0 = 0; m0 < in.n_traj; m0 += lay.Mc) {
+        const int64_t Mc = std::min<int64_t>(lay.Mc, in.n_traj - m0);
+        const size_t state = (size_t)2 * P * Mc;  // complex entries of one state
+        auto st_at = [&](size_t off, int64_t k) {
+            return reinterpret_cast<C*>(ws + off) + (size_t)k * state;
+        };
+        C* Y2 = st_at(lay.off_w3, 0);
+        C* Y3 = st_at(lay.off_w3, 1);
+        C* Y4 = st_at(lay.off_w3, 2);
+        C* lam = st_at(lay.off_lam, 0);
+        C* Lam = st_at(lay.off_lam, 1);
+        C* aA = st_at(lay.off_lam, 2);
+        C* aB = st_at(lay.off_lam, 3);
+        double* partial = reinterpret_cast<double*>(ws + lay.off_part);
+        const WaveGrid g = make_grid(P, Mc);
+        const dim3 cgrid((unsigned)((Mc + 255) / 256), (unsigned)(2 * P));
+        const C* rho0 = static_cast<const C*>(in.rho) + m0;
+
+        StreamChunk sc;
+        sc.N = N;
+        sc.P = P;
+        sc.Mc = Mc;
+        sc.ldy = Mc;
+        sc.acc = Y2;
+        sc.ya = Y3;
+        sc.yb = Y4;
+        sc.t = in.lat->t;
+        sc.U = in.U;
+        sc.dt = dt;
+
+        // ---- forward: checkpoints every ckpt_every steps
+        ftwa_status st;
+        for (int64_t k = 0; k < lay.n_ckpt; ++k) {
+            C* ck = st_at(lay.off_ckpt, k);
+            if (k == 0) {
+                hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc, rho0,
+                                   in.n_traj, ck, Mc);
+            } else {
+                hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc,
+                                   (const C*)st_at(lay.off_ckpt, k - 1), Mc, ck, Mc);
+                sc.y = ck;
+                for (int64_t n = 0; n < ckpt_every; ++n)
+                    if ((st = stream_step(sc, tab, dtype, stream)) != FTWA_OK) return st;
+            }
+            FTWA_LAUNCH_CHECK("copy_state_kernel");
+        }
+
+        // ---- reverse sweep
+        if ((st = zero_fill(reinterpret_cast<double*>(lam),
+                            (int64_t)(state * sizeof(C) / sizeof(double)), stream)) != FTWA_OK)
+            return st;
+        if ((st = zero_fill(partial, g.n_elem_chunks * 2 * Mc, stream)) != FTWA_OK) return st;
+        const dim3 sgrid((unsigned)((Mc + 255) / 256), (unsigned)D);
+        auto seed = [&](int64_t step) -> ftwa_status {
+            if (step % record_every != 0) return FTWA_OK;
+            hipLaunchKernelGGL(seed_kernel<T>, sgrid, blk, 0, stream, N, P, Mc, lam,
+                               dL + (step / record_every) * D, scale);
+            FTWA_LAUNCH_CHECK("seed_kernel");
+            return FTWA_OK;
+        };
+        if ((st = seed(n_steps)) != FTWA_OK) return st;
+
+        StageInArgs<T> S;
+        S.N = N; S.P = P; S.Mc = Mc; S.nb = tab.nb; S.elem = tab.elem;
+        S.t = (T)in.lat->t; S.U = (T)in.U; S.g = g;
+        VjpArgs<T> V;
+        V.N = N; V.P = P; V.Mc = Mc; V.nb = tab.nb; V.elem = tab.elem;
+        V.t = (T)in.lat->t; V.U = (T)in.U; V.partial = partial; V.g = g;
+        const int64_t n_el = (int64_t)state;
+        const dim3 egrid((unsigned)((n_el + 255) / 256));
+
+        for (int64_t k = lay.n_ckpt - 1; k >= 0; --k) {
+            const int64_t base = k * ckpt_every;
+            const int64_t L = std::min<int64_t>(ckpt_every, n_steps - base);
+            // states y_base .. y_{base+L-1} of the segment
+            hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc,
+                               (const C*)st_at(lay.off_ckpt, k), Mc, st_at(lay.off_seg, 0), Mc);
+            FTWA_LAUNCH_CHECK("copy_state_kernel");
+            for (int64_t n = 1; n < L; ++n) {
+                hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc,
+                                   (const C*)st_at(lay.off_seg, n - 1), Mc, st_at(lay.off_seg, n),
+                                   Mc);
+                sc.y = st_at(lay.off_seg, n);
+                if ((st = stream_step(sc, tab, dtype, stream)) != FTWA_OK) return st;
+            }
+            for (int64_t n = L - 1; n >= 0; --n) {
+                const C* y = st_at(lay.off_seg, n);
+                // stage inputs with the forward arithmetic
+                S.y = y;
+                S.yin = y;  S.yout = Y2; S.c = h2;
+                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S);
+                S.yin = Y2; S.yout = Y3; S.c = h2;
+                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S);
+                S.yin = Y3; S.yout = Y4; S.c = h1;
+                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S);
+                FTWA_LAUNCH_CHECK("stage_input_kernel");
+                hipLaunchKernelGGL(step_init_kernel<T>, egrid, blk, 0, stream, n_el, lam, Lam, aA,
+                                   h6);
+                FTWA_LAUNCH_CHECK("step_init_kernel");
+                V.lam = lam;
+                V.Lam = Lam;
+                V.Y = Y4; V.a = aA; V.a_next = aB; V.alpha = h3; V.beta = h1;
+                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                V.Y = Y3; V.a = aB; V.a_next = aA; V.alpha = h3; V.beta = h2;
+                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                V.Y = Y2; V.a = aA; V.a_next = aB; V.alpha = h6; V.beta = h2;
+                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                V.Y = y;  V.a = aB; V.a_next = nullptr;
+                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                FTWA_LAUNCH_CHECK("vjp_kernel");
+                std::swap(lam, Lam);
+                if ((st = seed(base + n)) != FTWA_OK) return st;
+            }
+        }
+        hipLaunchKernelGGL(final_reduce_kernel<T>, dim3((unsigned)(2 + D)), blk, 0, stream, N, P,
+                           Mc, g.n_elem_chunks, partial, lam, grad);
+        FTWA_LAUNCH_CHECK("final_reduce_kernel");
+    }
+    return FTWA_OK;
+}
+
+}  // namespace
+
+}  // namespace ftwa
+
+using namespace ftwa;
+
+extern "C" ftwa_status ftwa_adjoint_workspace_size(const ftwa_instance* inst, int64_t n_steps,
+                                                   int record_every, int ckpt_every,
+                                                   ftwa_dtype dtype, int64_t traj_chunk,
+                                                   size_t* bytes) {
+    if (!bytes) return fail(FTWA_EINVAL, "bytes is NULL");
+    AdjointLayout lay;
+    ftwa_status st = plan_adjoint(inst, n_steps, record_every, ckpt_every, dtype, traj_chunk, &lay);
+    if (st != FTWA_OK) return st;
+    *bytes = lay.total;
+    return FTWA_OK;
+}
+
+extern "C" ftwa_status ftwa_adjoint(const ftwa_instance* inst, double dt, int64_t n_steps,
+                                    int record_every, int ckpt_every, ftwa_dtype dtype,
+                                    int64_t n_total, const double* dL_dnbar, double* grad,
+                                    int64_t traj_chunk, void* workspace, size_t workspace_bytes,
+                                    void* stream_) {
+    AdjointLayout lay;
+    ftwa_status st = plan_adjoint(inst, n_steps, record_every, ckpt_every, dtype, traj_chunk, &lay);
+    if (st != FTWA_OK) return st;
+    const ftwa_instance& in = *inst;
+    if (!in.rho) return fail(FTWA_EINVAL, "ftwa_adjoint: rho is NULL");
+    if (!dL_dnbar || !grad) return fail(FTWA_EINVAL, "ftwa_adjoint: NULL dL_dnbar or grad");
+    if (n_total < in.n_traj) return fail(FTWA_EINVAL, "ftwa_adjoint: n_total < n_traj");
+    if (!workspace || workspace_bytes < lay.total)
+        return fail(FTWA_EINVAL, "ftwa_adjoint: workspace too small (" +
+                                     std::to_string(workspace_bytes) + " < " +
+                                     std::to_string(lay.total) + " bytes)");
+    DeviceTables tab;
+    if ((st = device_tables(in.lat, &tab)) != FTWA_OK) return st;
+    hipStream_t stream = (hipStream_t)stream_;
+    if ((st = zero_fill(grad, 2 + 2 * (int64_t)in.lat->N, stream)) != FTWA_OK) return st;
+    char* ws = static_cast<char*>(workspace);
+    if (dtype == FTWA_F64)
+        return adjoint_impl<double>(in, tab, lay, dt, n_steps, record_every, ckpt_every, n_total,
+                                    dL_dnbar, grad, ws, stream);
+    return adjoint_impl<float>(in, tab, lay, dt, n_steps, record_every, ckpt_every, n_total,
+                               dL_dnbar, grad, ws, stream);
+}

@@ -16,6 +16,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void sample_kernel(int N, int64_t P, int64_t n_traj,
                                                      int64_t traj_offset, uint32_t instance,
                                                      uint64_t seed, const double* __restrict__ n0,
+                                                     const double* __restrict__ shift,
                                                      const uint32_t* __restrict__ elem,
                                                      cplx_t<T>* __restrict__ rho) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -29,6 +30,7 @@ __global__ __launch_bounds__(256) void sample_kernel(int N, int64_t P, int64_t n
     double re = 0.0, im = 0.0;
     if (i == j) {
         re = ni - 0.5;
+        if (shift) re += shift[s * N + i];
     } else {
         const double var = 0.5 * ((ni + nj) - (2.0 * ni) * nj);
         if (var != 0.0) {
@@ -62,11 +64,11 @@ ftwa_status launch_sample(const ftwa_instance& in, const DeviceTables& tab, uint
     const dim3 grid((unsigned)((in.n_traj + 255) / 256), (unsigned)(2 * P));
     if (dtype == FTWA_F64)
         hipLaunchKernelGGL(sample_kernel<double>, grid, block, 0, stream, N, P, in.n_traj,
-                           in.traj_offset, in.instance, seed, in.n0, tab.elem,
+                           in.traj_offset, in.instance, seed, in.n0, in.n_shift, tab.elem,
                            static_cast<double2*>(in.rho));
     else
         hipLaunchKernelGGL(sample_kernel<float>, grid, block, 0, stream, N, P, in.n_traj,
-                           in.traj_offset, in.instance, seed, in.n0, tab.elem,
+                           in.traj_offset, in.instance, seed, in.n0, in.n_shift, tab.elem,
                            static_cast<float2*>(in.rho));
     FTWA_LAUNCH_CHECK("sample_kernel");
     return FTWA_OK;
