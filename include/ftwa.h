@@ -237,6 +237,48 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Batched launch as a HIP graph.  ftwa_evolve_graph plans the same run as
+ * ftwa_evolve (same arguments; kernel timing is not available), uploads its
+ * tables into `workspace` (synchronising `stream` once) and captures every
+ * launch of the run into a graph; nothing is computed yet.  Instances whose
+ * kernel configuration is the same are integrated by one persistent kernel
+ * per pass over a table of (instance, trajectory window) entries, so a batch
+ * of mixed lattice sizes and U values needs a handful of kernel nodes; the
+ * results are bitwise those of one ftwa_evolve per instance.
+ * ftwa_graph_launch queues the whole run on `stream` (one graph launch): it
+ * re-zeroes S1/S2/inv and integrates the current rho for n_steps steps.  The
+ * instance buffers and the workspace must stay allocated, and no other work
+ * may use the workspace, while the graph exists.  ftwa_graph_check waits for
+ * `stream` and reports what ftwa_evolve reports after its launches
+ * (FTWA_ETIMEOUT, FTWA_ENONFINITE).  Spin-split configurations rely on the
+ * GPU running no other work that would keep a pair's two workgroups from
+ * being resident together; their waits are bounded (FTWA_ETIMEOUT).
+ */
+typedef struct ftwa_graph_s* ftwa_graph;
+ftwa_status ftwa_evolve_graph(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
+                              int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
+                              void* workspace, size_t workspace_bytes, void* stream,
+                              ftwa_graph* out);
+ftwa_status ftwa_graph_launch(ftwa_graph graph, void* stream);
+ftwa_status ftwa_graph_check(ftwa_graph graph, void* stream);
+void ftwa_graph_free(ftwa_graph graph);
+
+/*
+ * ftwa_autotune -- times every resident kernel configuration that fits each
+ * distinct lattice of the instances (and the stream path) on a copy of the
+ * instance's first trajectories (rho is not modified), `probe_steps` steps
+ * each, and records the fastest per (device, lattice size, dtype); later
+ * plans with the automatic choice use it.  configs (host, NULL or [n_inst])
+ * receives the choice per instance (-1 = stream path).  Synchronises
+ * `stream`; must not be called under graph capture.  workspace: at least
+ * ftwa_autotune_workspace_size bytes.
+ */
+ftwa_status ftwa_autotune_workspace_size(const ftwa_instance* inst, int n_inst, ftwa_dtype dtype,
+                                         int probe_steps, size_t* bytes);
+ftwa_status ftwa_autotune(const ftwa_instance* inst, int n_inst, ftwa_dtype dtype, int probe_steps,
+                          void* workspace, size_t workspace_bytes, void* stream, int* configs);
+
+/*
  * ftwa_observables -- ensemble observables from the moments of M
  * trajectories (device pointers), plug-in estimators with divisor M:
  *   n_out [n_rec][D]      n_a = S1_a/M + 1/2                          (Eq. (4))

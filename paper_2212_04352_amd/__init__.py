@@ -15,10 +15,12 @@ from __future__ import annotations
 from dataclasses import dataclass
 
 from ._binding import (DTYPE, FtwaError, ftwa_adjoint, ftwa_adjoint_workspace_size,  # noqa: F401
-                       ftwa_build_lattice, ftwa_build_lattice_bonds, ftwa_evolve,
+                       ftwa_autotune, ftwa_autotune_workspace_size, ftwa_build_lattice,
+                       ftwa_build_lattice_bonds, ftwa_evolve, ftwa_evolve_graph,
                        ftwa_evolve_workspace_size, ftwa_fock_start, ftwa_free_lattice,
-                       ftwa_lattice_info, ftwa_last_error, ftwa_observables, ftwa_sample,
-                       ftwa_unpack, load, new_timing)
+                       ftwa_graph_check, ftwa_graph_free, ftwa_graph_launch, ftwa_lattice_info,
+                       ftwa_last_error, ftwa_observables, ftwa_sample, ftwa_unpack, load,
+                       new_timing)
 
 
 def packed_count(N: int) -> int:
@@ -125,6 +127,63 @@ def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str 
     ftwa_evolve(descs, dt, n_steps, record_every, dtype, workspace, path, traj_chunk, stream,
                 timing, config)
     return workspace
+
+
+class EvolveGraph:
+    """A whole ftwa_evolve run of one or more instances captured as one HIP
+    graph (ftwa_evolve_graph).  launch() integrates the current states for
+    n_steps steps and refills the moments; check() waits and reports spin-split
+    timeouts and non-finite trajectories.  Keeps the problems and the
+    workspace alive while it exists."""
+
+    def __init__(self, problems, dt: float, n_steps: int, record_every: int = 10,
+                 path: str = "auto", traj_chunk: int = 0, config: int = -1, stream=None):
+        import torch
+        problems = list(problems) if isinstance(problems, (list, tuple)) else [problems]
+        self.problems = problems
+        self.dtype = problems[0].dtype
+        n_rec = n_records(n_steps, record_every)
+        for p in problems:
+            p.ensure_moments(n_rec)
+        descs = [p.desc() for p in problems]
+        nbytes = ftwa_evolve_workspace_size(descs, n_steps, record_every, self.dtype, path,
+                                            traj_chunk, config)
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8,
+                                     device=problems[0].rho.device)
+        self.handle = ftwa_evolve_graph(descs, dt, n_steps, record_every, self.dtype,
+                                        self.workspace, path, traj_chunk, config, stream)
+
+    def launch(self, stream=None) -> None:
+        ftwa_graph_launch(self.handle, stream)
+
+    def check(self, stream=None) -> None:
+        ftwa_graph_check(self.handle, stream)
+
+    def close(self) -> None:
+        h = getattr(self, "handle", None)
+        if h and ftwa_graph_free is not None:
+            try:
+                ftwa_graph_free(h)
+            except Exception:
+                pass
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def autotune(problems, probe_steps: int = 10, stream=None):
+    """Times the kernel configurations that fit each distinct lattice of the
+    problems on copies of their first trajectories (states are not modified)
+    and records the fastest for later automatic plans; returns the chosen
+    configuration per problem (-1 = stream path)."""
+    import torch
+    problems = problems if isinstance(problems, (list, tuple)) else [problems]
+    dtype = problems[0].dtype
+    descs = [p.desc() for p in problems]
+    nbytes = ftwa_autotune_workspace_size(descs, dtype, probe_steps)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=problems[0].rho.device)
+    return ftwa_autotune(descs, dtype, probe_steps, ws, stream)
 
 
 def observables(problem: Problem, n_total: int = None, stream=None):

@@ -23,7 +23,8 @@ EXPORTS = (
     "ftwa_build_lattice", "ftwa_build_lattice_bonds", "ftwa_lattice_info", "ftwa_free_lattice",
     "ftwa_fock_start", "ftwa_sample", "ftwa_evolve_workspace_size", "ftwa_evolve",
     "ftwa_observables", "ftwa_unpack", "ftwa_adjoint_workspace_size", "ftwa_adjoint",
-    "ftwa_last_error",
+    "ftwa_evolve_graph", "ftwa_graph_launch", "ftwa_graph_check", "ftwa_graph_free",
+    "ftwa_autotune_workspace_size", "ftwa_autotune", "ftwa_last_error",
 )
 
 
@@ -85,6 +86,13 @@ def load() -> ctypes.CDLL:
                          vp], i32),
         "ftwa_observables": ([i32, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "ftwa_unpack": ([i32, i64, i32, vp, vp, vp], i32),
+        "ftwa_evolve_graph": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp,
+                               ctypes.c_size_t, vp, P(vp)], i32),
+        "ftwa_graph_launch": ([vp, vp], i32),
+        "ftwa_graph_check": ([vp, vp], i32),
+        "ftwa_graph_free": ([vp], None),
+        "ftwa_autotune_workspace_size": ([P(Instance), i32, i32, i32, P(ctypes.c_size_t)], i32),
+        "ftwa_autotune": ([P(Instance), i32, i32, i32, vp, ctypes.c_size_t, vp, P(i32)], i32),
         "ftwa_adjoint_workspace_size": ([P(Instance), i64, i32, i32, i32, i64,
                                          P(ctypes.c_size_t)], i32),
         "ftwa_adjoint": ([P(Instance), dbl, i64, i32, i32, i32, i64, vp, vp, i64, vp,
@@ -247,6 +255,48 @@ def ftwa_adjoint(inst, dt: float, n_steps: int, record_every: int, ckpt_every: i
                               DTYPE[dtype], int(n_total), _ptr(dL_dnbar), _ptr(grad),
                               int(traj_chunk), _ptr(workspace), nbytes, _stream(stream)),
           "ftwa_adjoint")
+
+
+def ftwa_evolve_graph(insts, dt: float, n_steps: int, record_every: int, dtype: str, workspace,
+                      path: str = "auto", traj_chunk: int = 0, config: int = -1,
+                      stream=None) -> int:
+    arr = _instances(insts)
+    tune = _tuning(path, traj_chunk, None, config)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    out = ctypes.c_void_p()
+    check(load().ftwa_evolve_graph(arr, len(insts), float(dt), int(n_steps), int(record_every),
+                                   DTYPE[dtype], ctypes.byref(tune), _ptr(workspace), nbytes,
+                                   _stream(stream), ctypes.byref(out)), "ftwa_evolve_graph")
+    return out.value
+
+
+def ftwa_graph_launch(graph: int, stream=None) -> None:
+    check(load().ftwa_graph_launch(graph, _stream(stream)), "ftwa_graph_launch")
+
+
+def ftwa_graph_check(graph: int, stream=None) -> None:
+    check(load().ftwa_graph_check(graph, _stream(stream)), "ftwa_graph_check")
+
+
+def ftwa_graph_free(graph: int) -> None:
+    load().ftwa_graph_free(graph)
+
+
+def ftwa_autotune_workspace_size(insts, dtype: str, probe_steps: int) -> int:
+    arr = _instances(insts)
+    out = ctypes.c_size_t()
+    check(load().ftwa_autotune_workspace_size(arr, len(insts), DTYPE[dtype], int(probe_steps),
+                                              ctypes.byref(out)), "ftwa_autotune_workspace_size")
+    return out.value
+
+
+def ftwa_autotune(insts, dtype: str, probe_steps: int, workspace, stream=None):
+    arr = _instances(insts)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    cfg = (ctypes.c_int * len(insts))()
+    check(load().ftwa_autotune(arr, len(insts), DTYPE[dtype], int(probe_steps), _ptr(workspace),
+                               nbytes, _stream(stream), cfg), "ftwa_autotune")
+    return list(cfg)
 
 
 def ftwa_last_error() -> str:

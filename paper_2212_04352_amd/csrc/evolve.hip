@@ -1,0 +1,749 @@
+// evolve.hip -- ftwa_evolve and its batched forms: the plan of a run (which
+// kernel path and configuration integrates each instance, how trajectories
+// are split into passes, where every buffer sits in the workspace), the
+// queueing of its launches, the HIP-graph form of the same launches, and the
+// autotuner that picks resident configurations by timing them.
+//
+// Batching.  Instances whose resident configuration is the same form a group;
+// each pass launches one persistent kernel per group over a device table of
+// (instance, trajectory window) entries, so mixed lattice sizes and U values
+// of a group run in one launch.  Instances that no resident configuration
+// fits run on the stream path.  The per-element arithmetic does not depend on
+// the grouping, the configuration or the pass split, so a batched run gives
+// bitwise the same trajectories as one run per instance.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "ftwa_internal.h"
+
+namespace ftwa {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+size_t cplx_bytes(ftwa_dtype d) { return d == FTWA_F64 ? 16 : 8; }
+
+constexpr size_t kRecordBudget = (size_t)4 << 30;  // FP64 record bytes per pass
+constexpr int64_t kStreamChunk = 4096;
+
+struct InstPlan {
+    ftwa_path path = FTWA_PATH_STREAM;
+    ResidentPlan res;
+    int group = -1;
+    int64_t chunk = 0;             // stream: trajectories per chunk; resident: per pass window
+    size_t off_x = 0, off_inv = 0; // resident: this instance's record regions
+};
+
+struct LaunchDesc {                // one resident launch: a group in a pass
+    int group = 0;
+    int64_t first_entry = 0;       // into the uploaded table
+    int n_entries = 0;
+    int64_t n_items = 0;
+    int64_t grid = 0;
+    double work = 0;               // trajectory-steps
+};
+
+struct GroupPlan {
+    int config = -1;
+    size_t lds = 0;
+    int Nmax = 0;
+    std::vector<int> members;
+    int64_t max_items = 0;
+    size_t off_mb = 0;
+};
+
+struct Plan {
+    int n_inst = 0;
+    int64_t n_rec = 0, n_steps = 0;
+    int record_every = 1;
+    double dt = 0;
+    ftwa_dtype dtype = FTWA_F64;
+    int n_pass = 0;
+    std::vector<InstPlan> inst;
+    std::vector<GroupPlan> groups;
+    std::vector<LaunchDesc> launches;  // pass-major
+    // stream area
+    size_t s_acc = 0, s_ya = 0, s_yb = 0, s_x = 0, s_mom = 0, s_inv = 0, s_total = 0;
+    // resident area
+    size_t r_table = 0, r_mom = 0, r_total = 0;
+    int64_t n_table = 0;
+    size_t total = 0;
+};
+
+void window(const Plan& p, const ftwa_instance& in, int k, int j, int64_t* m0, int64_t* Mc) {
+    const int64_t c = p.inst[k].chunk;
+    *m0 = std::min<int64_t>((int64_t)j * c, in.n_traj);
+    *Mc = std::min<int64_t>(c, in.n_traj - *m0);
+}
+
+ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
+                        int record_every, ftwa_dtype dtype, const ftwa_tuning* tune, Plan* out) {
+    if (dtype != FTWA_F64 && dtype != FTWA_F32) return fail(FTWA_EINVAL, "unknown dtype");
+    if (n_steps < 0) return fail(FTWA_EINVAL, "n_steps < 0");
+    if (record_every < 1) return fail(FTWA_EINVAL, "record_every < 1");
+    Plan p;
+    p.n_inst = n_inst;
+    p.n_steps = n_steps;
+    p.record_every = record_every;
+    p.dt = dt;
+    p.dtype = dtype;
+    p.n_rec = n_records(n_steps, record_every);
+    if (p.n_rec > 65535) return fail(FTWA_EINVAL, "more than 65535 records");
+    const ftwa_path want = tune ? tune->path : FTWA_PATH_AUTO;
+    if (want != FTWA_PATH_AUTO && want != FTWA_PATH_STREAM && want != FTWA_PATH_RESIDENT)
+        return fail(FTWA_EINVAL, "unknown path");
+    const int force = tune ? tune->resident_config : -1;
+    if (force >= resident_config_count()) return fail(FTWA_EINVAL, "resident_config out of range");
+    const int64_t user_chunk = tune && tune->traj_chunk > 0 ? tune->traj_chunk : 0;
+
+    // ---- path and configuration of every instance
+    std::map<int, int> group_of_config;
+    for (int k = 0; k < n_inst; ++k) {
+        InstPlan ip;
+        DeviceTables tab;
+        ftwa_status st = device_tables(inst[k].lat, &tab);
+        if (st != FTWA_OK) return st;
+        const int N = inst[k].lat->N;
+        int cfg = force;
+        bool tuned_stream = false;
+        if (cfg < 0 && want == FTWA_PATH_AUTO) {
+            int c = -1;
+            if (tuned_config(N, tab.n_even, dtype, &c)) {
+                if (c < 0) tuned_stream = true;
+                cfg = c;
+            }
+        }
+        const bool can_res = !tuned_stream && resident_plan(N, dtype, tab, &ip.res, cfg);
+        if (force >= 0 && !can_res)
+            return fail(FTWA_ENOTSUP, "the forced resident configuration does not fit");
+        if (want == FTWA_PATH_RESIDENT && !can_res)
+            return fail(FTWA_ENOTSUP, "no resident configuration fits this lattice and dtype");
+        ip.path = (want == FTWA_PATH_STREAM || !can_res) ? FTWA_PATH_STREAM : FTWA_PATH_RESIDENT;
+        if (ip.path == FTWA_PATH_RESIDENT) {
+            auto it = group_of_config.find(ip.res.config);
+            if (it == group_of_config.end()) {
+                it = group_of_config.emplace(ip.res.config, (int)p.groups.size()).first;
+                GroupPlan g;
+                g.config = ip.res.config;
+                p.groups.push_back(g);
+            }
+            ip.group = it->second;
+            GroupPlan& g = p.groups[ip.group];
+            g.members.push_back(k);
+            g.lds = std::max(g.lds, ip.res.lds);
+            g.Nmax = std::max(g.Nmax, N);
+        }
+        p.inst.push_back(ip);
+    }
+
+    // ---- stream instances: chunks of trajectories, one after another
+    size_t s_state = 0, s_x = 0, s_mom = 0, s_inv = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        InstPlan& ip = p.inst[k];
+        if (ip.path != FTWA_PATH_STREAM) continue;
+        const int N = inst[k].lat->N;
+        const int D = 2 * N;
+        const int64_t traj = std::max<int64_t>(inst[k].n_traj, 1);
+        const int64_t rec_cap = std::max<int64_t>(
+            64, (int64_t)(kRecordBudget / ((size_t)p.n_rec * D * sizeof(double))));
+        int64_t chunk = user_chunk > 0 ? user_chunk : kStreamChunk;
+        chunk = std::max<int64_t>(1, std::min({chunk, traj, rec_cap}));
+        ip.chunk = chunk;
+        s_state = std::max(s_state, (size_t)2 * packed_count(N) * chunk * cplx_bytes(dtype));
+        s_x = std::max(s_x, (size_t)p.n_rec * D * chunk * sizeof(double));
+        s_mom = std::max(s_mom, moments_workspace_bytes(D, chunk, p.n_rec));
+        if (inst[k].inv) s_inv = std::max(s_inv, (size_t)p.n_rec * 4 * chunk * sizeof(double));
+    }
+    size_t off = 0;
+    p.s_acc = off; off = align_up(off + s_state);
+    p.s_ya = off;  off = align_up(off + s_state);
+    p.s_yb = off;  off = align_up(off + s_state);
+    p.s_x = off;   off = align_up(off + s_x);
+    p.s_mom = off; off = align_up(off + s_mom);
+    p.s_inv = off; off = align_up(off + s_inv);
+    p.s_total = off;
+
+    // ---- resident instances: passes over trajectory windows.  Their area
+    // follows the stream area (no overlap: the launch tables are uploaded
+    // before the stream-path instances run, and must survive them)
+    size_t rec_bytes = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        if (p.inst[k].path != FTWA_PATH_RESIDENT) continue;
+        const int D = 2 * inst[k].lat->N;
+        rec_bytes += (size_t)p.n_rec * (D + (inst[k].inv ? 4 : 0)) * inst[k].n_traj * sizeof(double);
+    }
+    int64_t n_pass_goal = std::max<int64_t>(1, (int64_t)((rec_bytes + kRecordBudget - 1) / kRecordBudget));
+    p.n_pass = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        InstPlan& ip = p.inst[k];
+        if (ip.path != FTWA_PATH_RESIDENT) continue;
+        const int64_t M = inst[k].n_traj;
+        int64_t c;
+        if (user_chunk > 0) {
+            c = user_chunk;
+        } else {
+            // whole rounds of the trajectories the group runs at once
+            const int64_t align = std::max<int64_t>(
+                1, resident_concurrency(ip.res.config, p.groups[ip.group].lds));
+            c = (M + n_pass_goal - 1) / n_pass_goal;
+            c = (c + align - 1) / align * align;
+        }
+        c = std::max<int64_t>(1, std::min(c, std::max<int64_t>(M, 1)));
+        ip.chunk = c;
+        p.n_pass = std::max<int>(p.n_pass, (int)((M + c - 1) / c));
+    }
+    off = p.s_total;
+    for (int k = 0; k < n_inst; ++k) {
+        InstPlan& ip = p.inst[k];
+        if (ip.path != FTWA_PATH_RESIDENT) continue;
+        const int D = 2 * inst[k].lat->N;
+        ip.off_x = off; off = align_up(off + (size_t)p.n_rec * D * ip.chunk * sizeof(double));
+        if (inst[k].inv) {
+            ip.off_inv = off;
+            off = align_up(off + (size_t)p.n_rec * 4 * ip.chunk * sizeof(double));
+        }
+    }
+    size_t r_mom = 0;
+    for (int k = 0; k < n_inst; ++k)
+        if (p.inst[k].path == FTWA_PATH_RESIDENT)
+            r_mom = std::max(r_mom, moments_workspace_bytes(2 * inst[k].lat->N, p.inst[k].chunk,
+                                                            p.n_rec));
+    p.r_mom = off; off = align_up(off + r_mom);
+    // launches and their table entries
+    int64_t entry = 0;
+    for (int j = 0; j < p.n_pass; ++j)
+        for (int gi = 0; gi < (int)p.groups.size(); ++gi) {
+            GroupPlan& g = p.groups[gi];
+            LaunchDesc L;
+            L.group = gi;
+            L.first_entry = entry;
+            for (int k : g.members) {
+                int64_t m0, Mc;
+                window(p, inst[k], k, j, &m0, &Mc);
+                if (Mc <= 0) continue;
+                const int64_t per = resident_item_traj(g.config);
+                L.n_items += (Mc + per - 1) / per;
+                L.work += (double)Mc * n_steps;
+                ++L.n_entries;
+            }
+            entry += L.n_entries;
+            g.max_items = std::max(g.max_items, L.n_items);
+            L.grid = resident_grid(g.config, g.lds, std::max<int64_t>(L.n_items, 1));
+            p.launches.push_back(L);
+        }
+    p.n_table = entry;
+    for (GroupPlan& g : p.groups) {
+        g.off_mb = off;
+        off = align_up(off + resident_mailbox_bytes(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1)));
+    }
+    p.r_table = off; off = align_up(off + (size_t)std::max<int64_t>(entry, 1) * sizeof(ResidentInst));
+    p.r_total = off;
+    p.total = p.r_total;
+    *out = std::move(p);
+    return FTWA_OK;
+}
+
+// Host work before the launches: descriptor tables, the launch tables (one
+// upload, then the stream is synchronised so the host copy may go), and the
+// kernels' LDS limits.  Nothing here may run under graph capture.
+ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStream_t stream) {
+    ftwa_status st;
+    std::vector<ResidentInst> table;
+    table.reserve((size_t)p.n_table);
+    for (int j = 0; j < p.n_pass; ++j)
+        for (const GroupPlan& g : p.groups) {
+            int64_t item0 = 0;
+            const int64_t per = resident_item_traj(g.config);
+            for (int k : g.members) {
+                int64_t m0, Mc;
+                window(p, inst[k], k, j, &m0, &Mc);
+                if (Mc <= 0) continue;
+                const InstPlan& ip = p.inst[k];
+                ResidentInst e;
+                e.N = inst[k].lat->N;
+                e.P = (int)packed_count(e.N);
+                e.Mc = Mc;
+                e.rho = static_cast<char*>(inst[k].rho) + (size_t)m0 * cplx_bytes(p.dtype);
+                e.ldr = inst[k].n_traj;
+                if ((st = padded_descriptors(inst[k].lat, ip.res.even_slots, ip.res.odd_slots,
+                                             &e.desc)) != FTWA_OK)
+                    return st;
+                e.t = inst[k].lat->t;
+                e.U = inst[k].U;
+                e.X = reinterpret_cast<double*>(ws + ip.off_x);
+                e.inv_parts = inst[k].inv ? reinterpret_cast<double*>(ws + ip.off_inv) : nullptr;
+                e.item0 = item0;
+                item0 += (Mc + per - 1) / per;
+                table.push_back(e);
+            }
+        }
+    if (!table.empty()) {
+        FTWA_HIP_TRY(hipMemcpyAsync(ws + p.r_table, table.data(), table.size() * sizeof(ResidentInst),
+                                    hipMemcpyHostToDevice, stream));
+        FTWA_HIP_TRY(hipStreamSynchronize(stream));
+    }
+    for (const GroupPlan& g : p.groups)
+        if ((st = resident_prepare(g.config, g.lds)) != FTWA_OK) return st;
+    return FTWA_OK;
+}
+
+// Queues every launch of the run on `stream` (and nothing else: no host
+// synchronisation), so that it can be captured into a graph.
+ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStream_t stream,
+                    KernelTimer& timer, bool cooperative) {
+    ftwa_status st;
+    for (int k = 0; k < p.n_inst; ++k) {
+        const ftwa_instance& in = inst[k];
+        const int D = 2 * in.lat->N;
+        if ((st = zero_fill(in.S1, p.n_rec * D, stream)) != FTWA_OK) return st;
+        if ((st = zero_fill(in.S2, p.n_rec * s2_count(D), stream)) != FTWA_OK) return st;
+        if (in.inv && (st = zero_fill(in.inv, p.n_rec * 4, stream)) != FTWA_OK) return st;
+    }
+    for (const GroupPlan& g : p.groups) {
+        int* err = resident_error_word(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1),
+                                       ws + g.off_mb);
+        if (err && (st = zero_words(reinterpret_cast<unsigned*>(err), 1, stream)) != FTWA_OK)
+            return st;
+    }
+    // ---- stream instances
+    for (int k = 0; k < p.n_inst; ++k) {
+        const InstPlan& ip = p.inst[k];
+        if (ip.path != FTWA_PATH_STREAM) continue;
+        const ftwa_instance& in = inst[k];
+        DeviceTables tab;
+        if ((st = device_tables(in.lat, &tab)) != FTWA_OK) return st;
+        const int N = in.lat->N;
+        const int D = 2 * N;
+        double* X = reinterpret_cast<double*>(ws + p.s_x);
+        double* parts = in.inv ? reinterpret_cast<double*>(ws + p.s_inv) : nullptr;
+        for (int64_t m0 = 0; m0 < in.n_traj; m0 += ip.chunk) {
+            const int64_t Mc = std::min(ip.chunk, in.n_traj - m0);
+            StreamChunk c;
+            c.N = N;
+            c.P = packed_count(N);
+            c.Mc = Mc;
+            c.y = static_cast<char*>(in.rho) + (size_t)m0 * cplx_bytes(p.dtype);
+            c.ldy = in.n_traj;
+            c.acc = ws + p.s_acc;
+            c.ya = ws + p.s_ya;
+            c.yb = ws + p.s_yb;
+            c.t = in.lat->t;
+            c.U = in.U;
+            c.dt = p.dt;
+            if ((st = record_diag(c, tab, p.dtype, X, stream)) != FTWA_OK) return st;
+            if (parts && (st = record_inv(c, tab, p.dtype, parts, stream)) != FTWA_OK) return st;
+            int64_t open_steps = 0;
+            for (int64_t step = 1; step <= p.n_steps; ++step) {
+                if (open_steps == 0 && (st = timer.begin(stream)) != FTWA_OK) return st;
+                if ((st = stream_step(c, tab, p.dtype, stream)) != FTWA_OK) return st;
+                ++open_steps;
+                if (open_steps == 64 || step == p.n_steps) {
+                    if ((st = timer.end(stream, 4 * open_steps, (double)Mc * open_steps)) != FTWA_OK)
+                        return st;
+                    open_steps = 0;
+                }
+                if (step % p.record_every == 0) {
+                    const int64_t r = step / p.record_every;
+                    if ((st = record_diag(c, tab, p.dtype, X + r * D * Mc, stream)) != FTWA_OK)
+                        return st;
+                    if (parts &&
+                        (st = record_inv(c, tab, p.dtype, parts + r * 4 * Mc, stream)) != FTWA_OK)
+                        return st;
+                }
+            }
+            if ((st = moments_accumulate(D, Mc, p.n_rec, X, in.S1, in.S2, ws + p.s_mom, stream)) !=
+                FTWA_OK)
+                return st;
+            if (parts && (st = invariants_accumulate(N, Mc, p.n_rec, in.lat->t, in.U, X, parts,
+                                                     in.inv, stream)) != FTWA_OK)
+                return st;
+        }
+    }
+    // ---- resident groups, pass by pass
+    const ResidentInst* table = reinterpret_cast<const ResidentInst*>(ws + p.r_table);
+    for (int j = 0; j < p.n_pass; ++j) {
+        for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+            const LaunchDesc& Ld = p.launches[(size_t)j * p.groups.size() + gi];
+            if (Ld.n_items == 0) continue;
+            const GroupPlan& g = p.groups[gi];
+            ResidentLaunch L;
+            L.config = g.config;
+            L.lds = g.lds;
+            L.table = table + Ld.first_entry;
+            L.n_entries = Ld.n_entries;
+            L.n_items = Ld.n_items;
+            L.grid = Ld.grid;
+            L.Nmax = g.Nmax;
+            L.dt = p.dt;
+            L.n_steps = p.n_steps;
+            L.record_every = p.record_every;
+            L.mailbox = ws + g.off_mb;
+            L.error = resident_error_word(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1),
+                                          ws + g.off_mb);
+            L.cooperative = cooperative;
+            if ((st = timer.begin(stream)) != FTWA_OK) return st;
+            if ((st = resident_launch(L, stream)) != FTWA_OK) return st;
+            if ((st = timer.end(stream, 1, Ld.work)) != FTWA_OK) return st;
+        }
+        for (int k = 0; k < p.n_inst; ++k) {
+            const InstPlan& ip = p.inst[k];
+            if (ip.path != FTWA_PATH_RESIDENT) continue;
+            const ftwa_instance& in = inst[k];
+            int64_t m0, Mc;
+            window(p, in, k, j, &m0, &Mc);
+            if (Mc <= 0) continue;
+            const int N = in.lat->N;
+            double* X = reinterpret_cast<double*>(ws + ip.off_x);
+            if ((st = moments_accumulate(2 * N, Mc, p.n_rec, X, in.S1, in.S2, ws + p.r_mom,
+                                         stream)) != FTWA_OK)
+                return st;
+            if (in.inv &&
+                (st = invariants_accumulate(N, Mc, p.n_rec, in.lat->t, in.U, X,
+                                            reinterpret_cast<double*>(ws + ip.off_inv), in.inv,
+                                            stream)) != FTWA_OK)
+                return st;
+        }
+    }
+    return FTWA_OK;
+}
+
+// Host checks after the launches (synchronise the stream): spin-split
+// timeouts and non-finite trajectories.
+ftwa_status finish(const Plan& p, const ftwa_instance* inst, char* ws, hipStream_t stream) {
+    ftwa_status st;
+    for (const GroupPlan& g : p.groups) {
+        const int* err = resident_error_word(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1),
+                                             ws + g.off_mb);
+        bool timed_out = false;
+        if ((st = resident_check_error(err, stream, &timed_out)) != FTWA_OK) return st;
+        if (timed_out)
+            return fail(FTWA_ETIMEOUT,
+                        "a spin-split workgroup pair timed out waiting for its partner");
+    }
+    for (int k = 0; k < p.n_inst; ++k) {
+        if (!inst[k].inv) continue;
+        std::vector<double> h((size_t)p.n_rec * 4);
+        FTWA_HIP_TRY(hipMemcpyAsync(h.data(), inst[k].inv, h.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, stream));
+        FTWA_HIP_TRY(hipStreamSynchronize(stream));
+        for (int64_t r = 0; r < p.n_rec; ++r)
+            if (h[(size_t)r * 4 + 3] > 0)
+                return fail(FTWA_ENONFINITE, "instance " + std::to_string(k) +
+                                                 ": a trajectory became non-finite by record " +
+                                                 std::to_string(r));
+    }
+    return FTWA_OK;
+}
+
+// ---------------------------------------------------------------- tuning table
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t, int>, int> g_tuned;
+
+int current_device() {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d;
+}
+
+}  // namespace
+
+bool tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int* config) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(current_device(), N, n_even, (int)dtype));
+    if (it == g_tuned.end()) return false;
+    *config = it->second;
+    return true;
+}
+
+void set_tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int config) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[std::make_tuple(current_device(), N, n_even, (int)dtype)] = config;
+}
+
+}  // namespace ftwa
+
+using namespace ftwa;
+
+struct ftwa_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Plan plan;
+    std::vector<ftwa_instance> inst;
+    char* ws = nullptr;
+};
+
+extern "C" {
+
+ftwa_status ftwa_evolve_workspace_size(const ftwa_instance* inst, int n_inst, int64_t n_steps,
+                                       int record_every, ftwa_dtype dtype,
+                                       const ftwa_tuning* tune, size_t* bytes) {
+    ftwa_status st = check_instances(inst, n_inst, false, "ftwa_evolve_workspace_size");
+    if (st != FTWA_OK) return st;
+    if (!bytes) return fail(FTWA_EINVAL, "bytes is NULL");
+    Plan plan;
+    if ((st = plan_evolve(inst, n_inst, 0.0, n_steps, record_every, dtype, tune, &plan)) != FTWA_OK)
+        return st;
+    *bytes = plan.total;
+    return FTWA_OK;
+}
+
+ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
+                        int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
+                        void* workspace, size_t workspace_bytes, void* stream_) {
+    ftwa_status st = check_instances(inst, n_inst, true, "ftwa_evolve");
+    if (st != FTWA_OK) return st;
+    Plan plan;
+    if ((st = plan_evolve(inst, n_inst, dt, n_steps, record_every, dtype, tune, &plan)) != FTWA_OK)
+        return st;
+    if (workspace_bytes < plan.total || (!workspace && plan.total > 0))
+        return fail(FTWA_EINVAL, "workspace smaller than ftwa_evolve_workspace_size");
+    hipStream_t stream = (hipStream_t)stream_;
+    char* ws = static_cast<char*>(workspace);
+    if ((st = prepare(plan, inst, ws, stream)) != FTWA_OK) return st;
+    KernelTimer timer(tune && tune->kernel_ms);
+    if ((st = execute(plan, inst, ws, stream, timer, true)) != FTWA_OK) return st;
+    if (tune && tune->kernel_ms)
+        if ((st = timer.finish(tune->kernel_ms, tune->kernel_launches, tune->kernel_work)) != FTWA_OK)
+            return st;
+    return finish(plan, inst, ws, stream);
+}
+
+ftwa_status ftwa_evolve_graph(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
+                              int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
+                              void* workspace, size_t workspace_bytes, void* stream_,
+                              ftwa_graph* out) {
+    ftwa_status st = check_instances(inst, n_inst, true, "ftwa_evolve_graph");
+    if (st != FTWA_OK) return st;
+    if (!out) return fail(FTWA_EINVAL, "out is NULL");
+    if (tune && tune->kernel_ms) return fail(FTWA_EINVAL, "kernel timing is not available in a graph");
+    auto* g = new (std::nothrow) ftwa_graph_s;
+    if (!g) return fail(FTWA_ENOMEM, "graph handle");
+    if ((st = plan_evolve(inst, n_inst, dt, n_steps, record_every, dtype, tune, &g->plan)) != FTWA_OK) {
+        delete g;
+        return st;
+    }
+    if (workspace_bytes < g->plan.total || (!workspace && g->plan.total > 0)) {
+        delete g;
+        return fail(FTWA_EINVAL, "workspace smaller than ftwa_evolve_workspace_size");
+    }
+    g->inst.assign(inst, inst + n_inst);
+    g->ws = static_cast<char*>(workspace);
+    hipStream_t stream = (hipStream_t)stream_;
+    if ((st = prepare(g->plan, inst, g->ws, stream)) != FTWA_OK) {
+        delete g;
+        return st;
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        delete g;
+        return fail(FTWA_EHIP, "hipStreamCreateWithFlags");
+    }
+    KernelTimer off(false);
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = execute(g->plan, g->inst.data(), g->ws, cs, off, false);
+        hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+        if (st == FTWA_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamEndCapture");
+    } else {
+        st = hip_fail(e, "hipStreamBeginCapture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st == FTWA_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = hip_fail(e, "hipGraphInstantiate");
+    }
+    if (st != FTWA_OK) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return FTWA_OK;
+}
+
+ftwa_status ftwa_graph_launch(ftwa_graph g, void* stream) {
+    if (!g || !g->exec) return fail(FTWA_EINVAL, "invalid graph");
+    FTWA_HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return FTWA_OK;
+}
+
+ftwa_status ftwa_graph_check(ftwa_graph g, void* stream) {
+    if (!g) return fail(FTWA_EINVAL, "invalid graph");
+    return finish(g->plan, g->inst.data(), g->ws, (hipStream_t)stream);
+}
+
+void ftwa_graph_free(ftwa_graph g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+namespace ftwa {
+namespace {
+
+struct Probe {
+    std::vector<int> cands;  // resident configurations that fit, then -1 (stream path)
+    int64_t Mp = 0;          // trajectories timed
+    size_t off_rho = 0, off_s1 = 0, off_s2 = 0, off_ws = 0, total = 0;
+};
+
+ftwa_tuning probe_tuning(int cand) {
+    ftwa_tuning t;
+    std::memset(&t, 0, sizeof(t));
+    t.path = cand < 0 ? FTWA_PATH_STREAM : FTWA_PATH_RESIDENT;
+    t.traj_chunk = 0;
+    t.resident_config = cand;
+    return t;
+}
+
+ftwa_instance probe_instance(const ftwa_instance& in, int64_t Mp, char* ws, const Probe& pr) {
+    ftwa_instance q = in;
+    q.n_traj = Mp;
+    q.traj_offset = 0;
+    q.rho = ws ? ws + pr.off_rho : nullptr;
+    q.S1 = ws ? reinterpret_cast<double*>(ws + pr.off_s1) : nullptr;
+    q.S2 = ws ? reinterpret_cast<double*>(ws + pr.off_s2) : nullptr;
+    q.inv = nullptr;
+    return q;
+}
+
+ftwa_status plan_probe(const ftwa_instance& in, ftwa_dtype dtype, int probe_steps, Probe* out) {
+    Probe pr;
+    DeviceTables tab;
+    ftwa_status st = device_tables(in.lat, &tab);
+    if (st != FTWA_OK) return st;
+    const int N = in.lat->N;
+    int64_t want = 0;
+    for (int c = 0; c < resident_config_count(); ++c) {
+        ResidentPlan rp;
+        if (!resident_plan(N, dtype, tab, &rp, c)) continue;
+        pr.cands.push_back(c);
+        want = std::max(want, 2 * resident_concurrency(c, rp.lds));
+    }
+    pr.cands.push_back(-1);
+    if (want == 0) want = kStreamChunk;
+    pr.Mp = std::max<int64_t>(1, std::min(in.n_traj, want));
+    const int D = 2 * N;
+    size_t off = 0;
+    pr.off_rho = off; off = align_up(off + (size_t)2 * packed_count(N) * pr.Mp * cplx_bytes(dtype));
+    pr.off_s1 = off;  off = align_up(off + (size_t)2 * D * sizeof(double));
+    pr.off_s2 = off;  off = align_up(off + (size_t)2 * s2_count(D) * sizeof(double));
+    pr.off_ws = off;
+    size_t ews = 0;
+    const ftwa_instance q = probe_instance(in, pr.Mp, nullptr, pr);
+    for (int c : pr.cands) {
+        const ftwa_tuning t = probe_tuning(c);
+        Plan p;
+        if ((st = plan_evolve(&q, 1, 0.01, probe_steps, probe_steps, dtype, &t, &p)) != FTWA_OK)
+            return st;
+        ews = std::max(ews, p.total);
+    }
+    pr.total = align_up(off + ews);
+    *out = pr;
+    return FTWA_OK;
+}
+
+}  // namespace
+}  // namespace ftwa
+
+extern "C" {
+
+ftwa_status ftwa_autotune_workspace_size(const ftwa_instance* inst, int n_inst, ftwa_dtype dtype,
+                                         int probe_steps, size_t* bytes) {
+    ftwa_status st = check_instances(inst, n_inst, false, "ftwa_autotune_workspace_size");
+    if (st != FTWA_OK) return st;
+    if (!bytes || probe_steps < 1) return fail(FTWA_EINVAL, "bytes is NULL or probe_steps < 1");
+    if (dtype != FTWA_F64 && dtype != FTWA_F32) return fail(FTWA_EINVAL, "unknown dtype");
+    size_t total = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        Probe pr;
+        if ((st = plan_probe(inst[k], dtype, probe_steps, &pr)) != FTWA_OK) return st;
+        total = std::max(total, pr.total);
+    }
+    *bytes = total;
+    return FTWA_OK;
+}
+
+ftwa_status ftwa_autotune(const ftwa_instance* inst, int n_inst, ftwa_dtype dtype, int probe_steps,
+                          void* workspace, size_t workspace_bytes, void* stream_, int* configs) {
+    ftwa_status st = check_instances(inst, n_inst, false, "ftwa_autotune");
+    if (st != FTWA_OK) return st;
+    if (probe_steps < 1) return fail(FTWA_EINVAL, "probe_steps < 1");
+    if (dtype != FTWA_F64 && dtype != FTWA_F32) return fail(FTWA_EINVAL, "unknown dtype");
+    hipStream_t stream = (hipStream_t)stream_;
+    char* ws = static_cast<char*>(workspace);
+    std::map<std::pair<int, int64_t>, int> decided;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FTWA_HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(FTWA_EHIP, "hipEventCreate");
+    }
+    auto done = [&](ftwa_status s) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return s;
+    };
+    for (int k = 0; k < n_inst; ++k) {
+        const ftwa_instance& in = inst[k];
+        if (in.n_traj < 1 || !in.rho || !in.n0) return done(fail(FTWA_EINVAL, "instance without trajectories"));
+        DeviceTables tab;
+        if ((st = device_tables(in.lat, &tab)) != FTWA_OK) return done(st);
+        const int N = in.lat->N;
+        const auto key = std::make_pair(N, tab.n_even);
+        auto it = decided.find(key);
+        if (it != decided.end()) {
+            if (configs) configs[k] = it->second;
+            continue;
+        }
+        Probe pr;
+        if ((st = plan_probe(in, dtype, probe_steps, &pr)) != FTWA_OK) return done(st);
+        if (!ws || workspace_bytes < pr.total)
+            return done(fail(FTWA_EINVAL, "workspace smaller than ftwa_autotune_workspace_size"));
+        const ftwa_instance q = probe_instance(in, pr.Mp, ws, pr);
+        const size_t cb = cplx_bytes(dtype);
+        const size_t P2 = (size_t)2 * packed_count(N);
+        int best = -1;
+        double best_ms = -1.0;
+        for (int c : pr.cands) {
+            const ftwa_tuning t = probe_tuning(c);
+            Plan p;
+            if ((st = plan_evolve(&q, 1, 0.01, probe_steps, probe_steps, dtype, &t, &p)) != FTWA_OK)
+                return done(st);
+            char* ews = ws + pr.off_ws;
+            if ((st = prepare(p, &q, ews, stream)) != FTWA_OK) return done(st);
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2; ++rep) {  // the first run warms up
+                FTWA_HIP_TRY(hipMemcpy2DAsync(ws + pr.off_rho, pr.Mp * cb, in.rho, in.n_traj * cb,
+                                              pr.Mp * cb, P2, hipMemcpyDeviceToDevice, stream));
+                KernelTimer off(false);
+                FTWA_HIP_TRY(hipEventRecord(e0, stream));
+                if ((st = execute(p, &q, ews, stream, off, true)) != FTWA_OK) return done(st);
+                FTWA_HIP_TRY(hipEventRecord(e1, stream));
+                FTWA_HIP_TRY(hipEventSynchronize(e1));
+                FTWA_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            }
+            if ((st = finish(p, &q, ews, stream)) != FTWA_OK) return done(st);
+            if (best_ms < 0 || ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        set_tuned_config(N, tab.n_even, dtype, best);
+        decided[key] = best;
+        if (configs) configs[k] = best;
+    }
+    return done(FTWA_OK);
+}
+
+}  // extern "C"

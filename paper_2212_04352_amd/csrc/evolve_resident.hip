@@ -39,6 +39,8 @@
 // to, written and read with single 64-bit relaxed agent-scope atomics, so no
 // fence (and no cache write-back or invalidation) is needed.  Waits are
 // bounded; a timeout aborts both workgroups and is reported.
+#include <algorithm>
+
 #include "device_common.h"
 #include "ftwa_internal.h"
 
@@ -47,19 +49,15 @@ namespace ftwa {
 namespace {
 
 struct ResidentArgs {
-    int N;
-    int P;
-    int64_t Mc;            // trajectories of this pass
-    void* rho;             // instance state, offset to the pass's first trajectory
-    int64_t ldr;           // stride between packed elements (= instance n_traj)
-    const uint4* desc;     // padded: [NTU*UE even][NTU*UO odd]
-    double t, U, dt;
+    const ResidentInst* table;  // entries (instance windows), item0 ascending
+    int n_entries;
+    int64_t n_items;            // total items over the table
+    double dt;
     int64_t n_steps;
     int record_every;
-    double* X;             // [n_rec][2N][Mc]
-    double* inv_parts;     // NULL or [n_rec][2 spins][hop, frob][Mc]
-    uint64_t* mailbox;     // S = 1: [pairs][2 spins][2 slots][N] stage-stamped words
-    int* error;            // set to 1 when a wait times out
+    uint64_t* mailbox;          // S = 1: [pairs][2 spins][2 slots][Nmax] stage-stamped words
+    int Nmax;
+    int* error;                 // set to 1 when a wait times out
 };
 
 constexpr unsigned kSpinLimit = 1u << 26;  // ~2 s of polling
@@ -149,6 +147,14 @@ typedef const __attribute__((address_space(1))) uint4* gdesc_t;
 typedef const uint4* gdesc_t;  // host pass of the kernel source only
 #endif
 
+// A value the compiler cannot prove wave-uniform (read from the launch
+// table) moved into scalar registers: every lane holds the same value.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ gdesc_t launder(gdesc_t p) {
     uint64_t v = (uint64_t)p;
     __asm__ volatile("" : "+s"(v)::"memory");
@@ -167,231 +173,259 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int abort_flag;
     __shared__ double red[(NTU * UNITS) / 64][2 * S];  // per-wave partial sums (records)
-    const int N = A.N;
-    const int P = A.P;
-    const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
-    const int tid = threadIdx.x;
-    const int unit = tid / NTU;
-    const int t = tid % NTU;
-    C* const Yunit = reinterpret_cast<C*>(smem) + (size_t)unit * S * Pb;
-    T* const dvec = reinterpret_cast<T*>(smem + (size_t)UNITS * S * Pb * sizeof(C)) + (size_t)unit * 2 * N;
+    const int tid0 = threadIdx.x;
 
-    // trajectory and spins of this unit
-    int64_t m;
+    // Persistent schedule.  S = 2: workgroup b takes items b, b + grid, ...
+    // (an item is UNITS consecutive trajectories of one table entry).  S = 1:
+    // the two workgroups of pair p (same XCD: blocks b and b + 8 of a group of
+    // 16) take items p, p + n_pairs, ... (an item is one trajectory), in the
+    // same order, so their stage counters stay equal.
     int spin0 = 0;
     int pair = 0;
+    int64_t first, stride;
     if constexpr (S == 1) {
         const int b = blockIdx.x, xcd = b % 8, k = b / 8;
         spin0 = k % 2;
         pair = (k / 2) * 8 + xcd;
-        m = pair;
-        if (m >= A.Mc) return;  // both workgroups of an unused pair leave together
+        first = pair;
+        stride = gridDim.x / 2;
     } else {
-        m = (int64_t)blockIdx.x * UNITS + unit;
+        first = blockIdx.x;
+        stride = gridDim.x;
     }
-    const bool active = m < A.Mc;
-    C* const rho = static_cast<C*>(A.rho);
-    gdesc_t desc = (gdesc_t)A.desc;
-    const int lane = tid % 64;
-    const int wave = tid / 64;
+    if (tid0 == 0) abort_flag = 0;
+    uint64_t* const mb = A.mailbox;
+    int64_t g = 0;  // stage counter (continues across items)
 
     C y[S][UE + UO], acc[S][UE + UO], hold[S][UE];
 
-    // ---- load the trajectory into registers and LDS
-    if (tid == 0) abort_flag = 0;
+    for (int64_t item = first; item < A.n_items; item += stride) {
+        // thread coordinates are re-derived every item (an opaque copy of the
+        // thread index), so that per-slot offsets are not hoisted out of the
+        // item loop and kept in registers across it
+        int tid = tid0;
+        __asm__ volatile("" : "+v"(tid));
+        const int unit = tid / NTU;
+        const int t = tid % NTU;
+        const int lane = tid % 64;
+        const int wave = tid / 64;
+        // table entry of this item (uniform: scalar loads)
+        int ent = 0;
+        while (ent + 1 < A.n_entries && A.table[ent + 1].item0 <= item) ++ent;
+        ent = __builtin_amdgcn_readfirstlane(ent);
+        const ResidentInst& E = A.table[ent];
+        const int N = E.N;
+        const int P = E.P;
+        const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
+        C* const Yunit = reinterpret_cast<C*>(smem) + (size_t)unit * S * Pb;
+        T* const dvec =
+            reinterpret_cast<T*>(smem + (size_t)UNITS * S * Pb * sizeof(C)) + (size_t)unit * 2 * N;
+        const int64_t Mc = E.Mc;
+        const int64_t m = (item - E.item0) * (S == 1 ? 1 : UNITS) + (S == 1 ? 0 : unit);
+        const bool active = m < Mc;
+        C* const rho = reinterpret_cast<C*>(uniform64((uint64_t)E.rho));
+        const int64_t ldr = E.ldr;
+        double* const Xrec = E.X;
+        double* const inv_parts = E.inv_parts;
+        gdesc_t desc = (gdesc_t)uniform64((uint64_t)E.desc);
+        __syncthreads();  // the previous item is done with LDS and `red`
+
+        // ---- load the trajectory into registers and LDS
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int gs = spin0 + s;
+        for (int s = 0; s < S; ++s) {
+            const int gs = spin0 + s;
 #pragma unroll
-        for (int u = 0; u < UE + UO; ++u) {
-            const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-            const uint32_t p = desc[e].x & 0x7fffu;
-            C v;
-            v.x = 0;
-            v.y = 0;
-            if (active && (int)p < P) v = rho[((int64_t)gs * P + p) * A.ldr + m];
-            Yunit[s * Pb + p] = v;  // dummies write the scratch slot
-            y[s][u] = v;
-            acc[s][u] = v;
+            for (int u = 0; u < UE + UO; ++u) {
+                const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
+                const uint32_t p = desc[e].x & 0x7fffu;
+                C v;
+                v.x = 0;
+                v.y = 0;
+                if (active && (int)p < P) v = rho[((int64_t)gs * P + p) * ldr + m];
+                Yunit[s * Pb + p] = v;  // dummies write the scratch slot
+                y[s][u] = v;
+                acc[s][u] = v;
+            }
+            if (t == 0) {
+                C z;
+                z.x = 0;
+                z.y = 0;
+                Yunit[s * Pb + P] = z;
+                Yunit[s * Pb + P + 1] = z;
+            }
         }
-        if (t == 0) {
-            C z;
-            z.x = 0;
-            z.y = 0;
-            Yunit[s * Pb + P] = z;
-            Yunit[s * Pb + P + 1] = z;
+        for (int idx = t; idx < 2 * N; idx += NTU) {
+            const int gs = idx / N, i = idx - gs * N;
+            const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
+            dvec[idx] = active ? rho[((int64_t)gs * P + p) * ldr + m].x : (T)0;
         }
-    }
-    for (int idx = t; idx < 2 * N; idx += NTU) {
-        const int gs = idx / N, i = idx - gs * N;
-        const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
-        dvec[idx] = active ? rho[((int64_t)gs * P + p) * A.ldr + m].x : (T)0;
-    }
-    // records: the first N even elements are the diagonal (i = position)
-    // (every configuration has N <= NTU, so only slot 0 can hold them)
-    auto record = [&](int64_t r) {
-        if (active && t < N) {
+        // records: the first N even elements are the diagonal (i = position)
+        // (every configuration has N <= NTU, so only slot 0 can hold them)
+        auto record = [&](int64_t r) {
+            if (active && t < N) {
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                A.X[(r * 2 * N + (int64_t)(spin0 + s) * N + t) * A.Mc + m] = (double)y[s][0].x;
+                for (int s = 0; s < S; ++s)
+                    Xrec[(r * 2 * N + (int64_t)(spin0 + s) * N + t) * Mc + m] = (double)y[s][0].x;
+            }
+            if (inv_parts) {
+                // per-trajectory sums for the invariant checks, in FP64:
+                // hop = sum_i sum_{k in nb(i)} Re rho_ik (each bond twice),
+                // frob = sum_ij |rho_ij|^2 (off-diagonal elements twice)
+                double hop[S], frob[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    hop[s] = 0.0;
+                    frob[s] = 0.0;
+#pragma unroll
+                    for (int u = 0; u < UE + UO; ++u) {
+                        const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
+                        const uint32_t dx = desc[e].x;
+                        const double re = (double)y[s][u].x, im = (double)y[s][u].y;
+                        const bool diag = u < UE && e < N;
+                        frob[s] += diag ? re * re : 2.0 * (re * re + im * im);
+                        if (dx & 0x8000u) hop[s] += 2.0 * re;
+                    }
+                    for (int off = 32; off > 0; off /= 2) {
+                        hop[s] += __shfl_xor(hop[s], off, 64);
+                        frob[s] += __shfl_xor(frob[s], off, 64);
+                    }
+                }
+                if (lane == 0)
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        red[wave][2 * s] = hop[s];
+                        red[wave][2 * s + 1] = frob[s];
+                    }
+                __syncthreads();
+                if (t == 0 && active) {
+                    constexpr int kWavesPerUnit = NTU / 64;
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        double h = 0.0, f = 0.0;
+                        for (int w = 0; w < kWavesPerUnit; ++w) {
+                            h += red[unit * kWavesPerUnit + w][2 * s];
+                            f += red[unit * kWavesPerUnit + w][2 * s + 1];
+                        }
+                        const int64_t base = ((r * 2 + spin0 + s) * 2) * Mc + m;
+                        inv_parts[base] = h;
+                        inv_parts[base + Mc] = f;
+                    }
+                }
+            }
+        };
+        record(0);
+        __syncthreads();
+
+        const T tw = (T)E.t, Uw = (T)E.U;
+        const T c_half = (T)(0.5 * A.dt), c_full = (T)A.dt, c_sixth = (T)(A.dt / 6.0);
+
+        for (int64_t step = 1; step <= A.n_steps; ++step) {
+#pragma unroll 1
+            for (int stage = 1; stage <= 4; ++stage, ++g) {
+                const T c = stage <= 2 ? c_half : (stage == 3 ? c_full : c_sixth);
+                desc = launder(desc);  // descriptors are re-read every phase
+                // ---------------- phase 1: even elements (next values held in registers)
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const C* Yb = Yunit + s * Pb;
+                    const T* dother = dvec + (1 - (spin0 + s)) * N;
+#pragma unroll
+                    for (int u = 0; u < UE; ++u) {
+                        const uint4 d = (desc + NTU * u)[t];
+                        const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
+                        hold[s][u] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
+                    }
+                }
+                if constexpr (S == 1) {
+                    // publish the next-stage diagonal of this spin for the partner:
+                    // one 64-bit word per site, (stage number << 32) | value bits,
+                    // written with a single relaxed agent-scope atomic store
+                    if (t < N) {
+                        uint64_t* slot =
+                            mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * A.Nmax;
+                        const uint64_t word = ((uint64_t)(g + 1) << 32) | to_bits<T>(hold[0][0].x);
+                        __hip_atomic_store(slot + t, word, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                __syncthreads();
+                desc = launder(desc);
+                // ---------------- phase 2: odd elements (written straight to LDS)
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    C* Yb = Yunit + s * Pb;
+                    const T* dother = dvec + (1 - (spin0 + s)) * N;
+#pragma unroll
+                    for (int u = UE; u < UE + UO; ++u) {
+                        const uint4 d = (desc + kEvenPad + NTU * (u - UE))[t];
+                        const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
+                        Yb[d.x & 0x7fffu] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
+                    }
+                }
+                __syncthreads();
+                desc = launder(desc);
+                // ---------------- held even values and the diagonals
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    C* Yb = Yunit + s * Pb;
+#pragma unroll
+                    for (int u = 0; u < UE; ++u) Yb[(desc + NTU * u)[t].x & 0x7fffu] = hold[s][u];
+                    if (t < N) dvec[(spin0 + s) * N + t] = hold[s][0].x;
+                }
+                if constexpr (S == 1) {
+                    if (wave == 0) {
+                        // partner's diagonal for the next stage: poll each word until
+                        // it carries stage g+1 (bounded; two slots alternate by parity,
+                        // so a word is never overwritten before it has been read)
+                        const uint64_t* slot =
+                            mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * A.Nmax;
+                        const uint32_t want = (uint32_t)(g + 1);
+                        int ok = 1;
+                        for (int i = lane; i < N; i += 64) {
+                            uint64_t w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                            unsigned it = 0;
+                            while ((uint32_t)(w >> 32) != want) {
+                                if (++it >= kSpinLimit) {
+                                    ok = 0;
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                                w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                            }
+                            dvec[(1 - spin0) * N + i] = from_bits<T>((uint32_t)w);
+                        }
+                        if (__any(!ok) && lane == 0) {
+                            abort_flag = 1;
+                            atomicExch(A.error, 1);
+                        }
+                    }
+                }
+                __syncthreads();
+                if constexpr (S == 1) {
+                    if (abort_flag) return;
+                }
+            }
+            if (step % A.record_every == 0) record(step / A.record_every);
         }
-        if (A.inv_parts) {
-            // per-trajectory sums for the invariant checks, in FP64:
-            // hop = sum_i sum_{k in nb(i)} Re rho_ik (each bond twice),
-            // frob = sum_ij |rho_ij|^2 (off-diagonal elements twice)
-            double hop[S], frob[S];
+
+        // ---- final state back to HBM (addresses recomputed, not kept alive
+        // across the time loop)
+        if (active) {
+            C* rho_out = rho;
+            desc = launder(desc);
+            __asm__ volatile("" : "+s"(rho_out)::"memory");
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                hop[s] = 0.0;
-                frob[s] = 0.0;
+                const int gs = spin0 + s;
 #pragma unroll
                 for (int u = 0; u < UE + UO; ++u) {
                     const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                    const uint32_t dx = desc[e].x;
-                    const double re = (double)y[s][u].x, im = (double)y[s][u].y;
-                    const bool diag = u < UE && e < N;
-                    frob[s] += diag ? re * re : 2.0 * (re * re + im * im);
-                    if (dx & 0x8000u) hop[s] += 2.0 * re;
-                }
-                for (int off = 32; off > 0; off /= 2) {
-                    hop[s] += __shfl_xor(hop[s], off, 64);
-                    frob[s] += __shfl_xor(frob[s], off, 64);
+                    const uint32_t p = desc[e].x & 0x7fffu;
+                    if ((int)p < P) rho_out[((int64_t)gs * P + p) * ldr + m] = y[s][u];
                 }
             }
-            if (lane == 0)
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    red[wave][2 * s] = hop[s];
-                    red[wave][2 * s + 1] = frob[s];
-                }
-            __syncthreads();
-            if (t == 0 && active) {
-                constexpr int kWavesPerUnit = NTU / 64;
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    double h = 0.0, f = 0.0;
-                    for (int w = 0; w < kWavesPerUnit; ++w) {
-                        h += red[unit * kWavesPerUnit + w][2 * s];
-                        f += red[unit * kWavesPerUnit + w][2 * s + 1];
-                    }
-                    const int64_t base = ((r * 2 + spin0 + s) * 2) * A.Mc + m;
-                    A.inv_parts[base] = h;
-                    A.inv_parts[base + A.Mc] = f;
-                }
-            }
-        }
-    };
-    record(0);
-    __syncthreads();
-
-    const T tw = (T)A.t, Uw = (T)A.U;
-    const T c_half = (T)(0.5 * A.dt), c_full = (T)A.dt, c_sixth = (T)(A.dt / 6.0);
-    uint64_t* const mb = A.mailbox;
-    int64_t g = 0;  // stage counter
-
-    for (int64_t step = 1; step <= A.n_steps; ++step) {
-#pragma unroll 1
-        for (int stage = 1; stage <= 4; ++stage, ++g) {
-            const T c = stage <= 2 ? c_half : (stage == 3 ? c_full : c_sixth);
-            desc = launder(desc);  // descriptors are re-read every phase
-            // ---------------- phase 1: even elements (next values held in registers)
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const C* Yb = Yunit + s * Pb;
-                const T* dother = dvec + (1 - (spin0 + s)) * N;
-#pragma unroll
-                for (int u = 0; u < UE; ++u) {
-                    const uint4 d = (desc + NTU * u)[t];
-                    const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
-                    hold[s][u] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
-                }
-            }
-            if constexpr (S == 1) {
-                // publish the next-stage diagonal of this spin for the partner:
-                // one 64-bit word per site, (stage number << 32) | value bits,
-                // written with a single relaxed agent-scope atomic store
-                if (t < N) {
-                    uint64_t* slot = mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * N;
-                    const uint64_t word = ((uint64_t)(g + 1) << 32) | to_bits<T>(hold[0][0].x);
-                    __hip_atomic_store(slot + t, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            __syncthreads();
-            desc = launder(desc);
-            // ---------------- phase 2: odd elements (written straight to LDS)
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                C* Yb = Yunit + s * Pb;
-                const T* dother = dvec + (1 - (spin0 + s)) * N;
-#pragma unroll
-                for (int u = UE; u < UE + UO; ++u) {
-                    const uint4 d = (desc + kEvenPad + NTU * (u - UE))[t];
-                    const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
-                    Yb[d.x & 0x7fffu] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
-                }
-            }
-            __syncthreads();
-            desc = launder(desc);
-            // ---------------- held even values and the diagonals
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                C* Yb = Yunit + s * Pb;
-#pragma unroll
-                for (int u = 0; u < UE; ++u) Yb[(desc + NTU * u)[t].x & 0x7fffu] = hold[s][u];
-                if (t < N) dvec[(spin0 + s) * N + t] = hold[s][0].x;
-            }
-            if constexpr (S == 1) {
-                if (wave == 0) {
-                    // partner's diagonal for the next stage: poll each word until
-                    // it carries stage g+1 (bounded; two slots alternate by parity,
-                    // so a word is never overwritten before it has been read)
-                    const uint64_t* slot =
-                        mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * N;
-                    const uint32_t want = (uint32_t)(g + 1);
-                    int ok = 1;
-                    for (int i = lane; i < N; i += 64) {
-                        uint64_t w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                        unsigned it = 0;
-                        while ((uint32_t)(w >> 32) != want) {
-                            if (++it >= kSpinLimit) {
-                                ok = 0;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                            w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                        dvec[(1 - spin0) * N + i] = from_bits<T>((uint32_t)w);
-                    }
-                    if (__any(!ok) && lane == 0) {
-                        abort_flag = 1;
-                        atomicExch(A.error, 1);
-                    }
-                }
-            }
-            __syncthreads();
-            if constexpr (S == 1) {
-                if (abort_flag) return;
-            }
-        }
-        if (step % A.record_every == 0) record(step / A.record_every);
-    }
-
-    // ---- final state back to HBM (addresses recomputed, not kept alive
-    // across the time loop)
-    if (!active) return;
-    C* rho_out = rho;
-    desc = launder(desc);
-    __asm__ volatile("" : "+s"(rho_out)::"memory");
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int gs = spin0 + s;
-#pragma unroll
-        for (int u = 0; u < UE + UO; ++u) {
-            const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-            const uint32_t p = desc[e].x & 0x7fffu;
-            if ((int)p < P) rho_out[((int64_t)gs * P + p) * A.ldr + m] = y[s][u];
         }
     }
 }
@@ -458,71 +492,110 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
 
 int resident_config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
 
-int64_t resident_max_traj(const ResidentPlan& plan) {
+int resident_spins(int config) { return kConfigs[config].S; }
+
+int64_t resident_item_traj(int config) {
+    const Config& c = kConfigs[config];
+    return c.S == 1 ? 1 : c.UNITS;
+}
+
+namespace {
+int device_cus() {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     }
-    if (plan.spins_per_unit == 1) {
-        // one workgroup per CU (LDS bound), two per trajectory, pairs in groups of 8
-        int64_t pairs = (int64_t)cus / 2 / 8 * 8;
-        return pairs < 8 ? 8 : pairs;
-    }
-    return (int64_t)1 << 20;  // no co-residency needed: any number of workgroups
+    return cus;
+}
+}  // namespace
+
+ftwa_status resident_prepare(int config, size_t lds) {
+    (void)lds;  // the limit is raised to the whole LDS once; launches use less
+    FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    return FTWA_OK;
 }
 
-// Spin-split scratch: the mailbox words, then the error word.
-size_t resident_mailbox_bytes(const ResidentPlan& plan, int N, ftwa_dtype dtype, int64_t Mc) {
-    (void)dtype;
-    if (plan.spins_per_unit != 1) return 0;
-    const int64_t pairs = (Mc + 7) / 8 * 8;
-    return (size_t)pairs * 2 * 2 * N * sizeof(uint64_t) + 64;
+// Pairs of spin-split workgroups that are resident together: one workgroup
+// per CU (LDS bound), pairs in groups of 8 (one per XCD).
+int64_t resident_max_pairs() {
+    const int64_t pairs = (int64_t)device_cus() / 2 / 8 * 8;
+    return pairs < 8 ? 8 : pairs;
 }
 
-int* resident_error_word(const ResidentPlan& plan, int N, int64_t Mc, void* mailbox) {
-    const Config& c = kConfigs[plan.config];
-    if (c.S != 1) return nullptr;
-    const int64_t pairs = (Mc + 7) / 8 * 8;
-    char* base = static_cast<char*>(mailbox);
-    return reinterpret_cast<int*>(base + (size_t)pairs * 2 * 2 * N * sizeof(uint64_t));
+int64_t resident_concurrency(int config, size_t lds) {
+    const Config& c = kConfigs[config];
+    if (c.S == 1) return resident_max_pairs();
+    // the occupancy query honours the dynamic-LDS limit of the kernel
+    if (resident_prepare(config, kMaxLds) != FTWA_OK) return (int64_t)device_cus() * c.UNITS;
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.fn, c.NTU * c.UNITS, lds) !=
+            hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return (int64_t)per_cu * device_cus() * c.UNITS;
 }
 
-ftwa_status resident_run(const ResidentPlan& plan, const ResidentPass& pass, hipStream_t stream) {
-    const Config& c = kConfigs[plan.config];
-    ResidentArgs A;
-    A.N = pass.N;
-    A.P = (int)packed_count(pass.N);
-    A.Mc = pass.Mc;
-    A.rho = pass.rho;
-    A.ldr = pass.ldr;
-    A.desc = pass.desc;
-    A.t = pass.t;
-    A.U = pass.U;
-    A.dt = pass.dt;
-    A.n_steps = pass.n_steps;
-    A.record_every = pass.record_every;
-    A.X = pass.X;
-    A.inv_parts = pass.inv_parts;
-    A.mailbox = static_cast<uint64_t*>(pass.mailbox);
-    A.error = nullptr;
-    FTWA_HIP_TRY(hipFuncSetAttribute(c.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
-    void* args[] = {&A};
+int64_t resident_grid(int config, size_t lds, int64_t n_items) {
+    const Config& c = kConfigs[config];
     if (c.S == 1) {
-        const int64_t pairs = (pass.Mc + 7) / 8 * 8;
-        A.error = resident_error_word(plan, pass.N, pass.Mc, pass.mailbox);
+        const int64_t pairs = std::min((n_items + 7) / 8 * 8, resident_max_pairs());
+        return 2 * pairs;
+    }
+    const int64_t cap = resident_concurrency(config, lds) / c.UNITS;
+    return std::max<int64_t>(1, std::min(n_items, cap));
+}
+
+// Spin-split scratch of one launch: the mailbox words, then the error word.
+size_t resident_mailbox_bytes(int config, int Nmax, int64_t n_items) {
+    if (kConfigs[config].S != 1) return 0;
+    const int64_t pairs = resident_grid(config, 0, n_items) / 2;
+    return (size_t)pairs * 2 * 2 * Nmax * sizeof(uint64_t) + 64;
+}
+
+int* resident_error_word(int config, int Nmax, int64_t n_items, void* mailbox) {
+    if (kConfigs[config].S != 1) return nullptr;
+    const int64_t pairs = resident_grid(config, 0, n_items) / 2;
+    return reinterpret_cast<int*>(static_cast<char*>(mailbox) +
+                                  (size_t)pairs * 2 * 2 * Nmax * sizeof(uint64_t));
+}
+
+
+ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
+    const Config& c = kConfigs[L.config];
+    if (L.n_items <= 0) return FTWA_OK;
+    ResidentArgs A;
+    A.table = L.table;
+    A.n_entries = L.n_entries;
+    A.n_items = L.n_items;
+    A.dt = L.dt;
+    A.n_steps = L.n_steps;
+    A.record_every = L.record_every;
+    A.mailbox = static_cast<uint64_t*>(L.mailbox);
+    A.Nmax = L.Nmax;
+    A.error = L.error;
+    void* args[] = {&A};
+    const int64_t grid = L.grid;
+    if (c.S == 1) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,
-        // no memset node); the error word is cleared once per ftwa_evolve call
-        ftwa_status st = zero_words(static_cast<unsigned*>(pass.mailbox),
-                                    pairs * 2 * 2 * pass.N * 2, stream);
+        // no memset node)
+        ftwa_status st = zero_words(static_cast<unsigned*>(L.mailbox),
+                                    (grid / 2) * 2 * 2 * (int64_t)L.Nmax * 2, stream);
         if (st != FTWA_OK) return st;
-        // both workgroups of a pair must be resident at the same time
-        FTWA_HIP_TRY(hipLaunchCooperativeKernel(c.fn, dim3((unsigned)(2 * pairs)), dim3(plan.threads),
-                                                args, (unsigned)plan.lds, stream));
+        // both workgroups of a pair must be resident at the same time: the
+        // grid never exceeds one workgroup per CU; a cooperative launch checks
+        // it (not available under graph capture, where the bounded waits
+        // report a partner that never came)
+        if (L.cooperative)
+            FTWA_HIP_TRY(hipLaunchCooperativeKernel(c.fn, dim3((unsigned)grid),
+                                                    dim3(c.NTU * c.UNITS), args,
+                                                    (unsigned)L.lds, stream));
+        else
+            FTWA_HIP_TRY(hipLaunchKernel(c.fn, dim3((unsigned)grid), dim3(c.NTU * c.UNITS), args,
+                                         (unsigned)L.lds, stream));
     } else {
-        const int64_t blocks = (pass.Mc + c.UNITS - 1) / c.UNITS;
-        FTWA_HIP_TRY(hipLaunchKernel(c.fn, dim3((unsigned)blocks), dim3(plan.threads), args,
-                                     (unsigned)plan.lds, stream));
+        FTWA_HIP_TRY(hipLaunchKernel(c.fn, dim3((unsigned)grid), dim3(c.NTU * c.UNITS), args,
+                                     (unsigned)L.lds, stream));
     }
     return FTWA_OK;
 }

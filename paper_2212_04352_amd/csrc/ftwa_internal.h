@@ -74,6 +74,10 @@ ftwa_status hip_fail(hipError_t e, const char* what);
         if (_e != hipSuccess) return ::ftwa::hip_fail(_e, what);            \
     } while (0)
 
+// Host validation of an instance array (api.hip).
+ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_moments,
+                            const char* who);
+
 // Uploads (once per device) and returns the lattice's device tables.
 ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
 // Descriptor table with the even class padded to even_slots entries and the
@@ -139,28 +143,53 @@ struct ResidentPlan {
     int64_t odd_slots = 0;
     size_t lds = 0;
 };
-struct ResidentPass {
+// One entry of a resident launch's table: a window of trajectories of one
+// instance (device memory, read by the kernel).
+struct ResidentInst {
     int N;
-    int64_t Mc;
-    void* rho;           // instance rho offset to the pass's first trajectory
+    int P;
+    int64_t Mc;          // trajectories in the window (the record width)
+    void* rho;           // instance state offset to the window's first trajectory
     int64_t ldr;         // instance n_traj
     const uint4* desc;   // padded_descriptors(lat, plan.even_slots, plan.odd_slots)
-    double t, U, dt;
-    int64_t n_steps;
-    int record_every;
+    double t, U;
     double* X;           // [n_rec][2N][Mc]
     double* inv_parts;   // NULL or [n_rec][2 spins][hop, frob][Mc]
-    void* mailbox;       // resident_mailbox_bytes(...) of scratch
+    int64_t item0;       // first item of this entry (items of earlier entries before it)
+};
+struct ResidentLaunch {
+    int config;
+    size_t lds;                 // dynamic LDS: max over the entries
+    const ResidentInst* table;  // device
+    int n_entries;
+    int64_t n_items;
+    int64_t grid;               // resident_grid(config, lds, n_items), fixed at plan time
+    int Nmax;
+    double dt;
+    int64_t n_steps;
+    int record_every;
+    void* mailbox;              // resident_mailbox_bytes(config, Nmax, n_items) of scratch
+    int* error;                 // resident_error_word(...) or NULL
+    bool cooperative;           // false under graph capture
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
                    int force_config = -1);
 int resident_config_count();
-int64_t resident_max_traj(const ResidentPlan& plan);
-size_t resident_mailbox_bytes(const ResidentPlan& plan, int N, ftwa_dtype dtype, int64_t Mc);
-int* resident_error_word(const ResidentPlan& plan, int N, int64_t Mc, void* mailbox);
-ftwa_status resident_run(const ResidentPlan& plan, const ResidentPass& pass, hipStream_t stream);
+int resident_spins(int config);
+int64_t resident_item_traj(int config);      // trajectories per item of the schedule
+int64_t resident_max_pairs();
+int64_t resident_concurrency(int config, size_t lds);  // trajectories in flight at once
+int64_t resident_grid(int config, size_t lds, int64_t n_items);
+size_t resident_mailbox_bytes(int config, int Nmax, int64_t n_items);
+int* resident_error_word(int config, int Nmax, int64_t n_items, void* mailbox);
+ftwa_status resident_prepare(int config, size_t lds);  // host only, not under graph capture
+ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream);
 ftwa_status resident_check_error(const int* err, hipStream_t stream, bool* timed_out);
+
+// Configurations chosen by ftwa_autotune, per (device, N, even-class size, dtype).
+bool tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int* config);
+void set_tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int config);
 
 // Brackets launches of the dominant kernel with HIP events on one stream and
 // sums their durations (optional, see ftwa_tuning::kernel_ms).
