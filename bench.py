@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--horizon-steps", type=int, default=None,
                     help="override the number of RK4 steps (default: the full horizon)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "resident"])
+    ap.add_argument("--config", type=int, default=-1,
+                    help="force a resident kernel configuration (default: autotuned)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the configuration autotuner (first fitting configuration)")
     ap.add_argument("--fp64-traj", type=int, default=4096,
                     help="trajectories of the FP64 comparison (the first ones of the batch)")
     ap.add_argument("--fp64-steps", type=int, default=None,
@@ -83,13 +87,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_pass(ft, torch, W, lat, n0, dtype, M, n_steps, path, seed, workspace):
+def run_pass(ft, torch, W, lat, n0, dtype, M, n_steps, path, seed, workspace, config=-1):
     """One pass of the hot path; returns (problem, workspace, timing, observables)."""
     prob = ft.Problem.allocate(lat, W.U, M, n0, dtype)
     ft.sample(prob, seed)
     timing = ft.new_timing()
     workspace = ft.evolve(prob, W.dt, n_steps, W.record_every, path=path, workspace=workspace,
-                          timing=timing)
+                          timing=timing, config=config)
     obs = ft.observables(prob)
     return prob, workspace, timing, obs
 
@@ -153,11 +157,24 @@ def main():
     N = lat.N
 
     # ---------------------------------------------------------------- FP32 (headline)
-    path32 = resolved_path(ft, lat, "f32", args.path)
+    tuned = None
+    if args.config < 0 and not args.no_autotune and args.path == "auto":
+        probe = ft.Problem.allocate(lat, W.U, min(M, 2048), n0, "f32")
+        ft.sample(probe, W.seed)
+        tuned = ft.autotune(probe, probe_steps=20)[0]
+        del probe
+        log(f"autotuned configuration for N={N} f32: {tuned} (-1 = stream path)")
+    if args.config >= 0:
+        path32 = "resident"
+    elif tuned is not None:
+        path32 = "resident" if tuned >= 0 else "stream"
+    else:
+        path32 = resolved_path(ft, lat, "f32", args.path)
     ws = None
     for k in range(args.warmup):
         log(f"warmup pass {k + 1}/{args.warmup} (f32, {path32}, {M} trajectories x {n_steps} steps)")
-        prob, ws, _, _ = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, path32, W.seed, ws)
+        prob, ws, _, _ = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, path32, W.seed, ws,
+                                  args.config)
         del prob
     torch.cuda.synchronize()
     kernel_ms = 0.0
@@ -167,7 +184,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         prob32, ws, timing, obs32 = run_pass(ft, torch, W, lat, n0, "f32", M, n_steps, path32,
-                                             W.seed, ws)
+                                             W.seed, ws, args.config)
         kernel_ms += timing["ms"].value
         launches += timing["launches"].value
         work += timing["work"].value
@@ -196,7 +213,8 @@ def main():
         "data": "synthetic (seeded Philox Gaussian samples around a Neel Fock state)",
         "config": {"workload": W.name, "lattice": "armchair 10x20 trimmed, N=198", "U": W.U,
                    "trajectories": M, "dt": W.dt, "rk4_steps": n_steps,
-                   "record_every": W.record_every, "moments": "f64", "path": path32},
+                   "record_every": W.record_every, "moments": "f64", "path": path32,
+                   "kernel_config": args.config if args.config >= 0 else tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "kernel_avg_ms": avg_ms,

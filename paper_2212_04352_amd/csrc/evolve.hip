@@ -272,7 +272,7 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 e.rho = static_cast<char*>(inst[k].rho) + (size_t)m0 * cplx_bytes(p.dtype);
                 e.ldr = inst[k].n_traj;
                 if ((st = padded_descriptors(inst[k].lat, ip.res.even_slots, ip.res.odd_slots,
-                                             &e.desc)) != FTWA_OK)
+                                             (int)cplx_bytes(p.dtype), &e.desc)) != FTWA_OK)
                     return st;
                 e.t = inst[k].lat->t;
                 e.U = inst[k].U;

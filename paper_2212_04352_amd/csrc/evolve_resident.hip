@@ -9,12 +9,25 @@
 // Layout on chip.  A workgroup holds UNITS "units"; a unit is one trajectory
 // (S = 2: both spin blocks) or one spin block of one trajectory (S = 1, the
 // partner workgroup holds the other spin).  The current Runge-Kutta stage
-// input Y of a unit lives in LDS as packed upper triangles plus two extra
-// slots per block: slot P is always zero and stands in for missing
-// neighbours, slot P+1 is scratch owned by padding elements.  The base point
-// y and the accumulator acc of every element live in the registers of the
-// thread that owns it.  The two spin diagonals of the stage sit in a small
-// LDS vector.
+// input Y of a unit lives in LDS, one block of P + 2 complex slots per spin:
+// the packed elements in "class order" (the even class -- diagonal first,
+// element (i,i) at slot i -- then the odd class, see below), slot P always
+// zero (stands in for missing neighbours), slot P+1 scratch owned by padding
+// elements.  The base point y and the accumulator acc of every element live
+// in the registers of the thread that owns it.  The U term reads the other
+// spin's diagonal from slots 0..N-1 of its block (S = 2) or from a copy of
+// the partner's diagonal next to the block (S = 1).  The kernel declares no
+// static LDS, so block offsets are LDS addresses.
+//
+// Descriptors.  Each element has a 32-byte descriptor with the LDS byte
+// offsets of its six neighbour elements and of itself, and of the two
+// diagonal values; a neighbour stored as its transpose carries a flag, and
+// its imaginary part enters the sums with the factor -1 (fma(+-1, v, s)
+// rounds exactly like s +- v), so the arithmetic is that of the equation of
+// motion in a fixed order.  Consecutive threads own consecutive slots, so
+// own reads and writes of a wave are contiguous; neighbours of consecutive
+// same-class elements of a row are mostly consecutive slots of the other
+// class.
 //
 // Two-phase stages.  The honeycomb is bipartite: an element (i, j) with i and
 // j on the same sublattice ("even") reads only elements joining different
@@ -24,7 +37,9 @@
 // reads an odd element during phase 2 except its owner); after a second
 // barrier the held even values are written.  Only half of the next-stage
 // values is ever held, which is what lets the 198-site FP32 spin block live in
-// one CU (157.6 KB of LDS, y/acc in VGPRs).
+// one CU (157.6 KB of LDS, y/acc in VGPRs).  Each element's descriptor is
+// loaded one element ahead; every stage is compiled separately (no
+// per-element tests of the stage number).
 //
 // Element slots.  Thread t of a unit owns element t + NTU*u of the even class
 // for u < UE and of the odd class for UE <= u < UE + UO.  Both classes are
@@ -40,6 +55,7 @@
 // fence (and no cache write-back or invalidation) is needed.  Waits are
 // bounded; a timeout aborts both workgroups and is reported.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 #include "ftwa_internal.h"
@@ -57,75 +73,121 @@ struct ResidentArgs {
     int record_every;
     uint64_t* mailbox;          // S = 1: [pairs][2 spins][2 slots][Nmax] stage-stamped words
     int Nmax;
+    uint32_t tail_off;          // LDS byte offset of the record sums and the abort flag
     int* error;                 // set to 1 when a wait times out
 };
 
 constexpr unsigned kSpinLimit = 1u << 26;  // ~2 s of polling
 
-template <typename C>
-__device__ __forceinline__ C lds_nb(const C* Y, uint32_t field) {
-    C v = Y[field & 0x7fffu];
-    if (field & 0x8000u) v.y = -v.y;
-    return v;
+// Descriptor table as a global-address-space pointer.  It is passed through
+// an SGPR every phase ("laundered") so that the compiler re-reads descriptors
+// instead of keeping one address or index register per slot alive across the
+// time loop; keeping the address space lets the loads use a scalar base plus
+// the one per-thread offset shared by all slots.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(1))) ResDesc* gdesc_t;
+#else
+typedef const ResDesc* gdesc_t;  // host pass of the kernel source only
+#endif
+
+// A value the compiler cannot prove wave-uniform (read from the launch
+// table) moved into scalar registers: every lane holds the same value.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename T> __device__ __forceinline__ T uniform_real(T v);
+template <> __device__ __forceinline__ float uniform_real<float>(float v) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+template <> __device__ __forceinline__ double uniform_real<double>(double v) {
+    return __longlong_as_double((long long)uniform64((uint64_t)__double_as_longlong(v)));
 }
 
-template <typename C>
-__device__ __forceinline__ C lds_nb_plain(const C* Y, uint32_t field) {
-    return Y[field & 0x7fffu];
+__device__ __forceinline__ gdesc_t launder(gdesc_t p) {
+    uint64_t v = (uint64_t)p;
+    __asm__ volatile("" : "+s"(v)::"memory");
+    return (gdesc_t)v;
 }
 
-// Right-hand side of one element from its descriptor; CONJ selects the
-// variant that honours the conjugate flags (needed only near the diagonal).
-template <typename T, bool CONJ>
-__device__ __forceinline__ cplx_t<T> stencil(const cplx_t<T>* Yb, const T* dother, uint4 d, T t,
-                                             T U) {
-    using C = cplx_t<T>;
-    const uint32_t own = d.x & 0x7fffu;
-    const int i = (d.x >> 16) & 0xff, j = d.x >> 24;
-    C c0, c1, c2, r0, r1, r2;
-    if (CONJ) {
-        c0 = lds_nb(Yb, d.y); c1 = lds_nb(Yb, d.y >> 16); c2 = lds_nb(Yb, d.z);
-        r0 = lds_nb(Yb, d.z >> 16); r1 = lds_nb(Yb, d.w); r2 = lds_nb(Yb, d.w >> 16);
-    } else {
-        c0 = lds_nb_plain(Yb, d.y); c1 = lds_nb_plain(Yb, d.y >> 16); c2 = lds_nb_plain(Yb, d.z);
-        r0 = lds_nb_plain(Yb, d.z >> 16); r1 = lds_nb_plain(Yb, d.w); r2 = lds_nb_plain(Yb, d.w >> 16);
-    }
-    const C col = cadd(cadd(c0, c1), c2);
-    const C row = cadd(cadd(r0, r1), r2);
-    const C rho = Yb[own];
-    const T a = U * (dother[i] - dother[j]);
-    return rhs_element<T>(col, row, rho, t, a);
+__device__ __forceinline__ ResDesc load_desc(gdesc_t p) {
+    ResDesc d;
+    d.a = p->a;
+    d.b = p->b;
+    return d;
 }
 
-__device__ __forceinline__ bool needs_conj(uint4 d) {
-    return ((d.y | d.z | d.w) & 0x80008000u) != 0u;
+// Descriptor of slot `slot` of this thread: a wave-uniform slot base (scalar
+// registers, opaque so that it stays one) plus the thread's 32-bit byte
+// offset, the same for every slot.
+__device__ __forceinline__ ResDesc slot_desc(gdesc_t desc, int slot, uint32_t toff) {
+    uint64_t b = (uint64_t)(desc + slot);
+    __asm__("" : "+s"(b));
+    const __attribute__((address_space(1))) char* base =
+        (const __attribute__((address_space(1))) char*)b;
+    return load_desc((gdesc_t)(base + toff));
+}
+
+// Conjugation by the descriptor's bit 31: the imaginary part enters the
+// neighbour sums with the factor -1 (+1 otherwise).  The factor is formed
+// from the descriptor alone, so all LDS reads of an element can be issued
+// before any of their values is needed; fma(+-1, v, s) rounds exactly like
+// s +- v.
+template <typename T> __device__ __forceinline__ T conj_sign(uint32_t f);
+template <> __device__ __forceinline__ float conj_sign<float>(uint32_t f) {
+    return __uint_as_float((f & 0x80000000u) | 0x3f800000u);
+}
+template <> __device__ __forceinline__ double conj_sign<double>(uint32_t f) {
+    return __hiloint2double((int)((f & 0x80000000u) | 0x3ff00000u), 0);
 }
 
 template <typename T>
-__device__ __forceinline__ cplx_t<T> element_rhs(const cplx_t<T>* Yb, const T* dother, uint4 d,
-                                                 T t, T U) {
-    return __any(needs_conj(d)) ? stencil<T, true>(Yb, dother, d, t, U)
-                                : stencil<T, false>(Yb, dother, d, t, U);
+__device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t f) {
+    return *reinterpret_cast<const cplx_t<T>*>(base + (f & 0x7fffffffu));
+}
+
+// Right-hand side of one element from its descriptor: Yb is the LDS block of
+// its spin, Yd the block holding the other spin's diagonal at slots 0..N-1.
+// Sums as in the equation of motion: col = (v0 + v1) + v2 over the column
+// neighbours, row likewise, each v conjugated when its flag is set.
+template <typename T>
+__device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
+                                                 const ResDesc& d, T t, T U) {
+    using C = cplx_t<T>;
+    const C c0 = lds_at<T>(Yb, d.a.x), c1 = lds_at<T>(Yb, d.a.y), c2 = lds_at<T>(Yb, d.a.z);
+    const C r0 = lds_at<T>(Yb, d.b.x), r1 = lds_at<T>(Yb, d.b.y), r2 = lds_at<T>(Yb, d.b.z);
+    const C rho = *reinterpret_cast<const C*>(Yb + (d.a.w & 0x7fffffffu));
+    const T di = *reinterpret_cast<const T*>(Yd + (d.b.w & 0xffffu));
+    const T dj = *reinterpret_cast<const T*>(Yd + (d.b.w >> 16));
+    C col, row;
+    col.x = (c0.x + c1.x) + c2.x;
+    col.y = fma_rn<T>(conj_sign<T>(d.a.z), c2.y,
+                      fma_rn<T>(conj_sign<T>(d.a.y), c1.y, conj_sign<T>(d.a.x) * c0.y));
+    row.x = (r0.x + r1.x) + r2.x;
+    row.y = fma_rn<T>(conj_sign<T>(d.b.z), r2.y,
+                      fma_rn<T>(conj_sign<T>(d.b.y), r1.y, conj_sign<T>(d.b.x) * r0.y));
+    const T a = U * (di - dj);
+    return rhs_element<T>(col, row, rho, t, a);
 }
 
 // One Runge-Kutta stage update of an element from its slope k:
 //   stage 1: acc = k;                 next = fma(c, k, y)
 //   stage 2, 3: acc = fma(2, k, acc); next = fma(c, k, y)
 //   stage 4: acc = acc + k;           y = fma(c, acc, y); next = y
-template <typename T>
-__device__ __forceinline__ cplx_t<T> rk_update(int stage, T c, cplx_t<T> k, cplx_t<T>& y,
-                                               cplx_t<T>& acc) {
+template <int STAGE, typename T>
+__device__ __forceinline__ cplx_t<T> rk_update(T c, cplx_t<T> k, cplx_t<T>& y, cplx_t<T>& acc) {
     cplx_t<T> nx;
-    if (stage == 1) {
+    if constexpr (STAGE == 1) {
         acc = k;
-    } else if (stage < 4) {
+    } else if constexpr (STAGE < 4) {
         acc.x = fma_rn<T>((T)2, k.x, acc.x);
         acc.y = fma_rn<T>((T)2, k.y, acc.y);
     } else {
         acc.x = acc.x + k.x;
         acc.y = acc.y + k.y;
     }
-    if (stage < 4) {
+    if constexpr (STAGE < 4) {
         nx.x = fma_rn<T>(c, k.x, y.x);
         nx.y = fma_rn<T>(c, k.y, y.y);
     } else {
@@ -136,43 +198,26 @@ __device__ __forceinline__ cplx_t<T> rk_update(int stage, T c, cplx_t<T> k, cplx
     return nx;
 }
 
-// Descriptor table as a global-address-space pointer.  It is passed through
-// an SGPR every phase ("laundered") so that the compiler re-reads descriptors
-// instead of keeping one address or index register per slot alive across the
-// time loop; keeping the address space lets the loads use a scalar base plus
-// the one per-thread offset shared by all slots.
-#if defined(__HIP_DEVICE_COMPILE__)
-typedef const __attribute__((address_space(1))) uint4* gdesc_t;
-#else
-typedef const uint4* gdesc_t;  // host pass of the kernel source only
-#endif
-
-// A value the compiler cannot prove wave-uniform (read from the launch
-// table) moved into scalar registers: every lane holds the same value.
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ gdesc_t launder(gdesc_t p) {
-    uint64_t v = (uint64_t)p;
-    __asm__ volatile("" : "+s"(v)::"memory");
-    return (gdesc_t)v;
-}
-
 template <typename T> __device__ __forceinline__ unsigned to_bits(T v);
 template <> __device__ __forceinline__ unsigned to_bits<float>(float v) { return __float_as_uint(v); }
 template <typename T> __device__ __forceinline__ T from_bits(unsigned v);
 template <> __device__ __forceinline__ float from_bits<float>(unsigned v) { return __uint_as_float(v); }
 
+template <int V> using stage_c = std::integral_constant<int, V>;
+
+// Generic pointer to LDS byte address `a` (the kernel's dynamic LDS block
+// starts at address 0).
+__device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
+    return (unsigned char*)(__attribute__((address_space(3))) unsigned char*)(uintptr_t)a;
+}
+
 template <typename T, int S, int NTU, int UNITS, int UE, int UO>
 __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     constexpr int kEvenPad = NTU * UE;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int abort_flag;
-    __shared__ double red[(NTU * UNITS) / 64][2 * S];  // per-wave partial sums (records)
+    constexpr int CB = (int)sizeof(C);
+    extern __shared__ __align__(16) unsigned char smem[];  // dynamic LDS, at address 0
+    (void)smem;
     const int tid0 = threadIdx.x;
 
     // Persistent schedule.  S = 2: workgroup b takes items b, b + grid, ...
@@ -193,7 +238,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         first = blockIdx.x;
         stride = gridDim.x;
     }
-    if (tid0 == 0) abort_flag = 0;
+    if (tid0 == 0) *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU * UNITS / 64) * 2 * S * 8)) = 0;
     uint64_t* const mb = A.mailbox;
     int64_t g = 0;  // stage counter (continues across items)
 
@@ -203,12 +248,13 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         // thread coordinates are re-derived every item (an opaque copy of the
         // thread index), so that per-slot offsets are not hoisted out of the
         // item loop and kept in registers across it
-        int tid = tid0;
-        __asm__ volatile("" : "+v"(tid));
-        const int unit = tid / NTU;
-        const int t = tid % NTU;
+        const int tid = tid0;
+        const int unit = UNITS == 1 ? 0 : tid / NTU;
+        const int t = UNITS == 1 ? tid : tid % NTU;
+        const uint32_t toff = (uint32_t)t * (uint32_t)sizeof(ResDesc);
         const int lane = tid % 64;
         const int wave = tid / 64;
+
         // table entry of this item (uniform: scalar loads)
         int ent = 0;
         while (ent + 1 < A.n_entries && A.table[ent + 1].item0 <= item) ++ent;
@@ -217,9 +263,16 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const int N = E.N;
         const int P = E.P;
         const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
-        C* const Yunit = reinterpret_cast<C*>(smem) + (size_t)unit * S * Pb;
-        T* const dvec =
-            reinterpret_cast<T*>(smem + (size_t)UNITS * S * Pb * sizeof(C)) + (size_t)unit * 2 * N;
+        // LDS: UNITS x S blocks of Pb complex slots; S = 1 adds per unit the
+        // partner's diagonal as N complex values (imaginary parts zero)
+        // the launch has no static LDS, so the dynamic block starts at LDS
+        // address 0 and block offsets are addresses (no base register)
+        unsigned char* const Yunit = lds_ptr((uint32_t)((size_t)unit * S * Pb * CB));
+        unsigned char* const dpart = lds_ptr((uint32_t)((size_t)UNITS * S * Pb * CB + (size_t)unit * N * CB));
+        // per-wave partial sums of the records and the abort flag follow
+        // (placed after the largest blocks of the launch: A.tail_off)
+        double (*red)[2 * S] = reinterpret_cast<double (*)[2 * S]>(lds_ptr(A.tail_off));
+        int& abort_flag = *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU * UNITS / 64) * 2 * S * 8));
         const int64_t Mc = E.Mc;
         const int64_t m = (item - E.item0) * (S == 1 ? 1 : UNITS) + (S == 1 ? 0 : unit);
         const bool active = m < Mc;
@@ -230,6 +283,12 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         gdesc_t desc = (gdesc_t)uniform64((uint64_t)E.desc);
         __syncthreads();  // the previous item is done with LDS and `red`
 
+        // packed index of the element a descriptor describes (i, j from the
+        // diagonal offsets), for the state in HBM
+        auto packed_of = [&](const ResDesc& d) -> int64_t {
+            const int i = (int)((d.b.w & 0xffffu) / CB), j = (int)((d.b.w >> 16) / CB);
+            return (int64_t)i * N - (int64_t)i * (i - 1) / 2 + (j - i);
+        };
         // ---- load the trajectory into registers and LDS
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -237,12 +296,14 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
             for (int u = 0; u < UE + UO; ++u) {
                 const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                const uint32_t p = desc[e].x & 0x7fffu;
+                const ResDesc d = load_desc(desc + e);
+                const uint32_t own = d.a.w & 0x7fffffffu;
                 C v;
                 v.x = 0;
                 v.y = 0;
-                if (active && (int)p < P) v = rho[((int64_t)gs * P + p) * ldr + m];
-                Yunit[s * Pb + p] = v;  // dummies write the scratch slot
+                if (active && own < (uint32_t)P * CB)
+                    v = rho[((int64_t)gs * P + packed_of(d)) * ldr + m];
+                *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = v;  // dummies: scratch slot
                 y[s][u] = v;
                 acc[s][u] = v;
             }
@@ -250,14 +311,18 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 C z;
                 z.x = 0;
                 z.y = 0;
-                Yunit[s * Pb + P] = z;
-                Yunit[s * Pb + P + 1] = z;
+                reinterpret_cast<C*>(Yunit + s * Pb * CB)[P] = z;
+                reinterpret_cast<C*>(Yunit + s * Pb * CB)[P + 1] = z;
             }
         }
-        for (int idx = t; idx < 2 * N; idx += NTU) {
-            const int gs = idx / N, i = idx - gs * N;
-            const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
-            dvec[idx] = active ? rho[((int64_t)gs * P + p) * ldr + m].x : (T)0;
+        if constexpr (S == 1) {
+            for (int i = t; i < N; i += NTU) {
+                const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
+                C v;
+                v.x = active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
+                v.y = 0;
+                reinterpret_cast<C*>(dpart)[i] = v;
+            }
         }
         // records: the first N even elements are the diagonal (i = position)
         // (every configuration has N <= NTU, so only slot 0 can hold them)
@@ -279,11 +344,11 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
                     for (int u = 0; u < UE + UO; ++u) {
                         const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                        const uint32_t dx = desc[e].x;
+                        const uint32_t dw = desc[e].a.w;
                         const double re = (double)y[s][u].x, im = (double)y[s][u].y;
                         const bool diag = u < UE && e < N;
                         frob[s] += diag ? re * re : 2.0 * (re * re + im * im);
-                        if (dx & 0x8000u) hop[s] += 2.0 * re;
+                        if (dw & 0x80000000u) hop[s] += 2.0 * re;
                     }
                     for (int off = 32; off > 0; off /= 2) {
                         hop[s] += __shfl_xor(hop[s], off, 64);
@@ -316,97 +381,115 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         record(0);
         __syncthreads();
 
-        const T tw = (T)E.t, Uw = (T)E.U;
-        const T c_half = (T)(0.5 * A.dt), c_full = (T)A.dt, c_sixth = (T)(A.dt / 6.0);
+        const T tw = uniform_real<T>((T)E.t), Uw = uniform_real<T>((T)E.U);
+        const T c_half = uniform_real<T>((T)(0.5 * A.dt));
+        const T c_full = uniform_real<T>((T)A.dt);
+        const T c_sixth = uniform_real<T>((T)(A.dt / 6.0));
 
-        for (int64_t step = 1; step <= A.n_steps; ++step) {
-#pragma unroll 1
-            for (int stage = 1; stage <= 4; ++stage, ++g) {
-                const T c = stage <= 2 ? c_half : (stage == 3 ? c_full : c_sixth);
-                desc = launder(desc);  // descriptors are re-read every phase
-                // ---------------- phase 1: even elements (next values held in registers)
+        // One Runge-Kutta stage (STAGE = 1..4) of every element of the unit.
+        // Returns false when a spin-split wait timed out.
+        auto run_stage = [&](auto stage_tag) -> bool {
+            constexpr int STAGE = decltype(stage_tag)::value;
+            const T c = STAGE <= 2 ? c_half : (STAGE == 3 ? c_full : c_sixth);
+            desc = launder(desc);  // descriptors are re-read every phase
+            // ---------------- phase 1: even elements (next values held in
+            // registers); the next slot's descriptor is loaded one slot ahead
+            ResDesc dn = slot_desc(desc, 0, toff);
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                const ResDesc d = dn;
+                dn = slot_desc(desc, u + 1 < UE ? NTU * (u + 1) : kEvenPad, toff);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const C* Yb = Yunit + s * Pb;
-                    const T* dother = dvec + (1 - (spin0 + s)) * N;
-#pragma unroll
-                    for (int u = 0; u < UE; ++u) {
-                        const uint4 d = (desc + NTU * u)[t];
-                        const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
-                        hold[s][u] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
-                    }
+                    const unsigned char* Yb = Yunit + s * Pb * CB;
+                    const unsigned char* Yd = S == 1 ? dpart : Yunit + (1 - s) * Pb * CB;
+                    const C k = element_rhs<T>(Yb, Yd, d, tw, Uw);
+                    hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                 }
-                if constexpr (S == 1) {
-                    // publish the next-stage diagonal of this spin for the partner:
-                    // one 64-bit word per site, (stage number << 32) | value bits,
-                    // written with a single relaxed agent-scope atomic store
-                    if (t < N) {
-                        uint64_t* slot =
-                            mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * A.Nmax;
-                        const uint64_t word = ((uint64_t)(g + 1) << 32) | to_bits<T>(hold[0][0].x);
-                        __hip_atomic_store(slot + t, word, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-                __syncthreads();
-                desc = launder(desc);
-                // ---------------- phase 2: odd elements (written straight to LDS)
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    C* Yb = Yunit + s * Pb;
-                    const T* dother = dvec + (1 - (spin0 + s)) * N;
-#pragma unroll
-                    for (int u = UE; u < UE + UO; ++u) {
-                        const uint4 d = (desc + kEvenPad + NTU * (u - UE))[t];
-                        const C k = element_rhs<T>(Yb, dother, d, tw, Uw);
-                        Yb[d.x & 0x7fffu] = rk_update<T>(stage, c, k, y[s][u], acc[s][u]);
-                    }
-                }
-                __syncthreads();
-                desc = launder(desc);
-                // ---------------- held even values and the diagonals
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    C* Yb = Yunit + s * Pb;
-#pragma unroll
-                    for (int u = 0; u < UE; ++u) Yb[(desc + NTU * u)[t].x & 0x7fffu] = hold[s][u];
-                    if (t < N) dvec[(spin0 + s) * N + t] = hold[s][0].x;
-                }
-                if constexpr (S == 1) {
-                    if (wave == 0) {
-                        // partner's diagonal for the next stage: poll each word until
-                        // it carries stage g+1 (bounded; two slots alternate by parity,
-                        // so a word is never overwritten before it has been read)
-                        const uint64_t* slot =
-                            mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * A.Nmax;
-                        const uint32_t want = (uint32_t)(g + 1);
-                        int ok = 1;
-                        for (int i = lane; i < N; i += 64) {
-                            uint64_t w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                            unsigned it = 0;
-                            while ((uint32_t)(w >> 32) != want) {
-                                if (++it >= kSpinLimit) {
-                                    ok = 0;
-                                    break;
-                                }
-                                __builtin_amdgcn_s_sleep(1);
-                                w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                            }
-                            dvec[(1 - spin0) * N + i] = from_bits<T>((uint32_t)w);
-                        }
-                        if (__any(!ok) && lane == 0) {
-                            abort_flag = 1;
-                            atomicExch(A.error, 1);
-                        }
-                    }
-                }
-                __syncthreads();
-                if constexpr (S == 1) {
-                    if (abort_flag) return;
+                if (u == 0) {
+            if constexpr (S == 1) {
+                // publish the next-stage diagonal of this spin for the partner:
+                // one 64-bit word per site, (stage number << 32) | value bits,
+                // written with a single relaxed agent-scope atomic store
+                if (t < N) {
+                    uint64_t* slot = mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * A.Nmax;
+                    const uint64_t word = ((uint64_t)(g + 1) << 32) | to_bits<T>(hold[0][0].x);
+                    __hip_atomic_store(slot + t, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
+                }
+                // one element per scheduling region: the scheduler may not pull
+                // later slots' loads forward (their registers would not fit)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            // ---------------- phase 2: odd elements (written straight to LDS)
+#pragma unroll
+            for (int u = UE; u < UE + UO; ++u) {
+                const ResDesc d = dn;
+                if (u + 1 < UE + UO) dn = slot_desc(desc, kEvenPad + NTU * (u + 1 - UE), toff);
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    unsigned char* Yb = Yunit + s * Pb * CB;
+                    const unsigned char* Yd = S == 1 ? dpart : Yunit + (1 - s) * Pb * CB;
+                    const C k = element_rhs<T>(Yb, Yd, d, tw, Uw);
+                    *reinterpret_cast<C*>(Yb + (d.a.w & 0x7fffffffu)) =
+                        rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            desc = launder(desc);
+            // ---------------- held even values (their slot is the class
+            // position t + NTU*u; padding entries write the scratch slot)
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                const uint32_t own = slot_desc(desc, NTU * u, toff).a.w & 0x7fffffffu;
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = hold[s][u];
+            }
+            if constexpr (S == 1) {
+                if (wave == 0) {
+                    // partner's diagonal for the next stage: poll each word until
+                    // it carries stage g+1 (bounded; two slots alternate by parity,
+                    // so a word is never overwritten before it has been read)
+                    const uint64_t* slot =
+                        mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * A.Nmax;
+                    const uint32_t want = (uint32_t)(g + 1);
+                    int ok = 1;
+                    for (int i = lane; i < N; i += 64) {
+                        uint64_t w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        unsigned it = 0;
+                        while ((uint32_t)(w >> 32) != want) {
+                            if (++it >= kSpinLimit) {
+                                ok = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                            w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        reinterpret_cast<C*>(dpart)[i].x = from_bits<T>((uint32_t)w);
+                    }
+                    if (__any(!ok) && lane == 0) {
+                        abort_flag = 1;
+                        atomicExch(A.error, 1);
+                    }
+                }
+            }
+            __syncthreads();
+            ++g;
+            if constexpr (S == 1) return abort_flag == 0;
+            return true;
+        };
+
+        for (int64_t step = 1; step <= A.n_steps; ++step) {
+            if (!run_stage(stage_c<1>{})) return;
+            if (!run_stage(stage_c<2>{})) return;
+            if (!run_stage(stage_c<3>{})) return;
+            if (!run_stage(stage_c<4>{})) return;
             if (step % A.record_every == 0) record(step / A.record_every);
         }
 
@@ -422,8 +505,9 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
                 for (int u = 0; u < UE + UO; ++u) {
                     const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                    const uint32_t p = desc[e].x & 0x7fffu;
-                    if ((int)p < P) rho_out[((int64_t)gs * P + p) * ldr + m] = y[s][u];
+                    const ResDesc d = load_desc(desc + e);
+                    if ((d.a.w & 0x7fffffffu) < (uint32_t)P * CB)
+                        rho_out[((int64_t)gs * P + packed_of(d)) * ldr + m] = y[s][u];
                 }
             }
         }
@@ -453,14 +537,20 @@ const Config kConfigs[] = {
     FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 8, 8),
     FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 13, 13),
     FTWA_RES_CFG(float, FTWA_F32, 1, 1024, 1, 10, 10),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 512, 1, 20, 20),
 };
 
-constexpr size_t kMaxLds = 160 * 1024 - 1024;  // leave room for static shared variables
+constexpr size_t kMaxLds = 160 * 1024;  // the kernel declares no static LDS
 
-size_t lds_bytes(const Config& c, int N, int P) {
-    const size_t cb = c.dtype == FTWA_F64 ? 16 : 8, rb = cb / 2;
-    return (size_t)c.UNITS * c.S * (P + 2) * cb + (size_t)c.UNITS * 2 * N * rb;
+// Dynamic LDS of a launch: the state blocks (S = 1 adds the partner's
+// diagonal), then the per-wave record sums and the abort flag.
+size_t lds_blocks(const Config& c, int N, int P) {
+    const size_t cb = c.dtype == FTWA_F64 ? 16 : 8;
+    const size_t b = (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? (size_t)c.UNITS * N * cb : 0);
+    return (b + 15) / 16 * 16;
 }
+size_t lds_tail(const Config& c) { return (size_t)(c.NTU * c.UNITS / 64) * 2 * c.S * 8 + 16; }
+size_t lds_bytes(const Config& c, int N, int P) { return lds_blocks(c, N, P) + lds_tail(c); }
 
 }  // namespace
 
@@ -573,6 +663,7 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     A.record_every = L.record_every;
     A.mailbox = static_cast<uint64_t*>(L.mailbox);
     A.Nmax = L.Nmax;
+    A.tail_off = (uint32_t)(L.lds - lds_tail(c));
     A.error = L.error;
     void* args[] = {&A};
     const int64_t grid = L.grid;

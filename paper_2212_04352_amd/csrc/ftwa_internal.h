@@ -22,15 +22,23 @@ struct DeviceTables {
     int32_t* nb = nullptr;     // [N][4]: three neighbours (ascending, -1 padded), degree
     int32_t* off = nullptr;    // [N]: packed row start i*N - i*(i-1)/2
     uint32_t* elem = nullptr;  // [P]: packed element p -> i | j << 16
-    // Stencil descriptors of the resident path, one per packed element, even
-    // class (i, j on the same sublattice, diagonal first) then odd class:
-    //   x = own p (15 bits) | bond flag << 15 (j is a neighbour of i) | i << 16 | j << 24
-    //   y = col0 | col1 << 16, z = col2 | row0 << 16, w = row1 | row2 << 16
-    // each neighbour field = packed index (15 bits, P = the zero slot for a
-    // missing neighbour) | conjugate flag << 15.
-    uint4* desc = nullptr;
-    int64_t n_even = 0;        // size of the even class
+    int64_t n_even = 0;        // size of the even class (i, j on the same sublattice)
     bool bipartite = false;
+};
+
+// Stencil descriptor of one element for the resident kernel (32 bytes), all
+// offsets in bytes within the LDS block of one spin:
+//   a.x, a.y, a.z: the column neighbours rho_ik, k in nb(j), ascending;
+//   b.x, b.y, b.z: the row neighbours rho_kj, k in nb(i), ascending;
+//     each = offset of the stored element | bit 31 set when the stored
+//     element is rho_ki (read its conjugate); a missing neighbour reads the
+//     zero slot P;
+//   a.w: offset of the element itself | bit 31 set when j is a neighbour of i
+//     (padding entries own the scratch slot P+1);
+//   b.w: offset of the diagonal (i,i) | offset of (j,j) << 16 (diagonal
+//     elements come first in the block, element i at slot i).
+struct ResDesc {
+    uint4 a, b;
 };
 
 }  // namespace ftwa
@@ -45,9 +53,9 @@ struct ftwa_lattice_s {
     std::mutex mu;
     std::map<int, ftwa::DeviceTables> dev;  // by HIP device ordinal
     // resident-path descriptors padded per class to whole slots, by
-    // (device, even slots, odd slots)
-    std::map<std::tuple<int, int64_t, int64_t>, uint4*> padded;
-    std::vector<uint4> host_desc;           // unpadded descriptors (even, then odd)
+    // (device, even slots, odd slots, element bytes)
+    std::map<std::tuple<int, int64_t, int64_t, int>, ftwa::ResDesc*> padded;
+    std::vector<uint32_t> class_order;      // i | j << 16 of the elements in LDS-slot order
 };
 
 namespace ftwa {
@@ -80,11 +88,12 @@ ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_mom
 
 // Uploads (once per device) and returns the lattice's device tables.
 ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
-// Descriptor table with the even class padded to even_slots entries and the
-// odd class to odd_slots entries; padding entries are dummies that own the
-// scratch slot P+1 and read only the zero slot P (uploaded once per shape).
+// Descriptor table in LDS-slot order with the even class padded to
+// even_slots entries and the odd class to odd_slots entries; padding entries
+// own the scratch slot P+1 and read only the zero slot P (uploaded once per
+// shape and element size).
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               const uint4** out);
+                               int elem_bytes, const ResDesc** out);
 
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
@@ -151,7 +160,7 @@ struct ResidentInst {
     int64_t Mc;          // trajectories in the window (the record width)
     void* rho;           // instance state offset to the window's first trajectory
     int64_t ldr;         // instance n_traj
-    const uint4* desc;   // padded_descriptors(lat, plan.even_slots, plan.odd_slots)
+    const ResDesc* desc; // padded_descriptors(lat, plan.even_slots, plan.odd_slots, bytes)
     double t, U;
     double* X;           // [n_rec][2N][Mc]
     double* inv_parts;   // NULL or [n_rec][2 spins][hop, frob][Mc]

@@ -240,7 +240,6 @@ void ftwa_free_lattice(ftwa_lattice lat) {
         (void)hipFree(tab.nb);
         (void)hipFree(tab.off);
         (void)hipFree(tab.elem);
-        (void)hipFree(tab.desc);
     }
     for (auto& [key, ptr] : lat->padded) {
         if (hipSetDevice(std::get<0>(key)) != hipSuccess) continue;
@@ -288,9 +287,12 @@ namespace ftwa {
 // touches only elements joining different sublattices ("odd") and vice versa,
 // which lets the resident kernel update the two classes in separate phases.
 // Returns false when the graph has an odd cycle.
-bool build_descriptors(ftwa_lattice lat, std::vector<uint4>* desc, int64_t* n_even) {
+// Class order of the packed elements for the resident kernel: the even class
+// (i and j on the same sublattice; the diagonal first, then row-major), then
+// the odd class (row-major).  An element's position in this order is its
+// slot in the kernel's LDS block.  Returns false for a non-bipartite graph.
+bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* n_even) {
     const int N = lat->N;
-    const int64_t P = packed_count(N);
     std::vector<int> colour(N, -1);
     for (int root = 0; root < N; ++root) {
         if (colour[root] >= 0) continue;
@@ -306,70 +308,90 @@ bool build_descriptors(ftwa_lattice lat, std::vector<uint4>* desc, int64_t* n_ev
             }
         }
     }
-    auto field = [&](int a, int b) -> uint32_t {  // element (a, b) as stored
-        if (a <= b) return (uint32_t)(packed_row(N, a) + (b - a));
-        return (uint32_t)(packed_row(N, b) + (a - b)) | 0x8000u;
-    };
-    auto make = [&](int i, int j) {
-        uint32_t col[3], row[3];
-        for (int n = 0; n < kMaxDeg; ++n) {
-            const int kc = n < lat->deg[j] ? lat->nbr[(size_t)j * kMaxDeg + n] : -1;
-            const int kr = n < lat->deg[i] ? lat->nbr[(size_t)i * kMaxDeg + n] : -1;
-            col[n] = kc < 0 ? (uint32_t)P : field(i, kc);
-            row[n] = kr < 0 ? (uint32_t)P : field(kr, j);
-        }
-        bool bond = false;
-        for (int n = 0; n < lat->deg[i]; ++n) bond = bond || lat->nbr[(size_t)i * kMaxDeg + n] == j;
-        uint4 d;
-        d.x = (uint32_t)(packed_row(N, i) + (j - i)) | (bond ? 0x8000u : 0u) |
-              ((uint32_t)i << 16) | ((uint32_t)j << 24);
-        d.y = col[0] | (col[1] << 16);
-        d.z = col[2] | (row[0] << 16);
-        d.w = row[1] | (row[2] << 16);
-        return d;
-    };
-    desc->clear();
-    desc->reserve((size_t)P);
-    for (int i = 0; i < N; ++i) desc->push_back(make(i, i));
+    auto ij = [](int i, int j) { return (uint32_t)i | ((uint32_t)j << 16); };
+    order->clear();
+    order->reserve((size_t)packed_count(N));
+    for (int i = 0; i < N; ++i) order->push_back(ij(i, i));
     for (int i = 0; i < N; ++i)
         for (int j = i + 1; j < N; ++j)
-            if (colour[i] == colour[j]) desc->push_back(make(i, j));
-    *n_even = (int64_t)desc->size();
+            if (colour[i] == colour[j]) order->push_back(ij(i, j));
+    *n_even = (int64_t)order->size();
     for (int i = 0; i < N; ++i)
         for (int j = i + 1; j < N; ++j)
-            if (colour[i] != colour[j]) desc->push_back(make(i, j));
+            if (colour[i] != colour[j]) order->push_back(ij(i, j));
     return true;
 }
 
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               const uint4** out) {
+                               int elem_bytes, const ResDesc** out) {
     DeviceTables tab;
     ftwa_status st = device_tables(lat, &tab);
     if (st != FTWA_OK) return st;
     if (!tab.bipartite) return fail(FTWA_ENOTSUP, "lattice is not bipartite");
-    const int64_t n_even = tab.n_even, n_odd = (int64_t)lat->host_desc.size() - n_even;
+    const int N = lat->N;
+    const int64_t P = packed_count(N);
+    const std::vector<uint32_t>& order = lat->class_order;
+    const int64_t n_even = tab.n_even, n_odd = (int64_t)order.size() - n_even;
     if (even_slots < n_even || odd_slots < n_odd) return fail(FTWA_EINVAL, "padding too small");
+    if ((P + 2) * (int64_t)elem_bytes >= ((int64_t)1 << 31))
+        return fail(FTWA_EINVAL, "lattice too large for the resident layout");
     int dev = 0;
     FTWA_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(lat->mu);
-    const auto key = std::make_tuple(dev, even_slots, odd_slots);
+    const auto key = std::make_tuple(dev, even_slots, odd_slots, elem_bytes);
     auto it = lat->padded.find(key);
     if (it != lat->padded.end()) {
         *out = it->second;
         return FTWA_OK;
     }
-    const uint32_t P = (uint32_t)packed_count(lat->N);
-    uint4 dummy;
-    dummy.x = P + 1;  // own: scratch slot, i = j = 0
-    dummy.y = P | (P << 16);
-    dummy.z = P | (P << 16);
-    dummy.w = P | (P << 16);
-    std::vector<uint4> tabp((size_t)(even_slots + odd_slots), dummy);
-    std::copy(lat->host_desc.begin(), lat->host_desc.begin() + n_even, tabp.begin());
-    std::copy(lat->host_desc.begin() + n_even, lat->host_desc.end(), tabp.begin() + even_slots);
-    uint4* d = nullptr;
-    FTWA_HIP_TRY(hipMalloc(&d, tabp.size() * sizeof(uint4)));
-    FTWA_HIP_TRY(hipMemcpy(d, tabp.data(), tabp.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    // LDS slot of every packed element
+    std::vector<uint32_t> slot((size_t)P);
+    for (size_t q = 0; q < order.size(); ++q) {
+        const int i = (int)(order[q] & 0xffffu), j = (int)(order[q] >> 16);
+        slot[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)q;
+    }
+    const uint32_t eb = (uint32_t)elem_bytes;
+    const uint32_t zero = (uint32_t)P * eb, scratch = (uint32_t)(P + 1) * eb;
+    // byte offset of element (a, b) as stored; bit 31: read its conjugate
+    auto field = [&](int a, int b) -> uint32_t {
+        if (a <= b) return slot[(size_t)(packed_row(N, a) + (b - a))] * eb;
+        return (slot[(size_t)(packed_row(N, b) + (a - b))] * eb) | 0x80000000u;
+    };
+    auto make = [&](int i, int j) {
+        ResDesc d;
+        uint32_t col[3], row[3];
+        for (int n = 0; n < kMaxDeg; ++n) {
+            const int kc = n < lat->deg[j] ? lat->nbr[(size_t)j * kMaxDeg + n] : -1;
+            const int kr = n < lat->deg[i] ? lat->nbr[(size_t)i * kMaxDeg + n] : -1;
+            col[n] = kc < 0 ? zero : field(i, kc);
+            row[n] = kr < 0 ? zero : field(kr, j);
+        }
+        bool bond = false;
+        for (int n = 0; n < lat->deg[i]; ++n) bond = bond || lat->nbr[(size_t)i * kMaxDeg + n] == j;
+        d.a.x = col[0];
+        d.a.y = col[1];
+        d.a.z = col[2];
+        d.a.w = slot[(size_t)(packed_row(N, i) + (j - i))] * eb | (bond ? 0x80000000u : 0u);
+        d.b.x = row[0];
+        d.b.y = row[1];
+        d.b.z = row[2];
+        d.b.w = ((uint32_t)i * eb) | (((uint32_t)j * eb) << 16);
+        return d;
+    };
+    ResDesc dummy;
+    dummy.a.x = dummy.a.y = dummy.a.z = zero;
+    dummy.a.w = scratch;
+    dummy.b.x = dummy.b.y = dummy.b.z = zero;
+    dummy.b.w = 0;
+    std::vector<ResDesc> tabp((size_t)(even_slots + odd_slots), dummy);
+    for (int64_t q = 0; q < (int64_t)order.size(); ++q) {
+        const int i = (int)(order[q] & 0xffffu), j = (int)(order[q] >> 16);
+        const int64_t at = q < n_even ? q : even_slots + (q - n_even);
+        tabp[(size_t)at] = make(i, j);
+    }
+    ResDesc* d = nullptr;
+    FTWA_HIP_TRY(hipMalloc(&d, tabp.size() * sizeof(ResDesc)));
+    FTWA_HIP_TRY(hipMemcpy(d, tabp.data(), tabp.size() * sizeof(ResDesc), hipMemcpyHostToDevice));
     lat->padded[key] = d;
     *out = d;
     return FTWA_OK;
@@ -395,19 +417,15 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
         for (int j = i; j < N; ++j) elem[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)i | ((uint32_t)j << 16);
     }
     DeviceTables tab;
-    std::vector<uint4> desc;
-    tab.bipartite = build_descriptors(lat, &desc, &tab.n_even);
-    if (tab.bipartite) lat->host_desc = desc;
+    std::vector<uint32_t> order;
+    tab.bipartite = build_class_order(lat, &order, &tab.n_even);
+    if (tab.bipartite) lat->class_order = order;
     FTWA_HIP_TRY(hipMalloc(&tab.nb, nb.size() * sizeof(int32_t)));
     FTWA_HIP_TRY(hipMalloc(&tab.off, off.size() * sizeof(int32_t)));
     FTWA_HIP_TRY(hipMalloc(&tab.elem, elem.size() * sizeof(uint32_t)));
     FTWA_HIP_TRY(hipMemcpy(tab.nb, nb.data(), nb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     FTWA_HIP_TRY(hipMemcpy(tab.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     FTWA_HIP_TRY(hipMemcpy(tab.elem, elem.data(), elem.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    if (tab.bipartite) {
-        FTWA_HIP_TRY(hipMalloc(&tab.desc, desc.size() * sizeof(uint4)));
-        FTWA_HIP_TRY(hipMemcpy(tab.desc, desc.data(), desc.size() * sizeof(uint4), hipMemcpyHostToDevice));
-    }
     lat->dev[dev] = tab;
     *out = tab;
     return FTWA_OK;

@@ -158,6 +158,8 @@ def test_errors_are_reported(ft):
     ("f32", "hex", 5, 0, 3.3, 9, 20, -1),         # 150 sites: spin-split workgroup pairs
     ("f32", "armchair", 10, 20, 3.3, 12, 12, -1),  # 198-site flake, spin split
     ("f32", "armchair", 10, 20, 3.3, 12, 12, 10),  # alternative tile: 1024 threads per spin
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, 11),  # alternative tile: 512 threads per spin
+    ("f32", "hex", 4, 0, 2.0, 10, 20, 9),          # spin split with padding-heavy slots
 ])
 def test_evolve_resident_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, U, M, steps, config):
     import torch
