@@ -150,14 +150,15 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // Right-hand side of one element from its descriptor: Yb is the LDS block of
 // its spin, Yd the block holding the other spin's diagonal at slots 0..N-1.
 // Sums as in the equation of motion: col = (v0 + v1) + v2 over the column
-// neighbours, row likewise, each v conjugated when its flag is set.
-template <typename T>
+// neighbours, row likewise, each v conjugated when its flag is set.  The
+// element's own value is read from LDS, or taken from `own` (OWN_REG).
+template <typename T, bool OWN_REG>
 __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
-                                                 const ResDesc& d, T t, T U) {
+                                                 const ResDesc& d, T t, T U, cplx_t<T> own) {
     using C = cplx_t<T>;
     const C c0 = lds_at<T>(Yb, d.a.x), c1 = lds_at<T>(Yb, d.a.y), c2 = lds_at<T>(Yb, d.a.z);
     const C r0 = lds_at<T>(Yb, d.b.x), r1 = lds_at<T>(Yb, d.b.y), r2 = lds_at<T>(Yb, d.b.z);
-    const C rho = *reinterpret_cast<const C*>(Yb + (d.a.w & 0x7fffffffu));
+    const C rho = OWN_REG ? own : *reinterpret_cast<const C*>(Yb + (d.a.w & 0x7fffffffu));
     const T di = *reinterpret_cast<const T*>(Yd + (d.b.w & 0xffffu));
     const T dj = *reinterpret_cast<const T*>(Yd + (d.b.w >> 16));
     C col, row;
@@ -204,6 +205,13 @@ template <typename T> __device__ __forceinline__ T from_bits(unsigned v);
 template <> __device__ __forceinline__ float from_bits<float>(unsigned v) { return __uint_as_float(v); }
 
 template <int V> using stage_c = std::integral_constant<int, V>;
+
+// Pins a register value at this point of the program: it is computed here
+// (not sunk past a barrier, where it would be live together with the next
+// phase's values).
+template <typename C> __device__ __forceinline__ void pin(C& v) {
+    __asm__ volatile("" : "+v"(v.x), "+v"(v.y));
+}
 
 // Generic pointer to LDS byte address `a` (the kernel's dynamic LDS block
 // starts at address 0).
@@ -263,12 +271,14 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const int N = E.N;
         const int P = E.P;
         const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
-        // LDS: UNITS x S blocks of Pb complex slots; S = 1 adds per unit the
-        // partner's diagonal as N complex values (imaginary parts zero)
+        // LDS: UNITS x S blocks of Pb complex slots; S = 1 adds per unit two
+        // copies of the partner's diagonal as N complex values (imaginary
+        // parts zero)
         // the launch has no static LDS, so the dynamic block starts at LDS
         // address 0 and block offsets are addresses (no base register)
         unsigned char* const Yunit = lds_ptr((uint32_t)((size_t)unit * S * Pb * CB));
-        unsigned char* const dpart = lds_ptr((uint32_t)((size_t)UNITS * S * Pb * CB + (size_t)unit * N * CB));
+        unsigned char* const dpart =
+            lds_ptr((uint32_t)((size_t)UNITS * S * Pb * CB + (size_t)unit * 2 * N * CB));
         // per-wave partial sums of the records and the abort flag follow
         // (placed after the largest blocks of the launch: A.tail_off)
         double (*red)[2 * S] = reinterpret_cast<double (*)[2 * S]>(lds_ptr(A.tail_off));
@@ -306,6 +316,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = v;  // dummies: scratch slot
                 y[s][u] = v;
                 acc[s][u] = v;
+                if (u < UE) hold[s][u] = v;  // S = 1 writes held values in phase 1
             }
             if (t == 0) {
                 C z;
@@ -316,12 +327,16 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             }
         }
         if constexpr (S == 1) {
+            // the partner's diagonal in two alternating copies (stage parity);
+            // the current one from HBM, both imaginary parts zero
             for (int i = t; i < N; i += NTU) {
                 const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
                 C v;
                 v.x = active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
                 v.y = 0;
-                reinterpret_cast<C*>(dpart)[i] = v;
+                reinterpret_cast<C*>(dpart + (size_t)(g & 1) * N * CB)[i] = v;
+                v.x = 0;
+                reinterpret_cast<C*>(dpart + (size_t)((g + 1) & 1) * N * CB)[i] = v;
             }
         }
         // records: the first N even elements are the diagonal (i = position)
@@ -391,9 +406,15 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         auto run_stage = [&](auto stage_tag) -> bool {
             constexpr int STAGE = decltype(stage_tag)::value;
             const T c = STAGE <= 2 ? c_half : (STAGE == 3 ? c_full : c_sixth);
+            // S = 1: the partner's diagonal of this stage's input
+            const unsigned char* dcur = dpart + (size_t)(g & 1) * N * CB;
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
-            // registers); the next slot's descriptor is loaded one slot ahead
+            // registers); the next slot's descriptor is loaded one slot ahead.
+            // S = 1: the held values of the previous stage are written to LDS
+            // here (nothing reads an even element in phase 1: its own value
+            // comes from the register, the diagonal of the U term from the
+            // partner's copy), which saves a barrier per stage.
             ResDesc dn = slot_desc(desc, 0, toff);
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
@@ -401,22 +422,33 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 dn = slot_desc(desc, u + 1 < UE ? NTU * (u + 1) : kEvenPad, toff);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const unsigned char* Yb = Yunit + s * Pb * CB;
-                    const unsigned char* Yd = S == 1 ? dpart : Yunit + (1 - s) * Pb * CB;
-                    const C k = element_rhs<T>(Yb, Yd, d, tw, Uw);
+                    unsigned char* Yb = Yunit + s * Pb * CB;
+                    C k;
+                    if constexpr (S == 1) {
+                        // the stage input of this element: after a full step it
+                        // is y itself, so nothing is held across steps
+                        const C own = STAGE == 1 ? y[s][u] : hold[s][u];
+                        *reinterpret_cast<C*>(Yb + (d.a.w & 0x7fffffffu)) = own;
+                        k = element_rhs<T, true>(Yb, dcur, d, tw, Uw, own);
+                    } else {
+                        k = element_rhs<T, false>(Yb, Yunit + (1 - s) * Pb * CB, d, tw, Uw, hold[s][u]);
+                    }
                     hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
+                    pin(hold[s][u]);
+                    pin(acc[s][u]);
+                    if constexpr (STAGE == 4) pin(y[s][u]);
                 }
-                if (u == 0) {
-            if constexpr (S == 1) {
-                // publish the next-stage diagonal of this spin for the partner:
-                // one 64-bit word per site, (stage number << 32) | value bits,
-                // written with a single relaxed agent-scope atomic store
-                if (t < N) {
-                    uint64_t* slot = mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * A.Nmax;
-                    const uint64_t word = ((uint64_t)(g + 1) << 32) | to_bits<T>(hold[0][0].x);
-                    __hip_atomic_store(slot + t, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
+                if constexpr (S == 1) {
+                    if (u == 0 && t < N) {
+                        // publish the next-stage diagonal for the partner: one
+                        // 64-bit word per site, (stage number << 32) | value bits,
+                        // a single relaxed agent-scope atomic store
+                        uint64_t* slot =
+                            mb + ((size_t)(pair * 2 + spin0) * 2 + ((g + 1) & 1)) * A.Nmax;
+                        const uint64_t word = ((uint64_t)(g + 1) << 32) | to_bits<T>(hold[0][0].x);
+                        __hip_atomic_store(slot + t, word, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
                 // one element per scheduling region: the scheduler may not pull
                 // later slots' loads forward (their registers would not fit)
@@ -431,52 +463,51 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
-                    const unsigned char* Yd = S == 1 ? dpart : Yunit + (1 - s) * Pb * CB;
-                    const C k = element_rhs<T>(Yb, Yd, d, tw, Uw);
+                    const unsigned char* Yd = S == 1 ? dcur : Yunit + (1 - s) * Pb * CB;
+                    const C k = element_rhs<T, false>(Yb, Yd, d, tw, Uw, y[s][u]);
                     *reinterpret_cast<C*>(Yb + (d.a.w & 0x7fffffffu)) =
                         rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
+                    pin(acc[s][u]);
+                    if constexpr (STAGE == 4) pin(y[s][u]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            __syncthreads();
-            desc = launder(desc);
-            // ---------------- held even values (their slot is the class
-            // position t + NTU*u; padding entries write the scratch slot)
-#pragma unroll
-            for (int u = 0; u < UE; ++u) {
-                const uint32_t own = slot_desc(desc, NTU * u, toff).a.w & 0x7fffffffu;
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-                    *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = hold[s][u];
-            }
             if constexpr (S == 1) {
-                if (wave == 0) {
-                    // partner's diagonal for the next stage: poll each word until
-                    // it carries stage g+1 (bounded; two slots alternate by parity,
-                    // so a word is never overwritten before it has been read)
+                // the partner's diagonal of the next stage into the other copy
+                // (not read in this stage): thread i < N polls word i until it
+                // carries stage g+1 (bounded; the two mailbox slots alternate
+                // by parity, so a word is never overwritten before it is read)
+                if (tid < N) {
                     const uint64_t* slot =
                         mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * A.Nmax;
                     const uint32_t want = (uint32_t)(g + 1);
-                    int ok = 1;
-                    for (int i = lane; i < N; i += 64) {
-                        uint64_t w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                        unsigned it = 0;
-                        while ((uint32_t)(w >> 32) != want) {
-                            if (++it >= kSpinLimit) {
-                                ok = 0;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                            w = __hip_atomic_load(slot + i, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
+                    uint64_t w = __hip_atomic_load(slot + tid, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    unsigned it = 0;
+                    while ((uint32_t)(w >> 32) != want) {
+                        if (++it >= kSpinLimit) {
+                            abort_flag = 1;
+                            atomicExch(A.error, 1);
+                            break;
                         }
-                        reinterpret_cast<C*>(dpart)[i].x = from_bits<T>((uint32_t)w);
+                        __builtin_amdgcn_s_sleep(1);
+                        w = __hip_atomic_load(slot + tid, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    if (__any(!ok) && lane == 0) {
-                        abort_flag = 1;
-                        atomicExch(A.error, 1);
-                    }
+                    reinterpret_cast<C*>(dpart + (size_t)((g + 1) & 1) * N * CB)[tid].x =
+                        from_bits<T>((uint32_t)w);
+                }
+            } else {
+                __syncthreads();
+                desc = launder(desc);
+                // ---------------- held even values (slot t + NTU*u; padding
+                // entries write the scratch slot)
+#pragma unroll
+                for (int u = 0; u < UE; ++u) {
+                    const uint32_t own = slot_desc(desc, NTU * u, toff).a.w & 0x7fffffffu;
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = hold[s][u];
                 }
             }
             __syncthreads();
@@ -542,11 +573,12 @@ const Config kConfigs[] = {
 
 constexpr size_t kMaxLds = 160 * 1024;  // the kernel declares no static LDS
 
-// Dynamic LDS of a launch: the state blocks (S = 1 adds the partner's
-// diagonal), then the per-wave record sums and the abort flag.
+// Dynamic LDS of a launch: the state blocks (S = 1 adds two copies of the
+// partner's diagonal), then the per-wave record sums and the abort flag.
 size_t lds_blocks(const Config& c, int N, int P) {
     const size_t cb = c.dtype == FTWA_F64 ? 16 : 8;
-    const size_t b = (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? (size_t)c.UNITS * N * cb : 0);
+    const size_t b =
+        (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? (size_t)c.UNITS * 2 * N * cb : 0);
     return (b + 15) / 16 * 16;
 }
 size_t lds_tail(const Config& c) { return (size_t)(c.NTU * c.UNITS / 64) * 2 * c.S * 8 + 16; }
