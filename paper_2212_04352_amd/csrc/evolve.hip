@@ -272,8 +272,14 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 e.rho = static_cast<char*>(inst[k].rho) + (size_t)m0 * cplx_bytes(p.dtype);
                 e.ldr = inst[k].n_traj;
                 if ((st = padded_descriptors(inst[k].lat, ip.res.even_slots, ip.res.odd_slots,
-                                             (int)cplx_bytes(p.dtype), &e.desc)) != FTWA_OK)
+                                             (int)cplx_bytes(p.dtype),
+                                             resident_spins(g.config) == 1, &e.desc)) != FTWA_OK)
                     return st;
+                DeviceTables tab;
+                if ((st = device_tables(inst[k].lat, &tab)) != FTWA_OK) return st;
+                e.ord = tab.ord;
+                e.nb = tab.nb;
+                e.dpos = tab.dpos;
                 e.t = inst[k].lat->t;
                 e.U = inst[k].U;
                 e.X = reinterpret_cast<double*>(ws + ip.off_x);

@@ -16,7 +16,9 @@
 // elements.  The base point y and the accumulator acc of every element live
 // in the registers of the thread that owns it.  The U term reads the other
 // spin's diagonal from slots 0..N-1 of its block (S = 2) or from a copy of
-// the partner's diagonal next to the block (S = 1).  The kernel declares no
+// the partner's diagonal next to the block (S = 1; N reals ordered by
+// sublattice, so the diagonal values read by a wave's consecutive
+// same-sublattice sites sit in consecutive banks).  The kernel declares no
 // static LDS, so block offsets are LDS addresses.
 //
 // Descriptors.  Each element has a 32-byte descriptor with the LDS byte
@@ -158,9 +160,6 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
     using C = cplx_t<T>;
     const C c0 = lds_at<T>(Yb, d.a.x), c1 = lds_at<T>(Yb, d.a.y), c2 = lds_at<T>(Yb, d.a.z);
     const C r0 = lds_at<T>(Yb, d.b.x), r1 = lds_at<T>(Yb, d.b.y), r2 = lds_at<T>(Yb, d.b.z);
-    const C rho = OWN_REG ? own : *reinterpret_cast<const C*>(Yb + (d.a.w & 0x7fffffffu));
-    const T di = *reinterpret_cast<const T*>(Yd + (d.b.w & 0xffffu));
-    const T dj = *reinterpret_cast<const T*>(Yd + (d.b.w >> 16));
     C col, row;
     col.x = (c0.x + c1.x) + c2.x;
     col.y = fma_rn<T>(conj_sign<T>(d.a.z), c2.y,
@@ -168,6 +167,9 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
     row.x = (r0.x + r1.x) + r2.x;
     row.y = fma_rn<T>(conj_sign<T>(d.b.z), r2.y,
                       fma_rn<T>(conj_sign<T>(d.b.y), r1.y, conj_sign<T>(d.b.x) * r0.y));
+    const C rho = OWN_REG ? own : *reinterpret_cast<const C*>(Yb + d.a.w);
+    const T di = *reinterpret_cast<const T*>(Yd + (d.b.w & 0xffffu));
+    const T dj = *reinterpret_cast<const T*>(Yd + (d.b.w >> 16));
     const T a = U * (di - dj);
     return rhs_element<T>(col, row, rho, t, a);
 }
@@ -224,6 +226,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
+    constexpr int TB = (int)sizeof(T);
     extern __shared__ __align__(16) unsigned char smem[];  // dynamic LDS, at address 0
     (void)smem;
     const int tid0 = threadIdx.x;
@@ -272,13 +275,12 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const int P = E.P;
         const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
         // LDS: UNITS x S blocks of Pb complex slots; S = 1 adds per unit two
-        // copies of the partner's diagonal as N complex values (imaginary
-        // parts zero)
+        // copies of the partner's diagonal (N reals, sublattice-major)
         // the launch has no static LDS, so the dynamic block starts at LDS
         // address 0 and block offsets are addresses (no base register)
         unsigned char* const Yunit = lds_ptr((uint32_t)((size_t)unit * S * Pb * CB));
         unsigned char* const dpart =
-            lds_ptr((uint32_t)((size_t)UNITS * S * Pb * CB + (size_t)unit * 2 * N * CB));
+            lds_ptr((uint32_t)((size_t)UNITS * S * Pb * CB + (size_t)unit * 2 * N * TB));
         // per-wave partial sums of the records and the abort flag follow
         // (placed after the largest blocks of the launch: A.tail_off)
         double (*red)[2 * S] = reinterpret_cast<double (*)[2 * S]>(lds_ptr(A.tail_off));
@@ -293,10 +295,14 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         gdesc_t desc = (gdesc_t)uniform64((uint64_t)E.desc);
         __syncthreads();  // the previous item is done with LDS and `red`
 
-        // packed index of the element a descriptor describes (i, j from the
-        // diagonal offsets), for the state in HBM
+        // packed index of the element a descriptor describes (its LDS slot
+        // through the class-order table), for the state in HBM
+        const uint32_t* const ord = reinterpret_cast<const uint32_t*>(uniform64((uint64_t)E.ord));
+        const int32_t* const nbt = reinterpret_cast<const int32_t*>(uniform64((uint64_t)E.nb));
+
         auto packed_of = [&](const ResDesc& d) -> int64_t {
-            const int i = (int)((d.b.w & 0xffffu) / CB), j = (int)((d.b.w >> 16) / CB);
+            const uint32_t ij = ord[d.a.w / CB];
+            const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
             return (int64_t)i * N - (int64_t)i * (i - 1) / 2 + (j - i);
         };
         // ---- load the trajectory into registers and LDS
@@ -307,7 +313,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             for (int u = 0; u < UE + UO; ++u) {
                 const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
                 const ResDesc d = load_desc(desc + e);
-                const uint32_t own = d.a.w & 0x7fffffffu;
+                const uint32_t own = d.a.w;
                 C v;
                 v.x = 0;
                 v.y = 0;
@@ -326,17 +332,17 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 reinterpret_cast<C*>(Yunit + s * Pb * CB)[P + 1] = z;
             }
         }
+        const int32_t* const dpos = reinterpret_cast<const int32_t*>(uniform64((uint64_t)E.dpos));
+        const int qdiag = (S == 1 && tid < N) ? dpos[tid] : 0;  // this thread's polled site
         if constexpr (S == 1) {
-            // the partner's diagonal in two alternating copies (stage parity);
-            // the current one from HBM, both imaginary parts zero
+            // the partner's diagonal in two alternating copies (stage parity),
+            // reals in sublattice-major order; the current one from HBM
             for (int i = t; i < N; i += NTU) {
                 const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
-                C v;
-                v.x = active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
-                v.y = 0;
-                reinterpret_cast<C*>(dpart + (size_t)(g & 1) * N * CB)[i] = v;
-                v.x = 0;
-                reinterpret_cast<C*>(dpart + (size_t)((g + 1) & 1) * N * CB)[i] = v;
+                const int q = dpos[i];
+                reinterpret_cast<T*>(dpart + (size_t)(g & 1) * N * TB)[q] =
+                    active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
+                reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * N * TB)[q] = (T)0;
             }
         }
         // records: the first N even elements are the diagonal (i = position)
@@ -359,11 +365,17 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
                     for (int u = 0; u < UE + UO; ++u) {
                         const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                        const uint32_t dw = desc[e].a.w;
+                        const uint32_t own = desc[e].a.w;
                         const double re = (double)y[s][u].x, im = (double)y[s][u].y;
                         const bool diag = u < UE && e < N;
                         frob[s] += diag ? re * re : 2.0 * (re * re + im * im);
-                        if (dw & 0x80000000u) hop[s] += 2.0 * re;
+                        if (own < (uint32_t)P * CB) {  // bond: j a neighbour of i
+                            const uint32_t ij = ord[own / CB];
+                            const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
+                            bool bond = false;
+                            for (int n = 0; n < 3; ++n) bond = bond || nbt[i * 4 + n] == j;
+                            if (bond) hop[s] += 2.0 * re;
+                        }
                     }
                     for (int off = 32; off > 0; off /= 2) {
                         hop[s] += __shfl_xor(hop[s], off, 64);
@@ -407,7 +419,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             constexpr int STAGE = decltype(stage_tag)::value;
             const T c = STAGE <= 2 ? c_half : (STAGE == 3 ? c_full : c_sixth);
             // S = 1: the partner's diagonal of this stage's input
-            const unsigned char* dcur = dpart + (size_t)(g & 1) * N * CB;
+            const unsigned char* dcur = dpart + (size_t)(g & 1) * N * TB;
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
             // registers); the next slot's descriptor is loaded one slot ahead.
@@ -428,10 +440,11 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         // the stage input of this element: after a full step it
                         // is y itself, so nothing is held across steps
                         const C own = STAGE == 1 ? y[s][u] : hold[s][u];
-                        *reinterpret_cast<C*>(Yb + (d.a.w & 0x7fffffffu)) = own;
+                        *reinterpret_cast<C*>(Yb + d.a.w) = own;
                         k = element_rhs<T, true>(Yb, dcur, d, tw, Uw, own);
                     } else {
-                        k = element_rhs<T, false>(Yb, Yunit + (1 - s) * Pb * CB, d, tw, Uw, hold[s][u]);
+                        k = element_rhs<T, false>(Yb, Yunit + (1 - s) * Pb * CB, d, tw, Uw,
+                                                  hold[s][u]);
                     }
                     hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(hold[s][u]);
@@ -465,8 +478,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
                     const unsigned char* Yd = S == 1 ? dcur : Yunit + (1 - s) * Pb * CB;
                     const C k = element_rhs<T, false>(Yb, Yd, d, tw, Uw, y[s][u]);
-                    *reinterpret_cast<C*>(Yb + (d.a.w & 0x7fffffffu)) =
-                        rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
+                    *reinterpret_cast<C*>(Yb + d.a.w) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
                 }
@@ -478,6 +490,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 // carries stage g+1 (bounded; the two mailbox slots alternate
                 // by parity, so a word is never overwritten before it is read)
                 if (tid < N) {
+                    const int q = qdiag;
                     const uint64_t* slot =
                         mb + ((size_t)(pair * 2 + (1 - spin0)) * 2 + ((g + 1) & 1)) * A.Nmax;
                     const uint32_t want = (uint32_t)(g + 1);
@@ -494,7 +507,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         w = __hip_atomic_load(slot + tid, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    reinterpret_cast<C*>(dpart + (size_t)((g + 1) & 1) * N * CB)[tid].x =
+                    reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * N * TB)[q] =
                         from_bits<T>((uint32_t)w);
                 }
             } else {
@@ -504,7 +517,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 // entries write the scratch slot)
 #pragma unroll
                 for (int u = 0; u < UE; ++u) {
-                    const uint32_t own = slot_desc(desc, NTU * u, toff).a.w & 0x7fffffffu;
+                    const uint32_t own = slot_desc(desc, NTU * u, toff).a.w;
 #pragma unroll
                     for (int s = 0; s < S; ++s)
                         *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = hold[s][u];
@@ -537,7 +550,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 for (int u = 0; u < UE + UO; ++u) {
                     const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
                     const ResDesc d = load_desc(desc + e);
-                    if ((d.a.w & 0x7fffffffu) < (uint32_t)P * CB)
+                    if (d.a.w < (uint32_t)P * CB)
                         rho_out[((int64_t)gs * P + packed_of(d)) * ldr + m] = y[s][u];
                 }
             }
@@ -574,11 +587,12 @@ const Config kConfigs[] = {
 constexpr size_t kMaxLds = 160 * 1024;  // the kernel declares no static LDS
 
 // Dynamic LDS of a launch: the state blocks (S = 1 adds two copies of the
-// partner's diagonal), then the per-wave record sums and the abort flag.
+// partner's diagonal, N reals each), then the per-wave record sums and the
+// abort flag.
 size_t lds_blocks(const Config& c, int N, int P) {
     const size_t cb = c.dtype == FTWA_F64 ? 16 : 8;
     const size_t b =
-        (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? (size_t)c.UNITS * 2 * N * cb : 0);
+        (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? (size_t)c.UNITS * 2 * N * (cb / 2) : 0);
     return (b + 15) / 16 * 16;
 }
 size_t lds_tail(const Config& c) { return (size_t)(c.NTU * c.UNITS / 64) * 2 * c.S * 8 + 16; }

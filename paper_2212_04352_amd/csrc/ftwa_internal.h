@@ -24,6 +24,10 @@ struct DeviceTables {
     uint32_t* elem = nullptr;  // [P]: packed element p -> i | j << 16
     int64_t n_even = 0;        // size of the even class (i, j on the same sublattice)
     bool bipartite = false;
+    uint32_t* ord = nullptr;   // [P]: LDS slot (class order) -> i | j << 16
+    int32_t* dpos = nullptr;   // [N]: site -> its position in the sublattice-major
+                               // diagonal (the sites of one sublattice, ascending,
+                               // then the other's)
 };
 
 // Stencil descriptor of one element for the resident kernel (32 bytes), all
@@ -33,10 +37,13 @@ struct DeviceTables {
 //     each = offset of the stored element | bit 31 set when the stored
 //     element is rho_ki (read its conjugate); a missing neighbour reads the
 //     zero slot P;
-//   a.w: offset of the element itself | bit 31 set when j is a neighbour of i
-//     (padding entries own the scratch slot P+1);
-//   b.w: offset of the diagonal (i,i) | offset of (j,j) << 16 (diagonal
-//     elements come first in the block, element i at slot i).
+//   a.w: offset of the element itself (padding entries own the scratch slot
+//     P+1);
+//   b.w: offset of the diagonal value of site i | that of site j << 16: the
+//     values are
+//     the other spin's block (diagonal first, element (i,i) at slot i) or,
+//     for the spin-split kernels, in a compact real array in sublattice-major
+//     order (consecutive same-sublattice sites at consecutive words).
 struct ResDesc {
     uint4 a, b;
 };
@@ -53,9 +60,10 @@ struct ftwa_lattice_s {
     std::mutex mu;
     std::map<int, ftwa::DeviceTables> dev;  // by HIP device ordinal
     // resident-path descriptors padded per class to whole slots, by
-    // (device, even slots, odd slots, element bytes)
+    // (device, even slots, odd slots, element bytes and diagonal layout)
     std::map<std::tuple<int, int64_t, int64_t, int>, ftwa::ResDesc*> padded;
     std::vector<uint32_t> class_order;      // i | j << 16 of the elements in LDS-slot order
+    std::vector<int32_t> diag_pos;          // site -> sublattice-major diagonal position
 };
 
 namespace ftwa {
@@ -90,10 +98,11 @@ ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_mom
 ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
 // Descriptor table in LDS-slot order with the even class padded to
 // even_slots entries and the odd class to odd_slots entries; padding entries
-// own the scratch slot P+1 and read only the zero slot P (uploaded once per
-// shape and element size).
+// own the scratch slot P+1 and read only the zero slot P.  compact_diag
+// selects the sublattice-major real diagonal array of the spin-split kernels.
+// Uploaded once per shape, element size and diagonal layout.
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               int elem_bytes, const ResDesc** out);
+                               int elem_bytes, bool compact_diag, const ResDesc** out);
 
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
@@ -160,7 +169,10 @@ struct ResidentInst {
     int64_t Mc;          // trajectories in the window (the record width)
     void* rho;           // instance state offset to the window's first trajectory
     int64_t ldr;         // instance n_traj
-    const ResDesc* desc; // padded_descriptors(lat, plan.even_slots, plan.odd_slots, bytes)
+    const ResDesc* desc; // padded_descriptors(lat, plan.even_slots, plan.odd_slots, bytes, S == 1)
+    const uint32_t* ord; // DeviceTables::ord
+    const int32_t* nb;   // DeviceTables::nb
+    const int32_t* dpos; // DeviceTables::dpos
     double t, U;
     double* X;           // [n_rec][2N][Mc]
     double* inv_parts;   // NULL or [n_rec][2 spins][hop, frob][Mc]

@@ -240,6 +240,8 @@ void ftwa_free_lattice(ftwa_lattice lat) {
         (void)hipFree(tab.nb);
         (void)hipFree(tab.off);
         (void)hipFree(tab.elem);
+        if (tab.ord) (void)hipFree(tab.ord);
+        if (tab.dpos) (void)hipFree(tab.dpos);
     }
     for (auto& [key, ptr] : lat->padded) {
         if (hipSetDevice(std::get<0>(key)) != hipSuccess) continue;
@@ -291,7 +293,8 @@ namespace ftwa {
 // (i and j on the same sublattice; the diagonal first, then row-major), then
 // the odd class (row-major).  An element's position in this order is its
 // slot in the kernel's LDS block.  Returns false for a non-bipartite graph.
-bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* n_even) {
+bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* n_even,
+                       std::vector<int32_t>* diag_pos) {
     const int N = lat->N;
     std::vector<int> colour(N, -1);
     for (int root = 0; root < N; ++root) {
@@ -308,6 +311,11 @@ bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* 
             }
         }
     }
+    diag_pos->assign(N, 0);
+    int next = 0;
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < N; ++i)
+            if (colour[i] == c) (*diag_pos)[i] = next++;
     auto ij = [](int i, int j) { return (uint32_t)i | ((uint32_t)j << 16); };
     order->clear();
     order->reserve((size_t)packed_count(N));
@@ -323,7 +331,7 @@ bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* 
 }
 
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               int elem_bytes, const ResDesc** out) {
+                               int elem_bytes, bool compact_diag, const ResDesc** out) {
     DeviceTables tab;
     ftwa_status st = device_tables(lat, &tab);
     if (st != FTWA_OK) return st;
@@ -338,7 +346,8 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
     int dev = 0;
     FTWA_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(lat->mu);
-    const auto key = std::make_tuple(dev, even_slots, odd_slots, elem_bytes);
+    const auto key =
+        std::make_tuple(dev, even_slots, odd_slots, elem_bytes * 2 + (compact_diag ? 1 : 0));
     auto it = lat->padded.find(key);
     if (it != lat->padded.end()) {
         *out = it->second;
@@ -366,16 +375,19 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
             col[n] = kc < 0 ? zero : field(i, kc);
             row[n] = kr < 0 ? zero : field(kr, j);
         }
-        bool bond = false;
-        for (int n = 0; n < lat->deg[i]; ++n) bond = bond || lat->nbr[(size_t)i * kMaxDeg + n] == j;
         d.a.x = col[0];
         d.a.y = col[1];
         d.a.z = col[2];
-        d.a.w = slot[(size_t)(packed_row(N, i) + (j - i))] * eb | (bond ? 0x80000000u : 0u);
+        d.a.w = slot[(size_t)(packed_row(N, i) + (j - i))] * eb;
         d.b.x = row[0];
         d.b.y = row[1];
         d.b.z = row[2];
-        d.b.w = ((uint32_t)i * eb) | (((uint32_t)j * eb) << 16);
+        if (compact_diag) {
+            const uint32_t rb = eb / 2;  // one real
+            d.b.w = ((uint32_t)lat->diag_pos[i] * rb) | (((uint32_t)lat->diag_pos[j] * rb) << 16);
+        } else {
+            d.b.w = ((uint32_t)i * eb) | (((uint32_t)j * eb) << 16);
+        }
         return d;
     };
     ResDesc dummy;
@@ -418,8 +430,18 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
     }
     DeviceTables tab;
     std::vector<uint32_t> order;
-    tab.bipartite = build_class_order(lat, &order, &tab.n_even);
-    if (tab.bipartite) lat->class_order = order;
+    std::vector<int32_t> dpos;
+    tab.bipartite = build_class_order(lat, &order, &tab.n_even, &dpos);
+    if (tab.bipartite) {
+        lat->class_order = order;
+        lat->diag_pos = dpos;
+        FTWA_HIP_TRY(hipMalloc(&tab.ord, order.size() * sizeof(uint32_t)));
+        FTWA_HIP_TRY(hipMemcpy(tab.ord, order.data(), order.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice));
+        FTWA_HIP_TRY(hipMalloc(&tab.dpos, dpos.size() * sizeof(int32_t)));
+        FTWA_HIP_TRY(hipMemcpy(tab.dpos, dpos.data(), dpos.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice));
+    }
     FTWA_HIP_TRY(hipMalloc(&tab.nb, nb.size() * sizeof(int32_t)));
     FTWA_HIP_TRY(hipMalloc(&tab.off, off.size() * sizeof(int32_t)));
     FTWA_HIP_TRY(hipMalloc(&tab.elem, elem.size() * sizeof(uint32_t)));
