@@ -52,22 +52,37 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-traj", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=800)
+    ap.add_argument("--workload", default="flake198",
+                    choices=["flake198", "batch", "adjoint", "sizes"],
+                    help="flake198: the headline metric (default); batch: the 64-instance mixed "
+                         "batch as one graph launch; adjoint: the 54-site gradient workload; "
+                         "sizes: resident throughput per lattice size")
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-traj", type=int, default=2048)
+    ap.add_argument("--sequential", action="store_true",
+                    help="batch: also time one ftwa_evolve per instance")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a "
                          "known-size reference dispatch for HBM byte counters)")
     return ap.parse_args()
 
 
-def kernel_source_hash() -> str:
+KERNEL_SOURCES = {"rk4_resident": ("evolve_resident.hip", "device_common.h", "ftwa_internal.h"),
+                  "rk4_stage_stream": ("evolve_stream.hip", "device_common.h", "ftwa_internal.h")}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the source files that define a kernel (its code and argument
+    layouts): counters taken on other sources are not reported."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2212_04352_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float):
+def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float, config=None):
     """HBM bytes per launch of this run from committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (calibrated against a plain copy of known size, scaled from
     the counter run's trajectory-steps to this launch's), if the counters were
@@ -78,7 +93,9 @@ def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float):
     with open(path) as fh:
         data = json.load(fh)
     rec = data.get(f"{kernel}:{dtype}")
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    if config is not None and rec.get("kernel_config") not in (None, config):
         return None
     return rec["bytes_per_traj_step"] * traj_steps_per_launch
 
@@ -131,6 +148,139 @@ def cpu_baseline(W, n_traj, n_steps):
                       f"FP64, {dt:.1f} s"}
 
 
+def run_batch(args):
+    """The mixed batch: 64 instances (hex flakes of 24/54/96/150 sites and the
+    198-site flake, U/t on [0, 4], random Fock starts), FP32, integrated by one
+    graph launch of the persistent per-configuration kernels."""
+    import torch
+    import paper_2212_04352_amd as ft
+    from workloads import BATCH_SEED, batch_instances
+    specs = batch_instances(n_traj=args.batch_traj)
+    lats = {}
+    probs = []
+    for d in specs:
+        key = (d["kind"], d["a"], d["b"])
+        if key not in lats:
+            lats[key] = ft.Lattice(*key)
+        lat = lats[key]
+        p = ft.Problem.allocate(lat, d["U"], d["n_traj"],
+                                lat.fock_start("random", BATCH_SEED, d["instance"]), "f32",
+                                instance=d["instance"])
+        ft.sample(p, BATCH_SEED)
+        probs.append(p)
+    steps = args.batch_steps
+    cfgs = ft.autotune(probs, probe_steps=10)
+    log(f"batch: {len(probs)} instances, autotuned configurations {sorted(set(cfgs))}")
+    work = sum(p.n_traj for p in probs) * steps
+    g = ft.EvolveGraph(probs, 0.01, steps, 10)
+    log("batch: graph captured; warm-up launch")
+    g.launch()
+    g.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.launch()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    g.check()
+    out = {"metric": "trajectory*RK4-steps/s, mixed 64-instance batch, one graph launch",
+           "value": work / el, "unit": "trajectory*RK4-steps/s", "seconds_per_launch": el,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch64", "instances": len(probs),
+                      "trajectories_per_instance": args.batch_traj, "rk4_steps": steps,
+                      "dt": 0.01, "record_every": 10,
+                      "sites": sorted(set(p.lat.N for p in probs)),
+                      "configurations": sorted(set(cfgs))}}
+    g.close()
+    if args.sequential:
+        for p in probs:
+            ft.sample(p, BATCH_SEED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in probs:
+            ft.evolve(p, 0.01, steps, 10)
+        torch.cuda.synchronize()
+        es = time.perf_counter() - t0
+        out["sequential"] = {"value": work / es, "seconds": es,
+                             "note": "one ftwa_evolve per instance"}
+    print(json.dumps(out))
+
+
+def run_adjoint(args):
+    """The gradient workload: 54-site torus, 4096 trajectories, FP32, 2000
+    steps with checkpoints every 50; loss = sum (nbar(t_r) - target)^2 with the
+    target from the forward pass at U/t = 3.3, gradient at U/t = 2.5."""
+    import torch
+    import paper_2212_04352_amd as ft
+    from workloads import ADJOINT_54 as W
+    from paper_2212_04352_amd.autodiff import OccupationSpec, occupations
+    lat = ft.Lattice(W.kind, W.a, W.b, W.t_hop)
+    steps = args.horizon_steps or W.n_steps
+    spec = OccupationSpec(W.kind, W.a, W.b, lat.fock_start(W.start, W.seed), seed=W.seed,
+                          n_traj=W.n_traj, dt=W.dt, n_steps=steps,
+                          record_every=W.record_every, dtype="f32", ckpt_every=50)
+    f64 = torch.float64
+    dev = torch.device("cuda")
+    zero = torch.zeros((2, lat.N), dtype=f64, device=dev)
+    with torch.no_grad():
+        target = occupations(torch.tensor(3.3, dtype=f64), torch.tensor(W.t_hop, dtype=f64),
+                             zero, spec)
+    U = torch.tensor(W.U, dtype=f64, requires_grad=True)
+    t = torch.tensor(W.t_hop, dtype=f64, requires_grad=True)
+    delta = torch.zeros(lat.N, dtype=f64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nbar = occupations(U, t, delta.expand(2, lat.N), spec)
+    loss = torch.sum((nbar - target) ** 2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gU, gt, gd = torch.autograd.grad(loss, (U, t, delta))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    work = W.n_traj * steps
+    print(json.dumps({
+        "metric": "adjoint gradient, 54-site torus",
+        "forward_seconds": t1 - t0, "backward_seconds": t2 - t1,
+        "backward_over_forward": (t2 - t1) / (t1 - t0),
+        "forward_value": work / (t1 - t0), "backward_value": work / (t2 - t1),
+        "unit": "trajectory*RK4-steps/s", "dtype": "f32 state, f64 gradient sums",
+        "loss": float(loss.detach()), "dL_dU": float(gU), "dL_dt": float(gt),
+        "dL_ddelta_norm": float(gd.norm()),
+        "config": {"workload": W.name, "trajectories": W.n_traj, "rk4_steps": steps,
+                   "dt": W.dt, "ckpt_every": 50, "U_eval": W.U, "U_target": 3.3}}))
+
+
+def run_sizes(args):
+    """Resident-kernel throughput per lattice size (FP32 and FP64), autotuned."""
+    import torch
+    import paper_2212_04352_amd as ft
+    rows = []
+    for kind, a, b in [("torus", 2, 3), ("torus", 3, 9), ("hex", 4, 0), ("hex", 5, 0),
+                       ("armchair", 10, 20)]:
+        lat = ft.Lattice(kind, a, b)
+        for dtype in ("f32", "f64"):
+            M = 16384 if lat.N <= 54 else 8192
+            steps = 400
+            p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
+            ft.sample(p, 7)
+            cfg = ft.autotune(p, probe_steps=10)[0]
+            ft.evolve(p, 0.005, 20, 10)
+            timing = ft.new_timing()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ft.evolve(p, 0.005, steps, 10, timing=timing)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rows.append({"lattice": f"{kind} {a}x{b}", "N": lat.N, "dtype": dtype,
+                         "configuration": cfg, "trajectories": M, "rk4_steps": steps,
+                         "value": M * steps / el,
+                         "kernel_value": timing["work"].value / (timing["ms"].value * 1e-3)})
+            log(f"{kind} N={lat.N} {dtype}: config {cfg}, {M * steps / el:.3e} traj-steps/s")
+            del p
+    print(json.dumps({"metric": "trajectory*RK4-steps/s by lattice size (autotuned path)",
+                      "unit": "trajectory*RK4-steps/s", "rows": rows}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -139,6 +289,14 @@ def main():
     import torch
     import paper_2212_04352_amd as ft
     from workloads import FLAKE_198 as W
+
+    torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "adjoint":
+        return run_adjoint(args)
+    if args.workload == "sizes":
+        return run_sizes(args)
 
     torch.cuda.set_device(0)
     if args.copy_calibration_mib > 0:
@@ -161,7 +319,7 @@ def main():
     if args.config < 0 and not args.no_autotune and args.path == "auto":
         probe = ft.Problem.allocate(lat, W.U, min(M, 2048), n0, "f32")
         ft.sample(probe, W.seed)
-        tuned = ft.autotune(probe, probe_steps=20)[0]
+        tuned = ft.autotune(probe, probe_steps=200)[0]
         del probe
         log(f"autotuned configuration for N={N} f32: {tuned} (-1 = stream path)")
     if args.config >= 0:
@@ -197,7 +355,8 @@ def main():
     work_per_launch = work / max(launches, 1)
     achieved = bytes_per_ts_f32 * work_per_launch / (avg_ms * 1e-3) / 1e9
     kernel_name = "rk4_resident" if path32 == "resident" else "rk4_stage_stream"
-    traffic = counter_traffic(kernel_name, "f32", work_per_launch)
+    run_config = args.config if args.config >= 0 else tuned
+    traffic = counter_traffic(kernel_name, "f32", work_per_launch, run_config)
     result = {
         "metric": "trajectory*RK4-steps/s at N=198, FP32 vs FP64 plain, at stated obs. error",
         "value": value,
@@ -214,7 +373,7 @@ def main():
         "config": {"workload": W.name, "lattice": "armchair 10x20 trimmed, N=198", "U": W.U,
                    "trajectories": M, "dt": W.dt, "rk4_steps": n_steps,
                    "record_every": W.record_every, "moments": "f64", "path": path32,
-                   "kernel_config": args.config if args.config >= 0 else tuned},
+                   "kernel_config": run_config},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "kernel_avg_ms": avg_ms,
