@@ -84,18 +84,17 @@ def kernel_source_hash(kernel: str) -> str:
 
 def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float, config=None):
     """HBM bytes per launch of this run from committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (calibrated against a plain copy of known size, scaled from
-    the counter run's trajectory-steps to this launch's), if the counters were
-    taken on the current kernel sources; else None."""
+    WRITE_SIZE runs of the same kernel configuration (calibrated against a plain
+    copy of known size, scaled from the counter run's trajectory-steps to this
+    launch's), if the counters were taken on the current kernel sources; else
+    None."""
     path = os.path.join(ROOT, "profiles", "hbm_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         data = json.load(fh)
-    rec = data.get(f"{kernel}:{dtype}")
+    rec = data.get(f"{kernel}:{dtype}:{config}")
     if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
-        return None
-    if config is not None and rec.get("kernel_config") not in (None, config):
         return None
     return rec["bytes_per_traj_step"] * traj_steps_per_launch
 
