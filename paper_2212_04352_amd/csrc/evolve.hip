@@ -114,7 +114,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         bool tuned_stream = false;
         if (cfg < 0 && want == FTWA_PATH_AUTO) {
             int c = -1;
-            if (tuned_config(N, tab.n_even, dtype, &c)) {
+            if (tuned_config(N, class_shape(tab), dtype, &c)) {
                 if (c < 0) tuned_stream = true;
                 cfg = c;
             }
@@ -459,17 +459,17 @@ int current_device() {
 
 }  // namespace
 
-bool tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int* config) {
+bool tuned_config(int N, int64_t shape, ftwa_dtype dtype, int* config) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tuned.find(std::make_tuple(current_device(), N, n_even, (int)dtype));
+    auto it = g_tuned.find(std::make_tuple(current_device(), N, shape, (int)dtype));
     if (it == g_tuned.end()) return false;
     *config = it->second;
     return true;
 }
 
-void set_tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int config) {
+void set_tuned_config(int N, int64_t shape, ftwa_dtype dtype, int config) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tuned[std::make_tuple(current_device(), N, n_even, (int)dtype)] = config;
+    g_tuned[std::make_tuple(current_device(), N, shape, (int)dtype)] = config;
 }
 
 }  // namespace ftwa
@@ -708,7 +708,7 @@ ftwa_status ftwa_autotune(const ftwa_instance* inst, int n_inst, ftwa_dtype dtyp
         DeviceTables tab;
         if ((st = device_tables(in.lat, &tab)) != FTWA_OK) return done(st);
         const int N = in.lat->N;
-        const auto key = std::make_pair(N, tab.n_even);
+        const auto key = std::make_pair(N, class_shape(tab));
         auto it = decided.find(key);
         if (it != decided.end()) {
             if (configs) configs[k] = it->second;
@@ -750,7 +750,7 @@ ftwa_status ftwa_autotune(const ftwa_instance* inst, int n_inst, ftwa_dtype dtyp
                 best = c;
             }
         }
-        set_tuned_config(N, tab.n_even, dtype, best);
+        set_tuned_config(N, class_shape(tab), dtype, best);
         decided[key] = best;
         if (configs) configs[k] = best;
     }

@@ -23,10 +23,13 @@
 //
 // Descriptors.  Each element has a 32-byte descriptor with the LDS byte
 // offsets of its six neighbour elements and of itself, and of the two
-// diagonal values; a neighbour stored as its transpose carries a flag, and
-// its imaginary part enters the sums with the factor -1 (fma(+-1, v, s)
-// rounds exactly like s +- v), so the arithmetic is that of the equation of
-// motion in a fixed order.  Consecutive threads own consecutive slots, so
+// diagonal values.  The LDS stores one orientation of every pair (chosen by
+// a bandwidth-reducing site ranking); a neighbour stored as its transpose
+// carries a flag, and its imaginary part enters the sums with the factor -1
+// (fma(+-1, v, s) rounds exactly like s +- v), so the arithmetic is that of
+// the equation of motion in a fixed order.  The few elements with such
+// neighbours come first in their class and fill the leading GE even and GO
+// odd slots; all other slots are compiled without the flag handling.  Consecutive threads own consecutive slots, so
 // own reads and writes of a wave are contiguous; neighbours of consecutive
 // same-class elements of a row are mostly consecutive slots of the other
 // class.
@@ -152,26 +155,51 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // Right-hand side of one element from its descriptor: Yb is the LDS block of
 // its spin, Yd the block holding the other spin's diagonal at slots 0..N-1.
 // Sums as in the equation of motion: col = (v0 + v1) + v2 over the column
-// neighbours, row likewise, each v conjugated when its flag is set.  The
-// element's own value is read from LDS, or taken from `own` (OWN_REG).
-template <typename T, bool OWN_REG>
+// neighbours, row likewise.  GEN: a neighbour may be stored as its transpose
+// (flag in bit 31 of its offset; its imaginary part enters with the factor
+// -1); otherwise no offset carries a flag and the sums are plain (fma(1, v, s)
+// and s + v round alike, so both forms give the same bits).  The element's
+// own value is read from LDS, or taken from `own` (OWN_REG).
+template <typename T, bool OWN_REG, bool GEN>
 __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
                                                  const ResDesc& d, T t, T U, cplx_t<T> own) {
     using C = cplx_t<T>;
-    const C c0 = lds_at<T>(Yb, d.a.x), c1 = lds_at<T>(Yb, d.a.y), c2 = lds_at<T>(Yb, d.a.z);
-    const C r0 = lds_at<T>(Yb, d.b.x), r1 = lds_at<T>(Yb, d.b.y), r2 = lds_at<T>(Yb, d.b.z);
     C col, row;
-    col.x = (c0.x + c1.x) + c2.x;
-    col.y = fma_rn<T>(conj_sign<T>(d.a.z), c2.y,
-                      fma_rn<T>(conj_sign<T>(d.a.y), c1.y, conj_sign<T>(d.a.x) * c0.y));
-    row.x = (r0.x + r1.x) + r2.x;
-    row.y = fma_rn<T>(conj_sign<T>(d.b.z), r2.y,
-                      fma_rn<T>(conj_sign<T>(d.b.y), r1.y, conj_sign<T>(d.b.x) * r0.y));
+    if constexpr (GEN) {
+        const C c0 = lds_at<T>(Yb, d.a.x), c1 = lds_at<T>(Yb, d.a.y), c2 = lds_at<T>(Yb, d.a.z);
+        const C r0 = lds_at<T>(Yb, d.b.x), r1 = lds_at<T>(Yb, d.b.y), r2 = lds_at<T>(Yb, d.b.z);
+        col.x = (c0.x + c1.x) + c2.x;
+        col.y = fma_rn<T>(conj_sign<T>(d.a.z), c2.y,
+                          fma_rn<T>(conj_sign<T>(d.a.y), c1.y, conj_sign<T>(d.a.x) * c0.y));
+        row.x = (r0.x + r1.x) + r2.x;
+        row.y = fma_rn<T>(conj_sign<T>(d.b.z), r2.y,
+                          fma_rn<T>(conj_sign<T>(d.b.y), r1.y, conj_sign<T>(d.b.x) * r0.y));
+    } else {
+        const C c0 = *reinterpret_cast<const C*>(Yb + d.a.x);
+        const C c1 = *reinterpret_cast<const C*>(Yb + d.a.y);
+        const C c2 = *reinterpret_cast<const C*>(Yb + d.a.z);
+        const C r0 = *reinterpret_cast<const C*>(Yb + d.b.x);
+        const C r1 = *reinterpret_cast<const C*>(Yb + d.b.y);
+        const C r2 = *reinterpret_cast<const C*>(Yb + d.b.z);
+        col.x = (c0.x + c1.x) + c2.x;
+        col.y = (c0.y + c1.y) + c2.y;
+        row.x = (r0.x + r1.x) + r2.x;
+        row.y = (r0.y + r1.y) + r2.y;
+    }
     const C rho = OWN_REG ? own : *reinterpret_cast<const C*>(Yb + d.a.w);
     const T di = *reinterpret_cast<const T*>(Yd + (d.b.w & 0xffffu));
     const T dj = *reinterpret_cast<const T*>(Yd + (d.b.w >> 16));
     const T a = U * (di - dj);
     return rhs_element<T>(col, row, rho, t, a);
+}
+
+// The same with the variant chosen by a (compile-time) slot condition.
+template <typename T, bool OWN_REG>
+__device__ __forceinline__ cplx_t<T> element_rhs_sel(bool gen, const unsigned char* Yb,
+                                                     const unsigned char* Yd, const ResDesc& d,
+                                                     T t, T U, cplx_t<T> own) {
+    return gen ? element_rhs<T, OWN_REG, true>(Yb, Yd, d, t, U, own)
+               : element_rhs<T, OWN_REG, false>(Yb, Yd, d, t, U, own);
 }
 
 // One Runge-Kutta stage update of an element from its slope k:
@@ -221,7 +249,7 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
     return (unsigned char*)(__attribute__((address_space(3))) unsigned char*)(uintptr_t)a;
 }
 
-template <typename T, int S, int NTU, int UNITS, int UE, int UO>
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
 __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     constexpr int kEvenPad = NTU * UE;
@@ -300,9 +328,13 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const uint32_t* const ord = reinterpret_cast<const uint32_t*>(uniform64((uint64_t)E.ord));
         const int32_t* const nbt = reinterpret_cast<const int32_t*>(uniform64((uint64_t)E.nb));
 
-        auto packed_of = [&](const ResDesc& d) -> int64_t {
-            const uint32_t ij = ord[d.a.w / CB];
-            const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
+        // (the LDS holds rho_ab; rho_ba when b < a is the packed element, so
+        // it is conjugated on the way in and out)
+        auto packed_of = [&](const ResDesc& d, bool& transposed) -> int64_t {
+            const uint32_t ab = ord[d.a.w / CB];
+            const int a = (int)(ab & 0xffffu), b = (int)(ab >> 16);
+            const int i = a < b ? a : b, j = a < b ? b : a;
+            transposed = a > b;
             return (int64_t)i * N - (int64_t)i * (i - 1) / 2 + (j - i);
         };
         // ---- load the trajectory into registers and LDS
@@ -317,8 +349,12 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 C v;
                 v.x = 0;
                 v.y = 0;
-                if (active && own < (uint32_t)P * CB)
-                    v = rho[((int64_t)gs * P + packed_of(d)) * ldr + m];
+                if (active && own < (uint32_t)P * CB) {
+                    bool tr;
+                    const int64_t p = packed_of(d, tr);
+                    v = rho[((int64_t)gs * P + p) * ldr + m];
+                    if (tr) v.y = -v.y;
+                }
                 *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = v;  // dummies: scratch slot
                 y[s][u] = v;
                 acc[s][u] = v;
@@ -441,10 +477,10 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         // is y itself, so nothing is held across steps
                         const C own = STAGE == 1 ? y[s][u] : hold[s][u];
                         *reinterpret_cast<C*>(Yb + d.a.w) = own;
-                        k = element_rhs<T, true>(Yb, dcur, d, tw, Uw, own);
+                        k = element_rhs_sel<T, true>(u < GE, Yb, dcur, d, tw, Uw, own);
                     } else {
-                        k = element_rhs<T, false>(Yb, Yunit + (1 - s) * Pb * CB, d, tw, Uw,
-                                                  hold[s][u]);
+                        k = element_rhs_sel<T, false>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
+                                                      tw, Uw, hold[s][u]);
                     }
                     hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(hold[s][u]);
@@ -477,7 +513,11 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
                     const unsigned char* Yd = S == 1 ? dcur : Yunit + (1 - s) * Pb * CB;
-                    const C k = element_rhs<T, false>(Yb, Yd, d, tw, Uw, y[s][u]);
+                    // stage 1 reads the element's own value from y (the
+                    // stage input of a full step is its base point)
+                    const C k = STAGE == 1
+                        ? element_rhs_sel<T, true>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u])
+                        : element_rhs_sel<T, false>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u]);
                     *reinterpret_cast<C*>(Yb + d.a.w) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
@@ -550,8 +590,13 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 for (int u = 0; u < UE + UO; ++u) {
                     const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
                     const ResDesc d = load_desc(desc + e);
-                    if (d.a.w < (uint32_t)P * CB)
-                        rho_out[((int64_t)gs * P + packed_of(d)) * ldr + m] = y[s][u];
+                    if (d.a.w < (uint32_t)P * CB) {
+                        bool tr;
+                        const int64_t p = packed_of(d, tr);
+                        C v = y[s][u];
+                        if (tr) v.y = -v.y;
+                        rho_out[((int64_t)gs * P + p) * ldr + m] = v;
+                    }
                 }
             }
         }
@@ -559,29 +604,33 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 }
 
 // ---------------------------------------------------------------- configurations
+// GE, GO: the leading even and odd slots that take the general path (the
+// elements that read a transpose must fit in them).
 struct Config {
     ftwa_dtype dtype;
-    int S, NTU, UNITS, UE, UO;
+    int S, NTU, UNITS, UE, UO, GE, GO;
     const void* fn;
 };
 
-#define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO) \
-    Config{DT, S, NTU, UNITS, UE, UO, (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO>}
+#define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO, GE, GO)          \
+    Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                          \
+           (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO>}
 
 // Ordered by preference; the first one that fits a lattice is used.
 const Config kConfigs[] = {
-    FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1),
-    FTWA_RES_CFG(double, FTWA_F64, 2, 128, 8, 2, 2),
-    FTWA_RES_CFG(double, FTWA_F64, 2, 256, 3, 3, 3),
-    FTWA_RES_CFG(double, FTWA_F64, 2, 512, 1, 5, 5),
-    FTWA_RES_CFG(float, FTWA_F32, 2, 64, 16, 1, 1),
-    FTWA_RES_CFG(float, FTWA_F32, 2, 128, 8, 2, 2),
-    FTWA_RES_CFG(float, FTWA_F32, 2, 256, 4, 3, 3),
-    FTWA_RES_CFG(float, FTWA_F32, 2, 512, 1, 5, 5),
-    FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 8, 8),
-    FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 13, 13),
-    FTWA_RES_CFG(float, FTWA_F32, 1, 1024, 1, 10, 10),
-    FTWA_RES_CFG(float, FTWA_F32, 1, 512, 1, 20, 20),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 128, 8, 2, 2, 2, 2),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 256, 3, 3, 3, 3, 3),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 512, 1, 5, 5, 5, 5),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 64, 16, 1, 1, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 128, 8, 2, 2, 2, 2),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 256, 4, 3, 3, 3, 3),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 512, 1, 5, 5, 5, 5),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 8, 8, 2, 2),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 13, 13, 2, 2),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 1024, 1, 10, 10, 2, 2),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 512, 1, 20, 20, 2, 2),
+    FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 13, 13, 13, 13),
 };
 
 constexpr size_t kMaxLds = 160 * 1024;  // the kernel declares no static LDS
@@ -612,6 +661,8 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         const Config& c = kConfigs[k];
         if (c.dtype != dtype) continue;
         if ((int64_t)c.NTU * c.UE < n_even || (int64_t)c.NTU * c.UO < n_odd) continue;
+        if ((int64_t)c.NTU * c.GE < tab.n_gen_even || (int64_t)c.NTU * c.GO < tab.n_gen_odd)
+            continue;
         if (lds_bytes(c, N, P) > kMaxLds) continue;
         if (N > c.NTU) continue;  // the diagonal must sit in slot 0
         plan->config = k;

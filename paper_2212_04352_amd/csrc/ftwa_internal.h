@@ -23,15 +23,21 @@ struct DeviceTables {
     int32_t* off = nullptr;    // [N]: packed row start i*N - i*(i-1)/2
     uint32_t* elem = nullptr;  // [P]: packed element p -> i | j << 16
     int64_t n_even = 0;        // size of the even class (i, j on the same sublattice)
+    int64_t n_gen_even = 0;    // leading even-class elements that read a transpose
+    int64_t n_gen_odd = 0;     // leading odd-class elements that read a transpose
     bool bipartite = false;
-    uint32_t* ord = nullptr;   // [P]: LDS slot (class order) -> i | j << 16
+    uint32_t* ord = nullptr;   // [P]: LDS slot (class order) -> a | b << 16, the
+                               // element stored there is rho_ab ({a, b} = {i, j})
     int32_t* dpos = nullptr;   // [N]: site -> its position in the sublattice-major
                                // diagonal (the sites of one sublattice, ascending,
                                // then the other's)
 };
 
 // Stencil descriptor of one element for the resident kernel (32 bytes), all
-// offsets in bytes within the LDS block of one spin:
+// offsets in bytes within the LDS block of one spin.  Of every pair {i, j}
+// the LDS holds one orientation rho_ab (a ranks before b in a bandwidth-
+// reducing site order, so that few elements read a transposed neighbour);
+// the descriptor of the stored element rho_ij has
 //   a.x, a.y, a.z: the column neighbours rho_ik, k in nb(j), ascending;
 //   b.x, b.y, b.z: the row neighbours rho_kj, k in nb(i), ascending;
 //     each = offset of the stored element | bit 31 set when the stored
@@ -62,7 +68,7 @@ struct ftwa_lattice_s {
     // resident-path descriptors padded per class to whole slots, by
     // (device, even slots, odd slots, element bytes and diagonal layout)
     std::map<std::tuple<int, int64_t, int64_t, int>, ftwa::ResDesc*> padded;
-    std::vector<uint32_t> class_order;      // i | j << 16 of the elements in LDS-slot order
+    std::vector<uint32_t> class_order;      // a | b << 16 of the stored elements in LDS-slot order
     std::vector<int32_t> diag_pos;          // site -> sublattice-major diagonal position
 };
 
@@ -73,6 +79,11 @@ inline int64_t packed_count(int N) { return (int64_t)N * (N + 1) / 2; }
 inline int64_t packed_row(int N, int i) { return (int64_t)i * N - (int64_t)i * (i - 1) / 2; }
 inline int64_t n_records(int64_t n_steps, int record_every) { return n_steps / record_every + 1; }
 inline int64_t s2_count(int D) { return (int64_t)D * (D + 1) / 2; }
+// What the resident configurations that fit a lattice depend on besides N:
+// the class sizes of its stored elements (tuning results are kept by it).
+inline int64_t class_shape(const DeviceTables& t) {
+    return t.n_even | (t.n_gen_even << 20) | (t.n_gen_odd << 40);
+}
 
 // Error reporting (thread-local message, see ftwa_last_error).
 ftwa_status fail(ftwa_status st, const std::string& msg);
@@ -209,8 +220,8 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream);
 ftwa_status resident_check_error(const int* err, hipStream_t stream, bool* timed_out);
 
 // Configurations chosen by ftwa_autotune, per (device, N, even-class size, dtype).
-bool tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int* config);
-void set_tuned_config(int N, int64_t n_even, ftwa_dtype dtype, int config);
+bool tuned_config(int N, int64_t shape, ftwa_dtype dtype, int* config);
+void set_tuned_config(int N, int64_t shape, ftwa_dtype dtype, int config);
 
 // Brackets launches of the dominant kernel with HIP events on one stream and
 // sums their durations (optional, see ftwa_tuning::kernel_ms).

@@ -288,13 +288,24 @@ namespace ftwa {
 // stencil read of an element (i, j) with i, j on the same sublattice ("even")
 // touches only elements joining different sublattices ("odd") and vice versa,
 // which lets the resident kernel update the two classes in separate phases.
-// Returns false when the graph has an odd cycle.
-// Class order of the packed elements for the resident kernel: the even class
-// (i and j on the same sublattice; the diagonal first, then row-major), then
-// the odd class (row-major).  An element's position in this order is its
-// slot in the kernel's LDS block.  Returns false for a non-bipartite graph.
+//
+// Of each pair {i, j} the resident kernel stores one orientation rho_ab, a
+// ranking no later than b in a Cuthill-McKee order of the sites (breadth
+// first from a site of least degree, neighbours by ascending degree).  That
+// order keeps bonded sites close, so an element reads a neighbour stored as
+// its transpose only when a and b are close in rank: a small set, placed at
+// the front of its class, and every other element takes the kernel's
+// conjugation-free path.
+//
+// Class order of the stored elements: the even class (the diagonal first,
+// (i,i) at position i, then the elements that read a transpose, then the
+// rest), then the odd class (those that read a transpose, then the rest),
+// each group ordered by the ranks of (a, b).  An element's position in this
+// order is its slot in the kernel's LDS block.  Returns false for a
+// non-bipartite graph.
 bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* n_even,
-                       std::vector<int32_t>* diag_pos) {
+                       std::vector<int32_t>* diag_pos, int64_t* n_gen_even,
+                       int64_t* n_gen_odd) {
     const int N = lat->N;
     std::vector<int> colour(N, -1);
     for (int root = 0; root < N; ++root) {
@@ -316,17 +327,57 @@ bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* 
     for (int c = 0; c < 2; ++c)
         for (int i = 0; i < N; ++i)
             if (colour[i] == c) (*diag_pos)[i] = next++;
-    auto ij = [](int i, int j) { return (uint32_t)i | ((uint32_t)j << 16); };
+
+    // Cuthill-McKee rank of every site (each connected component in turn)
+    std::vector<int> rank(N, -1);
+    int r = 0;
+    while (r < N) {
+        int root = -1;
+        for (int i = 0; i < N; ++i)
+            if (rank[i] < 0 && (root < 0 || lat->deg[i] < lat->deg[root])) root = i;
+        rank[root] = r++;
+        std::deque<int> q{root};
+        while (!q.empty()) {
+            const int u = q.front();
+            q.pop_front();
+            int nb[kMaxDeg], n = 0;
+            for (int k = 0; k < lat->deg[u]; ++k) nb[n++] = lat->nbr[(size_t)u * kMaxDeg + k];
+            std::stable_sort(nb, nb + n, [&](int x, int y) { return lat->deg[x] < lat->deg[y]; });
+            for (int k = 0; k < n; ++k)
+                if (rank[nb[k]] < 0) { rank[nb[k]] = r++; q.push_back(nb[k]); }
+        }
+    }
+    // stored element (a, b) of rho_ab, rank[a] <= rank[b]; it reads a
+    // transpose when a column neighbour rho_ak (k in nb(b)) has rank[k] <
+    // rank[a] or a row neighbour rho_kb (k in nb(a)) has rank[k] > rank[b]
+    auto reads_transpose = [&](int a, int b) {
+        for (int k = 0; k < lat->deg[b]; ++k)
+            if (rank[lat->nbr[(size_t)b * kMaxDeg + k]] < rank[a]) return true;
+        for (int k = 0; k < lat->deg[a]; ++k)
+            if (rank[lat->nbr[(size_t)a * kMaxDeg + k]] > rank[b]) return true;
+        return false;
+    };
+    std::vector<int> by_rank(N);
+    for (int i = 0; i < N; ++i) by_rank[rank[i]] = i;
+    auto ab = [](int a, int b) { return (uint32_t)a | ((uint32_t)b << 16); };
     order->clear();
     order->reserve((size_t)packed_count(N));
-    for (int i = 0; i < N; ++i) order->push_back(ij(i, i));
-    for (int i = 0; i < N; ++i)
-        for (int j = i + 1; j < N; ++j)
-            if (colour[i] == colour[j]) order->push_back(ij(i, j));
-    *n_even = (int64_t)order->size();
-    for (int i = 0; i < N; ++i)
-        for (int j = i + 1; j < N; ++j)
-            if (colour[i] != colour[j]) order->push_back(ij(i, j));
+    for (int i = 0; i < N; ++i) order->push_back(ab(i, i));
+    for (int cls = 0; cls < 2; ++cls) {
+        const size_t start = order->size();
+        std::vector<uint32_t> rest;
+        for (int ra = 0; ra < N; ++ra)
+            for (int rb = ra + 1; rb < N; ++rb) {
+                const int a = by_rank[ra], b = by_rank[rb];
+                if ((colour[a] != colour[b]) != (cls == 1)) continue;
+                if (reads_transpose(a, b)) order->push_back(ab(a, b));
+                else rest.push_back(ab(a, b));
+            }
+        if (cls == 0) *n_gen_even = (int64_t)order->size();
+        else *n_gen_odd = (int64_t)(order->size() - start);
+        order->insert(order->end(), rest.begin(), rest.end());
+        if (cls == 0) *n_even = (int64_t)order->size();
+    }
     return true;
 }
 
@@ -353,18 +404,25 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
         *out = it->second;
         return FTWA_OK;
     }
-    // LDS slot of every packed element
+    // LDS slot of every pair {i, j} (packed index of i <= j) and whether the
+    // slot holds rho_ij (a = min) or rho_ji
     std::vector<uint32_t> slot((size_t)P);
+    std::vector<uint8_t> lower((size_t)P, 0);
     for (size_t q = 0; q < order.size(); ++q) {
-        const int i = (int)(order[q] & 0xffffu), j = (int)(order[q] >> 16);
+        const int a = (int)(order[q] & 0xffffu), b = (int)(order[q] >> 16);
+        const int i = std::min(a, b), j = std::max(a, b);
         slot[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)q;
+        lower[(size_t)(packed_row(N, i) + (j - i))] = a > b;
     }
     const uint32_t eb = (uint32_t)elem_bytes;
     const uint32_t zero = (uint32_t)P * eb, scratch = (uint32_t)(P + 1) * eb;
-    // byte offset of element (a, b) as stored; bit 31: read its conjugate
-    auto field = [&](int a, int b) -> uint32_t {
-        if (a <= b) return slot[(size_t)(packed_row(N, a) + (b - a))] * eb;
-        return (slot[(size_t)(packed_row(N, b) + (a - b))] * eb) | 0x80000000u;
+    // byte offset of element rho_xy as stored; bit 31: the slot holds rho_yx
+    // (read its conjugate)
+    auto field = [&](int x, int y) -> uint32_t {
+        const int i = std::min(x, y), j = std::max(x, y);
+        const size_t p = (size_t)(packed_row(N, i) + (j - i));
+        const bool stored_xy = (x <= y) != (lower[p] != 0) || x == y;
+        return slot[p] * eb | (stored_xy ? 0u : 0x80000000u);
     };
     auto make = [&](int i, int j) {
         ResDesc d;
@@ -378,7 +436,7 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
         d.a.x = col[0];
         d.a.y = col[1];
         d.a.z = col[2];
-        d.a.w = slot[(size_t)(packed_row(N, i) + (j - i))] * eb;
+        d.a.w = field(i, j);
         d.b.x = row[0];
         d.b.y = row[1];
         d.b.z = row[2];
@@ -397,9 +455,17 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
     dummy.b.w = 0;
     std::vector<ResDesc> tabp((size_t)(even_slots + odd_slots), dummy);
     for (int64_t q = 0; q < (int64_t)order.size(); ++q) {
-        const int i = (int)(order[q] & 0xffffu), j = (int)(order[q] >> 16);
+        const int a = (int)(order[q] & 0xffffu), b = (int)(order[q] >> 16);
         const int64_t at = q < n_even ? q : even_slots + (q - n_even);
-        tabp[(size_t)at] = make(i, j);
+        const ResDesc d = make(a, b);
+        // past the leading groups no neighbour is a transpose (the kernel
+        // reads those elements without the conjugation flags)
+        const bool general = q < n_even ? q < tab.n_gen_even : q - n_even < tab.n_gen_odd;
+        const uint32_t flags = d.a.x | d.a.y | d.a.z | d.a.w | d.b.x | d.b.y | d.b.z;
+        if (!general && (flags & 0x80000000u))
+            return fail(FTWA_ENOTSUP, "class order: transpose read outside the leading group");
+        if (d.a.w & 0x80000000u) return fail(FTWA_ENOTSUP, "class order: element not stored");
+        tabp[(size_t)at] = d;
     }
     ResDesc* d = nullptr;
     FTWA_HIP_TRY(hipMalloc(&d, tabp.size() * sizeof(ResDesc)));
@@ -431,7 +497,8 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
     DeviceTables tab;
     std::vector<uint32_t> order;
     std::vector<int32_t> dpos;
-    tab.bipartite = build_class_order(lat, &order, &tab.n_even, &dpos);
+    tab.bipartite =
+        build_class_order(lat, &order, &tab.n_even, &dpos, &tab.n_gen_even, &tab.n_gen_odd);
     if (tab.bipartite) {
         lat->class_order = order;
         lat->diag_pos = dpos;
