@@ -16,23 +16,27 @@
 // elements.  The base point y and the accumulator acc of every element live
 // in the registers of the thread that owns it.  The U term reads the other
 // spin's diagonal from slots 0..N-1 of its block (S = 2) or from a copy of
-// the partner's diagonal next to the block (S = 1; N reals ordered by
+// the partner's diagonal placed before the block (S = 1; N reals ordered by
 // sublattice, so the diagonal values read by a wave's consecutive
-// same-sublattice sites sit in consecutive banks).  The kernel declares no
-// static LDS, so block offsets are LDS addresses.
+// same-sublattice sites sit in consecutive banks; two copies at a fixed
+// distance, alternating by stage).  The kernel declares no static LDS, so
+// block offsets are LDS addresses.
 //
-// Descriptors.  Each element has a 32-byte descriptor with the LDS byte
-// offsets of its six neighbour elements and of itself, and of the two
-// diagonal values.  The LDS stores one orientation of every pair (chosen by
-// a bandwidth-reducing site ranking); a neighbour stored as its transpose
-// carries a flag, and its imaginary part enters the sums with the factor -1
-// (fma(+-1, v, s) rounds exactly like s +- v), so the arithmetic is that of
-// the equation of motion in a fixed order.  The few elements with such
-// neighbours come first in their class and fill the leading GE even and GO
-// odd slots; all other slots are compiled without the flag handling.  Consecutive threads own consecutive slots, so
-// own reads and writes of a wave are contiguous; neighbours of consecutive
-// same-class elements of a row are mostly consecutive slots of the other
-// class.
+// Descriptors.  Each element has a descriptor with the LDS locations of its
+// six neighbour elements and of itself, and of the two diagonal values: 32
+// bytes of byte offsets, or, for the spin split, 16 bytes of 16-bit slot
+// numbers and 8-bit diagonal positions (the descriptor stream is a large part
+// of the kernel's memory traffic; each field becomes a byte offset with one
+// sub-dword-select shift).  The LDS stores one orientation of every pair
+// (chosen by a bandwidth-reducing site ranking); a neighbour stored as its
+// transpose carries a flag, and its imaginary part enters the sums with the
+// factor -1 (fma(+-1, v, s) rounds exactly like s +- v), so the arithmetic is
+// that of the equation of motion in a fixed order.  The few elements with
+// such neighbours come first in their class and fill the leading GE even and
+// GO odd slots; all other slots are compiled without the flag handling.
+// Consecutive threads own consecutive slots, so own reads and writes of a
+// wave are contiguous; neighbours of consecutive same-class elements of a row
+// are mostly consecutive slots of the other class.
 //
 // Two-phase stages.  The honeycomb is bipartite: an element (i, j) with i and
 // j on the same sublattice ("even") reads only elements joining different
@@ -134,7 +138,93 @@ __device__ __forceinline__ ResDesc slot_desc(gdesc_t desc, int slot, uint32_t to
     return load_desc((gdesc_t)(base + toff));
 }
 
-// Conjugation by the descriptor's bit 31: the imaginary part enters the
+// The stage loop's descriptor reads: buffer loads with the slot base in a
+// scalar offset and the thread's byte offset in a vector register (no
+// per-thread address arithmetic).  DT = ResDesc (wide) or uint4 (compact).
+template <typename DT>
+__device__ __forceinline__ DT slot_desc_buf(__amdgpu_buffer_rsrc_t r, int slot, uint32_t toff) {
+    constexpr int B = (int)sizeof(DT);
+    if constexpr (B == 16) {
+        return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, toff, slot * B, 0));
+    } else {
+        ResDesc d;
+        d.a = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, toff, slot * B, 0));
+        d.b = __builtin_bit_cast(uint4,
+                                 __builtin_amdgcn_raw_buffer_load_b128(r, toff, slot * B + 16, 0));
+        return d;
+    }
+}
+
+// Byte offset = 16-bit field (low or high half of w) x 8, and diagonal word
+// offset = byte field 2 or 3 of w x 4: one VALU instruction each (a
+// sub-dword operand select).
+__device__ __forceinline__ uint32_t lo16x8(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:WORD_0" : "=v"(r) : "v"(w));
+    return r;
+}
+__device__ __forceinline__ uint32_t hi16x8(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:WORD_1" : "=v"(r) : "v"(w));
+    return r;
+}
+__device__ __forceinline__ uint32_t b2x4(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:BYTE_2" : "=v"(r) : "v"(w));
+    return r;
+}
+__device__ __forceinline__ uint32_t b3x4(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:BYTE_3" : "=v"(r) : "v"(w));
+    return r;
+}
+
+// One element's stencil in LDS byte offsets: n[0..2] the column neighbours,
+// n[3..5] the row neighbours (with GEN: bit 31 = read the conjugate), own the
+// element's slot (within its spin block), di, dj the diagonal values of the
+// U term (within the diagonal array).
+struct Stencil {
+    uint32_t n[6];
+    uint32_t own, di, dj;
+};
+
+template <bool GEN> __device__ __forceinline__ Stencil decode(const ResDesc& d) {
+    Stencil e;
+    e.n[0] = d.a.x;
+    e.n[1] = d.a.y;
+    e.n[2] = d.a.z;
+    e.n[3] = d.b.x;
+    e.n[4] = d.b.y;
+    e.n[5] = d.b.z;
+    e.own = d.a.w;
+    e.di = d.b.w & 0xffffu;
+    e.dj = d.b.w >> 16;
+    return e;
+}
+template <bool GEN> __device__ __forceinline__ Stencil decode(const uint4& w) {
+    Stencil e;
+    const uint32_t f[3] = {w.x, w.y, w.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if constexpr (GEN) {
+            e.n[2 * k] = ((f[k] & 0x7fffu) << 3) | ((f[k] & 0x8000u) << 16);
+            e.n[2 * k + 1] = ((f[k] >> 13) & 0x3fff8u) | (f[k] & 0x80000000u);
+        } else {
+            e.n[2 * k] = lo16x8(f[k]);
+            e.n[2 * k + 1] = hi16x8(f[k]);
+        }
+    }
+    e.own = lo16x8(w.w);
+    e.di = b2x4(w.w);
+    e.dj = b3x4(w.w);
+    return e;
+}
+
+// Conjugation by bit 31 of a neighbour offset: the imaginary part enters the
 // neighbour sums with the factor -1 (+1 otherwise).  The factor is formed
 // from the descriptor alone, so all LDS reads of an element can be issued
 // before any of their values is needed; fma(+-1, v, s) rounds exactly like
@@ -152,54 +242,58 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
     return *reinterpret_cast<const cplx_t<T>*>(base + (f & 0x7fffffffu));
 }
 
-// Right-hand side of one element from its descriptor: Yb is the LDS block of
-// its spin, Yd the block holding the other spin's diagonal at slots 0..N-1.
-// Sums as in the equation of motion: col = (v0 + v1) + v2 over the column
-// neighbours, row likewise.  GEN: a neighbour may be stored as its transpose
-// (flag in bit 31 of its offset; its imaginary part enters with the factor
-// -1); otherwise no offset carries a flag and the sums are plain (fma(1, v, s)
-// and s + v round alike, so both forms give the same bits).  The element's
-// own value is read from LDS, or taken from `own` (OWN_REG).
+// Right-hand side of one element from its stencil: Yb is the LDS block of its
+// spin, Yd the diagonal array of the U term.  Sums as in the equation of
+// motion: col = (v0 + v1) + v2 over the column neighbours, row likewise.
+// GEN: a neighbour may be stored as its transpose (its imaginary part enters
+// with the factor -1); otherwise no offset carries a flag and the sums are
+// plain (fma(1, v, s) and s + v round alike, so both forms give the same
+// bits).  The element's own value is read from LDS, or taken from `own`
+// (OWN_REG).
 template <typename T, bool OWN_REG, bool GEN>
 __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
-                                                 const ResDesc& d, T t, T U, cplx_t<T> own) {
+                                                 const Stencil& e, T t, T U, cplx_t<T> own) {
     using C = cplx_t<T>;
     C col, row;
     if constexpr (GEN) {
-        const C c0 = lds_at<T>(Yb, d.a.x), c1 = lds_at<T>(Yb, d.a.y), c2 = lds_at<T>(Yb, d.a.z);
-        const C r0 = lds_at<T>(Yb, d.b.x), r1 = lds_at<T>(Yb, d.b.y), r2 = lds_at<T>(Yb, d.b.z);
+        const C c0 = lds_at<T>(Yb, e.n[0]), c1 = lds_at<T>(Yb, e.n[1]), c2 = lds_at<T>(Yb, e.n[2]);
+        const C r0 = lds_at<T>(Yb, e.n[3]), r1 = lds_at<T>(Yb, e.n[4]), r2 = lds_at<T>(Yb, e.n[5]);
         col.x = (c0.x + c1.x) + c2.x;
-        col.y = fma_rn<T>(conj_sign<T>(d.a.z), c2.y,
-                          fma_rn<T>(conj_sign<T>(d.a.y), c1.y, conj_sign<T>(d.a.x) * c0.y));
+        col.y = fma_rn<T>(conj_sign<T>(e.n[2]), c2.y,
+                          fma_rn<T>(conj_sign<T>(e.n[1]), c1.y, conj_sign<T>(e.n[0]) * c0.y));
         row.x = (r0.x + r1.x) + r2.x;
-        row.y = fma_rn<T>(conj_sign<T>(d.b.z), r2.y,
-                          fma_rn<T>(conj_sign<T>(d.b.y), r1.y, conj_sign<T>(d.b.x) * r0.y));
+        row.y = fma_rn<T>(conj_sign<T>(e.n[5]), r2.y,
+                          fma_rn<T>(conj_sign<T>(e.n[4]), r1.y, conj_sign<T>(e.n[3]) * r0.y));
     } else {
-        const C c0 = *reinterpret_cast<const C*>(Yb + d.a.x);
-        const C c1 = *reinterpret_cast<const C*>(Yb + d.a.y);
-        const C c2 = *reinterpret_cast<const C*>(Yb + d.a.z);
-        const C r0 = *reinterpret_cast<const C*>(Yb + d.b.x);
-        const C r1 = *reinterpret_cast<const C*>(Yb + d.b.y);
-        const C r2 = *reinterpret_cast<const C*>(Yb + d.b.z);
+        const C c0 = *reinterpret_cast<const C*>(Yb + e.n[0]);
+        const C c1 = *reinterpret_cast<const C*>(Yb + e.n[1]);
+        const C c2 = *reinterpret_cast<const C*>(Yb + e.n[2]);
+        const C r0 = *reinterpret_cast<const C*>(Yb + e.n[3]);
+        const C r1 = *reinterpret_cast<const C*>(Yb + e.n[4]);
+        const C r2 = *reinterpret_cast<const C*>(Yb + e.n[5]);
         col.x = (c0.x + c1.x) + c2.x;
         col.y = (c0.y + c1.y) + c2.y;
         row.x = (r0.x + r1.x) + r2.x;
         row.y = (r0.y + r1.y) + r2.y;
     }
-    const C rho = OWN_REG ? own : *reinterpret_cast<const C*>(Yb + d.a.w);
-    const T di = *reinterpret_cast<const T*>(Yd + (d.b.w & 0xffffu));
-    const T dj = *reinterpret_cast<const T*>(Yd + (d.b.w >> 16));
+    const C rho = OWN_REG ? own : *reinterpret_cast<const C*>(Yb + e.own);
+    const T di = *reinterpret_cast<const T*>(Yd + e.di);
+    const T dj = *reinterpret_cast<const T*>(Yd + e.dj);
     const T a = U * (di - dj);
     return rhs_element<T>(col, row, rho, t, a);
 }
 
+// The element's own slot offset from its descriptor.
+__device__ __forceinline__ uint32_t own_off(const ResDesc& d) { return d.a.w; }
+__device__ __forceinline__ uint32_t own_off(const uint4& w) { return lo16x8(w.w); }
+
 // The same with the variant chosen by a (compile-time) slot condition.
-template <typename T, bool OWN_REG>
+template <typename T, bool OWN_REG, typename DT>
 __device__ __forceinline__ cplx_t<T> element_rhs_sel(bool gen, const unsigned char* Yb,
-                                                     const unsigned char* Yd, const ResDesc& d,
+                                                     const unsigned char* Yd, const DT& d,
                                                      T t, T U, cplx_t<T> own) {
-    return gen ? element_rhs<T, OWN_REG, true>(Yb, Yd, d, t, U, own)
-               : element_rhs<T, OWN_REG, false>(Yb, Yd, d, t, U, own);
+    return gen ? element_rhs<T, OWN_REG, true>(Yb, Yd, decode<true>(d), t, U, own)
+               : element_rhs<T, OWN_REG, false>(Yb, Yd, decode<false>(d), t, U, own);
 }
 
 // One Runge-Kutta stage update of an element from its slope k:
@@ -252,9 +346,13 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
 __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
+    // descriptor form: compact for the spin split, wide otherwise
+    using DT = std::conditional_t<S == 1, uint4, ResDesc>;
+    static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
+    constexpr uint32_t kDiagCopy = 256 * TB;  // S = 1: one copy of the partner's diagonal
     extern __shared__ __align__(16) unsigned char smem[];  // dynamic LDS, at address 0
     (void)smem;
     const int tid0 = threadIdx.x;
@@ -290,7 +388,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const int tid = tid0;
         const int unit = UNITS == 1 ? 0 : tid / NTU;
         const int t = UNITS == 1 ? tid : tid % NTU;
-        const uint32_t toff = (uint32_t)t * (uint32_t)sizeof(ResDesc);
+        const uint32_t toff = (uint32_t)t * (uint32_t)sizeof(DT);
         const int lane = tid % 64;
         const int wave = tid / 64;
 
@@ -302,13 +400,14 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const int N = E.N;
         const int P = E.P;
         const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
-        // LDS: UNITS x S blocks of Pb complex slots; S = 1 adds per unit two
-        // copies of the partner's diagonal (N reals, sublattice-major)
-        // the launch has no static LDS, so the dynamic block starts at LDS
-        // address 0 and block offsets are addresses (no base register)
-        unsigned char* const Yunit = lds_ptr((uint32_t)((size_t)unit * S * Pb * CB));
-        unsigned char* const dpart =
-            lds_ptr((uint32_t)((size_t)UNITS * S * Pb * CB + (size_t)unit * 2 * N * TB));
+        // LDS: UNITS x S blocks of Pb complex slots; S = 1: two copies of the
+        // partner's diagonal (N reals, sublattice-major, kDiagCopy bytes
+        // apart) first, then the block.  The launch has no static LDS, so the
+        // dynamic block starts at LDS address 0 and offsets are addresses (no
+        // base register; constant offsets go into the instructions).
+        unsigned char* const Yunit =
+            lds_ptr((uint32_t)((S == 1 ? 2 * kDiagCopy : 0) + (size_t)unit * S * Pb * CB));
+        unsigned char* const dpart = lds_ptr(0);
         // per-wave partial sums of the records and the abort flag follow
         // (placed after the largest blocks of the launch: A.tail_off)
         double (*red)[2 * S] = reinterpret_cast<double (*)[2 * S]>(lds_ptr(A.tail_off));
@@ -321,6 +420,15 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         double* const Xrec = E.X;
         double* const inv_parts = E.inv_parts;
         gdesc_t desc = (gdesc_t)uniform64((uint64_t)E.desc);
+        // LDS byte offset (within its spin block) of the element in
+        // descriptor entry e
+        auto own_of = [&](int e) -> uint32_t {
+            if constexpr (S == 1)
+                return (reinterpret_cast<const uint4*>((uint64_t)desc)[e].w & 0xffffu) *
+                       (uint32_t)CB;
+            else
+                return desc[e].a.w;
+        };
         __syncthreads();  // the previous item is done with LDS and `red`
 
         // packed index of the element a descriptor describes (its LDS slot
@@ -330,8 +438,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 
         // (the LDS holds rho_ab; rho_ba when b < a is the packed element, so
         // it is conjugated on the way in and out)
-        auto packed_of = [&](const ResDesc& d, bool& transposed) -> int64_t {
-            const uint32_t ab = ord[d.a.w / CB];
+        auto packed_of = [&](uint32_t own, bool& transposed) -> int64_t {
+            const uint32_t ab = ord[own / CB];
             const int a = (int)(ab & 0xffffu), b = (int)(ab >> 16);
             const int i = a < b ? a : b, j = a < b ? b : a;
             transposed = a > b;
@@ -344,14 +452,13 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
             for (int u = 0; u < UE + UO; ++u) {
                 const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                const ResDesc d = load_desc(desc + e);
-                const uint32_t own = d.a.w;
+                const uint32_t own = own_of(e);
                 C v;
                 v.x = 0;
                 v.y = 0;
                 if (active && own < (uint32_t)P * CB) {
                     bool tr;
-                    const int64_t p = packed_of(d, tr);
+                    const int64_t p = packed_of(own, tr);
                     v = rho[((int64_t)gs * P + p) * ldr + m];
                     if (tr) v.y = -v.y;
                 }
@@ -376,9 +483,9 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             for (int i = t; i < N; i += NTU) {
                 const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
                 const int q = dpos[i];
-                reinterpret_cast<T*>(dpart + (size_t)(g & 1) * N * TB)[q] =
+                reinterpret_cast<T*>(dpart + (size_t)(g & 1) * kDiagCopy)[q] =
                     active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
-                reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * N * TB)[q] = (T)0;
+                reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * kDiagCopy)[q] = (T)0;
             }
         }
         // records: the first N even elements are the diagonal (i = position)
@@ -401,7 +508,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
                     for (int u = 0; u < UE + UO; ++u) {
                         const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                        const uint32_t own = desc[e].a.w;
+                        const uint32_t own = own_of(e);
                         const double re = (double)y[s][u].x, im = (double)y[s][u].y;
                         const bool diag = u < UE && e < N;
                         frob[s] += diag ? re * re : 2.0 * (re * re + im * im);
@@ -454,8 +561,10 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         auto run_stage = [&](auto stage_tag) -> bool {
             constexpr int STAGE = decltype(stage_tag)::value;
             const T c = STAGE <= 2 ? c_half : (STAGE == 3 ? c_full : c_sixth);
-            // S = 1: the partner's diagonal of this stage's input
-            const unsigned char* dcur = dpart + (size_t)(g & 1) * N * TB;
+            // S = 1: the partner's diagonal of this stage's input (the copy
+            // of the stage counter's parity, which is that of STAGE - 1: every
+            // step advances the counter by four)
+            const unsigned char* dcur = dpart + ((STAGE - 1) & 1) * kDiagCopy;
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
             // registers); the next slot's descriptor is loaded one slot ahead.
@@ -463,11 +572,13 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             // here (nothing reads an even element in phase 1: its own value
             // comes from the register, the diagonal of the U term from the
             // partner's copy), which saves a barrier per stage.
-            ResDesc dn = slot_desc(desc, 0, toff);
+            const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)desc, (short)0, (int)((kEvenPad + NTU * UO) * sizeof(DT)), 0x00020000);
+            DT dn = slot_desc_buf<DT>(drs, 0, toff);
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
-                const ResDesc d = dn;
-                dn = slot_desc(desc, u + 1 < UE ? NTU * (u + 1) : kEvenPad, toff);
+                const DT d = dn;
+                dn = slot_desc_buf<DT>(drs, u + 1 < UE ? NTU * (u + 1) : kEvenPad, toff);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
@@ -476,7 +587,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         // the stage input of this element: after a full step it
                         // is y itself, so nothing is held across steps
                         const C own = STAGE == 1 ? y[s][u] : hold[s][u];
-                        *reinterpret_cast<C*>(Yb + d.a.w) = own;
+                        *reinterpret_cast<C*>(Yb + own_off(d)) = own;
                         k = element_rhs_sel<T, true>(u < GE, Yb, dcur, d, tw, Uw, own);
                     } else {
                         k = element_rhs_sel<T, false>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
@@ -507,8 +618,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             // ---------------- phase 2: odd elements (written straight to LDS)
 #pragma unroll
             for (int u = UE; u < UE + UO; ++u) {
-                const ResDesc d = dn;
-                if (u + 1 < UE + UO) dn = slot_desc(desc, kEvenPad + NTU * (u + 1 - UE), toff);
+                const DT d = dn;
+                if (u + 1 < UE + UO) dn = slot_desc_buf<DT>(drs, kEvenPad + NTU * (u + 1 - UE), toff);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
@@ -518,7 +629,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     const C k = STAGE == 1
                         ? element_rhs_sel<T, true>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u])
                         : element_rhs_sel<T, false>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u]);
-                    *reinterpret_cast<C*>(Yb + d.a.w) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
+                    *reinterpret_cast<C*>(Yb + own_off(d)) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
                 }
@@ -547,7 +658,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         w = __hip_atomic_load(slot + tid, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * N * TB)[q] =
+                    reinterpret_cast<T*>(dpart + (STAGE & 1) * kDiagCopy)[q] =
                         from_bits<T>((uint32_t)w);
                 }
             } else {
@@ -589,10 +700,10 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
                 for (int u = 0; u < UE + UO; ++u) {
                     const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                    const ResDesc d = load_desc(desc + e);
-                    if (d.a.w < (uint32_t)P * CB) {
+                    const uint32_t own = own_of(e);
+                    if (own < (uint32_t)P * CB) {
                         bool tr;
-                        const int64_t p = packed_of(d, tr);
+                        const int64_t p = packed_of(own, tr);
                         C v = y[s][u];
                         if (tr) v.y = -v.y;
                         rho_out[((int64_t)gs * P + p) * ldr + m] = v;
@@ -635,13 +746,13 @@ const Config kConfigs[] = {
 
 constexpr size_t kMaxLds = 160 * 1024;  // the kernel declares no static LDS
 
-// Dynamic LDS of a launch: the state blocks (S = 1 adds two copies of the
-// partner's diagonal, N reals each), then the per-wave record sums and the
-// abort flag.
+// Dynamic LDS of a launch: the state blocks (S = 1: after two copies of the
+// partner's diagonal, room for 256 reals each), then the per-wave record sums
+// and the abort flag.
 size_t lds_blocks(const Config& c, int N, int P) {
+    (void)N;
     const size_t cb = c.dtype == FTWA_F64 ? 16 : 8;
-    const size_t b =
-        (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? (size_t)c.UNITS * 2 * N * (cb / 2) : 0);
+    const size_t b = (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? 2 * 256 * (cb / 2) : 0);
     return (b + 15) / 16 * 16;
 }
 size_t lds_tail(const Config& c) { return (size_t)(c.NTU * c.UNITS / 64) * 2 * c.S * 8 + 16; }

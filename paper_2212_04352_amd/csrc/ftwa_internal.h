@@ -33,11 +33,11 @@ struct DeviceTables {
                                // then the other's)
 };
 
-// Stencil descriptor of one element for the resident kernel (32 bytes), all
-// offsets in bytes within the LDS block of one spin.  Of every pair {i, j}
-// the LDS holds one orientation rho_ab (a ranks before b in a bandwidth-
-// reducing site order, so that few elements read a transposed neighbour);
-// the descriptor of the stored element rho_ij has
+// Stencil descriptor of one element for the resident kernel.  Of every pair
+// {i, j} the LDS holds one orientation rho_ab (a ranks before b in a
+// bandwidth-reducing site order, so that few elements read a transposed
+// neighbour).  Wide form (32 bytes, ResDesc), all offsets in bytes within the
+// LDS block of one spin; the descriptor of the stored element rho_ij has
 //   a.x, a.y, a.z: the column neighbours rho_ik, k in nb(j), ascending;
 //   b.x, b.y, b.z: the row neighbours rho_kj, k in nb(i), ascending;
 //     each = offset of the stored element | bit 31 set when the stored
@@ -45,11 +45,15 @@ struct DeviceTables {
 //     zero slot P;
 //   a.w: offset of the element itself (padding entries own the scratch slot
 //     P+1);
-//   b.w: offset of the diagonal value of site i | that of site j << 16: the
-//     values are
-//     the other spin's block (diagonal first, element (i,i) at slot i) or,
-//     for the spin-split kernels, in a compact real array in sublattice-major
-//     order (consecutive same-sublattice sites at consecutive words).
+//   b.w: offset of the diagonal value of site i | that of site j << 16 in the
+//     other spin's block (diagonal first, element (i,i) at slot i).
+// Compact form (16 bytes, uint4) of the spin-split kernels: 16-bit slot
+// numbers instead of byte offsets,
+//   x = c0 | c1 << 16, y = c2 | r0 << 16, z = r1 | r2 << 16 (bit 15 of a
+//     neighbour's field: read its conjugate),
+//   w = own slot | pos(i) << 16 | pos(j) << 24, pos = the site's place in the
+//     partner's diagonal, a real array in sublattice-major order
+//     (consecutive same-sublattice sites at consecutive words).
 struct ResDesc {
     uint4 a, b;
 };
@@ -67,7 +71,7 @@ struct ftwa_lattice_s {
     std::map<int, ftwa::DeviceTables> dev;  // by HIP device ordinal
     // resident-path descriptors padded per class to whole slots, by
     // (device, even slots, odd slots, element bytes and diagonal layout)
-    std::map<std::tuple<int, int64_t, int64_t, int>, ftwa::ResDesc*> padded;
+    std::map<std::tuple<int, int64_t, int64_t, int>, void*> padded;
     std::vector<uint32_t> class_order;      // a | b << 16 of the stored elements in LDS-slot order
     std::vector<int32_t> diag_pos;          // site -> sublattice-major diagonal position
 };
@@ -109,11 +113,12 @@ ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_mom
 ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
 // Descriptor table in LDS-slot order with the even class padded to
 // even_slots entries and the odd class to odd_slots entries; padding entries
-// own the scratch slot P+1 and read only the zero slot P.  compact_diag
-// selects the sublattice-major real diagonal array of the spin-split kernels.
-// Uploaded once per shape, element size and diagonal layout.
+// own the scratch slot P+1 and read only the zero slot P.  compact selects
+// the 16-byte form of the spin-split kernels (else the wide form with
+// offsets for elem_bytes-byte elements).  Uploaded once per shape, element
+// size and form.
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               int elem_bytes, bool compact_diag, const ResDesc** out);
+                               int elem_bytes, bool compact, const void** out);
 
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
@@ -180,7 +185,7 @@ struct ResidentInst {
     int64_t Mc;          // trajectories in the window (the record width)
     void* rho;           // instance state offset to the window's first trajectory
     int64_t ldr;         // instance n_traj
-    const ResDesc* desc; // padded_descriptors(lat, plan.even_slots, plan.odd_slots, bytes, S == 1)
+    const void* desc;    // padded_descriptors(lat, plan.even_slots, plan.odd_slots, bytes, S == 1)
     const uint32_t* ord; // DeviceTables::ord
     const int32_t* nb;   // DeviceTables::nb
     const int32_t* dpos; // DeviceTables::dpos

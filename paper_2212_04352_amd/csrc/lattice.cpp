@@ -382,7 +382,7 @@ bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* 
 }
 
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               int elem_bytes, bool compact_diag, const ResDesc** out) {
+                               int elem_bytes, bool compact, const void** out) {
     DeviceTables tab;
     ftwa_status st = device_tables(lat, &tab);
     if (st != FTWA_OK) return st;
@@ -394,11 +394,13 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
     if (even_slots < n_even || odd_slots < n_odd) return fail(FTWA_EINVAL, "padding too small");
     if ((P + 2) * (int64_t)elem_bytes >= ((int64_t)1 << 31))
         return fail(FTWA_EINVAL, "lattice too large for the resident layout");
+    if (compact && (P + 2 > 0x8000 || N > 256))
+        return fail(FTWA_EINVAL, "lattice too large for compact descriptors");
     int dev = 0;
     FTWA_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(lat->mu);
     const auto key =
-        std::make_tuple(dev, even_slots, odd_slots, elem_bytes * 2 + (compact_diag ? 1 : 0));
+        std::make_tuple(dev, even_slots, odd_slots, elem_bytes * 2 + (compact ? 1 : 0));
     auto it = lat->padded.find(key);
     if (it != lat->padded.end()) {
         *out = it->second;
@@ -414,62 +416,86 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
         slot[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)q;
         lower[(size_t)(packed_row(N, i) + (j - i))] = a > b;
     }
-    const uint32_t eb = (uint32_t)elem_bytes;
-    const uint32_t zero = (uint32_t)P * eb, scratch = (uint32_t)(P + 1) * eb;
-    // byte offset of element rho_xy as stored; bit 31: the slot holds rho_yx
-    // (read its conjugate)
-    auto field = [&](int x, int y) -> uint32_t {
+    // one element's stencil as slot numbers; conj: the slot holds the
+    // transpose of the element read
+    struct Ref {
+        uint32_t slot;
+        bool conj;
+    };
+    struct Sten {
+        Ref n[6];  // c0 c1 c2 r0 r1 r2
+        uint32_t own;
+        int i, j;
+    };
+    auto ref = [&](int x, int y) -> Ref {
         const int i = std::min(x, y), j = std::max(x, y);
         const size_t p = (size_t)(packed_row(N, i) + (j - i));
         const bool stored_xy = (x <= y) != (lower[p] != 0) || x == y;
-        return slot[p] * eb | (stored_xy ? 0u : 0x80000000u);
+        return Ref{slot[p], !stored_xy};
     };
-    auto make = [&](int i, int j) {
-        ResDesc d;
-        uint32_t col[3], row[3];
+    auto stencil = [&](int i, int j) {
+        Sten e;
         for (int n = 0; n < kMaxDeg; ++n) {
             const int kc = n < lat->deg[j] ? lat->nbr[(size_t)j * kMaxDeg + n] : -1;
             const int kr = n < lat->deg[i] ? lat->nbr[(size_t)i * kMaxDeg + n] : -1;
-            col[n] = kc < 0 ? zero : field(i, kc);
-            row[n] = kr < 0 ? zero : field(kr, j);
+            e.n[n] = kc < 0 ? Ref{(uint32_t)P, false} : ref(i, kc);
+            e.n[3 + n] = kr < 0 ? Ref{(uint32_t)P, false} : ref(kr, j);
         }
-        d.a.x = col[0];
-        d.a.y = col[1];
-        d.a.z = col[2];
-        d.a.w = field(i, j);
-        d.b.x = row[0];
-        d.b.y = row[1];
-        d.b.z = row[2];
-        if (compact_diag) {
-            const uint32_t rb = eb / 2;  // one real
-            d.b.w = ((uint32_t)lat->diag_pos[i] * rb) | (((uint32_t)lat->diag_pos[j] * rb) << 16);
-        } else {
-            d.b.w = ((uint32_t)i * eb) | (((uint32_t)j * eb) << 16);
-        }
-        return d;
+        e.own = ref(i, j).slot;
+        e.i = i;
+        e.j = j;
+        return e;
     };
-    ResDesc dummy;
-    dummy.a.x = dummy.a.y = dummy.a.z = zero;
-    dummy.a.w = scratch;
-    dummy.b.x = dummy.b.y = dummy.b.z = zero;
-    dummy.b.w = 0;
-    std::vector<ResDesc> tabp((size_t)(even_slots + odd_slots), dummy);
+    std::vector<Sten> all((size_t)(even_slots + odd_slots));
+    {
+        Sten dummy;  // padding: reads the zero slot, owns the scratch slot
+        for (int n = 0; n < 6; ++n) dummy.n[n] = Ref{(uint32_t)P, false};
+        dummy.own = (uint32_t)(P + 1);
+        dummy.i = dummy.j = -1;
+        std::fill(all.begin(), all.end(), dummy);
+    }
     for (int64_t q = 0; q < (int64_t)order.size(); ++q) {
         const int a = (int)(order[q] & 0xffffu), b = (int)(order[q] >> 16);
         const int64_t at = q < n_even ? q : even_slots + (q - n_even);
-        const ResDesc d = make(a, b);
+        const Sten e = stencil(a, b);
         // past the leading groups no neighbour is a transpose (the kernel
         // reads those elements without the conjugation flags)
         const bool general = q < n_even ? q < tab.n_gen_even : q - n_even < tab.n_gen_odd;
-        const uint32_t flags = d.a.x | d.a.y | d.a.z | d.a.w | d.b.x | d.b.y | d.b.z;
-        if (!general && (flags & 0x80000000u))
+        bool any = false;
+        for (int n = 0; n < 6; ++n) any = any || e.n[n].conj;
+        if (!general && any)
             return fail(FTWA_ENOTSUP, "class order: transpose read outside the leading group");
-        if (d.a.w & 0x80000000u) return fail(FTWA_ENOTSUP, "class order: element not stored");
-        tabp[(size_t)at] = d;
+        if (e.own != (uint32_t)q) return fail(FTWA_ENOTSUP, "class order: element not stored");
+        all[(size_t)at] = e;
     }
-    ResDesc* d = nullptr;
-    FTWA_HIP_TRY(hipMalloc(&d, tabp.size() * sizeof(ResDesc)));
-    FTWA_HIP_TRY(hipMemcpy(d, tabp.data(), tabp.size() * sizeof(ResDesc), hipMemcpyHostToDevice));
+    void* d = nullptr;
+    if (compact) {
+        std::vector<uint4> tabp(all.size());
+        auto f = [](const Ref& r) { return r.slot | (r.conj ? 0x8000u : 0u); };
+        for (size_t k = 0; k < all.size(); ++k) {
+            const Sten& e = all[k];
+            const uint32_t pi = e.i < 0 ? 0u : (uint32_t)lat->diag_pos[e.i];
+            const uint32_t pj = e.j < 0 ? 0u : (uint32_t)lat->diag_pos[e.j];
+            tabp[k].x = f(e.n[0]) | f(e.n[1]) << 16;
+            tabp[k].y = f(e.n[2]) | f(e.n[3]) << 16;
+            tabp[k].z = f(e.n[4]) | f(e.n[5]) << 16;
+            tabp[k].w = e.own | pi << 16 | pj << 24;
+        }
+        FTWA_HIP_TRY(hipMalloc(&d, tabp.size() * sizeof(uint4)));
+        FTWA_HIP_TRY(hipMemcpy(d, tabp.data(), tabp.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    } else {
+        const uint32_t eb = (uint32_t)elem_bytes;
+        std::vector<ResDesc> tabp(all.size());
+        auto f = [&](const Ref& r) { return r.slot * eb | (r.conj ? 0x80000000u : 0u); };
+        for (size_t k = 0; k < all.size(); ++k) {
+            const Sten& e = all[k];
+            tabp[k].a = make_uint4(f(e.n[0]), f(e.n[1]), f(e.n[2]), e.own * eb);
+            tabp[k].b = make_uint4(f(e.n[3]), f(e.n[4]), f(e.n[5]), 0u);
+            if (e.i >= 0) tabp[k].b.w = ((uint32_t)e.i * eb) | (((uint32_t)e.j * eb) << 16);
+        }
+        FTWA_HIP_TRY(hipMalloc(&d, tabp.size() * sizeof(ResDesc)));
+        FTWA_HIP_TRY(hipMemcpy(d, tabp.data(), tabp.size() * sizeof(ResDesc), hipMemcpyHostToDevice));
+    }
     lat->padded[key] = d;
     *out = d;
     return FTWA_OK;
