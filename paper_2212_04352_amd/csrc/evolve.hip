@@ -47,6 +47,7 @@ struct LaunchDesc {                // one resident launch: a group in a pass
     int64_t n_items = 0;
     int64_t grid = 0;
     double work = 0;               // trajectory-steps
+    bool unit_hop = true;          // every instance has t = 1
 };
 
 struct GroupPlan {
@@ -230,6 +231,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 const int64_t per = resident_item_traj(g.config);
                 L.n_items += (Mc + per - 1) / per;
                 L.work += (double)Mc * n_steps;
+                if (inst[k].lat->t != 1.0) L.unit_hop = false;
                 ++L.n_entries;
             }
             entry += L.n_entries;
@@ -393,6 +395,7 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             L.error = resident_error_word(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1),
                                           ws + g.off_mb);
             L.cooperative = cooperative;
+            L.unit_hop = Ld.unit_hop;
             if ((st = timer.begin(stream)) != FTWA_OK) return st;
             if ((st = resident_launch(L, stream)) != FTWA_OK) return st;
             if ((st = timer.end(stream, 1, Ld.work)) != FTWA_OK) return st;

@@ -250,7 +250,7 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // plain (fma(1, v, s) and s + v round alike, so both forms give the same
 // bits).  The element's own value is read from LDS, or taken from `own`
 // (OWN_REG).
-template <typename T, bool OWN_REG, bool GEN>
+template <typename T, bool OWN_REG, bool GEN, bool T1>
 __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
                                                  const Stencil& e, T t, T U, cplx_t<T> own) {
     using C = cplx_t<T>;
@@ -280,6 +280,15 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
     const T di = *reinterpret_cast<const T*>(Yd + e.di);
     const T dj = *reinterpret_cast<const T*>(Yd + e.dj);
     const T a = U * (di - dj);
+    if constexpr (T1) {
+        // t = 1: t * x is x exactly, the hopping sums enter unscaled
+        cplx_t<T> f;
+        const T gr = fma_rn<T>(a, rho.x, col.x - row.x);
+        const T gi = fma_rn<T>(a, rho.y, col.y - row.y);
+        f.x = -gi;
+        f.y = gr;
+        return f;
+    }
     return rhs_element<T>(col, row, rho, t, a);
 }
 
@@ -288,12 +297,12 @@ __device__ __forceinline__ uint32_t own_off(const ResDesc& d) { return d.a.w; }
 __device__ __forceinline__ uint32_t own_off(const uint4& w) { return lo16x8(w.w); }
 
 // The same with the variant chosen by a (compile-time) slot condition.
-template <typename T, bool OWN_REG, typename DT>
+template <typename T, bool OWN_REG, bool T1, typename DT>
 __device__ __forceinline__ cplx_t<T> element_rhs_sel(bool gen, const unsigned char* Yb,
                                                      const unsigned char* Yd, const DT& d,
                                                      T t, T U, cplx_t<T> own) {
-    return gen ? element_rhs<T, OWN_REG, true>(Yb, Yd, decode<true>(d), t, U, own)
-               : element_rhs<T, OWN_REG, false>(Yb, Yd, decode<false>(d), t, U, own);
+    return gen ? element_rhs<T, OWN_REG, true, T1>(Yb, Yd, decode<true>(d), t, U, own)
+               : element_rhs<T, OWN_REG, false, T1>(Yb, Yd, decode<false>(d), t, U, own);
 }
 
 // One Runge-Kutta stage update of an element from its slope k:
@@ -343,7 +352,8 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
     return (unsigned char*)(__attribute__((address_space(3))) unsigned char*)(uintptr_t)a;
 }
 
-template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
+// T1: every instance of the launch has t = 1 (the usual unit of energy).
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1>
 __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     // descriptor form: compact for the spin split, wide otherwise
@@ -588,9 +598,9 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         // is y itself, so nothing is held across steps
                         const C own = STAGE == 1 ? y[s][u] : hold[s][u];
                         *reinterpret_cast<C*>(Yb + own_off(d)) = own;
-                        k = element_rhs_sel<T, true>(u < GE, Yb, dcur, d, tw, Uw, own);
+                        k = element_rhs_sel<T, true, T1>(u < GE, Yb, dcur, d, tw, Uw, own);
                     } else {
-                        k = element_rhs_sel<T, false>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
+                        k = element_rhs_sel<T, false, T1>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
                                                       tw, Uw, hold[s][u]);
                     }
                     hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
@@ -627,8 +637,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     // stage 1 reads the element's own value from y (the
                     // stage input of a full step is its base point)
                     const C k = STAGE == 1
-                        ? element_rhs_sel<T, true>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u])
-                        : element_rhs_sel<T, false>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u]);
+                        ? element_rhs_sel<T, true, T1>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u])
+                        : element_rhs_sel<T, false, T1>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u]);
                     *reinterpret_cast<C*>(Yb + own_off(d)) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
@@ -717,15 +727,26 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 // ---------------------------------------------------------------- configurations
 // GE, GO: the leading even and odd slots that take the general path (the
 // elements that read a transpose must fit in them).
+// fn_t1: the variant for launches whose instances all have t = 1 (FP32).
 struct Config {
     ftwa_dtype dtype;
     int S, NTU, UNITS, UE, UO, GE, GO;
     const void* fn;
+    const void* fn_t1;
 };
 
-#define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO, GE, GO)          \
-    Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                          \
-           (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO>}
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
+constexpr const void* unit_hop_fn() {
+    if constexpr (std::is_same<T, float>::value)
+        return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, true>;
+    else
+        return nullptr;
+}
+
+#define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO, GE, GO)                    \
+    Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                                    \
+           (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
+           unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
 
 // Ordered by preference; the first one that fits a lattice is used.
 const Config kConfigs[] = {
@@ -812,6 +833,9 @@ ftwa_status resident_prepare(int config, size_t lds) {
     (void)lds;  // the limit is raised to the whole LDS once; launches use less
     FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    if (kConfigs[config].fn_t1)
+        FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn_t1,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
     return FTWA_OK;
 }
 
@@ -875,6 +899,7 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     A.error = L.error;
     void* args[] = {&A};
     const int64_t grid = L.grid;
+    const void* fn = L.unit_hop && c.fn_t1 ? c.fn_t1 : c.fn;
     if (c.S == 1) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,
         // no memset node)
@@ -886,14 +911,14 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
         // it (not available under graph capture, where the bounded waits
         // report a partner that never came)
         if (L.cooperative)
-            FTWA_HIP_TRY(hipLaunchCooperativeKernel(c.fn, dim3((unsigned)grid),
+            FTWA_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3((unsigned)grid),
                                                     dim3(c.NTU * c.UNITS), args,
                                                     (unsigned)L.lds, stream));
         else
-            FTWA_HIP_TRY(hipLaunchKernel(c.fn, dim3((unsigned)grid), dim3(c.NTU * c.UNITS), args,
+            FTWA_HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(c.NTU * c.UNITS), args,
                                          (unsigned)L.lds, stream));
     } else {
-        FTWA_HIP_TRY(hipLaunchKernel(c.fn, dim3((unsigned)grid), dim3(c.NTU * c.UNITS), args,
+        FTWA_HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(c.NTU * c.UNITS), args,
                                      (unsigned)L.lds, stream));
     }
     return FTWA_OK;

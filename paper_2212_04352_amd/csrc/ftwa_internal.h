@@ -208,6 +208,7 @@ struct ResidentLaunch {
     void* mailbox;              // resident_mailbox_bytes(config, Nmax, n_items) of scratch
     int* error;                 // resident_error_word(...) or NULL
     bool cooperative;           // false under graph capture
+    bool unit_hop;              // every instance of the launch has t = 1
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,

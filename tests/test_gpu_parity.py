@@ -146,27 +146,32 @@ def test_errors_are_reported(ft):
 
 
 # ----------------------------------------------------------------- resident path
-@pytest.mark.parametrize("dtype,kind,a,b,U,M,steps,config", [
-    ("f64", "torus", 2, 3, 3.3, 130, 200, -1),    # 16 trajectories per workgroup, ragged
-    ("f32", "torus", 2, 3, 3.3, 130, 200, -1),
-    ("f64", "hex", 2, 0, 1.7, 33, 40, -1),        # degree-2 edge sites
-    ("f32", "hex", 2, 0, 1.7, 33, 40, -1),
-    ("f64", "torus", 3, 9, 3.3, 70, 60, -1),      # 54 sites, 3 trajectories per workgroup
-    ("f32", "torus", 3, 9, 3.3, 70, 60, -1),
-    ("f64", "hex", 4, 0, 2.0, 10, 20, -1),        # 96 sites, one trajectory per workgroup
-    ("f32", "hex", 4, 0, 2.0, 10, 20, -1),
-    ("f32", "hex", 5, 0, 3.3, 9, 20, -1),         # 150 sites: spin-split workgroup pairs
-    ("f32", "armchair", 10, 20, 3.3, 12, 12, -1),  # 198-site flake, spin split
-    ("f32", "armchair", 10, 20, 3.3, 12, 12, 10),  # alternative tile: 1024 threads per spin
-    ("f32", "armchair", 10, 20, 3.3, 12, 12, 11),  # alternative tile: 512 threads per spin
-    ("f32", "hex", 4, 0, 2.0, 10, 20, 9),          # spin split with padding-heavy slots
+@pytest.mark.parametrize("dtype,kind,a,b,U,M,steps,config,t", [
+    ("f64", "torus", 2, 3, 3.3, 130, 200, -1, 1.0),    # 16 trajectories per workgroup, ragged
+    ("f32", "torus", 2, 3, 3.3, 130, 200, -1, 1.0),
+    ("f64", "hex", 2, 0, 1.7, 33, 40, -1, 1.0),        # degree-2 edge sites
+    ("f32", "hex", 2, 0, 1.7, 33, 40, -1, 1.0),
+    ("f64", "torus", 3, 9, 3.3, 70, 60, -1, 1.0),      # 54 sites, 3 trajectories per workgroup
+    ("f32", "torus", 3, 9, 3.3, 70, 60, -1, 1.0),
+    ("f64", "hex", 4, 0, 2.0, 10, 20, -1, 1.0),        # 96 sites, one trajectory per workgroup
+    ("f32", "hex", 4, 0, 2.0, 10, 20, -1, 1.0),
+    ("f32", "hex", 5, 0, 3.3, 9, 20, -1, 1.0),         # 150 sites: spin-split workgroup pairs
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, -1, 1.0),  # 198-site flake, spin split
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, 10, 1.0),  # alternative tile: 1024 threads per spin
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, 11, 1.0),  # alternative tile: 512 threads per spin
+    ("f32", "hex", 4, 0, 2.0, 10, 20, 9, 1.0),          # spin split with padding-heavy slots
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, 12, 1.0),  # spin split, every slot general
+    ("f64", "torus", 2, 3, 3.3, 130, 200, -1, 0.6),     # hopping t != 1 (general kernels)
+    ("f32", "hex", 2, 0, 1.7, 33, 40, -1, 1.3),
+    ("f32", "armchair", 10, 20, 3.3, 12, 12, -1, 0.8),
 ])
-def test_evolve_resident_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, U, M, steps, config):
+def test_evolve_resident_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, U, M, steps, config,
+                                                 t):
     import torch
-    olat = orc.Lattice(kind, a, b)
+    olat = orc.Lattice(kind, a, b, t)
     n0 = orc.fock_start(olat, "random", 3)
     rho0 = orc.sample(olat, n0, 3, M)
-    lat = ft.Lattice(kind, a, b)
+    lat = ft.Lattice(kind, a, b, t)
     prob = ft.Problem.allocate(lat, U, M, n0, dtype)
     cdt = np.complex128 if dtype == "f64" else np.complex64
     prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
