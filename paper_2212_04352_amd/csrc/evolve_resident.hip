@@ -9,12 +9,14 @@
 // Layout on chip.  A workgroup holds UNITS "units"; a unit is one trajectory
 // (S = 2: both spin blocks) or one spin block of one trajectory (S = 1, the
 // partner workgroup holds the other spin).  The current Runge-Kutta stage
-// input Y of a unit lives in LDS, one block of P + 2 complex slots per spin:
-// the packed elements in "class order" (the even class -- diagonal first,
-// element (i,i) at slot i -- then the odd class, see below), slot P always
-// zero (stands in for missing neighbours), slot P+1 scratch owned by padding
-// elements.  The base point y and the accumulator acc of every element live
-// in the registers of the thread that owns it.  The U term reads the other
+// input Y of a unit lives in LDS, one block of complex slots per spin: the
+// P packed elements in "class order" (the even class -- diagonal first,
+// element (i,i) at slot i -- then the odd class, see below), then slots that
+// always hold zero (they stand in for missing neighbours: one, or for the
+// spin split 32, one per LDS bank pair, so that the zero reads of a 32-lane
+// group can avoid the banks its other lanes read), then a scratch slot owned
+// by padding elements.  The base point y and the accumulator acc of every
+// element live in the registers of the thread that owns it.  The U term reads the other
 // spin's diagonal from slots 0..N-1 of its block (S = 2) or from a copy of
 // the partner's diagonal placed before the block (S = 1; N reals ordered by
 // sublattice, so the diagonal values read by a wave's consecutive
@@ -363,6 +365,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
     constexpr uint32_t kDiagCopy = 256 * TB;  // S = 1: one copy of the partner's diagonal
+    constexpr int kTail = S == 1 ? 33 : 2;    // slots after the elements: zero(s), scratch
     extern __shared__ __align__(16) unsigned char smem[];  // dynamic LDS, at address 0
     (void)smem;
     const int tid0 = threadIdx.x;
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const ResidentInst& E = A.table[ent];
         const int N = E.N;
         const int P = E.P;
-        const int Pb = P + 2;  // per block: P elements, the zero slot, the scratch slot
+        const int Pb = P + kTail;  // per block: P elements, the zero slot(s), the scratch slot
         // LDS: UNITS x S blocks of Pb complex slots; S = 1: two copies of the
         // partner's diagonal (N reals, sublattice-major, kDiagCopy bytes
         // apart) first, then the block.  The launch has no static LDS, so the
@@ -477,12 +480,13 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 acc[s][u] = v;
                 if (u < UE) hold[s][u] = v;  // S = 1 writes held values in phase 1
             }
-            if (t == 0) {
+            // the zero slot(s) and the scratch slot after the elements (the
+            // compact descriptors of the spin split use 32 zero slots)
+            if (t < kTail) {
                 C z;
                 z.x = 0;
                 z.y = 0;
-                reinterpret_cast<C*>(Yunit + s * Pb * CB)[P] = z;
-                reinterpret_cast<C*>(Yunit + s * Pb * CB)[P + 1] = z;
+                reinterpret_cast<C*>(Yunit + s * Pb * CB)[P + t] = z;
             }
         }
         const int32_t* const dpos = reinterpret_cast<const int32_t*>(uniform64((uint64_t)E.dpos));
@@ -773,7 +777,8 @@ constexpr size_t kMaxLds = 160 * 1024;  // the kernel declares no static LDS
 size_t lds_blocks(const Config& c, int N, int P) {
     (void)N;
     const size_t cb = c.dtype == FTWA_F64 ? 16 : 8;
-    const size_t b = (size_t)c.UNITS * c.S * (P + 2) * cb + (c.S == 1 ? 2 * 256 * (cb / 2) : 0);
+    const size_t tail = c.S == 1 ? 33 : 2;  // zero slot(s) and scratch slot
+    const size_t b = (size_t)c.UNITS * c.S * (P + tail) * cb + (c.S == 1 ? 2 * 256 * (cb / 2) : 0);
     return (b + 15) / 16 * 16;
 }
 size_t lds_tail(const Config& c) { return (size_t)(c.NTU * c.UNITS / 64) * 2 * c.S * 8 + 16; }
@@ -786,7 +791,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
     if (!tab.bipartite) return false;
     const int P = (int)packed_count(N);
     const int n_even = (int)tab.n_even, n_odd = P - n_even;
-    if (P + 2 > 0x7fff) return false;
+    if (P + 33 > 0x7fff) return false;
     const int n_cfg = (int)(sizeof(kConfigs) / sizeof(kConfigs[0]));
     for (int k = 0; k < n_cfg; ++k) {
         if (force_config >= 0 && k != force_config) continue;

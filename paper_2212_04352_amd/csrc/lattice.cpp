@@ -394,7 +394,7 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
     if (even_slots < n_even || odd_slots < n_odd) return fail(FTWA_EINVAL, "padding too small");
     if ((P + 2) * (int64_t)elem_bytes >= ((int64_t)1 << 31))
         return fail(FTWA_EINVAL, "lattice too large for the resident layout");
-    if (compact && (P + 2 > 0x8000 || N > 256))
+    if (compact && (P + 33 > 0x8000 || N > 256))
         return fail(FTWA_EINVAL, "lattice too large for compact descriptors");
     int dev = 0;
     FTWA_HIP_TRY(hipGetDevice(&dev));
@@ -470,6 +470,26 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
     }
     void* d = nullptr;
     if (compact) {
+        // 32 zero slots P..P+31 (scratch P+32): the lanes of one 32-lane
+        // group that read a missing neighbour read the zero slot whose LDS
+        // bank no other lane of the group reads for that field, so the zero
+        // reads cost no bank conflict
+        for (int64_t c0 = 0; c0 < even_slots + odd_slots; c0 += 32) {
+            const int64_t c1 = std::min<int64_t>(c0 + 32, c0 < even_slots ? even_slots
+                                                                          : even_slots + odd_slots);
+            for (int n = 0; n < 6; ++n) {
+                uint32_t used = 0;
+                for (int64_t k = c0; k < c1; ++k)
+                    if (all[(size_t)k].n[n].slot != (uint32_t)P) used |= 1u << (all[(size_t)k].n[n].slot % 32);
+                uint32_t z = (uint32_t)P;
+                for (uint32_t r = 0; r < 32; ++r)
+                    if (!(used >> ((P + r) % 32) & 1u)) { z = (uint32_t)P + r; break; }
+                for (int64_t k = c0; k < c1; ++k)
+                    if (all[(size_t)k].n[n].slot == (uint32_t)P) all[(size_t)k].n[n].slot = z;
+            }
+            for (int64_t k = c0; k < c1; ++k)
+                if (all[(size_t)k].own == (uint32_t)(P + 1)) all[(size_t)k].own = (uint32_t)(P + 32);
+        }
         std::vector<uint4> tabp(all.size());
         auto f = [](const Ref& r) { return r.slot | (r.conj ? 0x8000u : 0u); };
         for (size_t k = 0; k < all.size(); ++k) {
