@@ -49,7 +49,7 @@
 // barrier the held even values are written.  Only half of the next-stage
 // values is ever held, which is what lets the 198-site FP32 spin block live in
 // one CU (157.6 KB of LDS, y/acc in VGPRs).  Each element's descriptor is
-// loaded one element ahead; every stage is compiled separately (no
+// loaded one or two elements ahead; every stage is compiled separately (no
 // per-element tests of the stage number).
 //
 // Element slots.  Thread t of a unit owns element t + NTU*u of the even class
@@ -581,18 +581,24 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             const unsigned char* dcur = dpart + ((STAGE - 1) & 1) * kDiagCopy;
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
-            // registers); the next slot's descriptor is loaded one slot ahead.
+            // registers); descriptors are loaded KP slots ahead.
             // S = 1: the held values of the previous stage are written to LDS
             // here (nothing reads an even element in phase 1: its own value
             // comes from the register, the diagonal of the U term from the
             // partner's copy), which saves a barrier per stage.
             const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)desc, (short)0, (int)((kEvenPad + NTU * UO) * sizeof(DT)), 0x00020000);
-            DT dn = slot_desc_buf<DT>(drs, 0, toff);
+            // descriptors in flight: two for the spin split (the L2 latency
+            // exceeds one element's time), one where registers are scarcer
+            constexpr int KP = S == 1 && NTU * UNITS <= 768 ? 2 : 1;
+            auto entry_of = [](int v) { return v < UE ? NTU * v : kEvenPad + NTU * (v - UE); };
+            DT dq[KP];
+#pragma unroll
+            for (int v = 0; v < KP; ++v) dq[v] = slot_desc_buf<DT>(drs, entry_of(v < UE + UO ? v : UE + UO - 1), toff);
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
-                const DT d = dn;
-                dn = slot_desc_buf<DT>(drs, u + 1 < UE ? NTU * (u + 1) : kEvenPad, toff);
+                const DT d = dq[u % KP];
+                if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<DT>(drs, entry_of(u + KP), toff);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
@@ -632,8 +638,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             // ---------------- phase 2: odd elements (written straight to LDS)
 #pragma unroll
             for (int u = UE; u < UE + UO; ++u) {
-                const DT d = dn;
-                if (u + 1 < UE + UO) dn = slot_desc_buf<DT>(drs, kEvenPad + NTU * (u + 1 - UE), toff);
+                const DT d = dq[u % KP];
+                if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<DT>(drs, entry_of(u + KP), toff);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
