@@ -313,7 +313,25 @@ struct AdjointLayout {
     int64_t Mc = 0, n_ckpt = 0, L = 0;
     size_t state = 0;
     size_t off_ckpt = 0, off_seg = 0, off_w3 = 0, off_lam = 0, off_part = 0, total = 0;
+    // forward checkpoints and segment states by resident runs that store their
+    // state (when a resident configuration fits): their workspace and moments
+    bool resident = false;
+    size_t off_ev = 0, ev_bytes = 0, off_s1 = 0, off_s2 = 0;
 };
+
+// The instance of a stored-state run over Mc trajectories starting at `rho`
+// (leading dimension Mc), moments into the layout's scratch.
+ftwa_instance stored_run_instance(const ftwa_instance& in, int64_t Mc, void* rho, char* ws,
+                                  const AdjointLayout& a) {
+    ftwa_instance q = in;
+    q.n_traj = Mc;
+    q.traj_offset = 0;
+    q.rho = rho;
+    q.S1 = ws ? reinterpret_cast<double*>(ws + a.off_s1) : nullptr;
+    q.S2 = ws ? reinterpret_cast<double*>(ws + a.off_s2) : nullptr;
+    q.inv = nullptr;
+    return q;
+}
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -341,6 +359,23 @@ ftwa_status plan_adjoint(const ftwa_instance* inst, int64_t n_steps, int record_
     a.off_w3 = off;   off = align_up(off + 3 * a.state);   // Y2, Y3, Y4 / acc, ya, yb
     a.off_lam = off;  off = align_up(off + 4 * a.state);   // lam, Lam, a (ping-pong)
     a.off_part = off; off = align_up(off + (size_t)g.n_elem_chunks * 2 * a.Mc * sizeof(double));
+    // stored-state runs: the forward (records every ckpt_every steps) and
+    // the longest segment (records every step)
+    const int64_t f_steps = (a.n_ckpt - 1) * ckpt_every, s_steps = a.L - 1;
+    const ftwa_instance q = stored_run_instance(*inst, a.Mc, nullptr, nullptr, a);
+    size_t bf = 0, bs = 0;
+    if (evolve_stored(q, 0.01, std::max<int64_t>(f_steps, 1), ckpt_every, dtype, nullptr, 0,
+                      nullptr, &bf, nullptr) == FTWA_OK &&
+        evolve_stored(q, 0.01, std::max<int64_t>(s_steps, 1), 1, dtype, nullptr, 0, nullptr, &bs,
+                      nullptr) == FTWA_OK) {
+        a.resident = true;
+        a.ev_bytes = std::max(bf, bs);
+        const int64_t n_rec = std::max<int64_t>({a.n_ckpt, a.L, 2});
+        const int D = 2 * N;
+        a.off_ev = off; off = align_up(off + a.ev_bytes);
+        a.off_s1 = off; off = align_up(off + (size_t)n_rec * D * sizeof(double));
+        a.off_s2 = off; off = align_up(off + (size_t)n_rec * s2_count(D) * sizeof(double));
+    }
     a.total = off;
     *out = a;
     return FTWA_OK;
@@ -391,7 +426,26 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
 
         // ---- forward: checkpoints every ckpt_every steps
         ftwa_status st;
-        for (int64_t k = 0; k < lay.n_ckpt; ++k) {
+        if (lay.resident) {
+            // one resident run from a working copy of rho(0), storing the
+            // state at every checkpoint
+            hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc, rho0, in.n_traj,
+                               st_at(lay.off_ckpt, 0), Mc);
+            FTWA_LAUNCH_CHECK("copy_state_kernel");
+            if (lay.n_ckpt > 1) {
+                C* work = st_at(lay.off_seg, 0);
+                hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc,
+                                   (const C*)st_at(lay.off_ckpt, 0), Mc, work, Mc);
+                FTWA_LAUNCH_CHECK("copy_state_kernel");
+                const ftwa_instance q = stored_run_instance(in, Mc, work, ws, lay);
+                size_t b = lay.ev_bytes;
+                if ((st = evolve_stored(q, dt, (lay.n_ckpt - 1) * ckpt_every, ckpt_every, dtype,
+                                        st_at(lay.off_ckpt, 1), (int64_t)state, ws + lay.off_ev,
+                                        &b, stream)) != FTWA_OK)
+                    return st;
+            }
+        }
+        for (int64_t k = 0; !lay.resident && k < lay.n_ckpt; ++k) {
             C* ck = st_at(lay.off_ckpt, k);
             if (k == 0) {
                 hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc, rho0,
@@ -437,7 +491,18 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
             hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc,
                                (const C*)st_at(lay.off_ckpt, k), Mc, st_at(lay.off_seg, 0), Mc);
             FTWA_LAUNCH_CHECK("copy_state_kernel");
-            for (int64_t n = 1; n < L; ++n) {
+            if (lay.resident && L > 1) {
+                // one resident run from a working copy (Y2 is free here)
+                hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc,
+                                   (const C*)st_at(lay.off_ckpt, k), Mc, Y2, Mc);
+                FTWA_LAUNCH_CHECK("copy_state_kernel");
+                const ftwa_instance q = stored_run_instance(in, Mc, Y2, ws, lay);
+                size_t b = lay.ev_bytes;
+                if ((st = evolve_stored(q, dt, L - 1, 1, dtype, st_at(lay.off_seg, 1),
+                                        (int64_t)state, ws + lay.off_ev, &b, stream)) != FTWA_OK)
+                    return st;
+            }
+            for (int64_t n = 1; !lay.resident && n < L; ++n) {
                 hipLaunchKernelGGL(copy_state_kernel<T>, cgrid, blk, 0, stream, Mc,
                                    (const C*)st_at(lay.off_seg, n - 1), Mc, st_at(lay.off_seg, n),
                                    Mc);

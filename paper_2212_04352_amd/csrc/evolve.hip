@@ -75,6 +75,9 @@ struct Plan {
     size_t r_table = 0, r_mom = 0, r_total = 0;
     int64_t n_table = 0;
     size_t total = 0;
+    // internal runs only (one instance): its state is stored at every record
+    void* dump = nullptr;
+    int64_t dump_stride = 0;
 };
 
 void window(const Plan& p, const ftwa_instance& in, int k, int j, int64_t* m0, int64_t* Mc) {
@@ -288,6 +291,9 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 e.inv_parts = inst[k].inv ? reinterpret_cast<double*>(ws + ip.off_inv) : nullptr;
                 e.item0 = item0;
                 item0 += (Mc + per - 1) / per;
+                e.dump = p.dump ? static_cast<char*>(p.dump) + (size_t)m0 * cplx_bytes(p.dtype)
+                                : nullptr;
+                e.dump_stride = p.dump_stride;
                 table.push_back(e);
             }
         }
@@ -396,6 +402,7 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                                           ws + g.off_mb);
             L.cooperative = cooperative;
             L.unit_hop = Ld.unit_hop;
+            L.dumps = p.dump != nullptr;
             if ((st = timer.begin(stream)) != FTWA_OK) return st;
             if ((st = resident_launch(L, stream)) != FTWA_OK) return st;
             if ((st = timer.end(stream, 1, Ld.work)) != FTWA_OK) return st;
@@ -461,6 +468,36 @@ int current_device() {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- stored-state runs
+// Resident integration of one instance (rho updated in place) that also
+// stores the state at every record: record r >= 1 (after r * record_every
+// steps) goes to dump + (r - 1) * dump_stride elements, in the layout of rho
+// (leading dimension in.n_traj).  For the adjoint's checkpoints and segment
+// states.  With ws == NULL only *bytes is set; fails with FTWA_ENOTSUP when
+// no resident configuration fits.
+ftwa_status evolve_stored(const ftwa_instance& in, double dt, int64_t n_steps, int record_every,
+                          ftwa_dtype dtype, void* dump, int64_t dump_stride, char* ws,
+                          size_t* bytes, hipStream_t stream) {
+    ftwa_tuning tune;
+    std::memset(&tune, 0, sizeof(tune));
+    tune.path = FTWA_PATH_RESIDENT;
+    tune.resident_config = -1;
+    Plan plan;
+    ftwa_status st = plan_evolve(&in, 1, dt, n_steps, record_every, dtype, &tune, &plan);
+    if (st != FTWA_OK) return st;
+    if (!ws) {
+        *bytes = plan.total;
+        return FTWA_OK;
+    }
+    if (*bytes < plan.total) return fail(FTWA_EINVAL, "stored-state run: workspace too small");
+    plan.dump = dump;
+    plan.dump_stride = dump_stride;
+    if ((st = prepare(plan, &in, ws, stream)) != FTWA_OK) return st;
+    KernelTimer off(false);
+    if ((st = execute(plan, &in, ws, stream, off, true)) != FTWA_OK) return st;
+    return finish(plan, &in, ws, stream);
+}
 
 bool tuned_config(int N, int64_t shape, ftwa_dtype dtype, int* config) {
     std::lock_guard<std::mutex> lock(g_tune_mu);

@@ -435,13 +435,14 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         gdesc_t desc = (gdesc_t)uniform64((uint64_t)E.desc);
         // LDS byte offset (within its spin block) of the element in
         // descriptor entry e
-        auto own_of = [&](int e) -> uint32_t {
+        auto own_at = [&](gdesc_t dt, int e) -> uint32_t {
             if constexpr (S == 1)
-                return (reinterpret_cast<const uint4*>((uint64_t)desc)[e].w & 0xffffu) *
+                return (reinterpret_cast<const uint4*>((uint64_t)dt)[e].w & 0xffffu) *
                        (uint32_t)CB;
             else
-                return desc[e].a.w;
+                return dt[e].a.w;
         };
+        auto own_of = [&](int e) -> uint32_t { return own_at(desc, e); };
         __syncthreads();  // the previous item is done with LDS and `red`
 
         // packed index of the element a descriptor describes (its LDS slot
@@ -700,37 +701,52 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             return true;
         };
 
-        for (int64_t step = 1; step <= A.n_steps; ++step) {
-            if (!run_stage(stage_c<1>{})) return;
-            if (!run_stage(stage_c<2>{})) return;
-            if (!run_stage(stage_c<3>{})) return;
-            if (!run_stage(stage_c<4>{})) return;
-            if (step % A.record_every == 0) record(step / A.record_every);
-        }
-
-        // ---- final state back to HBM (addresses recomputed, not kept alive
-        // across the time loop)
-        if (active) {
-            C* rho_out = rho;
-            desc = launder(desc);
-            __asm__ volatile("" : "+s"(rho_out)::"memory");
+        // the state y of every element to `out` (same layout as rho; stored
+        // elements are conjugated back to the upper triangle).  Addresses are
+        // recomputed, not kept alive across the time loop.
+        auto store_state = [&](C* out) {
+            const gdesc_t dl = launder(desc);  // a local copy: desc itself stays uniform
+            out = reinterpret_cast<C*>(uniform64((uint64_t)out));
+            if (!active) return;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int gs = spin0 + s;
 #pragma unroll
                 for (int u = 0; u < UE + UO; ++u) {
                     const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
-                    const uint32_t own = own_of(e);
+                    const uint32_t own = own_at(dl, e);
                     if (own < (uint32_t)P * CB) {
                         bool tr;
                         const int64_t p = packed_of(own, tr);
                         C v = y[s][u];
                         if (tr) v.y = -v.y;
-                        rho_out[((int64_t)gs * P + p) * ldr + m] = v;
+                        out[((int64_t)gs * P + p) * ldr + m] = v;
                     }
                 }
             }
+        };
+
+        for (int64_t step = 1; step <= A.n_steps; ++step) {
+            if (!run_stage(stage_c<1>{})) return;
+            if (!run_stage(stage_c<2>{})) return;
+            if (!run_stage(stage_c<3>{})) return;
+            if (!run_stage(stage_c<4>{})) return;
+            if (step % A.record_every == 0) {
+                const int64_t r = step / A.record_every;
+                record(r);
+                // optional stored state at every record (the adjoint's
+                // checkpoints and segment states; general kernels only, so
+                // that the unit-hopping variant's time loop carries no such
+                // code)
+                if constexpr (!T1) {
+                    C* const dump = reinterpret_cast<C*>(uniform64((uint64_t)E.dump));
+                    if (dump) store_state(dump + (r - 1) * E.dump_stride);
+                }
+            }
         }
+
+        // ---- final state back to HBM
+        store_state(rho);
     }
 }
 
@@ -910,7 +926,7 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     A.error = L.error;
     void* args[] = {&A};
     const int64_t grid = L.grid;
-    const void* fn = L.unit_hop && c.fn_t1 ? c.fn_t1 : c.fn;
+    const void* fn = L.unit_hop && !L.dumps && c.fn_t1 ? c.fn_t1 : c.fn;
     if (c.S == 1) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,
         // no memset node)

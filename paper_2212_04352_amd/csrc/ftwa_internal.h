@@ -193,6 +193,10 @@ struct ResidentInst {
     double* X;           // [n_rec][2N][Mc]
     double* inv_parts;   // NULL or [n_rec][2 spins][hop, frob][Mc]
     int64_t item0;       // first item of this entry (items of earlier entries before it)
+    void* dump;          // NULL, or the state at record r >= 1 is stored at
+                         // dump + (r - 1) * dump_stride elements (same layout and window
+                         // offset as rho)
+    int64_t dump_stride;
 };
 struct ResidentLaunch {
     int config;
@@ -209,6 +213,7 @@ struct ResidentLaunch {
     int* error;                 // resident_error_word(...) or NULL
     bool cooperative;           // false under graph capture
     bool unit_hop;              // every instance of the launch has t = 1
+    bool dumps;                 // an entry stores its state at records (ResidentInst::dump)
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
@@ -227,6 +232,11 @@ ftwa_status resident_check_error(const int* err, hipStream_t stream, bool* timed
 
 // Configurations chosen by ftwa_autotune, per (device, N, even-class size, dtype).
 bool tuned_config(int N, int64_t shape, ftwa_dtype dtype, int* config);
+// Resident run of one instance that stores its state at every record
+// (evolve.hip; ws == NULL: workspace size query into *bytes).
+ftwa_status evolve_stored(const ftwa_instance& in, double dt, int64_t n_steps, int record_every,
+                          ftwa_dtype dtype, void* dump, int64_t dump_stride, char* ws,
+                          size_t* bytes, hipStream_t stream);
 void set_tuned_config(int N, int64_t shape, ftwa_dtype dtype, int config);
 
 // Brackets launches of the dominant kernel with HIP events on one stream and
