@@ -154,6 +154,31 @@ __global__ __launch_bounds__(256) void stage_input_kernel(StageInArgs<T> A) {
     }
 }
 
+// The diagonal coupling term of the transposed right-hand side, one thread
+// per (spin s, site i, trajectory): R[s][i][m] = sum_{k != i} Im(conj(a_ik) Y_ik)
+// over the other spin's row i (ascending k), for the diagonal elements of
+// the following vjp_kernel launch.
+template <typename T>
+__global__ __launch_bounds__(256) void diag_coupling_kernel(int N, int64_t P, int64_t Mc,
+                                                            const cplx_t<T>* __restrict__ a,
+                                                            const cplx_t<T>* __restrict__ Y,
+                                                            T* __restrict__ R) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Mc) return;
+    const int si = blockIdx.y;
+    const int s = si >= N ? 1 : 0, i = si - s * N;
+    const cplx_t<T>* Ao = a + (int64_t)(1 - s) * P * Mc;
+    const cplx_t<T>* Yo = Y + (int64_t)(1 - s) * P * Mc;
+    T acc = 0;
+    for (int k = 0; k < N; ++k) {
+        if (k == i) continue;
+        const cplx_t<T> av = load_el<T>(Ao, Mc, N, i, k, m);
+        const cplx_t<T> yv = load_el<T>(Yo, Mc, N, i, k, m);
+        acc = acc + (av.x * yv.y - av.y * yv.x);  // Im(conj(a) y)
+    }
+    R[(int64_t)si * Mc + m] = acc;
+}
+
 template <typename T> struct VjpArgs {
     int N;
     int64_t P, Mc;
@@ -165,6 +190,7 @@ template <typename T> struct VjpArgs {
     const cplx_t<T>* lam;  // cotangent of y+ (for the next a)
     cplx_t<T>* Lam;        // accumulating cotangent of y: Lam += mu_s
     cplx_t<T>* a_next;     // a_{s-1} = alpha lam + beta mu_s (NULL for s = 1)
+    const T* R;            // [2][N][Mc]: diag_coupling_kernel of (a, Y)
     T alpha, beta;
     double* partial;       // [n_elem_chunks][2][Mc]: dU, dt partial sums
     WaveGrid g;
@@ -198,14 +224,7 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs<T> A) {
         mu.y = -fl.y;
         if (i == j) {
             // dependence of the other block's equation on this diagonal
-            const cplx_t<T>* Ao = A.a + (int64_t)(1 - s) * A.P * Mc;
-            T acc = 0;
-            for (int k = 0; k < N; ++k) {
-                if (k == i) continue;
-                const cplx_t<T> av = load_el<T>(Ao, Mc, N, i, k, m);
-                const cplx_t<T> yv = load_el<T>(Yo, Mc, N, i, k, m);
-                acc = acc + (av.x * yv.y - av.y * yv.x);  // Im(conj(a) y)
-            }
+            const T acc = A.R[((int64_t)s * N + i) * Mc + m];
             mu.x = fma_rn<T>((T)(-2) * A.U, acc, mu.x);
         }
         // parameter partials in FP64
@@ -312,7 +331,7 @@ __global__ __launch_bounds__(256) void final_reduce_kernel(int N, int64_t P, int
 struct AdjointLayout {
     int64_t Mc = 0, n_ckpt = 0, L = 0;
     size_t state = 0;
-    size_t off_ckpt = 0, off_seg = 0, off_w3 = 0, off_lam = 0, off_part = 0, total = 0;
+    size_t off_ckpt = 0, off_seg = 0, off_w3 = 0, off_lam = 0, off_part = 0, off_R = 0, total = 0;
     // forward checkpoints and segment states by resident runs that store their
     // state (when a resident configuration fits): their workspace and moments
     bool resident = false;
@@ -359,6 +378,7 @@ ftwa_status plan_adjoint(const ftwa_instance* inst, int64_t n_steps, int record_
     a.off_w3 = off;   off = align_up(off + 3 * a.state);   // Y2, Y3, Y4 / acc, ya, yb
     a.off_lam = off;  off = align_up(off + 4 * a.state);   // lam, Lam, a (ping-pong)
     a.off_part = off; off = align_up(off + (size_t)g.n_elem_chunks * 2 * a.Mc * sizeof(double));
+    a.off_R = off;    off = align_up(off + (size_t)2 * N * a.Mc * (dtype == FTWA_F64 ? 8 : 4));
     // stored-state runs: the forward (records every ckpt_every steps) and
     // the longest segment (records every step)
     const int64_t f_steps = (a.n_ckpt - 1) * ckpt_every, s_steps = a.L - 1;
@@ -481,6 +501,8 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
         VjpArgs<T> V;
         V.N = N; V.P = P; V.Mc = Mc; V.nb = tab.nb; V.elem = tab.elem;
         V.t = (T)in.lat->t; V.U = (T)in.U; V.partial = partial; V.g = g;
+        T* const Rbuf = reinterpret_cast<T*>(ws + lay.off_R);
+        V.R = Rbuf;
         const int64_t n_el = (int64_t)state;
         const dim3 egrid((unsigned)((n_el + 255) / 256));
 
@@ -525,14 +547,19 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
                 FTWA_LAUNCH_CHECK("step_init_kernel");
                 V.lam = lam;
                 V.Lam = Lam;
+                auto vjp = [&]() {
+                    hipLaunchKernelGGL(diag_coupling_kernel<T>, sgrid, blk, 0, stream, N, P, Mc,
+                                       (const C*)V.a, V.Y, Rbuf);
+                    hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                };
                 V.Y = Y4; V.a = aA; V.a_next = aB; V.alpha = h3; V.beta = h1;
-                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                vjp();
                 V.Y = Y3; V.a = aB; V.a_next = aA; V.alpha = h3; V.beta = h2;
-                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                vjp();
                 V.Y = Y2; V.a = aA; V.a_next = aB; V.alpha = h6; V.beta = h2;
-                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                vjp();
                 V.Y = y;  V.a = aB; V.a_next = nullptr;
-                hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                vjp();
                 FTWA_LAUNCH_CHECK("vjp_kernel");
                 std::swap(lam, Lam);
                 if ((st = seed(base + n)) != FTWA_OK) return st;
