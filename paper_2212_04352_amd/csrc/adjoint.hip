@@ -94,25 +94,6 @@ __device__ __forceinline__ cplx_t<T> load_el(const cplx_t<T>* X, int64_t Mc, int
     return conj(X[(prow(N, b) + (a - b)) * Mc + m]);
 }
 
-// col = sum_{k in nb(j)} X_ik and row = sum_{k in nb(i)} X_kj, ascending k
-template <typename T>
-__device__ __forceinline__ void nb_sums(const cplx_t<T>* X, int64_t Mc, int N,
-                                        const int32_t* __restrict__ nb, int i, int j, int64_t m,
-                                        cplx_t<T>& col, cplx_t<T>& row) {
-    col.x = col.y = 0;
-    row.x = row.y = 0;
-    const int dj = nb[j * 4 + 3];
-    for (int n = 0; n < dj; ++n) {
-        const cplx_t<T> v = load_el<T>(X, Mc, N, i, nb[j * 4 + n], m);
-        col = n == 0 ? v : cadd(col, v);
-    }
-    const int di = nb[i * 4 + 3];
-    for (int n = 0; n < di; ++n) {
-        const cplx_t<T> v = load_el<T>(X, Mc, N, nb[i * 4 + n], j, m);
-        row = n == 0 ? v : cadd(row, v);
-    }
-}
-
 template <typename T> struct StageInArgs {
     int N;
     int64_t P, Mc;
@@ -125,27 +106,54 @@ template <typename T> struct StageInArgs {
     WaveGrid g;
 };
 
+// Packed elements of a wave: (spin, i, j) of the first one from the element
+// table, then advanced along the rows (the next row, then the other spin).
+struct ElemWalk {
+    int s, i, j;
+    __device__ __forceinline__ void next(int N) {
+        if (++j == N) {
+            if (++i == N) {
+                s = 1;
+                i = 0;
+            }
+            j = i;
+        }
+    }
+};
+__device__ __forceinline__ ElemWalk walk_from(const uint32_t* elem, int64_t P, int64_t q0) {
+    ElemWalk w;
+    w.s = q0 >= P ? 1 : 0;
+    const uint32_t ij = elem[q0 - w.s * P];
+    w.i = (int)(ij & 0xffffu);
+    w.j = (int)(ij >> 16);
+    return w;
+}
+
+// nb4: the neighbour rows (also in A.nb) as a read-only argument, so that the
+// wave-uniform row reads are scalar loads; all loads of an element are
+// issued together.
 template <typename T>
-__global__ __launch_bounds__(256) void stage_input_kernel(StageInArgs<T> A) {
+__global__ __launch_bounds__(256) void stage_input_kernel(StageInArgs<T> A,
+                                                          const int4* __restrict__ nb4) {
     const Lane l = lane_work(A.g, A.Mc);
     if (!l.valid) return;
     const int64_t q0 = l.chunk * kElemsPerWave;
     const int64_t q1 = q0 + kElemsPerWave < 2 * A.P ? q0 + kElemsPerWave : 2 * A.P;
-    for (int64_t q = q0; q < q1; ++q) {
-        const int s = q >= A.P ? 1 : 0;
+    ElemWalk w = walk_from(A.elem, A.P, q0);
+    for (int64_t q = q0; q < q1; ++q, w.next(A.N)) {
+        const int s = w.s, i = w.i, j = w.j;
         const int64_t p = q - s * A.P;
-        const uint32_t ij = A.elem[p];
-        const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
         const cplx_t<T>* Ys = A.yin + (int64_t)s * A.P * A.Mc;
         const cplx_t<T>* Yo = A.yin + (int64_t)(1 - s) * A.P * A.Mc;
         cplx_t<T> col, row;
-        nb_sums<T>(Ys, A.Mc, A.N, A.nb, i, j, l.m, col, row);
+        neighbour_sums<T>(Ys, A.Mc, A.N, nb4[j], nb4[i], i, j, l.m, col, row);
         const cplx_t<T> own = Ys[p * A.Mc + l.m];
-        const T a = A.U * (Yo[prow(A.N, i) * A.Mc + l.m].x - Yo[prow(A.N, j) * A.Mc + l.m].x);
-        const cplx_t<T> k = rhs_element<T>(col, row, own, A.t, a);
+        const T di = Yo[prow(A.N, i) * A.Mc + l.m].x, dj = Yo[prow(A.N, j) * A.Mc + l.m].x;
         const int64_t e = ((int64_t)s * A.P + p) * A.Mc + l.m;
+        const cplx_t<T> yv = A.y[e];
+        const T a = A.U * (di - dj);
+        const cplx_t<T> k = rhs_element<T>(col, row, own, A.t, a);
         if (l.active) {
-            const cplx_t<T> yv = A.y[e];
             cplx_t<T> nx;
             nx.x = fma_rn<T>(A.c, k.x, yv.x);
             nx.y = fma_rn<T>(A.c, k.y, yv.y);
@@ -197,7 +205,7 @@ template <typename T> struct VjpArgs {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void vjp_kernel(VjpArgs<T> A) {
+__global__ __launch_bounds__(256) void vjp_kernel(VjpArgs<T> A, const int4* __restrict__ nb4) {
     const Lane l = lane_work(A.g, A.Mc);
     if (!l.valid) return;
     const int N = A.N;
@@ -205,27 +213,32 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs<T> A) {
     const int64_t q0 = l.chunk * kElemsPerWave;
     const int64_t q1 = q0 + kElemsPerWave < 2 * A.P ? q0 + kElemsPerWave : 2 * A.P;
     double eU = 0.0, et = 0.0;
-    for (int64_t q = q0; q < q1; ++q) {
-        const int s = q >= A.P ? 1 : 0;
+    ElemWalk wk = walk_from(A.elem, A.P, q0);
+    for (int64_t q = q0; q < q1; ++q, wk.next(N)) {
+        const int s = wk.s, i = wk.i, j = wk.j;
         const int64_t p = q - s * A.P;
-        const uint32_t ij = A.elem[p];
-        const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
         const cplx_t<T>* Ys = A.Y + (int64_t)s * A.P * Mc;
         const cplx_t<T>* Yo = A.Y + (int64_t)(1 - s) * A.P * Mc;
         const cplx_t<T>* As = A.a + (int64_t)s * A.P * Mc;
         cplx_t<T> col, row;
-        nb_sums<T>(As, Mc, N, A.nb, i, j, m, col, row);
+        neighbour_sums<T>(As, Mc, N, nb4[j], nb4[i], i, j, m, col, row);
         const cplx_t<T> own_a = As[p * Mc + m];
         const cplx_t<T> own_y = Ys[p * Mc + m];
         const T dd = Yo[prow(N, i) * Mc + m].x - Yo[prow(N, j) * Mc + m].x;
+        // operands of the updates, loaded with the stencil
+        const int64_t e = ((int64_t)s * A.P + p) * Mc + m;
+        const T Rd = i == j ? A.R[((int64_t)s * N + i) * Mc + m] : (T)0;
+        const cplx_t<T> Lv = A.Lam[e];
+        cplx_t<T> lv;
+        lv.x = lv.y = 0;
+        if (A.a_next) lv = A.lam[e];
         const cplx_t<T> fl = rhs_element<T>(col, row, own_a, A.t, A.U * dd);
         cplx_t<T> mu;
         mu.x = -fl.x;
         mu.y = -fl.y;
         if (i == j) {
             // dependence of the other block's equation on this diagonal
-            const T acc = A.R[((int64_t)s * N + i) * Mc + m];
-            mu.x = fma_rn<T>((T)(-2) * A.U, acc, mu.x);
+            mu.x = fma_rn<T>((T)(-2) * A.U, Rd, mu.x);
         }
         // parameter partials in FP64
         const double w = i == j ? 1.0 : 2.0;
@@ -234,14 +247,12 @@ __global__ __launch_bounds__(256) void vjp_kernel(VjpArgs<T> A) {
         const double im_gy = gx * own_y.y - gy * own_y.x;
         eU -= w * (double)dd * im_ay;
         et -= w * im_gy;
-        const int64_t e = ((int64_t)s * A.P + p) * Mc + m;
         if (l.active) {
-            cplx_t<T> L = A.Lam[e];
+            cplx_t<T> L = Lv;
             L.x = L.x + mu.x;
             L.y = L.y + mu.y;
             A.Lam[e] = L;
             if (A.a_next) {
-                const cplx_t<T> lv = A.lam[e];
                 cplx_t<T> an;
                 an.x = fma_rn<T>(A.beta, mu.x, A.alpha * lv.x);
                 an.y = fma_rn<T>(A.beta, mu.y, A.alpha * lv.y);
@@ -502,6 +513,7 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
         V.N = N; V.P = P; V.Mc = Mc; V.nb = tab.nb; V.elem = tab.elem;
         V.t = (T)in.lat->t; V.U = (T)in.U; V.partial = partial; V.g = g;
         T* const Rbuf = reinterpret_cast<T*>(ws + lay.off_R);
+        const int4* const nb4 = reinterpret_cast<const int4*>(tab.nb);
         V.R = Rbuf;
         const int64_t n_el = (int64_t)state;
         const dim3 egrid((unsigned)((n_el + 255) / 256));
@@ -536,11 +548,11 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
                 // stage inputs with the forward arithmetic
                 S.y = y;
                 S.yin = y;  S.yout = Y2; S.c = h2;
-                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S);
+                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S, nb4);
                 S.yin = Y2; S.yout = Y3; S.c = h2;
-                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S);
+                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S, nb4);
                 S.yin = Y3; S.yout = Y4; S.c = h1;
-                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S);
+                hipLaunchKernelGGL(stage_input_kernel<T>, grid_dim(g), blk, 0, stream, S, nb4);
                 FTWA_LAUNCH_CHECK("stage_input_kernel");
                 hipLaunchKernelGGL(step_init_kernel<T>, egrid, blk, 0, stream, n_el, lam, Lam, aA,
                                    h6);
@@ -550,7 +562,7 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
                 auto vjp = [&]() {
                     hipLaunchKernelGGL(diag_coupling_kernel<T>, sgrid, blk, 0, stream, N, P, Mc,
                                        (const C*)V.a, V.Y, Rbuf);
-                    hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V);
+                    hipLaunchKernelGGL(vjp_kernel<T>, grid_dim(g), blk, 0, stream, V, nb4);
                 };
                 V.Y = Y4; V.a = aA; V.a_next = aB; V.alpha = h3; V.beta = h1;
                 vjp();

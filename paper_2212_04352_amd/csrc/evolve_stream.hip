@@ -32,6 +32,7 @@ template <typename T> struct StageArgs {
     cplx_t<T>* yout;       // next stage input (stages 1-3)
     cplx_t<T>* acc;        // Runge-Kutta accumulator, stride Mc
     const int32_t* nb;     // [N][4]
+    const uint32_t* elem;  // [P]: packed element -> i | j << 16
     T t, U, c;             // c: this stage's coefficient (h/2, h/2, h, h/6)
     int64_t n_elem_chunks; // ceil(2P / kElemsPerWave)
     int64_t n_work;        // n_traj_blocks * n_elem_chunks waves
@@ -42,17 +43,11 @@ __device__ __forceinline__ int64_t prow(int N, int i) {
     return (int64_t)i * N - (int64_t)i * (i - 1) / 2;
 }
 
-// Element (a, b) of one spin block of the stage input for trajectory m,
-// read from the stored upper triangle (conjugated when a > b).
-template <typename T>
-__device__ __forceinline__ cplx_t<T> load_elem(const cplx_t<T>* base, int64_t ld, int N, int a,
-                                               int b, int64_t m) {
-    if (a <= b) return base[(prow(N, a) + (b - a)) * ld + m];
-    return conj(base[(prow(N, b) + (a - b)) * ld + m]);
-}
-
+// nb4: the neighbour rows (also in A.nb) as a separate read-only argument,
+// so that the wave-uniform row reads are scalar loads.
 template <typename T, int STAGE>
-__global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A) {
+__global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
+                                                        const int4* __restrict__ nb4) {
     // XCD-aware numbering: blocks are dealt round-robin to the 8 XCDs, so
     // consecutive virtual blocks (neighbouring elements of the same
     // trajectories) are made to run on the same XCD and share its L2.
@@ -72,48 +67,35 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A) {
     const int64_t P = A.P;
     const int64_t q0 = chunk * kElemsPerWave;
     const int64_t q1 = q0 + kElemsPerWave < 2 * P ? q0 + kElemsPerWave : 2 * P;
+    // (spin, i, j) of the first element, then advanced along the packed rows
+    int s = q0 >= P ? 1 : 0;
+    int i, j;
+    {
+        const uint32_t ij = A.elem[q0 - s * P];
+        i = (int)(ij & 0xffffu);
+        j = (int)(ij >> 16);
+    }
     for (int64_t q = q0; q < q1; ++q) {
-        const int s = q >= P ? 1 : 0;
         const int64_t p = q - s * P;
-        // recover (i, j) of packed element p: rows are contiguous runs
-        int i = 0;
-        {
-            // row i satisfies prow(i) <= p < prow(i+1); N <= 255 so a short search
-            int lo = 0, hi = N - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) / 2;
-                if (prow(N, mid) <= p) lo = mid; else hi = mid - 1;
-            }
-            i = lo;
-        }
-        const int j = (int)(p - prow(N, i)) + i;
         const cplx_t<T>* Ys = A.yin + (int64_t)s * P * A.ldin;
         const cplx_t<T>* Yo = A.yin + (int64_t)(1 - s) * P * A.ldin;
-        // col = sum_{k in nb(j)} rho_ik, ascending k
-        const int dj = A.nb[j * 4 + 3];
+        // col = sum_{k in nb(j)} rho_ik, row = sum_{k in nb(i)} rho_kj,
+        // ascending k (loads issued together)
         cplx_t<T> col, row;
-        col.x = col.y = 0;
-        row.x = row.y = 0;
-        for (int n = 0; n < dj; ++n) {
-            const int k = A.nb[j * 4 + n];
-            const cplx_t<T> v = load_elem<T>(Ys, A.ldin, N, i, k, m);
-            col = n == 0 ? v : cadd(col, v);
-        }
-        // row = sum_{k in nb(i)} rho_kj, ascending k
-        const int di = A.nb[i * 4 + 3];
-        for (int n = 0; n < di; ++n) {
-            const int k = A.nb[i * 4 + n];
-            const cplx_t<T> v = load_elem<T>(Ys, A.ldin, N, k, j, m);
-            row = n == 0 ? v : cadd(row, v);
-        }
-        const int64_t ep = (prow(N, i) + (j - i));
+        neighbour_sums<T>(Ys, A.ldin, N, nb4[j], nb4[i], i, j, m, col, row);
+        const int64_t ep = p;
+        const int64_t e_ws = ((int64_t)s * P + ep) * A.Mc + m;  // workspace index
+        const int64_t e_y = ((int64_t)s * P + ep) * A.ldy + m;   // state index
         const cplx_t<T> own = Ys[ep * A.ldin + m];
         const T d_i = Yo[prow(N, i) * A.ldin + m].x;
         const T d_j = Yo[prow(N, j) * A.ldin + m].x;
+        // operands of the update, loaded with the stencil (in bounds for
+        // inactive lanes too)
+        cplx_t<T> ac, yv;
+        if (STAGE > 1) ac = A.acc[e_ws];
+        if (STAGE > 1) yv = A.y[e_y];
         const T a = A.U * (d_i - d_j);
         const cplx_t<T> k = rhs_element<T>(col, row, own, A.t, a);
-        const int64_t e_ws = ((int64_t)s * P + ep) * A.Mc + m;  // workspace index
-        const int64_t e_y = ((int64_t)s * P + ep) * A.ldy + m;   // state index
         if (STAGE == 1) {
             // Y_1 = y, so `own` is y itself
             if (active) {
@@ -125,11 +107,9 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A) {
             }
         } else if (STAGE == 2 || STAGE == 3) {
             if (active) {
-                cplx_t<T> ac = A.acc[e_ws];
                 ac.x = fma_rn<T>((T)2, k.x, ac.x);
                 ac.y = fma_rn<T>((T)2, k.y, ac.y);
                 A.acc[e_ws] = ac;
-                const cplx_t<T> yv = A.y[e_y];
                 cplx_t<T> nx;
                 nx.x = fma_rn<T>(A.c, k.x, yv.x);
                 nx.y = fma_rn<T>(A.c, k.y, yv.y);
@@ -137,14 +117,21 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A) {
             }
         } else {
             if (active) {
-                cplx_t<T> ac = A.acc[e_ws];
                 ac.x = ac.x + k.x;
                 ac.y = ac.y + k.y;
-                cplx_t<T> yv = A.y[e_y];
                 yv.x = fma_rn<T>(A.c, ac.x, yv.x);
                 yv.y = fma_rn<T>(A.c, ac.y, yv.y);
                 A.y[e_y] = yv;
             }
+        }
+        // next packed element: along the row, then the next row, then the
+        // other spin
+        if (++j == N) {
+            if (++i == N) {
+                s = 1;
+                i = 0;
+            }
+            j = i;
         }
     }
 }
@@ -172,6 +159,7 @@ ftwa_status step_impl(const StreamChunk& c, const DeviceTables& tab, hipStream_t
     A.ldy = c.ldy;
     A.acc = static_cast<cplx_t<T>*>(c.acc);
     A.nb = tab.nb;
+    A.elem = tab.elem;
     A.t = (T)c.t;
     A.U = (T)c.U;
     A.n_elem_chunks = (2 * c.P + kElemsPerWave - 1) / kElemsPerWave;
@@ -183,15 +171,16 @@ ftwa_status step_impl(const StreamChunk& c, const DeviceTables& tab, hipStream_t
     cplx_t<T>* ya = static_cast<cplx_t<T>*>(c.ya);
     cplx_t<T>* yb = static_cast<cplx_t<T>*>(c.yb);
     const T c_half = (T)(0.5 * c.dt), c_full = (T)c.dt, c_sixth = (T)(c.dt / 6.0);
+    const int4* nb4 = reinterpret_cast<const int4*>(tab.nb);
 
     A.yin = A.y; A.ldin = c.ldy; A.yout = ya; A.c = c_half;
-    hipLaunchKernelGGL((rk4_stage_stream<T, 1>), grid, block, 0, stream, A);
+    hipLaunchKernelGGL((rk4_stage_stream<T, 1>), grid, block, 0, stream, A, nb4);
     A.yin = ya; A.ldin = c.Mc; A.yout = yb; A.c = c_half;
-    hipLaunchKernelGGL((rk4_stage_stream<T, 2>), grid, block, 0, stream, A);
+    hipLaunchKernelGGL((rk4_stage_stream<T, 2>), grid, block, 0, stream, A, nb4);
     A.yin = yb; A.ldin = c.Mc; A.yout = ya; A.c = c_full;
-    hipLaunchKernelGGL((rk4_stage_stream<T, 3>), grid, block, 0, stream, A);
+    hipLaunchKernelGGL((rk4_stage_stream<T, 3>), grid, block, 0, stream, A, nb4);
     A.yin = ya; A.ldin = c.Mc; A.yout = nullptr; A.c = c_sixth;
-    hipLaunchKernelGGL((rk4_stage_stream<T, 4>), grid, block, 0, stream, A);
+    hipLaunchKernelGGL((rk4_stage_stream<T, 4>), grid, block, 0, stream, A, nb4);
     FTWA_LAUNCH_CHECK("rk4_stage_stream");
     return FTWA_OK;
 }
