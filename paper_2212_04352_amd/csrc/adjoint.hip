@@ -177,12 +177,30 @@ __global__ __launch_bounds__(256) void diag_coupling_kernel(int N, int64_t P, in
     const int s = si >= N ? 1 : 0, i = si - s * N;
     const cplx_t<T>* Ao = a + (int64_t)(1 - s) * P * Mc;
     const cplx_t<T>* Yo = Y + (int64_t)(1 - s) * P * Mc;
+    // eight sites at a time: their sixteen loads are issued before the sums
+    // (the sum itself runs in ascending k)
+    constexpr int B = 8;
     T acc = 0;
-    for (int k = 0; k < N; ++k) {
-        if (k == i) continue;
-        const cplx_t<T> av = load_el<T>(Ao, Mc, N, i, k, m);
-        const cplx_t<T> yv = load_el<T>(Yo, Mc, N, i, k, m);
-        acc = acc + (av.x * yv.y - av.y * yv.x);  // Im(conj(a) y)
+    for (int k0 = 0; k0 < N; k0 += B) {
+        cplx_t<T> av[B], yv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int k = k0 + u < N ? k0 + u : i;  // past the row: a harmless in-bounds read
+            bool tr;
+            const int64_t e = packed_at(N, i, k, tr) * Mc + m;
+            av[u] = Ao[e];
+            yv[u] = Yo[e];
+            if (tr) {
+                av[u].y = -av[u].y;
+                yv[u].y = -yv[u].y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int k = k0 + u;
+            if (k < N && k != i)
+                acc = acc + (av[u].x * yv[u].y - av[u].y * yv[u].x);  // Im(conj(a) y)
+        }
     }
     R[(int64_t)si * Mc + m] = acc;
 }
