@@ -774,7 +774,6 @@ constexpr const void* unit_hop_fn() {
            (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
            unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
 
-// Ordered by preference; the first one that fits a lattice is used.
 const Config kConfigs[] = {
     FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1, 1, 1),
     FTWA_RES_CFG(double, FTWA_F64, 2, 128, 8, 2, 2, 2, 2),
@@ -789,7 +788,20 @@ const Config kConfigs[] = {
     FTWA_RES_CFG(float, FTWA_F32, 1, 1024, 1, 10, 10, 2, 2),
     FTWA_RES_CFG(float, FTWA_F32, 1, 512, 1, 20, 20, 2, 2),
     FTWA_RES_CFG(float, FTWA_F32, 1, 768, 1, 13, 13, 13, 13),
+    // the shared-block tiles with only the first slot of each class general
+    FTWA_RES_CFG(double, FTWA_F64, 2, 128, 8, 2, 2, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 256, 3, 3, 3, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 512, 1, 5, 5, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 128, 8, 2, 2, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 256, 4, 3, 3, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 512, 1, 5, 5, 1, 1),
 };
+
+// Order of preference of the first-fit choice (a tile with fewer general
+// slots before the same tile with more; indices are those of kConfigs).
+const int kPreference[] = {0, 13, 1, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11, 12};
+static_assert(sizeof(kPreference) == sizeof(kConfigs) / sizeof(kConfigs[0]) * sizeof(int),
+              "every configuration has a place in the preference order");
 
 constexpr size_t kMaxLds = 160 * 1024;  // the kernel declares no static LDS
 
@@ -815,7 +827,8 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
     const int n_even = (int)tab.n_even, n_odd = P - n_even;
     if (P + 33 > 0x7fff) return false;
     const int n_cfg = (int)(sizeof(kConfigs) / sizeof(kConfigs[0]));
-    for (int k = 0; k < n_cfg; ++k) {
+    for (int o = 0; o < n_cfg; ++o) {
+        const int k = kPreference[o];
         if (force_config >= 0 && k != force_config) continue;
         const Config& c = kConfigs[k];
         if (c.dtype != dtype) continue;
