@@ -180,6 +180,22 @@ typedef struct {
 ftwa_status ftwa_sample(const ftwa_instance* inst, int n_inst, uint64_t seed,
                         ftwa_dtype dtype, void* stream);
 
+/*
+ * ftwa_sample_thermal -- as ftwa_sample, for an initial state that is
+ * thermal in the site basis (non-integer occupations, Sec. III): the
+ * Gaussian initial density then has the full covariance of Appendix A.3,
+ * whose diagonal part is Var rho_ii = n_i (1 - n_i), independent of every
+ * other element.  rho_ii = n_i - 1/2 (+ n_shift) + sqrt(n_i (1 - n_i)) g_i,
+ * g_i a real standard normal from Philox4x32-10 with counter
+ *   (i, instance<<1 | s, traj_offset + m, 2), key = seed:
+ *   g = sqrt(-2 ln u1) cos(2 pi u2)  (u1, u2 as above);
+ * the off-diagonal elements are those of ftwa_sample (same counters), so for
+ * integer occupations both calls give identical points.  Same arguments,
+ * errors and layout as ftwa_sample.
+ */
+ftwa_status ftwa_sample_thermal(const ftwa_instance* inst, int n_inst, uint64_t seed,
+                                ftwa_dtype dtype, void* stream);
+
 /* Tuning of ftwa_evolve; pass NULL for the automatic choice. */
 typedef enum {
     FTWA_PATH_AUTO = 0,

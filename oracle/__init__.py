@@ -62,7 +62,9 @@ def _load():
                                       P(dbl)]
     lib.oracle_complex_normal.argtypes = [u64, u32, u32, u32, P(dbl), P(dbl)]
     lib.oracle_complex_normal.restype = None
-    lib.oracle_sample.argtypes = [ctypes.c_int, P(dbl), u64, u32, i64, i64, P(dbl)]
+    lib.oracle_sample.argtypes = [ctypes.c_int, P(dbl), u64, u32, i64, i64, ctypes.c_int, P(dbl)]
+    lib.oracle_real_normal.argtypes = [u64, u32, u32, u32, u32]
+    lib.oracle_real_normal.restype = dbl
     lib.oracle_sample.restype = None
     for suffix, real in (("f64", dbl), ("f32", ctypes.c_float)):
         rhs = getattr(lib, f"oracle_rhs_{suffix}")
@@ -198,14 +200,23 @@ def fock_start(lat: Lattice, kind: str = "neel", seed: int = 0, instance: int = 
 # Sampling (Eq. (6)), equation of motion (Eq. (5)), RK4, moments, observables
 # --------------------------------------------------------------------------
 def sample(lat: Lattice, n0: np.ndarray, seed: int, M: int, traj_offset: int = 0,
-           instance: int = 0) -> np.ndarray:
-    """Gaussian initial points rho(0), shape [M, 2, N, N] complex128 (Eq. (6))."""
+           instance: int = 0, thermal: bool = False) -> np.ndarray:
+    """Gaussian initial points rho(0), shape [M, 2, N, N] complex128 (Eq. (6));
+    thermal: also the diagonal fluctuation Var rho_ii = n(1 - n) of the
+    Appendix A.3 covariance."""
     lib = _load()
     n0c = np.ascontiguousarray(n0, dtype=np.float64).reshape(-1)
     out = np.zeros((M, 2, lat.N, lat.N), dtype=np.complex128)
     lib.oracle_sample(lat.N, _ptr(n0c, ctypes.c_double), ctypes.c_uint64(seed), instance,
-                      traj_offset, M, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                      traj_offset, M, 1 if thermal else 0,
+                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
+
+
+def real_normal(seed: int, c0: int, c1: int, c2: int, c3: int) -> float:
+    """One real standard normal of the thermal diagonal (Box-Muller on the
+    Philox draw of counter (c0, c1, c2, c3))."""
+    return float(_load().oracle_real_normal(ctypes.c_uint64(seed), c0, c1, c2, c3))
 
 
 def rhs(lat: Lattice, U: float, rho: np.ndarray, precision: str = "f64") -> np.ndarray:

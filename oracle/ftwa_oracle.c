@@ -324,8 +324,31 @@ void oracle_complex_normal(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
     *im = r * sin(theta);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Real standard normal for the diagonal of a thermal initial state: the     */
+/* covariance of Appendix A.3 at alpha = beta = mu = nu = i is                */
+/* (1 - n_i) n_i, and the diagonal is uncorrelated with every other element  */
+/* (the off-diagonal occupations vanish in the site basis), so              */
+/*   rho_ii = n_i - 1/2 + sqrt(n_i (1 - n_i)) g_i,                           */
+/* g_i by Box-Muller from the two uniforms of counter                        */
+/* (i, instance<<1|spin, m, 2):  g = sqrt(-2 ln u1) cos(2 pi u2).             */
+/* ------------------------------------------------------------------------ */
+double oracle_real_normal(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
+{
+    uint32_t key[2], x[4];
+    seed_to_key(seed, key);
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    oracle_philox4x32_10(ctr, key, x);
+    uint64_t a53, b53;
+    philox_53bit_pair(x, &a53, &b53);
+    const double two_m53 = 1.0 / 9007199254740992.0; /* 2^-53 */
+    double u1 = (double)(a53 + 1u) * two_m53;
+    double u2 = (double)b53 * two_m53;
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
 void oracle_sample(int N, const double* n0, uint64_t seed, uint32_t instance,
-                   int64_t traj_offset, int64_t M, double* rho_out)
+                   int64_t traj_offset, int64_t M, int thermal, double* rho_out)
 {
     #pragma omp parallel for schedule(static)
     for (int64_t m = 0; m < M; ++m) {
@@ -335,7 +358,12 @@ void oracle_sample(int N, const double* n0, uint64_t seed, uint32_t instance,
             const double* n = n0 + s * N;
             double* R = rho + (size_t)s * N * N * 2;
             for (int i = 0; i < N; ++i) {
-                R[2 * (i * N + i)] = n[i] - 0.5;
+                double d = n[i] - 0.5;
+                double var = n[i] * (1.0 - n[i]);
+                if (thermal && var != 0.0)
+                    d += sqrt(var) * oracle_real_normal(seed, (uint32_t)i,
+                                                        (instance << 1) | (uint32_t)s, gm, 2u);
+                R[2 * (i * N + i)] = d;
                 R[2 * (i * N + i) + 1] = 0.0;
             }
             for (int i = 0; i < N; ++i)

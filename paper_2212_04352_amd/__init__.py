@@ -19,7 +19,8 @@ from ._binding import (DTYPE, FtwaError, ftwa_adjoint, ftwa_adjoint_workspace_si
                        ftwa_build_lattice_bonds, ftwa_evolve, ftwa_evolve_graph,
                        ftwa_evolve_workspace_size, ftwa_fock_start, ftwa_free_lattice,
                        ftwa_graph_check, ftwa_graph_free, ftwa_graph_launch, ftwa_lattice_info,
-                       ftwa_last_error, ftwa_observables, ftwa_sample, ftwa_unpack, load,
+                       ftwa_last_error, ftwa_observables, ftwa_sample, ftwa_sample_thermal,
+                       ftwa_unpack, load,
                        new_timing)
 
 
@@ -104,10 +105,13 @@ class Problem:
             self.inv = torch.empty((n_rec, 4), dtype=torch.float64, device=self.rho.device)
 
 
-def sample(problems, seed: int, stream=None) -> None:
+def sample(problems, seed: int, stream=None, thermal: bool = False) -> None:
+    """ftwa_sample, or ftwa_sample_thermal (diagonal fluctuations of a
+    thermal initial state) when `thermal`."""
     problems = problems if isinstance(problems, (list, tuple)) else [problems]
     dt = problems[0].dtype
-    ftwa_sample([p.desc() for p in problems], seed, dt, stream)
+    fn = ftwa_sample_thermal if thermal else ftwa_sample
+    fn([p.desc() for p in problems], seed, dt, stream)
 
 
 def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str = "auto",

@@ -21,7 +21,8 @@ PATH = {"auto": 0, "stream": 1, "resident": 2}
 # Every symbol include/ftwa.h declares.
 EXPORTS = (
     "ftwa_build_lattice", "ftwa_build_lattice_bonds", "ftwa_lattice_info", "ftwa_free_lattice",
-    "ftwa_fock_start", "ftwa_sample", "ftwa_evolve_workspace_size", "ftwa_evolve",
+    "ftwa_fock_start", "ftwa_sample", "ftwa_sample_thermal", "ftwa_evolve_workspace_size",
+    "ftwa_evolve",
     "ftwa_observables", "ftwa_unpack", "ftwa_adjoint_workspace_size", "ftwa_adjoint",
     "ftwa_evolve_graph", "ftwa_graph_launch", "ftwa_graph_check", "ftwa_graph_free",
     "ftwa_autotune_workspace_size", "ftwa_autotune", "ftwa_last_error",
@@ -80,6 +81,7 @@ def load() -> ctypes.CDLL:
         "ftwa_free_lattice": ([vp], None),
         "ftwa_fock_start": ([vp, i32, u64, u32, vp], i32),
         "ftwa_sample": ([P(Instance), i32, u64, i32, vp], i32),
+        "ftwa_sample_thermal": ([P(Instance), i32, u64, i32, vp], i32),
         "ftwa_evolve_workspace_size": ([P(Instance), i32, i64, i32, i32, P(Tuning),
                                         P(ctypes.c_size_t)], i32),
         "ftwa_evolve": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp, ctypes.c_size_t,
@@ -200,6 +202,12 @@ def ftwa_sample(insts, seed: int, dtype: str, stream=None) -> None:
     arr = _instances(insts)
     check(load().ftwa_sample(arr, len(insts), ctypes.c_uint64(seed), DTYPE[dtype], _stream(stream)),
           "ftwa_sample")
+
+
+def ftwa_sample_thermal(insts, seed: int, dtype: str, stream=None) -> None:
+    arr = _instances(insts)
+    check(load().ftwa_sample_thermal(arr, len(insts), ctypes.c_uint64(seed), DTYPE[dtype],
+                                     _stream(stream)), "ftwa_sample_thermal")
 
 
 def ftwa_evolve_workspace_size(insts, n_steps: int, record_every: int, dtype: str,

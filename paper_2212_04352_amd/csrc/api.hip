@@ -113,6 +113,23 @@ ftwa_status KernelTimer::finish(double* ms, int64_t* launches, double* work) {
     return FTWA_OK;
 }
 
+
+namespace {
+ftwa_status sample_all(const ftwa_instance* inst, int n_inst, uint64_t seed, ftwa_dtype dtype,
+                       bool thermal, void* stream, const char* who) {
+    ftwa_status st = check_instances(inst, n_inst, false, who);
+    if (st != FTWA_OK) return st;
+    if (dtype != FTWA_F64 && dtype != FTWA_F32) return fail(FTWA_EINVAL, "unknown dtype");
+    for (int k = 0; k < n_inst; ++k) {
+        DeviceTables tab;
+        if ((st = device_tables(inst[k].lat, &tab)) != FTWA_OK) return st;
+        if ((st = launch_sample(inst[k], tab, seed, dtype, thermal, (hipStream_t)stream)) !=
+            FTWA_OK)
+            return st;
+    }
+    return FTWA_OK;
+}
+}  // namespace
 }  // namespace ftwa
 
 using namespace ftwa;
@@ -121,15 +138,12 @@ extern "C" {
 
 ftwa_status ftwa_sample(const ftwa_instance* inst, int n_inst, uint64_t seed, ftwa_dtype dtype,
                         void* stream) {
-    ftwa_status st = check_instances(inst, n_inst, false, "ftwa_sample");
-    if (st != FTWA_OK) return st;
-    if (dtype != FTWA_F64 && dtype != FTWA_F32) return fail(FTWA_EINVAL, "unknown dtype");
-    for (int k = 0; k < n_inst; ++k) {
-        DeviceTables tab;
-        if ((st = device_tables(inst[k].lat, &tab)) != FTWA_OK) return st;
-        if ((st = launch_sample(inst[k], tab, seed, dtype, (hipStream_t)stream)) != FTWA_OK) return st;
-    }
-    return FTWA_OK;
+    return sample_all(inst, n_inst, seed, dtype, false, stream, "ftwa_sample");
+}
+
+ftwa_status ftwa_sample_thermal(const ftwa_instance* inst, int n_inst, uint64_t seed,
+                                ftwa_dtype dtype, void* stream) {
+    return sample_all(inst, n_inst, seed, dtype, true, stream, "ftwa_sample_thermal");
 }
 
 ftwa_status ftwa_observables(int n_sites, int64_t M, int n_rec, const double* S1, const double* S2,

@@ -123,7 +123,7 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
 ftwa_status launch_sample(const ftwa_instance& in, const DeviceTables& tab, uint64_t seed,
-                          ftwa_dtype dtype, hipStream_t stream);
+                          ftwa_dtype dtype, bool thermal, hipStream_t stream);
 
 // Copies of the diagonal variables into the record buffer X[a][m] (FP64).
 struct RecordView {

@@ -1,5 +1,6 @@
 // sample.hip -- Gaussian initial phase-space points (Eq. (6) of
-// arXiv:2212.04352, amplitude from the covariance of Appendix A.3).
+// arXiv:2212.04352, amplitude from the covariance of Appendix A.3; for a
+// thermal initial state also the diagonal fluctuation of that covariance).
 //
 // One thread per (spin, packed element, trajectory); the trajectory index is
 // the fastest grid dimension so that every wave stores 64 consecutive
@@ -18,7 +19,7 @@ __global__ __launch_bounds__(256) void sample_kernel(int N, int64_t P, int64_t n
                                                      uint64_t seed, const double* __restrict__ n0,
                                                      const double* __restrict__ shift,
                                                      const uint32_t* __restrict__ elem,
-                                                     cplx_t<T>* __restrict__ rho) {
+                                                     cplx_t<T>* __restrict__ rho, int thermal) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n_traj) return;
     const int64_t row = blockIdx.y;  // s * P + p
@@ -31,6 +32,16 @@ __global__ __launch_bounds__(256) void sample_kernel(int N, int64_t P, int64_t n
     if (i == j) {
         re = ni - 0.5;
         if (shift) re += shift[s * N + i];
+        const double var = ni * (1.0 - ni);  // thermal state: Var rho_ii (Appendix A.3)
+        if (thermal && var != 0.0) {
+            const PhiloxBlock b = philox4x32_10(
+                {(uint32_t)i, (instance << 1) | (uint32_t)s, (uint32_t)(traj_offset + m), 2u}, seed);
+            const double scale = 1.0 / 9007199254740992.0;  // 2^-53
+            const double u1 = (double)(b.bits53_first() + 1u) * scale;
+            const double u2 = (double)b.bits53_second() * scale;
+            const double g = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+            re += sqrt(var) * g;
+        }
     } else {
         const double var = 0.5 * ((ni + nj) - (2.0 * ni) * nj);
         if (var != 0.0) {
@@ -56,7 +67,7 @@ __global__ __launch_bounds__(256) void sample_kernel(int N, int64_t P, int64_t n
 }  // namespace
 
 ftwa_status launch_sample(const ftwa_instance& in, const DeviceTables& tab, uint64_t seed,
-                          ftwa_dtype dtype, hipStream_t stream) {
+                          ftwa_dtype dtype, bool thermal, hipStream_t stream) {
     const int N = in.lat->N;
     const int64_t P = packed_count(N);
     if (in.n_traj == 0) return FTWA_OK;
@@ -65,11 +76,11 @@ ftwa_status launch_sample(const ftwa_instance& in, const DeviceTables& tab, uint
     if (dtype == FTWA_F64)
         hipLaunchKernelGGL(sample_kernel<double>, grid, block, 0, stream, N, P, in.n_traj,
                            in.traj_offset, in.instance, seed, in.n0, in.n_shift, tab.elem,
-                           static_cast<double2*>(in.rho));
+                           static_cast<double2*>(in.rho), thermal ? 1 : 0);
     else
         hipLaunchKernelGGL(sample_kernel<float>, grid, block, 0, stream, N, P, in.n_traj,
                            in.traj_offset, in.instance, seed, in.n0, in.n_shift, tab.elem,
-                           static_cast<float2*>(in.rho));
+                           static_cast<float2*>(in.rho), thermal ? 1 : 0);
     FTWA_LAUNCH_CHECK("sample_kernel");
     return FTWA_OK;
 }

@@ -56,6 +56,41 @@ def test_sample_matches_oracle(ft, orc, kind, a, b, M, start, off):
     assert np.max(np.abs(got32 - ref.astype(np.complex64))) <= 2 * np.finfo(np.float32).eps * 8
 
 
+@pytest.mark.parametrize("kind,a,b,M,off", [("torus", 3, 9, 65, 7), ("armchair", 10, 20, 9, 300)])
+def test_thermal_sample_matches_oracle(ft, orc, kind, a, b, M, off):
+    """ftwa_sample_thermal (fractional occupations, diagonal fluctuations of
+    the Appendix A.3 covariance) against the oracle: the off-diagonal part
+    equals the plain sampler's, the diagonal within a few ulp (device
+    log/cos), zeros where n is 0 or 1; then the trajectories evolve like the
+    oracle's from the oracle's samples."""
+    import torch
+    seed = 0x2212043520000077
+    lat = ft.Lattice(kind, a, b)
+    N = lat.N
+    rng = np.random.default_rng(5)
+    n0 = np.clip(rng.uniform(-0.2, 1.2, size=(2, N)), 0.0, 1.0)  # some exactly 0 or 1
+    prob = ft.Problem.allocate(lat, 3.3, M, n0, "f64", traj_offset=off)
+    ft.sample(prob, seed, thermal=True)
+    got = unpack(_to_host(prob.rho), lat.N)
+    ref = orc.sample(orc.Lattice(kind, a, b), n0, seed, M, traj_offset=off, thermal=True)
+    assert np.array_equal(got == 0, ref == 0)
+    assert np.max(np.abs(got - ref)) <= 8 * np.finfo(np.float64).eps * np.max(np.abs(ref))
+    plain = ft.Problem.allocate(lat, 3.3, M, n0, "f64", traj_offset=off)
+    ft.sample(plain, seed)
+    p = unpack(_to_host(plain.rho), lat.N)
+    off_diag = ~np.eye(N, dtype=bool)
+    assert np.array_equal(got[:, :, off_diag], p[:, :, off_diag])
+    integer = (n0 == 0) | (n0 == 1)
+    d_got = np.diagonal(got, axis1=2, axis2=3).real
+    assert np.array_equal(d_got[:, integer], np.broadcast_to(n0 - 0.5, d_got.shape)[:, integer])
+    # evolution from the oracle's thermal samples (resident FP32 path), bitwise
+    p32 = ft.Problem.allocate(lat, 3.3, M, n0, "f32")
+    p32.rho.copy_(torch.from_numpy(pack(ref.astype(np.complex64))))
+    ft.evolve(p32, 0.01, 10, 5)
+    y_ref, _, _ = orc.evolve(orc.Lattice(kind, a, b), 3.3, ref, 0.01, 10, 5, precision="f32")
+    assert np.array_equal(unpack(_to_host(p32.rho), lat.N), y_ref.astype(np.complex64))
+
+
 def _evolve_parity(ft, orc, kind, a, b, U, M, n_steps, dt, re, dtype, start="random", seed=3,
                    chunk=0, path="stream"):
     import torch

@@ -189,6 +189,58 @@ def test_sample_moments_match_appendix_covariance(orc):
                 assert sst.kstest((np.angle(v) + np.pi) / (2 * np.pi), "uniform").pvalue > 1e-4
 
 
+def test_thermal_sample_diagonal_matches_appendix_covariance(orc):
+    """Thermal (non-integer) initial state: the Appendix A.3 covariance at
+    alpha = beta = mu = nu = i is n_i (1 - n_i), so rho_ii fluctuates about
+    n_i - 1/2 with that variance, as a Gaussian, uncorrelated with the other
+    diagonal entries and with the off-diagonal elements; the off-diagonal
+    elements are those of the plain sampler (same counters)."""
+    N = 4
+    lat = orc.Lattice.from_bonds(N, [(0, 1), (1, 2), (2, 3), (3, 0)], [0, 1, 0, 1])
+    n0 = np.array([[1.0, 0.0, 0.3, 0.75], [0.5, 1.0, 0.6, 0.1]])
+    M = 40000
+    rho = orc.sample(lat, n0, seed=321, M=M, thermal=True)
+    plain = orc.sample(lat, n0, seed=321, M=M)
+    off = ~np.eye(N, dtype=bool)
+    assert np.array_equal(rho[:, :, off], plain[:, :, off])
+    for s in range(2):
+        d = rho[:, s, np.arange(N), np.arange(N)]
+        assert np.all(d.imag == 0)
+        for i in range(N):
+            var = n0[s, i] * (1 - n0[s, i])
+            x = d[:, i].real - (n0[s, i] - 0.5)
+            if var == 0:   # integer occupation: the plain, deterministic diagonal
+                assert np.all(x == 0)
+                continue
+            assert abs(x.mean()) < 5 * np.sqrt(var / M)
+            assert abs(np.mean(x * x) - var) < 5 * var * np.sqrt(2.0 / M)
+            assert sst.kstest(x / np.sqrt(var), "norm").pvalue > 1e-4
+            # independent of the other diagonal entries and of the off-diagonal
+            for k in range(N):
+                if k != i and n0[s, k] * (1 - n0[s, k]) > 0:
+                    y = d[:, k].real - (n0[s, k] - 0.5)
+                    assert abs(np.mean(x * y)) < 5 * np.sqrt(var * n0[s, k] * (1 - n0[s, k]) / M)
+            v = rho[:, s, 0, 2]
+            assert abs(np.mean(x * v)) < 5 * np.sqrt(var * np.mean(np.abs(v) ** 2) / M) + 1e-12
+    # one draw by hand: the counter (i, instance << 1 | s, m, 2) of the definition
+    g = orc.real_normal(321, 2, (0 << 1) | 1, 7, 2)
+    assert rho[7, 1, 2, 2].real == (n0[1, 2] - 0.5) + np.sqrt(n0[1, 2] * (1 - n0[1, 2])) * g
+
+
+def test_real_normal_is_box_muller_of_the_philox_draw(orc):
+    """g = sqrt(-2 ln u1) cos(2 pi u2) with u1 = (a+1) 2^-53, u2 = b 2^-53 and
+    (a, b) the two 53-bit halves of the Philox4x32-10 block, checked against
+    the block computed by the known-answer-tested Philox."""
+    seed, ctr = 0x1234_5678_9abc_def0, (5, 3, 11, 2)
+    x = orc.philox4x32_10(ctr, ((seed & 0xffffffff), seed >> 32))
+    a = (int(x[0]) << 21) | (int(x[1]) >> 11)
+    b = (int(x[2]) << 21) | (int(x[3]) >> 11)
+    u1 = (a + 1) * 2.0 ** -53
+    u2 = b * 2.0 ** -53
+    want = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    assert abs(orc.real_normal(seed, *ctr) - want) <= 4e-16 * max(1.0, abs(want))
+
+
 # ---------------------------------------------------------------------------
 # Equation of motion, Eq. (5)
 # ---------------------------------------------------------------------------
