@@ -53,10 +53,11 @@ def parse():
     ap.add_argument("--cpu-traj", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--workload", default="flake198",
-                    choices=["flake198", "batch", "adjoint", "sizes"],
+                    choices=["flake198", "batch", "adjoint", "sizes", "thermal"],
                     help="flake198: the headline metric (default); batch: the 64-instance mixed "
                          "batch as one graph launch; adjoint: the 54-site gradient workload; "
-                         "sizes: resident throughput per lattice size")
+                         "sizes: resident throughput per lattice size; thermal: sampling of "
+                         "thermal (fractional-occupation) starts on the 198-site flake")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-traj", type=int, default=2048)
     ap.add_argument("--sequential", action="store_true",
@@ -280,6 +281,50 @@ def run_sizes(args):
                       "unit": "trajectory*RK4-steps/s", "rows": rows}))
 
 
+def run_thermal(args):
+    """Thermal initial states on the 198-site flake: ftwa_sample_thermal of
+    32768 trajectories (fractional occupations), its rate against the HBM
+    roofline of the sampler's output, then 400 FP32 RK4 steps from them."""
+    import numpy as np
+    import torch
+    import paper_2212_04352_amd as ft
+    lat = ft.Lattice("armchair", 10, 20)
+    N = lat.N
+    M = args.traj or 32768
+    rng = np.random.default_rng(12)
+    n0 = rng.uniform(0.2, 0.8, size=(2, N))  # a seeded fractional filling
+    p = ft.Problem.allocate(lat, 3.3, M, n0, "f32")
+    P = N * (N + 1) // 2
+    ft.sample(p, 9, thermal=True)  # warm-up
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ft.sample(p, 9, thermal=True)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / reps
+    out_bytes = 2 * P * M * 8  # FP32 complex output, the sampler's only HBM traffic
+    steps = args.horizon_steps or 400
+    ft.autotune(p, probe_steps=50)
+    timing = ft.new_timing()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ft.evolve(p, 0.005, steps, 10, timing=timing)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t1
+    log(f"thermal: sample {ts * 1e3:.2f} ms ({out_bytes / ts / 1e9:.0f} GB/s), "
+        f"evolve {M * steps / te:.3e} traj-steps/s")
+    print(json.dumps({
+        "metric": "thermal initial states, 198-site flake: sampling rate and FP32 evolution",
+        "sample_seconds": ts, "sample_elements_per_s": 2 * P * M / ts,
+        "sample_roofline": {"bound": "hbm", "achieved": out_bytes / ts / 1e9,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": out_bytes / ts / 1e9 / HBM_PEAK_GBS},
+        "evolve_value": M * steps / te, "unit": "trajectory*RK4-steps/s",
+        "config": {"workload": "flake198_thermal", "trajectories": M, "rk4_steps": steps,
+                   "occupations": "uniform on [0.2, 0.8], seeded", "dtype": "f32"}}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -294,6 +339,8 @@ def main():
         return run_batch(args)
     if args.workload == "adjoint":
         return run_adjoint(args)
+    if args.workload == "thermal":
+        return run_thermal(args)
     if args.workload == "sizes":
         return run_sizes(args)
 
