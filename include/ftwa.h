@@ -283,8 +283,9 @@ void ftwa_graph_free(ftwa_graph graph);
  * ftwa_autotune -- times every resident kernel configuration that fits each
  * distinct lattice of the instances (and the stream path) on a copy of the
  * instance's first trajectories (rho is not modified), `probe_steps` steps
- * each, and records the fastest per (device, lattice size, dtype); later
- * plans with the automatic choice use it.  configs (host, NULL or [n_inst])
+ * each, and records the fastest per (device, lattice size, class sizes of
+ * the lattice's stored elements, dtype); later plans with the automatic
+ * choice use it.  configs (host, NULL or [n_inst])
  * receives the choice per instance (-1 = stream path).  Synchronises
  * `stream`; must not be called under graph capture.  workspace: at least
  * ftwa_autotune_workspace_size bytes.
@@ -342,8 +343,14 @@ ftwa_status ftwa_adjoint_workspace_size(const ftwa_instance* inst, int64_t n_ste
  *   traj_chunk    trajectories per pass (0 = all); smaller chunks need less
  *                 workspace and give the same result up to the order of the
  *                 final FP64 sums.
+ * When a resident configuration fits the lattice and dtype, the checkpoints
+ * and every segment's states come from resident runs that store their state
+ * (the workspace also holds their plan, and each run synchronises `stream`
+ * once on the host); otherwise from per-stage stream launches.  The
+ * trajectories and the gradient are the same either way.
  * Errors: FTWA_EINVAL (sizes, NULL pointers, workspace too small),
- * FTWA_EHIP on launch failure.
+ * FTWA_EHIP on launch failure, FTWA_ETIMEOUT (a spin-split resident run's
+ * bounded wait gave up).
  */
 ftwa_status ftwa_adjoint(const ftwa_instance* inst, double dt, int64_t n_steps,
                          int record_every, int ckpt_every, ftwa_dtype dtype, int64_t n_total,
