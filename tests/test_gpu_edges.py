@@ -1,0 +1,108 @@
+"""Edge cases of the evolution kernels against the oracle (through the C ABI):
+no steps, degenerate parameters (U = 0, t = 0), graphs other than the honeycomb
+generators (an open chain with degree-1 ends, an isolated site, an odd ring
+that is not bipartite and so only has the stream path), and the largest
+lattice the library accepts.  The evolved states must equal the oracle's
+bitwise (same operation order); the moments to 1e-12.
+"""
+import numpy as np
+import pytest
+
+from tests._util import pack, unpack
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ft():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_04352_amd as ft
+    ft.load()
+    return ft
+
+
+def _host(x):
+    import torch
+    torch.cuda.synchronize()
+    return x.detach().cpu().numpy()
+
+
+def _lattices(ft, orc, spec, t=1.0):
+    kind = spec[0]
+    if kind == "custom":
+        _, n, bonds, sub = spec
+        return (ft.Lattice("custom", 0, 0, t, bonds=bonds, sublattice=sub, n_sites=n),
+                orc.Lattice.from_bonds(n, bonds, sub, t=t))
+    _, a, b = spec
+    return ft.Lattice(kind, a, b, t), orc.Lattice(kind, a, b, t)
+
+
+def _run(ft, orc, spec, dtype, path, U=3.3, t=1.0, M=37, steps=25, re=5, seed=4, n0=None,
+         config=-1):
+    import torch
+    lat, olat = _lattices(ft, orc, spec, t)
+    if n0 is None:
+        n0 = orc.fock_start(olat, "random", seed)
+    rho0 = orc.sample(olat, n0, seed, M)
+    prob = ft.Problem.allocate(lat, U, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    ft.evolve(prob, 0.01, steps, re, path=path, config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, U, rho0, 0.01, steps, re, precision=dtype)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+    return got, rho0.astype(cdt)
+
+
+CHAIN7 = ("custom", 7, [(k, k + 1) for k in range(6)], [k % 2 for k in range(7)])
+# a comb with one isolated site: degrees 0..3
+COMB = ("custom", 9, [(0, 1), (1, 2), (2, 3), (1, 4), (3, 5), (5, 6), (5, 7)],
+        [0, 1, 0, 1, 0, 0, 1, 1, 0])
+RING5 = ("custom", 5, [(k, (k + 1) % 5) for k in range(5)], [0, 1, 0, 1, 0])
+
+
+@pytest.mark.parametrize("path", ["stream", "resident"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_zero_steps_leave_the_state(ft, orc, dtype, path):
+    got, rho0 = _run(ft, orc, ("torus", 2, 3), dtype, path, steps=0, re=1)
+    assert np.array_equal(got, rho0)
+
+
+@pytest.mark.parametrize("path", ["stream", "resident"])
+@pytest.mark.parametrize("U,t", [(0.0, 1.0), (3.3, 0.0), (-2.0, 0.7)])
+def test_degenerate_parameters(ft, orc, U, t, path):
+    got, rho0 = _run(ft, orc, ("hex", 2, 0), "f32", path, U=U, t=t)
+    if t == 0.0:  # no hopping: the diagonal of each block is conserved exactly
+        assert np.array_equal(np.diagonal(got, axis1=2, axis2=3),
+                              np.diagonal(rho0, axis1=2, axis2=3))
+
+
+@pytest.mark.parametrize("path", ["stream", "resident"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec", [CHAIN7, COMB], ids=["chain7", "comb"])
+def test_other_bipartite_graphs(ft, orc, spec, dtype, path):
+    sub = np.array(spec[3], dtype=float)
+    _run(ft, orc, spec, dtype, path, M=70, n0=np.array([1.0 - sub, sub]))  # Neel-like start
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_odd_ring_runs_on_the_stream_path_only(ft, orc, dtype):
+    _run(ft, orc, RING5, dtype, "auto", M=20, n0=np.array([[1, 0, 1, 0, 0.0], [0, 1, 0, 1, 1.0]]))
+    lat, _ = _lattices(ft, orc, RING5)
+    prob = ft.Problem.allocate(lat, 1.0, 4, np.array([[1, 0, 1, 0, 0.0], [0, 1, 0, 1, 1.0]]),
+                               dtype)
+    ft.sample(prob, 1)
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 2, 1, path="resident")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_largest_lattice(ft, orc, dtype):
+    """A 9 x 14 torus, 252 sites (the library takes up to 255): the stream path
+    in both precisions (no resident tile holds a block this large)."""
+    _run(ft, orc, ("torus", 9, 14), dtype, "auto", M=3, steps=3, re=1)
