@@ -123,7 +123,8 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 cfg = c;
             }
         }
-        const bool can_res = !tuned_stream && resident_plan(N, dtype, tab, &ip.res, cfg);
+        const bool can_res =
+            !tuned_stream && resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
         if (force >= 0 && !can_res)
             return fail(FTWA_ENOTSUP, "the forced resident configuration does not fit");
         if (want == FTWA_PATH_RESIDENT && !can_res)
@@ -276,10 +277,20 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 e.Mc = Mc;
                 e.rho = static_cast<char*>(inst[k].rho) + (size_t)m0 * cplx_bytes(p.dtype);
                 e.ldr = inst[k].n_traj;
-                if ((st = padded_descriptors(inst[k].lat, ip.res.even_slots, ip.res.odd_slots,
-                                             (int)cplx_bytes(p.dtype),
-                                             resident_spins(g.config) == 1, &e.desc)) != FTWA_OK)
+                e.part_words = 0;
+                e.hmax = 0;
+                if (resident_parts(g.config) > 1) {
+                    if ((st = split_tables(inst[k].lat, resident_parts(g.config),
+                                           ip.res.even_slots, ip.res.odd_slots,
+                                           (int)cplx_bytes(p.dtype), &e.desc, &e.part_words,
+                                           &e.hmax)) != FTWA_OK)
+                        return st;
+                } else if ((st = padded_descriptors(inst[k].lat, ip.res.even_slots,
+                                                    ip.res.odd_slots, (int)cplx_bytes(p.dtype),
+                                                    resident_spins(g.config) == 1, &e.desc)) !=
+                           FTWA_OK) {
                     return st;
+                }
                 DeviceTables tab;
                 if ((st = device_tables(inst[k].lat, &tab)) != FTWA_OK) return st;
                 e.ord = tab.ord;

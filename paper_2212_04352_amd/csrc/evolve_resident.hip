@@ -750,6 +750,409 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     }
 }
 
+// ---------------------------------------------------------------- split kernel
+// A spin block too large for one CU (the 198-site block in FP64: 315 KB)
+// spread over G workgroups ("parts") of one XCD: part p owns the stored
+// elements of a strip of rows (sites in rank order, strips of nearly equal
+// element count) and keeps, besides its own elements, the "halo" its stencils
+// read from the neighbouring strips in LDS.  Every stage each part publishes
+// the next values of its exported elements (those another part reads, and
+// the diagonal, which the other spin's parts read for the U term) into a
+// per-part slot of global memory, and copies in its halo and the partner
+// spin's diagonal.  The two-phase stage stays: the even halo of a stage's
+// input was published in the producers' previous phase 1 and is copied at the
+// end of phase 1 (phase 2 reads it); the odd halo is published in the
+// producers' phase 2 (exported elements fill the leading entries, so they are
+// written first) and copied at the end of phase 2 together with the partner's
+// diagonal.  Every published 32-bit word travels with the number of the stage
+// it belongs to in one 64-bit relaxed agent-scope atomic (two alternating
+// slots by stage parity), so no fences are needed; the read-before-overwrite
+// order follows from the stencil's symmetry (a part that reads a neighbour's
+// even element is read back by that element's odd neighbours) and the
+// all-to-all diagonal exchange.  Waits are bounded.
+
+// Sub-dword-select shifts with the shift as a template argument.
+template <int SH> __device__ __forceinline__ uint32_t lo16_shl(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:WORD_0" : "=v"(r) : "v"(w), "i"(SH));
+    return r;
+}
+template <int SH> __device__ __forceinline__ uint32_t hi16_shl(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:WORD_1" : "=v"(r) : "v"(w), "i"(SH));
+    return r;
+}
+template <int SH> __device__ __forceinline__ uint32_t b2_shl(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:BYTE_2" : "=v"(r) : "v"(w), "i"(SH));
+    return r;
+}
+template <int SH> __device__ __forceinline__ uint32_t b3_shl(uint32_t w) {
+    uint32_t r;
+    __asm__("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD "
+            "src1_sel:BYTE_3" : "=v"(r) : "v"(w), "i"(SH));
+    return r;
+}
+
+// Compact descriptor of the split kernel: slot numbers x 2^SH bytes, diagonal
+// positions x 2^DSH bytes; xp (constant once the slot loop is unrolled): the
+// own field may carry the export flag (bit 15).
+template <int SH, int DSH, bool GEN>
+__device__ __forceinline__ Stencil decode_split(const uint4& w, bool xp) {
+    Stencil e;
+    const uint32_t f[3] = {w.x, w.y, w.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if constexpr (GEN) {
+            e.n[2 * k] = ((f[k] & 0x7fffu) << SH) | ((f[k] & 0x8000u) << 16);
+            e.n[2 * k + 1] = (((f[k] >> 16) & 0x7fffu) << SH) | (f[k] & 0x80000000u);
+        } else {
+            e.n[2 * k] = lo16_shl<SH>(f[k]);
+            e.n[2 * k + 1] = hi16_shl<SH>(f[k]);
+        }
+    }
+    e.own = xp ? (w.w & 0x7fffu) << SH : lo16_shl<SH>(w.w);
+    e.di = b2_shl<DSH>(w.w);
+    e.dj = b3_shl<DSH>(w.w);
+    return e;
+}
+
+template <typename T, bool OWN_REG, bool T1, int SH, int DSH>
+__device__ __forceinline__ cplx_t<T> element_rhs_split(bool gen, bool xp, const unsigned char* Yb,
+                                                       const unsigned char* Yd, const uint4& d,
+                                                       T t, T U, cplx_t<T> own) {
+    return gen ? element_rhs<T, OWN_REG, true, T1>(Yb, Yd, decode_split<SH, DSH, true>(d, xp), t, U, own)
+               : element_rhs<T, OWN_REG, false, T1>(Yb, Yd, decode_split<SH, DSH, false>(d, xp), t, U, own);
+}
+
+// A complex value as 32-bit payload words and back.
+template <typename T> struct Payload {
+    static constexpr int W = (int)sizeof(cplx_t<T>) / 4;
+    uint32_t w[W];
+};
+template <typename T> __device__ __forceinline__ Payload<T> to_payload(cplx_t<T> v) {
+    return __builtin_bit_cast(Payload<T>, v);
+}
+template <typename T> __device__ __forceinline__ cplx_t<T> from_payload(const Payload<T>& p) {
+    return __builtin_bit_cast(cplx_t<T>, p);
+}
+
+// Publishes a value: every payload word with the stage number in the high half.
+template <typename T>
+__device__ __forceinline__ void publish(uint64_t* dst, cplx_t<T> v, uint32_t stamp) {
+    const Payload<T> p = to_payload<T>(v);
+#pragma unroll
+    for (int k = 0; k < Payload<T>::W; ++k)
+        __hip_atomic_store(dst + k, ((uint64_t)stamp << 32) | p.w[k], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t peek(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Payload of a published word once it carries stage `want` (bounded wait:
+// false and the abort flag set when it never comes).
+__device__ __forceinline__ uint32_t settle(const uint64_t* p, uint64_t w, uint32_t want, int& abort_flag,
+                                           int* error) {
+    unsigned it = 0;
+    while ((uint32_t)(w >> 32) != want) {
+        if (*reinterpret_cast<volatile int*>(&abort_flag)) return 0;  // another wait timed out
+        if (++it >= kSpinLimit) {
+            abort_flag = 1;
+            atomicExch(error, 1);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        w = peek(p);
+    }
+    return (uint32_t)w;
+}
+
+// T1: every instance of the launch has t = 1.  XE, XO: leading even and odd
+// slots that may hold exported elements.
+template <typename T, int G, int NTU, int UE, int UO, int GE, int GO, int XE, int XO, bool T1>
+__global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
+    using C = cplx_t<T>;
+    constexpr int CB = (int)sizeof(C);
+    constexpr int TB = (int)sizeof(T);
+    constexpr int SH = CB == 8 ? 3 : 4;   // slot number -> byte offset
+    constexpr int DSH = TB == 4 ? 2 : 3;  // diagonal position -> byte offset
+    constexpr int W = Payload<T>::W;      // published words per element
+    constexpr int kEnt = NTU * (UE + UO); // descriptor entries of a part
+    constexpr int kEvenPad = NTU * UE;
+    constexpr uint32_t kDiagCopy = 256 * TB;
+    constexpr int kBatch = 4;             // halo copies in flight per thread
+    static_assert(XE <= UE && XO <= UO && GE <= UE && GO <= UO, "leading slots within the class");
+    extern __shared__ __align__(16) unsigned char smem[];
+    (void)smem;
+    const int tid0 = threadIdx.x;
+
+    // groups of 2G workgroups on one XCD (blocks b = xcd + 8 k; members k =
+    // 2G c .. 2G c + 2G - 1): spin = member / G, part = member % G; the
+    // groups take items (trajectories) in the same order
+    const int b = blockIdx.x, xcd = b % 8, k = b / 8;
+    const int member = k % (2 * G);
+    const int spin0 = member / G, part = member % G;
+    const int group = (k / (2 * G)) * 8 + xcd;
+    const int64_t n_groups = gridDim.x / (2 * G);
+    if (tid0 == 0) *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU / 64) * 2 * 8)) = 0;
+    // published words of this group: [2 spins][G parts][2 parities][kEnt][W]
+    uint64_t* const xg = A.mailbox + (size_t)group * 2 * G * 2 * kEnt * W;
+    auto xslot = [&](int spin, int q, uint32_t stamp) {
+        return xg + ((size_t)(spin * G + q) * 2 + (stamp & 1)) * kEnt * W;
+    };
+    int64_t g = 0;  // stage counter (continues across items)
+
+    C y[UE + UO], acc[UE + UO], hold[UE];
+
+    for (int64_t item = group; item < A.n_items; item += n_groups) {
+        const int t = tid0;
+        const uint32_t toff = (uint32_t)t * 16u;
+        int ent = 0;
+        while (ent + 1 < A.n_entries && A.table[ent + 1].item0 <= item) ++ent;
+        ent = __builtin_amdgcn_readfirstlane(ent);
+        const ResidentInst& E = A.table[ent];
+        const int N = E.N;
+        const int P = E.P;
+        const int pw = __builtin_amdgcn_readfirstlane(E.part_words);
+        const int hmax = __builtin_amdgcn_readfirstlane(E.hmax);
+        const uint32_t* const blob = reinterpret_cast<const uint32_t*>(uniform64((uint64_t)E.desc));
+        const uint32_t* const pb = blob + (size_t)part * pw;
+        const int n_even = __builtin_amdgcn_readfirstlane((int)pb[0]);
+        const int n_own = __builtin_amdgcn_readfirstlane((int)pb[1]);
+        const int n_ie = __builtin_amdgcn_readfirstlane((int)pb[2]);
+        const int n_io = __builtin_amdgcn_readfirstlane((int)pb[3]);
+        const int n_diag = __builtin_amdgcn_readfirstlane((int)pb[4]);
+        (void)n_even;
+        gdesc_t desc = (gdesc_t)uniform64((uint64_t)(pb + 8));
+        const uint32_t* const pord = pb + 8 + 4 * kEnt;
+        const uint32_t* const imp = pord + kEnt;
+        const uint32_t* const dsite = imp + hmax;
+        const uint32_t* const dsrc = blob + (size_t)G * pw;
+        unsigned char* const Yb = lds_ptr(2 * kDiagCopy);
+        unsigned char* const dpart = lds_ptr(0);
+        int& abort_flag = *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU / 64) * 2 * 8));
+        const int64_t Mc = E.Mc;
+        const int64_t m = item - E.item0;
+        const bool active = m < Mc;
+        C* const rho = reinterpret_cast<C*>(uniform64((uint64_t)E.rho));
+        const int64_t ldr = E.ldr;
+        double* const Xrec = E.X;
+        auto own_slot_at = [&](gdesc_t dt, int e) -> uint32_t {
+            return reinterpret_cast<const uint4*>((uint64_t)dt)[e].w & 0x7fffu;
+        };
+        // packed index of stored element a | b << 16 (conjugated when b < a)
+        auto packed_ab = [&](uint32_t ab, bool& transposed) -> int64_t {
+            const int a = (int)(ab & 0xffffu), bb = (int)(ab >> 16);
+            const int i = a < bb ? a : bb, j = a < bb ? bb : a;
+            transposed = a > bb;
+            return (int64_t)i * N - (int64_t)i * (i - 1) / 2 + (j - i);
+        };
+        auto load_elem = [&](uint32_t ab) -> C {
+            C v;
+            v.x = 0;
+            v.y = 0;
+            if (active) {
+                bool tr;
+                const int64_t p = packed_ab(ab, tr);
+                v = rho[((int64_t)spin0 * P + p) * ldr + m];
+                if (tr) v.y = -v.y;
+            }
+            return v;
+        };
+        __syncthreads();  // the previous item is done with LDS
+
+        // ---- the trajectory's own elements, the halo, the zero and scratch
+        // slots, and the partner's diagonal
+#pragma unroll
+        for (int u = 0; u < UE + UO; ++u) {
+            const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
+            const uint32_t own = own_slot_at(desc, e);
+            C v;
+            v.x = 0;
+            v.y = 0;
+            if (own < (uint32_t)n_own) v = load_elem(pord[own]);
+            reinterpret_cast<C*>(Yb)[own] = v;
+            y[u] = v;
+            acc[u] = v;
+            if (u < UE) hold[u] = v;
+        }
+        for (int h = t; h < n_ie + n_io; h += NTU) {
+            const uint32_t qs = imp[h];
+            const uint32_t* const pq = blob + (size_t)(qs >> 16) * pw + 8 + 4 * kEnt;
+            reinterpret_cast<C*>(Yb)[n_own + h] = load_elem(pq[qs & 0xffffu]);
+        }
+        if (t < 33) {
+            C z;
+            z.x = 0;
+            z.y = 0;
+            reinterpret_cast<C*>(Yb)[n_own + n_ie + n_io + t] = z;
+        }
+        const int32_t* const dpos = reinterpret_cast<const int32_t*>(uniform64((uint64_t)E.dpos));
+        for (int i = t; i < N; i += NTU) {
+            const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
+            const int q = dpos[i];
+            reinterpret_cast<T*>(dpart + (size_t)(g & 1) * kDiagCopy)[q] =
+                active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
+            reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * kDiagCopy)[q] = (T)0;
+        }
+        // records: even entry t < n_diag is the diagonal element of site dsite[t]
+        auto record = [&](int64_t r) {
+            if (active && t < n_diag)
+                Xrec[(r * 2 * N + (int64_t)spin0 * N + (int64_t)dsite[t]) * Mc + m] = (double)y[0].x;
+        };
+        record(0);
+        __syncthreads();
+
+        const T tw = uniform_real<T>((T)E.t), Uw = uniform_real<T>((T)E.U);
+        const T c_half = uniform_real<T>((T)(0.5 * A.dt));
+        const T c_full = uniform_real<T>((T)A.dt);
+        const T c_sixth = uniform_real<T>((T)(A.dt / 6.0));
+        bool first = true;  // the item's first stage: its halo came from HBM
+
+        // copies halo entries [h0, h1) carrying stage `want` into their slots
+        auto copy_halo = [&](int h0, int h1, uint32_t want) {
+            for (int h = h0 + t; h < h1; h += kBatch * NTU) {
+                uint64_t w[kBatch][W];
+                const uint64_t* src[kBatch];
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    const int hj = h + j * NTU < h1 ? h + j * NTU : h;
+                    const uint32_t qs = imp[hj];
+                    src[j] = xslot(spin0, (int)(qs >> 16), want) + (size_t)(qs & 0xffffu) * W;
+#pragma unroll
+                    for (int kk = 0; kk < W; ++kk) w[j][kk] = peek(src[j] + kk);
+                }
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    if (h + j * NTU >= h1) break;
+                    Payload<T> p;
+#pragma unroll
+                    for (int kk = 0; kk < W; ++kk)
+                        p.w[kk] = settle(src[j] + kk, w[j][kk], want, abort_flag, A.error);
+                    reinterpret_cast<C*>(Yb)[n_own + h + j * NTU] = from_payload<T>(p);
+                }
+            }
+        };
+
+        auto run_stage = [&](auto stage_tag) -> bool {
+            constexpr int STAGE = decltype(stage_tag)::value;
+            const T c = STAGE <= 2 ? c_half : (STAGE == 3 ? c_full : c_sixth);
+            const unsigned char* dcur = dpart + ((STAGE - 1) & 1) * kDiagCopy;
+            const uint32_t stamp = (uint32_t)(g + 1);
+            uint64_t* const mine = xslot(spin0, part, stamp);
+            desc = launder(desc);
+            const __amdgpu_buffer_rsrc_t drs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)desc, (short)0, (int)(kEnt * 16), 0x00020000);
+            constexpr int KP = 2;
+            auto entry_of = [](int v) { return v < UE ? NTU * v : kEvenPad + NTU * (v - UE); };
+            uint4 dq[KP];
+#pragma unroll
+            for (int v = 0; v < KP; ++v) dq[v] = slot_desc_buf<uint4>(drs, entry_of(v < UE + UO ? v : UE + UO - 1), toff);
+            // ---------------- phase 1: even elements (next values held)
+#pragma unroll
+            for (int u = 0; u < UE; ++u) {
+                const uint4 d = dq[u % KP];
+                if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<uint4>(drs, entry_of(u + KP), toff);
+                const C own = STAGE == 1 ? y[u] : hold[u];
+                const bool xp = u < XE;
+                const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
+                *reinterpret_cast<C*>(Yb + ob) = own;
+                const C kk = element_rhs_split<T, true, T1, SH, DSH>(u < GE, xp, Yb, dcur, d, tw, Uw, own);
+                hold[u] = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
+                pin(hold[u]);
+                pin(acc[u]);
+                if constexpr (STAGE == 4) pin(y[u]);
+                if (xp && (d.w & 0x8000u))
+                    publish<T>(mine + (size_t)(d.w & 0x7fffu) * W, hold[u], stamp);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // the even halo of this stage's input (published in the
+            // producers' previous phase 1; read in phase 2)
+            if (!first) copy_halo(0, n_ie, (uint32_t)g);
+            __syncthreads();
+            // ---------------- phase 2: odd elements (written straight to LDS)
+#pragma unroll
+            for (int u = UE; u < UE + UO; ++u) {
+                const uint4 d = dq[u % KP];
+                if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<uint4>(drs, entry_of(u + KP), toff);
+                const bool xp = u - UE < XO;
+                const C kk = STAGE == 1
+                    ? element_rhs_split<T, true, T1, SH, DSH>(u - UE < GO, xp, Yb, dcur, d, tw, Uw, y[u])
+                    : element_rhs_split<T, false, T1, SH, DSH>(u - UE < GO, xp, Yb, dcur, d, tw, Uw, y[u]);
+                const C nx = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
+                const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
+                *reinterpret_cast<C*>(Yb + ob) = nx;
+                pin(acc[u]);
+                if constexpr (STAGE == 4) pin(y[u]);
+                if (xp && (d.w & 0x8000u)) publish<T>(mine + (size_t)(d.w & 0x7fffu) * W, nx, stamp);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // the odd halo and the partner's diagonal of the next stage's input
+            // (the diagonal into the copy this stage does not read)
+            {
+                uint64_t dw[W];
+                const uint64_t* dsrcp = nullptr;
+                if (t < N) {
+                    const uint32_t qs = dsrc[t];
+                    dsrcp = xslot(1 - spin0, (int)(qs >> 16), stamp) + (size_t)(qs & 0xffffu) * W;
+#pragma unroll
+                    for (int kk = 0; kk < W; ++kk) dw[kk] = peek(dsrcp + kk);
+                }
+                copy_halo(n_ie, n_ie + n_io, stamp);
+                if (t < N) {
+                    Payload<T> p;
+#pragma unroll
+                    for (int kk = 0; kk < W; ++kk) p.w[kk] = settle(dsrcp + kk, dw[kk], stamp, abort_flag, A.error);
+                    reinterpret_cast<T*>(dpart + (STAGE & 1) * kDiagCopy)[dpos[t]] = from_payload<T>(p).x;
+                }
+            }
+            __syncthreads();
+            ++g;
+            first = false;
+            return abort_flag == 0;
+        };
+
+        auto store_state = [&](C* out) {
+            const gdesc_t dl = launder(desc);
+            out = reinterpret_cast<C*>(uniform64((uint64_t)out));
+            if (!active) return;
+#pragma unroll
+            for (int u = 0; u < UE + UO; ++u) {
+                const int e = u < UE ? t + NTU * u : kEvenPad + t + NTU * (u - UE);
+                const uint32_t own = own_slot_at(dl, e);
+                if (own < (uint32_t)n_own) {
+                    bool tr;
+                    const int64_t p = packed_ab(pord[own], tr);
+                    C v = y[u];
+                    if (tr) v.y = -v.y;
+                    out[((int64_t)spin0 * P + p) * ldr + m] = v;
+                }
+            }
+        };
+
+        for (int64_t step = 1; step <= A.n_steps; ++step) {
+            if (!run_stage(stage_c<1>{})) return;
+            if (!run_stage(stage_c<2>{})) return;
+            if (!run_stage(stage_c<3>{})) return;
+            if (!run_stage(stage_c<4>{})) return;
+            if (step % A.record_every == 0) {
+                const int64_t r = step / A.record_every;
+                record(r);
+                if constexpr (!T1) {
+                    C* const dump = reinterpret_cast<C*>(uniform64((uint64_t)E.dump));
+                    if (dump) store_state(dump + (r - 1) * E.dump_stride);
+                }
+            }
+        }
+        store_state(rho);
+    }
+}
+
 // ---------------------------------------------------------------- configurations
 // GE, GO: the leading even and odd slots that take the general path (the
 // elements that read a transpose must fit in them).
@@ -759,6 +1162,8 @@ struct Config {
     int S, NTU, UNITS, UE, UO, GE, GO;
     const void* fn;
     const void* fn_t1;
+    int G = 1;         // workgroups per spin block (> 1: the split kernel)
+    int XE = 0, XO = 0;  // split: leading even and odd slots that may hold exported elements
 };
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
@@ -773,6 +1178,19 @@ constexpr const void* unit_hop_fn() {
     Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                                    \
            (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
            unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
+
+template <typename T, int G, int NTU, int UE, int UO, int GE, int GO, int XE, int XO>
+constexpr const void* split_unit_hop_fn() {
+    if constexpr (std::is_same<T, float>::value)
+        return (const void*)&rk4_split<T, G, NTU, UE, UO, GE, GO, XE, XO, true>;
+    else
+        return nullptr;
+}
+
+#define FTWA_SPLIT_CFG(T, DT, G, NTU, UE, UO, GE, GO, XE, XO)                          \
+    Config{DT, 1, NTU, 1, UE, UO, GE, GO,                                                \
+           (const void*)&rk4_split<T, G, NTU, UE, UO, GE, GO, XE, XO, false>,           \
+           split_unit_hop_fn<T, G, NTU, UE, UO, GE, GO, XE, XO>(), G, XE, XO}
 
 const Config kConfigs[] = {
     FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1, 1, 1),
@@ -795,11 +1213,14 @@ const Config kConfigs[] = {
     FTWA_RES_CFG(float, FTWA_F32, 2, 128, 8, 2, 2, 1, 1),
     FTWA_RES_CFG(float, FTWA_F32, 2, 256, 4, 3, 3, 1, 1),
     FTWA_RES_CFG(float, FTWA_F32, 2, 512, 1, 5, 5, 1, 1),
+    // spin blocks split over workgroups (FP64 blocks larger than one CU)
+    FTWA_SPLIT_CFG(double, FTWA_F64, 2, 768, 4, 4, 1, 1, 2, 2),
+    FTWA_SPLIT_CFG(double, FTWA_F64, 3, 768, 5, 5, 1, 1, 2, 2),
 };
 
 // Order of preference of the first-fit choice (a tile with fewer general
 // slots before the same tile with more; indices are those of kConfigs).
-const int kPreference[] = {0, 13, 1, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11, 12};
+const int kPreference[] = {0, 13, 1, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11, 12, 19, 20};
 static_assert(sizeof(kPreference) == sizeof(kConfigs) / sizeof(kConfigs[0]) * sizeof(int),
               "every configuration has a place in the preference order");
 
@@ -817,33 +1238,60 @@ size_t lds_blocks(const Config& c, int N, int P) {
 }
 size_t lds_tail(const Config& c) { return (size_t)(c.NTU * c.UNITS / 64) * 2 * c.S * 8 + 16; }
 size_t lds_bytes(const Config& c, int N, int P) { return lds_blocks(c, N, P) + lds_tail(c); }
+// The split kernel: two copies of the partner's diagonal, then the owned and
+// halo elements, 32 zero slots and the scratch slot of the largest part.
+size_t split_lds_bytes(const Config& c, int max_slots) {
+    const size_t cb = c.dtype == FTWA_F64 ? 16 : 8;
+    const size_t b = 2 * 256 * (cb / 2) + (size_t)(max_slots + 33) * cb;
+    return (b + 15) / 16 * 16 + lds_tail(c);
+}
+// Published words per element of the split kernel, and per group of 2G
+// workgroups: [2 spins][G parts][2 parities][entries][words].
+int64_t split_words(const Config& c) {
+    const int64_t w = c.dtype == FTWA_F64 ? 4 : 2;
+    return 2 * (int64_t)c.G * 2 * (int64_t)c.NTU * (c.UE + c.UO) * w;
+}
 
 }  // namespace
 
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
-                   int force_config) {
+                   int force_config, bool allow_split) {
     if (!tab.bipartite) return false;
     const int P = (int)packed_count(N);
     const int n_even = (int)tab.n_even, n_odd = P - n_even;
-    if (P + 33 > 0x7fff) return false;
     const int n_cfg = (int)(sizeof(kConfigs) / sizeof(kConfigs[0]));
     for (int o = 0; o < n_cfg; ++o) {
         const int k = kPreference[o];
         if (force_config >= 0 && k != force_config) continue;
         const Config& c = kConfigs[k];
         if (c.dtype != dtype) continue;
-        if ((int64_t)c.NTU * c.UE < n_even || (int64_t)c.NTU * c.UO < n_odd) continue;
-        if ((int64_t)c.NTU * c.GE < tab.n_gen_even || (int64_t)c.NTU * c.GO < tab.n_gen_odd)
-            continue;
-        if (lds_bytes(c, N, P) > kMaxLds) continue;
         if (N > c.NTU) continue;  // the diagonal must sit in slot 0
+        size_t lds;
+        if (c.G > 1) {
+            // the split kernel: every part must fit (no invariant sums)
+            if (!allow_split || N > 256) continue;
+            const SplitShape& sh = tab.split[c.G];
+            const int64_t n = c.NTU;
+            if (n * c.UE < sh.max_even || n * c.UO < sh.max_odd) continue;
+            if (n * c.GE < sh.gen_even || n * c.GO < sh.gen_odd) continue;
+            if (n * c.XE < sh.x_even || n * c.XO < sh.x_odd) continue;
+            if (sh.max_slots + 33 > 0x7fff) continue;
+            lds = split_lds_bytes(c, sh.max_slots);
+        } else {
+            if (P + 33 > 0x7fff) continue;
+            if ((int64_t)c.NTU * c.UE < n_even || (int64_t)c.NTU * c.UO < n_odd) continue;
+            if ((int64_t)c.NTU * c.GE < tab.n_gen_even || (int64_t)c.NTU * c.GO < tab.n_gen_odd)
+                continue;
+            lds = lds_bytes(c, N, P);
+        }
+        if (lds > kMaxLds) continue;
         plan->config = k;
         plan->spins_per_unit = c.S;
         plan->threads = c.NTU * c.UNITS;
         plan->units = c.UNITS;
         plan->even_slots = (int64_t)c.NTU * c.UE;
         plan->odd_slots = (int64_t)c.NTU * c.UO;
-        plan->lds = lds_bytes(c, N, P);
+        plan->lds = lds;
         return true;
     }
     return false;
@@ -852,6 +1300,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
 int resident_config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
 
 int resident_spins(int config) { return kConfigs[config].S; }
+int resident_parts(int config) { return kConfigs[config].G; }
 
 int64_t resident_item_traj(int config) {
     const Config& c = kConfigs[config];
@@ -886,9 +1335,20 @@ int64_t resident_max_pairs() {
     return pairs < 8 ? 8 : pairs;
 }
 
+// Groups of 2G split workgroups resident together: whole groups per XCD.
+int64_t split_max_groups(int G) {
+    const int64_t per_xcd = (int64_t)device_cus() / 8 / (2 * G);
+    return 8 * (per_xcd < 1 ? 1 : per_xcd);
+}
+
+// Trajectories (items) a spin-split launch runs at once, and its grid.
+int64_t spin_split_slots(const Config& c) {
+    return c.G > 1 ? split_max_groups(c.G) : resident_max_pairs();
+}
+
 int64_t resident_concurrency(int config, size_t lds) {
     const Config& c = kConfigs[config];
-    if (c.S == 1) return resident_max_pairs();
+    if (c.S == 1) return spin_split_slots(c);
     // the occupancy query honours the dynamic-LDS limit of the kernel
     if (resident_prepare(config, kMaxLds) != FTWA_OK) return (int64_t)device_cus() * c.UNITS;
     int per_cu = 1;
@@ -901,25 +1361,32 @@ int64_t resident_concurrency(int config, size_t lds) {
 int64_t resident_grid(int config, size_t lds, int64_t n_items) {
     const Config& c = kConfigs[config];
     if (c.S == 1) {
-        const int64_t pairs = std::min((n_items + 7) / 8 * 8, resident_max_pairs());
-        return 2 * pairs;
+        const int64_t units = std::min((n_items + 7) / 8 * 8, spin_split_slots(c));
+        return 2 * (int64_t)c.G * units;
     }
     const int64_t cap = resident_concurrency(config, lds) / c.UNITS;
     return std::max<int64_t>(1, std::min(n_items, cap));
 }
 
 // Spin-split scratch of one launch: the mailbox words, then the error word.
+// (split kernel: the published words of every group, then the error word)
+size_t mailbox_words(const Config& c, int Nmax, int64_t grid) {
+    if (c.G > 1) return (size_t)(grid / (2 * c.G)) * (size_t)split_words(c);
+    return (size_t)(grid / 2) * 2 * 2 * Nmax;
+}
+
 size_t resident_mailbox_bytes(int config, int Nmax, int64_t n_items) {
-    if (kConfigs[config].S != 1) return 0;
-    const int64_t pairs = resident_grid(config, 0, n_items) / 2;
-    return (size_t)pairs * 2 * 2 * Nmax * sizeof(uint64_t) + 64;
+    const Config& c = kConfigs[config];
+    if (c.S != 1) return 0;
+    return mailbox_words(c, Nmax, resident_grid(config, 0, n_items)) * sizeof(uint64_t) + 64;
 }
 
 int* resident_error_word(int config, int Nmax, int64_t n_items, void* mailbox) {
-    if (kConfigs[config].S != 1) return nullptr;
-    const int64_t pairs = resident_grid(config, 0, n_items) / 2;
+    const Config& c = kConfigs[config];
+    if (c.S != 1) return nullptr;
     return reinterpret_cast<int*>(static_cast<char*>(mailbox) +
-                                  (size_t)pairs * 2 * 2 * Nmax * sizeof(uint64_t));
+                                  mailbox_words(c, Nmax, resident_grid(config, 0, n_items)) *
+                                      sizeof(uint64_t));
 }
 
 
@@ -944,7 +1411,7 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,
         // no memset node)
         ftwa_status st = zero_words(static_cast<unsigned*>(L.mailbox),
-                                    (grid / 2) * 2 * 2 * (int64_t)L.Nmax * 2, stream);
+                                    (int64_t)mailbox_words(c, L.Nmax, grid) * 2, stream);
         if (st != FTWA_OK) return st;
         // both workgroups of a pair must be resident at the same time: the
         // grid never exceeds one workgroup per CU; a cooperative launch checks

@@ -16,6 +16,17 @@ namespace ftwa {
 
 constexpr int kMaxDeg = 3;
 constexpr int kMaxSites = 255;
+constexpr int kMaxParts = 4;  // workgroups per spin block of the split resident kernel
+
+// What a split configuration (one spin block over G workgroups, "parts") must
+// hold for a lattice: the maxima over its parts.
+struct SplitShape {
+    int max_even = 0, max_odd = 0;  // owned elements of each class
+    int gen_even = 0, gen_odd = 0;  // leading entries of each class that read a transpose
+    int x_even = 0, x_odd = 0;      // leading entries holding every exported element
+    int max_slots = 0;              // owned plus halo elements
+    int max_halo = 0;               // halo elements
+};
 
 // Index tables of a lattice on one device (uploaded once, owned by the handle).
 struct DeviceTables {
@@ -31,6 +42,7 @@ struct DeviceTables {
     int32_t* dpos = nullptr;   // [N]: site -> its position in the sublattice-major
                                // diagonal (the sites of one sublattice, ascending,
                                // then the other's)
+    SplitShape split[kMaxParts + 1];  // by part count G = 2..kMaxParts (bipartite only)
 };
 
 // Stencil descriptor of one element for the resident kernel.  Of every pair
@@ -74,6 +86,10 @@ struct ftwa_lattice_s {
     std::map<std::tuple<int, int64_t, int64_t, int>, void*> padded;
     std::vector<uint32_t> class_order;      // a | b << 16 of the stored elements in LDS-slot order
     std::vector<int32_t> diag_pos;          // site -> sublattice-major diagonal position
+    std::vector<int32_t> rank;              // site -> bandwidth-reducing rank
+    // split-kernel tables by (device, parts, even slots, odd slots, element
+    // bytes): device blob, words per part, import capacity
+    std::map<std::tuple<int, int, int64_t, int64_t, int>, std::tuple<void*, int, int>> split;
 };
 
 namespace ftwa {
@@ -119,6 +135,19 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
 // size and form.
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
                                int elem_bytes, bool compact, const void** out);
+
+// Tables of the split resident kernel for G parts (uploaded once per shape).
+// One block of *part_words 32-bit words per part:
+//   [0..7]   n_even, n_own, n_import_even, n_import_odd, n_diag, 0, 0, 0
+//   [8..)    descriptors (compact form, 16 bytes per entry, even_slots +
+//            odd_slots entries; own field bit 15: the element is exported)
+//   then     LDS slot -> a | b << 16 of the owned element (even_slots + odd_slots words)
+//   then     imports: producer part << 16 | producer slot, *hmax words
+//            (halo slot n_own + h takes import h; even halo first)
+//   then     the site of even entry t < n_diag (its diagonal element)
+// then, after the G blocks, [N]: site -> part << 16 | slot of its diagonal element.
+ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t odd_slots,
+                         int elem_bytes, const void** out, int* part_words, int* hmax);
 
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
@@ -197,6 +226,8 @@ struct ResidentInst {
                          // dump + (r - 1) * dump_stride elements (same layout and window
                          // offset as rho)
     int64_t dump_stride;
+    int part_words;      // split configurations: desc is split_tables(...), one block per
+    int hmax;            // part of part_words words; hmax: import capacity
 };
 struct ResidentLaunch {
     int config;
@@ -216,10 +247,13 @@ struct ResidentLaunch {
     bool dumps;                 // an entry stores its state at records (ResidentInst::dump)
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).
+// allow_split: the split configurations may be chosen (they keep no
+// invariant sums).
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
-                   int force_config = -1);
+                   int force_config = -1, bool allow_split = true);
 int resident_config_count();
 int resident_spins(int config);
+int resident_parts(int config);  // workgroups per spin block (> 1: split tables)
 int64_t resident_item_traj(int config);      // trajectories per item of the schedule
 int64_t resident_max_pairs();
 int64_t resident_concurrency(int config, size_t lds);  // trajectories in flight at once

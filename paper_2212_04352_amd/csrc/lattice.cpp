@@ -247,6 +247,10 @@ void ftwa_free_lattice(ftwa_lattice lat) {
         if (hipSetDevice(std::get<0>(key)) != hipSuccess) continue;
         (void)hipFree(ptr);
     }
+    for (auto& [key, val] : lat->split) {
+        if (hipSetDevice(std::get<0>(key)) != hipSuccess) continue;
+        (void)hipFree(std::get<0>(val));
+    }
     if (cur >= 0) (void)hipSetDevice(cur);
     delete lat;
 }
@@ -305,7 +309,7 @@ namespace ftwa {
 // non-bipartite graph.
 bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* n_even,
                        std::vector<int32_t>* diag_pos, int64_t* n_gen_even,
-                       int64_t* n_gen_odd) {
+                       int64_t* n_gen_odd, std::vector<int32_t>* rank_out) {
     const int N = lat->N;
     std::vector<int> colour(N, -1);
     for (int root = 0; root < N; ++root) {
@@ -378,7 +382,307 @@ bool build_class_order(ftwa_lattice lat, std::vector<uint32_t>* order, int64_t* 
         order->insert(order->end(), rest.begin(), rest.end());
         if (cls == 0) *n_even = (int64_t)order->size();
     }
+    rank_out->assign(rank.begin(), rank.end());
     return true;
+}
+
+namespace {
+
+// One part of the split layout of a spin block (see split_tables).
+struct SplitPart {
+    std::vector<int64_t> even, odd;  // owned elements (class-order indices) in entry order
+    std::vector<int64_t> halo;       // elements read from other parts, even class first,
+                                     // then by producer part and producer slot
+    int n_halo_even = 0;
+    int n_diag = 0;                  // leading even entries: the diagonal of the part's rows
+    int gen_even = 0, gen_odd = 0;   // leading entries that read a transpose
+    int x_even = 0, x_odd = 0;       // leading entries holding every exported element
+};
+
+// The rows of the stored elements (sites in rank order; the stored element
+// rho_ab has rank a <= rank b and belongs to row a) cut into G strips of
+// nearly equal element count; part p owns the elements of strip p.  An
+// element is exported when a stencil of another part reads it, and every
+// diagonal element is (the other spin's U term reads it).  Within a class the
+// entries are ordered: the diagonal (even class), the elements that read a
+// transpose, the other exported elements, the rest, each group in class
+// order.
+std::vector<SplitPart> split_layout(const ftwa_lattice_s& L, int G, int64_t n_even,
+                                    int64_t n_gen_even, int64_t n_gen_odd) {
+    const int N = L.N;
+    const std::vector<uint32_t>& order = L.class_order;
+    const int64_t P = packed_count(N), n = (int64_t)order.size();
+    std::vector<int> strip(N);
+    int64_t before = 0;
+    for (int r = 0; r < N; ++r) {
+        const int64_t mid2 = 2 * before + (N - r);  // twice the row's middle element
+        strip[r] = (int)std::min<int64_t>(G - 1, mid2 * G / (2 * P));
+        before += N - r;
+    }
+    std::vector<int64_t> q_of((size_t)P);
+    for (int64_t q = 0; q < n; ++q) {
+        const int a = (int)(order[q] & 0xffffu), b = (int)(order[q] >> 16);
+        const int i = std::min(a, b), j = std::max(a, b);
+        q_of[(size_t)(packed_row(N, i) + (j - i))] = q;
+    }
+    auto q_at = [&](int x, int y) {
+        const int i = std::min(x, y), j = std::max(x, y);
+        return q_of[(size_t)(packed_row(N, i) + (j - i))];
+    };
+    auto part_of = [&](int64_t q) { return strip[L.rank[order[q] & 0xffffu]]; };
+    std::vector<uint8_t> exported((size_t)n, 0);
+    std::vector<std::vector<uint8_t>> in_halo(G, std::vector<uint8_t>((size_t)n, 0));
+    std::vector<SplitPart> parts(G);
+    for (int64_t q = 0; q < n; ++q) {
+        const int a = (int)(order[q] & 0xffffu), b = (int)(order[q] >> 16);
+        const int pe = part_of(q);
+        auto touch = [&](int64_t r) {
+            if (part_of(r) == pe) return;
+            exported[(size_t)r] = 1;
+            if (!in_halo[pe][(size_t)r]) {
+                in_halo[pe][(size_t)r] = 1;
+                parts[pe].halo.push_back(r);
+            }
+        };
+        for (int k = 0; k < L.deg[b]; ++k) touch(q_at(a, L.nbr[(size_t)b * kMaxDeg + k]));
+        for (int k = 0; k < L.deg[a]; ++k) touch(q_at(L.nbr[(size_t)a * kMaxDeg + k], b));
+    }
+    for (int i = 0; i < N; ++i) exported[(size_t)i] = 1;  // (i,i) sits at class-order index i
+    for (int p = 0; p < G; ++p) {
+        SplitPart& sp = parts[p];
+        std::vector<int64_t> rest_e, rest_o;
+        for (int64_t q = 0; q < n; ++q) {
+            if (part_of(q) != p) continue;
+            if (q < N) sp.even.push_back(q);
+            else if (q < n_even) rest_e.push_back(q);
+            else rest_o.push_back(q);
+        }
+        sp.n_diag = (int)sp.even.size();
+        auto rank_key = [&](int64_t q, bool gen) { return (gen ? 0 : 2) + (exported[(size_t)q] ? 0 : 1); };
+        std::stable_sort(rest_e.begin(), rest_e.end(), [&](int64_t x, int64_t y) {
+            return rank_key(x, x < n_gen_even) < rank_key(y, y < n_gen_even);
+        });
+        std::stable_sort(rest_o.begin(), rest_o.end(), [&](int64_t x, int64_t y) {
+            return rank_key(x, x - n_even < n_gen_odd) < rank_key(y, y - n_even < n_gen_odd);
+        });
+        sp.even.insert(sp.even.end(), rest_e.begin(), rest_e.end());
+        sp.odd = rest_o;
+        for (size_t e = 0; e < sp.even.size(); ++e) {
+            if (sp.even[e] < n_gen_even) sp.gen_even = (int)e + 1;
+            if (exported[(size_t)sp.even[e]]) sp.x_even = (int)e + 1;
+        }
+        for (size_t e = 0; e < sp.odd.size(); ++e) {
+            if (sp.odd[e] - n_even < n_gen_odd) sp.gen_odd = (int)e + 1;
+            if (exported[(size_t)sp.odd[e]]) sp.x_odd = (int)e + 1;
+        }
+    }
+    // producer slots, then the halo order
+    std::vector<int> slot_q((size_t)n);
+    for (int p = 0; p < G; ++p) {
+        const SplitPart& sp = parts[p];
+        for (size_t e = 0; e < sp.even.size(); ++e) slot_q[(size_t)sp.even[e]] = (int)e;
+        for (size_t e = 0; e < sp.odd.size(); ++e)
+            slot_q[(size_t)sp.odd[e]] = (int)(sp.even.size() + e);
+    }
+    for (int p = 0; p < G; ++p) {
+        SplitPart& sp = parts[p];
+        auto hk = [&](int64_t q) {
+            return std::make_tuple(q >= n_even, part_of(q), slot_q[(size_t)q]);
+        };
+        std::sort(sp.halo.begin(), sp.halo.end(), [&](int64_t x, int64_t y) { return hk(x) < hk(y); });
+        sp.n_halo_even = 0;
+        for (int64_t q : sp.halo) sp.n_halo_even += q < n_even ? 1 : 0;
+    }
+    return parts;
+}
+
+SplitShape split_shape(const std::vector<SplitPart>& parts) {
+    SplitShape s;
+    for (const SplitPart& sp : parts) {
+        s.max_even = std::max(s.max_even, (int)sp.even.size());
+        s.max_odd = std::max(s.max_odd, (int)sp.odd.size());
+        s.gen_even = std::max(s.gen_even, sp.gen_even);
+        s.gen_odd = std::max(s.gen_odd, sp.gen_odd);
+        s.x_even = std::max(s.x_even, sp.x_even);
+        s.x_odd = std::max(s.x_odd, sp.x_odd);
+        s.max_halo = std::max(s.max_halo, (int)sp.halo.size());
+        s.max_slots =
+            std::max(s.max_slots, (int)(sp.even.size() + sp.odd.size() + sp.halo.size()));
+    }
+    return s;
+}
+
+}  // namespace
+
+ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t odd_slots,
+                         int elem_bytes, const void** out, int* part_words, int* hmax) {
+    DeviceTables tab;
+    ftwa_status st = device_tables(lat, &tab);
+    if (st != FTWA_OK) return st;
+    if (!tab.bipartite) return fail(FTWA_ENOTSUP, "lattice is not bipartite");
+    if (G < 2 || G > kMaxParts) return fail(FTWA_EINVAL, "split: part count out of range");
+    const int N = lat->N;
+    if (N > 256) return fail(FTWA_EINVAL, "split: more than 256 sites");
+    if (even_slots % 64 || odd_slots % 64) return fail(FTWA_EINVAL, "split: slots not whole waves");
+    int dev = 0;
+    FTWA_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(lat->mu);
+    const auto key = std::make_tuple(dev, G, even_slots, odd_slots, elem_bytes);
+    auto it = lat->split.find(key);
+    if (it != lat->split.end()) {
+        *out = std::get<0>(it->second);
+        *part_words = std::get<1>(it->second);
+        *hmax = std::get<2>(it->second);
+        return FTWA_OK;
+    }
+    const std::vector<uint32_t>& order = lat->class_order;
+    const int64_t n = (int64_t)order.size();
+    const std::vector<SplitPart> parts =
+        split_layout(*lat, G, tab.n_even, tab.n_gen_even, tab.n_gen_odd);
+    const int64_t E = even_slots + odd_slots;
+    int H = 1;
+    for (const SplitPart& sp : parts) H = std::max(H, (int)sp.halo.size());
+    const int64_t pw = (8 + 4 * E + E + H + 256 + 3) / 4 * 4;
+    std::vector<uint32_t> blob((size_t)(pw * G + N), 0u);
+    std::vector<int> part_q((size_t)n), slot_q((size_t)n);
+    for (int p = 0; p < G; ++p) {
+        const SplitPart& sp = parts[p];
+        if ((int64_t)sp.even.size() > even_slots || (int64_t)sp.odd.size() > odd_slots)
+            return fail(FTWA_EINVAL, "split: padding too small");
+        if (sp.even.size() + sp.odd.size() + sp.halo.size() + 33 > 0x7fff)
+            return fail(FTWA_EINVAL, "split: part too large for 15-bit slots");
+        for (size_t e = 0; e < sp.even.size(); ++e) {
+            part_q[(size_t)sp.even[e]] = p;
+            slot_q[(size_t)sp.even[e]] = (int)e;
+        }
+        for (size_t e = 0; e < sp.odd.size(); ++e) {
+            part_q[(size_t)sp.odd[e]] = p;
+            slot_q[(size_t)sp.odd[e]] = (int)(sp.even.size() + e);
+        }
+    }
+    std::vector<int64_t> q_of((size_t)packed_count(N));
+    for (int64_t q = 0; q < n; ++q) {
+        const int a = (int)(order[q] & 0xffffu), b = (int)(order[q] >> 16);
+        const int i = std::min(a, b), j = std::max(a, b);
+        q_of[(size_t)(packed_row(N, i) + (j - i))] = q;
+    }
+    // lanes that share one LDS pass and the slot residues that spread them
+    // over the banks: 64 banks of 4 bytes
+    const int R = 64 / (elem_bytes / 4);
+    std::vector<int> hslot((size_t)n, -1);
+    for (int p = 0; p < G; ++p) {
+        const SplitPart& sp = parts[p];
+        uint32_t* pb = blob.data() + (size_t)p * pw;
+        const int n_own = (int)(sp.even.size() + sp.odd.size());
+        const int Z0 = n_own + (int)sp.halo.size();
+        pb[0] = (uint32_t)sp.even.size();
+        pb[1] = (uint32_t)n_own;
+        pb[2] = (uint32_t)sp.n_halo_even;
+        pb[3] = (uint32_t)(sp.halo.size() - sp.n_halo_even);
+        pb[4] = (uint32_t)sp.n_diag;
+        std::fill(hslot.begin(), hslot.end(), -1);
+        for (size_t h = 0; h < sp.halo.size(); ++h) hslot[(size_t)sp.halo[h]] = n_own + (int)h;
+        struct Ref {
+            int slot;  // -1: missing neighbour (a zero slot)
+            bool conj;
+        };
+        auto ref = [&](int x, int y) -> Ref {
+            const int i = std::min(x, y), j = std::max(x, y);
+            const int64_t q = q_of[(size_t)(packed_row(N, i) + (j - i))];
+            const int a = (int)(order[q] & 0xffffu);
+            const bool conj = x != y && a != x;
+            const int s = part_q[(size_t)q] == p ? slot_q[(size_t)q] : hslot[(size_t)q];
+            return Ref{s, conj};
+        };
+        struct Ent {
+            Ref n[6];
+            int own;
+            bool exported;
+            int a, b;
+        };
+        std::vector<Ent> ent((size_t)E);
+        for (Ent& e : ent) {
+            for (int k = 0; k < 6; ++k) e.n[k] = Ref{-1, false};
+            e.own = Z0 + 32;  // padding entries own the scratch slot
+            e.exported = false;
+            e.a = e.b = -1;
+        }
+        std::vector<uint8_t> is_export((size_t)n, 0);
+        for (int pp = 0; pp < G; ++pp)
+            if (pp != p)
+                for (int64_t q : parts[pp].halo) is_export[(size_t)q] = 1;
+        for (int i = 0; i < N; ++i) is_export[(size_t)i] = 1;
+        auto fill = [&](int64_t q, int64_t at, bool gen) -> bool {
+            const int a = (int)(order[q] & 0xffffu), b = (int)(order[q] >> 16);
+            Ent& e = ent[(size_t)at];
+            for (int k = 0; k < kMaxDeg; ++k) {
+                if (k < lat->deg[b]) e.n[k] = ref(a, lat->nbr[(size_t)b * kMaxDeg + k]);
+                if (k < lat->deg[a]) e.n[3 + k] = ref(lat->nbr[(size_t)a * kMaxDeg + k], b);
+            }
+            for (int k = 0; k < 6; ++k) {
+                if (e.n[k].slot == -1 && ((k < 3 && k < lat->deg[b]) || (k >= 3 && k - 3 < lat->deg[a])))
+                    return false;  // a neighbour neither owned nor in the halo
+                if (e.n[k].conj && !gen) return false;
+            }
+            e.own = slot_q[(size_t)q];
+            e.exported = is_export[(size_t)q] != 0;
+            e.a = a;
+            e.b = b;
+            return true;
+        };
+        for (size_t k = 0; k < sp.even.size(); ++k)
+            if (!fill(sp.even[k], (int64_t)k, (int)k < sp.gen_even))
+                return fail(FTWA_ENOTSUP, "split: inconsistent stencil (even class)");
+        for (size_t k = 0; k < sp.odd.size(); ++k)
+            if (!fill(sp.odd[k], even_slots + (int64_t)k, (int)k < sp.gen_odd))
+                return fail(FTWA_ENOTSUP, "split: inconsistent stencil (odd class)");
+        // missing neighbours: the zero slot whose bank residue no other lane
+        // of the pass reads for that field
+        // (each class is a whole number of passes: even_slots is a multiple of 64)
+        for (int64_t c0 = 0; c0 < E; c0 += R) {
+            const int64_t c1 = std::min<int64_t>(c0 + R, E);
+            for (int k = 0; k < 6; ++k) {
+                uint32_t used = 0;
+                for (int64_t x = c0; x < c1; ++x)
+                    if (ent[(size_t)x].n[k].slot >= 0) used |= 1u << (ent[(size_t)x].n[k].slot % R);
+                int z = Z0;
+                for (int r = 0; r < 32; ++r)
+                    if (!(used >> ((Z0 + r) % R) & 1u)) { z = Z0 + r; break; }
+                for (int64_t x = c0; x < c1; ++x)
+                    if (ent[(size_t)x].n[k].slot < 0) ent[(size_t)x].n[k].slot = z;
+            }
+        }
+        uint32_t* dsc = pb + 8;
+        uint32_t* pord = dsc + 4 * E;
+        uint32_t* imp = pord + E;
+        uint32_t* dsite = imp + H;
+        auto f = [](const Ref& r) { return (uint32_t)r.slot | (r.conj ? 0x8000u : 0u); };
+        for (int64_t x = 0; x < E; ++x) {
+            const Ent& e = ent[(size_t)x];
+            const uint32_t pi = e.a < 0 ? 0u : (uint32_t)lat->diag_pos[e.a];
+            const uint32_t pj = e.b < 0 ? 0u : (uint32_t)lat->diag_pos[e.b];
+            dsc[4 * x + 0] = f(e.n[0]) | f(e.n[1]) << 16;
+            dsc[4 * x + 1] = f(e.n[2]) | f(e.n[3]) << 16;
+            dsc[4 * x + 2] = f(e.n[4]) | f(e.n[5]) << 16;
+            dsc[4 * x + 3] = (uint32_t)e.own | (e.exported ? 0x8000u : 0u) | pi << 16 | pj << 24;
+            if (e.a >= 0) pord[e.own] = (uint32_t)e.a | (uint32_t)e.b << 16;
+        }
+        for (size_t h = 0; h < sp.halo.size(); ++h) {
+            const int64_t q = sp.halo[h];
+            imp[h] = (uint32_t)part_q[(size_t)q] << 16 | (uint32_t)slot_q[(size_t)q];
+        }
+        for (int t = 0; t < sp.n_diag; ++t) dsite[t] = order[(size_t)sp.even[(size_t)t]] & 0xffffu;
+    }
+    uint32_t* dsrc = blob.data() + (size_t)G * pw;
+    for (int i = 0; i < N; ++i) dsrc[i] = (uint32_t)part_q[(size_t)i] << 16 | (uint32_t)slot_q[(size_t)i];
+    void* d = nullptr;
+    FTWA_HIP_TRY(hipMalloc(&d, blob.size() * sizeof(uint32_t)));
+    FTWA_HIP_TRY(hipMemcpy(d, blob.data(), blob.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    lat->split[key] = std::make_tuple(d, (int)pw, H);
+    *out = d;
+    *part_words = (int)pw;
+    *hmax = H;
+    return FTWA_OK;
 }
 
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
@@ -543,11 +847,16 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
     DeviceTables tab;
     std::vector<uint32_t> order;
     std::vector<int32_t> dpos;
-    tab.bipartite =
-        build_class_order(lat, &order, &tab.n_even, &dpos, &tab.n_gen_even, &tab.n_gen_odd);
+    std::vector<int32_t> rank;
+    tab.bipartite = build_class_order(lat, &order, &tab.n_even, &dpos, &tab.n_gen_even,
+                                      &tab.n_gen_odd, &rank);
     if (tab.bipartite) {
         lat->class_order = order;
         lat->diag_pos = dpos;
+        lat->rank = rank;
+        for (int G = 2; G <= kMaxParts; ++G)
+            tab.split[G] = split_shape(
+                split_layout(*lat, G, tab.n_even, tab.n_gen_even, tab.n_gen_odd));
         FTWA_HIP_TRY(hipMalloc(&tab.ord, order.size() * sizeof(uint32_t)));
         FTWA_HIP_TRY(hipMemcpy(tab.ord, order.data(), order.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice));
