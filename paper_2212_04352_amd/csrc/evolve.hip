@@ -281,7 +281,7 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 e.hmax = 0;
                 if (resident_parts(g.config) > 1) {
                     if ((st = split_tables(inst[k].lat, resident_parts(g.config),
-                                           ip.res.even_slots, ip.res.odd_slots,
+                                           ip.res.even_slots, ip.res.odd_slots, ip.res.bnd_entry,
                                            (int)cplx_bytes(p.dtype), &e.desc, &e.part_words,
                                            &e.hmax)) != FTWA_OK)
                         return st;

@@ -752,24 +752,30 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 
 // ---------------------------------------------------------------- split kernel
 // A spin block too large for one CU (the 198-site block in FP64: 315 KB)
-// spread over G workgroups ("parts") of one XCD: part p owns the stored
+// spread over G workgroups ("parts") placed on one XCD: part p owns the stored
 // elements of a strip of rows (sites in rank order, strips of nearly equal
 // element count) and keeps, besides its own elements, the "halo" its stencils
 // read from the neighbouring strips in LDS.  Every stage each part publishes
 // the next values of its exported elements (those another part reads, and
 // the diagonal, which the other spin's parts read for the U term) into a
-// per-part slot of global memory, and copies in its halo and the partner
-// spin's diagonal.  The two-phase stage stays: the even halo of a stage's
-// input was published in the producers' previous phase 1 and is copied at the
-// end of phase 1 (phase 2 reads it); the odd halo is published in the
-// producers' phase 2 (exported elements fill the leading entries, so they are
-// written first) and copied at the end of phase 2 together with the partner's
-// diagonal.  Every published 32-bit word travels with the number of the stage
-// it belongs to in one 64-bit relaxed agent-scope atomic (two alternating
-// slots by stage parity), so no fences are needed; the read-before-overwrite
-// order follows from the stencil's symmetry (a part that reads a neighbour's
-// even element is read back by that element's odd neighbours) and the
-// all-to-all diagonal exchange.  Waits are bounded.
+// per-part area of global memory, and copies in its halo and the partner
+// spin's diagonal.  Every published 32-bit word travels with the number of
+// the stage it belongs to in one 64-bit relaxed agent-scope atomic (two
+// areas alternating by stage parity), so no fences are needed; a word is
+// never overwritten before it is read because the stencil relation is
+// symmetric (a part that reads a neighbour's element is read back by it in
+// the other class) and the diagonal exchange is all-to-all, so no member of
+// a group runs two stages ahead of a reader.  Waits are bounded.
+//
+// The two-phase stage stays, with the waits placed where their data has had
+// the most time to arrive: the even elements of a part are ordered interior
+// (they read no other part's element) before boundary (the diagonal and the
+// exported ones).  The reads of both halos of a stage's input are issued at
+// the start of the stage; the odd halo (published early in the producers'
+// previous phase 2: exported odd elements come first) is needed only from the
+// boundary slots on, after a barrier; the even halo (published in the
+// producers' previous phase 1) before phase 2; the partner's diagonal of the
+// next stage's input is read during phase 2.
 
 // Sub-dword-select shifts with the shift as a template argument.
 template <int SH> __device__ __forceinline__ uint32_t lo16_shl(uint32_t w) {
@@ -840,7 +846,9 @@ template <typename T> __device__ __forceinline__ cplx_t<T> from_payload(const Pa
     return __builtin_bit_cast(cplx_t<T>, p);
 }
 
-// Publishes a value: every payload word with the stage number in the high half.
+// Publishes a value: every payload word with the stage number in the high
+// half, each a relaxed agent-scope atomic (a reader sees the old or the new
+// stage of a word, never a mixture).
 template <typename T>
 __device__ __forceinline__ void publish(uint64_t* dst, cplx_t<T> v, uint32_t stamp) {
     const Payload<T> p = to_payload<T>(v);
@@ -854,27 +862,42 @@ __device__ __forceinline__ uint64_t peek(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Payload of a published word once it carries stage `want` (bounded wait:
-// false and the abort flag set when it never comes).
-__device__ __forceinline__ uint32_t settle(const uint64_t* p, uint64_t w, uint32_t want, int& abort_flag,
-                                           int* error) {
+// Waits until NW published words carry stage `want`: w[k] was read from
+// src[k / WPE] + k % WPE (WPE = NW / NP, null pointers are skipped); while
+// any word is stale, all of them are read again (one round trip per retry).
+// Bounded: false (abort flag and error word set) when the stage never comes
+// or another wait of the workgroup gave up.
+template <int NW, int NP>
+__device__ __forceinline__ bool settle_words(const uint64_t* const* src, uint64_t* w, uint32_t want,
+                                             int& abort_flag, int* error) {
+    constexpr int WPE = NW / NP;
     unsigned it = 0;
-    while ((uint32_t)(w >> 32) != want) {
-        if (*reinterpret_cast<volatile int*>(&abort_flag)) return 0;  // another wait timed out
+    while (true) {
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            ok = ok && (src[k / WPE] == nullptr || (uint32_t)(w[k] >> 32) == want);
+        if (ok) return true;
+        if (*reinterpret_cast<volatile int*>(&abort_flag)) return false;
         if (++it >= kSpinLimit) {
             abort_flag = 1;
             atomicExch(error, 1);
-            return 0;
+            return false;
         }
         __builtin_amdgcn_s_sleep(1);
-        w = peek(p);
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            if (src[k / WPE]) w[k] = peek(src[k / WPE] + k % WPE);
     }
-    return (uint32_t)w;
 }
 
-// T1: every instance of the launch has t = 1.  XE, XO: leading even and odd
-// slots that may hold exported elements.
-template <typename T, int G, int NTU, int UE, int UO, int GE, int GO, int XE, int XO, bool T1>
+// T1: every instance of the launch has t = 1.  Even slots: interior elements
+// in u < UB (the first GE1 slots read transposes), boundary elements from UB
+// (the diagonal first; slots UB .. UB + GE2 - 1 read transposes); odd slots:
+// the first GO read transposes, exported elements in the first XO.  KB: halo
+// entries per thread whose reads are issued a phase ahead.
+template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
+          int KB, bool T1>
 __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     using C = cplx_t<T>;
     constexpr int CB = (int)sizeof(C);
@@ -882,11 +905,12 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     constexpr int SH = CB == 8 ? 3 : 4;   // slot number -> byte offset
     constexpr int DSH = TB == 4 ? 2 : 3;  // diagonal position -> byte offset
     constexpr int W = Payload<T>::W;      // published words per element
+    constexpr int DW = TB / 4;            // words of the real part
     constexpr int kEnt = NTU * (UE + UO); // descriptor entries of a part
     constexpr int kEvenPad = NTU * UE;
     constexpr uint32_t kDiagCopy = 256 * TB;
-    constexpr int kBatch = 4;             // halo copies in flight per thread
-    static_assert(XE <= UE && XO <= UO && GE <= UE && GO <= UO, "leading slots within the class");
+    static_assert(GE1 <= UB && UB < UE && UB + GE2 <= UE && GO <= UO && XO <= UO,
+                  "slot groups within their class");
     extern __shared__ __align__(16) unsigned char smem[];
     (void)smem;
     const int tid0 = threadIdx.x;
@@ -922,12 +946,10 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         const int hmax = __builtin_amdgcn_readfirstlane(E.hmax);
         const uint32_t* const blob = reinterpret_cast<const uint32_t*>(uniform64((uint64_t)E.desc));
         const uint32_t* const pb = blob + (size_t)part * pw;
-        const int n_even = __builtin_amdgcn_readfirstlane((int)pb[0]);
         const int n_own = __builtin_amdgcn_readfirstlane((int)pb[1]);
         const int n_ie = __builtin_amdgcn_readfirstlane((int)pb[2]);
         const int n_io = __builtin_amdgcn_readfirstlane((int)pb[3]);
         const int n_diag = __builtin_amdgcn_readfirstlane((int)pb[4]);
-        (void)n_even;
         gdesc_t desc = (gdesc_t)uniform64((uint64_t)(pb + 8));
         const uint32_t* const pord = pb + 8 + 4 * kEnt;
         const uint32_t* const imp = pord + kEnt;
@@ -1000,10 +1022,11 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
             reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * kDiagCopy)[q] = (T)0;
         }
-        // records: even entry t < n_diag is the diagonal element of site dsite[t]
+        // records: boundary entry t < n_diag (slot UB) is the diagonal element
+        // of site dsite[t]
         auto record = [&](int64_t r) {
             if (active && t < n_diag)
-                Xrec[(r * 2 * N + (int64_t)spin0 * N + (int64_t)dsite[t]) * Mc + m] = (double)y[0].x;
+                Xrec[(r * 2 * N + (int64_t)spin0 * N + (int64_t)dsite[t]) * Mc + m] = (double)y[UB].x;
         };
         record(0);
         __syncthreads();
@@ -1014,28 +1037,41 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         const T c_sixth = uniform_real<T>((T)(A.dt / 6.0));
         bool first = true;  // the item's first stage: its halo came from HBM
 
-        // copies halo entries [h0, h1) carrying stage `want` into their slots
-        auto copy_halo = [&](int h0, int h1, uint32_t want) {
-            for (int h = h0 + t; h < h1; h += kBatch * NTU) {
-                uint64_t w[kBatch][W];
-                const uint64_t* src[kBatch];
+        // Halo copies: the reads of this thread's first KB entries of [h0, h1)
+        // are issued early (issue), the values land in their slots later
+        // (land; further entries, if any, are read there).
+        struct Batch {
+            uint64_t w[KB * W];
+            const uint64_t* src[KB];
+        };
+        auto issue = [&](Batch& bt, int h0, int h1, uint32_t want) {
 #pragma unroll
-                for (int j = 0; j < kBatch; ++j) {
-                    const int hj = h + j * NTU < h1 ? h + j * NTU : h;
-                    const uint32_t qs = imp[hj];
-                    src[j] = xslot(spin0, (int)(qs >> 16), want) + (size_t)(qs & 0xffffu) * W;
+            for (int j = 0; j < KB; ++j) {
+                const int h = h0 + t + j * NTU;
+                bt.src[j] = nullptr;
+                if (h < h1) {
+                    const uint32_t qs = imp[h];
+                    bt.src[j] = xslot(spin0, (int)(qs >> 16), want) + (size_t)(qs & 0xffffu) * W;
 #pragma unroll
-                    for (int kk = 0; kk < W; ++kk) w[j][kk] = peek(src[j] + kk);
+                    for (int kk = 0; kk < W; ++kk) bt.w[j * W + kk] = peek(bt.src[j] + kk);
                 }
+            }
+        };
+        auto land = [&](Batch& bt, int h0, int h1, uint32_t want) {
+            for (int hb = h0;; ) {
+                if (!settle_words<KB * W, KB>(bt.src, bt.w, want, abort_flag, A.error)) return;
 #pragma unroll
-                for (int j = 0; j < kBatch; ++j) {
-                    if (h + j * NTU >= h1) break;
-                    Payload<T> p;
+                for (int j = 0; j < KB; ++j) {
+                    if (bt.src[j]) {
+                        Payload<T> pl;
 #pragma unroll
-                    for (int kk = 0; kk < W; ++kk)
-                        p.w[kk] = settle(src[j] + kk, w[j][kk], want, abort_flag, A.error);
-                    reinterpret_cast<C*>(Yb)[n_own + h + j * NTU] = from_payload<T>(p);
+                        for (int kk = 0; kk < W; ++kk) pl.w[kk] = (uint32_t)bt.w[j * W + kk];
+                        reinterpret_cast<C*>(Yb)[n_own + hb + t + j * NTU] = from_payload<T>(pl);
+                    }
                 }
+                hb += KB * NTU;
+                if (hb >= h1) return;
+                issue(bt, hb, h1, want);
             }
         };
 
@@ -1053,16 +1089,31 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
             uint4 dq[KP];
 #pragma unroll
             for (int v = 0; v < KP; ++v) dq[v] = slot_desc_buf<uint4>(drs, entry_of(v < UE + UO ? v : UE + UO - 1), toff);
+            // the halo of this stage's input (published in the producers'
+            // previous stage): reads issued now, landed before the elements
+            // that need them (the odd halo before the boundary, the even halo
+            // before phase 2)
+            Batch bo, be;
+            if (!first) {
+                issue(bo, n_ie, n_ie + n_io, (uint32_t)g);
+                issue(be, 0, n_ie, (uint32_t)g);
+            }
             // ---------------- phase 1: even elements (next values held)
 #pragma unroll
             for (int u = 0; u < UE; ++u) {
+                if (u == UB) {
+                    // the boundary elements read the odd halo
+                    if (!first) land(bo, n_ie, n_ie + n_io, (uint32_t)g);
+                    __syncthreads();
+                }
                 const uint4 d = dq[u % KP];
                 if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<uint4>(drs, entry_of(u + KP), toff);
                 const C own = STAGE == 1 ? y[u] : hold[u];
-                const bool xp = u < XE;
+                const bool xp = u >= UB;
+                const bool gen = u < GE1 || (u >= UB && u < UB + GE2);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
                 *reinterpret_cast<C*>(Yb + ob) = own;
-                const C kk = element_rhs_split<T, true, T1, SH, DSH>(u < GE, xp, Yb, dcur, d, tw, Uw, own);
+                const C kk = element_rhs_split<T, true, T1, SH, DSH>(gen, xp, Yb, dcur, d, tw, Uw, own);
                 hold[u] = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 pin(hold[u]);
                 pin(acc[u]);
@@ -1071,19 +1122,29 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                     publish<T>(mine + (size_t)(d.w & 0x7fffu) * W, hold[u], stamp);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            // the even halo of this stage's input (published in the
-            // producers' previous phase 1; read in phase 2)
-            if (!first) copy_halo(0, n_ie, (uint32_t)g);
+            // phase 2 reads the even halo
+            if (!first) land(be, 0, n_ie, (uint32_t)g);
             __syncthreads();
-            // ---------------- phase 2: odd elements (written straight to LDS)
+            // ---------------- phase 2: odd elements (written straight to LDS);
+            // the partner's diagonal of the next stage's input is read
+            // meanwhile (into the copy this stage does not read)
+            const uint64_t* dsrcp[1] = {nullptr};
+            uint64_t dw[DW];
+            if (t < N) {
+                const uint32_t qs = dsrc[t];
+                dsrcp[0] = xslot(1 - spin0, (int)(qs >> 16), stamp) + (size_t)(qs & 0xffffu) * W;
+#pragma unroll
+                for (int kk = 0; kk < DW; ++kk) dw[kk] = peek(dsrcp[0] + kk);
+            }
 #pragma unroll
             for (int u = UE; u < UE + UO; ++u) {
                 const uint4 d = dq[u % KP];
                 if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<uint4>(drs, entry_of(u + KP), toff);
                 const bool xp = u - UE < XO;
+                const bool gen = u - UE < GO;
                 const C kk = STAGE == 1
-                    ? element_rhs_split<T, true, T1, SH, DSH>(u - UE < GO, xp, Yb, dcur, d, tw, Uw, y[u])
-                    : element_rhs_split<T, false, T1, SH, DSH>(u - UE < GO, xp, Yb, dcur, d, tw, Uw, y[u]);
+                    ? element_rhs_split<T, true, T1, SH, DSH>(gen, xp, Yb, dcur, d, tw, Uw, y[u])
+                    : element_rhs_split<T, false, T1, SH, DSH>(gen, xp, Yb, dcur, d, tw, Uw, y[u]);
                 const C nx = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
                 *reinterpret_cast<C*>(Yb + ob) = nx;
@@ -1092,24 +1153,11 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 if (xp && (d.w & 0x8000u)) publish<T>(mine + (size_t)(d.w & 0x7fffu) * W, nx, stamp);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            // the odd halo and the partner's diagonal of the next stage's input
-            // (the diagonal into the copy this stage does not read)
-            {
-                uint64_t dw[W];
-                const uint64_t* dsrcp = nullptr;
-                if (t < N) {
-                    const uint32_t qs = dsrc[t];
-                    dsrcp = xslot(1 - spin0, (int)(qs >> 16), stamp) + (size_t)(qs & 0xffffu) * W;
+            if (t < N && settle_words<DW, 1>(dsrcp, dw, stamp, abort_flag, A.error)) {
+                Payload<T> pl;
 #pragma unroll
-                    for (int kk = 0; kk < W; ++kk) dw[kk] = peek(dsrcp + kk);
-                }
-                copy_halo(n_ie, n_ie + n_io, stamp);
-                if (t < N) {
-                    Payload<T> p;
-#pragma unroll
-                    for (int kk = 0; kk < W; ++kk) p.w[kk] = settle(dsrcp + kk, dw[kk], stamp, abort_flag, A.error);
-                    reinterpret_cast<T*>(dpart + (STAGE & 1) * kDiagCopy)[dpos[t]] = from_payload<T>(p).x;
-                }
+                for (int kk = 0; kk < W; ++kk) pl.w[kk] = kk < DW ? (uint32_t)dw[kk] : 0u;
+                reinterpret_cast<T*>(dpart + (STAGE & 1) * kDiagCopy)[dpos[t]] = from_payload<T>(pl).x;
             }
             __syncthreads();
             ++g;
@@ -1162,8 +1210,12 @@ struct Config {
     int S, NTU, UNITS, UE, UO, GE, GO;
     const void* fn;
     const void* fn_t1;
-    int G = 1;         // workgroups per spin block (> 1: the split kernel)
-    int XE = 0, XO = 0;  // split: leading even and odd slots that may hold exported elements
+    // split kernel (G > 1 workgroups per spin block): GE = GE1; boundary
+    // from slot UB, its first GE2 slots read transposes; exported odd
+    // elements in the first XO odd slots; KB halo reads issued ahead
+    int G = 1;
+    int UB = 0, GE2 = 0, XO = 0, KB = 0;
+    bool auto_pick = true;  // false: chosen only when forced or by the autotuner
 };
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
@@ -1179,18 +1231,20 @@ constexpr const void* unit_hop_fn() {
            (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
            unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
 
-template <typename T, int G, int NTU, int UE, int UO, int GE, int GO, int XE, int XO>
+template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
+          int KB>
 constexpr const void* split_unit_hop_fn() {
     if constexpr (std::is_same<T, float>::value)
-        return (const void*)&rk4_split<T, G, NTU, UE, UO, GE, GO, XE, XO, true>;
+        return (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, true>;
     else
         return nullptr;
 }
 
-#define FTWA_SPLIT_CFG(T, DT, G, NTU, UE, UO, GE, GO, XE, XO)                          \
-    Config{DT, 1, NTU, 1, UE, UO, GE, GO,                                                \
-           (const void*)&rk4_split<T, G, NTU, UE, UO, GE, GO, XE, XO, false>,           \
-           split_unit_hop_fn<T, G, NTU, UE, UO, GE, GO, XE, XO>(), G, XE, XO}
+#define FTWA_SPLIT_CFG(T, DT, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, AUTO)              \
+    Config{DT, 1, NTU, 1, UE, UO, GE1, GO,                                                   \
+           (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false>,     \
+           split_unit_hop_fn<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB>(), G, UB, GE2, XO, KB, \
+           AUTO}
 
 const Config kConfigs[] = {
     FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1, 1, 1),
@@ -1213,14 +1267,18 @@ const Config kConfigs[] = {
     FTWA_RES_CFG(float, FTWA_F32, 2, 128, 8, 2, 2, 1, 1),
     FTWA_RES_CFG(float, FTWA_F32, 2, 256, 4, 3, 3, 1, 1),
     FTWA_RES_CFG(float, FTWA_F32, 2, 512, 1, 5, 5, 1, 1),
-    // spin blocks split over workgroups (FP64 blocks larger than one CU)
-    FTWA_SPLIT_CFG(double, FTWA_F64, 2, 768, 4, 4, 1, 1, 2, 2),
-    FTWA_SPLIT_CFG(double, FTWA_F64, 3, 768, 5, 5, 1, 1, 2, 2),
+    // spin blocks split over workgroups (FP64 blocks larger than one CU);
+    // three and four parts wait on two exchanges per stage and are left to
+    // the autotuner
+    FTWA_SPLIT_CFG(double, FTWA_F64, 2, 512, 6, 6, 4, 1, 2, 1, 2, 1, true),
+    FTWA_SPLIT_CFG(double, FTWA_F64, 3, 512, 7, 7, 4, 1, 1, 2, 4, 2, false),
+    FTWA_SPLIT_CFG(double, FTWA_F64, 4, 512, 5, 5, 2, 1, 1, 1, 4, 3, false),
 };
 
 // Order of preference of the first-fit choice (a tile with fewer general
 // slots before the same tile with more; indices are those of kConfigs).
-const int kPreference[] = {0, 13, 1, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11, 12, 19, 20};
+const int kPreference[] = {0, 13, 1, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11, 12,
+                           19, 20, 21};
 static_assert(sizeof(kPreference) == sizeof(kConfigs) / sizeof(kConfigs[0]) * sizeof(int),
               "every configuration has a place in the preference order");
 
@@ -1265,6 +1323,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         if (force_config >= 0 && k != force_config) continue;
         const Config& c = kConfigs[k];
         if (c.dtype != dtype) continue;
+        if (!c.auto_pick && force_config < 0) continue;
         if (N > c.NTU) continue;  // the diagonal must sit in slot 0
         size_t lds;
         if (c.G > 1) {
@@ -1272,9 +1331,10 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if (!allow_split || N > 256) continue;
             const SplitShape& sh = tab.split[c.G];
             const int64_t n = c.NTU;
-            if (n * c.UE < sh.max_even || n * c.UO < sh.max_odd) continue;
-            if (n * c.GE < sh.gen_even || n * c.GO < sh.gen_odd) continue;
-            if (n * c.XE < sh.x_even || n * c.XO < sh.x_odd) continue;
+            if (n * c.UE < sh.n_even || n * c.UO < sh.n_odd) continue;
+            if (n * c.GE < sh.int_gen || n * (c.UE - c.UB) < sh.n_bnd || n * c.GE2 < sh.bnd_gen)
+                continue;
+            if (n * c.GO < sh.odd_gen || n * c.XO < sh.odd_x) continue;
             if (sh.max_slots + 33 > 0x7fff) continue;
             lds = split_lds_bytes(c, sh.max_slots);
         } else {
@@ -1292,6 +1352,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         plan->even_slots = (int64_t)c.NTU * c.UE;
         plan->odd_slots = (int64_t)c.NTU * c.UO;
         plan->lds = lds;
+        plan->bnd_entry = (int64_t)c.NTU * c.UB;
         return true;
     }
     return false;

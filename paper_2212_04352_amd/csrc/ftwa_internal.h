@@ -19,13 +19,18 @@ constexpr int kMaxSites = 255;
 constexpr int kMaxParts = 4;  // workgroups per spin block of the split resident kernel
 
 // What a split configuration (one spin block over G workgroups, "parts") must
-// hold for a lattice: the maxima over its parts.
+// hold for a lattice: the maxima over its parts.  Even class: "interior"
+// elements (read no other part's element) and "boundary" elements (the
+// diagonal and the elements other parts read); odd class: the exported ones
+// and the rest.
 struct SplitShape {
-    int max_even = 0, max_odd = 0;  // owned elements of each class
-    int gen_even = 0, gen_odd = 0;  // leading entries of each class that read a transpose
-    int x_even = 0, x_odd = 0;      // leading entries holding every exported element
-    int max_slots = 0;              // owned plus halo elements
-    int max_halo = 0;               // halo elements
+    int n_even = 0, n_odd = 0;  // owned elements of each class
+    int int_gen = 0;            // interior elements that read a transpose
+    int n_bnd = 0, bnd_gen = 0; // boundary elements, those of them that read a transpose
+    int odd_gen = 0;            // odd elements that read a transpose
+    int odd_x = 0;              // odd entries up to the last exported one
+    int max_slots = 0;          // owned plus halo elements
+    int max_halo = 0;           // halo elements
 };
 
 // Index tables of a lattice on one device (uploaded once, owned by the handle).
@@ -87,9 +92,9 @@ struct ftwa_lattice_s {
     std::vector<uint32_t> class_order;      // a | b << 16 of the stored elements in LDS-slot order
     std::vector<int32_t> diag_pos;          // site -> sublattice-major diagonal position
     std::vector<int32_t> rank;              // site -> bandwidth-reducing rank
-    // split-kernel tables by (device, parts, even slots, odd slots, element
-    // bytes): device blob, words per part, import capacity
-    std::map<std::tuple<int, int, int64_t, int64_t, int>, std::tuple<void*, int, int>> split;
+    // split-kernel tables by (device, parts, even slots, odd slots, boundary
+    // entry, element bytes): device blob, words per part, import capacity
+    std::map<std::tuple<int, int, int64_t, int64_t, int64_t, int>, std::tuple<void*, int, int>> split;
 };
 
 namespace ftwa {
@@ -140,14 +145,21 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
 // One block of *part_words 32-bit words per part:
 //   [0..7]   n_even, n_own, n_import_even, n_import_odd, n_diag, 0, 0, 0
 //   [8..)    descriptors (compact form, 16 bytes per entry, even_slots +
-//            odd_slots entries; own field bit 15: the element is exported)
+//            odd_slots entries; own field bit 15: the element is exported).
+//            Even entries: the interior elements (those that read a
+//            transpose first) up to bnd_entry, the boundary elements from
+//            bnd_entry (the diagonal, then those that read a transpose), then
+//            interior elements that did not fit before bnd_entry; odd entries:
+//            those that read a transpose (exported first), the other exported
+//            ones, the rest.
 //   then     LDS slot -> a | b << 16 of the owned element (even_slots + odd_slots words)
 //   then     imports: producer part << 16 | producer slot, *hmax words
 //            (halo slot n_own + h takes import h; even halo first)
 //   then     the site of even entry t < n_diag (its diagonal element)
 // then, after the G blocks, [N]: site -> part << 16 | slot of its diagonal element.
 ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t odd_slots,
-                         int elem_bytes, const void** out, int* part_words, int* hmax);
+                         int64_t bnd_entry, int elem_bytes, const void** out, int* part_words,
+                         int* hmax);
 
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
@@ -204,6 +216,7 @@ struct ResidentPlan {
     int units = 1;
     int64_t even_slots = 0;  // descriptor padding of the even / odd class
     int64_t odd_slots = 0;
+    int64_t bnd_entry = 0;   // split configurations: first boundary entry of the even class
     size_t lds = 0;
 };
 // One entry of a resident launch's table: a window of trajectories of one

@@ -390,23 +390,30 @@ namespace {
 
 // One part of the split layout of a spin block (see split_tables).
 struct SplitPart {
-    std::vector<int64_t> even, odd;  // owned elements (class-order indices) in entry order
+    std::vector<int64_t> interior;   // even, read no other part's element (transpose readers first)
+    std::vector<int64_t> boundary;   // even: the diagonal, then the exported (transpose readers first)
+    std::vector<int64_t> odd;        // transpose readers (exported first), exported, rest
     std::vector<int64_t> halo;       // elements read from other parts, even class first,
                                      // then by producer part and producer slot
     int n_halo_even = 0;
-    int n_diag = 0;                  // leading even entries: the diagonal of the part's rows
-    int gen_even = 0, gen_odd = 0;   // leading entries that read a transpose
-    int x_even = 0, x_odd = 0;       // leading entries holding every exported element
+    int n_diag = 0;
+    int int_gen = 0, bnd_gen = 0, odd_gen = 0, odd_x = 0;
 };
+
+// Owned elements in LDS-slot order: interior, boundary, odd.
+std::vector<int64_t> owned(const SplitPart& sp) {
+    std::vector<int64_t> v(sp.interior);
+    v.insert(v.end(), sp.boundary.begin(), sp.boundary.end());
+    v.insert(v.end(), sp.odd.begin(), sp.odd.end());
+    return v;
+}
 
 // The rows of the stored elements (sites in rank order; the stored element
 // rho_ab has rank a <= rank b and belongs to row a) cut into G strips of
 // nearly equal element count; part p owns the elements of strip p.  An
-// element is exported when a stencil of another part reads it, and every
-// diagonal element is (the other spin's U term reads it).  Within a class the
-// entries are ordered: the diagonal (even class), the elements that read a
-// transpose, the other exported elements, the rest, each group in class
-// order.
+// element is exported when a stencil of another part reads it (it then reads
+// that part's elements itself: the stencil relation is symmetric), and every
+// diagonal element is (the other spin's U term reads it).
 std::vector<SplitPart> split_layout(const ftwa_lattice_s& L, int G, int64_t n_even,
                                     int64_t n_gen_even, int64_t n_gen_odd) {
     const int N = L.N;
@@ -448,41 +455,37 @@ std::vector<SplitPart> split_layout(const ftwa_lattice_s& L, int G, int64_t n_ev
         for (int k = 0; k < L.deg[a]; ++k) touch(q_at(L.nbr[(size_t)a * kMaxDeg + k], b));
     }
     for (int i = 0; i < N; ++i) exported[(size_t)i] = 1;  // (i,i) sits at class-order index i
+    auto gen_e = [&](int64_t q) { return q < n_gen_even; };  // (includes the diagonal)
+    auto gen_o = [&](int64_t q) { return q - n_even < n_gen_odd; };
     for (int p = 0; p < G; ++p) {
         SplitPart& sp = parts[p];
-        std::vector<int64_t> rest_e, rest_o;
+        std::vector<int64_t> ig, ir, bg, br, og_x, og, ox, orr;
         for (int64_t q = 0; q < n; ++q) {
             if (part_of(q) != p) continue;
-            if (q < N) sp.even.push_back(q);
-            else if (q < n_even) rest_e.push_back(q);
-            else rest_o.push_back(q);
+            if (q < N) sp.boundary.push_back(q);
+            else if (q < n_even) (exported[(size_t)q] ? (gen_e(q) ? bg : br) : (gen_e(q) ? ig : ir)).push_back(q);
+            else if (gen_o(q)) (exported[(size_t)q] ? og_x : og).push_back(q);
+            else (exported[(size_t)q] ? ox : orr).push_back(q);
         }
-        sp.n_diag = (int)sp.even.size();
-        auto rank_key = [&](int64_t q, bool gen) { return (gen ? 0 : 2) + (exported[(size_t)q] ? 0 : 1); };
-        std::stable_sort(rest_e.begin(), rest_e.end(), [&](int64_t x, int64_t y) {
-            return rank_key(x, x < n_gen_even) < rank_key(y, y < n_gen_even);
-        });
-        std::stable_sort(rest_o.begin(), rest_o.end(), [&](int64_t x, int64_t y) {
-            return rank_key(x, x - n_even < n_gen_odd) < rank_key(y, y - n_even < n_gen_odd);
-        });
-        sp.even.insert(sp.even.end(), rest_e.begin(), rest_e.end());
-        sp.odd = rest_o;
-        for (size_t e = 0; e < sp.even.size(); ++e) {
-            if (sp.even[e] < n_gen_even) sp.gen_even = (int)e + 1;
-            if (exported[(size_t)sp.even[e]]) sp.x_even = (int)e + 1;
-        }
-        for (size_t e = 0; e < sp.odd.size(); ++e) {
-            if (sp.odd[e] - n_even < n_gen_odd) sp.gen_odd = (int)e + 1;
-            if (exported[(size_t)sp.odd[e]]) sp.x_odd = (int)e + 1;
-        }
+        sp.n_diag = (int)sp.boundary.size();
+        sp.interior = ig;
+        sp.interior.insert(sp.interior.end(), ir.begin(), ir.end());
+        sp.int_gen = (int)ig.size();
+        sp.boundary.insert(sp.boundary.end(), bg.begin(), bg.end());
+        sp.bnd_gen = (int)sp.boundary.size();
+        sp.boundary.insert(sp.boundary.end(), br.begin(), br.end());
+        sp.odd = og_x;
+        sp.odd.insert(sp.odd.end(), og.begin(), og.end());
+        sp.odd_gen = (int)sp.odd.size();
+        sp.odd.insert(sp.odd.end(), ox.begin(), ox.end());
+        sp.odd_x = ox.empty() ? (int)og_x.size() : (int)sp.odd.size();
+        sp.odd.insert(sp.odd.end(), orr.begin(), orr.end());
     }
     // producer slots, then the halo order
     std::vector<int> slot_q((size_t)n);
     for (int p = 0; p < G; ++p) {
-        const SplitPart& sp = parts[p];
-        for (size_t e = 0; e < sp.even.size(); ++e) slot_q[(size_t)sp.even[e]] = (int)e;
-        for (size_t e = 0; e < sp.odd.size(); ++e)
-            slot_q[(size_t)sp.odd[e]] = (int)(sp.even.size() + e);
+        const std::vector<int64_t> own = owned(parts[p]);
+        for (size_t e = 0; e < own.size(); ++e) slot_q[(size_t)own[e]] = (int)e;
     }
     for (int p = 0; p < G; ++p) {
         SplitPart& sp = parts[p];
@@ -499,15 +502,16 @@ std::vector<SplitPart> split_layout(const ftwa_lattice_s& L, int G, int64_t n_ev
 SplitShape split_shape(const std::vector<SplitPart>& parts) {
     SplitShape s;
     for (const SplitPart& sp : parts) {
-        s.max_even = std::max(s.max_even, (int)sp.even.size());
-        s.max_odd = std::max(s.max_odd, (int)sp.odd.size());
-        s.gen_even = std::max(s.gen_even, sp.gen_even);
-        s.gen_odd = std::max(s.gen_odd, sp.gen_odd);
-        s.x_even = std::max(s.x_even, sp.x_even);
-        s.x_odd = std::max(s.x_odd, sp.x_odd);
+        const int ne = (int)(sp.interior.size() + sp.boundary.size());
+        s.n_even = std::max(s.n_even, ne);
+        s.n_odd = std::max(s.n_odd, (int)sp.odd.size());
+        s.int_gen = std::max(s.int_gen, sp.int_gen);
+        s.n_bnd = std::max(s.n_bnd, (int)sp.boundary.size());
+        s.bnd_gen = std::max(s.bnd_gen, sp.bnd_gen);
+        s.odd_gen = std::max(s.odd_gen, sp.odd_gen);
+        s.odd_x = std::max(s.odd_x, sp.odd_x);
         s.max_halo = std::max(s.max_halo, (int)sp.halo.size());
-        s.max_slots =
-            std::max(s.max_slots, (int)(sp.even.size() + sp.odd.size() + sp.halo.size()));
+        s.max_slots = std::max(s.max_slots, ne + (int)(sp.odd.size() + sp.halo.size()));
     }
     return s;
 }
@@ -515,7 +519,8 @@ SplitShape split_shape(const std::vector<SplitPart>& parts) {
 }  // namespace
 
 ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t odd_slots,
-                         int elem_bytes, const void** out, int* part_words, int* hmax) {
+                         int64_t bnd_entry, int elem_bytes, const void** out, int* part_words,
+                         int* hmax) {
     DeviceTables tab;
     ftwa_status st = device_tables(lat, &tab);
     if (st != FTWA_OK) return st;
@@ -527,7 +532,7 @@ ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t od
     int dev = 0;
     FTWA_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(lat->mu);
-    const auto key = std::make_tuple(dev, G, even_slots, odd_slots, elem_bytes);
+    const auto key = std::make_tuple(dev, G, even_slots, odd_slots, bnd_entry, elem_bytes);
     auto it = lat->split.find(key);
     if (it != lat->split.end()) {
         *out = std::get<0>(it->second);
@@ -547,17 +552,16 @@ ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t od
     std::vector<int> part_q((size_t)n), slot_q((size_t)n);
     for (int p = 0; p < G; ++p) {
         const SplitPart& sp = parts[p];
-        if ((int64_t)sp.even.size() > even_slots || (int64_t)sp.odd.size() > odd_slots)
+        const int64_t ne = (int64_t)(sp.interior.size() + sp.boundary.size());
+        if (ne > even_slots || (int64_t)sp.odd.size() > odd_slots ||
+            (int64_t)sp.boundary.size() > even_slots - bnd_entry)
             return fail(FTWA_EINVAL, "split: padding too small");
-        if (sp.even.size() + sp.odd.size() + sp.halo.size() + 33 > 0x7fff)
+        const std::vector<int64_t> own = owned(sp);
+        if (own.size() + sp.halo.size() + 33 > 0x7fff)
             return fail(FTWA_EINVAL, "split: part too large for 15-bit slots");
-        for (size_t e = 0; e < sp.even.size(); ++e) {
-            part_q[(size_t)sp.even[e]] = p;
-            slot_q[(size_t)sp.even[e]] = (int)e;
-        }
-        for (size_t e = 0; e < sp.odd.size(); ++e) {
-            part_q[(size_t)sp.odd[e]] = p;
-            slot_q[(size_t)sp.odd[e]] = (int)(sp.even.size() + e);
+        for (size_t e = 0; e < own.size(); ++e) {
+            part_q[(size_t)own[e]] = p;
+            slot_q[(size_t)own[e]] = (int)e;
         }
     }
     std::vector<int64_t> q_of((size_t)packed_count(N));
@@ -573,9 +577,10 @@ ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t od
     for (int p = 0; p < G; ++p) {
         const SplitPart& sp = parts[p];
         uint32_t* pb = blob.data() + (size_t)p * pw;
-        const int n_own = (int)(sp.even.size() + sp.odd.size());
+        const int n_ev = (int)(sp.interior.size() + sp.boundary.size());
+        const int n_own = n_ev + (int)sp.odd.size();
         const int Z0 = n_own + (int)sp.halo.size();
-        pb[0] = (uint32_t)sp.even.size();
+        pb[0] = (uint32_t)n_ev;
         pb[1] = (uint32_t)n_own;
         pb[2] = (uint32_t)sp.n_halo_even;
         pb[3] = (uint32_t)(sp.halo.size() - sp.n_halo_even);
@@ -630,11 +635,21 @@ ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t od
             e.b = b;
             return true;
         };
-        for (size_t k = 0; k < sp.even.size(); ++k)
-            if (!fill(sp.even[k], (int64_t)k, (int)k < sp.gen_even))
-                return fail(FTWA_ENOTSUP, "split: inconsistent stencil (even class)");
+        // even entries: interior up to bnd_entry, boundary from bnd_entry,
+        // the interior overflow after it
+        const int64_t n_int0 = std::min<int64_t>((int64_t)sp.interior.size(), bnd_entry);
+        for (int64_t k = 0; k < n_int0; ++k)
+            if (!fill(sp.interior[(size_t)k], k, k < sp.int_gen))
+                return fail(FTWA_ENOTSUP, "split: inconsistent stencil (interior)");
+        for (size_t k = 0; k < sp.boundary.size(); ++k)
+            if (!fill(sp.boundary[k], bnd_entry + (int64_t)k, (int)k < sp.bnd_gen))
+                return fail(FTWA_ENOTSUP, "split: inconsistent stencil (boundary)");
+        for (int64_t k = n_int0; k < (int64_t)sp.interior.size(); ++k)
+            if (!fill(sp.interior[(size_t)k], bnd_entry + (int64_t)sp.boundary.size() + (k - n_int0),
+                      k < sp.int_gen))
+                return fail(FTWA_ENOTSUP, "split: inconsistent stencil (interior)");
         for (size_t k = 0; k < sp.odd.size(); ++k)
-            if (!fill(sp.odd[k], even_slots + (int64_t)k, (int)k < sp.gen_odd))
+            if (!fill(sp.odd[k], even_slots + (int64_t)k, (int)k < sp.odd_gen))
                 return fail(FTWA_ENOTSUP, "split: inconsistent stencil (odd class)");
         // missing neighbours: the zero slot whose bank residue no other lane
         // of the pass reads for that field
@@ -671,7 +686,7 @@ ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t od
             const int64_t q = sp.halo[h];
             imp[h] = (uint32_t)part_q[(size_t)q] << 16 | (uint32_t)slot_q[(size_t)q];
         }
-        for (int t = 0; t < sp.n_diag; ++t) dsite[t] = order[(size_t)sp.even[(size_t)t]] & 0xffffu;
+        for (int t = 0; t < sp.n_diag; ++t) dsite[t] = order[(size_t)sp.boundary[(size_t)t]] & 0xffffu;
     }
     uint32_t* dsrc = blob.data() + (size_t)G * pw;
     for (int i = 0; i < N; ++i) dsrc[i] = (uint32_t)part_q[(size_t)i] << 16 | (uint32_t)slot_q[(size_t)i];

@@ -13,7 +13,7 @@ from tests._util import pack, unpack
 
 pytestmark = pytest.mark.gpu
 
-SPLIT2, SPLIT3 = 19, 20  # configurations: 2 and 3 workgroups per spin block (FP64)
+SPLIT2, SPLIT3, SPLIT4 = 19, 20, 21  # configurations (FP64): 2, 3 and 4 workgroups per spin block
 
 
 @pytest.fixture(scope="module")
@@ -52,14 +52,30 @@ def _run(ft, orc, kind, a, b, config, M, steps, re, U=3.3, t=1.0, seed=11, start
 
 
 @pytest.mark.parametrize("kind,a,b,config", [("hex", 4, 0, SPLIT2), ("hex", 4, 0, SPLIT3),
-                                             ("torus", 3, 9, SPLIT2), ("hex", 5, 0, SPLIT2),
-                                             ("hex", 5, 0, SPLIT3),
-                                             ("armchair", 10, 20, SPLIT3)])
+                                             ("hex", 4, 0, SPLIT4), ("torus", 3, 9, SPLIT2),
+                                             ("hex", 5, 0, SPLIT2), ("hex", 5, 0, SPLIT3),
+                                             ("hex", 5, 0, SPLIT4),
+                                             ("armchair", 10, 20, SPLIT3),
+                                             ("armchair", 10, 20, SPLIT4)])
 def test_split_matches_oracle(ft, orc, kind, a, b, config):
     _run(ft, orc, kind, a, b, config, M=37, steps=12, re=4)
 
 
-def test_split_is_the_automatic_fp64_choice_at_198_sites(ft, orc):
+def test_two_part_split_is_the_automatic_fp64_choice_at_150_sites(ft, orc):
     """More trajectories than groups in flight (items are taken in turns),
-    U = -2 and t = 0.7 (the general hopping variant)."""
-    _run(ft, orc, "armchair", 10, 20, -1, M=45, steps=6, re=3, U=-2.0, t=0.7, start="neel")
+    U = -2 and t = 0.7 (the general hopping variant), no forced configuration."""
+    _run(ft, orc, "hex", 5, 0, -1, M=70, steps=6, re=3, U=-2.0, t=0.7, start="neel")
+
+
+def test_three_part_split_takes_items_in_turns(ft, orc):
+    _run(ft, orc, "armchair", 10, 20, SPLIT3, M=45, steps=5, re=5, U=2.5, start="neel")
+
+
+def test_fp64_at_198_sites_stays_on_the_stream_path_unless_forced(ft):
+    """Three and four parts are offered to the autotuner only."""
+    lat = ft.Lattice("armchair", 10, 20)
+    prob = ft.Problem.allocate(lat, 3.3, 2, lat.fock_start("neel"), "f64")
+    ft.sample(prob, 1)
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 1, 1, path="resident")
+    ft.evolve(prob, 0.01, 1, 1, path="resident", config=SPLIT3)
