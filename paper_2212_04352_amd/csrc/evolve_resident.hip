@@ -848,14 +848,15 @@ template <typename T> __device__ __forceinline__ cplx_t<T> from_payload(const Pa
 
 // Publishes a value: every payload word with the stage number in the high
 // half, each a relaxed agent-scope atomic (a reader sees the old or the new
-// stage of a word, never a mixture).
+// stage of a word, never a mixture); word k at dst + k * stride (word-major
+// areas: the threads of a wave write consecutive words).
 template <typename T>
-__device__ __forceinline__ void publish(uint64_t* dst, cplx_t<T> v, uint32_t stamp) {
+__device__ __forceinline__ void publish(uint64_t* dst, int stride, cplx_t<T> v, uint32_t stamp) {
     const Payload<T> p = to_payload<T>(v);
 #pragma unroll
     for (int k = 0; k < Payload<T>::W; ++k)
-        __hip_atomic_store(dst + k, ((uint64_t)stamp << 32) | p.w[k], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(dst + (size_t)k * stride, ((uint64_t)stamp << 32) | p.w[k],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t peek(const uint64_t* p) {
@@ -863,13 +864,14 @@ __device__ __forceinline__ uint64_t peek(const uint64_t* p) {
 }
 
 // Waits until NW published words carry stage `want`: w[k] was read from
-// src[k / WPE] + k % WPE (WPE = NW / NP, null pointers are skipped); while
-// any word is stale, all of them are read again (one round trip per retry).
+// src[k / WPE] + (k % WPE) * stride (WPE = NW / NP, null pointers are
+// skipped); while any word is stale, all of them are read again (one round
+// trip per retry).
 // Bounded: false (abort flag and error word set) when the stage never comes
 // or another wait of the workgroup gave up.
 template <int NW, int NP>
-__device__ __forceinline__ bool settle_words(const uint64_t* const* src, uint64_t* w, uint32_t want,
-                                             int& abort_flag, int* error) {
+__device__ __forceinline__ bool settle_words(const uint64_t* const* src, int stride, uint64_t* w,
+                                             uint32_t want, int& abort_flag, int* error) {
     constexpr int WPE = NW / NP;
     unsigned it = 0;
     while (true) {
@@ -887,7 +889,7 @@ __device__ __forceinline__ bool settle_words(const uint64_t* const* src, uint64_
         __builtin_amdgcn_s_sleep(1);
 #pragma unroll
         for (int k = 0; k < NW; ++k)
-            if (src[k / WPE]) w[k] = peek(src[k / WPE] + k % WPE);
+            if (src[k / WPE]) w[k] = peek(src[k / WPE] + (size_t)(k % WPE) * stride);
     }
 }
 
@@ -924,7 +926,7 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     const int group = (k / (2 * G)) * 8 + xcd;
     const int64_t n_groups = gridDim.x / (2 * G);
     if (tid0 == 0) *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU / 64) * 2 * 8)) = 0;
-    // published words of this group: [2 spins][G parts][2 parities][kEnt][W]
+    // published words of this group: [2 spins][G parts][2 parities][W][kEnt]
     uint64_t* const xg = A.mailbox + (size_t)group * 2 * G * 2 * kEnt * W;
     auto xslot = [&](int spin, int q, uint32_t stamp) {
         return xg + ((size_t)(spin * G + q) * 2 + (stamp & 1)) * kEnt * W;
@@ -1051,15 +1053,15 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 bt.src[j] = nullptr;
                 if (h < h1) {
                     const uint32_t qs = imp[h];
-                    bt.src[j] = xslot(spin0, (int)(qs >> 16), want) + (size_t)(qs & 0xffffu) * W;
+                    bt.src[j] = xslot(spin0, (int)(qs >> 16), want) + (qs & 0xffffu);
 #pragma unroll
-                    for (int kk = 0; kk < W; ++kk) bt.w[j * W + kk] = peek(bt.src[j] + kk);
+                    for (int kk = 0; kk < W; ++kk) bt.w[j * W + kk] = peek(bt.src[j] + (size_t)kk * kEnt);
                 }
             }
         };
         auto land = [&](Batch& bt, int h0, int h1, uint32_t want) {
             for (int hb = h0;; ) {
-                if (!settle_words<KB * W, KB>(bt.src, bt.w, want, abort_flag, A.error)) return;
+                if (!settle_words<KB * W, KB>(bt.src, kEnt, bt.w, want, abort_flag, A.error)) return;
 #pragma unroll
                 for (int j = 0; j < KB; ++j) {
                     if (bt.src[j]) {
@@ -1119,7 +1121,7 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 pin(acc[u]);
                 if constexpr (STAGE == 4) pin(y[u]);
                 if (xp && (d.w & 0x8000u))
-                    publish<T>(mine + (size_t)(d.w & 0x7fffu) * W, hold[u], stamp);
+                    publish<T>(mine + (d.w & 0x7fffu), kEnt, hold[u], stamp);
                 __builtin_amdgcn_sched_barrier(0);
             }
             // phase 2 reads the even halo
@@ -1132,9 +1134,9 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
             uint64_t dw[DW];
             if (t < N) {
                 const uint32_t qs = dsrc[t];
-                dsrcp[0] = xslot(1 - spin0, (int)(qs >> 16), stamp) + (size_t)(qs & 0xffffu) * W;
+                dsrcp[0] = xslot(1 - spin0, (int)(qs >> 16), stamp) + (qs & 0xffffu);
 #pragma unroll
-                for (int kk = 0; kk < DW; ++kk) dw[kk] = peek(dsrcp[0] + kk);
+                for (int kk = 0; kk < DW; ++kk) dw[kk] = peek(dsrcp[0] + (size_t)kk * kEnt);
             }
 #pragma unroll
             for (int u = UE; u < UE + UO; ++u) {
@@ -1150,10 +1152,10 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 *reinterpret_cast<C*>(Yb + ob) = nx;
                 pin(acc[u]);
                 if constexpr (STAGE == 4) pin(y[u]);
-                if (xp && (d.w & 0x8000u)) publish<T>(mine + (size_t)(d.w & 0x7fffu) * W, nx, stamp);
+                if (xp && (d.w & 0x8000u)) publish<T>(mine + (d.w & 0x7fffu), kEnt, nx, stamp);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (t < N && settle_words<DW, 1>(dsrcp, dw, stamp, abort_flag, A.error)) {
+            if (t < N && settle_words<DW, 1>(dsrcp, kEnt, dw, stamp, abort_flag, A.error)) {
                 Payload<T> pl;
 #pragma unroll
                 for (int kk = 0; kk < W; ++kk) pl.w[kk] = kk < DW ? (uint32_t)dw[kk] : 0u;
@@ -1267,12 +1269,10 @@ const Config kConfigs[] = {
     FTWA_RES_CFG(float, FTWA_F32, 2, 128, 8, 2, 2, 1, 1),
     FTWA_RES_CFG(float, FTWA_F32, 2, 256, 4, 3, 3, 1, 1),
     FTWA_RES_CFG(float, FTWA_F32, 2, 512, 1, 5, 5, 1, 1),
-    // spin blocks split over workgroups (FP64 blocks larger than one CU);
-    // three and four parts wait on two exchanges per stage and are left to
-    // the autotuner
+    // spin blocks split over workgroups (FP64 blocks larger than one CU)
     FTWA_SPLIT_CFG(double, FTWA_F64, 2, 512, 6, 6, 4, 1, 2, 1, 2, 1, true),
-    FTWA_SPLIT_CFG(double, FTWA_F64, 3, 512, 7, 7, 4, 1, 1, 2, 4, 2, false),
-    FTWA_SPLIT_CFG(double, FTWA_F64, 4, 512, 5, 5, 2, 1, 1, 1, 4, 3, false),
+    FTWA_SPLIT_CFG(double, FTWA_F64, 3, 512, 7, 7, 4, 1, 1, 2, 4, 2, true),
+    FTWA_SPLIT_CFG(double, FTWA_F64, 4, 512, 5, 5, 2, 1, 1, 1, 4, 3, true),
 };
 
 // Order of preference of the first-fit choice (a tile with fewer general

@@ -54,7 +54,7 @@ def _oracle_w(orc, olat, rho0, dt, ns, re, U):
     ("torus", 2, 3, "neel", 24, 60, 7),     # ragged last segment
     ("hex", 2, 0, "random", 17, 40, 40),    # degree-2 edge sites, one segment
     # 150 sites: FP32 recomputes checkpoints and segments with the spin-split
-    # resident kernel, FP64 (no resident configuration) with stream launches
+    # resident kernel, FP64 with the two-part split kernel
     ("hex", 5, 0, "neel", 4, 12, 5),
 ])
 def test_adjoint_matches_oracle_gradient(ft, orc, dtype, kind, a, b, start, M, steps, ckpt):

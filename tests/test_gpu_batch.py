@@ -60,7 +60,8 @@ def _assert_same(a, b):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_batched_evolve_matches_per_instance_runs(ft, dtype):
     """Mixed sizes and U in one call: FP32 uses three resident groups (two
-    spin-split); FP64 mixes resident groups and stream-path instances."""
+    spin-split); FP64 mixes one-CU resident groups with the two- and
+    three-part split kernels (150 and 198 sites)."""
     probs = _problems(ft, MIXED, dtype)
     single = _clone(ft, probs)
     for q in single:

@@ -239,13 +239,16 @@ def test_resident_and_stream_paths_agree(ft):
 
 
 def test_resident_rejects_unfit_configuration(ft):
+    big = ft.Lattice("torus", 9, 14)  # 252 sites: no FP64 block or part of it fits the LDS
+    prob = ft.Problem.allocate(big, 3.3, 2, big.fock_start("neel"), "f64")
+    ft.sample(prob, 1)
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 2, 1, path="resident")
     lat = ft.Lattice("armchair", 10, 20)
     prob = ft.Problem.allocate(lat, 3.3, 4, lat.fock_start("neel"), "f64")
     ft.sample(prob, 1)
     with pytest.raises(ft.FtwaError):
-        ft.evolve(prob, 0.01, 2, 1, path="resident")      # FP64 198-site block exceeds LDS
-    with pytest.raises(ft.FtwaError):
-        ft.evolve(prob, 0.01, 2, 1, path="resident", config=0)
+        ft.evolve(prob, 0.01, 2, 1, path="resident", config=0)  # one CU per trajectory
 
 
 def test_flake198_full_batch_sampled_trajectories(ft, orc):

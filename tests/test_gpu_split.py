@@ -71,11 +71,7 @@ def test_three_part_split_takes_items_in_turns(ft, orc):
     _run(ft, orc, "armchair", 10, 20, SPLIT3, M=45, steps=5, re=5, U=2.5, start="neel")
 
 
-def test_fp64_at_198_sites_stays_on_the_stream_path_unless_forced(ft):
-    """Three and four parts are offered to the autotuner only."""
-    lat = ft.Lattice("armchair", 10, 20)
-    prob = ft.Problem.allocate(lat, 3.3, 2, lat.fock_start("neel"), "f64")
-    ft.sample(prob, 1)
-    with pytest.raises(ft.FtwaError):
-        ft.evolve(prob, 0.01, 1, 1, path="resident")
-    ft.evolve(prob, 0.01, 1, 1, path="resident", config=SPLIT3)
+def test_fp64_at_198_sites_takes_the_split_path_by_default(ft, orc):
+    """No forced configuration: the resident path exists for the 198-site FP64
+    block (three workgroups per spin block) and matches the oracle."""
+    _run(ft, orc, "armchair", 10, 20, -1, M=9, steps=4, re=2, start="neel")
