@@ -409,8 +409,11 @@ std::vector<int64_t> owned(const SplitPart& sp) {
 }
 
 // The rows of the stored elements (sites in rank order; the stored element
-// rho_ab has rank a <= rank b and belongs to row a) cut into G strips of
-// nearly equal element count; part p owns the elements of strip p.  An
+// rho_ab has rank a <= rank b and belongs to row a) cut into G strips; part p
+// owns the elements of strip p.  An inner strip exchanges with two
+// neighbours, an end strip with one, so for G > 2 the end strips take a
+// larger share of the elements (1 + a each, the inner ones the rest; a =
+// kEndShare, small enough that the configurations still hold the parts).  An
 // element is exported when a stencil of another part reads it (it then reads
 // that part's elements itself: the stencil relation is symmetric), and every
 // diagonal element is (the other spin's U term reads it).
@@ -419,11 +422,23 @@ std::vector<SplitPart> split_layout(const ftwa_lattice_s& L, int G, int64_t n_ev
     const int N = L.N;
     const std::vector<uint32_t>& order = L.class_order;
     const int64_t P = packed_count(N), n = (int64_t)order.size();
+    const double kEndShare = G == 3 ? 0.05 : 0.02;
+    std::vector<double> upto(G);  // elements up to the end of strip p
+    double acc = 0.0;
+    for (int p = 0; p < G; ++p) {
+        const double w = G <= 2 ? 1.0
+                                : (p == 0 || p == G - 1 ? 1.0 + kEndShare
+                                                        : 1.0 - 2.0 * kEndShare / (G - 2));
+        acc += w;
+        upto[p] = acc / G * (double)P;
+    }
     std::vector<int> strip(N);
     int64_t before = 0;
     for (int r = 0; r < N; ++r) {
-        const int64_t mid2 = 2 * before + (N - r);  // twice the row's middle element
-        strip[r] = (int)std::min<int64_t>(G - 1, mid2 * G / (2 * P));
+        const double mid = (double)before + 0.5 * (N - r);  // the row's middle element
+        int sp = 0;
+        while (sp < G - 1 && mid >= upto[sp]) ++sp;
+        strip[r] = sp;
         before += N - r;
     }
     std::vector<int64_t> q_of((size_t)P);
