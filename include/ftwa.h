@@ -200,7 +200,12 @@ ftwa_status ftwa_sample_thermal(const ftwa_instance* inst, int n_inst, uint64_t 
 typedef enum {
     FTWA_PATH_AUTO = 0,
     FTWA_PATH_STREAM = 1,    /* state in HBM, one launch per Runge-Kutta stage */
-    FTWA_PATH_RESIDENT = 2   /* state held on chip for the whole horizon       */
+    FTWA_PATH_RESIDENT = 2   /* state held on chip for the whole horizon: one
+                                workgroup per trajectory or spin block, or (FP64
+                                blocks too large for one CU) a spin block over
+                                2-4 workgroups of one XCD that exchange their
+                                boundary rows every stage; not with inv in that
+                                last case                                      */
 } ftwa_path;
 
 typedef struct {
@@ -246,7 +251,10 @@ ftwa_status ftwa_evolve_workspace_size(const ftwa_instance* inst, int n_inst,
  * Errors: FTWA_EINVAL (sizes, NULL pointers, workspace too small),
  * FTWA_ENONFINITE if inv is given and a trajectory became non-finite
  * (checked after the run; inv[r][3] counts them; this synchronises the
- * stream), FTWA_EHIP on launch failure.
+ * stream), FTWA_ETIMEOUT when the workgroups of a resident run that share a
+ * trajectory were not resident together (bounded waits; checked after the
+ * run), FTWA_ENOTSUP when the resident path is forced and no configuration
+ * holds the lattice, FTWA_EHIP on launch failure.
  */
 ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
                         int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
@@ -266,9 +274,10 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
  * instance buffers and the workspace must stay allocated, and no other work
  * may use the workspace, while the graph exists.  ftwa_graph_check waits for
  * `stream` and reports what ftwa_evolve reports after its launches
- * (FTWA_ETIMEOUT, FTWA_ENONFINITE).  Spin-split configurations rely on the
- * GPU running no other work that would keep a pair's two workgroups from
- * being resident together; their waits are bounded (FTWA_ETIMEOUT).
+ * (FTWA_ETIMEOUT, FTWA_ENONFINITE).  Configurations whose trajectories span
+ * several workgroups (a spin block each, or parts of one) rely on the GPU
+ * running no other work that would keep those workgroups from being resident
+ * together; their waits are bounded (FTWA_ETIMEOUT).
  */
 typedef struct ftwa_graph_s* ftwa_graph;
 ftwa_status ftwa_evolve_graph(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,

@@ -451,7 +451,8 @@ ftwa_status finish(const Plan& p, const ftwa_instance* inst, char* ws, hipStream
         if ((st = resident_check_error(err, stream, &timed_out)) != FTWA_OK) return st;
         if (timed_out)
             return fail(FTWA_ETIMEOUT,
-                        "a spin-split workgroup pair timed out waiting for its partner");
+                        "a workgroup of a resident run timed out waiting for the others of its "
+                        "trajectory (were they resident together?)");
     }
     for (int k = 0; k < p.n_inst; ++k) {
         if (!inst[k].inv) continue;
