@@ -88,7 +88,8 @@ struct ResidentArgs {
     int* error;                 // set to 1 when a wait times out
 };
 
-constexpr unsigned kSpinLimit = 1u << 26;  // ~2 s of polling
+constexpr unsigned kSpinLimit = 1u << 26;       // ~2 s of polling
+constexpr unsigned kSplitSpinLimit = 1u << 22;  // ~3.5 s at the split kernel's longer sleeps
 
 // Descriptor table as a global-address-space pointer.  It is passed through
 // an SGPR every phase ("laundered") so that the compiler re-reads descriptors
@@ -881,12 +882,14 @@ __device__ __forceinline__ bool settle_words(const uint64_t* const* src, int str
             ok = ok && (src[k / WPE] == nullptr || (uint32_t)(w[k] >> 32) == want);
         if (ok) return true;
         if (*reinterpret_cast<volatile int*>(&abort_flag)) return false;
-        if (++it >= kSpinLimit) {
+        if (++it >= kSplitSpinLimit) {
             abort_flag = 1;
             atomicExch(error, 1);
             return false;
         }
-        __builtin_amdgcn_s_sleep(1);
+        // ~2000 cycles: polling less often leaves the memory system to the
+        // producers (a shorter sleep is slower overall)
+        __builtin_amdgcn_s_sleep(32);
 #pragma unroll
         for (int k = 0; k < NW; ++k)
             if (src[k / WPE]) w[k] = peek(src[k / WPE] + (size_t)(k % WPE) * stride);
