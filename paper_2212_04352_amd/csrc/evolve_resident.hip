@@ -88,8 +88,7 @@ struct ResidentArgs {
     int* error;                 // set to 1 when a wait times out
 };
 
-constexpr unsigned kSpinLimit = 1u << 26;       // ~2 s of polling
-constexpr unsigned kSplitSpinLimit = 1u << 22;  // ~3.5 s at the split kernel's longer sleeps
+constexpr unsigned kSpinLimit = 1u << 26;  // ~2 s of polling
 
 // Descriptor table as a global-address-space pointer.  It is passed through
 // an SGPR every phase ("laundered") so that the compiler re-reads descriptors
@@ -863,6 +862,8 @@ __device__ __forceinline__ void publish(uint64_t* dst, int stride, cplx_t<T> v, 
 __device__ __forceinline__ uint64_t peek(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+constexpr unsigned kSplitSpinLimit = 1u << 22;  // ~3.5 s at the longer sleeps below
 
 // Waits until NW published words carry stage `want`: w[k] was read from
 // src[k / WPE] + (k % WPE) * stride (WPE = NW / NP, null pointers are

@@ -80,11 +80,14 @@ def test_batched_passes_split_trajectories(ft):
     _assert_same(_snapshot(probs), _snapshot(ref))
 
 
-def test_graph_replays_match_direct_runs(ft):
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_graph_replays_match_direct_runs(ft, dtype):
     """The captured graph, replayed three times with eager work and
-    synchronisation in between, follows three direct ftwa_evolve calls."""
+    synchronisation in between, follows three direct ftwa_evolve calls (FP64:
+    with the split kernel's groups, whose exchange areas are cleared by a
+    fill kernel inside the graph)."""
     import torch
-    probs = _problems(ft, MIXED, "f32", seed=29)
+    probs = _problems(ft, MIXED, dtype, seed=29)
     ref = _clone(ft, probs)
     g = ft.EvolveGraph(probs, 0.01, 8, 4)
     for rep in range(3):

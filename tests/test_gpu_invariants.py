@@ -74,6 +74,20 @@ def test_invariants_flake198_spin_split(ft, orc):
     assert np.max(exp) > 1e3 * tol
 
 
+def test_invariants_fp64_flake198_take_the_stream_path(ft, orc):
+    """The split resident kernel (FP64 at 198 sites) keeps no per-trajectory
+    invariant sums: with monitors the automatic path is the stream path, and
+    forcing the resident path is refused."""
+    got, exp, tol = _run(ft, orc, "armchair", 10, 20, 3.3, 4, 8, 0.01, 4, "f64", "auto")
+    assert np.all(got[:, 3] == 0)
+    assert np.allclose(got[:, :3], exp, rtol=0, atol=tol), np.max(np.abs(got[:, :3] - exp))
+    lat = ft.Lattice("armchair", 10, 20)
+    prob = ft.Problem.allocate(lat, 3.3, 2, lat.fock_start("neel"), "f64", track_invariants=True)
+    ft.sample(prob, 1)
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 1, 1, path="resident")
+
+
 @pytest.mark.parametrize("path", ["stream", "resident"])
 def test_non_finite_trajectory_is_reported(ft, path):
     """A NaN planted in one trajectory's rho(0) stays in that trajectory: the
