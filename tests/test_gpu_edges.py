@@ -90,6 +90,20 @@ def test_other_bipartite_graphs(ft, orc, spec, dtype, path):
     _run(ft, orc, spec, dtype, path, M=70, n0=np.array([1.0 - sub, sub]))  # Neel-like start
 
 
+@pytest.mark.parametrize("config", [19, 20, 21], ids=["split2", "split3", "split4"])
+@pytest.mark.parametrize("spec", [CHAIN7, COMB, ("torus", 2, 3), ("hex", 1, 0)],
+                         ids=["chain7", "comb", "torus12", "hex6"])
+def test_split_kernel_on_small_and_irregular_graphs(ft, orc, spec, config):
+    """The FP64 split configurations forced on graphs far smaller than they are
+    made for: strips of one or two rows, parts that own no diagonal or no
+    element at all, degree-0 and degree-1 sites."""
+    n0 = None
+    if spec[0] == "custom":
+        sub = np.array(spec[3], dtype=float)
+        n0 = np.array([1.0 - sub, sub])
+    _run(ft, orc, spec, "f64", "resident", M=11, steps=9, re=3, n0=n0, config=config)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_odd_ring_runs_on_the_stream_path_only(ft, orc, dtype):
     _run(ft, orc, RING5, dtype, "auto", M=20, n0=np.array([[1, 0, 1, 0, 0.0], [0, 1, 0, 1, 1.0]]))
