@@ -74,6 +74,10 @@ def _load():
         ev.argtypes = [ctypes.c_int, P(i32), P(ctypes.c_uint8), dbl, dbl, dbl, i64, ctypes.c_int,
                        i64, P(dbl), P(dbl), P(dbl)]
         ev.restype = ctypes.c_int
+        evp = getattr(lib, f"oracle_evolve_pot_{suffix}")
+        evp.argtypes = [ctypes.c_int, P(i32), P(ctypes.c_uint8), dbl, dbl, P(dbl), P(dbl), dbl,
+                        i64, ctypes.c_int, i64, P(dbl), P(dbl), P(dbl)]
+        evp.restype = ctypes.c_int
     lib.oracle_moments.argtypes = [ctypes.c_int, i64, ctypes.c_int, P(dbl), P(dbl), P(dbl)]
     lib.oracle_moments.restype = None
     lib.oracle_observables.argtypes = [ctypes.c_int, i64, ctypes.c_int, P(dbl), P(dbl), P(dbl),
@@ -245,14 +249,22 @@ def n_records(n_steps: int, record_every: int) -> int:
 
 
 def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
-           record_every: int = 10, precision: str = "f64", want_inv: bool = False):
+           record_every: int = 10, precision: str = "f64", want_inv: bool = False,
+           vsite=None, env=None):
     """RK4 integration of every trajectory.  Returns (rho_final, X, inv).
 
     rho: [M, 2, N, N] complex128 (not modified).  X: [n_rec, M, 2N] diagonal
     records; inv: [n_rec, M, 5] (trace up, trace down, H_W, |rho_up|_F^2,
-    |rho_dn|_F^2) or None.
+    |rho_dn|_F^2) or None.  vsite ([N]) and env ([2 n_steps + 1]): an
+    external on-site potential V_i(tau) = env(tau) vsite[i] on both spins,
+    env sampled at t_n and t_n + dt/2 of every step (see oracle_evolve_pot).
     """
     lib = _load()
+    if vsite is not None:
+        vs = np.ascontiguousarray(vsite, dtype=np.float64).reshape(-1)
+        ev = np.ascontiguousarray(env, dtype=np.float64).reshape(-1)
+        if vs.size != lat.N or ev.size != 2 * n_steps + 1:
+            raise ValueError("vsite needs N values and env 2 n_steps + 1")
     M = rho.shape[0]
     y = np.ascontiguousarray(rho, dtype=np.complex128).copy()
     n_rec = n_records(n_steps, record_every)
@@ -260,11 +272,18 @@ def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
     inv = np.zeros((n_rec, M, 5), dtype=np.float64) if want_inv else None
     nbr = np.ascontiguousarray(lat.nbr.reshape(-1))
     deg = np.ascontiguousarray(lat.deg)
-    fn = lib.oracle_evolve_f64 if precision == "f64" else lib.oracle_evolve_f32
     dptr = ctypes.POINTER(ctypes.c_double)
-    rc = fn(lat.N, _ptr(nbr, ctypes.c_int32), _ptr(deg, ctypes.c_uint8), lat.t, float(U),
-            float(dt), int(n_steps), int(record_every), M, y.ctypes.data_as(dptr),
-            X.ctypes.data_as(dptr), inv.ctypes.data_as(dptr) if inv is not None else None)
+    if vsite is None:
+        fn = lib.oracle_evolve_f64 if precision == "f64" else lib.oracle_evolve_f32
+        rc = fn(lat.N, _ptr(nbr, ctypes.c_int32), _ptr(deg, ctypes.c_uint8), lat.t, float(U),
+                float(dt), int(n_steps), int(record_every), M, y.ctypes.data_as(dptr),
+                X.ctypes.data_as(dptr), inv.ctypes.data_as(dptr) if inv is not None else None)
+    else:
+        fn = lib.oracle_evolve_pot_f64 if precision == "f64" else lib.oracle_evolve_pot_f32
+        rc = fn(lat.N, _ptr(nbr, ctypes.c_int32), _ptr(deg, ctypes.c_uint8), lat.t, float(U),
+                vs.ctypes.data_as(dptr), ev.ctypes.data_as(dptr), float(dt), int(n_steps),
+                int(record_every), M, y.ctypes.data_as(dptr), X.ctypes.data_as(dptr),
+                inv.ctypes.data_as(dptr) if inv is not None else None)
     if rc != 0:
         raise RuntimeError(f"oracle evolve failed ({rc})")
     return y, X, inv

@@ -16,13 +16,19 @@
  *   d rho_ij,s / dt = i [ t ( sum_{k in nb(j)} rho_ik,s - sum_{k in nb(i)} rho_kj,s )
  *                         + U ( rho_ii,sbar - rho_jj,sbar ) rho_ij,s ]
  *
- * (the 1/2 of (rho_kk + 1/2) cancels between the two u terms).  Evaluation
- * order: each neighbour sum starts from the first (smallest) neighbour and
- * adds the others in ascending order; g = t*(col - row); then
- * a = U*(d_i - d_j) is applied with one fma per component; f = i*g.
+ * (the 1/2 of (rho_kk + 1/2) cancels between the two u terms).  An external
+ * on-site potential V_i (both spins) enters Eq. (5) like the U term, as the
+ * explicit term + (V_i - V_j) rho_ij inside the bracket (Sec. III notes that
+ * time dependence of such a potential appears as explicit terms of Eq. (5));
+ * here V_i = A v_i with `vsite` = v (NULL: no potential) and A the envelope
+ * at the stage time.  Evaluation order: each neighbour sum starts from the
+ * first (smallest) neighbour and adds the others in ascending order;
+ * g = t*(col - row); a = U*(d_i - d_j), then (potential) a = a + A*(v_i - v_j);
+ * a is applied with one fma per component; f = i*g.
  */
-void ORC_NAME(oracle_rhs)(int N, const int32_t* nbr, const uint8_t* deg,
-                          ORC_REAL t, ORC_REAL U, const ORC_REAL* rho, ORC_REAL* f)
+void ORC_NAME(oracle_rhs_pot)(int N, const int32_t* nbr, const uint8_t* deg,
+                              ORC_REAL t, ORC_REAL U, const ORC_REAL* vsite, ORC_REAL A,
+                              const ORC_REAL* rho, ORC_REAL* f)
 {
     const size_t NN2 = (size_t)N * N * 2;
     for (int s = 0; s < 2; ++s) {
@@ -55,12 +61,19 @@ void ORC_NAME(oracle_rhs)(int N, const int32_t* nbr, const uint8_t* deg,
                 ORC_REAL g_re = t * (col_re - row_re);
                 ORC_REAL g_im = t * (col_im - row_im);
                 ORC_REAL a = U * (Rbar[2 * (i * N + i)] - Rbar[2 * (j * N + j)]);
+                if (vsite) a = a + A * (vsite[i] - vsite[j]);
                 g_re = ORC_FMA(a, R[2 * (i * N + j)], g_re);
                 g_im = ORC_FMA(a, R[2 * (i * N + j) + 1], g_im);
                 F[2 * (i * N + j)] = -g_im; /* f = i * g */
                 F[2 * (i * N + j) + 1] = g_re;
             }
     }
+}
+
+void ORC_NAME(oracle_rhs)(int N, const int32_t* nbr, const uint8_t* deg,
+                          ORC_REAL t, ORC_REAL U, const ORC_REAL* rho, ORC_REAL* f)
+{
+    ORC_NAME(oracle_rhs_pot)(N, nbr, deg, t, U, NULL, (ORC_REAL)0, rho, f);
 }
 
 /*
@@ -112,11 +125,15 @@ static void ORC_NAME(invariants)(int N, const int32_t* nbr, const uint8_t* deg,
  * rho: [M][2][N][N] complex FP64 in/out (rounded to the working precision on
  * entry).  Records are taken at steps 0, record_every, 2 record_every, ...:
  *   X[r][m][s*N + i] = rho_ii,s (FP64), inv[r][m][0..4] (see invariants).
+ * vsite (NULL or [N]) and env ([2 n_steps + 1]): the on-site potential
+ * V_i(tau) = A(tau) v_i; step n (from t_n = n h) takes A = env[2n] in stage 1,
+ * env[2n+1] (t_n + h/2) in stages 2 and 3, env[2n+2] (t_n + h) in stage 4;
+ * v and A rounded once to the working precision.
  */
-int ORC_NAME(oracle_evolve)(int N, const int32_t* nbr, const uint8_t* deg,
-                            double t, double U, double dt, int64_t n_steps,
-                            int record_every, int64_t M, double* rho_io,
-                            double* X, double* inv)
+int ORC_NAME(oracle_evolve_pot)(int N, const int32_t* nbr, const uint8_t* deg,
+                                double t, double U, const double* vsite, const double* env,
+                                double dt, int64_t n_steps, int record_every, int64_t M,
+                                double* rho_io, double* X, double* inv)
 {
     if (N <= 0 || M < 0 || n_steps < 0 || record_every <= 0) return -1;
     const size_t E = (size_t)2 * N * N * 2; /* reals per trajectory */
@@ -125,6 +142,13 @@ int ORC_NAME(oracle_evolve)(int N, const int32_t* nbr, const uint8_t* deg,
     const ORC_REAL tw = (ORC_REAL)t, Uw = (ORC_REAL)U;
     const ORC_REAL c_half = (ORC_REAL)(0.5 * dt), c_full = (ORC_REAL)dt;
     const ORC_REAL c_sixth = (ORC_REAL)(dt / 6.0), two = (ORC_REAL)2;
+    ORC_REAL* vw = NULL;
+    if (vsite) {
+        if (!env) return -1;
+        vw = (ORC_REAL*)malloc(sizeof(ORC_REAL) * (size_t)N);
+        if (!vw) return -2;
+        for (int i = 0; i < N; ++i) vw[i] = (ORC_REAL)vsite[i];
+    }
     int failed = 0;
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t m = 0; m < M; ++m) {
@@ -152,25 +176,29 @@ int ORC_NAME(oracle_evolve)(int N, const int32_t* nbr, const uint8_t* deg,
                 }
                 if (step == n_steps) break;
                 /* stage 1 */
-                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, y, k);
+                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 0] : (ORC_REAL)0, y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = k[e];
                     Y[e] = ORC_FMA(c_half, k[e], y[e]);
                 }
                 /* stage 2 */
-                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, Y, k);
+                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = ORC_FMA(two, k[e], acc[e]);
                     Y[e] = ORC_FMA(c_half, k[e], y[e]);
                 }
                 /* stage 3 */
-                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, Y, k);
+                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = ORC_FMA(two, k[e], acc[e]);
                     Y[e] = ORC_FMA(c_full, k[e], y[e]);
                 }
                 /* stage 4 */
-                ORC_NAME(oracle_rhs)(N, nbr, deg, tw, Uw, Y, k);
+                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 2] : (ORC_REAL)0, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = acc[e] + k[e];
                     y[e] = ORC_FMA(c_sixth, acc[e], y[e]);
@@ -181,7 +209,17 @@ int ORC_NAME(oracle_evolve)(int N, const int32_t* nbr, const uint8_t* deg,
         }
         free(y); free(Y); free(k); free(acc);
     }
+    free(vw);
     return failed ? -2 : 0;
+}
+
+int ORC_NAME(oracle_evolve)(int N, const int32_t* nbr, const uint8_t* deg,
+                            double t, double U, double dt, int64_t n_steps,
+                            int record_every, int64_t M, double* rho_io,
+                            double* X, double* inv)
+{
+    return ORC_NAME(oracle_evolve_pot)(N, nbr, deg, t, U, NULL, NULL, dt, n_steps,
+                                       record_every, M, rho_io, X, inv);
 }
 
 #undef ORC_NAME
