@@ -148,6 +148,18 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        writes rho_ii,s(0) = n0[s][i] - 1/2 + n_shift[s][i] while the
  *        off-diagonal noise amplitude uses n0 alone (the noise is held fixed
  *        under the shift); ftwa_adjoint returns the gradient with respect to it.
+ *   v_site [N] FP64 or NULL, v_env [2 n_steps + 1] FP64  an external on-site
+ *        potential V_i(tau) = A(tau) v_site[i] acting on both spins (Sec. III:
+ *        the time dependence of an external potential enters Eq. (5) as
+ *        explicit terms): ftwa_evolve adds i (V_i(tau) - V_j(tau)) rho_ij to
+ *        the right-hand side, with A sampled by the caller at half steps from
+ *        the start of the call, v_env[k] = A(k dt/2): step n uses v_env[2n] in
+ *        its first Runge-Kutta stage, v_env[2n+1] in the second and third,
+ *        v_env[2n+2] in the fourth.  Arithmetic: a = U (d_i - d_j), then
+ *        a = a + A (v_i - v_j), A and v rounded once to the working precision.
+ *        Integrated by the stream kernels (FTWA_ENOTSUP when the resident path
+ *        or a resident configuration is forced); ftwa_adjoint refuses it.
+ *        v_env must hold 2 n_steps + 1 values (not checked: device memory).
  * Trajectory m of the instance has global index traj_offset + m; it keys the
  * random numbers, so any trajectory range reproduces the same trajectories.
  * `instance` enters the random-number counter (distinct streams per instance
@@ -165,6 +177,8 @@ typedef struct {
     double* S2;
     double* inv;
     const double* n_shift;
+    const double* v_site;
+    const double* v_env;
 } ftwa_instance;
 
 /*

@@ -48,6 +48,8 @@ class Instance(ctypes.Structure):
         ("S2", ctypes.c_void_p),
         ("inv", ctypes.c_void_p),
         ("n_shift", ctypes.c_void_p),
+        ("v_site", ctypes.c_void_p),
+        ("v_env", ctypes.c_void_p),
     ]
 
 
@@ -180,7 +182,7 @@ def _instances(insts):
         arr[k] = Instance(d["lat"], float(d["U"]), int(d["n_traj"]), int(d.get("traj_offset", 0)),
                           int(d.get("instance", 0)), _ptr(d["n0"]), _ptr(d["rho"]),
                           _ptr(d.get("S1")), _ptr(d.get("S2")), _ptr(d.get("inv")),
-                          _ptr(d.get("n_shift")))
+                          _ptr(d.get("n_shift")), _ptr(d.get("v_site")), _ptr(d.get("v_env")))
     return arr
 
 

@@ -393,6 +393,8 @@ ftwa_status plan_adjoint(const ftwa_instance* inst, int64_t n_steps, int record_
     if (ckpt_every < 1) return fail(FTWA_EINVAL, "ckpt_every < 1");
     if (inst->n_traj < 1) return fail(FTWA_EINVAL, "ftwa_adjoint: n_traj < 1");
     if (traj_chunk < 0) return fail(FTWA_EINVAL, "traj_chunk < 0");
+    if (inst->v_site)
+        return fail(FTWA_ENOTSUP, "ftwa_adjoint: no gradients through an external potential");
     AdjointLayout a;
     const int N = inst->lat->N;
     const int64_t P = packed_count(N);

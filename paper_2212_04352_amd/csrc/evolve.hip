@@ -123,8 +123,12 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 cfg = c;
             }
         }
-        const bool can_res =
-            !tuned_stream && resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
+        // an external potential is integrated by the stream kernels only
+        const bool pot = inst[k].v_site != nullptr;
+        if (pot && (want == FTWA_PATH_RESIDENT || force >= 0))
+            return fail(FTWA_ENOTSUP, "an external potential runs on the stream path only");
+        const bool can_res = !tuned_stream && !pot &&
+                             resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
         if (force >= 0 && !can_res)
             return fail(FTWA_ENOTSUP, "the forced resident configuration does not fit");
         if (want == FTWA_PATH_RESIDENT && !can_res)
@@ -361,11 +365,14 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             c.t = in.lat->t;
             c.U = in.U;
             c.dt = p.dt;
+            c.v_site = in.v_site;
+            c.v_env = in.v_env;
             if ((st = record_diag(c, tab, p.dtype, X, stream)) != FTWA_OK) return st;
             if (parts && (st = record_inv(c, tab, p.dtype, parts, stream)) != FTWA_OK) return st;
             int64_t open_steps = 0;
             for (int64_t step = 1; step <= p.n_steps; ++step) {
                 if (open_steps == 0 && (st = timer.begin(stream)) != FTWA_OK) return st;
+                c.step = step - 1;
                 if ((st = stream_step(c, tab, p.dtype, stream)) != FTWA_OK) return st;
                 ++open_steps;
                 if (open_steps == 64 || step == p.n_steps) {
@@ -674,6 +681,8 @@ ftwa_instance probe_instance(const ftwa_instance& in, int64_t Mp, char* ws, cons
     q.S1 = ws ? reinterpret_cast<double*>(ws + pr.off_s1) : nullptr;
     q.S2 = ws ? reinterpret_cast<double*>(ws + pr.off_s2) : nullptr;
     q.inv = nullptr;
+    q.v_site = nullptr;  // the probes time the kernels without the potential term
+    q.v_env = nullptr;
     return q;
 }
 

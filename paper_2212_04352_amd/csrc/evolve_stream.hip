@@ -34,6 +34,8 @@ template <typename T> struct StageArgs {
     const int32_t* nb;     // [N][4]
     const uint32_t* elem;  // [P]: packed element -> i | j << 16
     T t, U, c;             // c: this stage's coefficient (h/2, h/2, h, h/6)
+    const double* vsite;   // NULL, or [N]: profile of the external on-site potential
+    const double* env_at;  // its envelope at this stage's time
     int64_t n_elem_chunks; // ceil(2P / kElemsPerWave)
     int64_t n_work;        // n_traj_blocks * n_elem_chunks waves
     int64_t blocks_per_xcd;
@@ -94,7 +96,10 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
         cplx_t<T> ac, yv;
         if (STAGE > 1) ac = A.acc[e_ws];
         if (STAGE > 1) yv = A.y[e_y];
-        const T a = A.U * (d_i - d_j);
+        T a = A.U * (d_i - d_j);
+        // external potential: a + A(tau) (v_i - v_j), each factor rounded once
+        // to T (i, j and the envelope are wave-uniform: scalar loads)
+        if (A.vsite) a = a + (T)*A.env_at * ((T)A.vsite[i] - (T)A.vsite[j]);
         const cplx_t<T> k = rhs_element<T>(col, row, own, A.t, a);
         if (STAGE == 1) {
             // Y_1 = y, so `own` is y itself
@@ -172,14 +177,17 @@ ftwa_status step_impl(const StreamChunk& c, const DeviceTables& tab, hipStream_t
     cplx_t<T>* yb = static_cast<cplx_t<T>*>(c.yb);
     const T c_half = (T)(0.5 * c.dt), c_full = (T)c.dt, c_sixth = (T)(c.dt / 6.0);
     const int4* nb4 = reinterpret_cast<const int4*>(tab.nb);
+    // stage times t_n, t_n + h/2 (twice), t_n + h: envelope samples 2n, 2n+1, 2n+2
+    A.vsite = c.v_site;
+    const double* env = c.v_site ? c.v_env + 2 * c.step : nullptr;
 
-    A.yin = A.y; A.ldin = c.ldy; A.yout = ya; A.c = c_half;
+    A.yin = A.y; A.ldin = c.ldy; A.yout = ya; A.c = c_half; A.env_at = env;
     hipLaunchKernelGGL((rk4_stage_stream<T, 1>), grid, block, 0, stream, A, nb4);
-    A.yin = ya; A.ldin = c.Mc; A.yout = yb; A.c = c_half;
+    A.yin = ya; A.ldin = c.Mc; A.yout = yb; A.c = c_half; A.env_at = env ? env + 1 : nullptr;
     hipLaunchKernelGGL((rk4_stage_stream<T, 2>), grid, block, 0, stream, A, nb4);
-    A.yin = yb; A.ldin = c.Mc; A.yout = ya; A.c = c_full;
+    A.yin = yb; A.ldin = c.Mc; A.yout = ya; A.c = c_full; A.env_at = env ? env + 1 : nullptr;
     hipLaunchKernelGGL((rk4_stage_stream<T, 3>), grid, block, 0, stream, A, nb4);
-    A.yin = ya; A.ldin = c.Mc; A.yout = nullptr; A.c = c_sixth;
+    A.yin = ya; A.ldin = c.Mc; A.yout = nullptr; A.c = c_sixth; A.env_at = env ? env + 2 : nullptr;
     hipLaunchKernelGGL((rk4_stage_stream<T, 4>), grid, block, 0, stream, A, nb4);
     FTWA_LAUNCH_CHECK("rk4_stage_stream");
     return FTWA_OK;

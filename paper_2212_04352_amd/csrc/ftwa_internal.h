@@ -183,6 +183,12 @@ struct StreamChunk {
     void* ya;
     void* yb;
     double t, U, dt;
+    // external on-site potential V_i(tau) = A(tau) v_i (NULL: none): v_site
+    // [N], v_env the instance's envelope samples at half steps; `step` is the
+    // index of the step being taken (its stages read v_env[2 step + 0/1/1/2])
+    const double* v_site = nullptr;
+    const double* v_env = nullptr;
+    int64_t step = 0;
 };
 ftwa_status stream_step(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
                         hipStream_t stream);

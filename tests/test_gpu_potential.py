@@ -1,0 +1,133 @@
+"""An external on-site potential V_i(t) = A(t) v_i (the explicit time-dependent
+term of Eq. (5) for an external potential, Sec. III) through the C ABI: the
+stream kernels against the oracle bitwise (same operation order: a = U(d_i -
+d_j), then a + A(v_i - v_j), A and v rounded once), batches mixing instances
+with and without a potential, trajectory chunks, graph replays, and the paths
+that refuse it."""
+import numpy as np
+import pytest
+
+from tests._util import pack, unpack
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ft():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_04352_amd as ft
+    ft.load()
+    return ft
+
+
+def _host(x):
+    import torch
+    torch.cuda.synchronize()
+    return x.detach().cpu().numpy()
+
+
+def _pulse(n_steps, dt, A0=1.3, t0=0.1, w=0.05, nu=6.0):
+    tau = np.arange(2 * n_steps + 1) * dt / 2
+    return A0 * np.exp(-((tau - t0) / w) ** 2) * np.cos(nu * tau)
+
+
+def _setup(ft, orc, kind, a, b, M, dtype, seed, U=3.3, profile="staggered"):
+    import torch
+    olat = orc.Lattice(kind, a, b)
+    lat = ft.Lattice(kind, a, b)
+    n0 = orc.fock_start(olat, "random", seed)
+    rho0 = orc.sample(olat, n0, seed, M)
+    prob = ft.Problem.allocate(lat, U, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    if profile == "staggered":
+        v = np.array([(-1.0) ** s for s in olat.sub])
+    else:
+        v = np.random.default_rng(seed).uniform(-1, 1, lat.N)
+    return olat, lat, rho0, prob, v, cdt
+
+
+def _attach(prob, v, env):
+    import torch
+    prob.v_site = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+    prob.v_env = torch.from_numpy(np.ascontiguousarray(env, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kind,a,b,M,steps,profile", [
+    ("torus", 2, 3, 70, 60, "staggered"),
+    ("hex", 2, 0, 33, 40, "random"),        # degree-2 edge sites
+    ("armchair", 10, 20, 5, 12, "random"),  # 198 sites
+])
+def test_potential_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps, profile):
+    dt, re = 0.01, 4
+    olat, lat, rho0, prob, v, cdt = _setup(ft, orc, kind, a, b, M, dtype, 7, profile=profile)
+    env = _pulse(steps, dt)
+    _attach(prob, v, env)
+    ft.evolve(prob, dt, steps, re)  # automatic path: the stream kernels
+    y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype,
+                                 vsite=v, env=env)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+    # and the potential did something
+    y0, _, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype)
+    assert np.max(np.abs(y_ref - y0)) > 1e-4
+
+
+def test_batch_chunks_and_mixed_instances(ft, orc):
+    """One call with two instances, one with a potential and one without, in
+    trajectory chunks of 16: each equals its own oracle run."""
+    import torch
+    dt, steps, re = 0.01, 20, 5
+    o1, l1, r1, p1, v1, _ = _setup(ft, orc, "torus", 3, 9, 37, "f64", 11, U=2.0)
+    o2, l2, r2, p2, _, _ = _setup(ft, orc, "hex", 2, 0, 21, "f64", 12, U=1.0)
+    p2.instance = 1
+    env = _pulse(steps, dt, A0=0.8, t0=0.05)
+    _attach(p1, v1, env)
+    ft.evolve([p1, p2], dt, steps, re, traj_chunk=16)
+    y1, _, _ = orc.evolve(o1, 2.0, r1, dt, steps, re, vsite=v1, env=env)
+    y2, _, _ = orc.evolve(o2, 1.0, r2, dt, steps, re)
+    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1)
+    assert np.array_equal(unpack(_host(p2.rho), l2.N), y2)
+    torch.cuda.synchronize()
+
+
+def test_graph_replays_with_a_potential(ft, orc):
+    """A captured run with a potential replayed twice equals two direct runs."""
+    import torch
+    dt, steps, re = 0.01, 10, 5
+    olat, lat, rho0, prob, v, _ = _setup(ft, orc, "torus", 2, 3, 40, "f32", 13)
+    env = _pulse(steps, dt)
+    _attach(prob, v, env)
+    ref = ft.Problem.allocate(lat, 3.3, 40, prob.n0.cpu().numpy(), "f32")
+    ref.rho.copy_(prob.rho)
+    ref.v_site, ref.v_env = prob.v_site, prob.v_env
+    g = ft.EvolveGraph([prob], dt, steps, re)
+    for _ in range(2):
+        g.launch()
+        g.check()
+        ft.evolve(ref, dt, steps, re)
+        torch.cuda.synchronize()
+        assert torch.equal(prob.rho, ref.rho)
+    g.close()
+
+
+def test_paths_that_refuse_a_potential(ft, orc):
+    import torch
+    olat, lat, rho0, prob, v, _ = _setup(ft, orc, "torus", 2, 3, 8, "f32", 14)
+    _attach(prob, v, _pulse(4, 0.01))
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 4, 2, path="resident")
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 4, 2, config=4)
+    w = torch.zeros((2, 2 * lat.N), dtype=torch.float64, device="cuda")
+    with pytest.raises(ft.FtwaError):
+        ft.adjoint(prob, 0.01, 4, 4, 4, w)
+    prob.v_env = None  # a profile needs its envelope
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 4, 2)
