@@ -341,8 +341,9 @@ def run_pulse(args):
     """A time-dependent staggered potential on the 198-site flake (the
     external-potential term of Eq. (5)): V_i(t) = A(t) (+1 on one sublattice,
     -1 on the other), A a Gaussian pulse with a carrier; 4096 trajectories x
-    400 steps in FP32 and FP64 on the stream kernels, with and without the
-    potential (the cost of the term)."""
+    400 steps, FP32 on the spin-split resident kernel and on the stream
+    kernels, FP64 on the stream kernels, each with and without the potential
+    (the cost of the term)."""
     import numpy as np
     import torch
     import paper_2212_04352_amd as ft
@@ -356,36 +357,38 @@ def run_pulse(args):
     sub = np.asarray(lat.sub, dtype=np.float64)
     v = 1.0 - 2.0 * sub
     rows = []
-    for dtype in ("f32", "f64"):
+    runs = [("f32", "resident"), ("f32", "stream"), ("f64", "stream")]
+    for dtype, path in runs:
         for with_pot in (False, True):
             p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
             if with_pot:
                 p.v_site = torch.from_numpy(v).cuda()
                 p.v_env = torch.from_numpy(env).cuda()
             ft.sample(p, 5)
-            ws = ft.evolve(p, dt, 2, 1, path="stream")  # warm-up (the envelope's first samples)
+            ws = ft.evolve(p, dt, 2, 1, path=path)  # warm-up (the envelope's first samples)
             ft.sample(p, 5)
             timing = ft.new_timing()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ft.evolve(p, dt, steps, 10, path="stream", workspace=ws, timing=timing)
+            ft.evolve(p, dt, steps, 10, path=path, workspace=ws, timing=timing)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             kernel_s = timing["ms"].value / 1e3
             word = 4 if dtype == "f32" else 8
             alg = 2 * 2 * N * N * word * M * steps  # one read + one write of the state per step
-            rows.append({"dtype": dtype, "potential": with_pot, "value": M * steps / el,
+            rows.append({"dtype": dtype, "path": path, "potential": with_pot,
+                         "value": M * steps / el,
                          "kernel_value": M * steps / kernel_s,
                          "roofline": {"bound": "hbm", "achieved": alg / kernel_s / 1e9,
                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                       "frac": alg / kernel_s / 1e9 / HBM_PEAK_GBS}})
-            log(f"pulse: {dtype} potential={with_pot}: {M * steps / el:.3e} traj-steps/s")
+            log(f"pulse: {dtype} {path} potential={with_pot}: {M * steps / el:.3e} traj-steps/s")
             del p, ws
     print(json.dumps({
         "metric": "trajectory*RK4-steps/s with a time-dependent staggered potential, 198-site flake",
         "unit": "trajectory*RK4-steps/s", "rows": rows,
         "config": {"workload": "flake198_pulse", "trajectories": M, "rk4_steps": steps, "dt": dt,
-                   "path": "stream", "envelope": "exp(-((t-0.5)/0.2)^2) cos(6t)",
+                   "envelope": "exp(-((t-0.5)/0.2)^2) cos(6t)",
                    "profile": "+1 / -1 by sublattice"}}))
 
 

@@ -48,6 +48,7 @@ struct LaunchDesc {                // one resident launch: a group in a pass
     int64_t grid = 0;
     double work = 0;               // trajectory-steps
     bool unit_hop = true;          // every instance has t = 1
+    bool potential = false;        // an instance carries an external potential
 };
 
 struct GroupPlan {
@@ -123,12 +124,18 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 cfg = c;
             }
         }
-        // an external potential is integrated by the stream kernels only
+        // an external potential: the stream kernels, or a resident configuration
+        // with the potential variant (FP32 spin split)
         const bool pot = inst[k].v_site != nullptr;
-        if (pot && (want == FTWA_PATH_RESIDENT || force >= 0))
-            return fail(FTWA_ENOTSUP, "an external potential runs on the stream path only");
-        const bool can_res = !tuned_stream && !pot &&
-                             resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
+        bool can_res = !tuned_stream && resident_plan(N, dtype, tab, &ip.res, cfg,
+                                                      inst[k].inv == nullptr);
+        if (pot && can_res) {
+            // the configuration chosen without the potential, if it has the
+            // potential variant (else the stream path)
+            const int c0 = ip.res.config;
+            can_res = resident_has_potential(c0) &&
+                      resident_plan(N, dtype, tab, &ip.res, c0, inst[k].inv == nullptr, true);
+        }
         if (force >= 0 && !can_res)
             return fail(FTWA_ENOTSUP, "the forced resident configuration does not fit");
         if (want == FTWA_PATH_RESIDENT && !can_res)
@@ -240,6 +247,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 L.n_items += (Mc + per - 1) / per;
                 L.work += (double)Mc * n_steps;
                 if (inst[k].lat->t != 1.0) L.unit_hop = false;
+                if (inst[k].v_site) L.potential = true;
                 ++L.n_entries;
             }
             entry += L.n_entries;
@@ -309,6 +317,8 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 e.dump = p.dump ? static_cast<char*>(p.dump) + (size_t)m0 * cplx_bytes(p.dtype)
                                 : nullptr;
                 e.dump_stride = p.dump_stride;
+                e.v_site = inst[k].v_site;
+                e.v_env = inst[k].v_env;
                 table.push_back(e);
             }
         }
@@ -421,6 +431,7 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             L.cooperative = cooperative;
             L.unit_hop = Ld.unit_hop;
             L.dumps = p.dump != nullptr;
+            L.potential = Ld.potential;
             if ((st = timer.begin(stream)) != FTWA_OK) return st;
             if ((st = resident_launch(L, stream)) != FTWA_OK) return st;
             if ((st = timer.end(stream, 1, Ld.work)) != FTWA_OK) return st;

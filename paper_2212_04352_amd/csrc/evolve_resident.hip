@@ -252,9 +252,14 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // plain (fma(1, v, s) and s + v round alike, so both forms give the same
 // bits).  The element's own value is read from LDS, or taken from `own`
 // (OWN_REG).
-template <typename T, bool OWN_REG, bool GEN, bool T1>
+// POT: an external on-site potential adds A (v_i - v_j) to the U factor (Vd:
+// the profile v in the layout of the diagonal array, Aw: the envelope at the
+// stage time; only when `pot_on`).
+template <typename T, bool OWN_REG, bool GEN, bool T1, bool POT = false>
 __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
-                                                 const Stencil& e, T t, T U, cplx_t<T> own) {
+                                                 const Stencil& e, T t, T U, cplx_t<T> own,
+                                                 const unsigned char* Vd = nullptr, T Aw = 0,
+                                                 bool pot_on = false) {
     using C = cplx_t<T>;
     C col, row;
     if constexpr (GEN) {
@@ -281,7 +286,12 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
     const C rho = OWN_REG ? own : *reinterpret_cast<const C*>(Yb + e.own);
     const T di = *reinterpret_cast<const T*>(Yd + e.di);
     const T dj = *reinterpret_cast<const T*>(Yd + e.dj);
-    const T a = U * (di - dj);
+    T a = U * (di - dj);
+    if constexpr (POT) {
+        if (pot_on)
+            a = a + Aw * (*reinterpret_cast<const T*>(Vd + e.di) -
+                          *reinterpret_cast<const T*>(Vd + e.dj));
+    }
     if constexpr (T1) {
         // t = 1: t * x is x exactly, the hopping sums enter unscaled
         cplx_t<T> f;
@@ -299,12 +309,16 @@ __device__ __forceinline__ uint32_t own_off(const ResDesc& d) { return d.a.w; }
 __device__ __forceinline__ uint32_t own_off(const uint4& w) { return lo16x8(w.w); }
 
 // The same with the variant chosen by a (compile-time) slot condition.
-template <typename T, bool OWN_REG, bool T1, typename DT>
+template <typename T, bool OWN_REG, bool T1, typename DT, bool POT = false>
 __device__ __forceinline__ cplx_t<T> element_rhs_sel(bool gen, const unsigned char* Yb,
                                                      const unsigned char* Yd, const DT& d,
-                                                     T t, T U, cplx_t<T> own) {
-    return gen ? element_rhs<T, OWN_REG, true, T1>(Yb, Yd, decode<true>(d), t, U, own)
-               : element_rhs<T, OWN_REG, false, T1>(Yb, Yd, decode<false>(d), t, U, own);
+                                                     T t, T U, cplx_t<T> own,
+                                                     const unsigned char* Vd = nullptr, T Aw = 0,
+                                                     bool pot_on = false) {
+    return gen ? element_rhs<T, OWN_REG, true, T1, POT>(Yb, Yd, decode<true>(d), t, U, own, Vd,
+                                                         Aw, pot_on)
+               : element_rhs<T, OWN_REG, false, T1, POT>(Yb, Yd, decode<false>(d), t, U, own, Vd,
+                                                          Aw, pot_on);
 }
 
 // One Runge-Kutta stage update of an element from its slope k:
@@ -355,12 +369,16 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 }
 
 // T1: every instance of the launch has t = 1 (the usual unit of energy).
-template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1>
+// POT (spin split only): entries may carry an external on-site potential;
+// its profile sits in LDS after the partner's diagonal, in the same layout.
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1,
+          bool POT = false>
 __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     // descriptor form: compact for the spin split, wide otherwise
     using DT = std::conditional_t<S == 1, uint4, ResDesc>;
     static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
+    static_assert(!POT || (S == 1 && !T1), "the potential is built into general spin-split kernels");
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
@@ -419,7 +437,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         // dynamic block starts at LDS address 0 and offsets are addresses (no
         // base register; constant offsets go into the instructions).
         unsigned char* const Yunit =
-            lds_ptr((uint32_t)((S == 1 ? 2 * kDiagCopy : 0) + (size_t)unit * S * Pb * CB));
+            lds_ptr((uint32_t)((S == 1 ? (POT ? 3 : 2) * kDiagCopy : 0) + (size_t)unit * S * Pb * CB));
         unsigned char* const dpart = lds_ptr(0);
         // per-wave partial sums of the records and the abort flag follow
         // (placed after the largest blocks of the launch: A.tail_off)
@@ -492,6 +510,17 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         }
         const int32_t* const dpos = reinterpret_cast<const int32_t*>(uniform64((uint64_t)E.dpos));
         const int qdiag = (S == 1 && tid < N) ? dpos[tid] : 0;  // this thread's polled site
+        // external potential of this entry: its profile after the diagonal
+        // copies (same layout), the envelope read per stage
+        const double* const venv = POT ? reinterpret_cast<const double*>(uniform64((uint64_t)E.v_env))
+                                       : nullptr;
+        const bool pot_on = POT && E.v_site != nullptr;
+        unsigned char* const vpart = lds_ptr(2 * kDiagCopy);
+        if constexpr (POT) {
+            const double* const vs = reinterpret_cast<const double*>(uniform64((uint64_t)E.v_site));
+            for (int i = t; i < N; i += NTU)
+                reinterpret_cast<T*>(vpart)[dpos[i]] = pot_on ? (T)vs[i] : (T)0;
+        }
         if constexpr (S == 1) {
             // the partner's diagonal in two alternating copies (stage parity),
             // reals in sublattice-major order; the current one from HBM
@@ -570,6 +599,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         const T c_half = uniform_real<T>((T)(0.5 * A.dt));
         const T c_full = uniform_real<T>((T)A.dt);
         const T c_sixth = uniform_real<T>((T)(A.dt / 6.0));
+        int64_t cur_step = 0;  // index of the step being taken (the envelope's sample 2 cur_step)
 
         // One Runge-Kutta stage (STAGE = 1..4) of every element of the unit.
         // Returns false when a spin-split wait timed out.
@@ -580,6 +610,12 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             // of the stage counter's parity, which is that of STAGE - 1: every
             // step advances the counter by four)
             const unsigned char* dcur = dpart + ((STAGE - 1) & 1) * kDiagCopy;
+            // envelope at this stage's time: t_n, t_n + h/2 (twice), t_n + h
+            T Aw = 0;
+            if constexpr (POT) {
+                if (pot_on)
+                    Aw = uniform_real<T>((T)venv[2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)]);
+            }
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
             // registers); descriptors are loaded KP slots ahead.
@@ -609,7 +645,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         // is y itself, so nothing is held across steps
                         const C own = STAGE == 1 ? y[s][u] : hold[s][u];
                         *reinterpret_cast<C*>(Yb + own_off(d)) = own;
-                        k = element_rhs_sel<T, true, T1>(u < GE, Yb, dcur, d, tw, Uw, own);
+                        k = element_rhs_sel<T, true, T1, DT, POT>(u < GE, Yb, dcur, d, tw, Uw, own,
+                                                                  vpart, Aw, pot_on);
                     } else {
                         k = element_rhs_sel<T, false, T1>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
                                                       tw, Uw, hold[s][u]);
@@ -648,8 +685,10 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     // stage 1 reads the element's own value from y (the
                     // stage input of a full step is its base point)
                     const C k = STAGE == 1
-                        ? element_rhs_sel<T, true, T1>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u])
-                        : element_rhs_sel<T, false, T1>(u - UE < GO, Yb, Yd, d, tw, Uw, y[s][u]);
+                        ? element_rhs_sel<T, true, T1, DT, POT>(u - UE < GO, Yb, Yd, d, tw, Uw,
+                                                                 y[s][u], vpart, Aw, pot_on)
+                        : element_rhs_sel<T, false, T1, DT, POT>(u - UE < GO, Yb, Yd, d, tw, Uw,
+                                                                  y[s][u], vpart, Aw, pot_on);
                     *reinterpret_cast<C*>(Yb + own_off(d)) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
@@ -727,6 +766,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         };
 
         for (int64_t step = 1; step <= A.n_steps; ++step) {
+            cur_step = step - 1;
             if (!run_stage(stage_c<1>{})) return;
             if (!run_stage(stage_c<2>{})) return;
             if (!run_stage(stage_c<3>{})) return;
@@ -1222,6 +1262,7 @@ struct Config {
     int G = 1;
     int UB = 0, GE2 = 0, XO = 0, KB = 0;
     bool auto_pick = true;  // false: chosen only when forced or by the autotuner
+    const void* fn_pot = nullptr;  // variant with the external potential (FP32 spin split)
 };
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
@@ -1232,10 +1273,19 @@ constexpr const void* unit_hop_fn() {
         return nullptr;
 }
 
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
+constexpr const void* potential_fn() {
+    if constexpr (std::is_same<T, float>::value && S == 1)
+        return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false, true>;
+    else
+        return nullptr;
+}
+
 #define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO, GE, GO)                    \
     Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                                    \
            (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
-           unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
+           unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(), 1, 0, 0, 0, 0, true, \
+           potential_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
 
 template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
           int KB>
@@ -1317,7 +1367,7 @@ int64_t split_words(const Config& c) {
 }  // namespace
 
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
-                   int force_config, bool allow_split) {
+                   int force_config, bool allow_split, bool need_potential) {
     if (!tab.bipartite) return false;
     const int P = (int)packed_count(N);
     const int n_even = (int)tab.n_even, n_odd = P - n_even;
@@ -1328,6 +1378,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         const Config& c = kConfigs[k];
         if (c.dtype != dtype) continue;
         if (!c.auto_pick && force_config < 0) continue;
+        if (need_potential && !c.fn_pot) continue;
         if (N > c.NTU) continue;  // the diagonal must sit in slot 0
         size_t lds;
         if (c.G > 1) {
@@ -1347,6 +1398,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if ((int64_t)c.NTU * c.GE < tab.n_gen_even || (int64_t)c.NTU * c.GO < tab.n_gen_odd)
                 continue;
             lds = lds_bytes(c, N, P);
+            if (need_potential) lds += 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // the profile
         }
         if (lds > kMaxLds) continue;
         plan->config = k;
@@ -1366,6 +1418,7 @@ int resident_config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0]
 
 int resident_spins(int config) { return kConfigs[config].S; }
 int resident_parts(int config) { return kConfigs[config].G; }
+bool resident_has_potential(int config) { return kConfigs[config].fn_pot != nullptr; }
 
 int64_t resident_item_traj(int config) {
     const Config& c = kConfigs[config];
@@ -1389,6 +1442,9 @@ ftwa_status resident_prepare(int config, size_t lds) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
     if (kConfigs[config].fn_t1)
         FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn_t1,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    if (kConfigs[config].fn_pot)
+        FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn_pot,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
     return FTWA_OK;
 }
@@ -1471,7 +1527,8 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     A.error = L.error;
     void* args[] = {&A};
     const int64_t grid = L.grid;
-    const void* fn = L.unit_hop && !L.dumps && c.fn_t1 ? c.fn_t1 : c.fn;
+    const void* fn = L.potential ? c.fn_pot : (L.unit_hop && !L.dumps && c.fn_t1 ? c.fn_t1 : c.fn);
+    if (!fn) return fail(FTWA_ENOTSUP, "this configuration has no external-potential variant");
     if (c.S == 1) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,
         // no memset node)

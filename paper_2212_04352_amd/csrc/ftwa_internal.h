@@ -247,6 +247,8 @@ struct ResidentInst {
     int64_t dump_stride;
     int part_words;      // split configurations: desc is split_tables(...), one block per
     int hmax;            // part of part_words words; hmax: import capacity
+    const double* v_site;  // NULL or [N]: external on-site potential profile (ftwa_instance)
+    const double* v_env;   // its envelope at half steps from the start of the run
 };
 struct ResidentLaunch {
     int config;
@@ -264,15 +266,18 @@ struct ResidentLaunch {
     bool cooperative;           // false under graph capture
     bool unit_hop;              // every instance of the launch has t = 1
     bool dumps;                 // an entry stores its state at records (ResidentInst::dump)
+    bool potential;             // an entry carries an external potential (the POT variant)
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).
 // allow_split: the split configurations may be chosen (they keep no
-// invariant sums).
+// invariant sums); need_potential: only configurations with an
+// external-potential variant (the FP32 spin split).
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
-                   int force_config = -1, bool allow_split = true);
+                   int force_config = -1, bool allow_split = true, bool need_potential = false);
 int resident_config_count();
 int resident_spins(int config);
 int resident_parts(int config);  // workgroups per spin block (> 1: split tables)
+bool resident_has_potential(int config);  // has the external-potential variant
 int64_t resident_item_traj(int config);      // trajectories per item of the schedule
 int64_t resident_max_pairs();
 int64_t resident_concurrency(int config, size_t lds);  // trajectories in flight at once

@@ -79,6 +79,39 @@ def test_potential_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps, 
     assert np.max(np.abs(y_ref - y0)) > 1e-4
 
 
+@pytest.mark.parametrize("kind,a,b,M,steps", [("hex", 5, 0, 9, 10), ("armchair", 10, 20, 7, 10)])
+def test_potential_on_the_spin_split_resident_kernel(ft, orc, kind, a, b, M, steps):
+    """FP32 at 150 and 198 sites: the spin-split resident kernel's potential
+    variant (the profile in LDS beside the partner's diagonal, the envelope a
+    wave-uniform value per stage) bitwise equal to the oracle."""
+    dt, re = 0.01, 5
+    olat, lat, rho0, prob, v, cdt = _setup(ft, orc, kind, a, b, M, "f32", 17, profile="random")
+    env = _pulse(steps, dt, t0=0.04)
+    _attach(prob, v, env)
+    ft.evolve(prob, dt, steps, re, path="resident")
+    y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision="f32",
+                                 vsite=v, env=env)
+    assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref.astype(cdt))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+
+
+def test_resident_launch_mixing_entries_with_and_without_a_potential(ft, orc):
+    """Two 198-site FP32 instances in one resident launch (same configuration),
+    only the first with a potential: each equals its own oracle run."""
+    dt, steps, re = 0.01, 8, 4
+    o1, l1, r1, p1, v1, _ = _setup(ft, orc, "armchair", 10, 20, 5, "f32", 21, profile="random")
+    o2, l2, r2, p2, _, _ = _setup(ft, orc, "armchair", 10, 20, 6, "f32", 22, U=2.0)
+    p2.instance = 1
+    env = _pulse(steps, dt, t0=0.03)
+    _attach(p1, v1, env)
+    ft.evolve([p1, p2], dt, steps, re, path="resident")
+    y1, _, _ = orc.evolve(o1, 3.3, r1, dt, steps, re, precision="f32", vsite=v1, env=env)
+    y2, _, _ = orc.evolve(o2, 2.0, r2, dt, steps, re, precision="f32")
+    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1.astype(np.complex64))
+    assert np.array_equal(unpack(_host(p2.rho), l2.N), y2.astype(np.complex64))
+
+
 def test_batch_chunks_and_mixed_instances(ft, orc):
     """One call with two instances, one with a potential and one without, in
     trajectory chunks of 16: each equals its own oracle run."""
