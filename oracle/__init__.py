@@ -78,6 +78,10 @@ def _load():
         evp.argtypes = [ctypes.c_int, P(i32), P(ctypes.c_uint8), dbl, dbl, P(dbl), P(dbl), dbl,
                         i64, ctypes.c_int, i64, P(dbl), P(dbl), P(dbl)]
         evp.restype = ctypes.c_int
+        evg = getattr(lib, f"oracle_evolve_gen_{suffix}")
+        evg.argtypes = [ctypes.c_int, P(i32), P(ctypes.c_uint8), dbl, dbl, P(dbl), P(dbl),
+                        P(dbl), dbl, i64, ctypes.c_int, i64, P(dbl), P(dbl), P(dbl)]
+        evg.restype = ctypes.c_int
     lib.oracle_moments.argtypes = [ctypes.c_int, i64, ctypes.c_int, P(dbl), P(dbl), P(dbl)]
     lib.oracle_moments.restype = None
     lib.oracle_observables.argtypes = [ctypes.c_int, i64, ctypes.c_int, P(dbl), P(dbl), P(dbl),
@@ -250,7 +254,7 @@ def n_records(n_steps: int, record_every: int) -> int:
 
 def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
            record_every: int = 10, precision: str = "f64", want_inv: bool = False,
-           vsite=None, env=None):
+           vsite=None, env=None, umat=None):
     """RK4 integration of every trajectory.  Returns (rho_final, X, inv).
 
     rho: [M, 2, N, N] complex128 (not modified).  X: [n_rec, M, 2N] diagonal
@@ -258,6 +262,8 @@ def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
     |rho_dn|_F^2) or None.  vsite ([N]) and env ([2 n_steps + 1]): an
     external on-site potential V_i(tau) = env(tau) vsite[i] on both spins,
     env sampled at t_n and t_n + dt/2 of every step (see oracle_evolve_pot).
+    umat ([N, N], symmetric): a general density-density interaction u_ij between
+    opposite spins in place of the on-site U (see oracle_evolve_gen; no inv).
     """
     lib = _load()
     if vsite is not None:
@@ -273,7 +279,16 @@ def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
     nbr = np.ascontiguousarray(lat.nbr.reshape(-1))
     deg = np.ascontiguousarray(lat.deg)
     dptr = ctypes.POINTER(ctypes.c_double)
-    if vsite is None:
+    if umat is not None:
+        um = np.ascontiguousarray(umat, dtype=np.float64)
+        if um.shape != (lat.N, lat.N) or want_inv:
+            raise ValueError("umat must be N x N (and records no invariants)")
+        fn = lib.oracle_evolve_gen_f64 if precision == "f64" else lib.oracle_evolve_gen_f32
+        rc = fn(lat.N, _ptr(nbr, ctypes.c_int32), _ptr(deg, ctypes.c_uint8), lat.t, float(U),
+                um.ctypes.data_as(dptr), vs.ctypes.data_as(dptr) if vsite is not None else None,
+                ev.ctypes.data_as(dptr) if vsite is not None else None, float(dt), int(n_steps),
+                int(record_every), M, y.ctypes.data_as(dptr), X.ctypes.data_as(dptr), None)
+    elif vsite is None:
         fn = lib.oracle_evolve_f64 if precision == "f64" else lib.oracle_evolve_f32
         rc = fn(lat.N, _ptr(nbr, ctypes.c_int32), _ptr(deg, ctypes.c_uint8), lat.t, float(U),
                 float(dt), int(n_steps), int(record_every), M, y.ctypes.data_as(dptr),

@@ -21,16 +21,36 @@
  * explicit term + (V_i - V_j) rho_ij inside the bracket (Sec. III notes that
  * time dependence of such a potential appears as explicit terms of Eq. (5));
  * here V_i = A v_i with `vsite` = v (NULL: no potential) and A the envelope
- * at the stage time.  Evaluation order: each neighbour sum starts from the
- * first (smallest) neighbour and adds the others in ascending order;
- * g = t*(col - row); a = U*(d_i - d_j), then (potential) a = a + A*(v_i - v_j);
- * a is applied with one fma per component; f = i*g.
+ * at the stage time.  A general density-density interaction u_ij (`umat`,
+ * [N][N] symmetric, NULL: on-site U) gives Eq. (5)'s own form: the factor of
+ * rho_ij is D_i - D_j with D_i = sum_k u_ki (rho_kk,sbar + 1/2) (which is
+ * U (d_i - d_j) for u = U delta up to rounding).  Evaluation order: each
+ * neighbour sum starts from the first (smallest) neighbour and adds the
+ * others in ascending order; g = t*(col - row); a = U*(d_i - d_j), or with
+ * umat a = D_i - D_j where D_i = fma(u_ki, d_k + 1/2, D_i) over ascending k
+ * from 0; then (potential) a = a + A*(v_i - v_j); a is applied with one fma
+ * per component; f = i*g.
  */
-void ORC_NAME(oracle_rhs_pot)(int N, const int32_t* nbr, const uint8_t* deg,
-                              ORC_REAL t, ORC_REAL U, const ORC_REAL* vsite, ORC_REAL A,
+void ORC_NAME(oracle_rhs_gen)(int N, const int32_t* nbr, const uint8_t* deg,
+                              ORC_REAL t, ORC_REAL U, const ORC_REAL* umat,
+                              const ORC_REAL* vsite, ORC_REAL A,
                               const ORC_REAL* rho, ORC_REAL* f)
 {
     const size_t NN2 = (size_t)N * N * 2;
+    ORC_REAL* Dall = NULL;  /* [2][N]: D of each spin block (from the other's diagonal) */
+    if (umat) {
+        Dall = (ORC_REAL*)malloc(sizeof(ORC_REAL) * 2 * (size_t)N);
+        if (!Dall) return;
+        for (int s = 0; s < 2; ++s) {
+            const ORC_REAL* Rbar = rho + (1 - s) * NN2;
+            for (int i = 0; i < N; ++i) {
+                ORC_REAL D = 0;
+                for (int k = 0; k < N; ++k)
+                    D = ORC_FMA(umat[k * N + i], Rbar[2 * (k * N + k)] + (ORC_REAL)0.5, D);
+                Dall[s * N + i] = D;
+            }
+        }
+    }
     for (int s = 0; s < 2; ++s) {
         const ORC_REAL* R = rho + s * NN2;
         const ORC_REAL* Rbar = rho + (1 - s) * NN2;
@@ -60,7 +80,8 @@ void ORC_NAME(oracle_rhs_pot)(int N, const int32_t* nbr, const uint8_t* deg,
                 }
                 ORC_REAL g_re = t * (col_re - row_re);
                 ORC_REAL g_im = t * (col_im - row_im);
-                ORC_REAL a = U * (Rbar[2 * (i * N + i)] - Rbar[2 * (j * N + j)]);
+                ORC_REAL a = umat ? Dall[s * N + i] - Dall[s * N + j]
+                                  : U * (Rbar[2 * (i * N + i)] - Rbar[2 * (j * N + j)]);
                 if (vsite) a = a + A * (vsite[i] - vsite[j]);
                 g_re = ORC_FMA(a, R[2 * (i * N + j)], g_re);
                 g_im = ORC_FMA(a, R[2 * (i * N + j) + 1], g_im);
@@ -68,6 +89,14 @@ void ORC_NAME(oracle_rhs_pot)(int N, const int32_t* nbr, const uint8_t* deg,
                 F[2 * (i * N + j) + 1] = g_re;
             }
     }
+    free(Dall);
+}
+
+void ORC_NAME(oracle_rhs_pot)(int N, const int32_t* nbr, const uint8_t* deg,
+                              ORC_REAL t, ORC_REAL U, const ORC_REAL* vsite, ORC_REAL A,
+                              const ORC_REAL* rho, ORC_REAL* f)
+{
+    ORC_NAME(oracle_rhs_gen)(N, nbr, deg, t, U, NULL, vsite, A, rho, f);
 }
 
 void ORC_NAME(oracle_rhs)(int N, const int32_t* nbr, const uint8_t* deg,
@@ -128,12 +157,15 @@ static void ORC_NAME(invariants)(int N, const int32_t* nbr, const uint8_t* deg,
  * vsite (NULL or [N]) and env ([2 n_steps + 1]): the on-site potential
  * V_i(tau) = A(tau) v_i; step n (from t_n = n h) takes A = env[2n] in stage 1,
  * env[2n+1] (t_n + h/2) in stages 2 and 3, env[2n+2] (t_n + h) in stage 4;
- * v and A rounded once to the working precision.
+ * v and A rounded once to the working precision.  umat (NULL or [N][N]): the
+ * general interaction u_ij (U unused; rounded once); inv is then not
+ * computed (its H_W holds the on-site form).
  */
-int ORC_NAME(oracle_evolve_pot)(int N, const int32_t* nbr, const uint8_t* deg,
-                                double t, double U, const double* vsite, const double* env,
-                                double dt, int64_t n_steps, int record_every, int64_t M,
-                                double* rho_io, double* X, double* inv)
+int ORC_NAME(oracle_evolve_gen)(int N, const int32_t* nbr, const uint8_t* deg,
+                                double t, double U, const double* umat, const double* vsite,
+                                const double* env, double dt, int64_t n_steps,
+                                int record_every, int64_t M, double* rho_io, double* X,
+                                double* inv)
 {
     if (N <= 0 || M < 0 || n_steps < 0 || record_every <= 0) return -1;
     const size_t E = (size_t)2 * N * N * 2; /* reals per trajectory */
@@ -148,6 +180,13 @@ int ORC_NAME(oracle_evolve_pot)(int N, const int32_t* nbr, const uint8_t* deg,
         vw = (ORC_REAL*)malloc(sizeof(ORC_REAL) * (size_t)N);
         if (!vw) return -2;
         for (int i = 0; i < N; ++i) vw[i] = (ORC_REAL)vsite[i];
+    }
+    ORC_REAL* uw = NULL;
+    if (umat) {
+        if (inv) { free(vw); return -1; }
+        uw = (ORC_REAL*)malloc(sizeof(ORC_REAL) * (size_t)N * N);
+        if (!uw) { free(vw); return -2; }
+        for (size_t q = 0; q < (size_t)N * N; ++q) uw[q] = (ORC_REAL)umat[q];
     }
     int failed = 0;
     #pragma omp parallel for schedule(dynamic, 1)
@@ -176,28 +215,28 @@ int ORC_NAME(oracle_evolve_pot)(int N, const int32_t* nbr, const uint8_t* deg,
                 }
                 if (step == n_steps) break;
                 /* stage 1 */
-                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
                                          vw ? (ORC_REAL)env[2 * step + 0] : (ORC_REAL)0, y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = k[e];
                     Y[e] = ORC_FMA(c_half, k[e], y[e]);
                 }
                 /* stage 2 */
-                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
                                          vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = ORC_FMA(two, k[e], acc[e]);
                     Y[e] = ORC_FMA(c_half, k[e], y[e]);
                 }
                 /* stage 3 */
-                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
                                          vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = ORC_FMA(two, k[e], acc[e]);
                     Y[e] = ORC_FMA(c_full, k[e], y[e]);
                 }
                 /* stage 4 */
-                ORC_NAME(oracle_rhs_pot)(N, nbr, deg, tw, Uw, vw,
+                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
                                          vw ? (ORC_REAL)env[2 * step + 2] : (ORC_REAL)0, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = acc[e] + k[e];
@@ -210,7 +249,17 @@ int ORC_NAME(oracle_evolve_pot)(int N, const int32_t* nbr, const uint8_t* deg,
         free(y); free(Y); free(k); free(acc);
     }
     free(vw);
+    free(uw);
     return failed ? -2 : 0;
+}
+
+int ORC_NAME(oracle_evolve_pot)(int N, const int32_t* nbr, const uint8_t* deg,
+                                double t, double U, const double* vsite, const double* env,
+                                double dt, int64_t n_steps, int record_every, int64_t M,
+                                double* rho_io, double* X, double* inv)
+{
+    return ORC_NAME(oracle_evolve_gen)(N, nbr, deg, t, U, NULL, vsite, env, dt, n_steps,
+                                       record_every, M, rho_io, X, inv);
 }
 
 int ORC_NAME(oracle_evolve)(int N, const int32_t* nbr, const uint8_t* deg,
