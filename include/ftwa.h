@@ -162,6 +162,15 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        resident path or configuration without the potential variant gives
  *        FTWA_ENOTSUP); ftwa_adjoint refuses it.
  *        v_env must hold 2 n_steps + 1 values (not checked: device memory).
+ *   u_mat [N][N] FP64 or NULL  a general density-density interaction u_ij
+ *        between opposite spins (Eq. (1); symmetric) in place of the on-site
+ *        U (ignored then): Eq. (5)'s own form multiplies rho_ij,s by
+ *        D_i - D_j, D_i = sum_k u_ki (rho_kk,sbar + 1/2), accumulated as
+ *        D = fma(u_ki, d_k + 1/2, D) over ascending k in the working precision
+ *        (u rounded once).  Integrated by the stream kernels (a per-stage
+ *        kernel forms D for every site and trajectory); the resident path, a
+ *        forced configuration, invariant monitors (inv: their energy is the
+ *        on-site form) and ftwa_adjoint refuse it (FTWA_ENOTSUP / FTWA_EINVAL).
  * Trajectory m of the instance has global index traj_offset + m; it keys the
  * random numbers, so any trajectory range reproduces the same trajectories.
  * `instance` enters the random-number counter (distinct streams per instance
@@ -181,6 +190,7 @@ typedef struct {
     const double* n_shift;
     const double* v_site;
     const double* v_env;
+    const double* u_mat;
 } ftwa_instance;
 
 /*

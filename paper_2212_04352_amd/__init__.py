@@ -75,6 +75,7 @@ class Problem:
     n_shift: object = None   # optional [2, N] FP64 device tensor (see ftwa_instance)
     v_site: object = None    # optional [N] FP64 device tensor: external potential profile
     v_env: object = None     # with v_site: [2 n_steps + 1] FP64 envelope at half steps
+    u_mat: object = None     # optional [N, N] FP64 device tensor: general interaction u_ij
 
     @classmethod
     def allocate(cls, lat: Lattice, U: float, n_traj: int, n0, dtype: str = "f64",
@@ -92,7 +93,8 @@ class Problem:
         return {"lat": self.lat.handle, "U": self.U, "n_traj": self.n_traj,
                 "traj_offset": self.traj_offset, "instance": self.instance, "n0": self.n0,
                 "rho": self.rho, "S1": self.S1, "S2": self.S2, "inv": self.inv,
-                "n_shift": self.n_shift, "v_site": self.v_site, "v_env": self.v_env}
+                "n_shift": self.n_shift, "v_site": self.v_site, "v_env": self.v_env,
+                "u_mat": self.u_mat}
 
     def ensure_moments(self, n_rec: int):
         import torch

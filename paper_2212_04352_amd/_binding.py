@@ -50,6 +50,7 @@ class Instance(ctypes.Structure):
         ("n_shift", ctypes.c_void_p),
         ("v_site", ctypes.c_void_p),
         ("v_env", ctypes.c_void_p),
+        ("u_mat", ctypes.c_void_p),
     ]
 
 
@@ -182,7 +183,8 @@ def _instances(insts):
         arr[k] = Instance(d["lat"], float(d["U"]), int(d["n_traj"]), int(d.get("traj_offset", 0)),
                           int(d.get("instance", 0)), _ptr(d["n0"]), _ptr(d["rho"]),
                           _ptr(d.get("S1")), _ptr(d.get("S2")), _ptr(d.get("inv")),
-                          _ptr(d.get("n_shift")), _ptr(d.get("v_site")), _ptr(d.get("v_env")))
+                          _ptr(d.get("n_shift")), _ptr(d.get("v_site")), _ptr(d.get("v_env")),
+                          _ptr(d.get("u_mat")))
     return arr
 
 

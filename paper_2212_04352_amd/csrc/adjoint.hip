@@ -395,6 +395,8 @@ ftwa_status plan_adjoint(const ftwa_instance* inst, int64_t n_steps, int record_
     if (traj_chunk < 0) return fail(FTWA_EINVAL, "traj_chunk < 0");
     if (inst->v_site)
         return fail(FTWA_ENOTSUP, "ftwa_adjoint: no gradients through an external potential");
+    if (inst->u_mat)
+        return fail(FTWA_ENOTSUP, "ftwa_adjoint: no gradients with a general interaction");
     AdjointLayout a;
     const int N = inst->lat->N;
     const int64_t P = packed_count(N);

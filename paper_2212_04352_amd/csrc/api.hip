@@ -71,6 +71,8 @@ ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_mom
         if (need_moments && (!in.S1 || !in.S2)) return fail(FTWA_EINVAL, tag + ": NULL S1 or S2");
         if (in.instance >= (1u << 31)) return fail(FTWA_EINVAL, tag + ": instance id too large");
         if (in.v_site && !in.v_env) return fail(FTWA_EINVAL, tag + ": v_site without v_env");
+        if (in.u_mat && in.inv)
+            return fail(FTWA_EINVAL, tag + ": invariant monitors hold the on-site energy, not u_mat");
     }
     return FTWA_OK;
 }

@@ -71,7 +71,7 @@ struct Plan {
     std::vector<GroupPlan> groups;
     std::vector<LaunchDesc> launches;  // pass-major
     // stream area
-    size_t s_acc = 0, s_ya = 0, s_yb = 0, s_x = 0, s_mom = 0, s_inv = 0, s_total = 0;
+    size_t s_acc = 0, s_ya = 0, s_yb = 0, s_x = 0, s_mom = 0, s_inv = 0, s_D = 0, s_total = 0;
     // resident area
     size_t r_table = 0, r_mom = 0, r_total = 0;
     int64_t n_table = 0;
@@ -127,8 +127,11 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         // an external potential: the stream kernels, or a resident configuration
         // with the potential variant (FP32 spin split)
         const bool pot = inst[k].v_site != nullptr;
-        bool can_res = !tuned_stream && resident_plan(N, dtype, tab, &ip.res, cfg,
-                                                      inst[k].inv == nullptr);
+        // a general interaction: the stream kernels only
+        if (inst[k].u_mat && (want == FTWA_PATH_RESIDENT || force >= 0))
+            return fail(FTWA_ENOTSUP, "a general interaction u_ij runs on the stream path only");
+        bool can_res = !tuned_stream && !inst[k].u_mat &&
+                       resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
         if (pot && can_res) {
             // the configuration chosen without the potential, if it has the
             // potential variant (else the stream path)
@@ -159,7 +162,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     }
 
     // ---- stream instances: chunks of trajectories, one after another
-    size_t s_state = 0, s_x = 0, s_mom = 0, s_inv = 0;
+    size_t s_state = 0, s_x = 0, s_mom = 0, s_inv = 0, s_D = 0;
     for (int k = 0; k < n_inst; ++k) {
         InstPlan& ip = p.inst[k];
         if (ip.path != FTWA_PATH_STREAM) continue;
@@ -175,6 +178,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         s_x = std::max(s_x, (size_t)p.n_rec * D * chunk * sizeof(double));
         s_mom = std::max(s_mom, moments_workspace_bytes(D, chunk, p.n_rec));
         if (inst[k].inv) s_inv = std::max(s_inv, (size_t)p.n_rec * 4 * chunk * sizeof(double));
+        if (inst[k].u_mat) s_D = std::max(s_D, (size_t)2 * N * chunk * sizeof(double));
     }
     size_t off = 0;
     p.s_acc = off; off = align_up(off + s_state);
@@ -183,6 +187,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     p.s_x = off;   off = align_up(off + s_x);
     p.s_mom = off; off = align_up(off + s_mom);
     p.s_inv = off; off = align_up(off + s_inv);
+    p.s_D = off;   off = align_up(off + s_D);
     p.s_total = off;
 
     // ---- resident instances: passes over trajectory windows.  Their area
@@ -377,6 +382,8 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             c.dt = p.dt;
             c.v_site = in.v_site;
             c.v_env = in.v_env;
+            c.u_mat = in.u_mat;
+            c.D = in.u_mat ? ws + p.s_D : nullptr;
             if ((st = record_diag(c, tab, p.dtype, X, stream)) != FTWA_OK) return st;
             if (parts && (st = record_inv(c, tab, p.dtype, parts, stream)) != FTWA_OK) return st;
             int64_t open_steps = 0;
@@ -694,6 +701,7 @@ ftwa_instance probe_instance(const ftwa_instance& in, int64_t Mp, char* ws, cons
     q.inv = nullptr;
     q.v_site = nullptr;  // the probes time the kernels without the potential term
     q.v_env = nullptr;
+    q.u_mat = nullptr;   // and with the on-site interaction
     return q;
 }
 

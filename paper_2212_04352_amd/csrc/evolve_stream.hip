@@ -36,6 +36,7 @@ template <typename T> struct StageArgs {
     T t, U, c;             // c: this stage's coefficient (h/2, h/2, h, h/6)
     const double* vsite;   // NULL, or [N]: profile of the external on-site potential
     const double* env_at;  // its envelope at this stage's time
+    const T* D;            // NULL (on-site U), or [2][N][Mc]: D_i of a general interaction
     int64_t n_elem_chunks; // ceil(2P / kElemsPerWave)
     int64_t n_work;        // n_traj_blocks * n_elem_chunks waves
     int64_t blocks_per_xcd;
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
         cplx_t<T> ac, yv;
         if (STAGE > 1) ac = A.acc[e_ws];
         if (STAGE > 1) yv = A.y[e_y];
-        T a = A.U * (d_i - d_j);
+        T a = A.D ? A.D[((int64_t)s * N + i) * A.Mc + m] - A.D[((int64_t)s * N + j) * A.Mc + m]
+                  : A.U * (d_i - d_j);
         // external potential: a + A(tau) (v_i - v_j), each factor rounded once
         // to T (i, j and the envelope are wave-uniform: scalar loads)
         if (A.vsite) a = a + (T)*A.env_at * ((T)A.vsite[i] - (T)A.vsite[j]);
@@ -154,6 +156,30 @@ __global__ __launch_bounds__(256) void record_diag_kernel(int N, int64_t P, int6
     X[(int64_t)a * Mc + m] = (double)y[((int64_t)s * P + p) * ldy + m].x;
 }
 
+// D[s][i][m] = sum_k u_ki (d_k + 1/2) for spin block s from the other block's
+// diagonal d of the stage input (the general interaction of Eq. (5)):
+// fma over ascending k from 0, u rounded once to T.  One thread per
+// trajectory; blocks over (trajectory block, site, spin), so u_ki is
+// wave-uniform (scalar loads) and the diagonal loads are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void interaction_kernel(int N, int64_t P, int64_t Mc,
+                                                          const cplx_t<T>* __restrict__ yin,
+                                                          int64_t ldin,
+                                                          const double* __restrict__ u,
+                                                          T* __restrict__ D) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int s = blockIdx.z;
+    const int64_t mm = m < Mc ? m : Mc - 1;  // in-bounds loads for the tail, no store
+    const cplx_t<T>* Yo = yin + (int64_t)(1 - s) * P * ldin;
+    T acc = 0;
+    for (int k = 0; k < N; ++k) {
+        const T dk = Yo[((int64_t)k * N - (int64_t)k * (k - 1) / 2) * ldin + mm].x;
+        acc = fma_rn<T>((T)u[(int64_t)k * N + i], dk + (T)0.5, acc);
+    }
+    if (m < Mc) D[((int64_t)s * N + i) * Mc + m] = acc;
+}
+
 template <typename T>
 ftwa_status step_impl(const StreamChunk& c, const DeviceTables& tab, hipStream_t stream) {
     StageArgs<T> A;
@@ -180,14 +206,26 @@ ftwa_status step_impl(const StreamChunk& c, const DeviceTables& tab, hipStream_t
     // stage times t_n, t_n + h/2 (twice), t_n + h: envelope samples 2n, 2n+1, 2n+2
     A.vsite = c.v_site;
     const double* env = c.v_site ? c.v_env + 2 * c.step : nullptr;
+    // general interaction: D of each stage input before the stage
+    A.D = c.u_mat ? static_cast<T*>(c.D) : nullptr;
+    const dim3 igrid((unsigned)((c.Mc + 255) / 256), (unsigned)c.N, 2u), iblock(256);
+    auto interaction = [&](const cplx_t<T>* yin, int64_t ldin) {
+        if (c.u_mat)
+            hipLaunchKernelGGL((interaction_kernel<T>), igrid, iblock, 0, stream, c.N, c.P, c.Mc,
+                               yin, ldin, c.u_mat, static_cast<T*>(c.D));
+    };
 
     A.yin = A.y; A.ldin = c.ldy; A.yout = ya; A.c = c_half; A.env_at = env;
+    interaction(A.yin, A.ldin);
     hipLaunchKernelGGL((rk4_stage_stream<T, 1>), grid, block, 0, stream, A, nb4);
     A.yin = ya; A.ldin = c.Mc; A.yout = yb; A.c = c_half; A.env_at = env ? env + 1 : nullptr;
+    interaction(A.yin, A.ldin);
     hipLaunchKernelGGL((rk4_stage_stream<T, 2>), grid, block, 0, stream, A, nb4);
     A.yin = yb; A.ldin = c.Mc; A.yout = ya; A.c = c_full; A.env_at = env ? env + 1 : nullptr;
+    interaction(A.yin, A.ldin);
     hipLaunchKernelGGL((rk4_stage_stream<T, 3>), grid, block, 0, stream, A, nb4);
     A.yin = ya; A.ldin = c.Mc; A.yout = nullptr; A.c = c_sixth; A.env_at = env ? env + 2 : nullptr;
+    interaction(A.yin, A.ldin);
     hipLaunchKernelGGL((rk4_stage_stream<T, 4>), grid, block, 0, stream, A, nb4);
     FTWA_LAUNCH_CHECK("rk4_stage_stream");
     return FTWA_OK;

@@ -189,6 +189,10 @@ struct StreamChunk {
     const double* v_site = nullptr;
     const double* v_env = nullptr;
     int64_t step = 0;
+    // general interaction (NULL: on-site U): u_mat [N][N]; D the workspace
+    // [2][N][Mc] (working precision) of D_i = sum_k u_ki (d_k + 1/2) per stage
+    const double* u_mat = nullptr;
+    void* D = nullptr;
 };
 ftwa_status stream_step(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
                         hipStream_t stream);

@@ -1,0 +1,107 @@
+"""A general density-density interaction u_ij between opposite spins (Eq. (1),
+Eq. (5)'s own form) through the C ABI: the stream kernels (a per-stage kernel
+forming D_i = sum_k u_ki (d_k + 1/2), fma over ascending k) against the oracle
+bitwise in both precisions, together with an external potential, in a batch
+with an on-site instance, and the paths that refuse it."""
+import numpy as np
+import pytest
+
+from tests._util import pack, unpack
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ft():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_04352_amd as ft
+    ft.load()
+    return ft
+
+
+def _host(x):
+    import torch
+    torch.cuda.synchronize()
+    return x.detach().cpu().numpy()
+
+
+def _long_range(olat, U, seed, decay=1.5):
+    """u_ij = U on site, a screened tail exp(-|i - j| / decay) / 2 between
+    sites (index distance as a stand-in for distance), symmetric."""
+    N = olat.N
+    idx = np.arange(N)
+    u = 0.5 * np.exp(-np.abs(idx[:, None] - idx[None, :]) / decay)
+    np.fill_diagonal(u, U)
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-0.05, 0.05, (N, N))
+    return u + 0.5 * (x + x.T)
+
+
+def _setup(ft, orc, kind, a, b, M, dtype, seed):
+    import torch
+    olat = orc.Lattice(kind, a, b)
+    lat = ft.Lattice(kind, a, b)
+    n0 = orc.fock_start(olat, "random", seed)
+    rho0 = orc.sample(olat, n0, seed, M)
+    prob = ft.Problem.allocate(lat, 0.0, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    u = _long_range(olat, 3.3, seed)
+    prob.u_mat = torch.from_numpy(u).cuda()
+    return olat, lat, rho0, prob, u, cdt
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kind,a,b,M,steps", [("torus", 2, 3, 70, 50), ("hex", 2, 0, 33, 30),
+                                              ("armchair", 10, 20, 5, 8)])
+def test_interaction_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps):
+    dt, re = 0.01, 5
+    olat, lat, rho0, prob, u, cdt = _setup(ft, orc, kind, a, b, M, dtype, 3)
+    ft.evolve(prob, dt, steps, re)
+    y_ref, X_ref, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, precision=dtype, umat=u)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
+def test_interaction_with_a_potential_and_an_on_site_neighbour(ft, orc):
+    """One call: a general-u instance that also carries a time-dependent
+    potential, and an on-site instance, in trajectory chunks of 16."""
+    import torch
+    dt, steps, re = 0.01, 20, 5
+    o1, l1, r1, p1, u1, _ = _setup(ft, orc, "torus", 3, 9, 37, "f64", 8)
+    tau = np.arange(2 * steps + 1) * dt / 2
+    env = 0.9 * np.sin(7.0 * tau)
+    v = np.array([(-1.0) ** s for s in o1.sub])
+    p1.v_site = torch.from_numpy(v).cuda()
+    p1.v_env = torch.from_numpy(env).cuda()
+    o2 = orc.Lattice("hex", 2, 0)
+    l2 = ft.Lattice("hex", 2, 0)
+    n2 = orc.fock_start(o2, "random", 9)
+    r2 = orc.sample(o2, n2, 9, 21)
+    p2 = ft.Problem.allocate(l2, 1.7, 21, n2, "f64", instance=1)
+    p2.rho.copy_(torch.from_numpy(pack(r2)))
+    ft.evolve([p1, p2], dt, steps, re, traj_chunk=16)
+    y1, _, _ = orc.evolve(o1, 0.0, r1, dt, steps, re, umat=u1, vsite=v, env=env)
+    y2, _, _ = orc.evolve(o2, 1.7, r2, dt, steps, re)
+    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1)
+    assert np.array_equal(unpack(_host(p2.rho), l2.N), y2)
+
+
+def test_paths_that_refuse_a_general_interaction(ft, orc):
+    import torch
+    olat, lat, rho0, prob, u, _ = _setup(ft, orc, "armchair", 10, 20, 4, "f32", 5)
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 2, 1, path="resident")
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 2, 1, config=9)
+    w = torch.zeros((2, 2 * lat.N), dtype=torch.float64, device="cuda")
+    with pytest.raises(ft.FtwaError):
+        ft.adjoint(prob, 0.01, 2, 2, 2, w)
+    prob.track_invariants = True
+    with pytest.raises(ft.FtwaError):
+        ft.evolve(prob, 0.01, 2, 1)
