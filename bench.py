@@ -53,12 +53,14 @@ def parse():
     ap.add_argument("--cpu-traj", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--workload", default="flake198",
-                    choices=["flake198", "batch", "adjoint", "sizes", "thermal", "pulse"],
+                    choices=["flake198", "batch", "adjoint", "sizes", "thermal", "pulse",
+                             "longrange"],
                     help="flake198: the headline metric (default); batch: the 64-instance mixed "
                          "batch as one graph launch; adjoint: the 54-site gradient workload; "
                          "sizes: resident throughput per lattice size; thermal: sampling of "
                          "thermal (fractional-occupation) starts on the 198-site flake; pulse: "
-                         "a time-dependent staggered potential on the 198-site flake")
+                         "a time-dependent staggered potential on the 198-site flake; "
+                         "longrange: a general density-density interaction on the same")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-traj", type=int, default=2048)
     ap.add_argument("--sequential", action="store_true",
@@ -392,6 +394,58 @@ def run_pulse(args):
                    "profile": "+1 / -1 by sublattice"}}))
 
 
+def run_longrange(args):
+    """A general density-density interaction on the 198-site flake: u_ii = 3.3,
+    u_ij = exp(-d_ij) / 2 between sites (d_ij the graph distance, a screened
+    tail), FP32 and FP64 on the stream kernels, 4096 trajectories x 400 steps,
+    next to the on-site run of the same kernels."""
+    import numpy as np
+    import torch
+    from collections import deque
+    import paper_2212_04352_amd as ft
+    lat = ft.Lattice("armchair", 10, 20)
+    N = lat.N
+    dist = np.full((N, N), np.inf)
+    for r in range(N):  # breadth-first graph distances
+        dist[r, r] = 0
+        q = deque([r])
+        while q:
+            x = q.popleft()
+            for y in lat.nbr[x][:lat.deg[x]]:
+                if dist[r, y] == np.inf:
+                    dist[r, y] = dist[r, x] + 1
+                    q.append(y)
+    u = 0.5 * np.exp(-dist)
+    np.fill_diagonal(u, 3.3)
+    M = args.traj or 4096
+    steps = args.horizon_steps or 400
+    rows = []
+    for dtype in ("f32", "f64"):
+        for general in (False, True):
+            p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
+            if general:
+                p.u_mat = torch.from_numpy(u).cuda()
+            ft.sample(p, 5)
+            ws = ft.evolve(p, 0.005, 2, 1, path="stream")
+            ft.sample(p, 5)
+            timing = ft.new_timing()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ft.evolve(p, 0.005, steps, 10, path="stream", workspace=ws, timing=timing)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rows.append({"dtype": dtype, "interaction": "general" if general else "on-site",
+                         "value": M * steps / el})
+            log(f"longrange: {dtype} general={general}: {M * steps / el:.3e} traj-steps/s")
+            del p, ws
+    print(json.dumps({
+        "metric": "trajectory*RK4-steps/s with a general density-density interaction, 198-site flake",
+        "unit": "trajectory*RK4-steps/s", "rows": rows,
+        "config": {"workload": "flake198_longrange", "trajectories": M, "rk4_steps": steps,
+                   "dt": 0.005, "path": "stream",
+                   "interaction": "u_ii = 3.3, u_ij = exp(-graph distance) / 2"}}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -412,6 +466,8 @@ def main():
         return run_sizes(args)
     if args.workload == "pulse":
         return run_pulse(args)
+    if args.workload == "longrange":
+        return run_longrange(args)
 
     torch.cuda.set_device(0)
     if args.copy_calibration_mib > 0:
