@@ -82,6 +82,10 @@ def _load():
         evg.argtypes = [ctypes.c_int, P(i32), P(ctypes.c_uint8), dbl, dbl, P(dbl), P(dbl),
                         P(dbl), dbl, i64, ctypes.c_int, i64, P(dbl), P(dbl), P(dbl)]
         evg.restype = ctypes.c_int
+        evh = getattr(lib, f"oracle_evolve_hop_{suffix}")
+        evh.argtypes = [ctypes.c_int, P(i32), P(ctypes.c_uint8), dbl, dbl, P(dbl), P(dbl),
+                        P(dbl), P(dbl), dbl, i64, ctypes.c_int, i64, P(dbl), P(dbl), P(dbl)]
+        evh.restype = ctypes.c_int
     lib.oracle_moments.argtypes = [ctypes.c_int, i64, ctypes.c_int, P(dbl), P(dbl), P(dbl)]
     lib.oracle_moments.restype = None
     lib.oracle_observables.argtypes = [ctypes.c_int, i64, ctypes.c_int, P(dbl), P(dbl), P(dbl),
@@ -254,7 +258,7 @@ def n_records(n_steps: int, record_every: int) -> int:
 
 def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
            record_every: int = 10, precision: str = "f64", want_inv: bool = False,
-           vsite=None, env=None, umat=None):
+           vsite=None, env=None, umat=None, hop=None):
     """RK4 integration of every trajectory.  Returns (rho_final, X, inv).
 
     rho: [M, 2, N, N] complex128 (not modified).  X: [n_rec, M, 2N] diagonal
@@ -264,6 +268,9 @@ def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
     env sampled at t_n and t_n + dt/2 of every step (see oracle_evolve_pot).
     umat ([N, N], symmetric): a general density-density interaction u_ij between
     opposite spins in place of the on-site U (see oracle_evolve_gen; no inv).
+    hop ([2 n_steps + 1, N, 3] complex): complex hopping j_ik(tau) = t hop[h, i, n]
+    for k = lat.nbr[i, n] at the half steps of env (Peierls phases; Hermitian:
+    the entry of k for i is the conjugate; slots beyond deg are ignored; no inv).
     """
     lib = _load()
     if vsite is not None:
@@ -279,7 +286,21 @@ def evolve(lat: Lattice, U: float, rho: np.ndarray, dt: float, n_steps: int,
     nbr = np.ascontiguousarray(lat.nbr.reshape(-1))
     deg = np.ascontiguousarray(lat.deg)
     dptr = ctypes.POINTER(ctypes.c_double)
-    if umat is not None:
+    if hop is not None:
+        hw = np.ascontiguousarray(hop, dtype=np.complex128)
+        if hw.shape != (2 * n_steps + 1, lat.N, 3) or want_inv:
+            raise ValueError("hop must be [2 n_steps + 1, N, 3] (and records no invariants)")
+        um = None if umat is None else np.ascontiguousarray(umat, dtype=np.float64)
+        if um is not None and um.shape != (lat.N, lat.N):
+            raise ValueError("umat must be N x N")
+        fn = lib.oracle_evolve_hop_f64 if precision == "f64" else lib.oracle_evolve_hop_f32
+        rc = fn(lat.N, _ptr(nbr, ctypes.c_int32), _ptr(deg, ctypes.c_uint8), lat.t, float(U),
+                um.ctypes.data_as(dptr) if um is not None else None,
+                vs.ctypes.data_as(dptr) if vsite is not None else None,
+                ev.ctypes.data_as(dptr) if vsite is not None else None,
+                hw.ctypes.data_as(dptr), float(dt), int(n_steps), int(record_every), M,
+                y.ctypes.data_as(dptr), X.ctypes.data_as(dptr), None)
+    elif umat is not None:
         um = np.ascontiguousarray(umat, dtype=np.float64)
         if um.shape != (lat.N, lat.N) or want_inv:
             raise ValueError("umat must be N x N (and records no invariants)")

@@ -9,6 +9,16 @@
 #define ORC_CAT(a, b) ORC_CAT2(a, b)
 #define ORC_NAME(base) ORC_CAT(base, ORC_SUFFIX)
 
+/* x <- w x for a complex hop ratio w = (w_re, w_im): re = fma(w_re, x_re,
+ * -(w_im x_im)), im = fma(w_re, x_im, w_im x_re). */
+static void ORC_NAME(cmul_w)(ORC_REAL w_re, ORC_REAL w_im, ORC_REAL* x_re, ORC_REAL* x_im)
+{
+    const ORC_REAL re = ORC_FMA(w_re, *x_re, -(w_im * *x_im));
+    const ORC_REAL im = ORC_FMA(w_re, *x_im, w_im * *x_re);
+    *x_re = re;
+    *x_im = im;
+}
+
 /*
  * Right-hand side of the fTWA equation of motion, Sec. III, Eq. (5), with
  * j_ij = t on bonds and u_ij = U delta_ij (Sec. II):
@@ -30,10 +40,17 @@
  * umat a = D_i - D_j where D_i = fma(u_ki, d_k + 1/2, D_i) over ascending k
  * from 0; then (potential) a = a + A*(v_i - v_j); a is applied with one fma
  * per component; f = i*g.
+ *
+ * Complex (Peierls) hopping, `hop` non-NULL ([N][3] complex ratios
+ * w_ik = j_ik / t, slot n of site i for its neighbour k = nbr[i][n]): the two
+ * hopping sums of Eq. (5) are taken literally, col = sum_{k in nb(j)} j_jk
+ * rho_ik / t and row = sum_{k in nb(i)} j_ki rho_kj / t, j_ki read from k's
+ * own row (the entry of k for its neighbour i), each product by cmul_w before
+ * it enters the ascending sum.
  */
-void ORC_NAME(oracle_rhs_gen)(int N, const int32_t* nbr, const uint8_t* deg,
+void ORC_NAME(oracle_rhs_hop)(int N, const int32_t* nbr, const uint8_t* deg,
                               ORC_REAL t, ORC_REAL U, const ORC_REAL* umat,
-                              const ORC_REAL* vsite, ORC_REAL A,
+                              const ORC_REAL* vsite, ORC_REAL A, const ORC_REAL* hop,
                               const ORC_REAL* rho, ORC_REAL* f)
 {
     const size_t NN2 = (size_t)N * N * 2;
@@ -60,22 +77,36 @@ void ORC_NAME(oracle_rhs_gen)(int N, const int32_t* nbr, const uint8_t* deg,
                 ORC_REAL col_re = 0, col_im = 0, row_re = 0, row_im = 0;
                 for (int n = 0; n < deg[j]; ++n) {
                     int k = nbr[j * ORC_MAXDEG + n];
+                    ORC_REAL x_re = R[2 * (i * N + k)], x_im = R[2 * (i * N + k) + 1];
+                    if (hop) {
+                        /* j_jk / t = hop[j][n] (k = nbr[j][n]) times rho_ik */
+                        const ORC_REAL* w = hop + 2 * (j * ORC_MAXDEG + n);
+                        ORC_NAME(cmul_w)(w[0], w[1], &x_re, &x_im);
+                    }
                     if (n == 0) {
-                        col_re = R[2 * (i * N + k)];
-                        col_im = R[2 * (i * N + k) + 1];
+                        col_re = x_re;
+                        col_im = x_im;
                     } else {
-                        col_re = col_re + R[2 * (i * N + k)];
-                        col_im = col_im + R[2 * (i * N + k) + 1];
+                        col_re = col_re + x_re;
+                        col_im = col_im + x_im;
                     }
                 }
                 for (int n = 0; n < deg[i]; ++n) {
                     int k = nbr[i * ORC_MAXDEG + n];
+                    ORC_REAL x_re = R[2 * (k * N + j)], x_im = R[2 * (k * N + j) + 1];
+                    if (hop) {
+                        /* j_ki / t: the entry of k's row for its neighbour i */
+                        int nk = 0;
+                        while (nbr[k * ORC_MAXDEG + nk] != i) ++nk;
+                        const ORC_REAL* w = hop + 2 * (k * ORC_MAXDEG + nk);
+                        ORC_NAME(cmul_w)(w[0], w[1], &x_re, &x_im);
+                    }
                     if (n == 0) {
-                        row_re = R[2 * (k * N + j)];
-                        row_im = R[2 * (k * N + j) + 1];
+                        row_re = x_re;
+                        row_im = x_im;
                     } else {
-                        row_re = row_re + R[2 * (k * N + j)];
-                        row_im = row_im + R[2 * (k * N + j) + 1];
+                        row_re = row_re + x_re;
+                        row_im = row_im + x_im;
                     }
                 }
                 ORC_REAL g_re = t * (col_re - row_re);
@@ -90,6 +121,14 @@ void ORC_NAME(oracle_rhs_gen)(int N, const int32_t* nbr, const uint8_t* deg,
             }
     }
     free(Dall);
+}
+
+void ORC_NAME(oracle_rhs_gen)(int N, const int32_t* nbr, const uint8_t* deg,
+                              ORC_REAL t, ORC_REAL U, const ORC_REAL* umat,
+                              const ORC_REAL* vsite, ORC_REAL A,
+                              const ORC_REAL* rho, ORC_REAL* f)
+{
+    ORC_NAME(oracle_rhs_hop)(N, nbr, deg, t, U, umat, vsite, A, NULL, rho, f);
 }
 
 void ORC_NAME(oracle_rhs_pot)(int N, const int32_t* nbr, const uint8_t* deg,
@@ -159,13 +198,15 @@ static void ORC_NAME(invariants)(int N, const int32_t* nbr, const uint8_t* deg,
  * env[2n+1] (t_n + h/2) in stages 2 and 3, env[2n+2] (t_n + h) in stage 4;
  * v and A rounded once to the working precision.  umat (NULL or [N][N]): the
  * general interaction u_ij (U unused; rounded once); inv is then not
- * computed (its H_W holds the on-site form).
+ * computed (its H_W holds the on-site form).  hopw (NULL or
+ * [2 n_steps + 1][N][3] complex): hop ratios w_ik(tau) = j_ik(tau) / t at the
+ * same half steps as env (no inv either); rounded once.
  */
-int ORC_NAME(oracle_evolve_gen)(int N, const int32_t* nbr, const uint8_t* deg,
+int ORC_NAME(oracle_evolve_hop)(int N, const int32_t* nbr, const uint8_t* deg,
                                 double t, double U, const double* umat, const double* vsite,
-                                const double* env, double dt, int64_t n_steps,
-                                int record_every, int64_t M, double* rho_io, double* X,
-                                double* inv)
+                                const double* env, const double* hopw, double dt,
+                                int64_t n_steps, int record_every, int64_t M, double* rho_io,
+                                double* X, double* inv)
 {
     if (N <= 0 || M < 0 || n_steps < 0 || record_every <= 0) return -1;
     const size_t E = (size_t)2 * N * N * 2; /* reals per trajectory */
@@ -187,6 +228,14 @@ int ORC_NAME(oracle_evolve_gen)(int N, const int32_t* nbr, const uint8_t* deg,
         uw = (ORC_REAL*)malloc(sizeof(ORC_REAL) * (size_t)N * N);
         if (!uw) { free(vw); return -2; }
         for (size_t q = 0; q < (size_t)N * N; ++q) uw[q] = (ORC_REAL)umat[q];
+    }
+    ORC_REAL* hw = NULL;  /* hop ratios of every half step, rounded once */
+    const size_t HS = (size_t)N * ORC_MAXDEG * 2;
+    if (hopw) {
+        if (inv) { free(vw); free(uw); return -1; }
+        hw = (ORC_REAL*)malloc(sizeof(ORC_REAL) * HS * (size_t)(2 * n_steps + 1));
+        if (!hw) { free(vw); free(uw); return -2; }
+        for (size_t q = 0; q < HS * (size_t)(2 * n_steps + 1); ++q) hw[q] = (ORC_REAL)hopw[q];
     }
     int failed = 0;
     #pragma omp parallel for schedule(dynamic, 1)
@@ -215,29 +264,33 @@ int ORC_NAME(oracle_evolve_gen)(int N, const int32_t* nbr, const uint8_t* deg,
                 }
                 if (step == n_steps) break;
                 /* stage 1 */
-                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
-                                         vw ? (ORC_REAL)env[2 * step + 0] : (ORC_REAL)0, y, k);
+                ORC_NAME(oracle_rhs_hop)(N, nbr, deg, tw, Uw, uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 0] : (ORC_REAL)0,
+                                         hw ? hw + (size_t)(2 * step + 0) * HS : NULL, y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = k[e];
                     Y[e] = ORC_FMA(c_half, k[e], y[e]);
                 }
                 /* stage 2 */
-                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
-                                         vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0, Y, k);
+                ORC_NAME(oracle_rhs_hop)(N, nbr, deg, tw, Uw, uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0,
+                                         hw ? hw + (size_t)(2 * step + 1) * HS : NULL, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = ORC_FMA(two, k[e], acc[e]);
                     Y[e] = ORC_FMA(c_half, k[e], y[e]);
                 }
                 /* stage 3 */
-                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
-                                         vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0, Y, k);
+                ORC_NAME(oracle_rhs_hop)(N, nbr, deg, tw, Uw, uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 1] : (ORC_REAL)0,
+                                         hw ? hw + (size_t)(2 * step + 1) * HS : NULL, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = ORC_FMA(two, k[e], acc[e]);
                     Y[e] = ORC_FMA(c_full, k[e], y[e]);
                 }
                 /* stage 4 */
-                ORC_NAME(oracle_rhs_gen)(N, nbr, deg, tw, Uw, uw, vw,
-                                         vw ? (ORC_REAL)env[2 * step + 2] : (ORC_REAL)0, Y, k);
+                ORC_NAME(oracle_rhs_hop)(N, nbr, deg, tw, Uw, uw, vw,
+                                         vw ? (ORC_REAL)env[2 * step + 2] : (ORC_REAL)0,
+                                         hw ? hw + (size_t)(2 * step + 2) * HS : NULL, Y, k);
                 for (size_t e = 0; e < E; ++e) {
                     acc[e] = acc[e] + k[e];
                     y[e] = ORC_FMA(c_sixth, acc[e], y[e]);
@@ -250,7 +303,18 @@ int ORC_NAME(oracle_evolve_gen)(int N, const int32_t* nbr, const uint8_t* deg,
     }
     free(vw);
     free(uw);
+    free(hw);
     return failed ? -2 : 0;
+}
+
+int ORC_NAME(oracle_evolve_gen)(int N, const int32_t* nbr, const uint8_t* deg,
+                                double t, double U, const double* umat, const double* vsite,
+                                const double* env, double dt, int64_t n_steps,
+                                int record_every, int64_t M, double* rho_io, double* X,
+                                double* inv)
+{
+    return ORC_NAME(oracle_evolve_hop)(N, nbr, deg, t, U, umat, vsite, env, NULL, dt, n_steps,
+                                       record_every, M, rho_io, X, inv);
 }
 
 int ORC_NAME(oracle_evolve_pot)(int N, const int32_t* nbr, const uint8_t* deg,
