@@ -171,6 +171,22 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        kernel forms D for every site and trajectory); the resident path, a
  *        forced configuration, invariant monitors (inv: their energy is the
  *        on-site form) and ftwa_adjoint refuse it (FTWA_ENOTSUP / FTWA_EINVAL).
+ *   hop_w [2 n_steps + 1][N][3] complex FP64 (interleaved re, im) or NULL
+ *        complex, time-dependent hopping j_ik(tau) = t hop_w[h][i][n] for the
+ *        neighbour k = nbr[i][n] of ftwa_lattice_info (Peierls phases; Sec. III:
+ *        time dependence enters Eq. (5) as explicit terms), sampled at the
+ *        half steps of v_env: step n reads table 2n in its first stage, 2n+1
+ *        in the second and third, 2n+2 in the fourth.  The Hamiltonian is
+ *        Hermitian, so the caller gives both directions of a bond as
+ *        conjugates (not checked) and ftwa_evolve uses
+ *        col = sum_{k in nb(j)} w_jk rho_ik, row = sum_{k in nb(i)} conj(w_ik)
+ *        rho_kj in f_ij = i [t (col - row) + a rho_ij], each product as
+ *        (fma(wr, xr, -(wi xi)), fma(wr, xi, wi xr)) with w rounded once to
+ *        the working precision, slots summed in ascending order; slots
+ *        n >= deg(i) are ignored (any finite or non-finite value).  Integrated by the stream kernels (a forced
+ *        resident path or configuration gives FTWA_ENOTSUP); invariant
+ *        monitors (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.
+ *        Combines with v_site and u_mat.
  * Trajectory m of the instance has global index traj_offset + m; it keys the
  * random numbers, so any trajectory range reproduces the same trajectories.
  * `instance` enters the random-number counter (distinct streams per instance
@@ -191,6 +207,7 @@ typedef struct {
     const double* v_site;
     const double* v_env;
     const double* u_mat;
+    const double* hop_w;
 } ftwa_instance;
 
 /*

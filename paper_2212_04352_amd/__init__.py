@@ -76,6 +76,8 @@ class Problem:
     v_site: object = None    # optional [N] FP64 device tensor: external potential profile
     v_env: object = None     # with v_site: [2 n_steps + 1] FP64 envelope at half steps
     u_mat: object = None     # optional [N, N] FP64 device tensor: general interaction u_ij
+    hop_w: object = None     # optional [2 n_steps + 1, N, 3] complex128 device tensor:
+                             # complex hopping ratios j_ik / t at half steps (Peierls)
 
     @classmethod
     def allocate(cls, lat: Lattice, U: float, n_traj: int, n0, dtype: str = "f64",
@@ -94,7 +96,7 @@ class Problem:
                 "traj_offset": self.traj_offset, "instance": self.instance, "n0": self.n0,
                 "rho": self.rho, "S1": self.S1, "S2": self.S2, "inv": self.inv,
                 "n_shift": self.n_shift, "v_site": self.v_site, "v_env": self.v_env,
-                "u_mat": self.u_mat}
+                "u_mat": self.u_mat, "hop_w": self.hop_w}
 
     def ensure_moments(self, n_rec: int):
         import torch

@@ -51,6 +51,7 @@ class Instance(ctypes.Structure):
         ("v_site", ctypes.c_void_p),
         ("v_env", ctypes.c_void_p),
         ("u_mat", ctypes.c_void_p),
+        ("hop_w", ctypes.c_void_p),
     ]
 
 
@@ -184,7 +185,7 @@ def _instances(insts):
                           int(d.get("instance", 0)), _ptr(d["n0"]), _ptr(d["rho"]),
                           _ptr(d.get("S1")), _ptr(d.get("S2")), _ptr(d.get("inv")),
                           _ptr(d.get("n_shift")), _ptr(d.get("v_site")), _ptr(d.get("v_env")),
-                          _ptr(d.get("u_mat")))
+                          _ptr(d.get("u_mat")), _ptr(d.get("hop_w")))
     return arr
 
 

@@ -397,6 +397,8 @@ ftwa_status plan_adjoint(const ftwa_instance* inst, int64_t n_steps, int record_
         return fail(FTWA_ENOTSUP, "ftwa_adjoint: no gradients through an external potential");
     if (inst->u_mat)
         return fail(FTWA_ENOTSUP, "ftwa_adjoint: no gradients with a general interaction");
+    if (inst->hop_w)
+        return fail(FTWA_ENOTSUP, "ftwa_adjoint: no gradients with complex hopping");
     AdjointLayout a;
     const int N = inst->lat->N;
     const int64_t P = packed_count(N);

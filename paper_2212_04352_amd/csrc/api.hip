@@ -73,6 +73,8 @@ ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_mom
         if (in.v_site && !in.v_env) return fail(FTWA_EINVAL, tag + ": v_site without v_env");
         if (in.u_mat && in.inv)
             return fail(FTWA_EINVAL, tag + ": invariant monitors hold the on-site energy, not u_mat");
+        if (in.hop_w && in.inv)
+            return fail(FTWA_EINVAL, tag + ": invariant monitors hold the real-hopping energy");
     }
     return FTWA_OK;
 }

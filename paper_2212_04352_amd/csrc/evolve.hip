@@ -130,7 +130,10 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         // a general interaction: the stream kernels only
         if (inst[k].u_mat && (want == FTWA_PATH_RESIDENT || force >= 0))
             return fail(FTWA_ENOTSUP, "a general interaction u_ij runs on the stream path only");
-        bool can_res = !tuned_stream && !inst[k].u_mat &&
+        // complex hopping: the stream kernels only
+        if (inst[k].hop_w && (want == FTWA_PATH_RESIDENT || force >= 0))
+            return fail(FTWA_ENOTSUP, "complex hopping runs on the stream path only");
+        bool can_res = !tuned_stream && !inst[k].u_mat && !inst[k].hop_w &&
                        resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
         if (pot && can_res) {
             // the configuration chosen without the potential, if it has the
@@ -384,6 +387,7 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             c.v_env = in.v_env;
             c.u_mat = in.u_mat;
             c.D = in.u_mat ? ws + p.s_D : nullptr;
+            c.hop_w = in.hop_w;
             if ((st = record_diag(c, tab, p.dtype, X, stream)) != FTWA_OK) return st;
             if (parts && (st = record_inv(c, tab, p.dtype, parts, stream)) != FTWA_OK) return st;
             int64_t open_steps = 0;
@@ -702,6 +706,7 @@ ftwa_instance probe_instance(const ftwa_instance& in, int64_t Mp, char* ws, cons
     q.v_site = nullptr;  // the probes time the kernels without the potential term
     q.v_env = nullptr;
     q.u_mat = nullptr;   // and with the on-site interaction
+    q.hop_w = nullptr;   // and real hopping
     return q;
 }
 

@@ -10,7 +10,10 @@
 // trajectories and walks a run of packed elements; (i, j) and all neighbour
 // indices are therefore wave-uniform (scalar registers) and every load is one
 // coalesced 512 B (FP32) or 1 KiB (FP64) row segment.  Elements i > j are read
-// as conjugates of the stored upper triangle.
+// as conjugates of the stored upper triangle.  With complex (Peierls)
+// hopping j_ik = t w_ik the two sums become sum_{k in nb(j)} w_jk rho_ik and
+// sum_{k in nb(i)} conj(w_ik) rho_kj (j_ki = conj(j_ik): the Hamiltonian is
+// Hermitian), so both read only the rows of i and j of the ratio table.
 #include "device_common.h"
 #include "ftwa_internal.h"
 
@@ -37,6 +40,7 @@ template <typename T> struct StageArgs {
     const double* vsite;   // NULL, or [N]: profile of the external on-site potential
     const double* env_at;  // its envelope at this stage's time
     const T* D;            // NULL (on-site U), or [2][N][Mc]: D_i of a general interaction
+    const double2* hop;    // complex hopping: [N][3] ratios w_ik = j_ik / t at this stage's time
     int64_t n_elem_chunks; // ceil(2P / kElemsPerWave)
     int64_t n_work;        // n_traj_blocks * n_elem_chunks waves
     int64_t blocks_per_xcd;
@@ -46,9 +50,54 @@ __device__ __forceinline__ int64_t prow(int N, int i) {
     return (int64_t)i * N - (int64_t)i * (i - 1) / 2;
 }
 
+// x <- w x, w rounded once to T: re = fma(wr, xr, -(wi xi)),
+// im = fma(wr, xi, wi xr); `cj` takes conj(w).
+template <typename T>
+__device__ __forceinline__ void cmul_ratio(double2 w, bool cj, cplx_t<T>& x) {
+    const T wr = (T)w.x;
+    const T wi = cj ? -(T)w.y : (T)w.y;
+    const T re = fma_rn<T>(wr, x.x, -(wi * x.y));
+    const T im = fma_rn<T>(wr, x.y, wi * x.x);
+    x.x = re;
+    x.y = im;
+}
+
+// Neighbour sums with complex hopping: col = sum_n w[j][n] rho_{i, nb(j)_n},
+// row = sum_n conj(w[i][n]) rho_{nb(i)_n, j}, slots (ascending k) summed in
+// order as in neighbour_sums.  Ratios of i and j are wave-uniform.
+template <typename T>
+__device__ __forceinline__ void hop_sums(const cplx_t<T>* X, int64_t ld, int N, int4 nbj,
+                                         int4 nbi, int i, int j, int64_t m,
+                                         const double2* __restrict__ w, cplx_t<T>& col,
+                                         cplx_t<T>& row) {
+    using C = cplx_t<T>;
+    const int kc[3] = {nbj.x, nbj.y, nbj.z};
+    const int kr[3] = {nbi.x, nbi.y, nbi.z};
+    C c[3], r[3];
+    bool tc[3], tr[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        const int k1 = n < nbj.w ? kc[n] : j;
+        const int k2 = n < nbi.w ? kr[n] : i;
+        c[n] = X[packed_at(N, i, k1, tc[n]) * ld + m];
+        r[n] = X[packed_at(N, k2, j, tr[n]) * ld + m];
+    }
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        if (tc[n]) c[n].y = -c[n].y;
+        if (tr[n]) r[n].y = -r[n].y;
+        cmul_ratio<T>(w[j * 3 + n], false, c[n]);
+        cmul_ratio<T>(w[i * 3 + n], true, r[n]);
+        if (n >= nbj.w) c[n].x = c[n].y = 0;
+        if (n >= nbi.w) r[n].x = r[n].y = 0;
+    }
+    col = cadd(cadd(c[0], c[1]), c[2]);
+    row = cadd(cadd(r[0], r[1]), r[2]);
+}
+
 // nb4: the neighbour rows (also in A.nb) as a separate read-only argument,
-// so that the wave-uniform row reads are scalar loads.
-template <typename T, int STAGE>
+// so that the wave-uniform row reads are scalar loads.  HOP: complex hopping.
+template <typename T, int STAGE, bool HOP>
 __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
                                                         const int4* __restrict__ nb4) {
     // XCD-aware numbering: blocks are dealt round-robin to the 8 XCDs, so
@@ -85,7 +134,10 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
         // col = sum_{k in nb(j)} rho_ik, row = sum_{k in nb(i)} rho_kj,
         // ascending k (loads issued together)
         cplx_t<T> col, row;
-        neighbour_sums<T>(Ys, A.ldin, N, nb4[j], nb4[i], i, j, m, col, row);
+        if (HOP)
+            hop_sums<T>(Ys, A.ldin, N, nb4[j], nb4[i], i, j, m, A.hop, col, row);
+        else
+            neighbour_sums<T>(Ys, A.ldin, N, nb4[j], nb4[i], i, j, m, col, row);
         const int64_t ep = p;
         const int64_t e_ws = ((int64_t)s * P + ep) * A.Mc + m;  // workspace index
         const int64_t e_y = ((int64_t)s * P + ep) * A.ldy + m;   // state index
@@ -215,18 +267,28 @@ ftwa_status step_impl(const StreamChunk& c, const DeviceTables& tab, hipStream_t
                                yin, ldin, c.u_mat, static_cast<T*>(c.D));
     };
 
-    A.yin = A.y; A.ldin = c.ldy; A.yout = ya; A.c = c_half; A.env_at = env;
-    interaction(A.yin, A.ldin);
-    hipLaunchKernelGGL((rk4_stage_stream<T, 1>), grid, block, 0, stream, A, nb4);
-    A.yin = ya; A.ldin = c.Mc; A.yout = yb; A.c = c_half; A.env_at = env ? env + 1 : nullptr;
-    interaction(A.yin, A.ldin);
-    hipLaunchKernelGGL((rk4_stage_stream<T, 2>), grid, block, 0, stream, A, nb4);
-    A.yin = yb; A.ldin = c.Mc; A.yout = ya; A.c = c_full; A.env_at = env ? env + 1 : nullptr;
-    interaction(A.yin, A.ldin);
-    hipLaunchKernelGGL((rk4_stage_stream<T, 3>), grid, block, 0, stream, A, nb4);
-    A.yin = ya; A.ldin = c.Mc; A.yout = nullptr; A.c = c_sixth; A.env_at = env ? env + 2 : nullptr;
-    interaction(A.yin, A.ldin);
-    hipLaunchKernelGGL((rk4_stage_stream<T, 4>), grid, block, 0, stream, A, nb4);
+    // complex hopping: the ratio table of the same half step as the envelope
+    const size_t hop_half = (size_t)c.N * 3;
+    const double2* hop = c.hop_w ? reinterpret_cast<const double2*>(c.hop_w) + 2 * c.step * hop_half
+                                 : nullptr;
+    auto stage = [&](auto kernel_plain, auto kernel_hop, int half) {
+        A.env_at = env ? env + half : nullptr;
+        A.hop = hop ? hop + half * hop_half : nullptr;
+        interaction(A.yin, A.ldin);
+        if (hop)
+            hipLaunchKernelGGL(kernel_hop, grid, block, 0, stream, A, nb4);
+        else
+            hipLaunchKernelGGL(kernel_plain, grid, block, 0, stream, A, nb4);
+    };
+
+    A.yin = A.y; A.ldin = c.ldy; A.yout = ya; A.c = c_half;
+    stage(rk4_stage_stream<T, 1, false>, rk4_stage_stream<T, 1, true>, 0);
+    A.yin = ya; A.ldin = c.Mc; A.yout = yb; A.c = c_half;
+    stage(rk4_stage_stream<T, 2, false>, rk4_stage_stream<T, 2, true>, 1);
+    A.yin = yb; A.ldin = c.Mc; A.yout = ya; A.c = c_full;
+    stage(rk4_stage_stream<T, 3, false>, rk4_stage_stream<T, 3, true>, 1);
+    A.yin = ya; A.ldin = c.Mc; A.yout = nullptr; A.c = c_sixth;
+    stage(rk4_stage_stream<T, 4, false>, rk4_stage_stream<T, 4, true>, 2);
     FTWA_LAUNCH_CHECK("rk4_stage_stream");
     return FTWA_OK;
 }

@@ -193,6 +193,9 @@ struct StreamChunk {
     // [2][N][Mc] (working precision) of D_i = sum_k u_ki (d_k + 1/2) per stage
     const double* u_mat = nullptr;
     void* D = nullptr;
+    // complex hopping (NULL: real t): [2 n_steps + 1][N][3] complex ratios
+    // j_ik / t of the instance at half steps, read like v_env
+    const double* hop_w = nullptr;
 };
 ftwa_status stream_step(const StreamChunk& c, const DeviceTables& tab, ftwa_dtype dtype,
                         hipStream_t stream);
