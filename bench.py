@@ -54,13 +54,14 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--workload", default="flake198",
                     choices=["flake198", "batch", "adjoint", "sizes", "thermal", "pulse",
-                             "longrange"],
+                             "longrange", "peierls"],
                     help="flake198: the headline metric (default); batch: the 64-instance mixed "
                          "batch as one graph launch; adjoint: the 54-site gradient workload; "
                          "sizes: resident throughput per lattice size; thermal: sampling of "
                          "thermal (fractional-occupation) starts on the 198-site flake; pulse: "
                          "a time-dependent staggered potential on the 198-site flake; "
-                         "longrange: a general density-density interaction on the same")
+                         "longrange: a general density-density interaction on the same; "
+                         "peierls: complex time-dependent hopping (a field pulse) on the same")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-traj", type=int, default=2048)
     ap.add_argument("--sequential", action="store_true",
@@ -446,6 +447,64 @@ def run_longrange(args):
                    "interaction": "u_ii = 3.3, u_ij = exp(-graph distance) / 2"}}))
 
 
+def run_peierls(args):
+    """Complex time-dependent hopping on the 198-site flake: a field pulse
+    j_ik(tau) = t exp(i (x_k - x_i) B(tau)), x the graph distance from site 0
+    (a stand-in for the coordinate along the field), B(tau) = 0.5 sin(2 tau),
+    tables at half steps; FP32 and FP64 on the stream kernels, 4096
+    trajectories x 400 steps, next to real hopping on the same kernels."""
+    import numpy as np
+    import torch
+    from collections import deque
+    import paper_2212_04352_amd as ft
+    lat = ft.Lattice("armchair", 10, 20)
+    N = lat.N
+    x = np.full(N, -1.0)
+    x[0] = 0
+    q = deque([0])
+    while q:  # breadth-first graph distance from site 0
+        a = q.popleft()
+        for b in lat.nbr[a][:lat.deg[a]]:
+            if x[b] < 0:
+                x[b] = x[a] + 1
+                q.append(b)
+    M = args.traj or 4096
+    steps = args.horizon_steps or 400
+    dt = 0.005
+    Bh = 0.5 * np.sin(2.0 * 0.5 * dt * np.arange(2 * steps + 1))
+    nbr = lat.nbr.astype(np.int64)
+    ii = np.arange(N)[:, None]
+    fwd = ii < nbr  # the direction i < k carries exp(i d B), the other its conjugate
+    d = np.where(fwd, x[nbr] - x[ii], x[ii] - x[nbr])
+    z = np.exp(1j * d[None] * Bh[:, None, None])
+    w = np.where(fwd[None], z, np.conj(z))
+    w[:, np.arange(3)[None, :] >= lat.deg[:, None]] = 0
+    rows = []
+    for dtype in ("f32", "f64"):
+        for peierls in (False, True):
+            p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
+            if peierls:
+                p.hop_w = torch.from_numpy(np.ascontiguousarray(w)).cuda()
+            ft.sample(p, 5)
+            ws = ft.evolve(p, dt, 2, 1, path="stream")
+            ft.sample(p, 5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ft.evolve(p, dt, steps, 10, path="stream", workspace=ws)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rows.append({"dtype": dtype, "hopping": "complex" if peierls else "real",
+                         "value": M * steps / el})
+            log(f"peierls: {dtype} complex={peierls}: {M * steps / el:.3e} traj-steps/s")
+            del p, ws
+    print(json.dumps({
+        "metric": "trajectory*RK4-steps/s with complex time-dependent hopping, 198-site flake",
+        "unit": "trajectory*RK4-steps/s", "rows": rows,
+        "config": {"workload": "flake198_peierls", "trajectories": M, "rk4_steps": steps,
+                   "dt": dt, "path": "stream", "U": 3.3,
+                   "hopping": "t exp(i (x_k - x_i) 0.5 sin(2 tau)), x = graph distance"}}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -468,6 +527,8 @@ def main():
         return run_pulse(args)
     if args.workload == "longrange":
         return run_longrange(args)
+    if args.workload == "peierls":
+        return run_peierls(args)
 
     torch.cuda.set_device(0)
     if args.copy_calibration_mib > 0:
