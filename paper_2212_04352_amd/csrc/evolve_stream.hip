@@ -50,26 +50,33 @@ __device__ __forceinline__ int64_t prow(int N, int i) {
     return (int64_t)i * N - (int64_t)i * (i - 1) / 2;
 }
 
-// x <- w x, w rounded once to T: re = fma(wr, xr, -(wi xi)),
-// im = fma(wr, xi, wi xr); `cj` takes conj(w).
+// The ratio w rounded once to T, conjugated if `cj`.
 template <typename T>
-__device__ __forceinline__ void cmul_ratio(double2 w, bool cj, cplx_t<T>& x) {
-    const T wr = (T)w.x;
-    const T wi = cj ? -(T)w.y : (T)w.y;
-    const T re = fma_rn<T>(wr, x.x, -(wi * x.y));
-    const T im = fma_rn<T>(wr, x.y, wi * x.x);
+__device__ __forceinline__ cplx_t<T> ratio(double2 w, bool cj) {
+    cplx_t<T> r;
+    r.x = (T)w.x;
+    r.y = cj ? -(T)w.y : (T)w.y;
+    return r;
+}
+
+// x <- w x: re = fma(wr, xr, -(wi xi)), im = fma(wr, xi, wi xr).
+template <typename T>
+__device__ __forceinline__ void cmul_ratio(cplx_t<T> w, cplx_t<T>& x) {
+    const T re = fma_rn<T>(w.x, x.x, -(w.y * x.y));
+    const T im = fma_rn<T>(w.x, x.y, w.y * x.x);
     x.x = re;
     x.y = im;
 }
 
 // Neighbour sums with complex hopping: col = sum_n w[j][n] rho_{i, nb(j)_n},
 // row = sum_n conj(w[i][n]) rho_{nb(i)_n, j}, slots (ascending k) summed in
-// order as in neighbour_sums.  Ratios of i and j are wave-uniform.
+// order as in neighbour_sums.  wi: conj(w[i][.]) already in T (constant
+// along a packed row); the ratios of j are read here (wave-uniform).
 template <typename T>
 __device__ __forceinline__ void hop_sums(const cplx_t<T>* X, int64_t ld, int N, int4 nbj,
                                          int4 nbi, int i, int j, int64_t m,
-                                         const double2* __restrict__ w, cplx_t<T>& col,
-                                         cplx_t<T>& row) {
+                                         const double2* __restrict__ w, const cplx_t<T>* wi,
+                                         cplx_t<T>& col, cplx_t<T>& row) {
     using C = cplx_t<T>;
     const int kc[3] = {nbj.x, nbj.y, nbj.z};
     const int kr[3] = {nbi.x, nbi.y, nbi.z};
@@ -86,8 +93,8 @@ __device__ __forceinline__ void hop_sums(const cplx_t<T>* X, int64_t ld, int N, 
     for (int n = 0; n < 3; ++n) {
         if (tc[n]) c[n].y = -c[n].y;
         if (tr[n]) r[n].y = -r[n].y;
-        cmul_ratio<T>(w[j * 3 + n], false, c[n]);
-        cmul_ratio<T>(w[i * 3 + n], true, r[n]);
+        cmul_ratio<T>(ratio<T>(w[j * 3 + n], false), c[n]);
+        cmul_ratio<T>(wi[n], r[n]);
         if (n >= nbj.w) c[n].x = c[n].y = 0;
         if (n >= nbi.w) r[n].x = r[n].y = 0;
     }
@@ -127,6 +134,12 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
         i = (int)(ij & 0xffffu);
         j = (int)(ij >> 16);
     }
+    // complex hopping: conj(w[i][.]) in T, renewed when the row changes
+    cplx_t<T> wi[3];
+    if (HOP) {
+#pragma unroll
+        for (int n = 0; n < 3; ++n) wi[n] = ratio<T>(A.hop[i * 3 + n], true);
+    }
     for (int64_t q = q0; q < q1; ++q) {
         const int64_t p = q - s * P;
         const cplx_t<T>* Ys = A.yin + (int64_t)s * P * A.ldin;
@@ -135,7 +148,7 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
         // ascending k (loads issued together)
         cplx_t<T> col, row;
         if (HOP)
-            hop_sums<T>(Ys, A.ldin, N, nb4[j], nb4[i], i, j, m, A.hop, col, row);
+            hop_sums<T>(Ys, A.ldin, N, nb4[j], nb4[i], i, j, m, A.hop, wi, col, row);
         else
             neighbour_sums<T>(Ys, A.ldin, N, nb4[j], nb4[i], i, j, m, col, row);
         const int64_t ep = p;
@@ -191,6 +204,10 @@ __global__ __launch_bounds__(256) void rk4_stage_stream(StageArgs<T> A,
                 i = 0;
             }
             j = i;
+            if (HOP && q + 1 < q1) {
+#pragma unroll
+                for (int n = 0; n < 3; ++n) wi[n] = ratio<T>(A.hop[i * 3 + n], true);
+            }
         }
     }
 }
