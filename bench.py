@@ -344,9 +344,9 @@ def run_pulse(args):
     """A time-dependent staggered potential on the 198-site flake (the
     external-potential term of Eq. (5)): V_i(t) = A(t) (+1 on one sublattice,
     -1 on the other), A a Gaussian pulse with a carrier; 4096 trajectories x
-    400 steps, FP32 on the spin-split resident kernel and on the stream
-    kernels, FP64 on the stream kernels, each with and without the potential
-    (the cost of the term)."""
+    400 steps, FP32 and FP64 on the spin-split resident kernels (FP64: the
+    split kernel) and on the stream kernels, each with and without the
+    potential (the cost of the term)."""
     import numpy as np
     import torch
     import paper_2212_04352_amd as ft
@@ -360,7 +360,7 @@ def run_pulse(args):
     sub = np.asarray(lat.sub, dtype=np.float64)
     v = 1.0 - 2.0 * sub
     rows = []
-    runs = [("f32", "resident"), ("f32", "stream"), ("f64", "stream")]
+    runs = [("f32", "resident"), ("f32", "stream"), ("f64", "resident"), ("f64", "stream")]
     for dtype, path in runs:
         for with_pot in (False, True):
             p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)

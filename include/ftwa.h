@@ -157,8 +157,9 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        its first Runge-Kutta stage, v_env[2n+1] in the second and third,
  *        v_env[2n+2] in the fourth.  Arithmetic: a = U (d_i - d_j), then
  *        a = a + A (v_i - v_j), A and v rounded once to the working precision.
- *        Integrated by the FP32 spin-split resident kernels where the
- *        automatic choice is one of them, else by the stream kernels (a forced
+ *        Integrated by the spin-split resident kernels (FP32 one workgroup
+ *        per spin block, FP64 split over several) where the automatic choice
+ *        is one of them, else by the stream kernels (a forced
  *        resident path or configuration without the potential variant gives
  *        FTWA_ENOTSUP); ftwa_adjoint refuses it.
  *        v_env must hold 2 n_steps + 1 values (not checked: device memory).

@@ -108,7 +108,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     const int64_t user_chunk = tune && tune->traj_chunk > 0 ? tune->traj_chunk : 0;
 
     // ---- path and configuration of every instance
-    std::map<int, int> group_of_config;
+    std::map<int, int> group_of_config;  // 2 config + (external potential)
     for (int k = 0; k < n_inst; ++k) {
         InstPlan ip;
         DeviceTables tab;
@@ -125,7 +125,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             }
         }
         // an external potential: the stream kernels, or a resident configuration
-        // with the potential variant (FP32 spin split)
+        // with the potential variant (spin split)
         const bool pot = inst[k].v_site != nullptr;
         // a general interaction: the stream kernels only
         if (inst[k].u_mat && (want == FTWA_PATH_RESIDENT || force >= 0))
@@ -148,9 +148,13 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             return fail(FTWA_ENOTSUP, "no resident configuration fits this lattice and dtype");
         ip.path = (want == FTWA_PATH_STREAM || !can_res) ? FTWA_PATH_STREAM : FTWA_PATH_RESIDENT;
         if (ip.path == FTWA_PATH_RESIDENT) {
-            auto it = group_of_config.find(ip.res.config);
+            // instances with a potential form groups of their own: their
+            // launches run the potential variant, whose LDS layout holds the
+            // profile and is sized for it
+            const int key = 2 * ip.res.config + (pot ? 1 : 0);
+            auto it = group_of_config.find(key);
             if (it == group_of_config.end()) {
-                it = group_of_config.emplace(ip.res.config, (int)p.groups.size()).first;
+                it = group_of_config.emplace(key, (int)p.groups.size()).first;
                 GroupPlan g;
                 g.config = ip.res.config;
                 p.groups.push_back(g);

@@ -866,12 +866,16 @@ __device__ __forceinline__ Stencil decode_split(const uint4& w, bool xp) {
     return e;
 }
 
-template <typename T, bool OWN_REG, bool T1, int SH, int DSH>
+template <typename T, bool OWN_REG, bool T1, int SH, int DSH, bool POT = false>
 __device__ __forceinline__ cplx_t<T> element_rhs_split(bool gen, bool xp, const unsigned char* Yb,
                                                        const unsigned char* Yd, const uint4& d,
-                                                       T t, T U, cplx_t<T> own) {
-    return gen ? element_rhs<T, OWN_REG, true, T1>(Yb, Yd, decode_split<SH, DSH, true>(d, xp), t, U, own)
-               : element_rhs<T, OWN_REG, false, T1>(Yb, Yd, decode_split<SH, DSH, false>(d, xp), t, U, own);
+                                                       T t, T U, cplx_t<T> own,
+                                                       const unsigned char* Vd = nullptr,
+                                                       T Aw = 0, bool pot_on = false) {
+    return gen ? element_rhs<T, OWN_REG, true, T1, POT>(Yb, Yd, decode_split<SH, DSH, true>(d, xp),
+                                                        t, U, own, Vd, Aw, pot_on)
+               : element_rhs<T, OWN_REG, false, T1, POT>(Yb, Yd, decode_split<SH, DSH, false>(d, xp),
+                                                         t, U, own, Vd, Aw, pot_on);
 }
 
 // A complex value as 32-bit payload words and back.
@@ -941,9 +945,11 @@ __device__ __forceinline__ bool settle_words(const uint64_t* const* src, int str
 // in u < UB (the first GE1 slots read transposes), boundary elements from UB
 // (the diagonal first; slots UB .. UB + GE2 - 1 read transposes); odd slots:
 // the first GO read transposes, exported elements in the first XO.  KB: halo
-// entries per thread whose reads are issued a phase ahead.
+// entries per thread whose reads are issued a phase ahead.  POT: entries may
+// carry an external potential (its profile after the two diagonal copies, in
+// their layout; the element slots follow it).
 template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
-          int KB, bool T1>
+          int KB, bool T1, bool POT = false>
 __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     using C = cplx_t<T>;
     constexpr int CB = (int)sizeof(C);
@@ -1001,7 +1007,7 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         const uint32_t* const imp = pord + kEnt;
         const uint32_t* const dsite = imp + hmax;
         const uint32_t* const dsrc = blob + (size_t)G * pw;
-        unsigned char* const Yb = lds_ptr(2 * kDiagCopy);
+        unsigned char* const Yb = lds_ptr((POT ? 3 : 2) * kDiagCopy);
         unsigned char* const dpart = lds_ptr(0);
         int& abort_flag = *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU / 64) * 2 * 8));
         const int64_t Mc = E.Mc;
@@ -1068,6 +1074,18 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
             reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * kDiagCopy)[q] = (T)0;
         }
+        // external potential of this entry: the profile v (zero without one)
+        // and the envelope, read per stage
+        const double* const venv = POT ? reinterpret_cast<const double*>(uniform64((uint64_t)E.v_env))
+                                       : nullptr;
+        const bool pot_on = POT && E.v_site != nullptr;
+        unsigned char* const vpart = lds_ptr(2 * kDiagCopy);
+        if constexpr (POT) {
+            const double* const vs = reinterpret_cast<const double*>(uniform64((uint64_t)E.v_site));
+            for (int i = t; i < N; i += NTU)
+                reinterpret_cast<T*>(vpart)[dpos[i]] = pot_on ? (T)vs[i] : (T)0;
+        }
+        int64_t cur_step = 0;  // index of the step being taken (the envelope's sample 2 cur_step)
         // records: boundary entry t < n_diag (slot UB) is the diagonal element
         // of site dsite[t]
         auto record = [&](int64_t r) {
@@ -1125,6 +1143,12 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
             constexpr int STAGE = decltype(stage_tag)::value;
             const T c = STAGE <= 2 ? c_half : (STAGE == 3 ? c_full : c_sixth);
             const unsigned char* dcur = dpart + ((STAGE - 1) & 1) * kDiagCopy;
+            // envelope at this stage's time: t_n, t_n + h/2 (twice), t_n + h
+            T Aw = 0;
+            if constexpr (POT) {
+                if (pot_on)
+                    Aw = uniform_real<T>((T)venv[2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)]);
+            }
             const uint32_t stamp = (uint32_t)(g + 1);
             uint64_t* const mine = xslot(spin0, part, stamp);
             desc = launder(desc);
@@ -1159,7 +1183,9 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 const bool gen = u < GE1 || (u >= UB && u < UB + GE2);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
                 *reinterpret_cast<C*>(Yb + ob) = own;
-                const C kk = element_rhs_split<T, true, T1, SH, DSH>(gen, xp, Yb, dcur, d, tw, Uw, own);
+                const C kk = element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, dcur, d, tw,
+                                                                          Uw, own, vpart, Aw,
+                                                                          pot_on);
                 hold[u] = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 pin(hold[u]);
                 pin(acc[u]);
@@ -1189,8 +1215,10 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 const bool xp = u - UE < XO;
                 const bool gen = u - UE < GO;
                 const C kk = STAGE == 1
-                    ? element_rhs_split<T, true, T1, SH, DSH>(gen, xp, Yb, dcur, d, tw, Uw, y[u])
-                    : element_rhs_split<T, false, T1, SH, DSH>(gen, xp, Yb, dcur, d, tw, Uw, y[u]);
+                    ? element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, dcur, d, tw, Uw,
+                                                                   y[u], vpart, Aw, pot_on)
+                    : element_rhs_split<T, false, T1, SH, DSH, POT>(gen, xp, Yb, dcur, d, tw, Uw,
+                                                                    y[u], vpart, Aw, pot_on);
                 const C nx = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
                 *reinterpret_cast<C*>(Yb + ob) = nx;
@@ -1230,6 +1258,7 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         };
 
         for (int64_t step = 1; step <= A.n_steps; ++step) {
+            cur_step = step - 1;
             if (!run_stage(stage_c<1>{})) return;
             if (!run_stage(stage_c<2>{})) return;
             if (!run_stage(stage_c<3>{})) return;
@@ -1262,7 +1291,7 @@ struct Config {
     int G = 1;
     int UB = 0, GE2 = 0, XO = 0, KB = 0;
     bool auto_pick = true;  // false: chosen only when forced or by the autotuner
-    const void* fn_pot = nullptr;  // variant with the external potential (FP32 spin split)
+    const void* fn_pot = nullptr;  // variant with the external potential (spin split)
 };
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
@@ -1300,7 +1329,7 @@ constexpr const void* split_unit_hop_fn() {
     Config{DT, 1, NTU, 1, UE, UO, GE1, GO,                                                   \
            (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false>,     \
            split_unit_hop_fn<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB>(), G, UB, GE2, XO, KB, \
-           AUTO}
+           AUTO, (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false, true>}
 
 const Config kConfigs[] = {
     FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1, 1, 1),
@@ -1392,6 +1421,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if (n * c.GO < sh.odd_gen || n * c.XO < sh.odd_x) continue;
             if (sh.max_slots + 33 > 0x7fff) continue;
             lds = split_lds_bytes(c, sh.max_slots);
+            if (need_potential) lds += 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // the profile
         } else {
             if (P + 33 > 0x7fff) continue;
             if ((int64_t)c.NTU * c.UE < n_even || (int64_t)c.NTU * c.UO < n_odd) continue;

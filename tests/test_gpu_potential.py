@@ -97,8 +97,9 @@ def test_potential_on_the_spin_split_resident_kernel(ft, orc, kind, a, b, M, ste
 
 
 def test_resident_launch_mixing_entries_with_and_without_a_potential(ft, orc):
-    """Two 198-site FP32 instances in one resident launch (same configuration),
-    only the first with a potential: each equals its own oracle run."""
+    """Two 198-site FP32 instances of one resident configuration, only the first
+    with a potential (each in a launch of its own kind): each equals its own
+    oracle run."""
     dt, steps, re = 0.01, 8, 4
     o1, l1, r1, p1, v1, _ = _setup(ft, orc, "armchair", 10, 20, 5, "f32", 21, profile="random")
     o2, l2, r2, p2, _, _ = _setup(ft, orc, "armchair", 10, 20, 6, "f32", 22, U=2.0)
@@ -110,6 +111,45 @@ def test_resident_launch_mixing_entries_with_and_without_a_potential(ft, orc):
     y2, _, _ = orc.evolve(o2, 2.0, r2, dt, steps, re, precision="f32")
     assert np.array_equal(unpack(_host(p1.rho), l1.N), y1.astype(np.complex64))
     assert np.array_equal(unpack(_host(p2.rho), l2.N), y2.astype(np.complex64))
+
+
+@pytest.mark.parametrize("kind,a,b,config", [("hex", 5, 0, 19), ("hex", 5, 0, 20), ("hex", 5, 0, 21),
+                                             ("armchair", 10, 20, 20), ("armchair", 10, 20, 21)])
+def test_potential_on_the_split_kernel(ft, orc, kind, a, b, config):
+    """FP64 at 150 and 198 sites: the split kernel's potential variant (the
+    profile in LDS after the two diagonal copies, in their layout) bitwise
+    equal to the oracle in every split configuration that fits."""
+    dt, steps, re = 0.01, 10, 5
+    olat, lat, rho0, prob, v, _ = _setup(ft, orc, kind, a, b, 7, "f64", 31, profile="random")
+    env = _pulse(steps, dt, t0=0.04)
+    _attach(prob, v, env)
+    ft.evolve(prob, dt, steps, re, config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, vsite=v, env=env)
+    assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref)
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
+def test_split_kernel_batch_with_and_without_a_potential(ft, orc):
+    """FP64, automatic path: a 198-site instance with a potential, a larger-M
+    198-site instance without one and a 150-site instance with one, in one
+    call (split kernel groups by configuration and potential)."""
+    dt, steps, re = 0.01, 8, 4
+    o1, l1, r1, p1, v1, _ = _setup(ft, orc, "armchair", 10, 20, 5, "f64", 41, profile="random")
+    o2, l2, r2, p2, _, _ = _setup(ft, orc, "armchair", 10, 20, 9, "f64", 42, U=2.0)
+    o3, l3, r3, p3, v3, _ = _setup(ft, orc, "hex", 5, 0, 6, "f64", 43, U=1.5)
+    p2.instance, p3.instance = 1, 2
+    env = _pulse(steps, dt, t0=0.03)
+    _attach(p1, v1, env)
+    _attach(p3, v3, env)
+    ft.evolve([p1, p2, p3], dt, steps, re, path="resident")
+    y1, _, _ = orc.evolve(o1, 3.3, r1, dt, steps, re, vsite=v1, env=env)
+    y2, _, _ = orc.evolve(o2, 2.0, r2, dt, steps, re)
+    y3, _, _ = orc.evolve(o3, 1.5, r3, dt, steps, re, vsite=v3, env=env)
+    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1)
+    assert np.array_equal(unpack(_host(p2.rho), l2.N), y2)
+    assert np.array_equal(unpack(_host(p3.rho), l3.N), y3)
 
 
 def test_batch_chunks_and_mixed_instances(ft, orc):
