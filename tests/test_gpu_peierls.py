@@ -116,6 +116,25 @@ def test_peierls_with_potential_interaction_and_a_plain_neighbour(ft, orc):
     assert np.array_equal(unpack(_host(p2.rho), l2.N), y2)
 
 
+def test_graph_replays_with_complex_hopping(ft, orc):
+    """A captured run with complex hopping replayed twice equals two direct
+    runs (the tables are read at the step index of each replay's own run)."""
+    import torch
+    dt, steps, re = 0.01, 10, 5
+    olat, lat, rho0, prob, w, _ = _setup(ft, orc, "torus", 2, 3, 40, 2.0, "f32", 6, steps, dt)
+    ref = ft.Problem.allocate(lat, 2.0, 40, prob.n0.cpu().numpy(), "f32")
+    ref.rho.copy_(prob.rho)
+    ref.hop_w = prob.hop_w
+    g = ft.EvolveGraph([prob], dt, steps, re)
+    for _ in range(2):
+        g.launch()
+        g.check()
+        ft.evolve(ref, dt, steps, re)
+        torch.cuda.synchronize()
+        assert torch.equal(prob.rho, ref.rho)
+    g.close()
+
+
 def test_paths_that_refuse_complex_hopping(ft, orc):
     import torch
     olat, lat, rho0, prob, w, _ = _setup(ft, orc, "armchair", 10, 20, 4, 3.3, "f32", 5, 2, 0.01)

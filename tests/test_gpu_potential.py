@@ -152,6 +152,24 @@ def test_split_kernel_batch_with_and_without_a_potential(ft, orc):
     assert np.array_equal(unpack(_host(p3.rho), l3.N), y3)
 
 
+def test_larger_instance_without_a_potential_beside_a_smaller_one_with_it(ft, orc):
+    """FP32, both forced onto the 198-site configuration: a 198-site instance
+    without a potential and a 150-site one with it.  The potential variant's
+    LDS layout is larger by the profile, so the two run as launches of their
+    own kinds, each sized for its entries; each equals its own oracle run."""
+    dt, steps, re = 0.01, 8, 4
+    o1, l1, r1, p1, _, _ = _setup(ft, orc, "armchair", 10, 20, 6, "f32", 51, U=2.0)
+    o2, l2, r2, p2, v2, _ = _setup(ft, orc, "hex", 5, 0, 5, "f32", 52, profile="random")
+    p2.instance = 1
+    env = _pulse(steps, dt, t0=0.03)
+    _attach(p2, v2, env)
+    ft.evolve([p1, p2], dt, steps, re, config=9)
+    y1, _, _ = orc.evolve(o1, 2.0, r1, dt, steps, re, precision="f32")
+    y2, _, _ = orc.evolve(o2, 3.3, r2, dt, steps, re, precision="f32", vsite=v2, env=env)
+    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1.astype(np.complex64))
+    assert np.array_equal(unpack(_host(p2.rho), l2.N), y2.astype(np.complex64))
+
+
 def test_batch_chunks_and_mixed_instances(ft, orc):
     """One call with two instances, one with a potential and one without, in
     trajectory chunks of 16: each equals its own oracle run."""
