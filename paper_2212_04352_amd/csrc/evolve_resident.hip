@@ -378,7 +378,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     // descriptor form: compact for the spin split, wide otherwise
     using DT = std::conditional_t<S == 1, uint4, ResDesc>;
     static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
-    static_assert(!POT || (S == 1 && !T1), "the potential is built into general spin-split kernels");
+    static_assert(!POT || S == 1, "the potential is built into spin-split kernels");
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
@@ -1292,6 +1292,7 @@ struct Config {
     int UB = 0, GE2 = 0, XO = 0, KB = 0;
     bool auto_pick = true;  // false: chosen only when forced or by the autotuner
     const void* fn_pot = nullptr;  // variant with the external potential (spin split)
+    const void* fn_pot_t1 = nullptr;  // the same for launches with t = 1 (FP32 spin split)
 };
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
@@ -1310,11 +1311,20 @@ constexpr const void* potential_fn() {
         return nullptr;
 }
 
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
+constexpr const void* potential_t1_fn() {
+    if constexpr (std::is_same<T, float>::value && S == 1)
+        return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, true, true>;
+    else
+        return nullptr;
+}
+
 #define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO, GE, GO)                    \
     Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                                    \
            (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
            unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(), 1, 0, 0, 0, 0, true, \
-           potential_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
+           potential_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(),                     \
+           potential_t1_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
 
 template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
           int KB>
@@ -1476,6 +1486,9 @@ ftwa_status resident_prepare(int config, size_t lds) {
     if (kConfigs[config].fn_pot)
         FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn_pot,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    if (kConfigs[config].fn_pot_t1)
+        FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn_pot_t1,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
     return FTWA_OK;
 }
 
@@ -1557,7 +1570,9 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     A.error = L.error;
     void* args[] = {&A};
     const int64_t grid = L.grid;
-    const void* fn = L.potential ? c.fn_pot : (L.unit_hop && !L.dumps && c.fn_t1 ? c.fn_t1 : c.fn);
+    const bool t1 = L.unit_hop && !L.dumps;
+    const void* fn = L.potential ? (t1 && c.fn_pot_t1 ? c.fn_pot_t1 : c.fn_pot)
+                                 : (t1 && c.fn_t1 ? c.fn_t1 : c.fn);
     if (!fn) return fail(FTWA_ENOTSUP, "this configuration has no external-potential variant");
     if (c.S == 1) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,

@@ -96,6 +96,26 @@ def test_potential_on_the_spin_split_resident_kernel(ft, orc, kind, a, b, M, ste
     assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
 
 
+def test_potential_on_the_spin_split_resident_kernel_with_general_t(ft, orc):
+    """FP32 at 198 sites with t = 0.8: the general-t potential variant (t = 1
+    launches take the variant without the hopping multiply) bitwise equal to
+    the oracle."""
+    import torch
+    dt, steps, re = 0.01, 10, 5
+    olat = orc.Lattice("armchair", 10, 20, t=0.8)
+    lat = ft.Lattice("armchair", 10, 20, t=0.8)
+    n0 = orc.fock_start(olat, "random", 61)
+    rho0 = orc.sample(olat, n0, 61, 6)
+    prob = ft.Problem.allocate(lat, 3.3, 6, n0, "f32")
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(np.complex64))))
+    v = np.random.default_rng(61).uniform(-1, 1, lat.N)
+    env = _pulse(steps, dt, t0=0.04)
+    _attach(prob, v, env)
+    ft.evolve(prob, dt, steps, re, path="resident")
+    y_ref, _, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision="f32", vsite=v, env=env)
+    assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref.astype(np.complex64))
+
+
 def test_resident_launch_mixing_entries_with_and_without_a_potential(ft, orc):
     """Two 198-site FP32 instances of one resident configuration, only the first
     with a potential (each in a launch of its own kind): each equals its own
