@@ -187,7 +187,8 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        n >= deg(i) are ignored (any finite or non-finite value).  Integrated by the stream kernels (a forced
  *        resident path or configuration gives FTWA_ENOTSUP); invariant
  *        monitors (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.
- *        Combines with v_site and u_mat.
+ *        Combines with v_site and u_mat.  hop_w must hold
+ *        (2 n_steps + 1) N 3 complex values (not checked: device memory).
  * Trajectory m of the instance has global index traj_offset + m; it keys the
  * random numbers, so any trajectory range reproduces the same trajectories.
  * `instance` enters the random-number counter (distinct streams per instance
