@@ -8,9 +8,9 @@ records every 10 steps; FP32 trajectories with FP64 ensemble moments, next to
 the FP64 run on identical samples and the observable error between them.
 
 One benchmark step is one pass of the whole hot path over the batch:
-sampling of rho(0) (Eq. (6) of arXiv:2212.04352), RK4 integration of Eq. (5)
+sampling of rho(0) (Eq. (7) of arXiv:2212.04352), RK4 integration of Eq. (6)
 for every trajectory with FP64 moments at every record, and the observables
-(Eq. (4), Eq. (8)).  Inputs are generated on the device (nothing crosses
+(Eq. (5), Eq. (10)).  Inputs are generated on the device (nothing crosses
 PCIe in the timed region).  Warm-up steps run first; then exactly --steps
 steps are timed between device synchronisations.
 
@@ -342,7 +342,7 @@ def run_thermal(args):
 
 def run_pulse(args):
     """A time-dependent staggered potential on the 198-site flake (the
-    external-potential term of Eq. (5)): V_i(t) = A(t) (+1 on one sublattice,
+    external-potential term of Eq. (6)): V_i(t) = A(t) (+1 on one sublattice,
     -1 on the other), A a Gaussian pulse with a carrier; 4096 trajectories x
     400 steps, FP32 and FP64 on the spin-split resident kernels (FP64: the
     split kernel) and on the stream kernels, each with and without the

@@ -6,13 +6,13 @@
  * Paper: F. Rousse, O. Eriksson, M. Ogren, "Correlated quantum dynamics of
  * graphene", arXiv:2212.04352.  The library computes, on the GPU:
  *   1. Gaussian initial phase-space points rho(0) around a Fock state
- *      (Sec. III, Eq. (6));
- *   2. trajectories of the fTWA equation of motion (Sec. III, Eq. (5)) with
+ *      (Sec. III, Eq. (7));
+ *   2. trajectories of the fTWA equation of motion (Sec. III, Eq. (6)) with
  *      nearest-neighbour hopping t and on-site U (Sec. II, Eq. (1)),
  *      integrated with the classical fourth-order Runge-Kutta method;
  *   3. FP64 ensemble moments of the diagonal variables, giving the site
- *      occupations (Eq. (4)), connected density-density correlations and g2
- *      (Eq. (8)).
+ *      occupations (Eq. (5)), connected density-density correlations and g2
+ *      (Eq. (10)).
  *
  * General rules for every entry point:
  *   - Return value: FTWA_OK (0) or a negative ftwa_status.  Nothing throws
@@ -150,7 +150,7 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        under the shift); ftwa_adjoint returns the gradient with respect to it.
  *   v_site [N] FP64 or NULL, v_env [2 n_steps + 1] FP64  an external on-site
  *        potential V_i(tau) = A(tau) v_site[i] acting on both spins (Sec. III:
- *        the time dependence of an external potential enters Eq. (5) as
+ *        the time dependence of an external potential enters Eq. (6) as
  *        explicit terms): ftwa_evolve adds i (V_i(tau) - V_j(tau)) rho_ij to
  *        the right-hand side, with A sampled by the caller at half steps from
  *        the start of the call, v_env[k] = A(k dt/2): step n uses v_env[2n] in
@@ -165,7 +165,7 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        v_env must hold 2 n_steps + 1 values (not checked: device memory).
  *   u_mat [N][N] FP64 or NULL  a general density-density interaction u_ij
  *        between opposite spins (Eq. (1); symmetric) in place of the on-site
- *        U (ignored then): Eq. (5)'s own form multiplies rho_ij,s by
+ *        U (ignored then): Eq. (6)'s own form multiplies rho_ij,s by
  *        D_i - D_j, D_i = sum_k u_ki (rho_kk,sbar + 1/2), accumulated as
  *        D = fma(u_ki, d_k + 1/2, D) over ascending k in the working precision
  *        (u rounded once).  Integrated by the stream kernels (a per-stage
@@ -175,7 +175,7 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *   hop_w [2 n_steps + 1][N][3] complex FP64 (interleaved re, im) or NULL
  *        complex, time-dependent hopping j_ik(tau) = t hop_w[h][i][n] for the
  *        neighbour k = nbr[i][n] of ftwa_lattice_info (Peierls phases; Sec. III:
- *        time dependence enters Eq. (5) as explicit terms), sampled at the
+ *        time dependence enters Eq. (6) as explicit terms), sampled at the
  *        half steps of v_env: step n reads table 2n in its first stage, 2n+1
  *        in the second and third, 2n+2 in the fourth.  The Hamiltonian is
  *        Hermitian, so the caller gives both directions of a bond as
@@ -214,7 +214,7 @@ typedef struct {
 
 /*
  * ftwa_sample -- writes rho(0) of every trajectory of every instance
- * (Eq. (6)): rho_ii = n_i - 1/2 (+ n_shift, if given); for i < j,
+ * (Eq. (7)): rho_ii = n_i - 1/2 (+ n_shift, if given); for i < j,
  *   rho_ij = xi_ij sqrt((n_i + n_j - 2 n_i n_j) / 2),
  * xi complex normal (E|xi|^2 = 1, E xi^2 = 0) by Box-Muller from two 53-bit
  * uniforms of Philox4x32-10 with counter
@@ -282,7 +282,7 @@ ftwa_status ftwa_evolve_workspace_size(const ftwa_instance* inst, int n_inst,
 
 /*
  * ftwa_evolve -- integrates every trajectory of every instance for n_steps
- * steps of size dt with classical RK4 applied to Eq. (5):
+ * steps of size dt with classical RK4 applied to Eq. (6):
  *   d rho_ij,s/dt = i [ t (sum_{k in nb(j)} rho_ik,s - sum_{k in nb(i)} rho_kj,s)
  *                       + U (rho_ii,sbar - rho_jj,sbar) rho_ij,s ],
  * overwriting rho with rho(n_steps dt), and fills S1/S2 (zeroed first) and
@@ -352,10 +352,10 @@ ftwa_status ftwa_autotune(const ftwa_instance* inst, int n_inst, ftwa_dtype dtyp
 /*
  * ftwa_observables -- ensemble observables from the moments of M
  * trajectories (device pointers), plug-in estimators with divisor M:
- *   n_out [n_rec][D]      n_a = S1_a/M + 1/2                          (Eq. (4))
+ *   n_out [n_rec][D]      n_a = S1_a/M + 1/2                          (Eq. (5))
  *   C_out [n_rec][D][D]   C_ab = S2_ab/M - (S1_a/M)(S1_b/M)
  *   g2_out[n_rec][D][D]   (S2_ab/M + (S1_a+S1_b)/(2M) + 1/4)
- *                         / ((S1_a/M + 1/2)(S1_b/M + 1/2))            (Eq. (8))
+ *                         / ((S1_a/M + 1/2)(S1_b/M + 1/2))            (Eq. (10))
  * with a = s*N + i.  The a = b entries of C and g2 are Weyl-symbol
  * variances, not same-site observables.  C_out and g2_out may be NULL.
  */
@@ -380,10 +380,10 @@ ftwa_status ftwa_adjoint_workspace_size(const ftwa_instance* inst, int64_t n_ste
 
 /*
  * ftwa_adjoint -- gradient of a loss of the ensemble occupations
- * nbar_a(r) = (1/n_total) sum_m rho_aa(t_r) + 1/2 (Eq. (4); a = s*N + i,
+ * nbar_a(r) = (1/n_total) sum_m rho_aa(t_r) + 1/2 (Eq. (5); a = s*N + i,
  * t_r = r * record_every * dt) with respect to U, t and the initial diagonal
  * shift, with the sampled noise held fixed, by the discrete adjoint of the
- * classical Runge-Kutta map of Eq. (5) (reverse sweep over the stages,
+ * classical Runge-Kutta map of Eq. (6) (reverse sweep over the stages,
  * states recomputed from checkpoints every ckpt_every steps).
  *   inst          one instance; inst->rho holds rho(0) as written by
  *                 ftwa_sample (device, not modified); S1, S2, inv unused.

@@ -209,11 +209,11 @@ def fock_start(lat: Lattice, kind: str = "neel", seed: int = 0, instance: int = 
 
 
 # --------------------------------------------------------------------------
-# Sampling (Eq. (6)), equation of motion (Eq. (5)), RK4, moments, observables
+# Sampling (Eq. (7)), equation of motion (Eq. (6)), RK4, moments, observables
 # --------------------------------------------------------------------------
 def sample(lat: Lattice, n0: np.ndarray, seed: int, M: int, traj_offset: int = 0,
            instance: int = 0, thermal: bool = False) -> np.ndarray:
-    """Gaussian initial points rho(0), shape [M, 2, N, N] complex128 (Eq. (6));
+    """Gaussian initial points rho(0), shape [M, 2, N, N] complex128 (Eq. (7));
     thermal: also the diagonal fluctuation Var rho_ii = n(1 - n) of the
     Appendix A.3 covariance."""
     lib = _load()
@@ -232,7 +232,7 @@ def real_normal(seed: int, c0: int, c1: int, c2: int, c3: int) -> float:
 
 
 def rhs(lat: Lattice, U: float, rho: np.ndarray, precision: str = "f64") -> np.ndarray:
-    """d rho/dt of one trajectory (Eq. (5)); rho shape [2, N, N] complex."""
+    """d rho/dt of one trajectory (Eq. (6)); rho shape [2, N, N] complex."""
     lib = _load()
     nbr = np.ascontiguousarray(lat.nbr.reshape(-1))
     deg = np.ascontiguousarray(lat.deg)
@@ -354,7 +354,7 @@ def evolve_tangent(lat: Lattice, U: float, rho0: np.ndarray, dt: float, n_steps:
 def occupation_loss_grad(lat: Lattice, U: float, rho0: np.ndarray, dt: float, n_steps: int,
                          record_every: int, target: np.ndarray):
     """Loss L = sum_{r,a} (nbar_a(r) - target_a(r))^2 over the ensemble-mean
-    occupations nbar = mean_m X + 1/2 (Eq. (4)), and its gradient with respect
+    occupations nbar = mean_m X + 1/2 (Eq. (5)), and its gradient with respect
     to U, t and the initial diagonal shifts [2][N], each component from one
     tangent run (noise held fixed).  Returns (L, dU, dt, dshift[2][N])."""
     N = lat.N
@@ -392,7 +392,7 @@ def moments(X: np.ndarray):
 
 
 def observables(N: int, M: int, S1: np.ndarray, S2: np.ndarray):
-    """(n [n_rec, 2N], C [n_rec, 2N, 2N], g2 [n_rec, 2N, 2N]) -- Eq. (4), Eq. (8)."""
+    """(n [n_rec, 2N], C [n_rec, 2N, 2N], g2 [n_rec, 2N, 2N]) -- Eq. (5), Eq. (10)."""
     lib = _load()
     n_rec, D = S1.shape
     n = np.zeros((n_rec, D))

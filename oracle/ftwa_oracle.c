@@ -12,12 +12,12 @@
  *   - honeycomb lattices with nearest-neighbour hopping j_ij = t and on-site
  *     interaction u_ij = U delta_ij (Sec. II, Eq. (1));
  *   - Gaussian initial phase-space points around a Fock state (Sec. III,
- *     Eq. (6); covariance derived in Appendix A.3);
- *   - trajectories of the fTWA equation of motion (Sec. III, Eq. (5)),
+ *     Eq. (7); covariance derived in Appendix A.3);
+ *   - trajectories of the fTWA equation of motion (Sec. III, Eq. (6)),
  *     integrated with the classical fourth-order Runge-Kutta method
  *     (the paper does not name its integrator);
  *   - stochastic averages of the diagonal phase-space variables, giving site
- *     occupations and density-density moments (Eq. (4), Eq. (8)).
+ *     occupations and density-density moments (Eq. (5), Eq. (10)).
  *
  * Conventions that the paper leaves open are fixed here and listed, with
  * their reasons, in the design notes of the repository:
@@ -294,7 +294,7 @@ int oracle_fock_start(int N, const uint8_t* sub, int kind, uint64_t seed,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Initial phase-space point of one trajectory (Eq. (6)):                    */
+/* Initial phase-space point of one trajectory (Eq. (7)):                    */
 /*   rho_ii = n_i - 1/2,                                                     */
 /*   rho_ij = xi_ij * sqrt((n_i + n_j - 2 n_i n_j)/2) for i < j,             */
 /*   rho_ji = conj(rho_ij),                                                  */
@@ -409,7 +409,7 @@ void oracle_sample(int N, const double* n0, uint64_t seed, uint32_t instance,
 
 /* ------------------------------------------------------------------------ */
 /* Ensemble moments of the diagonal variables x_m = (rho_ii up, rho_ii down) */
-/* (Eq. (4) and Eq. (8) need their first and second moments):               */
+/* (Eq. (5) and Eq. (10) need their first and second moments):               */
 /*   S1[a] = sum_m x_m[a],  S2[a,b] = sum_m x_m[a] x_m[b]  (a <= b),         */
 /* sums taken pairwise over m.  X: [n_rec][M][D], D = 2N.                    */
 /* S2 is the packed upper triangle, index a*D - a(a-1)/2 + (b-a).            */
@@ -445,10 +445,10 @@ void oracle_moments(int D, int64_t M, int n_rec, const double* X, double* S1,
 
 /* ------------------------------------------------------------------------ */
 /* Observables from the moments (plug-in estimators, divisor M):             */
-/*   n_a   = S1_a/M + 1/2                              (Eq. (4), first line) */
+/*   n_a   = S1_a/M + 1/2                              (Eq. (5), first line) */
 /*   C_ab  = S2_ab/M - (S1_a/M)(S1_b/M)   connected density-density          */
 /*   g2_ab = (S2_ab/M + (S1_a+S1_b)/(2M) + 1/4) / ((S1_a/M+1/2)(S1_b/M+1/2)) */
-/*                                                              (Eq. (8))    */
+/*                                                              (Eq. (10))    */
 /* a = spin*N + site.  C and g2 are full D x D matrices; their diagonal is   */
 /* the Weyl-symbol variance, not a same-site observable.                     */
 /* ------------------------------------------------------------------------ */
@@ -500,7 +500,7 @@ void oracle_set_num_threads(int n)
  * gradient of losses built on the site occupations.  Parameters: the
  * interaction U, the hopping t, and a shift of the initial diagonal
  * rho_ii,s(0) (the off-diagonal noise is held fixed).  The right-hand side
- * of Eq. (5),
+ * of Eq. (6),
  *   f_ij = i [ t (C_ij - R_ij) + U (d_i - d_j) rho_ij ],
  *   C_ij = sum_{k in nb(j)} rho_ik,  R_ij = sum_{k in nb(i)} rho_kj,
  *   d = diagonal of the other spin block,

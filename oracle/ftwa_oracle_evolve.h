@@ -20,19 +20,19 @@ static void ORC_NAME(cmul_w)(ORC_REAL w_re, ORC_REAL w_im, ORC_REAL* x_re, ORC_R
 }
 
 /*
- * Right-hand side of the fTWA equation of motion, Sec. III, Eq. (5), with
+ * Right-hand side of the fTWA equation of motion, Sec. III, Eq. (6), with
  * j_ij = t on bonds and u_ij = U delta_ij (Sec. II):
  *
  *   d rho_ij,s / dt = i [ t ( sum_{k in nb(j)} rho_ik,s - sum_{k in nb(i)} rho_kj,s )
  *                         + U ( rho_ii,sbar - rho_jj,sbar ) rho_ij,s ]
  *
  * (the 1/2 of (rho_kk + 1/2) cancels between the two u terms).  An external
- * on-site potential V_i (both spins) enters Eq. (5) like the U term, as the
+ * on-site potential V_i (both spins) enters Eq. (6) like the U term, as the
  * explicit term + (V_i - V_j) rho_ij inside the bracket (Sec. III notes that
- * time dependence of such a potential appears as explicit terms of Eq. (5));
+ * time dependence of such a potential appears as explicit terms of Eq. (6));
  * here V_i = A v_i with `vsite` = v (NULL: no potential) and A the envelope
  * at the stage time.  A general density-density interaction u_ij (`umat`,
- * [N][N] symmetric, NULL: on-site U) gives Eq. (5)'s own form: the factor of
+ * [N][N] symmetric, NULL: on-site U) gives Eq. (6)'s own form: the factor of
  * rho_ij is D_i - D_j with D_i = sum_k u_ki (rho_kk,sbar + 1/2) (which is
  * U (d_i - d_j) for u = U delta up to rounding).  Evaluation order: each
  * neighbour sum starts from the first (smallest) neighbour and adds the
@@ -43,7 +43,7 @@ static void ORC_NAME(cmul_w)(ORC_REAL w_re, ORC_REAL w_im, ORC_REAL* x_re, ORC_R
  *
  * Complex (Peierls) hopping, `hop` non-NULL ([N][3] complex ratios
  * w_ik = j_ik / t, slot n of site i for its neighbour k = nbr[i][n]): the two
- * hopping sums of Eq. (5) are taken literally, col = sum_{k in nb(j)} j_jk
+ * hopping sums of Eq. (6) are taken literally, col = sum_{k in nb(j)} j_jk
  * rho_ik / t and row = sum_{k in nb(i)} j_ki rho_kj / t, j_ki read from k's
  * own row (the entry of k for its neighbour i), each product by cmul_w before
  * it enters the ascending sum.
@@ -147,7 +147,7 @@ void ORC_NAME(oracle_rhs)(int N, const int32_t* nbr, const uint8_t* deg,
 /*
  * Per-trajectory quantities conserved by the exact flow (used as checks):
  *   inv[0], inv[1]: trace of rho_up, rho_down;
- *   inv[2]: Weyl Hamiltonian, Appendix A.3, Eq. (A9):
+ *   inv[2]: Weyl Hamiltonian, Appendix A.3, Eq. (A10):
  *           H_W = - sum_{ij s} j_ij rho_ij,s + U sum_i (rho_ii,up + 1/2)(rho_ii,dn + 1/2);
  *   inv[3], inv[4]: squared Frobenius norm of rho_up, rho_down.
  * Accumulated in FP64 in plain row-major order.

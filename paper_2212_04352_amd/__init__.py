@@ -4,7 +4,7 @@ honeycomb lattices, and FP64 ensemble moments -> occupations, connected
 density-density correlations and g2.
 
 Paper: Rousse, Eriksson, Ogren, "Correlated quantum dynamics of graphene",
-arXiv:2212.04352 (Sec. III, Eqs. (4)-(6) and (8)).
+arXiv:2212.04352 (Sec. III, Eqs. (6)-(7) and (10)).
 
 All computation runs in the HIP library libftwa.so (include/ftwa.h); this
 package marshals torch tensors (device memory, streams) into it.  Importing

@@ -1,7 +1,7 @@
 """torch.autograd interface to the adjoint of libftwa.
 
 `occupations(U, t, shift, spec)` returns the ensemble site occupations
-nbar[r, s*N + i] (Eq. (4) of arXiv:2212.04352) at the records
+nbar[r, s*N + i] (Eq. (5) of arXiv:2212.04352) at the records
 t_r = r * record_every * dt as a differentiable function of the interaction
 U, the hopping t and the shift of the initial diagonal rho_ii,s(0) (shape
 [2, N]; a per-site shift delta_i is delta.expand(2, N)).  The sampled

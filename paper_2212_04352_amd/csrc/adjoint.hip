@@ -1,6 +1,6 @@
 // adjoint.hip -- gradient of losses of the ensemble occupations with respect
 // to U, t and the initial diagonal, by the discrete adjoint of the classical
-// Runge-Kutta map of the fTWA equation of motion (Eq. (5) of
+// Runge-Kutta map of the fTWA equation of motion (Eq. (6) of
 // arXiv:2212.04352), with the sampled noise held fixed.
 //
 // Inner product: the state of one spin block is a Hermitian matrix and

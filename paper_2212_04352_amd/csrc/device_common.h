@@ -79,7 +79,7 @@ __device__ __forceinline__ void neighbour_sums(const cplx_t<T>* X, int64_t ld, i
 
 // f = i [ t (col - row) + a rho ] evaluated as: g = t*(col - row) per
 // component, g = fma(a, rho, g) per component, f = (-g.im, g.re), where
-// a = U (d_i - d_j) with d the other spin's diagonal (Eq. (5); the 1/2 of
+// a = U (d_i - d_j) with d the other spin's diagonal (Eq. (6); the 1/2 of
 // (rho_kk + 1/2) cancels between the two interaction terms).
 template <typename T>
 __device__ __forceinline__ cplx_t<T> rhs_element(cplx_t<T> col, cplx_t<T> row, cplx_t<T> rho,

@@ -1,7 +1,7 @@
 // evolve_resident.hip -- "resident" path of the fTWA time integration: every
 // trajectory stays on chip for the whole horizon.
 //
-// Equation of motion: Eq. (5) of arXiv:2212.04352 with j_ij = t on bonds and
+// Equation of motion: Eq. (6) of arXiv:2212.04352 with j_ij = t on bonds and
 // u_ij = U delta_ij (Sec. II):
 //   f_ij = i [ t (sum_{k in nb(j)} rho_ik - sum_{k in nb(i)} rho_kj) + U (d_i - d_j) rho_ij ],
 // d = diagonal of the other spin, integrated with classical RK4.

@@ -3,7 +3,7 @@
 // the classical Runge-Kutta step is one kernel launch over all elements of a
 // chunk of trajectories.
 //
-// Equation of motion: Eq. (5) of arXiv:2212.04352 with j_ij = t on bonds and
+// Equation of motion: Eq. (6) of arXiv:2212.04352 with j_ij = t on bonds and
 // u_ij = U delta_ij:
 //   f_ij = i [ t (sum_{k in nb(j)} rho_ik - sum_{k in nb(i)} rho_kj) + U (d_i - d_j) rho_ij ],
 // d = diagonal of the other spin block.  A wave owns 64 consecutive
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void record_diag_kernel(int N, int64_t P, int6
 }
 
 // D[s][i][m] = sum_k u_ki (d_k + 1/2) for spin block s from the other block's
-// diagonal d of the stage input (the general interaction of Eq. (5)):
+// diagonal d of the stage input (the general interaction of Eq. (6)):
 // fma over ascending k from 0, u rounded once to T.  One thread per
 // trajectory; blocks over (trajectory block, site, spin), so u_ki is
 // wave-uniform (scalar loads) and the diagonal loads are coalesced.

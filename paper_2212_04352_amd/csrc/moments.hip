@@ -1,5 +1,5 @@
 // moments.hip -- FP64 ensemble moments of the diagonal phase-space variables
-// (the stochastic averages of Eq. (4) and Eq. (8) of arXiv:2212.04352):
+// (the stochastic averages of Eq. (5) and Eq. (10) of arXiv:2212.04352):
 //   S1[r][a]  += sum_m X[r][a][m]
 //   S2[r][ab] += sum_m X[r][a][m] X[r][b][m]      (a <= b, packed)
 // X holds one chunk of trajectories, m innermost.  S2 is a symmetric rank-Mc
@@ -185,7 +185,7 @@ ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream) {
 namespace {
 
 // One block per record r.  For every trajectory m of the chunk: trace of each
-// spin, the Weyl Hamiltonian of Appendix A.3 (Eq. (A9) with j_ij = t on bonds,
+// spin, the Weyl Hamiltonian of Appendix A.3 (Eq. (A10) with j_ij = t on bonds,
 // u_ij = U delta_ij),
 //   H_W = -t (hop_up + hop_dn) + U sum_i (rho_ii,up + 1/2)(rho_ii,dn + 1/2),
 // and the squared Frobenius norms, each compared with record 0.  Maxima over

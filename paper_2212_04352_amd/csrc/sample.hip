@@ -1,4 +1,4 @@
-// sample.hip -- Gaussian initial phase-space points (Eq. (6) of
+// sample.hip -- Gaussian initial phase-space points (Eq. (7) of
 // arXiv:2212.04352, amplitude from the covariance of Appendix A.3; for a
 // thermal initial state also the diagonal fluctuation of that covariance).
 //

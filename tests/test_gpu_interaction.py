@@ -1,5 +1,5 @@
 """A general density-density interaction u_ij between opposite spins (Eq. (1),
-Eq. (5)'s own form) through the C ABI: the stream kernels (a per-stage kernel
+Eq. (6)'s own form) through the C ABI: the stream kernels (a per-stage kernel
 forming D_i = sum_k u_ki (d_k + 1/2), fma over ascending k) against the oracle
 bitwise in both precisions, together with an external potential, in a batch
 with an on-site instance, and the paths that refuse it."""

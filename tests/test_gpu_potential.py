@@ -1,5 +1,5 @@
 """An external on-site potential V_i(t) = A(t) v_i (the explicit time-dependent
-term of Eq. (5) for an external potential, Sec. III) through the C ABI: the
+term of Eq. (6) for an external potential, Sec. III) through the C ABI: the
 stream kernels against the oracle bitwise (same operation order: a = U(d_i -
 d_j), then a + A(v_i - v_j), A and v rounded once), batches mixing instances
 with and without a potential, trajectory chunks, graph replays, and the paths

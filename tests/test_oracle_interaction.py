@@ -1,5 +1,5 @@
 """Pins of the oracle's general density-density interaction u_ij between
-opposite spins (Eq. (1)); Eq. (5)'s own form then multiplies rho_ij by
+opposite spins (Eq. (1)); Eq. (6)'s own form then multiplies rho_ij by
 sum_k (u_ki - u_kj)(rho_kk,sbar + 1/2).  Pinned against a closed form, a
 conservation law and two reductions, not against the oracle itself."""
 import numpy as np

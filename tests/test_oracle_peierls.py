@@ -1,5 +1,5 @@
 """Pins of the oracle's complex (Peierls) hopping j_ik(tau) = t w_ik(tau) in
-Eq. (5) (Sec. III: explicit time-dependent terms of the Hamiltonian enter the
+Eq. (6) (Sec. III: explicit time-dependent terms of the Hamiltonian enter the
 equation of motion directly).  Pinned against the closed form of the
 non-interacting flow, gauge covariance (static and time-dependent, the latter
 against the on-site potential) and a reduction to real hopping; none of them
@@ -35,7 +35,7 @@ def _random_flux_phase(rng, N):
 
 def test_free_flow_closed_form(orc):
     """U = 0, static complex hopping J (Hermitian, random fluxes): the flow of
-    Eq. (5) is rho' = i (rho J^T - J^T rho), solved by
+    Eq. (6) is rho' = i (rho J^T - J^T rho), solved by
     rho(T) = exp(-i J^T T) rho(0) exp(i J^T T) (scipy's expm).  Fourth-order
     convergence; the transposed hopping (J in place of J^T) misses by O(1)."""
     lat = orc.Lattice("hex", 2, 0, t=0.9)

@@ -141,7 +141,7 @@ def test_fock_random(orc):
 
 
 # ---------------------------------------------------------------------------
-# Initial Gaussian sampling, Eq. (6) and the covariance of Appendix A.3
+# Initial Gaussian sampling, Eq. (7) and the covariance of Appendix A.3
 # ---------------------------------------------------------------------------
 def test_sample_structure(orc):
     lat = orc.Lattice("torus", 2, 3)
@@ -242,7 +242,7 @@ def test_real_normal_is_box_muller_of_the_philox_draw(orc):
 
 
 # ---------------------------------------------------------------------------
-# Equation of motion, Eq. (5)
+# Equation of motion, Eq. (6)
 # ---------------------------------------------------------------------------
 def _ring(N, t=1.0):
     return [(i, (i + 1) % N) for i in range(N)], [i % 2 for i in range(N)]
@@ -273,7 +273,7 @@ def test_rhs_hermitian_and_real_diagonal(orc):
 
 
 def test_rhs_is_a_commutator_with_a_hermitian_generator(orc):
-    """Eq. (5) equals i[rho, J] + i U [diag(rho_sbar), rho] in matrix form: the
+    """Eq. (6) equals i[rho, J] + i U [diag(rho_sbar), rho] in matrix form: the
     trace of f vanishes and f is anti-Hermitian-conjugate-symmetric; checked with
     random non-Hermitian input, where the stencil and the matrix product differ
     if an index is transposed."""
@@ -344,7 +344,7 @@ def test_free_fermions_exponential_and_fourth_order(orc):
 def test_invariants(orc):
     """Trace is conserved to round-off (linear invariant of the commutator
     flow); rho stays Hermitian bitwise; the Weyl Hamiltonian H_W of Appendix A.3,
-    Eq. (A9) and the Frobenius norm drift at O(dt^4) or faster (the norm of
+    Eq. (A10) and the Frobenius norm drift at O(dt^4) or faster (the norm of
     the RK4 stability polynomial on the imaginary axis deviates from 1 at
     sixth order per step, so that drift falls ~32x).  A sign error or a wrong
     spin index in the U term breaks energy conservation."""
@@ -386,7 +386,7 @@ def test_energy_not_conserved_with_wrong_u_sign(orc):
 
 def test_noise_free_trajectory_is_hartree_fock(orc):
     """Sec. III.A / Appendix A.2: with xi = 0 the fTWA trajectory is the
-    Hartree-Fock solution of Eq. (A5), n_ij = rho_ij + delta_ij / 2.  The HF
+    Hartree-Fock solution of Eq. (A6), n_ij = rho_ij + delta_ij / 2.  The HF
     equations are integrated independently with an adaptive 8th-order method."""
     lat = orc.Lattice("hex", 2, 0)
     N = lat.N
@@ -401,7 +401,7 @@ def test_noise_free_trajectory_is_hartree_fock(orc):
         n = v.reshape(2, N, N)
         out = np.empty_like(n)
         for s in range(2):
-            # Eq. (A5): dn_ij/dt = i sum_l ( j_jl n_il - j_li n_lj + (u_il - u_lj) n_ll,sbar n_ij )
+            # Eq. (A6): dn_ij/dt = i sum_l ( j_jl n_il - j_li n_lj + (u_il - u_lj) n_ll,sbar n_ij )
             nl = n[1 - s].diagonal()
             out[s] = 1j * (n[s] @ J.T - J.T @ n[s]) + 1j * U * (nl[:, None] - nl[None, :]) * n[s]
         return out.ravel()
@@ -415,7 +415,7 @@ def test_noise_free_trajectory_is_hartree_fock(orc):
 
 
 # ---------------------------------------------------------------------------
-# Ensemble statistics: moments, observables, Eq. (4) and Eq. (8)
+# Ensemble statistics: moments, observables, Eq. (5) and Eq. (10)
 # ---------------------------------------------------------------------------
 def test_moments_against_matrix_products(orc):
     rng = np.random.default_rng(3)
@@ -428,9 +428,9 @@ def test_moments_against_matrix_products(orc):
 
 
 def test_observables_both_forms_of_g2(orc):
-    """Eq. (8) written as a ratio of raw moments equals its second line, the
+    """Eq. (10) written as a ratio of raw moments equals its second line, the
     mean of (rho_ii+1/2)(rho_jj+1/2) over the product of the means; n follows
-    Eq. (4); C is the covariance of the diagonal variables."""
+    Eq. (5); C is the covariance of the diagonal variables."""
     rng = np.random.default_rng(4)
     N, M = 3, 500
     X = rng.uniform(-0.5, 0.5, size=(2, M, 2 * N))
@@ -511,7 +511,7 @@ def test_short_time_occupation_second_order(orc):
 
 
 def test_short_time_g2_two_thirds(orc):
-    """Appendix C.2, Eq. (C13): for an empty site 2 whose neighbours are all full,
+    """Appendix C.2, Eq. (C8): for an empty site 2 whose neighbours are all full,
     g2_{1 up, 2 up}(0+) = (sum_i j_2i^2 - j_12^2) / sum_i j_2i^2 = 2/3 with three
     neighbours (Sec. V, 198-site discussion)."""
     lat = orc.Lattice("torus", 2, 3)
@@ -532,7 +532,7 @@ def test_short_time_g2_two_thirds(orc):
 
 
 def test_long_time_limits(orc):
-    """Sec. IV.C and Appendix C.3, Eq. (C16) with Table I: at long times the
+    """Sec. IV.D and Appendix C.3, Eq. (C11) with Table I: at long times the
     occupations approach 1/2 (Sec. IV.B) and same-spin g2 between different
     sites approaches 2 C(n-2, n/2-2) / C(n-1, n/2-1) = (n-2)/(n-1) at half
     filling (10/11 for the 12-site torus).  Run at U = J as in the paper."""

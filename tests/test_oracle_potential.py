@@ -1,5 +1,5 @@
 """Pins of the oracle's external on-site potential (the time-dependent term of
-Eq. (5) that Sec. III describes for an external potential): the extra term
+Eq. (6) that Sec. III describes for an external potential): the extra term
 i (V_i(tau) - V_j(tau)) rho_ij with V_i(tau) = A(tau) v_i on both spins, the
 envelope sampled at the Runge-Kutta stage times (t_n; t_n + h/2 twice;
 t_n + h).  Pinned against closed forms and an independent integrator, not
