@@ -29,6 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # published; the dual-issue (packed) FP32 rate
+FP32_PLAIN_PEAK_TFLOPS = 78.6     # without packed FP32 (which this build does not emit)
+# arithmetic of one stored complex element and Runge-Kutta stage: six neighbour
+# sums (8), col - row (2), the t and U factors (4), the U term (4), the stage
+# input and accumulator updates (8)
+FLOPS_PER_ELEMENT_STAGE = 26
 
 
 def parse():
@@ -53,9 +59,11 @@ def parse():
     ap.add_argument("--cpu-traj", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--workload", default="flake198",
-                    choices=["flake198", "batch", "adjoint", "sizes", "thermal", "pulse",
-                             "longrange", "peierls"],
-                    help="flake198: the headline metric (default); batch: the 64-instance mixed "
+                    choices=["flake198", "torus54", "batch", "adjoint", "sizes", "thermal",
+                             "pulse", "longrange", "peierls"],
+                    help="flake198: the headline metric (default); torus54: FP32 against FP64 on "
+                         "identical samples on the 54-site torus at U/t = 1 and 3.3 (throughput "
+                         "and the stated accuracy); batch: the 64-instance mixed "
                          "batch as one graph launch; adjoint: the 54-site gradient workload; "
                          "sizes: resident throughput per lattice size; thermal: sampling of "
                          "thermal (fractional-occupation) starts on the 198-site flake; pulse: "
@@ -98,12 +106,10 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float, config=None):
-    """HBM bytes per launch of this run from committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs of the same kernel configuration (calibrated against a plain
-    copy of known size, scaled from the counter run's trajectory-steps to this
-    launch's), if the counters were taken on the current kernel sources; else
-    None."""
+def counter_record(kernel: str, dtype: str, config=None):
+    """The committed rocprofv3 counter record of this kernel configuration
+    (profiles/hbm_counters.json), if it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_counters.json")
     if not os.path.exists(path):
         return None
@@ -111,6 +117,18 @@ def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float, confi
         data = json.load(fh)
     rec = data.get(f"{kernel}:{dtype}:{config}")
     if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    return rec
+
+
+def counter_traffic(kernel: str, dtype: str, traj_steps_per_launch: float, config=None):
+    """HBM bytes per launch of this run from committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs of the same kernel configuration (calibrated against a plain
+    copy of known size, scaled from the counter run's trajectory-steps to this
+    launch's), if the counters were taken on the current kernel sources; else
+    None."""
+    rec = counter_record(kernel, dtype, config)
+    if not rec or "bytes_per_traj_step" not in rec:
         return None
     return rec["bytes_per_traj_step"] * traj_steps_per_launch
 
@@ -145,10 +163,34 @@ def resolved_path(ft, lat, dtype, path):
         del prob, torch
 
 
+def host_cpus():
+    """(threads the oracle may use, the host's CPU count, the CPU model).  The
+    threads are every CPU this process may run on (its affinity mask), within
+    OMP_NUM_THREADS when that is set (the GPU host gives one GPU's job a share
+    of its CPUs that way)."""
+    total = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = total
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(avail, int(omp)) if omp.isdigit() and int(omp) > 0 else avail
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, total, model
+
+
 def cpu_baseline(W, n_traj, n_steps):
     import numpy as np
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads, total, model = host_cpus()
     oracle.set_num_threads(threads)
     lat = oracle.Lattice(W.kind, W.a, W.b)
     n0 = oracle.fock_start(lat, W.start, W.seed)
@@ -158,9 +200,72 @@ def cpu_baseline(W, n_traj, n_steps):
     dt = time.perf_counter() - t0
     del np
     return {"value": n_traj * n_steps / dt, "unit": "trajectory*RK4-steps/s", "cores": threads,
-            "kind": "oracle",
+            "host_cpus": total, "cpu_model": model, "kind": "oracle",
             "sample": f"first {n_traj} trajectories x {n_steps} RK4 steps of the same workload, "
                       f"FP64, {dt:.1f} s"}
+
+
+def run_torus54(args):
+    """The 54-site torus (3 x 9 cells), random half-filled Fock start,
+    16384 trajectories, dt = 0.01 to T = 20, at U/t = 1 and 3.3: FP64 and FP32
+    on identical samples, their throughput, and the FP32 accuracy against
+    FP64 (observable error against time; the stated contract of the FP32 form:
+    1e-4 up to t32(U), statistical equivalence after)."""
+    import numpy as np
+    import torch
+    import paper_2212_04352_amd as ft
+    from workloads import FP32_HORIZON, MID_TORUS as W, fp32_contract
+    lat = ft.Lattice(W.kind, W.a, W.b, W.t_hop)
+    n0 = lat.fock_start(W.start, W.seed)
+    M = args.traj or W.n_traj
+    steps = args.horizon_steps or W.n_steps
+    times = np.arange(steps // W.record_every + 1) * W.record_every * W.dt
+    rows = []
+    for U in (1.0, 3.3):
+        runs = {}
+        for dtype in ("f64", "f32"):
+            p = ft.Problem.allocate(lat, U, M, n0, dtype)
+            ft.sample(p, W.seed)
+            ws = ft.evolve(p, W.dt, 20, W.record_every)  # warm-up
+            ft.sample(p, W.seed)
+            timing = ft.new_timing()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ft.evolve(p, W.dt, steps, W.record_every, workspace=ws, timing=timing)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            n, C, _ = ft.observables(p)
+            runs[dtype] = {"value": M * steps / el, "seconds": el,
+                           "kernel_value": timing["work"].value / (timing["ms"].value * 1e-3),
+                           "n": n.cpu().numpy(), "C": C.cpu().numpy(),
+                           "S1": p.S1.cpu().numpy(), "S2": p.S2.cpu().numpy()}
+            log(f"torus54 U={U} {dtype}: {M * steps / el:.3e} traj-steps/s")
+            del p, ws
+        r32, r64 = runs["f32"], runs["f64"]
+        t32 = FP32_HORIZON[U]
+        contract = fp32_contract(r32["n"], r32["C"], r64["n"], r64["C"], r64["S1"], r64["S2"],
+                                 M, times, t32)
+        dn = np.abs(r32["n"] - r64["n"]).max(axis=1)
+        D = r64["n"].shape[1]
+        off = ~np.eye(D, dtype=bool)
+        dC = np.abs(r32["C"] - r64["C"])[:, off].max(axis=1)
+        curve = {f"t<={T}": {"max_abs_dn": float(dn[times <= T + 1e-9].max()),
+                             "max_abs_dC": float(dC[times <= T + 1e-9].max())}
+                 for T in (2, 4, 6, 8, 10, 12, 14, 16, 18, 20)}
+        rows.append({"U": U, "fp64": {k: r64[k] for k in ("value", "seconds", "kernel_value")},
+                     "fp32": {k: r32[k] for k in ("value", "seconds", "kernel_value")},
+                     "fp32_over_fp64": r32["value"] / r64["value"], "error_vs_t": curve,
+                     "contract": contract})
+        log(f"torus54 U={U}: FP32/FP64 {r32['value'] / r64['value']:.2f}, contract "
+            f"{'holds' if contract['holds'] else 'FAILS'} (t32 = {t32})")
+    print(json.dumps({
+        "metric": "trajectory*RK4-steps/s at N=54, FP32 vs FP64 on identical samples, "
+                  "with the FP32 observable error",
+        "unit": "trajectory*RK4-steps/s", "rows": rows,
+        "config": {"workload": W.name, "lattice": "torus 3x9, N=54", "start": "random half filling",
+                   "trajectories": M, "dt": W.dt, "rk4_steps": steps,
+                   "record_every": W.record_every, "moments": "f64"}}))
+    lat.close()
 
 
 def run_batch(args):
@@ -515,6 +620,8 @@ def main():
     from workloads import FLAKE_198 as W
 
     torch.cuda.set_device(0)
+    if args.workload == "torus54":
+        return run_torus54(args)
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "adjoint":
@@ -589,6 +696,9 @@ def main():
     kernel_name = "rk4_resident" if path32 == "resident" else "rk4_stage_stream"
     run_config = args.config if args.config >= 0 else tuned
     traffic = counter_traffic(kernel_name, "f32", work_per_launch, run_config)
+    flops_per_ts = FLOPS_PER_ELEMENT_STAGE * 4 * 2 * (N * (N + 1) // 2)
+    tflops = flops_per_ts * work_per_launch / (avg_ms * 1e-3) / 1e12
+    issue = counter_record(kernel_name, "f32", run_config) or {}
     result = {
         "metric": "trajectory*RK4-steps/s at N=198, FP32 vs FP64 plain, at stated obs. error",
         "value": value,
@@ -610,7 +720,20 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "kernel_avg_ms": avg_ms,
                      "algorithmic_bytes_per_traj_step": bytes_per_ts_f32,
-                     "traj_steps_per_launch": work_per_launch},
+                     "traj_steps_per_launch": work_per_launch,
+                     "note": "the resident kernel keeps each trajectory on chip: achieved is the "
+                             "byte-equivalent rate of the state's algorithmic traffic; alu and "
+                             "issue give the on-chip view",
+                     "alu": {"achieved": tflops, "unit": "TFLOP/s",
+                             "peak": FP32_VECTOR_PEAK_TFLOPS,
+                             "frac": tflops / FP32_VECTOR_PEAK_TFLOPS,
+                             "peak_plain_fp32": FP32_PLAIN_PEAK_TFLOPS,
+                             "frac_plain_fp32": tflops / FP32_PLAIN_PEAK_TFLOPS,
+                             "algorithmic_flops_per_traj_step": flops_per_ts},
+                     "issue": {k: issue[k] for k in ("valu_busy", "lds_busy", "lds_bank_conflict",
+                                                     "valu_insts_per_element_stage",
+                                                     "lds_insts_per_element_stage")
+                               if k in issue} or None},
     }
     del ws
 
@@ -650,12 +773,26 @@ def main():
             "max_abs_dC": {"t<=5": upto(dC, 5), "t<=8": upto(dC, 8), "t<=10": upto(dC, 10),
                            "t<=20": upto(dC, 20)},
         }
+        # the stated accuracy (every other record, to bound host memory)
+        from workloads import FP32_HORIZON, fp32_contract
+        sl = slice(None, None, 2)
+        result["obs_error_fp32_vs_fp64"]["contract"] = fp32_contract(
+            n32[sl].cpu().numpy(), C32[sl].cpu().numpy(), n64[sl].cpu().numpy(),
+            C64[sl].cpu().numpy(), prob64.S1[sl].cpu().numpy(), prob64.S2[sl].cpu().numpy(),
+            M64, times[::2], FP32_HORIZON[W.U])
         del prob64, ws64
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_traj} trajectories x {args.cpu_steps} steps")
         result["cpu_baseline"] = cpu_baseline(W, args.cpu_traj, args.cpu_steps)
-    print(json.dumps(result))
+    print(json.dumps(result), flush=True)
+    # explicit teardown: device buffers and the lattice's tables are released
+    # here, while the HIP runtime is certainly up, not by finalizers at exit
+    del prob32, obs32
+    if not args.no_fp64:
+        del obs64, obs32s
+    torch.cuda.synchronize()
+    lat.close()
 
 
 if __name__ == "__main__":

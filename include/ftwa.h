@@ -23,11 +23,16 @@
  *   - "device" pointers are HIP device allocations owned by the caller; the
  *     library never frees them.  "host" pointers are ordinary memory.
  *   - Device work is queued asynchronously on `stream` (a hipStream_t; NULL
- *     means the default stream) of the current HIP device.  The caller
- *     synchronises before reading outputs.
- *   - The library allocates device memory only for a lattice's small index
- *     tables (once per lattice and device, freed by ftwa_free_lattice).
- *     Scratch memory comes from the caller through `workspace`.
+ *     means the default stream) of the current HIP device; the calls that
+ *     queue it return without waiting for the device.  The caller
+ *     synchronises before reading outputs.  The calls that wait are named
+ *     as such: ftwa_lattice_upload, ftwa_evolve_check, ftwa_graph_check,
+ *     ftwa_autotune, ftwa_adjoint (it sizes its passes from stored states),
+ *     and ftwa_evolve only when its optional kernel timing is asked for.
+ *   - The library allocates device memory only in ftwa_lattice_upload: a
+ *     lattice's index and descriptor tables, once per lattice and device,
+ *     freed by ftwa_free_lattice.  No other call allocates device memory;
+ *     scratch memory comes from the caller through `workspace`.
  *
  * Data layout of the phase-space state ("packed layout"):
  *   For N sites, one spin block is Hermitian, so only its upper triangle
@@ -114,6 +119,20 @@ ftwa_status ftwa_build_lattice_bonds(int n_sites, int n_bonds, const int32_t* bo
 ftwa_status ftwa_lattice_info(ftwa_lattice lat, int* n_sites, int* n_bonds,
                               const int32_t** nbr, const uint8_t** deg,
                               const uint8_t** sublattice);
+
+/*
+ * ftwa_lattice_upload -- allocates and uploads to the current HIP device
+ * every device table the kernels read for this lattice: the neighbour and
+ * packed-index tables, and the stencil descriptors of every resident kernel
+ * configuration that holds the lattice in either precision (a few MB at
+ * N = 198).  Synchronous; idempotent (a second call on the same device does
+ * nothing).  Must run on a device before any call there that queues work for
+ * the lattice (ftwa_sample, ftwa_evolve, ftwa_evolve_graph, ftwa_autotune,
+ * ftwa_adjoint), which otherwise fail with FTWA_EINVAL before launching
+ * anything.  Errors: FTWA_EINVAL (NULL lattice), FTWA_EHIP / FTWA_ENOMEM
+ * when an allocation or copy fails.
+ */
+ftwa_status ftwa_lattice_upload(ftwa_lattice lat);
 
 /* ftwa_free_lattice -- releases host and device tables; NULL is a no-op. */
 void ftwa_free_lattice(ftwa_lattice lat);
@@ -269,6 +288,17 @@ typedef struct {
     double* kernel_ms;
     int64_t* kernel_launches;
     double* kernel_work;
+    /* Polls before a bounded wait of a multi-workgroup resident kernel gives
+       up and the run reports FTWA_ETIMEOUT (0 = the default, about 2 s of
+       polling). */
+    unsigned spin_limit;
+    /* Fault injection for tests of the timeout path; 0 in every production
+       call.  Nonzero: every launch of a spin-split configuration (one
+       workgroup per spin block) runs only the up-spin workgroups of eight
+       pairs, whose partners are absent, so each of them gives up its first
+       wait after spin_limit polls and exits; rho is left as it was and
+       ftwa_evolve_check reports FTWA_ETIMEOUT. */
+    int drop_partners;
 } ftwa_tuning;
 
 /*
@@ -292,24 +322,39 @@ ftwa_status ftwa_evolve_workspace_size(const ftwa_instance* inst, int n_inst,
  * stage inputs fma(c, k, y), acc = k1, fma(2, k2, acc), fma(2, k3, acc),
  * acc + k4, y = fma(dt/6, acc, y) -- so results do not depend on the kernel
  * path, the tiling or the batch composition.  S1/S2 are always FP64.
- * workspace: device scratch of at least ftwa_evolve_workspace_size bytes.
- * Errors: FTWA_EINVAL (sizes, NULL pointers, workspace too small),
- * FTWA_ENONFINITE if inv is given and a trajectory became non-finite
- * (checked after the run; inv[r][3] counts them; this synchronises the
- * stream), FTWA_ETIMEOUT when the workgroups of a resident run that share a
- * trajectory were not resident together (bounded waits; checked after the
- * run), FTWA_ENOTSUP when the resident path is forced and no configuration
- * holds the lattice, FTWA_EHIP on launch failure.
+ * workspace: device scratch of at least ftwa_evolve_workspace_size bytes;
+ * it starts with the run's status block, which kernels of the run fill
+ * (a timeout of a bounded wait, non-finite trajectories counted by the
+ * invariant monitors) and ftwa_evolve_check reads.  The call queues the run
+ * and returns without waiting (unless tune->kernel_ms asks for timing).
+ * Errors, all detected on the host before anything is queued: FTWA_EINVAL
+ * (sizes, NULL pointers, workspace too small, lattice not uploaded to this
+ * device), FTWA_ENOTSUP when the resident path is forced and no
+ * configuration holds the lattice, FTWA_EHIP on launch failure.  What
+ * happens on the device is reported by ftwa_evolve_check.
  */
 ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
                         int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * ftwa_evolve_check -- waits for `stream` and reads the status block of the
+ * last run (ftwa_evolve or a graph launch) that used `workspace`:
+ * FTWA_ETIMEOUT when the workgroups of a resident run that share a
+ * trajectory were not resident together (a bounded wait gave up; rho and
+ * the moments are then incomplete), else FTWA_ENONFINITE when an instance
+ * with invariant monitors (inv) had a non-finite trajectory (inv[r][3]
+ * counts them; the message names the first instance and record), else
+ * FTWA_OK.  FTWA_EINVAL when the workspace holds no run's status.
+ */
+ftwa_status ftwa_evolve_check(const void* workspace, void* stream);
+
+/*
  * Batched launch as a HIP graph.  ftwa_evolve_graph plans the same run as
- * ftwa_evolve (same arguments; kernel timing is not available), uploads its
- * tables into `workspace` (synchronising `stream` once) and captures every
- * launch of the run into a graph; nothing is computed yet.  Instances whose
+ * ftwa_evolve (same arguments; kernel timing is not available) and captures
+ * every launch of the run, the writes of its launch table into `workspace`
+ * included, into a graph on a stream of its own; nothing is computed yet and
+ * `stream` is not used.  Instances whose
  * kernel configuration is the same are integrated by one persistent kernel
  * per pass over a table of (instance, trajectory window) entries, so a batch
  * of mixed lattice sizes and U values needs a handful of kernel nodes; the
@@ -318,7 +363,7 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
  * re-zeroes S1/S2/inv and integrates the current rho for n_steps steps.  The
  * instance buffers and the workspace must stay allocated, and no other work
  * may use the workspace, while the graph exists.  ftwa_graph_check waits for
- * `stream` and reports what ftwa_evolve reports after its launches
+ * `stream` and reports what ftwa_evolve_check reports for the last launch
  * (FTWA_ETIMEOUT, FTWA_ENONFINITE).  Configurations whose trajectories span
  * several workgroups (a spin block each, or parts of one) rely on the GPU
  * running no other work that would keep those workgroups from being resident

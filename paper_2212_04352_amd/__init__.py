@@ -14,14 +14,14 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-from ._binding import (DTYPE, FtwaError, ftwa_adjoint, ftwa_adjoint_workspace_size,  # noqa: F401
-                       ftwa_autotune, ftwa_autotune_workspace_size, ftwa_build_lattice,
-                       ftwa_build_lattice_bonds, ftwa_evolve, ftwa_evolve_graph,
-                       ftwa_evolve_workspace_size, ftwa_fock_start, ftwa_free_lattice,
-                       ftwa_graph_check, ftwa_graph_free, ftwa_graph_launch, ftwa_lattice_info,
+from ._binding import (DTYPE, FtwaError, exiting, ftwa_adjoint,  # noqa: F401
+                       ftwa_adjoint_workspace_size, ftwa_autotune, ftwa_autotune_workspace_size,
+                       ftwa_build_lattice, ftwa_build_lattice_bonds, ftwa_evolve,
+                       ftwa_evolve_check, ftwa_evolve_graph, ftwa_evolve_workspace_size,
+                       ftwa_fock_start, ftwa_free_lattice, ftwa_graph_check, ftwa_graph_free,
+                       ftwa_graph_launch, ftwa_lattice_info, ftwa_lattice_upload,
                        ftwa_last_error, ftwa_observables, ftwa_sample, ftwa_sample_thermal,
-                       ftwa_unpack, load,
-                       new_timing)
+                       ftwa_unpack, load, new_timing)
 
 
 def packed_count(N: int) -> int:
@@ -47,14 +47,25 @@ class Lattice:
     def fock_start(self, kind: str = "neel", seed: int = 0, instance: int = 0):
         return ftwa_fock_start(self.handle, kind, seed, instance)
 
-    def __del__(self):
+    def upload(self) -> None:
+        """ftwa_lattice_upload on the current device (once; later calls return at once)."""
+        ftwa_lattice_upload(self.handle)
+
+    def close(self) -> None:
+        """Releases the handle and its device tables now."""
         h = getattr(self, "handle", None)
-        if h and ftwa_free_lattice is not None:  # module globals may be gone at exit
-            try:
-                ftwa_free_lattice(h)
-            except Exception:
-                pass
-            self.handle = None
+        self.handle = None
+        if h and ftwa_free_lattice is not None:
+            ftwa_free_lattice(h)
+
+    def __del__(self):
+        # at interpreter exit the handle is left to the process's end
+        if exiting is None or exiting():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass
@@ -86,6 +97,8 @@ class Problem:
         import torch
         cdt = torch.complex128 if dtype == "f64" else torch.complex64
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(dev):
+            lat.upload()
         n0_t = torch.as_tensor(n0, dtype=torch.float64).reshape(2, lat.N).to(dev).contiguous()
         rho = torch.empty((2, packed_count(lat.N), n_traj), dtype=cdt, device=dev)
         return cls(lat, float(U), int(n_traj), dtype, n0_t, rho, traj_offset=traj_offset,
@@ -121,8 +134,13 @@ def sample(problems, seed: int, stream=None, thermal: bool = False) -> None:
 
 
 def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str = "auto",
-           traj_chunk: int = 0, workspace=None, stream=None, timing=None, config: int = -1):
-    """Runs ftwa_evolve; allocates the workspace as a torch tensor unless given."""
+           traj_chunk: int = 0, workspace=None, stream=None, timing=None, config: int = -1,
+           check: bool = True, spin_limit: int = 0, drop_partners: bool = False):
+    """Runs ftwa_evolve; allocates the workspace as a torch tensor unless given.
+    check: then waits for the stream and raises what ftwa_evolve_check
+    reports (a timed-out wait, non-finite trajectories); with check=False the
+    call returns as soon as the run is queued (call ftwa_evolve_check on the
+    returned workspace later)."""
     import torch
     problems = problems if isinstance(problems, (list, tuple)) else [problems]
     dtype = problems[0].dtype
@@ -135,7 +153,9 @@ def evolve(problems, dt: float, n_steps: int, record_every: int = 10, path: str 
     if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=problems[0].rho.device)
     ftwa_evolve(descs, dt, n_steps, record_every, dtype, workspace, path, traj_chunk, stream,
-                timing, config)
+                timing, config, spin_limit, drop_partners)
+    if check:
+        ftwa_evolve_check(workspace, stream)
     return workspace
 
 
@@ -171,15 +191,17 @@ class EvolveGraph:
 
     def close(self) -> None:
         h = getattr(self, "handle", None)
-        if h and ftwa_graph_free is not None:
-            try:
-                ftwa_graph_free(h)
-            except Exception:
-                pass
         self.handle = None
+        if h and ftwa_graph_free is not None:
+            ftwa_graph_free(h)
 
     def __del__(self):
-        self.close()
+        if exiting is None or exiting():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def autotune(problems, probe_steps: int = 10, stream=None):

@@ -4,6 +4,7 @@ stream into the C ABI.  No arithmetic happens here.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -21,8 +22,9 @@ PATH = {"auto": 0, "stream": 1, "resident": 2}
 # Every symbol include/ftwa.h declares.
 EXPORTS = (
     "ftwa_build_lattice", "ftwa_build_lattice_bonds", "ftwa_lattice_info", "ftwa_free_lattice",
+    "ftwa_lattice_upload",
     "ftwa_fock_start", "ftwa_sample", "ftwa_sample_thermal", "ftwa_evolve_workspace_size",
-    "ftwa_evolve",
+    "ftwa_evolve", "ftwa_evolve_check",
     "ftwa_observables", "ftwa_unpack", "ftwa_adjoint_workspace_size", "ftwa_adjoint",
     "ftwa_evolve_graph", "ftwa_graph_launch", "ftwa_graph_check", "ftwa_graph_free",
     "ftwa_autotune_workspace_size", "ftwa_autotune", "ftwa_last_error",
@@ -60,10 +62,26 @@ class Tuning(ctypes.Structure):
                 ("resident_config", ctypes.c_int),
                 ("kernel_ms", ctypes.POINTER(ctypes.c_double)),
                 ("kernel_launches", ctypes.POINTER(ctypes.c_int64)),
-                ("kernel_work", ctypes.POINTER(ctypes.c_double))]
+                ("kernel_work", ctypes.POINTER(ctypes.c_double)),
+                ("spin_limit", ctypes.c_uint),
+                ("drop_partners", ctypes.c_int)]
 
 
 _lib = None
+_exiting = False
+
+
+@atexit.register
+def _mark_exit() -> None:
+    """From here on the interpreter is shutting down: handles still alive are
+    left to the process's end (no HIP call from finalizers, whose order
+    against the HIP runtime's and a profiler's own teardown is not fixed)."""
+    global _exiting
+    _exiting = True
+
+
+def exiting() -> bool:
+    return _exiting
 
 
 def load() -> ctypes.CDLL:
@@ -83,6 +101,7 @@ def load() -> ctypes.CDLL:
         "ftwa_build_lattice_bonds": ([i32, i32, vp, vp, dbl, P(vp)], i32),
         "ftwa_lattice_info": ([vp, P(i32), P(i32), P(vp), P(vp), P(vp)], i32),
         "ftwa_free_lattice": ([vp], None),
+        "ftwa_lattice_upload": ([vp], i32),
         "ftwa_fock_start": ([vp, i32, u64, u32, vp], i32),
         "ftwa_sample": ([P(Instance), i32, u64, i32, vp], i32),
         "ftwa_sample_thermal": ([P(Instance), i32, u64, i32, vp], i32),
@@ -90,6 +109,7 @@ def load() -> ctypes.CDLL:
                                         P(ctypes.c_size_t)], i32),
         "ftwa_evolve": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp, ctypes.c_size_t,
                          vp], i32),
+        "ftwa_evolve_check": ([vp, vp], i32),
         "ftwa_observables": ([i32, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "ftwa_unpack": ([i32, i64, i32, vp, vp, vp], i32),
         "ftwa_evolve_graph": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp,
@@ -168,6 +188,10 @@ def ftwa_free_lattice(lat: int) -> None:
     load().ftwa_free_lattice(lat)
 
 
+def ftwa_lattice_upload(lat: int) -> None:
+    check(load().ftwa_lattice_upload(lat), "ftwa_lattice_upload")
+
+
 def ftwa_fock_start(lat: int, kind: str = "neel", seed: int = 0, instance: int = 0):
     """Host array n0[2, N] (numpy float64)."""
     import numpy as np
@@ -189,8 +213,10 @@ def _instances(insts):
     return arr
 
 
-def _tuning(path: str = "auto", traj_chunk: int = 0, timing=None, config: int = -1):
-    t = Tuning(PATH[path], int(traj_chunk), int(config), None, None, None)
+def _tuning(path: str = "auto", traj_chunk: int = 0, timing=None, config: int = -1,
+            spin_limit: int = 0, drop_partners: bool = False):
+    t = Tuning(PATH[path], int(traj_chunk), int(config), None, None, None, int(spin_limit),
+               1 if drop_partners else 0)
     if timing is not None:
         t.kernel_ms = ctypes.pointer(timing["ms"])
         t.kernel_launches = ctypes.pointer(timing["launches"])
@@ -228,13 +254,17 @@ def ftwa_evolve_workspace_size(insts, n_steps: int, record_every: int, dtype: st
 
 def ftwa_evolve(insts, dt: float, n_steps: int, record_every: int, dtype: str, workspace,
                 path: str = "auto", traj_chunk: int = 0, stream=None, timing=None,
-                config: int = -1) -> None:
+                config: int = -1, spin_limit: int = 0, drop_partners: bool = False) -> None:
     arr = _instances(insts)
-    tune = _tuning(path, traj_chunk, timing, config)
+    tune = _tuning(path, traj_chunk, timing, config, spin_limit, drop_partners)
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     check(load().ftwa_evolve(arr, len(insts), float(dt), int(n_steps), int(record_every),
                              DTYPE[dtype], ctypes.byref(tune), _ptr(workspace), nbytes,
                              _stream(stream)), "ftwa_evolve")
+
+
+def ftwa_evolve_check(workspace, stream=None) -> None:
+    check(load().ftwa_evolve_check(_ptr(workspace), _stream(stream)), "ftwa_evolve_check")
 
 
 def ftwa_observables(n_sites: int, M: int, n_rec: int, S1, S2, n_out, C_out=None, g2_out=None,

@@ -32,6 +32,50 @@ size_t cplx_bytes(ftwa_dtype d) { return d == FTWA_F64 ? 16 : 8; }
 constexpr size_t kRecordBudget = (size_t)4 << 30;  // FP64 record bytes per pass
 constexpr int64_t kStreamChunk = 4096;
 
+// Status block of a run at the start of its workspace (32-bit words): a
+// marker, the timeout flag the multi-workgroup resident kernels set, the
+// number of (instance, record) pairs whose invariant monitor counted a
+// non-finite trajectory, and the first such pair as instance << 16 | record.
+// Written only by kernels queued with the run, read by ftwa_evolve_check.
+constexpr size_t kStatusBytes = 256;
+constexpr uint32_t kStatusMagic = 0x46545741u;
+
+__global__ void status_init_kernel(uint32_t* st) {
+    if (threadIdx.x == 0) {
+        st[0] = kStatusMagic;
+        st[1] = 0u;
+        st[2] = 0u;
+        st[3] = 0xffffffffu;
+    }
+}
+
+__global__ __launch_bounds__(64) void status_nonfinite_kernel(const double* __restrict__ inv,
+                                                              int64_t n_rec, uint32_t inst,
+                                                              uint32_t* st) {
+    for (int64_t r = threadIdx.x; r < n_rec; r += blockDim.x)
+        if (inv[r * 4 + 3] > 0.0) {
+            atomicAdd(st + 2, 1u);
+            atomicMin(st + 3, (inst << 16) | (uint32_t)r);
+        }
+}
+
+// Launch-table entries travel to the device as kernel arguments (no host
+// buffer has to outlive the call, and the write can be captured in a graph).
+constexpr int kTableChunk = 16;
+struct TableChunk {
+    int n;
+    ResidentInst e[kTableChunk];
+};
+static_assert(sizeof(ResidentInst) % 4 == 0, "table entries are copied as 32-bit words");
+static_assert(sizeof(TableChunk) <= 3072, "kernel argument size");
+
+__global__ __launch_bounds__(256) void write_table_kernel(ResidentInst* dst, TableChunk c) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(c.e);
+    uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+    const int words = c.n * (int)(sizeof(ResidentInst) / 4);
+    for (int w = threadIdx.x; w < words; w += blockDim.x) out[w] = src[w];
+}
+
 struct InstPlan {
     ftwa_path path = FTWA_PATH_STREAM;
     ResidentPlan res;
@@ -72,6 +116,7 @@ struct Plan {
     std::vector<LaunchDesc> launches;  // pass-major
     // stream area
     size_t s_acc = 0, s_ya = 0, s_yb = 0, s_x = 0, s_mom = 0, s_inv = 0, s_D = 0, s_total = 0;
+    size_t off_status = 0;  // the status block (kStatusBytes at the start of the workspace)
     // resident area
     size_t r_table = 0, r_mom = 0, r_total = 0;
     int64_t n_table = 0;
@@ -79,6 +124,11 @@ struct Plan {
     // internal runs only (one instance): its state is stored at every record
     void* dump = nullptr;
     int64_t dump_stride = 0;
+    // the launch table's entries, filled on the host by build_table and
+    // written to r_table by kernels queued at the start of every run
+    std::vector<ResidentInst> table;
+    unsigned spin_limit = 0;   // 0: the kernels' default
+    bool drop_partners = false;
 };
 
 void window(const Plan& p, const ftwa_instance& in, int k, int j, int64_t* m0, int64_t* Mc) {
@@ -106,14 +156,14 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     const int force = tune ? tune->resident_config : -1;
     if (force >= resident_config_count()) return fail(FTWA_EINVAL, "resident_config out of range");
     const int64_t user_chunk = tune && tune->traj_chunk > 0 ? tune->traj_chunk : 0;
+    p.spin_limit = tune ? tune->spin_limit : 0;
+    p.drop_partners = tune && tune->drop_partners;
 
     // ---- path and configuration of every instance
     std::map<int, int> group_of_config;  // 2 config + (external potential)
     for (int k = 0; k < n_inst; ++k) {
         InstPlan ip;
-        DeviceTables tab;
-        ftwa_status st = device_tables(inst[k].lat, &tab);
-        if (st != FTWA_OK) return st;
+        const DeviceTables& tab = host_tables(inst[k].lat);
         const int N = inst[k].lat->N;
         int cfg = force;
         bool tuned_stream = false;
@@ -187,7 +237,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         if (inst[k].inv) s_inv = std::max(s_inv, (size_t)p.n_rec * 4 * chunk * sizeof(double));
         if (inst[k].u_mat) s_D = std::max(s_D, (size_t)2 * N * chunk * sizeof(double));
     }
-    size_t off = 0;
+    size_t off = kStatusBytes;  // the run's status block comes first
     p.s_acc = off; off = align_up(off + s_state);
     p.s_ya = off;  off = align_up(off + s_state);
     p.s_yb = off;  off = align_up(off + s_state);
@@ -279,13 +329,13 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     return FTWA_OK;
 }
 
-// Host work before the launches: descriptor tables, the launch tables (one
-// upload, then the stream is synchronised so the host copy may go), and the
-// kernels' LDS limits.  Nothing here may run under graph capture.
-ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStream_t stream) {
+// Host work before the launches, nothing queued: the launch-table entries
+// (their descriptor tables looked up; ftwa_lattice_upload created them) and
+// the kernels' LDS limits.  Not under graph capture.
+ftwa_status build_table(Plan& p, const ftwa_instance* inst, char* ws) {
     ftwa_status st;
-    std::vector<ResidentInst> table;
-    table.reserve((size_t)p.n_table);
+    p.table.clear();
+    p.table.reserve((size_t)p.n_table);
     for (int j = 0; j < p.n_pass; ++j)
         for (const GroupPlan& g : p.groups) {
             int64_t item0 = 0;
@@ -331,13 +381,13 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 e.dump_stride = p.dump_stride;
                 e.v_site = inst[k].v_site;
                 e.v_env = inst[k].v_env;
-                table.push_back(e);
+                p.table.push_back(e);
             }
         }
-    if (!table.empty()) {
-        FTWA_HIP_TRY(hipMemcpyAsync(ws + p.r_table, table.data(), table.size() * sizeof(ResidentInst),
-                                    hipMemcpyHostToDevice, stream));
-        FTWA_HIP_TRY(hipStreamSynchronize(stream));
+    // the stream path's tables must be on this device as well
+    for (int k = 0; k < p.n_inst; ++k) {
+        DeviceTables tab;
+        if ((st = device_tables(inst[k].lat, &tab)) != FTWA_OK) return st;
     }
     for (const GroupPlan& g : p.groups)
         if ((st = resident_prepare(g.config, g.lds)) != FTWA_OK) return st;
@@ -349,18 +399,23 @@ ftwa_status prepare(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
 ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStream_t stream,
                     KernelTimer& timer, bool cooperative) {
     ftwa_status st;
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + p.off_status);
+    hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, stream, status);
+    FTWA_LAUNCH_CHECK("status_init_kernel");
+    for (size_t e0 = 0; e0 < p.table.size(); e0 += kTableChunk) {
+        TableChunk c;
+        c.n = (int)std::min<size_t>(kTableChunk, p.table.size() - e0);
+        std::memcpy(c.e, p.table.data() + e0, (size_t)c.n * sizeof(ResidentInst));
+        hipLaunchKernelGGL(write_table_kernel, dim3(1), dim3(256), 0, stream,
+                           reinterpret_cast<ResidentInst*>(ws + p.r_table) + e0, c);
+        FTWA_LAUNCH_CHECK("write_table_kernel");
+    }
     for (int k = 0; k < p.n_inst; ++k) {
         const ftwa_instance& in = inst[k];
         const int D = 2 * in.lat->N;
         if ((st = zero_fill(in.S1, p.n_rec * D, stream)) != FTWA_OK) return st;
         if ((st = zero_fill(in.S2, p.n_rec * s2_count(D), stream)) != FTWA_OK) return st;
         if (in.inv && (st = zero_fill(in.inv, p.n_rec * 4, stream)) != FTWA_OK) return st;
-    }
-    for (const GroupPlan& g : p.groups) {
-        int* err = resident_error_word(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1),
-                                       ws + g.off_mb);
-        if (err && (st = zero_words(reinterpret_cast<unsigned*>(err), 1, stream)) != FTWA_OK)
-            return st;
     }
     // ---- stream instances
     for (int k = 0; k < p.n_inst; ++k) {
@@ -441,8 +496,9 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             L.n_steps = p.n_steps;
             L.record_every = p.record_every;
             L.mailbox = ws + g.off_mb;
-            L.error = resident_error_word(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1),
-                                          ws + g.off_mb);
+            L.error = reinterpret_cast<int*>(status + 1);
+            L.spin_limit = p.spin_limit;
+            L.drop_partners = p.drop_partners;
             L.cooperative = cooperative;
             L.unit_hop = Ld.unit_hop;
             L.dumps = p.dump != nullptr;
@@ -470,35 +526,32 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                 return st;
         }
     }
+    // ---- non-finite trajectories counted by the invariant monitors
+    for (int k = 0; k < p.n_inst; ++k) {
+        if (!inst[k].inv) continue;
+        hipLaunchKernelGGL(status_nonfinite_kernel, dim3(1), dim3(64), 0, stream, inst[k].inv,
+                           p.n_rec, (uint32_t)std::min(k, 0xffff), status);
+        FTWA_LAUNCH_CHECK("status_nonfinite_kernel");
+    }
     return FTWA_OK;
 }
 
-// Host checks after the launches (synchronise the stream): spin-split
-// timeouts and non-finite trajectories.
-ftwa_status finish(const Plan& p, const ftwa_instance* inst, char* ws, hipStream_t stream) {
-    ftwa_status st;
-    for (const GroupPlan& g : p.groups) {
-        const int* err = resident_error_word(g.config, g.Nmax, std::max<int64_t>(g.max_items, 1),
-                                             ws + g.off_mb);
-        bool timed_out = false;
-        if ((st = resident_check_error(err, stream, &timed_out)) != FTWA_OK) return st;
-        if (timed_out)
-            return fail(FTWA_ETIMEOUT,
-                        "a workgroup of a resident run timed out waiting for the others of its "
-                        "trajectory (were they resident together?)");
-    }
-    for (int k = 0; k < p.n_inst; ++k) {
-        if (!inst[k].inv) continue;
-        std::vector<double> h((size_t)p.n_rec * 4);
-        FTWA_HIP_TRY(hipMemcpyAsync(h.data(), inst[k].inv, h.size() * sizeof(double),
-                                    hipMemcpyDeviceToHost, stream));
-        FTWA_HIP_TRY(hipStreamSynchronize(stream));
-        for (int64_t r = 0; r < p.n_rec; ++r)
-            if (h[(size_t)r * 4 + 3] > 0)
-                return fail(FTWA_ENONFINITE, "instance " + std::to_string(k) +
-                                                 ": a trajectory became non-finite by record " +
-                                                 std::to_string(r));
-    }
+// Waits for `stream` and reports what the status block of the last run in
+// the workspace recorded: a bounded wait that gave up (FTWA_ETIMEOUT), then
+// non-finite trajectories (FTWA_ENONFINITE).
+ftwa_status check_status(const char* ws, hipStream_t stream) {
+    uint32_t h[4] = {0, 0, 0, 0};
+    FTWA_HIP_TRY(hipMemcpyAsync(h, ws, sizeof(h), hipMemcpyDeviceToHost, stream));
+    FTWA_HIP_TRY(hipStreamSynchronize(stream));
+    if (h[0] != kStatusMagic) return fail(FTWA_EINVAL, "no ftwa_evolve run recorded in this workspace");
+    if (h[1] != 0)
+        return fail(FTWA_ETIMEOUT,
+                    "a workgroup of a resident run timed out waiting for the others of its "
+                    "trajectory (were they resident together?)");
+    if (h[2] != 0)
+        return fail(FTWA_ENONFINITE, "instance " + std::to_string(h[3] >> 16) +
+                                         ": a trajectory became non-finite by record " +
+                                         std::to_string(h[3] & 0xffffu));
     return FTWA_OK;
 }
 
@@ -538,10 +591,10 @@ ftwa_status evolve_stored(const ftwa_instance& in, double dt, int64_t n_steps, i
     if (*bytes < plan.total) return fail(FTWA_EINVAL, "stored-state run: workspace too small");
     plan.dump = dump;
     plan.dump_stride = dump_stride;
-    if ((st = prepare(plan, &in, ws, stream)) != FTWA_OK) return st;
+    if ((st = build_table(plan, &in, ws)) != FTWA_OK) return st;
     KernelTimer off(false);
     if ((st = execute(plan, &in, ws, stream, off, true)) != FTWA_OK) return st;
-    return finish(plan, &in, ws, stream);
+    return check_status(ws, stream);
 }
 
 bool tuned_config(int N, int64_t shape, ftwa_dtype dtype, int* config) {
@@ -571,6 +624,48 @@ struct ftwa_graph_s {
 
 extern "C" {
 
+ftwa_status ftwa_lattice_upload(ftwa_lattice lat) {
+    if (!lat) return fail(FTWA_EINVAL, "ftwa_lattice_upload: NULL lattice");
+    ftwa_status st = upload_tables(lat);
+    if (st != FTWA_OK) return st;
+    const DeviceTables& tab = host_tables(lat);
+    if (!tab.bipartite) return FTWA_OK;  // the stream path needs no descriptors
+    int dev = 0;
+    FTWA_HIP_TRY(hipGetDevice(&dev));
+    const int N = lat->N;
+    // every table a plan may look up: each configuration that holds the
+    // lattice, in either precision, with and without the potential's layout
+    for (int c = 0; c < resident_config_count(); ++c)
+        for (ftwa_dtype dtype : {FTWA_F64, FTWA_F32})
+            for (bool pot : {false, true}) {
+                ResidentPlan rp;
+                if (!resident_plan(N, dtype, tab, &rp, c, true, pot)) continue;
+                const int eb = (int)cplx_bytes(dtype);
+                const void* d = nullptr;
+                std::string key;
+                if (resident_parts(c) > 1) {
+                    int pw = 0, hm = 0;
+                    st = split_tables(lat, resident_parts(c), rp.even_slots, rp.odd_slots,
+                                      rp.bnd_entry, eb, &d, &pw, &hm, true);
+                    key = split_key(dev, resident_parts(c), rp.even_slots, rp.odd_slots,
+                                    rp.bnd_entry, eb);
+                } else {
+                    st = padded_descriptors(lat, rp.even_slots, rp.odd_slots, eb,
+                                            resident_spins(c) == 1, &d, true);
+                    key = padded_key(dev, rp.even_slots, rp.odd_slots, eb, resident_spins(c) == 1);
+                }
+                if (st == FTWA_EHIP || st == FTWA_ENOMEM) return st;
+                if (st != FTWA_OK) {
+                    // this configuration cannot hold the lattice after all: a
+                    // plan that picks it reports the same error
+                    std::lock_guard<std::mutex> lock(lat->mu);
+                    lat->table_err[key] = std::make_pair(st, std::string(ftwa_last_error()));
+                }
+                if ((st = resident_prepare(c, rp.lds)) != FTWA_OK) return st;
+            }
+    return FTWA_OK;
+}
+
 ftwa_status ftwa_evolve_workspace_size(const ftwa_instance* inst, int n_inst, int64_t n_steps,
                                        int record_every, ftwa_dtype dtype,
                                        const ftwa_tuning* tune, size_t* bytes) {
@@ -596,13 +691,18 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         return fail(FTWA_EINVAL, "workspace smaller than ftwa_evolve_workspace_size");
     hipStream_t stream = (hipStream_t)stream_;
     char* ws = static_cast<char*>(workspace);
-    if ((st = prepare(plan, inst, ws, stream)) != FTWA_OK) return st;
+    if ((st = build_table(plan, inst, ws)) != FTWA_OK) return st;
     KernelTimer timer(tune && tune->kernel_ms);
     if ((st = execute(plan, inst, ws, stream, timer, true)) != FTWA_OK) return st;
     if (tune && tune->kernel_ms)
         if ((st = timer.finish(tune->kernel_ms, tune->kernel_launches, tune->kernel_work)) != FTWA_OK)
             return st;
-    return finish(plan, inst, ws, stream);
+    return FTWA_OK;
+}
+
+ftwa_status ftwa_evolve_check(const void* workspace, void* stream) {
+    if (!workspace) return fail(FTWA_EINVAL, "ftwa_evolve_check: NULL workspace");
+    return check_status(static_cast<const char*>(workspace), (hipStream_t)stream);
 }
 
 ftwa_status ftwa_evolve_graph(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
@@ -625,8 +725,8 @@ ftwa_status ftwa_evolve_graph(const ftwa_instance* inst, int n_inst, double dt, 
     }
     g->inst.assign(inst, inst + n_inst);
     g->ws = static_cast<char*>(workspace);
-    hipStream_t stream = (hipStream_t)stream_;
-    if ((st = prepare(g->plan, inst, g->ws, stream)) != FTWA_OK) {
+    (void)stream_;
+    if ((st = build_table(g->plan, inst, g->ws)) != FTWA_OK) {
         delete g;
         return st;
     }
@@ -666,7 +766,7 @@ ftwa_status ftwa_graph_launch(ftwa_graph g, void* stream) {
 
 ftwa_status ftwa_graph_check(ftwa_graph g, void* stream) {
     if (!g) return fail(FTWA_EINVAL, "invalid graph");
-    return finish(g->plan, g->inst.data(), g->ws, (hipStream_t)stream);
+    return check_status(g->ws, (hipStream_t)stream);
 }
 
 void ftwa_graph_free(ftwa_graph g) {
@@ -716,9 +816,8 @@ ftwa_instance probe_instance(const ftwa_instance& in, int64_t Mp, char* ws, cons
 
 ftwa_status plan_probe(const ftwa_instance& in, ftwa_dtype dtype, int probe_steps, Probe* out) {
     Probe pr;
-    DeviceTables tab;
-    ftwa_status st = device_tables(in.lat, &tab);
-    if (st != FTWA_OK) return st;
+    ftwa_status st;
+    const DeviceTables& tab = host_tables(in.lat);
     const int N = in.lat->N;
     int64_t want = 0;
     for (int c = 0; c < resident_config_count(); ++c) {
@@ -818,7 +917,7 @@ ftwa_status ftwa_autotune(const ftwa_instance* inst, int n_inst, ftwa_dtype dtyp
             if ((st = plan_evolve(&q, 1, 0.01, probe_steps, probe_steps, dtype, &t, &p)) != FTWA_OK)
                 return done(st);
             char* ews = ws + pr.off_ws;
-            if ((st = prepare(p, &q, ews, stream)) != FTWA_OK) return done(st);
+            if ((st = build_table(p, &q, ews)) != FTWA_OK) return done(st);
             // one warm-up run, then the fastest of kProbeReps timed runs
             float ms = -1.0f;
             for (int rep = 0; rep <= kProbeReps; ++rep) {
@@ -833,7 +932,7 @@ ftwa_status ftwa_autotune(const ftwa_instance* inst, int n_inst, ftwa_dtype dtyp
                 FTWA_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
                 if (rep > 0 && (ms < 0 || t < ms)) ms = t;
             }
-            if ((st = finish(p, &q, ews, stream)) != FTWA_OK) return done(st);
+            if ((st = check_status(ews, stream)) != FTWA_OK) return done(st);
             if (best_ms < 0 || ms < best_ms) {
                 best_ms = ms;
                 best = c;

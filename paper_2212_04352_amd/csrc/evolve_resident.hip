@@ -86,9 +86,10 @@ struct ResidentArgs {
     int Nmax;
     uint32_t tail_off;          // LDS byte offset of the record sums and the abort flag
     int* error;                 // set to 1 when a wait times out
+    unsigned spin_limit;        // polls before a bounded wait gives up
 };
 
-constexpr unsigned kSpinLimit = 1u << 26;  // ~2 s of polling
+constexpr unsigned kSpinLimit = 1u << 26;  // default: ~2 s of polling
 
 // Descriptor table as a global-address-space pointer.  It is passed through
 // an SGPR every phase ("laundered") so that the compiler re-reads descriptors
@@ -709,7 +710,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                                                    __HIP_MEMORY_SCOPE_AGENT);
                     unsigned it = 0;
                     while ((uint32_t)(w >> 32) != want) {
-                        if (++it >= kSpinLimit) {
+                        if (++it >= A.spin_limit) {
                             abort_flag = 1;
                             atomicExch(A.error, 1);
                             break;
@@ -907,7 +908,7 @@ __device__ __forceinline__ uint64_t peek(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-constexpr unsigned kSplitSpinLimit = 1u << 22;  // ~3.5 s at the longer sleeps below
+constexpr unsigned kSplitSpinLimit = 1u << 22;  // default: ~3.5 s at the longer sleeps below
 
 // Waits until NW published words carry stage `want`: w[k] was read from
 // src[k / WPE] + (k % WPE) * stride (WPE = NW / NP, null pointers are
@@ -917,7 +918,8 @@ constexpr unsigned kSplitSpinLimit = 1u << 22;  // ~3.5 s at the longer sleeps b
 // or another wait of the workgroup gave up.
 template <int NW, int NP>
 __device__ __forceinline__ bool settle_words(const uint64_t* const* src, int stride, uint64_t* w,
-                                             uint32_t want, int& abort_flag, int* error) {
+                                             uint32_t want, int& abort_flag, int* error,
+                                             unsigned limit) {
     constexpr int WPE = NW / NP;
     unsigned it = 0;
     while (true) {
@@ -927,7 +929,7 @@ __device__ __forceinline__ bool settle_words(const uint64_t* const* src, int str
             ok = ok && (src[k / WPE] == nullptr || (uint32_t)(w[k] >> 32) == want);
         if (ok) return true;
         if (*reinterpret_cast<volatile int*>(&abort_flag)) return false;
-        if (++it >= kSplitSpinLimit) {
+        if (++it >= limit) {
             abort_flag = 1;
             atomicExch(error, 1);
             return false;
@@ -1123,7 +1125,9 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         };
         auto land = [&](Batch& bt, int h0, int h1, uint32_t want) {
             for (int hb = h0;; ) {
-                if (!settle_words<KB * W, KB>(bt.src, kEnt, bt.w, want, abort_flag, A.error)) return;
+                if (!settle_words<KB * W, KB>(bt.src, kEnt, bt.w, want, abort_flag, A.error,
+                                              A.spin_limit))
+                    return;
 #pragma unroll
                 for (int j = 0; j < KB; ++j) {
                     if (bt.src[j]) {
@@ -1227,7 +1231,8 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 if (xp && (d.w & 0x8000u)) publish<T>(mine + (d.w & 0x7fffu), kEnt, nx, stamp);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (t < N && settle_words<DW, 1>(dsrcp, kEnt, dw, stamp, abort_flag, A.error)) {
+            if (t < N && settle_words<DW, 1>(dsrcp, kEnt, dw, stamp, abort_flag, A.error,
+                                             A.spin_limit)) {
                 Payload<T> pl;
 #pragma unroll
                 for (int kk = 0; kk < W; ++kk) pl.w[kk] = kk < DW ? (uint32_t)dw[kk] : 0u;
@@ -1532,8 +1537,8 @@ int64_t resident_grid(int config, size_t lds, int64_t n_items) {
     return std::max<int64_t>(1, std::min(n_items, cap));
 }
 
-// Spin-split scratch of one launch: the mailbox words, then the error word.
-// (split kernel: the published words of every group, then the error word)
+// Spin-split scratch of one launch: the mailbox words (split kernel: the
+// published words of every group).
 size_t mailbox_words(const Config& c, int Nmax, int64_t grid) {
     if (c.G > 1) return (size_t)(grid / (2 * c.G)) * (size_t)split_words(c);
     return (size_t)(grid / 2) * 2 * 2 * Nmax;
@@ -1542,15 +1547,7 @@ size_t mailbox_words(const Config& c, int Nmax, int64_t grid) {
 size_t resident_mailbox_bytes(int config, int Nmax, int64_t n_items) {
     const Config& c = kConfigs[config];
     if (c.S != 1) return 0;
-    return mailbox_words(c, Nmax, resident_grid(config, 0, n_items)) * sizeof(uint64_t) + 64;
-}
-
-int* resident_error_word(int config, int Nmax, int64_t n_items, void* mailbox) {
-    const Config& c = kConfigs[config];
-    if (c.S != 1) return nullptr;
-    return reinterpret_cast<int*>(static_cast<char*>(mailbox) +
-                                  mailbox_words(c, Nmax, resident_grid(config, 0, n_items)) *
-                                      sizeof(uint64_t));
+    return mailbox_words(c, Nmax, resident_grid(config, 0, n_items)) * sizeof(uint64_t);
 }
 
 
@@ -1568,8 +1565,12 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     A.Nmax = L.Nmax;
     A.tail_off = (uint32_t)(L.lds - lds_tail(c));
     A.error = L.error;
+    A.spin_limit = L.spin_limit ? L.spin_limit : (c.G > 1 ? kSplitSpinLimit : kSpinLimit);
     void* args[] = {&A};
-    const int64_t grid = L.grid;
+    // fault injection for tests of the timeout path: only the up-spin
+    // workgroups of eight pairs run, so that each of them gives up its first
+    // wait for the absent partner and exits
+    const int64_t grid = (L.drop_partners && c.S == 1 && c.G == 1) ? 8 : L.grid;
     const bool t1 = L.unit_hop && !L.dumps;
     const void* fn = L.potential ? (t1 && c.fn_pot_t1 ? c.fn_pot_t1 : c.fn_pot)
                                  : (t1 && c.fn_t1 ? c.fn_t1 : c.fn);
@@ -1595,16 +1596,6 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
         FTWA_HIP_TRY(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(c.NTU * c.UNITS), args,
                                      (unsigned)L.lds, stream));
     }
-    return FTWA_OK;
-}
-
-ftwa_status resident_check_error(const int* err, hipStream_t stream, bool* timed_out) {
-    *timed_out = false;
-    if (!err) return FTWA_OK;
-    int h = 0;
-    FTWA_HIP_TRY(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, stream));
-    FTWA_HIP_TRY(hipStreamSynchronize(stream));
-    *timed_out = h != 0;
     return FTWA_OK;
 }
 

@@ -95,6 +95,12 @@ struct ftwa_lattice_s {
     // split-kernel tables by (device, parts, even slots, odd slots, boundary
     // entry, element bytes): device blob, words per part, import capacity
     std::map<std::tuple<int, int, int64_t, int64_t, int64_t, int>, std::tuple<void*, int, int>> split;
+    // host part of the tables (class sizes, split shapes; no device pointers),
+    // computed when the lattice is built
+    ftwa::DeviceTables host;
+    // kernel tables ftwa_lattice_upload could not build, by split_key /
+    // padded_key: the error it met
+    std::map<std::string, std::pair<ftwa_status, std::string>> table_err;
 };
 
 namespace ftwa {
@@ -130,18 +136,32 @@ ftwa_status hip_fail(hipError_t e, const char* what);
 ftwa_status check_instances(const ftwa_instance* inst, int n_inst, bool need_moments,
                             const char* who);
 
-// Uploads (once per device) and returns the lattice's device tables.
+// Host part of the tables, computed by ftwa_build_lattice(_bonds): class
+// order, diagonal positions, class sizes and split shapes.
+void compute_host_tables(ftwa_lattice lat);
+const DeviceTables& host_tables(ftwa_lattice lat);
+// The lattice's device tables on the current device (FTWA_EINVAL unless
+// ftwa_lattice_upload ran there).
 ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out);
+// Allocates and uploads the basic tables on the current device (idempotent).
+ftwa_status upload_tables(ftwa_lattice lat);
+std::string split_key(int dev, int G, int64_t even_slots, int64_t odd_slots, int64_t bnd_entry,
+                      int elem_bytes);
+std::string padded_key(int dev, int64_t even_slots, int64_t odd_slots, int elem_bytes,
+                       bool compact);
 // Descriptor table in LDS-slot order with the even class padded to
 // even_slots entries and the odd class to odd_slots entries; padding entries
 // own the scratch slot P+1 and read only the zero slot P.  compact selects
 // the 16-byte form of the spin-split kernels (else the wide form with
 // offsets for elem_bytes-byte elements).  Uploaded once per shape, element
-// size and form.
+// size and form by ftwa_lattice_upload (create = true); the compute calls
+// only look it up.
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               int elem_bytes, bool compact, const void** out);
+                               int elem_bytes, bool compact, const void** out,
+                               bool create = false);
 
-// Tables of the split resident kernel for G parts (uploaded once per shape).
+// Tables of the split resident kernel for G parts (uploaded once per shape by
+// ftwa_lattice_upload).
 // One block of *part_words 32-bit words per part:
 //   [0..7]   n_even, n_own, n_import_even, n_import_odd, n_diag, 0, 0, 0
 //   [8..)    descriptors (compact form, 16 bytes per entry, even_slots +
@@ -159,7 +179,7 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
 // then, after the G blocks, [N]: site -> part << 16 | slot of its diagonal element.
 ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t odd_slots,
                          int64_t bnd_entry, int elem_bytes, const void** out, int* part_words,
-                         int* hmax);
+                         int* hmax, bool create = false);
 
 // ---------------------------------------------------------------- launches
 // Sampling of rho(0) for one instance (sample.hip).
@@ -269,7 +289,9 @@ struct ResidentLaunch {
     int64_t n_steps;
     int record_every;
     void* mailbox;              // resident_mailbox_bytes(config, Nmax, n_items) of scratch
-    int* error;                 // resident_error_word(...) or NULL
+    int* error;                 // the run's timeout word (set to 1 by a wait that gave up)
+    unsigned spin_limit;        // polls before a bounded wait gives up (0: the default)
+    bool drop_partners;         // fault injection: run only one workgroup of each pair
     bool cooperative;           // false under graph capture
     bool unit_hop;              // every instance of the launch has t = 1
     bool dumps;                 // an entry stores its state at records (ResidentInst::dump)
@@ -290,10 +312,8 @@ int64_t resident_max_pairs();
 int64_t resident_concurrency(int config, size_t lds);  // trajectories in flight at once
 int64_t resident_grid(int config, size_t lds, int64_t n_items);
 size_t resident_mailbox_bytes(int config, int Nmax, int64_t n_items);
-int* resident_error_word(int config, int Nmax, int64_t n_items, void* mailbox);
 ftwa_status resident_prepare(int config, size_t lds);  // host only, not under graph capture
 ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream);
-ftwa_status resident_check_error(const int* err, hipStream_t stream, bool* timed_out);
 
 // Configurations chosen by ftwa_autotune, per (device, N, even-class size, dtype).
 bool tuned_config(int N, int64_t shape, ftwa_dtype dtype, int* config);

@@ -181,6 +181,7 @@ ftwa_status ftwa_build_lattice(ftwa_lattice_kind kind, int a, int b, double t_ho
         delete lat;
         return fail(FTWA_EINVAL, "lattice has more than 255 sites");
     }
+    compute_host_tables(lat);
     *out = lat;
     return FTWA_OK;
 }
@@ -216,6 +217,7 @@ ftwa_status ftwa_build_lattice_bonds(int n_sites, int n_bonds, const int32_t* bo
         lat->deg[i] = (uint8_t)k;
         lat->sub[i] = sublattice ? (uint8_t)(sublattice[i] & 1) : 0;
     }
+    compute_host_tables(lat);
     *out = lat;
     return FTWA_OK;
 }
@@ -233,6 +235,10 @@ ftwa_status ftwa_lattice_info(ftwa_lattice lat, int* n_sites, int* n_bonds, cons
 
 void ftwa_free_lattice(ftwa_lattice lat) {
     if (!lat) return;
+    if (lat->dev.empty() && lat->padded.empty() && lat->split.empty()) {
+        delete lat;  // never uploaded: no HIP call
+        return;
+    }
     int cur = -1;
     (void)hipGetDevice(&cur);
     for (auto& [dev, tab] : lat->dev) {
@@ -533,12 +539,33 @@ SplitShape split_shape(const std::vector<SplitPart>& parts) {
 
 }  // namespace
 
+std::string split_key(int dev, int G, int64_t even_slots, int64_t odd_slots, int64_t bnd_entry,
+                      int elem_bytes) {
+    return "s" + std::to_string(dev) + ":" + std::to_string(G) + ":" + std::to_string(even_slots) +
+           ":" + std::to_string(odd_slots) + ":" + std::to_string(bnd_entry) + ":" +
+           std::to_string(elem_bytes);
+}
+
+std::string padded_key(int dev, int64_t even_slots, int64_t odd_slots, int elem_bytes,
+                       bool compact) {
+    return "p" + std::to_string(dev) + ":" + std::to_string(even_slots) + ":" +
+           std::to_string(odd_slots) + ":" + std::to_string(elem_bytes) + ":" +
+           std::to_string(compact ? 1 : 0);
+}
+
+// A table that ftwa_lattice_upload could not build for this device: the
+// error it met then, else "not uploaded".
+ftwa_status missing_table(ftwa_lattice lat, const std::string& key) {
+    auto it = lat->table_err.find(key);
+    if (it != lat->table_err.end()) return fail(it->second.first, it->second.second);
+    return fail(FTWA_EINVAL,
+                "the lattice's kernel tables are not on this device: call ftwa_lattice_upload first");
+}
+
 ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t odd_slots,
                          int64_t bnd_entry, int elem_bytes, const void** out, int* part_words,
-                         int* hmax) {
-    DeviceTables tab;
-    ftwa_status st = device_tables(lat, &tab);
-    if (st != FTWA_OK) return st;
+                         int* hmax, bool create) {
+    const DeviceTables& tab = host_tables(lat);
     if (!tab.bipartite) return fail(FTWA_ENOTSUP, "lattice is not bipartite");
     if (G < 2 || G > kMaxParts) return fail(FTWA_EINVAL, "split: part count out of range");
     const int N = lat->N;
@@ -555,6 +582,8 @@ ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t od
         *hmax = std::get<2>(it->second);
         return FTWA_OK;
     }
+    if (!create)
+        return missing_table(lat, split_key(dev, G, even_slots, odd_slots, bnd_entry, elem_bytes));
     const std::vector<uint32_t>& order = lat->class_order;
     const int64_t n = (int64_t)order.size();
     const std::vector<SplitPart> parts =
@@ -716,10 +745,8 @@ ftwa_status split_tables(ftwa_lattice lat, int G, int64_t even_slots, int64_t od
 }
 
 ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd_slots,
-                               int elem_bytes, bool compact, const void** out) {
-    DeviceTables tab;
-    ftwa_status st = device_tables(lat, &tab);
-    if (st != FTWA_OK) return st;
+                               int elem_bytes, bool compact, const void** out, bool create) {
+    const DeviceTables& tab = host_tables(lat);
     if (!tab.bipartite) return fail(FTWA_ENOTSUP, "lattice is not bipartite");
     const int N = lat->N;
     const int64_t P = packed_count(N);
@@ -740,6 +767,7 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
         *out = it->second;
         return FTWA_OK;
     }
+    if (!create) return missing_table(lat, padded_key(dev, even_slots, odd_slots, elem_bytes, compact));
     // LDS slot of every pair {i, j} (packed index of i <= j) and whether the
     // slot holds rho_ij (a = min) or rho_ji
     std::vector<uint32_t> slot((size_t)P);
@@ -855,26 +883,8 @@ ftwa_status padded_descriptors(ftwa_lattice lat, int64_t even_slots, int64_t odd
     return FTWA_OK;
 }
 
-ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
-    int dev = 0;
-    FTWA_HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(lat->mu);
-    auto it = lat->dev.find(dev);
-    if (it != lat->dev.end()) {
-        *out = it->second;
-        return FTWA_OK;
-    }
-    const int N = lat->N;
-    const int64_t P = packed_count(N);
-    std::vector<int32_t> nb((size_t)N * 4), off(N);
-    std::vector<uint32_t> elem((size_t)P);
-    for (int i = 0; i < N; ++i) {
-        for (int k = 0; k < kMaxDeg; ++k) nb[(size_t)i * 4 + k] = lat->nbr[(size_t)i * kMaxDeg + k];
-        nb[(size_t)i * 4 + 3] = lat->deg[i];
-        off[i] = (int32_t)packed_row(N, i);
-        for (int j = i; j < N; ++j) elem[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)i | ((uint32_t)j << 16);
-    }
-    DeviceTables tab;
+void compute_host_tables(ftwa_lattice lat) {
+    DeviceTables& tab = lat->host;
     std::vector<uint32_t> order;
     std::vector<int32_t> dpos;
     std::vector<int32_t> rank;
@@ -887,6 +897,42 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
         for (int G = 2; G <= kMaxParts; ++G)
             tab.split[G] = split_shape(
                 split_layout(*lat, G, tab.n_even, tab.n_gen_even, tab.n_gen_odd));
+    }
+}
+
+const DeviceTables& host_tables(ftwa_lattice lat) { return lat->host; }
+
+ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
+    int dev = 0;
+    FTWA_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(lat->mu);
+    auto it = lat->dev.find(dev);
+    if (it == lat->dev.end())
+        return fail(FTWA_EINVAL,
+                    "the lattice's tables are not on this device: call ftwa_lattice_upload first");
+    *out = it->second;
+    return FTWA_OK;
+}
+
+ftwa_status upload_tables(ftwa_lattice lat) {
+    int dev = 0;
+    FTWA_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(lat->mu);
+    if (lat->dev.count(dev)) return FTWA_OK;
+    const int N = lat->N;
+    const int64_t P = packed_count(N);
+    std::vector<int32_t> nb((size_t)N * 4), off(N);
+    std::vector<uint32_t> elem((size_t)P);
+    for (int i = 0; i < N; ++i) {
+        for (int k = 0; k < kMaxDeg; ++k) nb[(size_t)i * 4 + k] = lat->nbr[(size_t)i * kMaxDeg + k];
+        nb[(size_t)i * 4 + 3] = lat->deg[i];
+        off[i] = (int32_t)packed_row(N, i);
+        for (int j = i; j < N; ++j) elem[(size_t)(packed_row(N, i) + (j - i))] = (uint32_t)i | ((uint32_t)j << 16);
+    }
+    DeviceTables tab = lat->host;
+    if (tab.bipartite) {
+        const std::vector<uint32_t>& order = lat->class_order;
+        const std::vector<int32_t>& dpos = lat->diag_pos;
         FTWA_HIP_TRY(hipMalloc(&tab.ord, order.size() * sizeof(uint32_t)));
         FTWA_HIP_TRY(hipMemcpy(tab.ord, order.data(), order.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice));
@@ -901,7 +947,6 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
     FTWA_HIP_TRY(hipMemcpy(tab.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     FTWA_HIP_TRY(hipMemcpy(tab.elem, elem.data(), elem.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     lat->dev[dev] = tab;
-    *out = tab;
     return FTWA_OK;
 }
 
