@@ -346,8 +346,32 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
  * with invariant monitors (inv) had a non-finite trajectory (inv[r][3]
  * counts them; the message names the first instance and record), else
  * FTWA_OK.  FTWA_EINVAL when the workspace holds no run's status.
+ * workspace NULL: the status of the last ftwa_evolve_static run on the
+ * current device.
  */
 ftwa_status ftwa_evolve_check(const void* workspace, void* stream);
+
+/*
+ * ftwa_evolve_static -- ftwa_evolve for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same run, bitwise the same results, with the
+ * workspace in a fixed 64 MiB array of device memory that the library holds
+ * on every device it runs on (its address looked up once per device).  The
+ * call allocates nothing; the caller still passes the instances' buffers,
+ * and the lattices must have been uploaded (ftwa_lattice_upload).  Limit:
+ * runs whose ftwa_evolve_workspace_size exceeds 64 MiB (67108864 bytes) are
+ * refused with FTWA_EINVAL before anything is queued (a few thousand
+ * trajectories with a few hundred records at N = 54; use ftwa_evolve, or
+ * fewer trajectories per call).  Kernel timing (tune->kernel_ms) is refused.
+ * All calls on one device share that array, and it keeps the last call's
+ * contents (every run clears what must start at zero): calls that overlap on
+ * one device -- on different streams, or from several threads -- race, so
+ * the caller serialises them (one stream).  ftwa_evolve_check(NULL, stream)
+ * reports the device status of the last such run.  Errors as ftwa_evolve.
+ */
+ftwa_status ftwa_evolve_static(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
+                               int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
+                               void* stream);
 
 /*
  * Batched launch as a HIP graph.  ftwa_evolve_graph plans the same run as

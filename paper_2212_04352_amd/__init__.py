@@ -17,7 +17,8 @@ from dataclasses import dataclass
 from ._binding import (DTYPE, FtwaError, exiting, ftwa_adjoint,  # noqa: F401
                        ftwa_adjoint_workspace_size, ftwa_autotune, ftwa_autotune_workspace_size,
                        ftwa_build_lattice, ftwa_build_lattice_bonds, ftwa_evolve,
-                       ftwa_evolve_check, ftwa_evolve_graph, ftwa_evolve_workspace_size,
+                       ftwa_evolve_check, ftwa_evolve_graph, ftwa_evolve_static,
+                       ftwa_evolve_workspace_size,
                        ftwa_fock_start, ftwa_free_lattice, ftwa_graph_check, ftwa_graph_free,
                        ftwa_graph_launch, ftwa_lattice_info, ftwa_lattice_upload,
                        ftwa_last_error, ftwa_observables, ftwa_sample, ftwa_sample_thermal,

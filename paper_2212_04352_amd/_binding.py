@@ -24,7 +24,7 @@ EXPORTS = (
     "ftwa_build_lattice", "ftwa_build_lattice_bonds", "ftwa_lattice_info", "ftwa_free_lattice",
     "ftwa_lattice_upload",
     "ftwa_fock_start", "ftwa_sample", "ftwa_sample_thermal", "ftwa_evolve_workspace_size",
-    "ftwa_evolve", "ftwa_evolve_check",
+    "ftwa_evolve", "ftwa_evolve_check", "ftwa_evolve_static",
     "ftwa_observables", "ftwa_unpack", "ftwa_adjoint_workspace_size", "ftwa_adjoint",
     "ftwa_evolve_graph", "ftwa_graph_launch", "ftwa_graph_check", "ftwa_graph_free",
     "ftwa_autotune_workspace_size", "ftwa_autotune", "ftwa_last_error",
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
         "ftwa_evolve": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp, ctypes.c_size_t,
                          vp], i32),
         "ftwa_evolve_check": ([vp, vp], i32),
+        "ftwa_evolve_static": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp], i32),
         "ftwa_observables": ([i32, i64, i32, vp, vp, vp, vp, vp, vp], i32),
         "ftwa_unpack": ([i32, i64, i32, vp, vp, vp], i32),
         "ftwa_evolve_graph": ([P(Instance), i32, dbl, i64, i32, i32, P(Tuning), vp,
@@ -264,7 +265,18 @@ def ftwa_evolve(insts, dt: float, n_steps: int, record_every: int, dtype: str, w
 
 
 def ftwa_evolve_check(workspace, stream=None) -> None:
+    """workspace None: the last ftwa_evolve_static run on the current device."""
     check(load().ftwa_evolve_check(_ptr(workspace), _stream(stream)), "ftwa_evolve_check")
+
+
+def ftwa_evolve_static(insts, dt: float, n_steps: int, record_every: int, dtype: str,
+                       path: str = "auto", traj_chunk: int = 0, stream=None,
+                       config: int = -1) -> None:
+    arr = _instances(insts)
+    tune = _tuning(path, traj_chunk, None, config)
+    check(load().ftwa_evolve_static(arr, len(insts), float(dt), int(n_steps), int(record_every),
+                                    DTYPE[dtype], ctypes.byref(tune), _stream(stream)),
+          "ftwa_evolve_static")
 
 
 def ftwa_observables(n_sites: int, M: int, n_rec: int, S1, S2, n_out, C_out=None, g2_out=None,

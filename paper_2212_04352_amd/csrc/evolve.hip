@@ -555,6 +555,34 @@ ftwa_status check_status(const char* ws, hipStream_t stream) {
     return FTWA_OK;
 }
 
+// ---------------------------------------------------------------- static workspace
+// The workspace of ftwa_evolve_static: a fixed array in device memory that
+// the code object brings with it (each device the library runs on holds its
+// own copy until the process ends).  Its name is only a host-side stand-in:
+// host code uses the device address hipGetSymbolAddress returns, kept per
+// device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;  // device ordinal -> address of its copy
+
+// The address of the current device's copy, looked up once per device.
+ftwa_status static_scratch(char** out) {
+    int dev = 0;
+    FTWA_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        FTWA_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(FTWA_EHIP, "hipGetSymbolAddress returned no address");
+        it = g_scratch_ptr.emplace(dev, static_cast<char*>(ptr)).first;
+    }
+    *out = it->second;
+    return FTWA_OK;
+}
+
 // ---------------------------------------------------------------- tuning table
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int64_t, int>, int> g_tuned;
@@ -701,8 +729,37 @@ ftwa_status ftwa_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
 }
 
 ftwa_status ftwa_evolve_check(const void* workspace, void* stream) {
-    if (!workspace) return fail(FTWA_EINVAL, "ftwa_evolve_check: NULL workspace");
+    if (!workspace) {
+        // the last ftwa_evolve_static run on the current device
+        char* ptr = nullptr;
+        ftwa_status st = static_scratch(&ptr);
+        if (st != FTWA_OK) return st;
+        return check_status(ptr, (hipStream_t)stream);
+    }
     return check_status(static_cast<const char*>(workspace), (hipStream_t)stream);
+}
+
+ftwa_status ftwa_evolve_static(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
+                               int record_every, ftwa_dtype dtype, const ftwa_tuning* tune,
+                               void* stream_) {
+    ftwa_status st = check_instances(inst, n_inst, true, "ftwa_evolve_static");
+    if (st != FTWA_OK) return st;
+    if (tune && tune->kernel_ms)
+        return fail(FTWA_EINVAL, "ftwa_evolve_static: kernel timing is not available");
+    Plan plan;
+    if ((st = plan_evolve(inst, n_inst, dt, n_steps, record_every, dtype, tune, &plan)) != FTWA_OK)
+        return st;
+    if (plan.total > kStaticScratchBytes)
+        return fail(FTWA_EINVAL, "ftwa_evolve_static: this run needs " + std::to_string(plan.total) +
+                                     " bytes of workspace, more than the static " +
+                                     std::to_string(kStaticScratchBytes) +
+                                     " (use ftwa_evolve with a workspace, or fewer trajectories "
+                                     "per call)");
+    char* ws = nullptr;
+    if ((st = static_scratch(&ws)) != FTWA_OK) return st;
+    if ((st = build_table(plan, inst, ws)) != FTWA_OK) return st;
+    KernelTimer off(false);
+    return execute(plan, inst, ws, (hipStream_t)stream_, off, true);
 }
 
 ftwa_status ftwa_evolve_graph(const ftwa_instance* inst, int n_inst, double dt, int64_t n_steps,
