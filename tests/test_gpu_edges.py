@@ -90,7 +90,7 @@ def test_other_bipartite_graphs(ft, orc, spec, dtype, path):
     _run(ft, orc, spec, dtype, path, M=70, n0=np.array([1.0 - sub, sub]))  # Neel-like start
 
 
-@pytest.mark.parametrize("config", [19, 20, 21], ids=["split2", "split3", "split4"])
+@pytest.mark.parametrize("config", [19, 20, 21, 22], ids=["split2", "split3", "split4", "split2w"])
 @pytest.mark.parametrize("spec", [CHAIN7, COMB, ("torus", 2, 3), ("hex", 1, 0)],
                          ids=["chain7", "comb", "torus12", "hex6"])
 def test_split_kernel_on_small_and_irregular_graphs(ft, orc, spec, config):

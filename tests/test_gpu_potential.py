@@ -133,7 +133,7 @@ def test_resident_launch_mixing_entries_with_and_without_a_potential(ft, orc):
     assert np.array_equal(unpack(_host(p2.rho), l2.N), y2.astype(np.complex64))
 
 
-@pytest.mark.parametrize("kind,a,b,config", [("hex", 5, 0, 19), ("hex", 5, 0, 20), ("hex", 5, 0, 21),
+@pytest.mark.parametrize("kind,a,b,config", [("hex", 5, 0, 19), ("hex", 5, 0, 20), ("hex", 5, 0, 21), ("hex", 5, 0, 22),
                                              ("armchair", 10, 20, 20), ("armchair", 10, 20, 21)])
 def test_potential_on_the_split_kernel(ft, orc, kind, a, b, config):
     """FP64 at 150 and 198 sites: the split kernel's potential variant (the

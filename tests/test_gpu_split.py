@@ -14,6 +14,7 @@ from tests._util import pack, unpack
 pytestmark = pytest.mark.gpu
 
 SPLIT2, SPLIT3, SPLIT4 = 19, 20, 21  # configurations (FP64): 2, 3 and 4 workgroups per spin block
+SPLIT2W = 22  # two workgroups of 768 threads
 
 
 @pytest.fixture(scope="module")
@@ -54,7 +55,8 @@ def _run(ft, orc, kind, a, b, config, M, steps, re, U=3.3, t=1.0, seed=11, start
 @pytest.mark.parametrize("kind,a,b,config", [("hex", 4, 0, SPLIT2), ("hex", 4, 0, SPLIT3),
                                              ("hex", 4, 0, SPLIT4), ("torus", 3, 9, SPLIT2),
                                              ("hex", 5, 0, SPLIT2), ("hex", 5, 0, SPLIT3),
-                                             ("hex", 5, 0, SPLIT4),
+                                             ("hex", 5, 0, SPLIT4), ("hex", 4, 0, SPLIT2W),
+                                             ("hex", 5, 0, SPLIT2W), ("torus", 3, 9, SPLIT2W),
                                              ("armchair", 10, 20, SPLIT3),
                                              ("armchair", 10, 20, SPLIT4)])
 def test_split_matches_oracle(ft, orc, kind, a, b, config):
