@@ -365,6 +365,8 @@ struct AdjointLayout {
     // state (when a resident configuration fits): their workspace and moments
     bool resident = false;
     size_t off_ev = 0, ev_bytes = 0, off_s1 = 0, off_s2 = 0;
+    // the reverse sweep on chip (reverse_resident; -1: per-stage stream launches)
+    int rev_config = -1;
 };
 
 // The instance of a stored-state run over Mc trajectories starting at `rho`
@@ -431,6 +433,7 @@ ftwa_status plan_adjoint(const ftwa_instance* inst, int64_t n_steps, int record_
         a.off_s1 = off; off = align_up(off + (size_t)n_rec * D * sizeof(double));
         a.off_s2 = off; off = align_up(off + (size_t)n_rec * s2_count(D) * sizeof(double));
     }
+    if (a.resident && a.n_ckpt > 0) a.rev_config = reverse_resident_config(N, dtype);
     a.total = off;
     *out = a;
     return FTWA_OK;
@@ -516,6 +519,39 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
         }
 
         // ---- reverse sweep
+        if (lay.rev_config >= 0 && tab.rdesc) {
+            // on chip, one launch per segment (last first)
+            if ((st = zero_fill(partial, 2 * Mc, stream)) != FTWA_OK) return st;
+            ReverseSegment rs;
+            rs.N = N;
+            rs.record_every = record_every;
+            rs.Mc = Mc;
+            rs.Lmax = lay.L;
+            rs.n_steps = n_steps;
+            rs.desc = tab.rdesc;
+            rs.seg = st_at(lay.off_seg, 0);
+            rs.lamT = lam;
+            rs.lam_out = Lam;
+            rs.partial = partial;
+            rs.dL = dL;
+            rs.scale = scale;
+            rs.t = in.lat->t;
+            rs.U = in.U;
+            rs.dt = dt;
+            for (int64_t k = lay.n_ckpt - 1; k >= 0; --k) {
+                rs.base = k * ckpt_every;
+                rs.L = std::min<int64_t>(ckpt_every, n_steps - rs.base);
+                rs.first = k == lay.n_ckpt - 1;
+                rs.last = k == 0;
+                rs.ckpt = st_at(lay.off_ckpt, k);
+                if ((st = reverse_resident(lay.rev_config, rs, stream)) != FTWA_OK) return st;
+                FTWA_LAUNCH_CHECK("reverse_segment");
+            }
+            hipLaunchKernelGGL(final_reduce_kernel<T>, dim3((unsigned)(2 + D)), blk, 0, stream, N,
+                               P, Mc, (int64_t)1, partial, (const C*)Lam, grad);
+            FTWA_LAUNCH_CHECK("final_reduce_kernel");
+            continue;
+        }
         if ((st = zero_fill(reinterpret_cast<double*>(lam),
                             (int64_t)(state * sizeof(C) / sizeof(double)), stream)) != FTWA_OK)
             return st;

@@ -48,6 +48,8 @@ struct DeviceTables {
                                // diagonal (the sites of one sublattice, ascending,
                                // then the other's)
     SplitShape split[kMaxParts + 1];  // by part count G = 2..kMaxParts (bipartite only)
+    uint4* rdesc = nullptr;    // [2P]: stencil descriptors of the on-chip reverse sweep
+                               // (2P < 2^15 only; see reverse_descriptors)
 };
 
 // Stencil descriptor of one element for the resident kernel.  Of every pair
@@ -239,6 +241,33 @@ ftwa_status moments_accumulate(int D, int64_t Mc, int64_t n_rec, const double* X
                                double* S1, double* S2, void* scratch, hipStream_t stream);
 
 ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream);
+
+// Stencil descriptors of the on-chip reverse sweep, element e = s P + p(i, j)
+// of both spin blocks (2P < 2^15): x = c0 | c1 << 16, y = c2 | r0 << 16,
+// z = r1 | r2 << 16 with c_n the entry of rho_ik (k the n-th neighbour of j,
+// ascending) and r_n that of rho_kj (k the n-th neighbour of i); bit 15 of a
+// field: the stored element is the transpose (read its conjugate); a missing
+// neighbour reads entry 2P (a zero); w = i | j << 8 | s << 16.
+std::vector<uint4> reverse_descriptors(const ftwa_lattice_s& lat);
+
+// One checkpoint segment of the on-chip reverse sweep (adjoint_resident.hip).
+struct ReverseSegment {
+    int N;
+    int record_every;
+    int64_t Mc, L, Lmax, base, n_steps;
+    bool first, last;
+    const uint4* desc;
+    const void* ckpt;   // y_base, trajectory-innermost [2P][Mc]
+    void* seg;          // [Mc][Lmax][2P]
+    void* lamT;         // [Mc][2P]
+    void* lam_out;      // [2P][Mc] (diagonal entries, written by the last segment)
+    double* partial;    // [2][Mc]
+    const double* dL;   // [n_rec][2N]
+    double scale, t, U, dt;
+};
+// The configuration of the on-chip reverse sweep for N sites (-1: none fits).
+int reverse_resident_config(int N, ftwa_dtype dtype);
+ftwa_status reverse_resident(int config, const ReverseSegment& s, hipStream_t stream);
 ftwa_status zero_words(unsigned* p, int64_t n, hipStream_t stream);
 
 // Resident path (evolve_resident.hip).

@@ -248,6 +248,7 @@ void ftwa_free_lattice(ftwa_lattice lat) {
         (void)hipFree(tab.elem);
         if (tab.ord) (void)hipFree(tab.ord);
         if (tab.dpos) (void)hipFree(tab.dpos);
+        if (tab.rdesc) (void)hipFree(tab.rdesc);
     }
     for (auto& [key, ptr] : lat->padded) {
         if (hipSetDevice(std::get<0>(key)) != hipSuccess) continue;
@@ -914,6 +915,33 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
     return FTWA_OK;
 }
 
+std::vector<uint4> reverse_descriptors(const ftwa_lattice_s& lat) {
+    const int N = lat.N;
+    const int64_t P = packed_count(N), E = 2 * P;
+    std::vector<uint4> out((size_t)E);
+    auto entry = [&](int s, int a, int b) -> uint32_t {
+        const int i = std::min(a, b), j = std::max(a, b);
+        return (uint32_t)(s * P + packed_row(N, i) + (j - i)) | (a > b ? 0x8000u : 0u);
+    };
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < N; ++i)
+            for (int j = i; j < N; ++j) {
+                uint32_t f[6];
+                for (int n = 0; n < kMaxDeg; ++n) {
+                    const int kc = n < lat.deg[j] ? lat.nbr[(size_t)j * kMaxDeg + n] : -1;
+                    const int kr = n < lat.deg[i] ? lat.nbr[(size_t)i * kMaxDeg + n] : -1;
+                    f[n] = kc < 0 ? (uint32_t)E : entry(s, i, kc);
+                    f[3 + n] = kr < 0 ? (uint32_t)E : entry(s, kr, j);
+                }
+                uint4& d = out[(size_t)(s * P + packed_row(N, i) + (j - i))];
+                d.x = f[0] | f[1] << 16;
+                d.y = f[2] | f[3] << 16;
+                d.z = f[4] | f[5] << 16;
+                d.w = (uint32_t)i | (uint32_t)j << 8 | (uint32_t)s << 16;
+            }
+    return out;
+}
+
 ftwa_status upload_tables(ftwa_lattice lat) {
     int dev = 0;
     FTWA_HIP_TRY(hipGetDevice(&dev));
@@ -938,6 +966,12 @@ ftwa_status upload_tables(ftwa_lattice lat) {
                                hipMemcpyHostToDevice));
         FTWA_HIP_TRY(hipMalloc(&tab.dpos, dpos.size() * sizeof(int32_t)));
         FTWA_HIP_TRY(hipMemcpy(tab.dpos, dpos.data(), dpos.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice));
+    }
+    if (2 * P + 1 <= 0x7fff) {
+        const std::vector<uint4> rd = reverse_descriptors(*lat);
+        FTWA_HIP_TRY(hipMalloc(&tab.rdesc, rd.size() * sizeof(uint4)));
+        FTWA_HIP_TRY(hipMemcpy(tab.rdesc, rd.data(), rd.size() * sizeof(uint4),
                                hipMemcpyHostToDevice));
     }
     FTWA_HIP_TRY(hipMalloc(&tab.nb, nb.size() * sizeof(int32_t)));

@@ -53,6 +53,7 @@ def _oracle_w(orc, olat, rho0, dt, ns, re, U):
 @pytest.mark.parametrize("kind,a,b,start,M,steps,ckpt", [
     ("torus", 2, 3, "neel", 24, 60, 7),     # ragged last segment
     ("hex", 2, 0, "random", 17, 40, 40),    # degree-2 edge sites, one segment
+    ("torus", 3, 9, "random", 6, 20, 7),    # the 54-site gradient lattice
     # 150 sites: FP32 recomputes checkpoints and segments with the spin-split
     # resident kernel, FP64 with the two-part split kernel
     ("hex", 5, 0, "neel", 4, 12, 5),
@@ -72,6 +73,19 @@ def test_adjoint_matches_oracle_gradient(ft, orc, dtype, kind, a, b, start, M, s
     # rho(0) is an input only
     cdt = np.complex128 if dtype == "f64" else np.complex64
     assert np.array_equal(prob.rho.cpu().numpy(), pack(rho0.astype(cdt)))
+
+
+def test_adjoint_is_deterministic(ft, orc):
+    """Two runs of the same gradient give the same bits (every sum has a
+    fixed order), on the on-chip reverse sweep at 54 sites."""
+    import torch
+    dt, ns, re = 0.01, 30, 10
+    olat, rho0, prob = _setup(ft, orc, "torus", 3, 9, "random", 5, 9, "f32")
+    w = torch.from_numpy(np.random.default_rng(3).standard_normal((ns // re + 1, 2 * olat.N))).cuda()
+    g1, _ = ft.adjoint(prob, dt, ns, re, 8, w)
+    g2, _ = ft.adjoint(prob, dt, ns, re, 8, w)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
 
 
 def test_adjoint_trajectory_chunks_agree(ft, orc):
