@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -56,6 +58,8 @@ def parse():
                     help="RK4 steps of the FP64 comparison run (default: full horizon)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint-checks", action="store_true",
+                    help="adjoint workload: skip the FP64 gradient and finite-difference report")
     ap.add_argument("--cpu-traj", type=int, default=96)
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--workload", default="flake198",
@@ -358,6 +362,8 @@ def run_adjoint(args):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     work = W.n_traj * steps
+    g32 = np.concatenate([[float(gU), float(gt)], gd.detach().cpu().numpy()])
+    checks = {} if args.no_adjoint_checks else adjoint_checks(W, lat, steps, g32)
     print(json.dumps({
         "metric": "adjoint gradient, 54-site torus",
         "forward_seconds": t1 - t0, "backward_seconds": t2 - t1,
@@ -365,9 +371,92 @@ def run_adjoint(args):
         "forward_value": work / (t1 - t0), "backward_value": work / (t2 - t1),
         "unit": "trajectory*RK4-steps/s", "dtype": "f32 state, f64 gradient sums",
         "loss": float(loss.detach()), "dL_dU": float(gU), "dL_dt": float(gt),
-        "dL_ddelta_norm": float(gd.norm()),
+        "dL_ddelta_norm": float(gd.norm()), **checks,
         "config": {"workload": W.name, "trajectories": W.n_traj, "rk4_steps": steps,
                    "dt": W.dt, "ckpt_every": 50, "U_eval": W.U, "U_target": 3.3}}))
+
+
+def _occupation_grad(W, lat, steps, dtype, U_eval, t_eval=None, delta=None):
+    """(loss, [dL/dU, dL/dt, dL/ddelta]) of the gradient workload's loss in
+    `dtype`, target from the U/t = 3.3 run in the same dtype."""
+    import torch
+    from paper_2212_04352_amd.autodiff import OccupationSpec, occupations
+    spec = OccupationSpec(W.kind, W.a, W.b, lat.fock_start(W.start, W.seed), seed=W.seed,
+                          n_traj=W.n_traj, dt=W.dt, n_steps=steps,
+                          record_every=W.record_every, dtype=dtype, ckpt_every=50)
+    f64 = torch.float64
+    dev = torch.device("cuda")
+    zero = torch.zeros((2, lat.N), dtype=f64, device=dev)
+    with torch.no_grad():
+        target = occupations(torch.tensor(3.3, dtype=f64), torch.tensor(W.t_hop, dtype=f64),
+                             zero, spec)
+    U = torch.tensor(U_eval, dtype=f64, requires_grad=True)
+    t = torch.tensor(W.t_hop if t_eval is None else t_eval, dtype=f64, requires_grad=True)
+    d = torch.zeros(lat.N, dtype=f64, device=dev) if delta is None else delta.clone()
+    d.requires_grad_(True)
+    loss = torch.sum((occupations(U, t, d.expand(2, lat.N), spec) - target) ** 2)
+    gU, gt, gd = torch.autograd.grad(loss, (U, t, d))
+    return float(loss.detach()), np.concatenate([[float(gU), float(gt)],
+                                                 gd.detach().cpu().numpy()])
+
+
+def adjoint_checks(W, lat, steps, g32):
+    """The accuracy report of the gradient workload: the FP32 gradient against
+    the FP64 one at the full size and horizon (reported, not asserted: at
+    T = 20 the chaotic sensitivity amplifies rounding), and central finite
+    differences (h = 1e-6, FP64) of the loss against the FP64 adjoint at
+    T = 5 along U, t and one random direction of the per-site offsets."""
+    import torch
+    _, g64 = _occupation_grad(W, lat, steps, "f64", W.U)
+    scale = float(np.max(np.abs(g64)))
+    out = {"fp32_vs_fp64_adjoint": {
+        "T": steps * W.dt, "max_abs_diff_over_max_abs": float(np.max(np.abs(g32 - g64))) / scale,
+        "dL_dU": [float(g32[0]), float(g64[0])], "dL_dt": [float(g32[1]), float(g64[1])],
+        "rel_dU": abs(g32[0] - g64[0]) / abs(g64[0]), "rel_dt": abs(g32[1] - g64[1]) / abs(g64[1]),
+        "rel_ddelta_norm": float(np.linalg.norm(g32[2:] - g64[2:]) / np.linalg.norm(g64[2:]))}}
+    s5 = min(steps, 500)
+    _, g = _occupation_grad(W, lat, s5, "f64", W.U)
+    h = 1e-6
+    v = np.random.default_rng(W.seed).standard_normal(lat.N)
+    vt = torch.from_numpy(v).cuda()
+
+    spec5, target5 = _fd_setup(W, lat, s5)
+
+    def L(dU=0.0, dt=0.0, dd=0.0):
+        with torch.no_grad():
+            return _fd_loss(spec5, target5, lat, W.U + dU, W.t_hop + dt, dd * vt)
+    fd = [(L(dU=h) - L(dU=-h)) / (2 * h), (L(dt=h) - L(dt=-h)) / (2 * h),
+          (L(dd=h) - L(dd=-h)) / (2 * h)]
+    ad = [g[0], g[1], float(np.dot(g[2:], v))]
+    out["finite_difference_fp64"] = {
+        "T": s5 * W.dt, "h": h, "directions": ["U", "t", "random offset direction"],
+        "adjoint": ad, "central_difference": fd,
+        "rel_err": [abs(a - f) / max(abs(a), 1e-300) for a, f in zip(ad, fd)]}
+    return out
+
+
+def _fd_setup(W, lat, steps):
+    """FP64 occupation spec of the finite-difference check and its target."""
+    import torch
+    from paper_2212_04352_amd.autodiff import OccupationSpec, occupations
+    spec = OccupationSpec(W.kind, W.a, W.b, lat.fock_start(W.start, W.seed), seed=W.seed,
+                          n_traj=W.n_traj, dt=W.dt, n_steps=steps,
+                          record_every=W.record_every, dtype="f64", ckpt_every=50)
+    f64 = torch.float64
+    zero = torch.zeros((2, lat.N), dtype=f64, device=torch.device("cuda"))
+    with torch.no_grad():
+        target = occupations(torch.tensor(3.3, dtype=f64), torch.tensor(W.t_hop, dtype=f64),
+                             zero, spec)
+    return spec, target
+
+
+def _fd_loss(spec, target, lat, U, t, delta):
+    import torch
+    from paper_2212_04352_amd.autodiff import occupations
+    f64 = torch.float64
+    nbar = occupations(torch.tensor(U, dtype=f64), torch.tensor(t, dtype=f64),
+                       delta.expand(2, lat.N), spec)
+    return float(torch.sum((nbar - target) ** 2))
 
 
 def run_sizes(args):
