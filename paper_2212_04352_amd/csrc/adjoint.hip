@@ -519,7 +519,7 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
         }
 
         // ---- reverse sweep
-        if (lay.rev_config >= 0 && tab.rdesc) {
+        if (lay.rev_config >= 0) {
             // on chip, one launch per segment (last first)
             if ((st = zero_fill(partial, 2 * Mc, stream)) != FTWA_OK) return st;
             ReverseSegment rs;
@@ -529,6 +529,7 @@ ftwa_status adjoint_impl(const ftwa_instance& in, const DeviceTables& tab, const
             rs.Lmax = lay.L;
             rs.n_steps = n_steps;
             rs.desc = tab.rdesc;
+            rs.desc_full = tab.rdescf;
             rs.seg = st_at(lay.off_seg, 0);
             rs.lamT = lam;
             rs.lam_out = Lam;

@@ -48,8 +48,9 @@ struct DeviceTables {
                                // diagonal (the sites of one sublattice, ascending,
                                // then the other's)
     SplitShape split[kMaxParts + 1];  // by part count G = 2..kMaxParts (bipartite only)
-    uint4* rdesc = nullptr;    // [2P]: stencil descriptors of the on-chip reverse sweep
-                               // (2P < 2^15 only; see reverse_descriptors)
+    uint4* rdesc = nullptr;    // [2P][2]: descriptors of the on-chip reverse sweep with a
+                               // packed X (N <= kReverseMaxSites; see reverse_descriptors)
+    uint4* rdescf = nullptr;   // [2P][2]: the same with a full X (N <= kReverseFullMaxSites)
 };
 
 // Stencil descriptor of one element for the resident kernel.  Of every pair
@@ -242,13 +243,21 @@ ftwa_status moments_accumulate(int D, int64_t Mc, int64_t n_rec, const double* X
 
 ftwa_status zero_fill(double* p, int64_t n, hipStream_t stream);
 
-// Stencil descriptors of the on-chip reverse sweep, element e = s P + p(i, j)
-// of both spin blocks (2P < 2^15): x = c0 | c1 << 16, y = c2 | r0 << 16,
-// z = r1 | r2 << 16 with c_n the entry of rho_ik (k the n-th neighbour of j,
-// ascending) and r_n that of rho_kj (k the n-th neighbour of i); bit 15 of a
-// field: the stored element is the transpose (read its conjugate); a missing
-// neighbour reads entry 2P (a zero); w = i | j << 8 | s << 16.
-std::vector<uint4> reverse_descriptors(const ftwa_lattice_s& lat);
+// Descriptors of the on-chip reverse sweep: a pair (q0, q1) per element
+// e = s P + p(i, j) of both spin blocks, in that order.  X is the LDS copy of
+// a state: packed (entry e; full = false) or the full matrices of both spins
+// (entry (s N + a) N + b for element (a, b) of spin s; full = true); W is
+// always full.  q0: x = c0 | c1 << 16, y = c2 | r0 << 16, z = r1 | r2 << 16,
+// with c_n the X entry of rho_ik (k the n-th neighbour of j, ascending) and r_n
+// that of rho_kj (k the n-th neighbour of i); packed: bit 15 of a field marks a
+// stored transpose (read its conjugate); a missing neighbour reads the zero
+// entry after the last; w = yi | yj << 16, the entries (1 - s) N + i and
+// (1 - s) N + j of the other spin's diagonal in a [2N] row.  q1: x = X entry
+// of the element | of its transpose << 16 (packed: e twice), y = W entry of
+// the element | of its transpose << 16, z = s N + i | (i == j) << 16, w = e.
+constexpr int kReverseMaxSites = 180;      // packed X entries < 2^15, W entries < 2^16
+constexpr int kReverseFullMaxSites = 64;   // full X: beyond this it no longer fits LDS
+std::vector<uint4> reverse_descriptors(const ftwa_lattice_s& lat, bool full);
 
 // One checkpoint segment of the on-chip reverse sweep (adjoint_resident.hip).
 struct ReverseSegment {
@@ -256,7 +265,8 @@ struct ReverseSegment {
     int record_every;
     int64_t Mc, L, Lmax, base, n_steps;
     bool first, last;
-    const uint4* desc;
+    const uint4* desc;       // the packed-X and full-X descriptor tables
+    const uint4* desc_full;
     const void* ckpt;   // y_base, trajectory-innermost [2P][Mc]
     void* seg;          // [Mc][Lmax][2P]
     void* lamT;         // [Mc][2P]

@@ -249,6 +249,7 @@ void ftwa_free_lattice(ftwa_lattice lat) {
         if (tab.ord) (void)hipFree(tab.ord);
         if (tab.dpos) (void)hipFree(tab.dpos);
         if (tab.rdesc) (void)hipFree(tab.rdesc);
+        if (tab.rdescf) (void)hipFree(tab.rdescf);
     }
     for (auto& [key, ptr] : lat->padded) {
         if (hipSetDevice(std::get<0>(key)) != hipSuccess) continue;
@@ -915,29 +916,39 @@ ftwa_status device_tables(ftwa_lattice lat, DeviceTables* out) {
     return FTWA_OK;
 }
 
-std::vector<uint4> reverse_descriptors(const ftwa_lattice_s& lat) {
+std::vector<uint4> reverse_descriptors(const ftwa_lattice_s& lat, bool full) {
     const int N = lat.N;
     const int64_t P = packed_count(N), E = 2 * P;
-    std::vector<uint4> out((size_t)E);
-    auto entry = [&](int s, int a, int b) -> uint32_t {
+    const uint32_t zero = full ? (uint32_t)(2 * N * N) : (uint32_t)E;
+    std::vector<uint4> out((size_t)(2 * E));
+    auto x_entry = [&](int s, int a, int b) -> uint32_t {  // element (a, b) of spin s
+        if (full) return (uint32_t)((s * N + a) * N + b);
         const int i = std::min(a, b), j = std::max(a, b);
         return (uint32_t)(s * P + packed_row(N, i) + (j - i)) | (a > b ? 0x8000u : 0u);
     };
     for (int s = 0; s < 2; ++s)
         for (int i = 0; i < N; ++i)
             for (int j = i; j < N; ++j) {
+                const int64_t e = s * P + packed_row(N, i) + (j - i);
                 uint32_t f[6];
                 for (int n = 0; n < kMaxDeg; ++n) {
                     const int kc = n < lat.deg[j] ? lat.nbr[(size_t)j * kMaxDeg + n] : -1;
                     const int kr = n < lat.deg[i] ? lat.nbr[(size_t)i * kMaxDeg + n] : -1;
-                    f[n] = kc < 0 ? (uint32_t)E : entry(s, i, kc);
-                    f[3 + n] = kr < 0 ? (uint32_t)E : entry(s, kr, j);
+                    f[n] = kc < 0 ? zero : x_entry(s, i, kc);
+                    f[3 + n] = kr < 0 ? zero : x_entry(s, kr, j);
                 }
-                uint4& d = out[(size_t)(s * P + packed_row(N, i) + (j - i))];
-                d.x = f[0] | f[1] << 16;
-                d.y = f[2] | f[3] << 16;
-                d.z = f[4] | f[5] << 16;
-                d.w = (uint32_t)i | (uint32_t)j << 8 | (uint32_t)s << 16;
+                const uint32_t so = (uint32_t)((1 - s) * N);
+                uint4& q0 = out[(size_t)(2 * e)];
+                q0.x = f[0] | f[1] << 16;
+                q0.y = f[2] | f[3] << 16;
+                q0.z = f[4] | f[5] << 16;
+                q0.w = (so + i) | (so + j) << 16;
+                uint4& q1 = out[(size_t)(2 * e + 1)];
+                q1.x = full ? x_entry(s, i, j) | x_entry(s, j, i) << 16
+                            : (uint32_t)e | (uint32_t)e << 16;
+                q1.y = (uint32_t)((s * N + i) * N + j) | (uint32_t)((s * N + j) * N + i) << 16;
+                q1.z = (uint32_t)(s * N + i) | (i == j ? 1u << 16 : 0u);
+                q1.w = (uint32_t)e;
             }
     return out;
 }
@@ -968,11 +979,12 @@ ftwa_status upload_tables(ftwa_lattice lat) {
         FTWA_HIP_TRY(hipMemcpy(tab.dpos, dpos.data(), dpos.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice));
     }
-    if (2 * P + 1 <= 0x7fff) {
-        const std::vector<uint4> rd = reverse_descriptors(*lat);
-        FTWA_HIP_TRY(hipMalloc(&tab.rdesc, rd.size() * sizeof(uint4)));
-        FTWA_HIP_TRY(hipMemcpy(tab.rdesc, rd.data(), rd.size() * sizeof(uint4),
-                               hipMemcpyHostToDevice));
+    for (int full = 0; full < 2; ++full) {
+        if (N > (full ? kReverseFullMaxSites : kReverseMaxSites)) continue;
+        const std::vector<uint4> rd = reverse_descriptors(*lat, full != 0);
+        uint4*& dst = full ? tab.rdescf : tab.rdesc;
+        FTWA_HIP_TRY(hipMalloc(&dst, rd.size() * sizeof(uint4)));
+        FTWA_HIP_TRY(hipMemcpy(dst, rd.data(), rd.size() * sizeof(uint4), hipMemcpyHostToDevice));
     }
     FTWA_HIP_TRY(hipMalloc(&tab.nb, nb.size() * sizeof(int32_t)));
     FTWA_HIP_TRY(hipMalloc(&tab.off, off.size() * sizeof(int32_t)));
