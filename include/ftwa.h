@@ -467,10 +467,15 @@ ftwa_status ftwa_adjoint_workspace_size(const ftwa_instance* inst, int64_t n_ste
  *                 workspace and give the same result up to the order of the
  *                 final FP64 sums.
  * When a resident configuration fits the lattice and dtype, the checkpoints
- * and every segment's states come from resident runs that store their state
- * (the workspace also holds their plan, and each run synchronises `stream`
- * once on the host); otherwise from per-stage stream launches.  The
- * trajectories and the gradient are the same either way.
+ * come from one resident run that stores its state (the workspace also holds
+ * its plan; the run synchronises `stream` once on the host), and, for up to
+ * 71 sites in FP32 and 54 in FP64, the reverse sweep runs on chip: one
+ * launch per segment, one workgroup per trajectory, which recomputes the
+ * segment's states from its checkpoint and then runs the transposed stages
+ * with the cotangent in registers.  Otherwise the segments and the reverse
+ * sweep are per-stage stream launches.  The trajectories are the same either
+ * way; the gradient agrees to rounding (the on-chip sweep forms some products
+ * and row sums in the working precision).
  * Errors: FTWA_EINVAL (sizes, NULL pointers, workspace too small),
  * FTWA_EHIP on launch failure, FTWA_ETIMEOUT (a spin-split resident run's
  * bounded wait gave up).
