@@ -74,6 +74,9 @@ def parse():
                          "a time-dependent staggered potential on the 198-site flake; "
                          "longrange: a general density-density interaction on the same; "
                          "peierls: complex time-dependent hopping (a field pulse) on the same")
+    ap.add_argument("--sizes", default=None,
+                    help="sizes workload: comma-separated site counts to run (default: all of "
+                         "12, 54, 96, 150, 198)")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-traj", type=int, default=2048)
     ap.add_argument("--sequential", action="store_true",
@@ -464,8 +467,11 @@ def run_sizes(args):
     import torch
     import paper_2212_04352_amd as ft
     rows = []
-    for kind, a, b in [("torus", 2, 3), ("torus", 3, 9), ("hex", 4, 0), ("hex", 5, 0),
-                       ("armchair", 10, 20)]:
+    wanted = {int(x) for x in args.sizes.split(",")} if args.sizes else None
+    for kind, a, b, n in [("torus", 2, 3, 12), ("torus", 3, 9, 54), ("hex", 4, 0, 96),
+                          ("hex", 5, 0, 150), ("armchair", 10, 20, 198)]:
+        if wanted is not None and n not in wanted:
+            continue
         lat = ft.Lattice(kind, a, b)
         for dtype in ("f32", "f64"):
             M = 16384 if lat.N <= 54 else 8192

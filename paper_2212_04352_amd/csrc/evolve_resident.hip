@@ -1374,12 +1374,17 @@ const Config kConfigs[] = {
     // two parts of 768 threads (three waves per SIMD): 12 % faster than 512
     // threads at N = 150; at three and four parts the extra waves spill
     FTWA_SPLIT_CFG(double, FTWA_F64, 2, 768, 4, 4, 3, 1, 1, 1, 2, 1, true),
+    // FP64 shared-block tiles of 384 threads x 2 units with (2, 2) slots: the
+    // same 768 entries per class as 256 x (3, 3), with two thirds of its
+    // registers per thread (the wider tiles spill in FP64)
+    FTWA_RES_CFG(double, FTWA_F64, 2, 384, 2, 2, 2, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 384, 2, 2, 2, 2, 2),
 };
 
 // Order of preference of the first-fit choice (a tile with fewer general
 // slots before the same tile with more; indices are those of kConfigs).
-const int kPreference[] = {0, 13, 1, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11, 12,
-                           22, 19, 20, 21};
+const int kPreference[] = {0, 13, 1, 23, 24, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11,
+                           12, 22, 19, 20, 21};
 static_assert(sizeof(kPreference) == sizeof(kConfigs) / sizeof(kConfigs[0]) * sizeof(int),
               "every configuration has a place in the preference order");
 

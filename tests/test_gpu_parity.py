@@ -198,6 +198,8 @@ def test_errors_are_reported(ft):
     ("f32", "armchair", 10, 20, 3.3, 12, 12, 12, 1.0),  # spin split, every slot general
     ("f32", "torus", 3, 9, 3.3, 70, 60, 6, 1.0),        # shared-block tiles, every slot general
     ("f64", "hex", 4, 0, 2.0, 10, 20, 3, 1.0),
+    ("f64", "torus", 3, 9, 3.3, 70, 60, 23, 1.0),       # FP64 384 x 2 tiles (one general slot,
+    ("f64", "torus", 3, 9, 3.3, 70, 60, 24, 1.0),       # every slot general), ragged items
     ("f64", "torus", 2, 3, 3.3, 130, 200, -1, 0.6),     # hopping t != 1 (general kernels)
     ("f32", "hex", 2, 0, 1.7, 33, 40, -1, 1.3),
     ("f32", "armchair", 10, 20, 3.3, 12, 12, -1, 0.8),
