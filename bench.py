@@ -319,6 +319,35 @@ def run_batch(args):
                       "sites": sorted(set(p.lat.N for p in probs)),
                       "configurations": sorted(set(cfgs))}}
     g.close()
+    # per configuration group: its instances alone through one ftwa_evolve,
+    # kernel time by HIP events, and the byte-equivalent rate of its state
+    # traffic (one read and one write of both FP32 spin blocks per
+    # trajectory-step) against 8 TB/s
+    groups = {}
+    for p, c in zip(probs, cfgs):
+        groups.setdefault(c, []).append(p)
+    rows, total_bytes = [], 0.0
+    for c, ps in sorted(groups.items()):
+        for p in ps:
+            ft.sample(p, BATCH_SEED)
+        timing = ft.new_timing()
+        torch.cuda.synchronize()
+        ft.evolve(ps, 0.01, steps, 10, timing=timing)
+        torch.cuda.synchronize()
+        ms = timing["ms"].value
+        gbytes = sum(p.n_traj * 2 * 2 * p.lat.N ** 2 * 4 for p in ps) * steps
+        total_bytes += gbytes
+        rows.append({"configuration": c, "instances": len(ps),
+                     "sites": sorted(set(p.lat.N for p in ps)),
+                     "trajectories": sum(p.n_traj for p in ps), "kernel_ms": ms,
+                     "trajectory_steps_per_s": sum(p.n_traj for p in ps) * steps / (ms * 1e-3),
+                     "byte_equivalent_GBps": gbytes / (ms * 1e-3) / 1e9})
+    out["groups"] = rows
+    out["roofline"] = {"bound": "hbm", "achieved": total_bytes / el / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": total_bytes / el / 1e9 / HBM_PEAK_GBS,
+                       "note": "byte-equivalent rate of the batch's algorithmic state traffic "
+                               "over the graph launch (the resident kernels keep the state on "
+                               "chip)"}
     if args.sequential:
         for p in probs:
             ft.sample(p, BATCH_SEED)
