@@ -680,8 +680,10 @@ def run_peierls(args):
     """Complex time-dependent hopping on the 198-site flake: a field pulse
     j_ik(tau) = t exp(i (x_k - x_i) B(tau)), x the graph distance from site 0
     (a stand-in for the coordinate along the field), B(tau) = 0.5 sin(2 tau),
-    tables at half steps; FP32 and FP64 on the stream kernels, 4096
-    trajectories x 400 steps, next to real hopping on the same kernels."""
+    tables at half steps; FP32 and FP64, 4096 trajectories x 400 steps, on the
+    stream kernels and on the automatic path (FP32: the spin-split resident
+    kernel's complex-hopping variant; FP64: the stream kernels, the split
+    kernel has none), next to real hopping on the same paths."""
     import numpy as np
     import torch
     from collections import deque
@@ -710,27 +712,31 @@ def run_peierls(args):
     w[:, np.arange(3)[None, :] >= lat.deg[:, None]] = 0
     rows = []
     for dtype in ("f32", "f64"):
-        for peierls in (False, True):
-            p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
-            if peierls:
-                p.hop_w = torch.from_numpy(np.ascontiguousarray(w)).cuda()
-            ft.sample(p, 5)
-            ws = ft.evolve(p, dt, 2, 1, path="stream")
-            ft.sample(p, 5)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ft.evolve(p, dt, steps, 10, path="stream", workspace=ws)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            rows.append({"dtype": dtype, "hopping": "complex" if peierls else "real",
-                         "value": M * steps / el})
-            log(f"peierls: {dtype} complex={peierls}: {M * steps / el:.3e} traj-steps/s")
-            del p, ws
+        for path in ("stream", "auto"):
+            for peierls in (False, True):
+                p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
+                if peierls:
+                    p.hop_w = torch.from_numpy(np.ascontiguousarray(w)).cuda()
+                ft.sample(p, 5)
+                ws = ft.evolve(p, dt, steps, 10, path=path)  # warm-up, workspace
+                ft.sample(p, 5)
+                timing = ft.new_timing()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ft.evolve(p, dt, steps, 10, path=path, workspace=ws, timing=timing)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                rows.append({"dtype": dtype, "path": path,
+                             "hopping": "complex" if peierls else "real",
+                             "value": M * steps / el,
+                             "kernel_value": timing["work"].value / (timing["ms"].value * 1e-3)})
+                log(f"peierls: {dtype} {path} complex={peierls}: {M * steps / el:.3e} traj-steps/s")
+                del p, ws
     print(json.dumps({
         "metric": "trajectory*RK4-steps/s with complex time-dependent hopping, 198-site flake",
         "unit": "trajectory*RK4-steps/s", "rows": rows,
         "config": {"workload": "flake198_peierls", "trajectories": M, "rk4_steps": steps,
-                   "dt": dt, "path": "stream", "U": 3.3,
+                   "dt": dt, "paths": ["stream", "auto"], "U": 3.3,
                    "hopping": "t exp(i (x_k - x_i) 0.5 sin(2 tau)), x = graph distance"}}))
 
 

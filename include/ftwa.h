@@ -203,10 +203,15 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        rho_kj in f_ij = i [t (col - row) + a rho_ij], each product as
  *        (fma(wr, xr, -(wi xi)), fma(wr, xi, wi xr)) with w rounded once to
  *        the working precision, slots summed in ascending order; slots
- *        n >= deg(i) are ignored (any finite or non-finite value).  Integrated by the stream kernels (a forced
- *        resident path or configuration gives FTWA_ENOTSUP); invariant
- *        monitors (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.
- *        Combines with v_site and u_mat.  hop_w must hold
+ *        n >= deg(i) are ignored (any finite or non-finite value).
+ *        Integrated by the FP32 spin-split resident kernels' complex-hopping
+ *        variant where the automatic choice is one of them and the instance
+ *        has no v_site (the ratios, rounded once and with unused slots
+ *        zeroed, are staged by a kernel into the workspace), else by the
+ *        stream kernels; a forced resident path or configuration without the
+ *        variant, or with v_site, gives FTWA_ENOTSUP.  Invariant monitors
+ *        (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.  Combines
+ *        with v_site and u_mat on the stream kernels.  hop_w must hold
  *        (2 n_steps + 1) N 3 complex values (not checked: device memory).
  * Trajectory m of the instance has global index traj_offset + m; it keys the
  * random numbers, so any trajectory range reproduces the same trajectories.

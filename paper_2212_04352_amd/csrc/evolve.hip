@@ -82,6 +82,7 @@ struct InstPlan {
     int group = -1;
     int64_t chunk = 0;             // stream: trajectories per chunk; resident: per pass window
     size_t off_x = 0, off_inv = 0; // resident: this instance's record regions
+    size_t off_hop = 0;            // resident with complex hopping: its ratio table
 };
 
 struct LaunchDesc {                // one resident launch: a group in a pass
@@ -93,6 +94,7 @@ struct LaunchDesc {                // one resident launch: a group in a pass
     double work = 0;               // trajectory-steps
     bool unit_hop = true;          // every instance has t = 1
     bool potential = false;        // an instance carries an external potential
+    bool hopping = false;          // every instance carries complex hopping
 };
 
 struct GroupPlan {
@@ -160,7 +162,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     p.drop_partners = tune && tune->drop_partners;
 
     // ---- path and configuration of every instance
-    std::map<int, int> group_of_config;  // 2 config + (external potential)
+    std::map<int, int> group_of_config;  // 4 config + 2 (complex hopping) + (external potential)
     for (int k = 0; k < n_inst; ++k) {
         InstPlan ip;
         const DeviceTables& tab = host_tables(inst[k].lat);
@@ -180,11 +182,22 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         // a general interaction: the stream kernels only
         if (inst[k].u_mat && (want == FTWA_PATH_RESIDENT || force >= 0))
             return fail(FTWA_ENOTSUP, "a general interaction u_ij runs on the stream path only");
-        // complex hopping: the stream kernels only
-        if (inst[k].hop_w && (want == FTWA_PATH_RESIDENT || force >= 0))
-            return fail(FTWA_ENOTSUP, "complex hopping runs on the stream path only");
-        bool can_res = !tuned_stream && !inst[k].u_mat && !inst[k].hop_w &&
+        // complex hopping: the stream kernels, or a resident configuration with
+        // the complex-hopping variant (the FP32 spin split; not together with
+        // a potential)
+        const bool hop = inst[k].hop_w != nullptr;
+        if (hop && pot && (want == FTWA_PATH_RESIDENT || force >= 0))
+            return fail(FTWA_ENOTSUP,
+                        "complex hopping together with a potential runs on the stream path only");
+        bool can_res = !tuned_stream && !inst[k].u_mat && !(hop && pot) &&
                        resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
+        if (hop && can_res) {
+            // the configuration chosen for real hopping, if it has the variant
+            const int c0 = ip.res.config;
+            can_res = resident_has_hop(c0) &&
+                      resident_plan(N, dtype, tab, &ip.res, c0, inst[k].inv == nullptr, false,
+                                    true);
+        }
         if (pot && can_res) {
             // the configuration chosen without the potential, if it has the
             // potential variant (else the stream path)
@@ -193,7 +206,9 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                       resident_plan(N, dtype, tab, &ip.res, c0, inst[k].inv == nullptr, true);
         }
         if (force >= 0 && !can_res)
-            return fail(FTWA_ENOTSUP, "the forced resident configuration does not fit");
+            return fail(FTWA_ENOTSUP, hop ? "the forced resident configuration has no "
+                                            "complex-hopping variant or does not fit"
+                                          : "the forced resident configuration does not fit");
         if (want == FTWA_PATH_RESIDENT && !can_res)
             return fail(FTWA_ENOTSUP, "no resident configuration fits this lattice and dtype");
         ip.path = (want == FTWA_PATH_STREAM || !can_res) ? FTWA_PATH_STREAM : FTWA_PATH_RESIDENT;
@@ -201,7 +216,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             // instances with a potential form groups of their own: their
             // launches run the potential variant, whose LDS layout holds the
             // profile and is sized for it
-            const int key = 2 * ip.res.config + (pot ? 1 : 0);
+            const int key = 4 * ip.res.config + (hop ? 2 : 0) + (pot ? 1 : 0);
             auto it = group_of_config.find(key);
             if (it == group_of_config.end()) {
                 it = group_of_config.emplace(key, (int)p.groups.size()).first;
@@ -282,6 +297,11 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         if (ip.path != FTWA_PATH_RESIDENT) continue;
         const int D = 2 * inst[k].lat->N;
         ip.off_x = off; off = align_up(off + (size_t)p.n_rec * D * ip.chunk * sizeof(double));
+        if (inst[k].hop_w) {
+            ip.off_hop = off;
+            off = align_up(off + (size_t)(2 * p.n_steps + 1) * inst[k].lat->N * 3 *
+                                     cplx_bytes(p.dtype));
+        }
         if (inst[k].inv) {
             ip.off_inv = off;
             off = align_up(off + (size_t)p.n_rec * 4 * ip.chunk * sizeof(double));
@@ -310,6 +330,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 L.work += (double)Mc * n_steps;
                 if (inst[k].lat->t != 1.0) L.unit_hop = false;
                 if (inst[k].v_site) L.potential = true;
+                if (inst[k].hop_w) L.hopping = true;
                 ++L.n_entries;
             }
             entry += L.n_entries;
@@ -381,6 +402,7 @@ ftwa_status build_table(Plan& p, const ftwa_instance* inst, char* ws) {
                 e.dump_stride = p.dump_stride;
                 e.v_site = inst[k].v_site;
                 e.v_env = inst[k].v_env;
+                e.hop = inst[k].hop_w ? ws + ip.off_hop : nullptr;
                 p.table.push_back(e);
             }
         }
@@ -478,6 +500,16 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
         }
     }
     // ---- resident groups, pass by pass
+    // the ratio tables of the instances with complex hopping first
+    for (int k = 0; k < p.n_inst; ++k) {
+        const InstPlan& ip = p.inst[k];
+        if (ip.path != FTWA_PATH_RESIDENT || !inst[k].hop_w) continue;
+        DeviceTables tab;
+        if ((st = device_tables(inst[k].lat, &tab)) != FTWA_OK) return st;
+        if ((st = hop_table(inst[k].hop_w, tab.nb, tab.dpos, inst[k].lat->N, p.n_steps, p.dtype,
+                            ws + ip.off_hop, stream)) != FTWA_OK)
+            return st;
+    }
     const ResidentInst* table = reinterpret_cast<const ResidentInst*>(ws + p.r_table);
     for (int j = 0; j < p.n_pass; ++j) {
         for (size_t gi = 0; gi < p.groups.size(); ++gi) {
@@ -503,6 +535,7 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             L.unit_hop = Ld.unit_hop;
             L.dumps = p.dump != nullptr;
             L.potential = Ld.potential;
+            L.hopping = Ld.hopping;
             if ((st = timer.begin(stream)) != FTWA_OK) return st;
             if ((st = resident_launch(L, stream)) != FTWA_OK) return st;
             if ((st = timer.end(stream, 1, Ld.work)) != FTWA_OK) return st;

@@ -256,14 +256,50 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // POT: an external on-site potential adds A (v_i - v_j) to the U factor (Vd:
 // the profile v in the layout of the diagonal array, Aw: the envelope at the
 // stage time; only when `pot_on`).
-template <typename T, bool OWN_REG, bool GEN, bool T1, bool POT = false>
+// HOP (spin split): complex hopping j_ik = t w_ik: col = sum_n w_jn x_n over
+// the column neighbours x_n = rho_ik, row = sum_n conj(w_in) rho_kj, each
+// product as (fma(wr, xr, -(wi xi)), fma(wr, xi, wi xr)), slots summed in
+// order; Wt: this stage's ratio table in global memory, three complex ratios
+// per site at the site's place in the diagonal array (zero for a missing
+// neighbour), so that the diagonal offsets of the descriptor index it.
+template <typename T>
+__device__ __forceinline__ cplx_t<T> hop_mul(cplx_t<T> w, cplx_t<T> x) {
+    cplx_t<T> r;
+    r.x = fma_rn<T>(w.x, x.x, -(w.y * x.y));
+    r.y = fma_rn<T>(w.x, x.y, w.y * x.x);
+    return r;
+}
+
+template <typename T, bool OWN_REG, bool GEN, bool T1, bool POT = false, bool HOP = false>
 __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
                                                  const Stencil& e, T t, T U, cplx_t<T> own,
                                                  const unsigned char* Vd = nullptr, T Aw = 0,
-                                                 bool pot_on = false) {
+                                                 bool pot_on = false,
+                                                 const unsigned char* Wt = nullptr) {
     using C = cplx_t<T>;
     C col, row;
-    if constexpr (GEN) {
+    if constexpr (HOP) {
+        // ratios of the element's sites: j's for the column sums, i's
+        // (conjugated) for the row sums; the diagonal offsets are site
+        // places x sizeof(T), a ratio triple is 3 sizeof(C) = 6 sizeof(T)
+        const C* wj = reinterpret_cast<const C*>(Wt + 6 * e.dj);
+        const C* wi = reinterpret_cast<const C*>(Wt + 6 * e.di);
+        C x[6], w[6];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            x[n] = GEN ? lds_at<T>(Yb, e.n[n]) : *reinterpret_cast<const C*>(Yb + e.n[n]);
+            if constexpr (GEN) x[n].y = conj_sign<T>(e.n[n]) * x[n].y;
+            w[n] = n < 3 ? wj[n] : wi[n - 3];
+        }
+        C p[6];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            if (n >= 3) w[n].y = -w[n].y;
+            p[n] = hop_mul<T>(w[n], x[n]);
+        }
+        col = cadd(cadd(p[0], p[1]), p[2]);
+        row = cadd(cadd(p[3], p[4]), p[5]);
+    } else if constexpr (GEN) {
         const C c0 = lds_at<T>(Yb, e.n[0]), c1 = lds_at<T>(Yb, e.n[1]), c2 = lds_at<T>(Yb, e.n[2]);
         const C r0 = lds_at<T>(Yb, e.n[3]), r1 = lds_at<T>(Yb, e.n[4]), r2 = lds_at<T>(Yb, e.n[5]);
         col.x = (c0.x + c1.x) + c2.x;
@@ -310,16 +346,17 @@ __device__ __forceinline__ uint32_t own_off(const ResDesc& d) { return d.a.w; }
 __device__ __forceinline__ uint32_t own_off(const uint4& w) { return lo16x8(w.w); }
 
 // The same with the variant chosen by a (compile-time) slot condition.
-template <typename T, bool OWN_REG, bool T1, typename DT, bool POT = false>
+template <typename T, bool OWN_REG, bool T1, typename DT, bool POT = false, bool HOP = false>
 __device__ __forceinline__ cplx_t<T> element_rhs_sel(bool gen, const unsigned char* Yb,
                                                      const unsigned char* Yd, const DT& d,
                                                      T t, T U, cplx_t<T> own,
                                                      const unsigned char* Vd = nullptr, T Aw = 0,
-                                                     bool pot_on = false) {
-    return gen ? element_rhs<T, OWN_REG, true, T1, POT>(Yb, Yd, decode<true>(d), t, U, own, Vd,
-                                                         Aw, pot_on)
-               : element_rhs<T, OWN_REG, false, T1, POT>(Yb, Yd, decode<false>(d), t, U, own, Vd,
-                                                          Aw, pot_on);
+                                                     bool pot_on = false,
+                                                     const unsigned char* Wt = nullptr) {
+    return gen ? element_rhs<T, OWN_REG, true, T1, POT, HOP>(Yb, Yd, decode<true>(d), t, U, own,
+                                                              Vd, Aw, pot_on, Wt)
+               : element_rhs<T, OWN_REG, false, T1, POT, HOP>(Yb, Yd, decode<false>(d), t, U,
+                                                               own, Vd, Aw, pot_on, Wt);
 }
 
 // One Runge-Kutta stage update of an element from its slope k:
@@ -372,14 +409,17 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 // T1: every instance of the launch has t = 1 (the usual unit of energy).
 // POT (spin split only): entries may carry an external on-site potential;
 // its profile sits in LDS after the partner's diagonal, in the same layout.
+// HOP (spin split only): every entry carries complex hopping (ResidentInst::hop:
+// the ratio table hop_table_kernel prepared, read from global memory).
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1,
-          bool POT = false>
+          bool POT = false, bool HOP = false>
 __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     // descriptor form: compact for the spin split, wide otherwise
     using DT = std::conditional_t<S == 1, uint4, ResDesc>;
     static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
     static_assert(!POT || S == 1, "the potential is built into spin-split kernels");
+    static_assert(!HOP || (S == 1 && !POT), "complex hopping: spin-split kernels, no potential");
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
@@ -522,6 +562,9 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             for (int i = t; i < N; i += NTU)
                 reinterpret_cast<T*>(vpart)[dpos[i]] = pot_on ? (T)vs[i] : (T)0;
         }
+        // complex hopping: the prepared ratio tables, [2 n_steps + 1][N][3]
+        const unsigned char* const hop_tab =
+            HOP ? reinterpret_cast<const unsigned char*>(uniform64((uint64_t)E.hop)) : nullptr;
         if constexpr (S == 1) {
             // the partner's diagonal in two alternating copies (stage parity),
             // reals in sublattice-major order; the current one from HBM
@@ -617,6 +660,11 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 if (pot_on)
                     Aw = uniform_real<T>((T)venv[2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)]);
             }
+            // the ratio table of this stage's time (the same half-step samples)
+            const unsigned char* const Wt =
+                HOP ? hop_tab + (size_t)(2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)) *
+                                    (size_t)N * 3 * CB
+                    : nullptr;
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
             // registers); descriptors are loaded KP slots ahead.
@@ -646,8 +694,9 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         // is y itself, so nothing is held across steps
                         const C own = STAGE == 1 ? y[s][u] : hold[s][u];
                         *reinterpret_cast<C*>(Yb + own_off(d)) = own;
-                        k = element_rhs_sel<T, true, T1, DT, POT>(u < GE, Yb, dcur, d, tw, Uw, own,
-                                                                  vpart, Aw, pot_on);
+                        k = element_rhs_sel<T, true, T1, DT, POT, HOP>(u < GE, Yb, dcur, d, tw,
+                                                                       Uw, own, vpart, Aw, pot_on,
+                                                                       Wt);
                     } else {
                         k = element_rhs_sel<T, false, T1>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
                                                       tw, Uw, hold[s][u]);
@@ -686,10 +735,12 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     // stage 1 reads the element's own value from y (the
                     // stage input of a full step is its base point)
                     const C k = STAGE == 1
-                        ? element_rhs_sel<T, true, T1, DT, POT>(u - UE < GO, Yb, Yd, d, tw, Uw,
-                                                                 y[s][u], vpart, Aw, pot_on)
-                        : element_rhs_sel<T, false, T1, DT, POT>(u - UE < GO, Yb, Yd, d, tw, Uw,
-                                                                  y[s][u], vpart, Aw, pot_on);
+                        ? element_rhs_sel<T, true, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
+                                                                      Uw, y[s][u], vpart, Aw,
+                                                                      pot_on, Wt)
+                        : element_rhs_sel<T, false, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
+                                                                       Uw, y[s][u], vpart, Aw,
+                                                                       pot_on, Wt);
                     *reinterpret_cast<C*>(Yb + own_off(d)) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
@@ -1298,6 +1349,8 @@ struct Config {
     bool auto_pick = true;  // false: chosen only when forced or by the autotuner
     const void* fn_pot = nullptr;  // variant with the external potential (spin split)
     const void* fn_pot_t1 = nullptr;  // the same for launches with t = 1 (FP32 spin split)
+    const void* fn_hop = nullptr;     // variant with complex hopping (FP32 spin split)
+    const void* fn_hop_t1 = nullptr;  // the same for launches with t = 1
 };
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
@@ -1324,12 +1377,22 @@ constexpr const void* potential_t1_fn() {
         return nullptr;
 }
 
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1>
+constexpr const void* hopping_fn() {
+    if constexpr (std::is_same<T, float>::value && S == 1)
+        return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, T1, false, true>;
+    else
+        return nullptr;
+}
+
 #define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO, GE, GO)                    \
     Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                                    \
            (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
            unit_hop_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(), 1, 0, 0, 0, 0, true, \
            potential_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(),                     \
-           potential_t1_fn<T, S, NTU, UNITS, UE, UO, GE, GO>()}
+           potential_t1_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(),                  \
+           hopping_fn<T, S, NTU, UNITS, UE, UO, GE, GO, false>(),                \
+           hopping_fn<T, S, NTU, UNITS, UE, UO, GE, GO, true>()}
 
 template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
           int KB>
@@ -1419,7 +1482,7 @@ int64_t split_words(const Config& c) {
 }  // namespace
 
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
-                   int force_config, bool allow_split, bool need_potential) {
+                   int force_config, bool allow_split, bool need_potential, bool need_hop) {
     if (!tab.bipartite) return false;
     const int P = (int)packed_count(N);
     const int n_even = (int)tab.n_even, n_odd = P - n_even;
@@ -1431,6 +1494,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         if (c.dtype != dtype) continue;
         if (!c.auto_pick && force_config < 0) continue;
         if (need_potential && !c.fn_pot) continue;
+        if (need_hop && !c.fn_hop) continue;
         if (N > c.NTU) continue;  // the diagonal must sit in slot 0
         size_t lds;
         if (c.G > 1) {
@@ -1472,6 +1536,7 @@ int resident_config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0]
 int resident_spins(int config) { return kConfigs[config].S; }
 int resident_parts(int config) { return kConfigs[config].G; }
 bool resident_has_potential(int config) { return kConfigs[config].fn_pot != nullptr; }
+bool resident_has_hop(int config) { return kConfigs[config].fn_hop != nullptr; }
 
 int64_t resident_item_traj(int config) {
     const Config& c = kConfigs[config];
@@ -1559,6 +1624,46 @@ size_t resident_mailbox_bytes(int config, int Nmax, int64_t n_items) {
 }
 
 
+namespace {
+// The ratio table of the complex-hopping variant: out[r][dpos[i]][n] = w[r][i][n]
+// rounded once to T for n < deg(i), zero for a missing neighbour (whose
+// caller-side value may be anything), r over the 2 n_steps + 1 half steps.
+template <typename T>
+__global__ __launch_bounds__(256) void hop_table_kernel(const double2* __restrict__ w,
+                                                        const int32_t* __restrict__ nb,
+                                                        const int32_t* __restrict__ dpos, int N,
+                                                        int64_t n_rows, cplx_t<T>* __restrict__ out) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_rows * N * 3) return;
+    const int64_t r = x / (3 * N);
+    const int i = (int)(x / 3 - r * N), n = (int)(x % 3);
+    cplx_t<T> v;
+    v.x = 0;
+    v.y = 0;
+    if (n < nb[i * 4 + 3]) {
+        const double2 a = w[x];
+        v.x = (T)a.x;
+        v.y = (T)a.y;
+    }
+    out[(r * N + dpos[i]) * 3 + n] = v;
+}
+}  // namespace
+
+ftwa_status hop_table(const double* hop_w, const int32_t* nb, const int32_t* dpos, int N,
+                      int64_t n_steps, ftwa_dtype dtype, void* out, hipStream_t stream) {
+    const int64_t n_rows = 2 * n_steps + 1, n = n_rows * N * 3;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    const double2* w = reinterpret_cast<const double2*>(hop_w);
+    if (dtype == FTWA_F64)
+        hipLaunchKernelGGL(hop_table_kernel<double>, grid, dim3(256), 0, stream, w, nb, dpos, N,
+                           n_rows, static_cast<cplx_t<double>*>(out));
+    else
+        hipLaunchKernelGGL(hop_table_kernel<float>, grid, dim3(256), 0, stream, w, nb, dpos, N,
+                           n_rows, static_cast<cplx_t<float>*>(out));
+    FTWA_LAUNCH_CHECK("hop_table_kernel");
+    return FTWA_OK;
+}
+
 ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     const Config& c = kConfigs[L.config];
     if (L.n_items <= 0) return FTWA_OK;
@@ -1580,9 +1685,12 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     // wait for the absent partner and exits
     const int64_t grid = (L.drop_partners && c.S == 1 && c.G == 1) ? 8 : L.grid;
     const bool t1 = L.unit_hop && !L.dumps;
-    const void* fn = L.potential ? (t1 && c.fn_pot_t1 ? c.fn_pot_t1 : c.fn_pot)
-                                 : (t1 && c.fn_t1 ? c.fn_t1 : c.fn);
-    if (!fn) return fail(FTWA_ENOTSUP, "this configuration has no external-potential variant");
+    const void* fn = L.hopping     ? (t1 && c.fn_hop_t1 ? c.fn_hop_t1 : c.fn_hop)
+                     : L.potential ? (t1 && c.fn_pot_t1 ? c.fn_pot_t1 : c.fn_pot)
+                                   : (t1 && c.fn_t1 ? c.fn_t1 : c.fn);
+    if (!fn)
+        return fail(FTWA_ENOTSUP, L.hopping ? "this configuration has no complex-hopping variant"
+                                            : "this configuration has no external-potential variant");
     if (c.S == 1) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,
         // no memset node)

@@ -1,8 +1,9 @@
 """Complex, time-dependent (Peierls) hopping j_ik(tau) = t w_ik(tau) through
-the C ABI: the stream kernels against the oracle bitwise in both precisions,
-the ratio table built for each side from its own neighbour table; together
-with an external potential and a general interaction in a batch with a
-real-hopping instance; and the paths that refuse it."""
+the C ABI: the stream kernels and the FP32 spin-split resident kernels (every
+spin-split configuration, t = 1 and t != 1) against the oracle bitwise, the
+ratio table built for each side from its own neighbour table; together with
+an external potential and a general interaction in a batch with a
+real-hopping instance; graph replays; and the paths that refuse it."""
 import numpy as np
 import pytest
 
@@ -135,13 +136,81 @@ def test_graph_replays_with_complex_hopping(ft, orc):
     g.close()
 
 
+@pytest.mark.parametrize("kind,a,b,config,t", [
+    ("hex", 5, 0, -1, 1.0),          # 150 sites: the automatic choice (768 x (8,8))
+    ("armchair", 10, 20, -1, 1.0),   # 198 sites: the automatic choice (768 x (13,13))
+    ("armchair", 10, 20, 10, 1.0),   # 1024 x (10,10)
+    ("armchair", 10, 20, 11, 1.0),   # 512 x (20,20)
+    ("armchair", 10, 20, 12, 1.0),   # every slot general
+    ("armchair", 10, 20, -1, 0.8),   # t != 1: the general-hopping variant
+    ("hex", 4, 0, 9, 1.3),           # 96 sites on the 198-site tile (padding-heavy slots)
+])
+def test_resident_peierls_matches_oracle_bitwise(ft, orc, kind, a, b, config, t):
+    """The spin-split resident kernel's complex-hopping variant: the ratio
+    table (prepared on the device in the place order of the partner's
+    diagonal, missing neighbours zero while the caller's unused slots hold
+    NaN) read from global memory per stage; both directions of a transposed
+    orientation come out exact conjugates, so the state equals the oracle's."""
+    import torch
+    dt, steps, re = 0.01, 8, 4
+    olat = orc.Lattice(kind, a, b, t)
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = orc.fock_start(olat, "random", 12)
+    M = 9
+    rho0 = orc.sample(olat, n0, 12, M)
+    prob = ft.Problem.allocate(lat, 3.3, M, n0, "f32")
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(np.complex64))))
+    fn = _phase_fn(olat.N, 12, dt)
+    w = _table(olat.nbr, olat.deg, fn, 2 * steps + 1)
+    prob.hop_w = torch.from_numpy(_table(lat.nbr, lat.deg, fn, 2 * steps + 1, fill=np.nan)).cuda()
+    ft.evolve(prob, dt, steps, re, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision="f32", hop=w)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(np.complex64)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
+def test_resident_peierls_graph_replays(ft, orc):
+    """The resident variant captured in a graph (the table preparation is a
+    kernel of the graph) and replayed twice equals two direct runs."""
+    import torch
+    dt, steps, re = 0.01, 6, 3
+    olat, lat, rho0, prob, w, _ = _setup(ft, orc, "armchair", 10, 20, 6, 3.3, "f32", 7, steps, dt)
+    ref = ft.Problem.allocate(lat, 3.3, 6, prob.n0.cpu().numpy(), "f32")
+    ref.rho.copy_(prob.rho)
+    ref.hop_w = prob.hop_w
+    g = ft.EvolveGraph([prob], dt, steps, re, path="resident")
+    for _ in range(2):
+        g.launch()
+        g.check()
+        ft.evolve(ref, dt, steps, re, path="resident")
+        torch.cuda.synchronize()
+        assert torch.equal(prob.rho, ref.rho)
+    g.close()
+
+
 def test_paths_that_refuse_complex_hopping(ft, orc):
     import torch
     olat, lat, rho0, prob, w, _ = _setup(ft, orc, "armchair", 10, 20, 4, 3.3, "f32", 5, 2, 0.01)
-    with pytest.raises(ft.FtwaError):
+    # FP64: the split kernel has no complex-hopping variant
+    o64, l64, r64, p64, w64, _ = _setup(ft, orc, "armchair", 10, 20, 4, 3.3, "f64", 5, 2, 0.01)
+    with pytest.raises(ft.FtwaError) as e:
+        ft.evolve(p64, 0.01, 2, 1, path="resident")
+    assert e.value.status == -4
+    # the shared-block tiles have none either
+    os_, ls, rs, ps, ws_, _ = _setup(ft, orc, "torus", 2, 3, 8, 3.3, "f32", 5, 2, 0.01)
+    with pytest.raises(ft.FtwaError) as e:
+        ft.evolve(ps, 0.01, 2, 1, config=4)
+    assert e.value.status == -4
+    # complex hopping together with a potential: stream only
+    prob.v_site = torch.zeros(lat.N, dtype=torch.float64, device="cuda")
+    prob.v_env = torch.zeros(5, dtype=torch.float64, device="cuda")
+    with pytest.raises(ft.FtwaError) as e:
         ft.evolve(prob, 0.01, 2, 1, path="resident")
-    with pytest.raises(ft.FtwaError):
-        ft.evolve(prob, 0.01, 2, 1, config=9)
+    assert e.value.status == -4
+    prob.v_site = prob.v_env = None
     g = torch.zeros((2, 2 * lat.N), dtype=torch.float64, device="cuda")
     with pytest.raises(ft.FtwaError):
         ft.adjoint(prob, 0.01, 2, 2, 2, g)
