@@ -627,8 +627,10 @@ def run_pulse(args):
 def run_longrange(args):
     """A general density-density interaction on the 198-site flake: u_ii = 3.3,
     u_ij = exp(-d_ij) / 2 between sites (d_ij the graph distance, a screened
-    tail), FP32 and FP64 on the stream kernels, 4096 trajectories x 400 steps,
-    next to the on-site run of the same kernels."""
+    tail), FP32 and FP64, 4096 trajectories x 400 steps, on the stream kernels
+    and on the automatic path (FP32: the spin-split resident kernel's
+    general-interaction variant; FP64: the stream kernels, the split kernel
+    has none), next to the on-site run of the same paths."""
     import numpy as np
     import torch
     from collections import deque
@@ -651,28 +653,32 @@ def run_longrange(args):
     steps = args.horizon_steps or 400
     rows = []
     for dtype in ("f32", "f64"):
-        for general in (False, True):
-            p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
-            if general:
-                p.u_mat = torch.from_numpy(u).cuda()
-            ft.sample(p, 5)
-            ws = ft.evolve(p, 0.005, 2, 1, path="stream")
-            ft.sample(p, 5)
-            timing = ft.new_timing()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ft.evolve(p, 0.005, steps, 10, path="stream", workspace=ws, timing=timing)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            rows.append({"dtype": dtype, "interaction": "general" if general else "on-site",
-                         "value": M * steps / el})
-            log(f"longrange: {dtype} general={general}: {M * steps / el:.3e} traj-steps/s")
-            del p, ws
+        for path in ("stream", "auto"):
+            for general in (False, True):
+                p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
+                if general:
+                    p.u_mat = torch.from_numpy(u).cuda()
+                ft.sample(p, 5)
+                ws = ft.evolve(p, 0.005, steps, 10, path=path)  # warm-up, workspace
+                ft.sample(p, 5)
+                timing = ft.new_timing()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ft.evolve(p, 0.005, steps, 10, path=path, workspace=ws, timing=timing)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                rows.append({"dtype": dtype, "path": path,
+                             "interaction": "general" if general else "on-site",
+                             "value": M * steps / el,
+                             "kernel_value": timing["work"].value / (timing["ms"].value * 1e-3)})
+                log(f"longrange: {dtype} {path} general={general}: {M * steps / el:.3e} "
+                    f"traj-steps/s")
+                del p, ws
     print(json.dumps({
         "metric": "trajectory*RK4-steps/s with a general density-density interaction, 198-site flake",
         "unit": "trajectory*RK4-steps/s", "rows": rows,
         "config": {"workload": "flake198_longrange", "trajectories": M, "rk4_steps": steps,
-                   "dt": 0.005, "path": "stream",
+                   "dt": 0.005, "paths": ["stream", "auto"],
                    "interaction": "u_ii = 3.3, u_ij = exp(-graph distance) / 2"}}))
 
 

@@ -187,10 +187,16 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        U (ignored then): Eq. (6)'s own form multiplies rho_ij,s by
  *        D_i - D_j, D_i = sum_k u_ki (rho_kk,sbar + 1/2), accumulated as
  *        D = fma(u_ki, d_k + 1/2, D) over ascending k in the working precision
- *        (u rounded once).  Integrated by the stream kernels (a per-stage
- *        kernel forms D for every site and trajectory); the resident path, a
- *        forced configuration, invariant monitors (inv: their energy is the
- *        on-site form) and ftwa_adjoint refuse it (FTWA_ENOTSUP / FTWA_EINVAL).
+ *        (u rounded once).  Integrated by the FP32 spin-split resident
+ *        kernels' general-interaction variant where the automatic choice is
+ *        one of them and the instance has neither v_site nor hop_w (u,
+ *        rounded once, is staged by a kernel into the workspace; each stage
+ *        forms D in LDS before the elements), else by the stream kernels (a
+ *        per-stage kernel forms D for every site and trajectory); a forced
+ *        resident path or configuration without the variant, or with v_site
+ *        or hop_w, gives FTWA_ENOTSUP.  Invariant monitors (inv: their energy
+ *        is the on-site form; FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP)
+ *        refuse it.
  *   hop_w [2 n_steps + 1][N][3] complex FP64 (interleaved re, im) or NULL
  *        complex, time-dependent hopping j_ik(tau) = t hop_w[h][i][n] for the
  *        neighbour k = nbr[i][n] of ftwa_lattice_info (Peierls phases; Sec. III:

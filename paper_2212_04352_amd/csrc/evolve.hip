@@ -83,6 +83,7 @@ struct InstPlan {
     int64_t chunk = 0;             // stream: trajectories per chunk; resident: per pass window
     size_t off_x = 0, off_inv = 0; // resident: this instance's record regions
     size_t off_hop = 0;            // resident with complex hopping: its ratio table
+    size_t off_umat = 0;           // resident with a general interaction: u in dtype
 };
 
 struct LaunchDesc {                // one resident launch: a group in a pass
@@ -95,6 +96,7 @@ struct LaunchDesc {                // one resident launch: a group in a pass
     bool unit_hop = true;          // every instance has t = 1
     bool potential = false;        // an instance carries an external potential
     bool hopping = false;          // every instance carries complex hopping
+    bool interaction = false;      // every instance carries a general interaction
 };
 
 struct GroupPlan {
@@ -162,7 +164,8 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
     p.drop_partners = tune && tune->drop_partners;
 
     // ---- path and configuration of every instance
-    std::map<int, int> group_of_config;  // 4 config + 2 (complex hopping) + (external potential)
+    // 8 config + 4 (general interaction) + 2 (complex hopping) + (external potential)
+    std::map<int, int> group_of_config;
     for (int k = 0; k < n_inst; ++k) {
         InstPlan ip;
         const DeviceTables& tab = host_tables(inst[k].lat);
@@ -179,18 +182,26 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         // an external potential: the stream kernels, or a resident configuration
         // with the potential variant (spin split)
         const bool pot = inst[k].v_site != nullptr;
-        // a general interaction: the stream kernels only
-        if (inst[k].u_mat && (want == FTWA_PATH_RESIDENT || force >= 0))
-            return fail(FTWA_ENOTSUP, "a general interaction u_ij runs on the stream path only");
+        // a general interaction: the stream kernels, or a resident configuration
+        // with the general-interaction variant (the FP32 spin split; alone)
+        const bool gint = inst[k].u_mat != nullptr;
         // complex hopping: the stream kernels, or a resident configuration with
         // the complex-hopping variant (the FP32 spin split; not together with
         // a potential)
         const bool hop = inst[k].hop_w != nullptr;
-        if (hop && pot && (want == FTWA_PATH_RESIDENT || force >= 0))
-            return fail(FTWA_ENOTSUP,
-                        "complex hopping together with a potential runs on the stream path only");
-        bool can_res = !tuned_stream && !inst[k].u_mat && !(hop && pot) &&
+        const int n_var = (pot ? 1 : 0) + (hop ? 1 : 0) + (gint ? 1 : 0);
+        if (n_var > 1 && (want == FTWA_PATH_RESIDENT || force >= 0))
+            return fail(FTWA_ENOTSUP, "a potential, complex hopping and a general interaction "
+                                      "together run on the stream path only");
+        bool can_res = !tuned_stream && n_var <= 1 &&
                        resident_plan(N, dtype, tab, &ip.res, cfg, inst[k].inv == nullptr);
+        if (gint && can_res) {
+            // the configuration chosen for the on-site U, if it has the variant
+            const int c0 = ip.res.config;
+            can_res = resident_has_interaction(c0) &&
+                      resident_plan(N, dtype, tab, &ip.res, c0, inst[k].inv == nullptr, false,
+                                    false, true);
+        }
         if (hop && can_res) {
             // the configuration chosen for real hopping, if it has the variant
             const int c0 = ip.res.config;
@@ -206,9 +217,11 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                       resident_plan(N, dtype, tab, &ip.res, c0, inst[k].inv == nullptr, true);
         }
         if (force >= 0 && !can_res)
-            return fail(FTWA_ENOTSUP, hop ? "the forced resident configuration has no "
-                                            "complex-hopping variant or does not fit"
-                                          : "the forced resident configuration does not fit");
+            return fail(FTWA_ENOTSUP, hop    ? "the forced resident configuration has no "
+                                               "complex-hopping variant or does not fit"
+                                      : gint ? "the forced resident configuration has no "
+                                               "general-interaction variant or does not fit"
+                                             : "the forced resident configuration does not fit");
         if (want == FTWA_PATH_RESIDENT && !can_res)
             return fail(FTWA_ENOTSUP, "no resident configuration fits this lattice and dtype");
         ip.path = (want == FTWA_PATH_STREAM || !can_res) ? FTWA_PATH_STREAM : FTWA_PATH_RESIDENT;
@@ -216,7 +229,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             // instances with a potential form groups of their own: their
             // launches run the potential variant, whose LDS layout holds the
             // profile and is sized for it
-            const int key = 4 * ip.res.config + (hop ? 2 : 0) + (pot ? 1 : 0);
+            const int key = 8 * ip.res.config + (gint ? 4 : 0) + (hop ? 2 : 0) + (pot ? 1 : 0);
             auto it = group_of_config.find(key);
             if (it == group_of_config.end()) {
                 it = group_of_config.emplace(key, (int)p.groups.size()).first;
@@ -302,6 +315,10 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             off = align_up(off + (size_t)(2 * p.n_steps + 1) * inst[k].lat->N * 3 *
                                      cplx_bytes(p.dtype));
         }
+        if (inst[k].u_mat) {
+            ip.off_umat = off;
+            off = align_up(off + (size_t)inst[k].lat->N * inst[k].lat->N * cplx_bytes(p.dtype) / 2);
+        }
         if (inst[k].inv) {
             ip.off_inv = off;
             off = align_up(off + (size_t)p.n_rec * 4 * ip.chunk * sizeof(double));
@@ -331,6 +348,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
                 if (inst[k].lat->t != 1.0) L.unit_hop = false;
                 if (inst[k].v_site) L.potential = true;
                 if (inst[k].hop_w) L.hopping = true;
+                if (inst[k].u_mat) L.interaction = true;
                 ++L.n_entries;
             }
             entry += L.n_entries;
@@ -403,6 +421,7 @@ ftwa_status build_table(Plan& p, const ftwa_instance* inst, char* ws) {
                 e.v_site = inst[k].v_site;
                 e.v_env = inst[k].v_env;
                 e.hop = inst[k].hop_w ? ws + ip.off_hop : nullptr;
+                e.umat = inst[k].u_mat ? ws + ip.off_umat : nullptr;
                 p.table.push_back(e);
             }
         }
@@ -510,6 +529,13 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
                             ws + ip.off_hop, stream)) != FTWA_OK)
             return st;
     }
+    for (int k = 0; k < p.n_inst; ++k) {
+        const InstPlan& ip = p.inst[k];
+        if (ip.path != FTWA_PATH_RESIDENT || !inst[k].u_mat) continue;
+        if ((st = umat_table(inst[k].u_mat, inst[k].lat->N, p.dtype, ws + ip.off_umat, stream)) !=
+            FTWA_OK)
+            return st;
+    }
     const ResidentInst* table = reinterpret_cast<const ResidentInst*>(ws + p.r_table);
     for (int j = 0; j < p.n_pass; ++j) {
         for (size_t gi = 0; gi < p.groups.size(); ++gi) {
@@ -536,6 +562,7 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
             L.dumps = p.dump != nullptr;
             L.potential = Ld.potential;
             L.hopping = Ld.hopping;
+            L.interaction = Ld.interaction;
             if ((st = timer.begin(stream)) != FTWA_OK) return st;
             if ((st = resident_launch(L, stream)) != FTWA_OK) return st;
             if ((st = timer.end(stream, 1, Ld.work)) != FTWA_OK) return st;

@@ -411,8 +411,13 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 // its profile sits in LDS after the partner's diagonal, in the same layout.
 // HOP (spin split only): every entry carries complex hopping (ResidentInst::hop:
 // the ratio table hop_table_kernel prepared, read from global memory).
+// GINT (spin split only): every entry carries a general interaction u_ij
+// (ResidentInst::umat, u rounded to T, [k][i]): each stage starts with
+// D_i = sum_k u_ki (d_k + 1/2) over the partner's diagonal, one ascending
+// fused chain per site, into LDS after the diagonal copies (in their
+// layout), and the U factor of an element is D_i - D_j (U = 1 exactly).
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1,
-          bool POT = false, bool HOP = false>
+          bool POT = false, bool HOP = false, bool GINT = false>
 __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     // descriptor form: compact for the spin split, wide otherwise
@@ -420,6 +425,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
     static_assert(!POT || S == 1, "the potential is built into spin-split kernels");
     static_assert(!HOP || (S == 1 && !POT), "complex hopping: spin-split kernels, no potential");
+    static_assert(!GINT || (S == 1 && !POT && !HOP),
+                  "general interaction: spin-split kernels, no potential or complex hopping");
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
@@ -477,8 +484,12 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         // apart) first, then the block.  The launch has no static LDS, so the
         // dynamic block starts at LDS address 0 and offsets are addresses (no
         // base register; constant offsets go into the instructions).
-        unsigned char* const Yunit =
-            lds_ptr((uint32_t)((S == 1 ? (POT ? 3 : 2) * kDiagCopy : 0) + (size_t)unit * S * Pb * CB));
+        // S = 1: two diagonal copies, then the potential's profile (POT) or
+        // D and two site-ordered copies of the partner's diagonal (GINT)
+        constexpr uint32_t kPre = S == 1 ? (GINT ? 5 : POT ? 3 : 2) * kDiagCopy : 0;
+        unsigned char* const Yunit = lds_ptr((uint32_t)(kPre + (size_t)unit * S * Pb * CB));
+        // GINT: the partner's diagonal in site order, copy c (stage parity)
+        auto dsite = [&](int c) { return reinterpret_cast<T*>(lds_ptr((3 + c) * kDiagCopy)); };
         unsigned char* const dpart = lds_ptr(0);
         // per-wave partial sums of the records and the abort flag follow
         // (placed after the largest blocks of the launch: A.tail_off)
@@ -565,15 +576,21 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         // complex hopping: the prepared ratio tables, [2 n_steps + 1][N][3]
         const unsigned char* const hop_tab =
             HOP ? reinterpret_cast<const unsigned char*>(uniform64((uint64_t)E.hop)) : nullptr;
+        // general interaction: u in T, [k][i]; D goes where the profile would
+        const T* const utab = GINT ? reinterpret_cast<const T*>(uniform64((uint64_t)E.umat)) : nullptr;
         if constexpr (S == 1) {
             // the partner's diagonal in two alternating copies (stage parity),
             // reals in sublattice-major order; the current one from HBM
             for (int i = t; i < N; i += NTU) {
                 const int64_t p = (int64_t)i * N - (int64_t)i * (i - 1) / 2;
                 const int q = dpos[i];
-                reinterpret_cast<T*>(dpart + (size_t)(g & 1) * kDiagCopy)[q] =
-                    active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
+                const T v = active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
+                reinterpret_cast<T*>(dpart + (size_t)(g & 1) * kDiagCopy)[q] = v;
                 reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * kDiagCopy)[q] = (T)0;
+                if constexpr (GINT) {
+                    dsite((int)(g & 1))[i] = v;
+                    dsite((int)((g + 1) & 1))[i] = (T)0;
+                }
             }
         }
         // records: the first N even elements are the diagonal (i = position)
@@ -665,6 +682,43 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 HOP ? hop_tab + (size_t)(2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)) *
                                     (size_t)N * 3 * CB
                     : nullptr;
+            // general interaction: D of this stage's input (the partner's
+            // diagonal in dcur is complete: the previous stage ended with a
+            // barrier after it landed), then the elements take D in place of
+            // the diagonal and 1 in place of U
+            const unsigned char* Ud = dcur;
+            T Uu = Uw;
+            if constexpr (GINT) {
+                if (tid < N) {
+                    // batches of 16 sites: their u loads (buffer loads, one
+                    // coalesced row segment per site across the threads) and
+                    // the site-ordered diagonal reads are issued before the
+                    // batch's part of the chain
+                    constexpr int B = 16;
+                    const T* const ds = dsite((STAGE - 1) & 1);
+                    const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)utab, (short)0, (int)(N * N * TB), 0x00020000);
+                    T accD = 0;
+                    for (int k0 = 0; k0 < N; k0 += B) {
+                        T ub[B], db[B];
+#pragma unroll
+                        for (int q = 0; q < B; ++q) {
+                            const int k = k0 + q < N ? k0 + q : N - 1;  // in bounds
+                            ub[q] = __builtin_bit_cast(
+                                T, __builtin_amdgcn_raw_buffer_load_b32(
+                                       urs, (uint32_t)(tid * TB), k * N * TB, 0));
+                            db[q] = ds[k];
+                        }
+#pragma unroll
+                        for (int q = 0; q < B; ++q)
+                            if (k0 + q < N) accD = fma_rn<T>(ub[q], db[q] + (T)0.5, accD);
+                    }
+                    reinterpret_cast<T*>(vpart)[qdiag] = accD;
+                }
+                __syncthreads();
+                Ud = vpart;
+                Uu = (T)1;
+            }
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
             // registers); descriptors are loaded KP slots ahead.
@@ -694,8 +748,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                         // is y itself, so nothing is held across steps
                         const C own = STAGE == 1 ? y[s][u] : hold[s][u];
                         *reinterpret_cast<C*>(Yb + own_off(d)) = own;
-                        k = element_rhs_sel<T, true, T1, DT, POT, HOP>(u < GE, Yb, dcur, d, tw,
-                                                                       Uw, own, vpart, Aw, pot_on,
+                        k = element_rhs_sel<T, true, T1, DT, POT, HOP>(u < GE, Yb, Ud, d, tw,
+                                                                       Uu, own, vpart, Aw, pot_on,
                                                                        Wt);
                     } else {
                         k = element_rhs_sel<T, false, T1>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
@@ -731,16 +785,16 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
-                    const unsigned char* Yd = S == 1 ? dcur : Yunit + (1 - s) * Pb * CB;
+                    const unsigned char* Yd = S == 1 ? Ud : Yunit + (1 - s) * Pb * CB;
                     // stage 1 reads the element's own value from y (the
                     // stage input of a full step is its base point)
                     const C k = STAGE == 1
                         ? element_rhs_sel<T, true, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
-                                                                      Uw, y[s][u], vpart, Aw,
-                                                                      pot_on, Wt)
+                                                                      S == 1 ? Uu : Uw, y[s][u],
+                                                                      vpart, Aw, pot_on, Wt)
                         : element_rhs_sel<T, false, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
-                                                                       Uw, y[s][u], vpart, Aw,
-                                                                       pot_on, Wt);
+                                                                       S == 1 ? Uu : Uw, y[s][u],
+                                                                       vpart, Aw, pot_on, Wt);
                     *reinterpret_cast<C*>(Yb + own_off(d)) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
@@ -772,6 +826,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     }
                     reinterpret_cast<T*>(dpart + (STAGE & 1) * kDiagCopy)[q] =
                         from_bits<T>((uint32_t)w);
+                    if constexpr (GINT) dsite(STAGE & 1)[tid] = from_bits<T>((uint32_t)w);
                 }
             } else {
                 __syncthreads();
@@ -1351,6 +1406,8 @@ struct Config {
     const void* fn_pot_t1 = nullptr;  // the same for launches with t = 1 (FP32 spin split)
     const void* fn_hop = nullptr;     // variant with complex hopping (FP32 spin split)
     const void* fn_hop_t1 = nullptr;  // the same for launches with t = 1
+    const void* fn_gint = nullptr;    // variant with a general interaction (FP32 spin split)
+    const void* fn_gint_t1 = nullptr;
 };
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
@@ -1385,6 +1442,15 @@ constexpr const void* hopping_fn() {
         return nullptr;
 }
 
+template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1>
+constexpr const void* interaction_fn() {
+    if constexpr (std::is_same<T, float>::value && S == 1)
+        return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, T1, false, false,
+                                          true>;
+    else
+        return nullptr;
+}
+
 #define FTWA_RES_CFG(T, DT, S, NTU, UNITS, UE, UO, GE, GO)                    \
     Config{DT, S, NTU, UNITS, UE, UO, GE, GO,                                    \
            (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false>, \
@@ -1392,7 +1458,9 @@ constexpr const void* hopping_fn() {
            potential_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(),                     \
            potential_t1_fn<T, S, NTU, UNITS, UE, UO, GE, GO>(),                  \
            hopping_fn<T, S, NTU, UNITS, UE, UO, GE, GO, false>(),                \
-           hopping_fn<T, S, NTU, UNITS, UE, UO, GE, GO, true>()}
+           hopping_fn<T, S, NTU, UNITS, UE, UO, GE, GO, true>(),                 \
+           interaction_fn<T, S, NTU, UNITS, UE, UO, GE, GO, false>(),            \
+           interaction_fn<T, S, NTU, UNITS, UE, UO, GE, GO, true>()}
 
 template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
           int KB>
@@ -1482,7 +1550,8 @@ int64_t split_words(const Config& c) {
 }  // namespace
 
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
-                   int force_config, bool allow_split, bool need_potential, bool need_hop) {
+                   int force_config, bool allow_split, bool need_potential, bool need_hop,
+                   bool need_interaction) {
     if (!tab.bipartite) return false;
     const int P = (int)packed_count(N);
     const int n_even = (int)tab.n_even, n_odd = P - n_even;
@@ -1495,6 +1564,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         if (!c.auto_pick && force_config < 0) continue;
         if (need_potential && !c.fn_pot) continue;
         if (need_hop && !c.fn_hop) continue;
+        if (need_interaction && !c.fn_gint) continue;
         if (N > c.NTU) continue;  // the diagonal must sit in slot 0
         size_t lds;
         if (c.G > 1) {
@@ -1515,7 +1585,11 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if ((int64_t)c.NTU * c.GE < tab.n_gen_even || (int64_t)c.NTU * c.GO < tab.n_gen_odd)
                 continue;
             lds = lds_bytes(c, N, P);
-            if (need_potential) lds += 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // the profile
+            // the potential's profile, or the general interaction's D and two
+            // site-ordered copies of the partner's diagonal
+            const size_t tb = c.dtype == FTWA_F64 ? 8 : 4;
+            if (need_interaction) lds += 3 * 256 * tb;
+            else if (need_potential) lds += 256 * tb;
         }
         if (lds > kMaxLds) continue;
         plan->config = k;
@@ -1537,6 +1611,7 @@ int resident_spins(int config) { return kConfigs[config].S; }
 int resident_parts(int config) { return kConfigs[config].G; }
 bool resident_has_potential(int config) { return kConfigs[config].fn_pot != nullptr; }
 bool resident_has_hop(int config) { return kConfigs[config].fn_hop != nullptr; }
+bool resident_has_interaction(int config) { return kConfigs[config].fn_gint != nullptr; }
 
 int64_t resident_item_traj(int config) {
     const Config& c = kConfigs[config];
@@ -1664,6 +1739,30 @@ ftwa_status hop_table(const double* hop_w, const int32_t* nb, const int32_t* dpo
     return FTWA_OK;
 }
 
+namespace {
+// u of the general-interaction variant rounded once to T, in its [k][i] order.
+template <typename T>
+__global__ __launch_bounds__(256) void umat_table_kernel(const double* __restrict__ u, int64_t n,
+                                                         T* __restrict__ out) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) out[x] = (T)u[x];
+}
+}  // namespace
+
+ftwa_status umat_table(const double* u_mat, int N, ftwa_dtype dtype, void* out,
+                       hipStream_t stream) {
+    const int64_t n = (int64_t)N * N;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (dtype == FTWA_F64)
+        hipLaunchKernelGGL(umat_table_kernel<double>, grid, dim3(256), 0, stream, u_mat, n,
+                           static_cast<double*>(out));
+    else
+        hipLaunchKernelGGL(umat_table_kernel<float>, grid, dim3(256), 0, stream, u_mat, n,
+                           static_cast<float*>(out));
+    FTWA_LAUNCH_CHECK("umat_table_kernel");
+    return FTWA_OK;
+}
+
 ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     const Config& c = kConfigs[L.config];
     if (L.n_items <= 0) return FTWA_OK;
@@ -1685,12 +1784,14 @@ ftwa_status resident_launch(const ResidentLaunch& L, hipStream_t stream) {
     // wait for the absent partner and exits
     const int64_t grid = (L.drop_partners && c.S == 1 && c.G == 1) ? 8 : L.grid;
     const bool t1 = L.unit_hop && !L.dumps;
-    const void* fn = L.hopping     ? (t1 && c.fn_hop_t1 ? c.fn_hop_t1 : c.fn_hop)
+    const void* fn = L.interaction ? (t1 && c.fn_gint_t1 ? c.fn_gint_t1 : c.fn_gint)
+                     : L.hopping   ? (t1 && c.fn_hop_t1 ? c.fn_hop_t1 : c.fn_hop)
                      : L.potential ? (t1 && c.fn_pot_t1 ? c.fn_pot_t1 : c.fn_pot)
                                    : (t1 && c.fn_t1 ? c.fn_t1 : c.fn);
     if (!fn)
-        return fail(FTWA_ENOTSUP, L.hopping ? "this configuration has no complex-hopping variant"
-                                            : "this configuration has no external-potential variant");
+        return fail(FTWA_ENOTSUP, L.interaction ? "this configuration has no general-interaction variant"
+                                  : L.hopping   ? "this configuration has no complex-hopping variant"
+                                                : "this configuration has no external-potential variant");
     if (c.S == 1) {
         // every word starts at stage 0, which no wait accepts (a fill kernel,
         // no memset node)

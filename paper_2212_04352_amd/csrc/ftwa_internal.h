@@ -316,6 +316,7 @@ struct ResidentInst {
     const double* v_site;  // NULL or [N]: external on-site potential profile (ftwa_instance)
     const double* v_env;   // its envelope at half steps from the start of the run
     const void* hop;       // NULL or the complex-hopping ratio table (hop_table)
+    const void* umat;      // NULL or the general interaction in the working precision (umat_table)
 };
 struct ResidentLaunch {
     int config;
@@ -337,20 +338,26 @@ struct ResidentLaunch {
     bool dumps;                 // an entry stores its state at records (ResidentInst::dump)
     bool potential;             // an entry carries an external potential (the POT variant)
     bool hopping;               // every entry carries complex hopping (the HOP variant)
+    bool interaction;           // every entry carries a general interaction (the GINT variant)
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).
 // allow_split: the split configurations may be chosen (they keep no
 // invariant sums); need_potential: only configurations with an
 // external-potential variant (the FP32 spin split).
-// need_hop: only configurations with a complex-hopping variant (FP32 spin split).
+// need_hop, need_interaction: only configurations with a complex-hopping or a
+// general-interaction variant (FP32 spin split).
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
                    int force_config = -1, bool allow_split = true, bool need_potential = false,
-                   bool need_hop = false);
+                   bool need_hop = false, bool need_interaction = false);
 int resident_config_count();
 int resident_spins(int config);
 int resident_parts(int config);  // workgroups per spin block (> 1: split tables)
 bool resident_has_potential(int config);  // has the external-potential variant
 bool resident_has_hop(int config);        // has the complex-hopping variant
+bool resident_has_interaction(int config);  // has the general-interaction variant
+// u_mat ([N][N] FP64, u_ki at k N + i) rounded once to dtype, same order (queued on stream).
+ftwa_status umat_table(const double* u_mat, int N, ftwa_dtype dtype, void* out,
+                       hipStream_t stream);
 // The ratio table of the complex-hopping variant from ftwa_instance::hop_w
 // ([2 n_steps + 1][N][3] complex FP64): [2 n_steps + 1][N][3] complex in dtype,
 // row r's site i at place dpos[i], missing neighbours zero (queued on stream).

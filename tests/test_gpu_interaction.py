@@ -1,8 +1,9 @@
 """A general density-density interaction u_ij between opposite spins (Eq. (1),
 Eq. (6)'s own form) through the C ABI: the stream kernels (a per-stage kernel
-forming D_i = sum_k u_ki (d_k + 1/2), fma over ascending k) against the oracle
-bitwise in both precisions, together with an external potential, in a batch
-with an on-site instance, and the paths that refuse it."""
+forming D_i = sum_k u_ki (d_k + 1/2), fma over ascending k) and the FP32
+spin-split resident kernels (D formed at the start of every stage from the
+partner's diagonal) against the oracle bitwise, together with an external
+potential, in a batch with an on-site instance, and the paths that refuse it."""
 import numpy as np
 import pytest
 
@@ -92,13 +93,101 @@ def test_interaction_with_a_potential_and_an_on_site_neighbour(ft, orc):
     assert np.array_equal(unpack(_host(p2.rho), l2.N), y2)
 
 
+@pytest.mark.parametrize("kind,a,b,config,t", [
+    ("hex", 5, 0, -1, 1.0),          # 150 sites: the automatic choice (768 x (8,8))
+    ("armchair", 10, 20, -1, 1.0),   # 198 sites: the automatic choice (768 x (13,13))
+    ("armchair", 10, 20, 10, 1.0),   # 1024 x (10,10)
+    ("armchair", 10, 20, 11, 1.0),   # 512 x (20,20)
+    ("armchair", 10, 20, 12, 1.0),   # every slot general
+    ("armchair", 10, 20, -1, 0.7),   # t != 1: the general-hopping variant
+    ("hex", 4, 0, 9, 1.0),           # 96 sites on the 198-site tile
+])
+def test_resident_interaction_matches_oracle_bitwise(ft, orc, kind, a, b, config, t):
+    """The spin-split resident kernel's general-interaction variant: per
+    stage, each of the first N threads forms D_i over ascending k from the
+    partner's diagonal in LDS and u (rounded once to FP32) from global memory;
+    the elements take D_i - D_j as their U factor."""
+    import torch
+    dt, steps, re = 0.01, 8, 4
+    olat = orc.Lattice(kind, a, b, t)
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = orc.fock_start(olat, "random", 14)
+    M = 9
+    rho0 = orc.sample(olat, n0, 14, M)
+    prob = ft.Problem.allocate(lat, 0.0, M, n0, "f32")
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(np.complex64))))
+    u = _long_range(olat, 3.3, 14)
+    prob.u_mat = torch.from_numpy(u).cuda()
+    ft.evolve(prob, dt, steps, re, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, precision="f32", umat=u)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(np.complex64)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
+def test_resident_interaction_next_to_on_site_instances(ft, orc):
+    """One automatic call: a 198-site general-u instance (its own launch
+    group, the variant's larger LDS layout) next to a 198-site on-site
+    instance of the same configuration, several passes of windows."""
+    import torch
+    dt, steps, re = 0.01, 6, 3
+    o1, l1, r1, p1, u1, _ = _setup(ft, orc, "armchair", 10, 20, 7, "f32", 21)
+    n2 = orc.fock_start(o1, "random", 22)
+    r2 = orc.sample(o1, n2, 22, 5)
+    p2 = ft.Problem.allocate(l1, 3.3, 5, n2, "f32", instance=1)
+    p2.rho.copy_(torch.from_numpy(pack(r2.astype(np.complex64))))
+    ft.evolve([p1, p2], dt, steps, re, traj_chunk=3)
+    y1, _, _ = orc.evolve(o1, 0.0, r1, dt, steps, re, precision="f32", umat=u1)
+    y2, _, _ = orc.evolve(o1, 3.3, r2, dt, steps, re, precision="f32")
+    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1.astype(np.complex64))
+    assert np.array_equal(unpack(_host(p2.rho), l1.N), y2.astype(np.complex64))
+
+
+def test_resident_interaction_graph_replays(ft, orc):
+    """The resident variant captured in a graph (staging u in the working
+    precision is a kernel of the graph) and replayed twice equals two direct
+    runs; the first replay also equals the oracle."""
+    import torch
+    dt, steps, re = 0.01, 6, 3
+    olat, lat, rho0, prob, u, _ = _setup(ft, orc, "armchair", 10, 20, 6, "f32", 8)
+    ref = ft.Problem.allocate(lat, 0.0, 6, prob.n0.cpu().numpy(), "f32")
+    ref.rho.copy_(prob.rho)
+    ref.u_mat = prob.u_mat
+    g = ft.EvolveGraph([prob], dt, steps, re, path="resident")
+    y_ref, _, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, precision="f32", umat=u)
+    for r in range(2):
+        g.launch()
+        g.check()
+        ft.evolve(ref, dt, steps, re, path="resident")
+        torch.cuda.synchronize()
+        assert torch.equal(prob.rho, ref.rho)
+        if r == 0:
+            assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref.astype(np.complex64))
+    g.close()
+
+
 def test_paths_that_refuse_a_general_interaction(ft, orc):
     import torch
     olat, lat, rho0, prob, u, _ = _setup(ft, orc, "armchair", 10, 20, 4, "f32", 5)
-    with pytest.raises(ft.FtwaError):
+    # FP64: the split kernel has no general-interaction variant
+    o64, l64, r64, p64, u64, _ = _setup(ft, orc, "armchair", 10, 20, 4, "f64", 5)
+    with pytest.raises(ft.FtwaError) as e:
+        ft.evolve(p64, 0.01, 2, 1, path="resident")
+    assert e.value.status == -4
+    # nor do the shared-block tiles
+    os_, ls, rs, ps, us, _ = _setup(ft, orc, "torus", 2, 3, 8, "f32", 5)
+    with pytest.raises(ft.FtwaError) as e:
+        ft.evolve(ps, 0.01, 2, 1, config=4)
+    assert e.value.status == -4
+    # together with a potential: stream only
+    prob.v_site = torch.zeros(lat.N, dtype=torch.float64, device="cuda")
+    prob.v_env = torch.zeros(5, dtype=torch.float64, device="cuda")
+    with pytest.raises(ft.FtwaError) as e:
         ft.evolve(prob, 0.01, 2, 1, path="resident")
-    with pytest.raises(ft.FtwaError):
-        ft.evolve(prob, 0.01, 2, 1, config=9)
+    assert e.value.status == -4
+    prob.v_site = prob.v_env = None
     w = torch.zeros((2, 2 * lat.N), dtype=torch.float64, device="cuda")
     with pytest.raises(ft.FtwaError):
         ft.adjoint(prob, 0.01, 2, 2, 2, w)
