@@ -317,7 +317,8 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         }
         if (inst[k].u_mat) {
             ip.off_umat = off;
-            off = align_up(off + (size_t)inst[k].lat->N * inst[k].lat->N * cplx_bytes(p.dtype) / 2);
+            off = align_up(off + (size_t)umat_rows(inst[k].lat->N) * inst[k].lat->N *
+                                   cplx_bytes(p.dtype) / 2);
         }
         if (inst[k].inv) {
             ip.off_inv = off;

@@ -262,6 +262,27 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // order; Wt: this stage's ratio table in global memory, three complex ratios
 // per site at the site's place in the diagonal array (zero for a missing
 // neighbour), so that the diagonal offsets of the descriptor index it.
+// The ratio table of one stage: base and size in bytes (read through a
+// buffer resource: 32-bit offsets, its own wait counter).
+struct HopTab {
+    const unsigned char* p = nullptr;
+    int bytes = 0;
+};
+
+// A site's three FP32 ratios (24 bytes at byte offset `off`).
+__device__ __forceinline__ void ratio_triple(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                             cplx_t<float>* w) {
+    const float4 a = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const float2 b =
+        __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off + 16, 0, 0));
+    w[0].x = a.x;
+    w[0].y = a.y;
+    w[1].x = a.z;
+    w[1].y = a.w;
+    w[2].x = b.x;
+    w[2].y = b.y;
+}
+
 template <typename T>
 __device__ __forceinline__ cplx_t<T> hop_mul(cplx_t<T> w, cplx_t<T> x) {
     cplx_t<T> r;
@@ -275,21 +296,24 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
                                                  const Stencil& e, T t, T U, cplx_t<T> own,
                                                  const unsigned char* Vd = nullptr, T Aw = 0,
                                                  bool pot_on = false,
-                                                 const unsigned char* Wt = nullptr) {
+                                                 HopTab Wt = {}) {
     using C = cplx_t<T>;
     C col, row;
     if constexpr (HOP) {
+        static_assert(std::is_same<T, float>::value, "complex hopping: FP32 resident kernels");
         // ratios of the element's sites: j's for the column sums, i's
         // (conjugated) for the row sums; the diagonal offsets are site
         // places x sizeof(T), a ratio triple is 3 sizeof(C) = 6 sizeof(T)
-        const C* wj = reinterpret_cast<const C*>(Wt + 6 * e.dj);
-        const C* wi = reinterpret_cast<const C*>(Wt + 6 * e.di);
+        // (places < 256: a 24-bit product)
+        const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)Wt.p, (short)0, Wt.bytes, 0x00020000);
         C x[6], w[6];
+        ratio_triple(wr, __umul24(e.dj, 6u), w);
+        ratio_triple(wr, __umul24(e.di, 6u), w + 3);
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
             x[n] = GEN ? lds_at<T>(Yb, e.n[n]) : *reinterpret_cast<const C*>(Yb + e.n[n]);
             if constexpr (GEN) x[n].y = conj_sign<T>(e.n[n]) * x[n].y;
-            w[n] = n < 3 ? wj[n] : wi[n - 3];
         }
         C p[6];
 #pragma unroll
@@ -352,7 +376,7 @@ __device__ __forceinline__ cplx_t<T> element_rhs_sel(bool gen, const unsigned ch
                                                      T t, T U, cplx_t<T> own,
                                                      const unsigned char* Vd = nullptr, T Aw = 0,
                                                      bool pot_on = false,
-                                                     const unsigned char* Wt = nullptr) {
+                                                     HopTab Wt = {}) {
     return gen ? element_rhs<T, OWN_REG, true, T1, POT, HOP>(Yb, Yd, decode<true>(d), t, U, own,
                                                               Vd, Aw, pot_on, Wt)
                : element_rhs<T, OWN_REG, false, T1, POT, HOP>(Yb, Yd, decode<false>(d), t, U,
@@ -425,8 +449,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
     static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
     static_assert(!POT || S == 1, "the potential is built into spin-split kernels");
     static_assert(!HOP || (S == 1 && !POT), "complex hopping: spin-split kernels, no potential");
-    static_assert(!GINT || (S == 1 && !POT && !HOP),
-                  "general interaction: spin-split kernels, no potential or complex hopping");
+    static_assert(!GINT || (S == 1 && !POT && !HOP && std::is_same<T, float>::value),
+                  "general interaction: FP32 spin-split kernels, no potential or complex hopping");
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
@@ -488,7 +512,8 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
         // D and two site-ordered copies of the partner's diagonal (GINT)
         constexpr uint32_t kPre = S == 1 ? (GINT ? 5 : POT ? 3 : 2) * kDiagCopy : 0;
         unsigned char* const Yunit = lds_ptr((uint32_t)(kPre + (size_t)unit * S * Pb * CB));
-        // GINT: the partner's diagonal in site order, copy c (stage parity)
+        // GINT: h_k = d_k + 1/2 of the partner's diagonal in site order, copy c
+        // (stage parity), zero from N up to the u table's padded row count
         auto dsite = [&](int c) { return reinterpret_cast<T*>(lds_ptr((3 + c) * kDiagCopy)); };
         unsigned char* const dpart = lds_ptr(0);
         // per-wave partial sums of the records and the abort flag follow
@@ -588,8 +613,14 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                 reinterpret_cast<T*>(dpart + (size_t)(g & 1) * kDiagCopy)[q] = v;
                 reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * kDiagCopy)[q] = (T)0;
                 if constexpr (GINT) {
-                    dsite((int)(g & 1))[i] = v;
+                    dsite((int)(g & 1))[i] = v + (T)0.5;
                     dsite((int)((g + 1) & 1))[i] = (T)0;
+                }
+            }
+            if constexpr (GINT) {
+                for (int i = N + t; i < umat_rows(N); i += NTU) {
+                    dsite(0)[i] = (T)0;
+                    dsite(1)[i] = (T)0;
                 }
             }
         }
@@ -678,10 +709,11 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     Aw = uniform_real<T>((T)venv[2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)]);
             }
             // the ratio table of this stage's time (the same half-step samples)
-            const unsigned char* const Wt =
+            const HopTab Wt{
                 HOP ? hop_tab + (size_t)(2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)) *
                                     (size_t)N * 3 * CB
-                    : nullptr;
+                    : nullptr,
+                N * 3 * CB};
             // general interaction: D of this stage's input (the partner's
             // diagonal in dcur is complete: the previous stage ended with a
             // barrier after it landed), then the elements take D in place of
@@ -690,28 +722,37 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
             T Uu = Uw;
             if constexpr (GINT) {
                 if (tid < N) {
-                    // batches of 16 sites: their u loads (buffer loads, one
-                    // coalesced row segment per site across the threads) and
-                    // the site-ordered diagonal reads are issued before the
-                    // batch's part of the chain
-                    constexpr int B = 16;
-                    const T* const ds = dsite((STAGE - 1) & 1);
+                    // u blocked by four along k ([k/4][i][4], zero rows up to a
+                    // multiple of 32): one 16-byte buffer load per lane carries
+                    // four terms of the chain and a wave reads one contiguous
+                    // segment; four such loads are in flight per batch of 16
+                    // terms (eight spill registers of the held state at 13 + 13
+                    // slots and ran 4 % slower).  h_k = d_k + 1/2 comes from the site-ordered copy
+                    // (one wave-uniform 16-byte LDS read per four terms).  The
+                    // padded terms are fma(0, 0, D) = D + 0 = D exactly (D never
+                    // holds -0: it starts at +0 and a round-to-nearest sum is -0
+                    // only when both addends are).
+                    constexpr int B = 4;
+                    const int K = umat_rows(N);
+                    const T* const hs = dsite((STAGE - 1) & 1);
                     const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
-                        (void*)utab, (short)0, (int)(N * N * TB), 0x00020000);
+                        (void*)utab, (short)0, (int)(K * N * TB), 0x00020000);
                     T accD = 0;
-                    for (int k0 = 0; k0 < N; k0 += B) {
-                        T ub[B], db[B];
+                    for (int k0 = 0; k0 < K; k0 += 4 * B) {
+                        float4 ub[B];
 #pragma unroll
-                        for (int q = 0; q < B; ++q) {
-                            const int k = k0 + q < N ? k0 + q : N - 1;  // in bounds
-                            ub[q] = __builtin_bit_cast(
-                                T, __builtin_amdgcn_raw_buffer_load_b32(
-                                       urs, (uint32_t)(tid * TB), k * N * TB, 0));
-                            db[q] = ds[k];
+                        for (int b = 0; b < B; ++b)
+                            ub[b] = __builtin_bit_cast(
+                                float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                            urs, (uint32_t)(tid * 16), (k0 / 4 + b) * N * 16, 0));
+#pragma unroll
+                        for (int b = 0; b < B; ++b) {
+                            const float4 h = *reinterpret_cast<const float4*>(hs + k0 + 4 * b);
+                            accD = fma_rn<T>(ub[b].x, h.x, accD);
+                            accD = fma_rn<T>(ub[b].y, h.y, accD);
+                            accD = fma_rn<T>(ub[b].z, h.z, accD);
+                            accD = fma_rn<T>(ub[b].w, h.w, accD);
                         }
-#pragma unroll
-                        for (int q = 0; q < B; ++q)
-                            if (k0 + q < N) accD = fma_rn<T>(ub[q], db[q] + (T)0.5, accD);
                     }
                     reinterpret_cast<T*>(vpart)[qdiag] = accD;
                 }
@@ -826,7 +867,7 @@ __global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
                     }
                     reinterpret_cast<T*>(dpart + (STAGE & 1) * kDiagCopy)[q] =
                         from_bits<T>((uint32_t)w);
-                    if constexpr (GINT) dsite(STAGE & 1)[tid] = from_bits<T>((uint32_t)w);
+                    if constexpr (GINT) dsite(STAGE & 1)[tid] = from_bits<T>((uint32_t)w) + (T)0.5;
                 }
             } else {
                 __syncthreads();
@@ -1740,24 +1781,30 @@ ftwa_status hop_table(const double* hop_w, const int32_t* nb, const int32_t* dpo
 }
 
 namespace {
-// u of the general-interaction variant rounded once to T, in its [k][i] order.
+// u of the general-interaction variant rounded once to T, blocked by four
+// along k: out[((k / 4) N + i) 4 + k % 4] = u_ki, rows k >= N zero.
 template <typename T>
-__global__ __launch_bounds__(256) void umat_table_kernel(const double* __restrict__ u, int64_t n,
-                                                         T* __restrict__ out) {
+__global__ __launch_bounds__(256) void umat_table_kernel(const double* __restrict__ u, int N,
+                                                         int64_t n, T* __restrict__ out) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < n) out[x] = (T)u[x];
+    if (x >= n) return;
+    const int64_t kb = x / (4 * (int64_t)N);
+    const int64_t rem = x - kb * 4 * N;
+    const int64_t i = rem / 4;
+    const int64_t k = 4 * kb + (rem & 3);
+    out[x] = k < N ? (T)u[k * N + i] : (T)0;
 }
 }  // namespace
 
 ftwa_status umat_table(const double* u_mat, int N, ftwa_dtype dtype, void* out,
                        hipStream_t stream) {
-    const int64_t n = (int64_t)N * N;
+    const int64_t n = (int64_t)umat_rows(N) * N;
     const dim3 grid((unsigned)((n + 255) / 256));
     if (dtype == FTWA_F64)
-        hipLaunchKernelGGL(umat_table_kernel<double>, grid, dim3(256), 0, stream, u_mat, n,
+        hipLaunchKernelGGL(umat_table_kernel<double>, grid, dim3(256), 0, stream, u_mat, N, n,
                            static_cast<double*>(out));
     else
-        hipLaunchKernelGGL(umat_table_kernel<float>, grid, dim3(256), 0, stream, u_mat, n,
+        hipLaunchKernelGGL(umat_table_kernel<float>, grid, dim3(256), 0, stream, u_mat, N, n,
                            static_cast<float*>(out));
     FTWA_LAUNCH_CHECK("umat_table_kernel");
     return FTWA_OK;

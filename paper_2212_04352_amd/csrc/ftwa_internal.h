@@ -355,7 +355,11 @@ int resident_parts(int config);  // workgroups per spin block (> 1: split tables
 bool resident_has_potential(int config);  // has the external-potential variant
 bool resident_has_hop(int config);        // has the complex-hopping variant
 bool resident_has_interaction(int config);  // has the general-interaction variant
-// u_mat ([N][N] FP64, u_ki at k N + i) rounded once to dtype, same order (queued on stream).
+// Rows of the general-interaction variant's u table: N rounded up to 32.
+__host__ __device__ inline int umat_rows(int N) { return (N + 31) & ~31; }
+// u_mat ([N][N] FP64, u_ki at k N + i) rounded once to dtype, blocked by four
+// along k (((k / 4) N + i) 4 + k % 4), rows N..umat_rows(N)-1 zero (queued on
+// stream; umat_rows(N) N elements).
 ftwa_status umat_table(const double* u_mat, int N, ftwa_dtype dtype, void* out,
                        hipStream_t stream);
 // The ratio table of the complex-hopping variant from ftwa_instance::hop_w
