@@ -81,6 +81,11 @@ def parse():
     ap.add_argument("--batch-traj", type=int, default=2048)
     ap.add_argument("--sequential", action="store_true",
                     help="batch: also time one ftwa_evolve per instance")
+    ap.add_argument("--dtypes", default="f32,f64",
+                    help="pulse, longrange, peierls: the precisions to run (comma list)")
+    ap.add_argument("--paths", default=None,
+                    help="pulse, longrange, peierls: the paths to run (comma list; default "
+                         "resident,stream for pulse, stream,auto for the others)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a "
                          "known-size reference dispatch for HBM byte counters)")
@@ -589,7 +594,8 @@ def run_pulse(args):
     sub = np.asarray(lat.sub, dtype=np.float64)
     v = 1.0 - 2.0 * sub
     rows = []
-    runs = [("f32", "resident"), ("f32", "stream"), ("f64", "resident"), ("f64", "stream")]
+    runs = [(d, q) for d in args.dtypes.split(",")
+            for q in (args.paths or "resident,stream").split(",")]
     for dtype, path in runs:
         for with_pot in (False, True):
             p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
@@ -652,8 +658,8 @@ def run_longrange(args):
     M = args.traj or 4096
     steps = args.horizon_steps or 400
     rows = []
-    for dtype in ("f32", "f64"):
-        for path in ("stream", "auto"):
+    for dtype in args.dtypes.split(","):
+        for path in (args.paths or "stream,auto").split(","):
             for general in (False, True):
                 p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
                 if general:
@@ -717,8 +723,8 @@ def run_peierls(args):
     w = np.where(fwd[None], z, np.conj(z))
     w[:, np.arange(3)[None, :] >= lat.deg[:, None]] = 0
     rows = []
-    for dtype in ("f32", "f64"):
-        for path in ("stream", "auto"):
+    for dtype in args.dtypes.split(","):
+        for path in (args.paths or "stream,auto").split(","):
             for peierls in (False, True):
                 p = ft.Problem.allocate(lat, 3.3, M, lat.fock_start("neel"), dtype)
                 if peierls:

@@ -440,9 +440,22 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 // D_i = sum_k u_ki (d_k + 1/2) over the partner's diagonal, one ascending
 // fused chain per site, into LDS after the diagonal copies (in their
 // layout), and the U factor of an element is D_i - D_j (U = 1 exactly).
+// Minimum waves per SIMD the compiler must leave room for.  The FP32 tile of
+// 16 units of 64 threads (lattices up to 15 sites) holds little state per
+// thread: at 64 registers two 1024-thread workgroups share a CU (8 waves per
+// SIMD instead of 4; 10 % faster at 12 sites with eight scratch accesses per
+// lane and RK4 step).  Every other tile keeps the register file for its state
+// (the same hint spills FP64 and larger tiles and makes them 2-5x slower).
+template <typename T, int S, int NTU, int UNITS>
+constexpr int resident_min_waves() {
+    return std::is_same<T, float>::value && S == 2 && NTU == 64 && UNITS == 16 ? 8 : 1;
+}
+
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1,
           bool POT = false, bool HOP = false, bool GINT = false>
-__global__ __launch_bounds__(NTU * UNITS) void rk4_resident(ResidentArgs A) {
+__global__ __launch_bounds__(NTU * UNITS)
+__attribute__((amdgpu_waves_per_eu(resident_min_waves<T, S, NTU, UNITS>(), 8)))
+void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     // descriptor form: compact for the spin split, wide otherwise
     using DT = std::conditional_t<S == 1, uint4, ResDesc>;
