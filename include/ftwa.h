@@ -213,7 +213,8 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        Integrated by the FP32 spin-split resident kernels' complex-hopping
  *        variant where the automatic choice is one of them and the instance
  *        has no v_site (the ratios, rounded once and with unused slots
- *        zeroed, are staged by a kernel into the workspace), else by the
+ *        zeroed, are staged by a kernel into the workspace; each stage keeps
+ *        the first 152 sites' ratios in LDS), else by the
  *        stream kernels; a forced resident path or configuration without the
  *        variant, or with v_site, gives FTWA_ENOTSUP.  Invariant monitors
  *        (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.  Combines

@@ -263,10 +263,14 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // per site at the site's place in the diagonal array (zero for a missing
 // neighbour), so that the diagonal offsets of the descriptor index it.
 // The ratio table of one stage: base and size in bytes (read through a
-// buffer resource: 32-bit offsets, its own wait counter).
+// buffer resource: 32-bit offsets, its own wait counter), and its copy of the
+// first places in LDS (`lds`; places below lds_end / 4, lds_end in diagonal
+// offset units, are read there).
 struct HopTab {
     const unsigned char* p = nullptr;
     int bytes = 0;
+    const unsigned char* lds = nullptr;
+    uint32_t lds_end = 0;
 };
 
 // A site's three FP32 ratios (24 bytes at byte offset `off`).
@@ -305,11 +309,25 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
         // (conjugated) for the row sums; the diagonal offsets are site
         // places x sizeof(T), a ratio triple is 3 sizeof(C) = 6 sizeof(T)
         // (places < 256: a 24-bit product)
+        // (places kHopLds and up from global memory, the first ones from the
+        // stage's copy in LDS: only the lanes of the other kind issue each
+        // access, so the texture unit sees the global ones alone)
         const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
             (void*)Wt.p, (short)0, Wt.bytes, 0x00020000);
+        // (every lane reads LDS, at place 0 when its site is not there, so
+        // that the global loads come after and overwrite those lanes' values)
+        auto triple = [&](uint32_t d, C* w) {
+            const uint32_t o = __umul24(d, 6u);
+            const bool in_lds = d < Wt.lds_end;
+            const C* l = reinterpret_cast<const C*>(Wt.lds + (in_lds ? o : 0u));
+            w[0] = l[0];
+            w[1] = l[1];
+            w[2] = l[2];
+            if (!in_lds) ratio_triple(wr, o, w);
+        };
         C x[6], w[6];
-        ratio_triple(wr, __umul24(e.dj, 6u), w);
-        ratio_triple(wr, __umul24(e.di, 6u), w + 3);
+        triple(e.dj, w);
+        triple(e.di, w + 3);
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
             x[n] = GEN ? lds_at<T>(Yb, e.n[n]) : *reinterpret_cast<const C*>(Yb + e.n[n]);
@@ -440,6 +458,12 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 // D_i = sum_k u_ki (d_k + 1/2) over the partner's diagonal, one ascending
 // fused chain per site, into LDS after the diagonal copies (in their
 // layout), and the U factor of an element is D_i - D_j (U = 1 exactly).
+// Places whose complex-hopping ratios (three FP32 complex numbers, 24 bytes)
+// a stage keeps in LDS: the most that fit beside a 198-site spin block (its
+// elements, the two diagonal copies and the record sums leave 3,712 bytes of
+// the 160 KB); the table's later places are read from global memory.
+constexpr int kHopLds = 152;
+
 // Minimum waves per SIMD the compiler must leave room for.  The FP32 tile of
 // 16 units of 64 threads (lattices up to 15 sites) holds little state per
 // thread: at 64 registers two 1024-thread workgroups share a CU (8 waves per
@@ -521,9 +545,13 @@ void rk4_resident(ResidentArgs A) {
         // apart) first, then the block.  The launch has no static LDS, so the
         // dynamic block starts at LDS address 0 and offsets are addresses (no
         // base register; constant offsets go into the instructions).
-        // S = 1: two diagonal copies, then the potential's profile (POT) or
-        // D and two site-ordered copies of the partner's diagonal (GINT)
-        constexpr uint32_t kPre = S == 1 ? (GINT ? 5 : POT ? 3 : 2) * kDiagCopy : 0;
+        // S = 1: two diagonal copies, then the potential's profile (POT), or
+        // D and two site-ordered copies of the partner's diagonal (GINT), or
+        // the first kHopLds places' ratios of the stage's table (HOP)
+        constexpr uint32_t kPre =
+            S == 1 ? (HOP ? 2 * kDiagCopy + kHopLds * 6 * TB
+                          : (GINT ? 5 : POT ? 3 : 2) * kDiagCopy)
+                   : 0;
         unsigned char* const Yunit = lds_ptr((uint32_t)(kPre + (size_t)unit * S * Pb * CB));
         // GINT: h_k = d_k + 1/2 of the partner's diagonal in site order, copy c
         // (stage parity), zero from N up to the u table's padded row count
@@ -722,11 +750,24 @@ void rk4_resident(ResidentArgs A) {
                     Aw = uniform_real<T>((T)venv[2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)]);
             }
             // the ratio table of this stage's time (the same half-step samples)
+            const int n_lds = N < kHopLds ? N : kHopLds;
             const HopTab Wt{
                 HOP ? hop_tab + (size_t)(2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)) *
                                     (size_t)N * 3 * CB
                     : nullptr,
-                N * 3 * CB};
+                N * 3 * CB, lds_ptr(2 * kDiagCopy), (uint32_t)n_lds * TB};
+            if constexpr (HOP) {
+                // a new table at stages 2 and 4 (stage 1 reuses the previous
+                // step's stage-4 table, except at an item's first step); the
+                // previous stage ended with a barrier, so no thread still reads
+                // the old copy
+                if (STAGE == 2 || STAGE == 4 || cur_step == 0) {
+                    const T* src = reinterpret_cast<const T*>(Wt.p);
+                    for (int k = tid; k < 6 * n_lds; k += NTU)
+                        reinterpret_cast<T*>(lds_ptr(2 * kDiagCopy))[k] = src[k];
+                    __syncthreads();
+                }
+            }
             // general interaction: D of this stage's input (the partner's
             // diagonal in dcur is complete: the previous stage ended with a
             // barrier after it landed), then the elements take D in place of
@@ -1639,10 +1680,12 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if ((int64_t)c.NTU * c.GE < tab.n_gen_even || (int64_t)c.NTU * c.GO < tab.n_gen_odd)
                 continue;
             lds = lds_bytes(c, N, P);
-            // the potential's profile, or the general interaction's D and two
-            // site-ordered copies of the partner's diagonal
+            // the potential's profile, the general interaction's D and two
+            // site-ordered copies of the partner's diagonal, or the first
+            // kHopLds places of the complex-hopping stage table
             const size_t tb = c.dtype == FTWA_F64 ? 8 : 4;
             if (need_interaction) lds += 3 * 256 * tb;
+            else if (need_hop) lds += (size_t)kHopLds * 6 * tb;
             else if (need_potential) lds += 256 * tb;
         }
         if (lds > kMaxLds) continue;
