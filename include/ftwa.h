@@ -187,11 +187,12 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        U (ignored then): Eq. (6)'s own form multiplies rho_ij,s by
  *        D_i - D_j, D_i = sum_k u_ki (rho_kk,sbar + 1/2), accumulated as
  *        D = fma(u_ki, d_k + 1/2, D) over ascending k in the working precision
- *        (u rounded once).  Integrated by the FP32 spin-split resident
- *        kernels' general-interaction variant where the automatic choice is
- *        one of them and the instance has neither v_site nor hop_w (u,
- *        rounded once, is staged by a kernel into the workspace; each stage
- *        forms D in LDS before the elements), else by the stream kernels (a
+ *        (u rounded once).  Integrated by the general-interaction variants
+ *        of the FP32 spin-split resident kernels and the FP64 split kernel
+ *        where the automatic choice is one of them and the instance has
+ *        neither v_site nor hop_w (u, rounded once, is staged by a kernel into
+ *        the workspace; each stage forms D in LDS before the elements), else
+ *        by the stream kernels (a
  *        per-stage kernel forms D for every site and trajectory); a forced
  *        resident path or configuration without the variant, or with v_site
  *        or hop_w, gives FTWA_ENOTSUP.  Invariant monitors (inv: their energy

@@ -183,7 +183,8 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         // with the potential variant (spin split)
         const bool pot = inst[k].v_site != nullptr;
         // a general interaction: the stream kernels, or a resident configuration
-        // with the general-interaction variant (the FP32 spin split; alone)
+        // with the general-interaction variant (the FP32 spin split or the FP64
+        // split kernel; alone)
         const bool gint = inst[k].u_mat != nullptr;
         // complex hopping: the stream kernels, or a resident configuration with
         // the complex-hopping variant (the FP32 spin split; not together with

@@ -1150,9 +1150,14 @@ __device__ __forceinline__ bool settle_words(const uint64_t* const* src, int str
 // the first GO read transposes, exported elements in the first XO.  KB: halo
 // entries per thread whose reads are issued a phase ahead.  POT: entries may
 // carry an external potential (its profile after the two diagonal copies, in
-// their layout; the element slots follow it).
+// their layout; the element slots follow it).  GINT: every entry carries a
+// general interaction u_ij (ResidentInst::umat, as the spin-split kernels
+// read it): every part forms D_i = sum_k u_ki (d_k + 1/2) for all sites at
+// the start of each stage from the partner's whole diagonal (which every
+// part receives), into LDS after the diagonal copies, and the U factor of an
+// element is D_i - D_j (U = 1 exactly).
 template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
-          int KB, bool T1, bool POT = false>
+          int KB, bool T1, bool POT = false, bool GINT = false>
 __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     using C = cplx_t<T>;
     constexpr int CB = (int)sizeof(C);
@@ -1166,6 +1171,7 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     constexpr uint32_t kDiagCopy = 256 * TB;
     static_assert(GE1 <= UB && UB < UE && UB + GE2 <= UE && GO <= UO && XO <= UO,
                   "slot groups within their class");
+    static_assert(!(POT && GINT), "a potential or a general interaction, not both");
     extern __shared__ __align__(16) unsigned char smem[];
     (void)smem;
     const int tid0 = threadIdx.x;
@@ -1210,8 +1216,13 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         const uint32_t* const imp = pord + kEnt;
         const uint32_t* const dsite = imp + hmax;
         const uint32_t* const dsrc = blob + (size_t)G * pw;
-        unsigned char* const Yb = lds_ptr((POT ? 3 : 2) * kDiagCopy);
+        // LDS: two copies of the partner's diagonal (sublattice-major), then
+        // the potential's profile (POT) or D and two site-ordered copies of
+        // h_k = d_k + 1/2, zero from N up to the u table's row count (GINT),
+        // then the part's elements
+        unsigned char* const Yb = lds_ptr((GINT ? 5 : POT ? 3 : 2) * kDiagCopy);
         unsigned char* const dpart = lds_ptr(0);
+        auto hsite = [&](int c) { return reinterpret_cast<T*>(lds_ptr((3 + c) * kDiagCopy)); };
         int& abort_flag = *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU / 64) * 2 * 8));
         const int64_t Mc = E.Mc;
         const int64_t m = item - E.item0;
@@ -1276,7 +1287,20 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
             reinterpret_cast<T*>(dpart + (size_t)(g & 1) * kDiagCopy)[q] =
                 active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0;
             reinterpret_cast<T*>(dpart + (size_t)((g + 1) & 1) * kDiagCopy)[q] = (T)0;
+            if constexpr (GINT) {
+                hsite((int)(g & 1))[i] =
+                    (active ? rho[((int64_t)(1 - spin0) * P + p) * ldr + m].x : (T)0) + (T)0.5;
+                hsite((int)((g + 1) & 1))[i] = (T)0;
+            }
         }
+        if constexpr (GINT) {
+            for (int i = N + t; i < umat_rows(N); i += NTU) {
+                hsite(0)[i] = (T)0;
+                hsite(1)[i] = (T)0;
+            }
+        }
+        // general interaction: u in T, blocked by four along k
+        const T* const utab = GINT ? reinterpret_cast<const T*>(uniform64((uint64_t)E.umat)) : nullptr;
         // external potential of this entry: the profile v (zero without one)
         // and the envelope, read per stage
         const double* const venv = POT ? reinterpret_cast<const double*>(uniform64((uint64_t)E.v_env))
@@ -1354,6 +1378,48 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 if (pot_on)
                     Aw = uniform_real<T>((T)venv[2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)]);
             }
+            // general interaction: D of this stage's input from the
+            // site-ordered copy (complete: the previous stage ended with a
+            // barrier after it landed), one ascending fused chain per site on
+            // threads t < N; u blocked by four along k, two 16-byte loads per
+            // lane and block (FP64), four blocks in flight; padded terms add
+            // exactly +0 (the chain starts at +0 and never holds -0)
+            const unsigned char* Ud = dcur;
+            T Uu = Uw;
+            if constexpr (GINT) {
+                if (t < N) {
+                    constexpr int B = 4;
+                    const int K = umat_rows(N);
+                    const T* const hs = hsite((STAGE - 1) & 1);
+                    const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)utab, (short)0, (int)(K * N * TB), 0x00020000);
+                    T accD = 0;
+                    for (int k0 = 0; k0 < K; k0 += 4 * B) {
+                        double2 ua[B], ub[B];
+#pragma unroll
+                        for (int b = 0; b < B; ++b) {
+                            const int so = (k0 / 4 + b) * N * 32;
+                            ua[b] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                                                    urs, (uint32_t)(t * 32), so, 0));
+                            ub[b] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                                                    urs, (uint32_t)(t * 32 + 16), so, 0));
+                        }
+#pragma unroll
+                        for (int b = 0; b < B; ++b) {
+                            const double2 h0 = *reinterpret_cast<const double2*>(hs + k0 + 4 * b);
+                            const double2 h1 = *reinterpret_cast<const double2*>(hs + k0 + 4 * b + 2);
+                            accD = fma_rn<T>(ua[b].x, h0.x, accD);
+                            accD = fma_rn<T>(ua[b].y, h0.y, accD);
+                            accD = fma_rn<T>(ub[b].x, h1.x, accD);
+                            accD = fma_rn<T>(ub[b].y, h1.y, accD);
+                        }
+                    }
+                    reinterpret_cast<T*>(vpart)[dpos[t]] = accD;
+                }
+                __syncthreads();
+                Ud = vpart;
+                Uu = (T)1;
+            }
             const uint32_t stamp = (uint32_t)(g + 1);
             uint64_t* const mine = xslot(spin0, part, stamp);
             desc = launder(desc);
@@ -1388,8 +1454,8 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 const bool gen = u < GE1 || (u >= UB && u < UB + GE2);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
                 *reinterpret_cast<C*>(Yb + ob) = own;
-                const C kk = element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, dcur, d, tw,
-                                                                          Uw, own, vpart, Aw,
+                const C kk = element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, Ud, d, tw,
+                                                                          Uu, own, vpart, Aw,
                                                                           pot_on);
                 hold[u] = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 pin(hold[u]);
@@ -1420,9 +1486,9 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 const bool xp = u - UE < XO;
                 const bool gen = u - UE < GO;
                 const C kk = STAGE == 1
-                    ? element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, dcur, d, tw, Uw,
+                    ? element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, Ud, d, tw, Uu,
                                                                    y[u], vpart, Aw, pot_on)
-                    : element_rhs_split<T, false, T1, SH, DSH, POT>(gen, xp, Yb, dcur, d, tw, Uw,
+                    : element_rhs_split<T, false, T1, SH, DSH, POT>(gen, xp, Yb, Ud, d, tw, Uu,
                                                                     y[u], vpart, Aw, pot_on);
                 const C nx = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
@@ -1438,6 +1504,7 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
 #pragma unroll
                 for (int kk = 0; kk < W; ++kk) pl.w[kk] = kk < DW ? (uint32_t)dw[kk] : 0u;
                 reinterpret_cast<T*>(dpart + (STAGE & 1) * kDiagCopy)[dpos[t]] = from_payload<T>(pl).x;
+                if constexpr (GINT) hsite(STAGE & 1)[t] = from_payload<T>(pl).x + (T)0.5;
             }
             __syncthreads();
             ++g;
@@ -1501,7 +1568,7 @@ struct Config {
     const void* fn_pot_t1 = nullptr;  // the same for launches with t = 1 (FP32 spin split)
     const void* fn_hop = nullptr;     // variant with complex hopping (FP32 spin split)
     const void* fn_hop_t1 = nullptr;  // the same for launches with t = 1
-    const void* fn_gint = nullptr;    // variant with a general interaction (FP32 spin split)
+    const void* fn_gint = nullptr;    // variant with a general interaction (FP32 spin split, FP64 split)
     const void* fn_gint_t1 = nullptr;
 };
 
@@ -1570,7 +1637,10 @@ constexpr const void* split_unit_hop_fn() {
     Config{DT, 1, NTU, 1, UE, UO, GE1, GO,                                                   \
            (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false>,     \
            split_unit_hop_fn<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB>(), G, UB, GE2, XO, KB, \
-           AUTO, (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false, true>}
+           AUTO, (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false, true>, \
+           nullptr, nullptr, nullptr,                                                        \
+           (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false, false, true>, \
+           nullptr}
 
 const Config kConfigs[] = {
     FTWA_RES_CFG(double, FTWA_F64, 2, 64, 16, 1, 1, 1, 1),
@@ -1673,7 +1743,8 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if (n * c.GO < sh.odd_gen || n * c.XO < sh.odd_x) continue;
             if (sh.max_slots + 33 > 0x7fff) continue;
             lds = split_lds_bytes(c, sh.max_slots);
-            if (need_potential) lds += 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // the profile
+            if (need_interaction) lds += 3 * 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // D, h copies
+            else if (need_potential) lds += 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // the profile
         } else {
             if (P + 33 > 0x7fff) continue;
             if ((int64_t)c.NTU * c.UE < n_even || (int64_t)c.NTU * c.UO < n_odd) continue;
@@ -1736,9 +1807,12 @@ ftwa_status resident_prepare(int config, size_t lds) {
     if (kConfigs[config].fn_pot)
         FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn_pot,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
-    if (kConfigs[config].fn_pot_t1)
-        FTWA_HIP_TRY(hipFuncSetAttribute(kConfigs[config].fn_pot_t1,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+    for (const void* f : {kConfigs[config].fn_pot_t1, kConfigs[config].fn_hop,
+                          kConfigs[config].fn_hop_t1, kConfigs[config].fn_gint,
+                          kConfigs[config].fn_gint_t1})
+        if (f)
+            FTWA_HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)kMaxLds));
     return FTWA_OK;
 }
 

@@ -1,9 +1,10 @@
 """A general density-density interaction u_ij between opposite spins (Eq. (1),
 Eq. (6)'s own form) through the C ABI: the stream kernels (a per-stage kernel
-forming D_i = sum_k u_ki (d_k + 1/2), fma over ascending k) and the FP32
-spin-split resident kernels (D formed at the start of every stage from the
-partner's diagonal) against the oracle bitwise, together with an external
-potential, in a batch with an on-site instance, and the paths that refuse it."""
+forming D_i = sum_k u_ki (d_k + 1/2), fma over ascending k), the FP32
+spin-split resident kernels and the FP64 split kernel (D formed at the start
+of every stage from the partner's diagonal) against the oracle bitwise,
+together with an external potential, in a batch with an on-site instance, and
+the paths that refuse it."""
 import numpy as np
 import pytest
 
@@ -127,6 +128,37 @@ def test_resident_interaction_matches_oracle_bitwise(ft, orc, kind, a, b, config
     assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("kind,a,b,config,t", [
+    ("hex", 5, 0, -1, 1.0),          # 150 sites: the automatic choice (two parts of 768)
+    ("hex", 5, 0, 19, 0.7),          # two parts of 512, t != 1
+    ("armchair", 10, 20, -1, 1.0),   # 198 sites: the automatic choice (three parts of 512)
+    ("armchair", 10, 20, 21, 1.0),   # four parts of 512
+])
+def test_split_interaction_matches_oracle_bitwise(ft, orc, kind, a, b, config, t):
+    """The FP64 split kernel's general-interaction variant: every part forms
+    D_i over ascending k from the partner's whole diagonal (site-ordered copy
+    in LDS) and u (FP64, blocked by four along k) per stage; the elements of
+    every part take D_i - D_j as their U factor."""
+    import torch
+    dt, steps, re = 0.01, 8, 4
+    olat = orc.Lattice(kind, a, b, t)
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = orc.fock_start(olat, "random", 15)
+    M = 7
+    rho0 = orc.sample(olat, n0, 15, M)
+    prob = ft.Problem.allocate(lat, 0.0, M, n0, "f64")
+    prob.rho.copy_(torch.from_numpy(pack(rho0)))
+    u = _long_range(olat, 3.3, 15)
+    prob.u_mat = torch.from_numpy(u).cuda()
+    ft.evolve(prob, dt, steps, re, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, umat=u)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
 def test_resident_interaction_next_to_on_site_instances(ft, orc):
     """One automatic call: a 198-site general-u instance (its own launch
     group, the variant's larger LDS layout) next to a 198-site on-site
@@ -171,12 +203,7 @@ def test_resident_interaction_graph_replays(ft, orc):
 def test_paths_that_refuse_a_general_interaction(ft, orc):
     import torch
     olat, lat, rho0, prob, u, _ = _setup(ft, orc, "armchair", 10, 20, 4, "f32", 5)
-    # FP64: the split kernel has no general-interaction variant
-    o64, l64, r64, p64, u64, _ = _setup(ft, orc, "armchair", 10, 20, 4, "f64", 5)
-    with pytest.raises(ft.FtwaError) as e:
-        ft.evolve(p64, 0.01, 2, 1, path="resident")
-    assert e.value.status == -4
-    # nor do the shared-block tiles
+    # the shared-block tiles have no general-interaction variant
     os_, ls, rs, ps, us, _ = _setup(ft, orc, "torus", 2, 3, 8, "f32", 5)
     with pytest.raises(ft.FtwaError) as e:
         ft.evolve(ps, 0.01, 2, 1, config=4)
