@@ -634,9 +634,9 @@ def run_longrange(args):
     """A general density-density interaction on the 198-site flake: u_ii = 3.3,
     u_ij = exp(-d_ij) / 2 between sites (d_ij the graph distance, a screened
     tail), FP32 and FP64, 4096 trajectories x 400 steps, on the stream kernels
-    and on the automatic path (FP32: the spin-split resident kernel's
-    general-interaction variant; FP64: the stream kernels, the split kernel
-    has none), next to the on-site run of the same paths."""
+    and on the automatic path (the general-interaction variants of the FP32
+    spin-split and FP64 split resident kernels), next to the on-site run of
+    the same paths."""
     import numpy as np
     import torch
     from collections import deque
@@ -693,9 +693,9 @@ def run_peierls(args):
     j_ik(tau) = t exp(i (x_k - x_i) B(tau)), x the graph distance from site 0
     (a stand-in for the coordinate along the field), B(tau) = 0.5 sin(2 tau),
     tables at half steps; FP32 and FP64, 4096 trajectories x 400 steps, on the
-    stream kernels and on the automatic path (FP32: the spin-split resident
-    kernel's complex-hopping variant; FP64: the stream kernels, the split
-    kernel has none), next to real hopping on the same paths."""
+    stream kernels and on the automatic path (the complex-hopping variants of
+    the FP32 spin-split and FP64 split resident kernels), next to real
+    hopping on the same paths."""
     import numpy as np
     import torch
     from collections import deque

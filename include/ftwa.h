@@ -211,12 +211,13 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        (fma(wr, xr, -(wi xi)), fma(wr, xi, wi xr)) with w rounded once to
  *        the working precision, slots summed in ascending order; slots
  *        n >= deg(i) are ignored (any finite or non-finite value).
- *        Integrated by the FP32 spin-split resident kernels' complex-hopping
- *        variant where the automatic choice is one of them and the instance
- *        has no v_site (the ratios, rounded once and with unused slots
- *        zeroed, are staged by a kernel into the workspace; each stage keeps
- *        the first 152 sites' ratios in LDS), else by the
- *        stream kernels; a forced resident path or configuration without the
+ *        Integrated by the complex-hopping variants of the FP32 spin-split
+ *        resident kernels and the FP64 split kernel where the automatic
+ *        choice is one of them and the instance has no v_site (the ratios,
+ *        rounded once and with unused slots zeroed, are staged by a kernel
+ *        into the workspace; each stage keeps the first 152 sites' ratios in
+ *        LDS, all of them in FP64), else by the stream kernels; a forced
+ *        resident path or configuration without the
  *        variant, or with v_site, gives FTWA_ENOTSUP.  Invariant monitors
  *        (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.  Combines
  *        with v_site and u_mat on the stream kernels.  hop_w must hold

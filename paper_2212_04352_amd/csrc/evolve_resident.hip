@@ -273,7 +273,17 @@ struct HopTab {
     uint32_t lds_end = 0;
 };
 
-// A site's three FP32 ratios (24 bytes at byte offset `off`).
+// A site's three ratios (24 bytes in FP32, 48 in FP64, at byte offset `off`).
+__device__ __forceinline__ void ratio_triple(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                             cplx_t<double>* w) {
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        const double2 a =
+            __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16 * n, 0, 0));
+        w[n].x = a.x;
+        w[n].y = a.y;
+    }
+}
 __device__ __forceinline__ void ratio_triple(__amdgpu_buffer_rsrc_t r, uint32_t off,
                                              cplx_t<float>* w) {
     const float4 a = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
@@ -304,7 +314,6 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
     using C = cplx_t<T>;
     C col, row;
     if constexpr (HOP) {
-        static_assert(std::is_same<T, float>::value, "complex hopping: FP32 resident kernels");
         // ratios of the element's sites: j's for the column sums, i's
         // (conjugated) for the row sums; the diagonal offsets are site
         // places x sizeof(T), a ratio triple is 3 sizeof(C) = 6 sizeof(T)
@@ -1068,16 +1077,18 @@ __device__ __forceinline__ Stencil decode_split(const uint4& w, bool xp) {
     return e;
 }
 
-template <typename T, bool OWN_REG, bool T1, int SH, int DSH, bool POT = false>
+template <typename T, bool OWN_REG, bool T1, int SH, int DSH, bool POT = false, bool HOP = false>
 __device__ __forceinline__ cplx_t<T> element_rhs_split(bool gen, bool xp, const unsigned char* Yb,
                                                        const unsigned char* Yd, const uint4& d,
                                                        T t, T U, cplx_t<T> own,
                                                        const unsigned char* Vd = nullptr,
-                                                       T Aw = 0, bool pot_on = false) {
-    return gen ? element_rhs<T, OWN_REG, true, T1, POT>(Yb, Yd, decode_split<SH, DSH, true>(d, xp),
-                                                        t, U, own, Vd, Aw, pot_on)
-               : element_rhs<T, OWN_REG, false, T1, POT>(Yb, Yd, decode_split<SH, DSH, false>(d, xp),
-                                                         t, U, own, Vd, Aw, pot_on);
+                                                       T Aw = 0, bool pot_on = false,
+                                                       HopTab Wt = {}) {
+    return gen ? element_rhs<T, OWN_REG, true, T1, POT, HOP>(Yb, Yd, decode_split<SH, DSH, true>(d, xp),
+                                                             t, U, own, Vd, Aw, pot_on, Wt)
+               : element_rhs<T, OWN_REG, false, T1, POT, HOP>(Yb, Yd,
+                                                              decode_split<SH, DSH, false>(d, xp),
+                                                              t, U, own, Vd, Aw, pot_on, Wt);
 }
 
 // A complex value as 32-bit payload words and back.
@@ -1155,9 +1166,11 @@ __device__ __forceinline__ bool settle_words(const uint64_t* const* src, int str
 // read it): every part forms D_i = sum_k u_ki (d_k + 1/2) for all sites at
 // the start of each stage from the partner's whole diagonal (which every
 // part receives), into LDS after the diagonal copies, and the U factor of an
-// element is D_i - D_j (U = 1 exactly).
+// element is D_i - D_j (U = 1 exactly).  HOP: every entry carries complex
+// hopping (ResidentInst::hop, as the spin-split kernels read it); each stage
+// keeps the whole ratio table of its time in LDS after the diagonal copies.
 template <typename T, int G, int NTU, int UE, int UO, int UB, int GE1, int GE2, int GO, int XO,
-          int KB, bool T1, bool POT = false, bool GINT = false>
+          int KB, bool T1, bool POT = false, bool GINT = false, bool HOP = false>
 __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     using C = cplx_t<T>;
     constexpr int CB = (int)sizeof(C);
@@ -1171,7 +1184,8 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
     constexpr uint32_t kDiagCopy = 256 * TB;
     static_assert(GE1 <= UB && UB < UE && UB + GE2 <= UE && GO <= UO && XO <= UO,
                   "slot groups within their class");
-    static_assert(!(POT && GINT), "a potential or a general interaction, not both");
+    static_assert((POT ? 1 : 0) + (GINT ? 1 : 0) + (HOP ? 1 : 0) <= 1,
+                  "one of a potential, a general interaction and complex hopping");
     extern __shared__ __align__(16) unsigned char smem[];
     (void)smem;
     const int tid0 = threadIdx.x;
@@ -1219,8 +1233,10 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         // LDS: two copies of the partner's diagonal (sublattice-major), then
         // the potential's profile (POT) or D and two site-ordered copies of
         // h_k = d_k + 1/2, zero from N up to the u table's row count (GINT),
-        // then the part's elements
-        unsigned char* const Yb = lds_ptr((GINT ? 5 : POT ? 3 : 2) * kDiagCopy);
+        // then the part's elements; HOP: the stage's ratio table (256 places)
+        // in place of those
+        unsigned char* const Yb =
+            lds_ptr(HOP ? 2 * kDiagCopy + 256 * 6 * TB : (GINT ? 5 : POT ? 3 : 2) * kDiagCopy);
         unsigned char* const dpart = lds_ptr(0);
         auto hsite = [&](int c) { return reinterpret_cast<T*>(lds_ptr((3 + c) * kDiagCopy)); };
         int& abort_flag = *reinterpret_cast<int*>(lds_ptr(A.tail_off + (NTU / 64) * 2 * 8));
@@ -1301,6 +1317,9 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
         }
         // general interaction: u in T, blocked by four along k
         const T* const utab = GINT ? reinterpret_cast<const T*>(uniform64((uint64_t)E.umat)) : nullptr;
+        // complex hopping: the prepared ratio tables, [2 n_steps + 1][N][3]
+        const unsigned char* const hop_tab =
+            HOP ? reinterpret_cast<const unsigned char*>(uniform64((uint64_t)E.hop)) : nullptr;
         // external potential of this entry: the profile v (zero without one)
         // and the envelope, read per stage
         const double* const venv = POT ? reinterpret_cast<const double*>(uniform64((uint64_t)E.v_env))
@@ -1384,6 +1403,22 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
             // threads t < N; u blocked by four along k, two 16-byte loads per
             // lane and block (FP64), four blocks in flight; padded terms add
             // exactly +0 (the chain starts at +0 and never holds -0)
+            // complex hopping: this stage's ratio table, all of it in LDS
+            // (copied when the table changes: stages 2 and 4, and an item's
+            // first stage; the previous stage ended with a barrier)
+            const HopTab Wt{
+                HOP ? hop_tab + (size_t)(2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)) *
+                                    (size_t)N * 3 * CB
+                    : nullptr,
+                N * 3 * CB, lds_ptr(2 * kDiagCopy), (uint32_t)N * TB};
+            if constexpr (HOP) {
+                if (STAGE == 2 || STAGE == 4 || cur_step == 0) {
+                    const T* src = reinterpret_cast<const T*>(Wt.p);
+                    for (int k = t; k < 6 * N; k += NTU)
+                        reinterpret_cast<T*>(lds_ptr(2 * kDiagCopy))[k] = src[k];
+                    __syncthreads();
+                }
+            }
             const unsigned char* Ud = dcur;
             T Uu = Uw;
             if constexpr (GINT) {
@@ -1454,9 +1489,8 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 const bool gen = u < GE1 || (u >= UB && u < UB + GE2);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
                 *reinterpret_cast<C*>(Yb + ob) = own;
-                const C kk = element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, Ud, d, tw,
-                                                                          Uu, own, vpart, Aw,
-                                                                          pot_on);
+                const C kk = element_rhs_split<T, true, T1, SH, DSH, POT, HOP>(
+                    gen, xp, Yb, Ud, d, tw, Uu, own, vpart, Aw, pot_on, Wt);
                 hold[u] = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 pin(hold[u]);
                 pin(acc[u]);
@@ -1486,10 +1520,10 @@ __global__ __launch_bounds__(NTU) void rk4_split(ResidentArgs A) {
                 const bool xp = u - UE < XO;
                 const bool gen = u - UE < GO;
                 const C kk = STAGE == 1
-                    ? element_rhs_split<T, true, T1, SH, DSH, POT>(gen, xp, Yb, Ud, d, tw, Uu,
-                                                                   y[u], vpart, Aw, pot_on)
-                    : element_rhs_split<T, false, T1, SH, DSH, POT>(gen, xp, Yb, Ud, d, tw, Uu,
-                                                                    y[u], vpart, Aw, pot_on);
+                    ? element_rhs_split<T, true, T1, SH, DSH, POT, HOP>(gen, xp, Yb, Ud, d, tw, Uu,
+                                                                        y[u], vpart, Aw, pot_on, Wt)
+                    : element_rhs_split<T, false, T1, SH, DSH, POT, HOP>(gen, xp, Yb, Ud, d, tw, Uu,
+                                                                         y[u], vpart, Aw, pot_on, Wt);
                 const C nx = rk_update<STAGE, T>(c, kk, y[u], acc[u]);
                 const uint32_t ob = xp ? (d.w & 0x7fffu) << SH : lo16_shl<SH>(d.w);
                 *reinterpret_cast<C*>(Yb + ob) = nx;
@@ -1566,7 +1600,7 @@ struct Config {
     bool auto_pick = true;  // false: chosen only when forced or by the autotuner
     const void* fn_pot = nullptr;  // variant with the external potential (spin split)
     const void* fn_pot_t1 = nullptr;  // the same for launches with t = 1 (FP32 spin split)
-    const void* fn_hop = nullptr;     // variant with complex hopping (FP32 spin split)
+    const void* fn_hop = nullptr;     // variant with complex hopping (FP32 spin split, FP64 split)
     const void* fn_hop_t1 = nullptr;  // the same for launches with t = 1
     const void* fn_gint = nullptr;    // variant with a general interaction (FP32 spin split, FP64 split)
     const void* fn_gint_t1 = nullptr;
@@ -1638,7 +1672,10 @@ constexpr const void* split_unit_hop_fn() {
            (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false>,     \
            split_unit_hop_fn<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB>(), G, UB, GE2, XO, KB, \
            AUTO, (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false, true>, \
-           nullptr, nullptr, nullptr,                                                        \
+           nullptr,                                                                          \
+           (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false, false, false, \
+                                   true>,                                                    \
+           nullptr,                                                                          \
            (const void*)&rk4_split<T, G, NTU, UE, UO, UB, GE1, GE2, GO, XO, KB, false, false, true>, \
            nullptr}
 
@@ -1744,6 +1781,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if (sh.max_slots + 33 > 0x7fff) continue;
             lds = split_lds_bytes(c, sh.max_slots);
             if (need_interaction) lds += 3 * 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // D, h copies
+            else if (need_hop) lds += 256 * 6 * (c.dtype == FTWA_F64 ? 8 : 4);  // ratio table
             else if (need_potential) lds += 256 * (c.dtype == FTWA_F64 ? 8 : 4);  // the profile
         } else {
             if (P + 33 > 0x7fff) continue;

@@ -1,6 +1,7 @@
 """Complex, time-dependent (Peierls) hopping j_ik(tau) = t w_ik(tau) through
-the C ABI: the stream kernels and the FP32 spin-split resident kernels (every
-spin-split configuration, t = 1 and t != 1) against the oracle bitwise, the
+the C ABI: the stream kernels, the FP32 spin-split resident kernels (every
+spin-split configuration, t = 1 and t != 1) and the FP64 split kernel (two,
+three and four parts) against the oracle bitwise, the
 ratio table built for each side from its own neighbour table; together with
 an external potential and a general interaction in a batch with a
 real-hopping instance; graph replays; and the paths that refuse it."""
@@ -172,6 +173,37 @@ def test_resident_peierls_matches_oracle_bitwise(ft, orc, kind, a, b, config, t)
     assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("kind,a,b,config,t", [
+    ("hex", 5, 0, -1, 1.0),          # 150 sites: the automatic choice (two parts of 768)
+    ("hex", 5, 0, 19, 0.8),          # two parts of 512, t != 1
+    ("armchair", 10, 20, -1, 1.0),   # 198 sites: the automatic choice (three parts of 512)
+    ("armchair", 10, 20, 21, 1.0),   # four parts of 512
+])
+def test_split_peierls_matches_oracle_bitwise(ft, orc, kind, a, b, config, t):
+    """The FP64 split kernel's complex-hopping variant: each stage's whole
+    ratio table in LDS, read by the elements of every part through the
+    descriptors' diagonal offsets; unused slots hold NaN on the caller's side."""
+    import torch
+    dt, steps, re = 0.01, 8, 4
+    olat = orc.Lattice(kind, a, b, t)
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = orc.fock_start(olat, "random", 13)
+    M = 7
+    rho0 = orc.sample(olat, n0, 13, M)
+    prob = ft.Problem.allocate(lat, 3.3, M, n0, "f64")
+    prob.rho.copy_(torch.from_numpy(pack(rho0)))
+    fn = _phase_fn(olat.N, 13, dt)
+    w = _table(olat.nbr, olat.deg, fn, 2 * steps + 1)
+    prob.hop_w = torch.from_numpy(_table(lat.nbr, lat.deg, fn, 2 * steps + 1, fill=np.nan)).cuda()
+    ft.evolve(prob, dt, steps, re, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, hop=w)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
 def test_resident_peierls_graph_replays(ft, orc):
     """The resident variant captured in a graph (the table preparation is a
     kernel of the graph) and replayed twice equals two direct runs."""
@@ -194,12 +226,7 @@ def test_resident_peierls_graph_replays(ft, orc):
 def test_paths_that_refuse_complex_hopping(ft, orc):
     import torch
     olat, lat, rho0, prob, w, _ = _setup(ft, orc, "armchair", 10, 20, 4, 3.3, "f32", 5, 2, 0.01)
-    # FP64: the split kernel has no complex-hopping variant
-    o64, l64, r64, p64, w64, _ = _setup(ft, orc, "armchair", 10, 20, 4, 3.3, "f64", 5, 2, 0.01)
-    with pytest.raises(ft.FtwaError) as e:
-        ft.evolve(p64, 0.01, 2, 1, path="resident")
-    assert e.value.status == -4
-    # the shared-block tiles have none either
+    # the shared-block tiles have no complex-hopping variant
     os_, ls, rs, ps, ws_, _ = _setup(ft, orc, "torus", 2, 3, 8, 3.3, "f32", 5, 2, 0.01)
     with pytest.raises(ft.FtwaError) as e:
         ft.evolve(ps, 0.01, 2, 1, config=4)
