@@ -159,36 +159,39 @@ def test_split_interaction_matches_oracle_bitwise(ft, orc, kind, a, b, config, t
     assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
 
 
-def test_resident_interaction_next_to_on_site_instances(ft, orc):
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_resident_interaction_next_to_on_site_instances(ft, orc, dtype):
     """One automatic call: a 198-site general-u instance (its own launch
     group, the variant's larger LDS layout) next to a 198-site on-site
-    instance of the same configuration, several passes of windows."""
+    instance of the same configuration, several passes of windows (FP32:
+    the spin-split tile; FP64: the split kernel)."""
     import torch
     dt, steps, re = 0.01, 6, 3
-    o1, l1, r1, p1, u1, _ = _setup(ft, orc, "armchair", 10, 20, 7, "f32", 21)
+    o1, l1, r1, p1, u1, cdt = _setup(ft, orc, "armchair", 10, 20, 7, dtype, 21)
     n2 = orc.fock_start(o1, "random", 22)
     r2 = orc.sample(o1, n2, 22, 5)
-    p2 = ft.Problem.allocate(l1, 3.3, 5, n2, "f32", instance=1)
-    p2.rho.copy_(torch.from_numpy(pack(r2.astype(np.complex64))))
+    p2 = ft.Problem.allocate(l1, 3.3, 5, n2, dtype, instance=1)
+    p2.rho.copy_(torch.from_numpy(pack(r2.astype(cdt))))
     ft.evolve([p1, p2], dt, steps, re, traj_chunk=3)
-    y1, _, _ = orc.evolve(o1, 0.0, r1, dt, steps, re, precision="f32", umat=u1)
-    y2, _, _ = orc.evolve(o1, 3.3, r2, dt, steps, re, precision="f32")
-    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1.astype(np.complex64))
-    assert np.array_equal(unpack(_host(p2.rho), l1.N), y2.astype(np.complex64))
+    y1, _, _ = orc.evolve(o1, 0.0, r1, dt, steps, re, precision=dtype, umat=u1)
+    y2, _, _ = orc.evolve(o1, 3.3, r2, dt, steps, re, precision=dtype)
+    assert np.array_equal(unpack(_host(p1.rho), l1.N), y1.astype(cdt))
+    assert np.array_equal(unpack(_host(p2.rho), l1.N), y2.astype(cdt))
 
 
-def test_resident_interaction_graph_replays(ft, orc):
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_resident_interaction_graph_replays(ft, orc, dtype):
     """The resident variant captured in a graph (staging u in the working
     precision is a kernel of the graph) and replayed twice equals two direct
     runs; the first replay also equals the oracle."""
     import torch
     dt, steps, re = 0.01, 6, 3
-    olat, lat, rho0, prob, u, _ = _setup(ft, orc, "armchair", 10, 20, 6, "f32", 8)
-    ref = ft.Problem.allocate(lat, 0.0, 6, prob.n0.cpu().numpy(), "f32")
+    olat, lat, rho0, prob, u, cdt = _setup(ft, orc, "armchair", 10, 20, 6, dtype, 8)
+    ref = ft.Problem.allocate(lat, 0.0, 6, prob.n0.cpu().numpy(), dtype)
     ref.rho.copy_(prob.rho)
     ref.u_mat = prob.u_mat
     g = ft.EvolveGraph([prob], dt, steps, re, path="resident")
-    y_ref, _, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, precision="f32", umat=u)
+    y_ref, _, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, precision=dtype, umat=u)
     for r in range(2):
         g.launch()
         g.check()
@@ -196,7 +199,7 @@ def test_resident_interaction_graph_replays(ft, orc):
         torch.cuda.synchronize()
         assert torch.equal(prob.rho, ref.rho)
         if r == 0:
-            assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref.astype(np.complex64))
+            assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref.astype(cdt))
     g.close()
 
 

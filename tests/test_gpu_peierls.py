@@ -204,22 +204,29 @@ def test_split_peierls_matches_oracle_bitwise(ft, orc, kind, a, b, config, t):
     assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
 
 
-def test_resident_peierls_graph_replays(ft, orc):
-    """The resident variant captured in a graph (the table preparation is a
-    kernel of the graph) and replayed twice equals two direct runs."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_resident_peierls_graph_replays(ft, orc, dtype):
+    """The resident variant (FP32: the spin-split tile; FP64: the split
+    kernel) captured in a graph (the table preparation is a kernel of the
+    graph) and replayed twice equals two direct runs; the first replay also
+    equals the oracle."""
     import torch
     dt, steps, re = 0.01, 6, 3
-    olat, lat, rho0, prob, w, _ = _setup(ft, orc, "armchair", 10, 20, 6, 3.3, "f32", 7, steps, dt)
-    ref = ft.Problem.allocate(lat, 3.3, 6, prob.n0.cpu().numpy(), "f32")
+    olat, lat, rho0, prob, w, cdt = _setup(ft, orc, "armchair", 10, 20, 6, 3.3, dtype, 7, steps,
+                                           dt)
+    ref = ft.Problem.allocate(lat, 3.3, 6, prob.n0.cpu().numpy(), dtype)
     ref.rho.copy_(prob.rho)
     ref.hop_w = prob.hop_w
     g = ft.EvolveGraph([prob], dt, steps, re, path="resident")
-    for _ in range(2):
+    y_ref, _, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype, hop=w)
+    for r in range(2):
         g.launch()
         g.check()
         ft.evolve(ref, dt, steps, re, path="resident")
         torch.cuda.synchronize()
         assert torch.equal(prob.rho, ref.rho)
+        if r == 0:
+            assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref.astype(cdt))
     g.close()
 
 
