@@ -215,8 +215,8 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        resident kernels and the FP64 split kernel where the automatic
  *        choice is one of them and the instance has no v_site (the ratios,
  *        rounded once and with unused slots zeroed, are staged by a kernel
- *        into the workspace; each stage keeps the first 152 sites' ratios in
- *        LDS, all of them in FP64), else by the stream kernels; a forced
+ *        into the workspace; each stage keeps the ratios of up to 152 sites
+ *        in LDS in FP32, of all sites in FP64), else by the stream kernels; a forced
  *        resident path or configuration without the
  *        variant, or with v_site, gives FTWA_ENOTSUP.  Invariant monitors
  *        (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.  Combines

@@ -314,17 +314,16 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
     using C = cplx_t<T>;
     C col, row;
     if constexpr (HOP) {
-        // ratios of the element's sites: j's for the column sums, i's
-        // (conjugated) for the row sums; the diagonal offsets are site
-        // places x sizeof(T), a ratio triple is 3 sizeof(C) = 6 sizeof(T)
-        // (places < 256: a 24-bit product)
-        // (places kHopLds and up from global memory, the first ones from the
-        // stage's copy in LDS: only the lanes of the other kind issue each
-        // access, so the texture unit sees the global ones alone)
+        // Ratios of the element's sites: j's for the column sums, i's
+        // (conjugated) for the row sums.  The diagonal offsets are site
+        // places x sizeof(T) and a ratio triple is 3 sizeof(C) = 6 sizeof(T)
+        // (places < 256: a 24-bit product).  Places below Wt.lds_end / sizeof(T)
+        // come from the stage's copy in LDS, the others from global memory:
+        // every lane reads LDS (at place 0 when its site is not there) and
+        // only the other lanes then issue the global loads, which overwrite
+        // those values, so the texture unit sees the global reads alone.
         const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
             (void*)Wt.p, (short)0, Wt.bytes, 0x00020000);
-        // (every lane reads LDS, at place 0 when its site is not there, so
-        // that the global loads come after and overwrite those lanes' values)
         auto triple = [&](uint32_t d, C* w) {
             const uint32_t o = __umul24(d, 6u);
             const bool in_lds = d < Wt.lds_end;
@@ -790,11 +789,11 @@ void rk4_resident(ResidentArgs A) {
                     // four terms of the chain and a wave reads one contiguous
                     // segment; four such loads are in flight per batch of 16
                     // terms (eight spill registers of the held state at 13 + 13
-                    // slots and ran 4 % slower).  h_k = d_k + 1/2 comes from the site-ordered copy
-                    // (one wave-uniform 16-byte LDS read per four terms).  The
-                    // padded terms are fma(0, 0, D) = D + 0 = D exactly (D never
-                    // holds -0: it starts at +0 and a round-to-nearest sum is -0
-                    // only when both addends are).
+                    // slots and ran 4 % slower).  h_k = d_k + 1/2 comes from the
+                    // site-ordered copy (one wave-uniform 16-byte LDS read per
+                    // four terms).  The padded terms are fma(0, 0, D) = D + 0 = D
+                    // exactly (D never holds -0: it starts at +0 and a
+                    // round-to-nearest sum is -0 only when both addends are).
                     constexpr int B = 4;
                     const int K = umat_rows(N);
                     const T* const hs = dsite((STAGE - 1) & 1);
