@@ -187,8 +187,8 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         // split kernel; alone)
         const bool gint = inst[k].u_mat != nullptr;
         // complex hopping: the stream kernels, or a resident configuration with
-        // the complex-hopping variant (the FP32 spin split; not together with
-        // a potential)
+        // the complex-hopping variant (the FP32 spin split or the FP64 split
+        // kernel; alone)
         const bool hop = inst[k].hop_w != nullptr;
         const int n_var = (pot ? 1 : 0) + (hop ? 1 : 0) + (gint ? 1 : 0);
         if (n_var > 1 && (want == FTWA_PATH_RESIDENT || force >= 0))

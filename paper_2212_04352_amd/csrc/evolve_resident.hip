@@ -1597,11 +1597,14 @@ struct Config {
     int G = 1;
     int UB = 0, GE2 = 0, XO = 0, KB = 0;
     bool auto_pick = true;  // false: chosen only when forced or by the autotuner
-    const void* fn_pot = nullptr;  // variant with the external potential (spin split)
-    const void* fn_pot_t1 = nullptr;  // the same for launches with t = 1 (FP32 spin split)
-    const void* fn_hop = nullptr;     // variant with complex hopping (FP32 spin split, FP64 split)
-    const void* fn_hop_t1 = nullptr;  // the same for launches with t = 1
-    const void* fn_gint = nullptr;    // variant with a general interaction (FP32 spin split, FP64 split)
+    // variants (the FP32 spin split and the FP64 split kernel; _t1: the same
+    // for launches with t = 1, FP32 only): external potential, complex
+    // hopping, general interaction
+    const void* fn_pot = nullptr;
+    const void* fn_pot_t1 = nullptr;
+    const void* fn_hop = nullptr;
+    const void* fn_hop_t1 = nullptr;
+    const void* fn_gint = nullptr;
     const void* fn_gint_t1 = nullptr;
 };
 

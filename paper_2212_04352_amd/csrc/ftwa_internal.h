@@ -342,10 +342,9 @@ struct ResidentLaunch {
 };
 // Picks the first kernel configuration that fits (or only `force_config` if >= 0).
 // allow_split: the split configurations may be chosen (they keep no
-// invariant sums); need_potential: only configurations with an
-// external-potential variant (the FP32 spin split).
-// need_hop, need_interaction: only configurations with a complex-hopping or a
-// general-interaction variant (FP32 spin split).
+// invariant sums); need_potential, need_hop, need_interaction: only
+// configurations with an external-potential, complex-hopping or
+// general-interaction variant (the FP32 spin split and the FP64 split kernel).
 bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPlan* plan,
                    int force_config = -1, bool allow_split = true, bool need_potential = false,
                    bool need_hop = false, bool need_interaction = false);
