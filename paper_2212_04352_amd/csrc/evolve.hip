@@ -183,12 +183,10 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
         // with the potential variant (spin split)
         const bool pot = inst[k].v_site != nullptr;
         // a general interaction: the stream kernels, or a resident configuration
-        // with the general-interaction variant (the FP32 spin split or the FP64
-        // split kernel; alone)
+        // with the general-interaction variant (alone)
         const bool gint = inst[k].u_mat != nullptr;
         // complex hopping: the stream kernels, or a resident configuration with
-        // the complex-hopping variant (the FP32 spin split or the FP64 split
-        // kernel; alone)
+        // the complex-hopping variant (alone)
         const bool hop = inst[k].hop_w != nullptr;
         const int n_var = (pot ? 1 : 0) + (hop ? 1 : 0) + (gint ? 1 : 0);
         if (n_var > 1 && (want == FTWA_PATH_RESIDENT || force >= 0))
@@ -527,7 +525,10 @@ ftwa_status execute(const Plan& p, const ftwa_instance* inst, char* ws, hipStrea
         if (ip.path != FTWA_PATH_RESIDENT || !inst[k].hop_w) continue;
         DeviceTables tab;
         if ((st = device_tables(inst[k].lat, &tab)) != FTWA_OK) return st;
-        if ((st = hop_table(inst[k].hop_w, tab.nb, tab.dpos, inst[k].lat->N, p.n_steps, p.dtype,
+        // spin split: place order (the partner's diagonal); shared blocks:
+        // site order
+        const int32_t* const order = resident_spins(ip.res.config) == 1 ? tab.dpos : nullptr;
+        if ((st = hop_table(inst[k].hop_w, tab.nb, order, inst[k].lat->N, p.n_steps, p.dtype,
                             ws + ip.off_hop, stream)) != FTWA_OK)
             return st;
     }

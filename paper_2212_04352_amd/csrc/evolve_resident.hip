@@ -271,6 +271,7 @@ struct HopTab {
     int bytes = 0;
     const unsigned char* lds = nullptr;
     uint32_t lds_end = 0;
+    uint32_t mul = 6;  // diagonal offset -> triple offset (6: place x sizeof(T); 3: site x sizeof(C))
 };
 
 // A site's three ratios (24 bytes in FP32, 48 in FP64, at byte offset `off`).
@@ -315,9 +316,10 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
     C col, row;
     if constexpr (HOP) {
         // Ratios of the element's sites: j's for the column sums, i's
-        // (conjugated) for the row sums.  The diagonal offsets are site
-        // places x sizeof(T) and a ratio triple is 3 sizeof(C) = 6 sizeof(T)
-        // (places < 256: a 24-bit product).  Places below Wt.lds_end / sizeof(T)
+        // (conjugated) for the row sums.  A ratio triple is 3 sizeof(C) =
+        // 6 sizeof(T); the diagonal offsets are site places x sizeof(T) (spin
+        // split: Wt.mul = 6) or sites x sizeof(C) (shared blocks: Wt.mul = 3),
+        // < 4096, so the product fits 24 bits.  Offsets below Wt.lds_end
         // come from the stage's copy in LDS, the others from global memory:
         // every lane reads LDS (at place 0 when its site is not there) and
         // only the other lanes then issue the global loads, which overwrite
@@ -325,7 +327,7 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
         const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
             (void*)Wt.p, (short)0, Wt.bytes, 0x00020000);
         auto triple = [&](uint32_t d, C* w) {
-            const uint32_t o = __umul24(d, 6u);
+            const uint32_t o = __umul24(d, Wt.mul);
             const bool in_lds = d < Wt.lds_end;
             const C* l = reinterpret_cast<const C*>(Wt.lds + (in_lds ? o : 0u));
             w[0] = l[0];
@@ -493,9 +495,8 @@ void rk4_resident(ResidentArgs A) {
     using DT = std::conditional_t<S == 1, uint4, ResDesc>;
     static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
     static_assert(!POT || S == 1, "the potential is built into spin-split kernels");
-    static_assert(!HOP || (S == 1 && !POT), "complex hopping: spin-split kernels, no potential");
-    static_assert(!GINT || (S == 1 && !POT && !HOP && std::is_same<T, float>::value),
-                  "general interaction: FP32 spin-split kernels, no potential or complex hopping");
+    static_assert(!HOP || !POT, "complex hopping without a potential");
+    static_assert(!GINT || (!POT && !HOP), "a general interaction alone");
     constexpr int kEvenPad = NTU * UE;
     constexpr int CB = (int)sizeof(C);
     constexpr int TB = (int)sizeof(T);
@@ -561,6 +562,11 @@ void rk4_resident(ResidentArgs A) {
                           : (GINT ? 5 : POT ? 3 : 2) * kDiagCopy)
                    : 0;
         unsigned char* const Yunit = lds_ptr((uint32_t)(kPre + (size_t)unit * S * Pb * CB));
+        // S = 2: after the blocks of all units, D of every unit and spin
+        // (GINT: [unit][spin][site] at the element stride, so that the
+        // descriptors' diagonal offsets index it) or the stage's ratio table
+        // in site order (HOP)
+        unsigned char* const xarea = lds_ptr(((uint32_t)(UNITS * S * Pb * CB) + 15u) & ~15u);
         // GINT: h_k = d_k + 1/2 of the partner's diagonal in site order, copy c
         // (stage parity), zero from N up to the u table's padded row count
         auto dsite = [&](int c) { return reinterpret_cast<T*>(lds_ptr((3 + c) * kDiagCopy)); };
@@ -758,12 +764,15 @@ void rk4_resident(ResidentArgs A) {
                     Aw = uniform_real<T>((T)venv[2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)]);
             }
             // the ratio table of this stage's time (the same half-step samples)
-            const int n_lds = N < kHopLds ? N : kHopLds;
+            // (spin split: the first kHopLds places in LDS; shared blocks: the
+            // whole table, in site order)
+            const int n_lds = S == 2 ? N : (N < kHopLds ? N : kHopLds);
             const HopTab Wt{
                 HOP ? hop_tab + (size_t)(2 * cur_step + (STAGE == 1 ? 0 : STAGE == 4 ? 2 : 1)) *
                                     (size_t)N * 3 * CB
                     : nullptr,
-                N * 3 * CB, lds_ptr(2 * kDiagCopy), (uint32_t)n_lds * TB};
+                N * 3 * CB, S == 2 ? xarea : lds_ptr(2 * kDiagCopy),
+                (uint32_t)n_lds * (S == 2 ? CB : TB), S == 2 ? 3u : 6u};
             if constexpr (HOP) {
                 // a new table at stages 2 and 4 (stage 1 reuses the previous
                 // step's stage-4 table, except at an item's first step); the
@@ -771,8 +780,8 @@ void rk4_resident(ResidentArgs A) {
                 // the old copy
                 if (STAGE == 2 || STAGE == 4 || cur_step == 0) {
                     const T* src = reinterpret_cast<const T*>(Wt.p);
-                    for (int k = tid; k < 6 * n_lds; k += NTU)
-                        reinterpret_cast<T*>(lds_ptr(2 * kDiagCopy))[k] = src[k];
+                    for (int k = tid; k < 6 * n_lds; k += NTU * UNITS)
+                        reinterpret_cast<T*>(const_cast<unsigned char*>(Wt.lds))[k] = src[k];
                     __syncthreads();
                 }
             }
@@ -782,7 +791,7 @@ void rk4_resident(ResidentArgs A) {
             // the diagonal and 1 in place of U
             const unsigned char* Ud = dcur;
             T Uu = Uw;
-            if constexpr (GINT) {
+            if constexpr (GINT && S == 1) {
                 if (tid < N) {
                     // u blocked by four along k ([k/4][i][4], zero rows up to a
                     // multiple of 32): one 16-byte buffer load per lane carries
@@ -822,6 +831,48 @@ void rk4_resident(ResidentArgs A) {
                 Ud = vpart;
                 Uu = (T)1;
             }
+            if constexpr (GINT && S == 2) {
+                // shared blocks: D of both spins of this unit's trajectory,
+                // one ascending chain per (spin, site) on threads t < 2N, from
+                // the partner block's diagonal (slot k holds rho_kk) and u
+                // blocked by four along k (terms k >= N skipped: those slots
+                // hold other elements)
+                for (int cs = t; cs < 2 * N; cs += NTU) {
+                    const int s = cs >= N ? 1 : 0;
+                    const int i = cs - s * N;
+                    const unsigned char* const dsrc = Yunit + (1 - s) * Pb * CB;
+                    const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)utab, (short)0, (int)(umat_rows(N) * N * TB), 0x00020000);
+                    T accD = 0;
+#pragma unroll 2
+                    for (int k0 = 0; k0 < N; k0 += 4) {
+                        T ub[4];
+                        if constexpr (TB == 4) {
+                            const float4 v = __builtin_bit_cast(
+                                float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                            urs, (uint32_t)(i * 16), (k0 / 4) * N * 16, 0));
+                            ub[0] = v.x; ub[1] = v.y; ub[2] = v.z; ub[3] = v.w;
+                        } else {
+                            const double2 v0 = __builtin_bit_cast(
+                                double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                             urs, (uint32_t)(i * 32), (k0 / 4) * N * 32, 0));
+                            const double2 v1 = __builtin_bit_cast(
+                                double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                             urs, (uint32_t)(i * 32 + 16), (k0 / 4) * N * 32, 0));
+                            ub[0] = v0.x; ub[1] = v0.y; ub[2] = v1.x; ub[3] = v1.y;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (k0 + q < N)
+                                accD = fma_rn<T>(ub[q],
+                                                 *reinterpret_cast<const T*>(dsrc + (k0 + q) * CB) +
+                                                     (T)0.5,
+                                                 accD);
+                    }
+                    *reinterpret_cast<T*>(xarea + ((unit * 2 + s) * N + i) * CB) = accD;
+                }
+                __syncthreads();
+            }
             desc = launder(desc);  // descriptors are re-read every phase
             // ---------------- phase 1: even elements (next values held in
             // registers); descriptors are loaded KP slots ahead.
@@ -855,8 +906,15 @@ void rk4_resident(ResidentArgs A) {
                                                                        Uu, own, vpart, Aw, pot_on,
                                                                        Wt);
                     } else {
-                        k = element_rhs_sel<T, false, T1>(u < GE, Yb, Yunit + (1 - s) * Pb * CB, d,
-                                                      tw, Uw, hold[s][u]);
+                        // the U term from the partner block's diagonal, or
+                        // (GINT) from this unit's D of spin s with U = 1
+                        const unsigned char* Yd2 =
+                            GINT ? xarea + (size_t)(unit * 2 + s) * N * CB
+                                 : Yunit + (1 - s) * Pb * CB;
+                        k = element_rhs_sel<T, false, T1, DT, false, HOP>(u < GE, Yb, Yd2, d, tw,
+                                                                          GINT ? (T)1 : Uw,
+                                                                          hold[s][u], nullptr,
+                                                                          (T)0, false, Wt);
                     }
                     hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(hold[s][u]);
@@ -888,16 +946,20 @@ void rk4_resident(ResidentArgs A) {
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
-                    const unsigned char* Yd = S == 1 ? Ud : Yunit + (1 - s) * Pb * CB;
+                    const unsigned char* Yd =
+                        S == 1 ? Ud
+                               : (GINT ? xarea + (size_t)(unit * 2 + s) * N * CB
+                                       : Yunit + (1 - s) * Pb * CB);
+                    const T Us = S == 1 ? Uu : (GINT ? (T)1 : Uw);
                     // stage 1 reads the element's own value from y (the
                     // stage input of a full step is its base point)
                     const C k = STAGE == 1
                         ? element_rhs_sel<T, true, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
-                                                                      S == 1 ? Uu : Uw, y[s][u],
-                                                                      vpart, Aw, pot_on, Wt)
+                                                                      Us, y[s][u], vpart, Aw,
+                                                                      pot_on, Wt)
                         : element_rhs_sel<T, false, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
-                                                                       S == 1 ? Uu : Uw, y[s][u],
-                                                                       vpart, Aw, pot_on, Wt);
+                                                                       Us, y[s][u], vpart, Aw,
+                                                                       pot_on, Wt);
                     *reinterpret_cast<C*>(Yb + own_off(d)) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
@@ -1634,7 +1696,8 @@ constexpr const void* potential_t1_fn() {
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1>
 constexpr const void* hopping_fn() {
-    if constexpr (std::is_same<T, float>::value && S == 1)
+    // spin split (FP32) and shared blocks (FP32 and FP64; t = 1: FP32)
+    if constexpr (std::is_same<T, float>::value || !T1)
         return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, T1, false, true>;
     else
         return nullptr;
@@ -1642,7 +1705,7 @@ constexpr const void* hopping_fn() {
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1>
 constexpr const void* interaction_fn() {
-    if constexpr (std::is_same<T, float>::value && S == 1)
+    if constexpr (std::is_same<T, float>::value || !T1)
         return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, T1, false, false,
                                           true>;
     else
@@ -1795,8 +1858,11 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             // site-ordered copies of the partner's diagonal, or the first
             // kHopLds places of the complex-hopping stage table
             const size_t tb = c.dtype == FTWA_F64 ? 8 : 4;
-            if (need_interaction) lds += 3 * 256 * tb;
-            else if (need_hop) lds += (size_t)kHopLds * 6 * tb;
+            const size_t cbb = 2 * tb;
+            if (need_interaction)
+                lds += c.S == 1 ? 3 * 256 * tb : ((size_t)c.UNITS * 2 * N * cbb + 15) / 16 * 16;
+            else if (need_hop)
+                lds += c.S == 1 ? (size_t)kHopLds * 6 * tb : ((size_t)N * 3 * cbb + 15) / 16 * 16;
             else if (need_potential) lds += 256 * tb;
         }
         if (lds > kMaxLds) continue;
@@ -1931,7 +1997,7 @@ __global__ __launch_bounds__(256) void hop_table_kernel(const double2* __restric
         v.x = (T)a.x;
         v.y = (T)a.y;
     }
-    out[(r * N + dpos[i]) * 3 + n] = v;
+    out[(r * N + (dpos ? dpos[i] : i)) * 3 + n] = v;
 }
 }  // namespace
 

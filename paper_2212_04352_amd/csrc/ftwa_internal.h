@@ -363,7 +363,8 @@ ftwa_status umat_table(const double* u_mat, int N, ftwa_dtype dtype, void* out,
                        hipStream_t stream);
 // The ratio table of the complex-hopping variant from ftwa_instance::hop_w
 // ([2 n_steps + 1][N][3] complex FP64): [2 n_steps + 1][N][3] complex in dtype,
-// row r's site i at place dpos[i], missing neighbours zero (queued on stream).
+// row r's site i at place dpos[i] (at i when dpos is NULL), missing neighbours
+// zero (queued on stream).
 ftwa_status hop_table(const double* hop_w, const int32_t* nb, const int32_t* dpos, int N,
                       int64_t n_steps, ftwa_dtype dtype, void* out, hipStream_t stream);
 int64_t resident_item_traj(int config);      // trajectories per item of the schedule

@@ -159,6 +159,40 @@ def test_split_interaction_matches_oracle_bitwise(ft, orc, kind, a, b, config, t
     assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype,kind,a,b,config,t", [
+    ("f32", "torus", 2, 3, -1, 1.0), ("f64", "torus", 2, 3, -1, 1.0),
+    ("f32", "torus", 3, 9, -1, 1.0), ("f64", "torus", 3, 9, -1, 1.0),
+    ("f32", "torus", 3, 9, 6, 1.0),    # every slot general
+    ("f64", "torus", 3, 9, 2, 1.0),
+    ("f32", "torus", 3, 9, -1, 0.7),   # t != 1: the general-hopping variant
+    ("f32", "hex", 4, 0, -1, 1.0), ("f64", "hex", 4, 0, -1, 1.0),
+])
+def test_shared_block_interaction_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, config, t):
+    """The shared-block tiles' general-interaction variant (both spins of a
+    trajectory in one unit): per stage, threads t < 2N of each unit form D of
+    both spins from the partner block's diagonal and u (blocked by four along
+    k), the elements take D_i - D_j as their U factor."""
+    import torch
+    dt, steps, re = 0.01, 8, 4
+    olat = orc.Lattice(kind, a, b, t)
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = orc.fock_start(olat, "random", 16)
+    M = 11
+    rho0 = orc.sample(olat, n0, 16, M)
+    prob = ft.Problem.allocate(lat, 0.0, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    u = _long_range(olat, 3.3, 16)
+    prob.u_mat = torch.from_numpy(u).cuda()
+    ft.evolve(prob, dt, steps, re, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, precision=dtype, umat=u)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_resident_interaction_next_to_on_site_instances(ft, orc, dtype):
     """One automatic call: a 198-site general-u instance (its own launch
@@ -206,11 +240,6 @@ def test_resident_interaction_graph_replays(ft, orc, dtype):
 def test_paths_that_refuse_a_general_interaction(ft, orc):
     import torch
     olat, lat, rho0, prob, u, _ = _setup(ft, orc, "armchair", 10, 20, 4, "f32", 5)
-    # the shared-block tiles have no general-interaction variant
-    os_, ls, rs, ps, us, _ = _setup(ft, orc, "torus", 2, 3, 8, "f32", 5)
-    with pytest.raises(ft.FtwaError) as e:
-        ft.evolve(ps, 0.01, 2, 1, config=4)
-    assert e.value.status == -4
     # together with a potential: stream only
     prob.v_site = torch.zeros(lat.N, dtype=torch.float64, device="cuda")
     prob.v_env = torch.zeros(5, dtype=torch.float64, device="cuda")

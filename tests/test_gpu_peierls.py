@@ -204,6 +204,40 @@ def test_split_peierls_matches_oracle_bitwise(ft, orc, kind, a, b, config, t):
     assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype,kind,a,b,config,t", [
+    ("f32", "torus", 2, 3, -1, 1.0), ("f64", "torus", 2, 3, -1, 1.0),
+    ("f32", "torus", 3, 9, -1, 1.0), ("f64", "torus", 3, 9, -1, 1.0),
+    ("f32", "torus", 3, 9, 6, 1.0),    # every slot general
+    ("f64", "torus", 3, 9, 2, 1.0),
+    ("f32", "torus", 3, 9, -1, 0.8),   # t != 1: the general-hopping variant
+    ("f32", "hex", 4, 0, -1, 1.0), ("f64", "hex", 4, 0, -1, 1.0),
+])
+def test_shared_block_peierls_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, config, t):
+    """The shared-block tiles' complex-hopping variant: each stage's whole
+    ratio table in LDS in site order, indexed by the descriptors' diagonal
+    offsets; unused slots hold NaN on the caller's side."""
+    import torch
+    dt, steps, re = 0.01, 8, 4
+    olat = orc.Lattice(kind, a, b, t)
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = orc.fock_start(olat, "random", 17)
+    M = 11
+    rho0 = orc.sample(olat, n0, 17, M)
+    prob = ft.Problem.allocate(lat, 3.3, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    fn = _phase_fn(olat.N, 17, dt)
+    w = _table(olat.nbr, olat.deg, fn, 2 * steps + 1)
+    prob.hop_w = torch.from_numpy(_table(lat.nbr, lat.deg, fn, 2 * steps + 1, fill=np.nan)).cuda()
+    ft.evolve(prob, dt, steps, re, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype, hop=w)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_resident_peierls_graph_replays(ft, orc, dtype):
     """The resident variant (FP32: the spin-split tile; FP64: the split
@@ -233,11 +267,6 @@ def test_resident_peierls_graph_replays(ft, orc, dtype):
 def test_paths_that_refuse_complex_hopping(ft, orc):
     import torch
     olat, lat, rho0, prob, w, _ = _setup(ft, orc, "armchair", 10, 20, 4, 3.3, "f32", 5, 2, 0.01)
-    # the shared-block tiles have no complex-hopping variant
-    os_, ls, rs, ps, ws_, _ = _setup(ft, orc, "torus", 2, 3, 8, 3.3, "f32", 5, 2, 0.01)
-    with pytest.raises(ft.FtwaError) as e:
-        ft.evolve(ps, 0.01, 2, 1, config=4)
-    assert e.value.status == -4
     # complex hopping together with a potential: stream only
     prob.v_site = torch.zeros(lat.N, dtype=torch.float64, device="cuda")
     prob.v_env = torch.zeros(5, dtype=torch.float64, device="cuda")
