@@ -459,8 +459,10 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 }
 
 // T1: every instance of the launch has t = 1 (the usual unit of energy).
-// POT (spin split only): entries may carry an external on-site potential;
-// its profile sits in LDS after the partner's diagonal, in the same layout.
+// POT: entries may carry an external on-site potential; its profile sits in
+// LDS in the layout of the diagonal that the descriptors index (spin split:
+// after the partner's diagonal copies; shared blocks: after the blocks, site
+// i at i sizeof(C)).
 // HOP (spin split only): every entry carries complex hopping (ResidentInst::hop:
 // the ratio table hop_table_kernel prepared, read from global memory).
 // GINT (spin split only): every entry carries a general interaction u_ij
@@ -494,7 +496,6 @@ void rk4_resident(ResidentArgs A) {
     // descriptor form: compact for the spin split, wide otherwise
     using DT = std::conditional_t<S == 1, uint4, ResDesc>;
     static_assert(S == 2 || UNITS == 1, "the spin split holds one spin block per workgroup");
-    static_assert(!POT || S == 1, "the potential is built into spin-split kernels");
     static_assert(!HOP || !POT, "complex hopping without a potential");
     static_assert(!GINT || (!POT && !HOP), "a general interaction alone");
     constexpr int kEvenPad = NTU * UE;
@@ -564,8 +565,9 @@ void rk4_resident(ResidentArgs A) {
         unsigned char* const Yunit = lds_ptr((uint32_t)(kPre + (size_t)unit * S * Pb * CB));
         // S = 2: after the blocks of all units, D of every unit and spin
         // (GINT: [unit][spin][site] at the element stride, so that the
-        // descriptors' diagonal offsets index it) or the stage's ratio table
-        // in site order (HOP)
+        // descriptors' diagonal offsets index it), the stage's ratio table in
+        // site order (HOP) or the potential's profile (POT, [site] at the
+        // element stride)
         unsigned char* const xarea = lds_ptr(((uint32_t)(UNITS * S * Pb * CB) + 15u) & ~15u);
         // GINT: h_k = d_k + 1/2 of the partner's diagonal in site order, copy c
         // (stage parity), zero from N up to the u table's padded row count
@@ -642,16 +644,23 @@ void rk4_resident(ResidentArgs A) {
         }
         const int32_t* const dpos = reinterpret_cast<const int32_t*>(uniform64((uint64_t)E.dpos));
         const int qdiag = (S == 1 && tid < N) ? dpos[tid] : 0;  // this thread's polled site
-        // external potential of this entry: its profile after the diagonal
-        // copies (same layout), the envelope read per stage
+        // external potential of this entry: its profile in the diagonal's
+        // layout (spin split: after the diagonal copies; shared blocks: in the
+        // area after the blocks, one value per site at the element stride),
+        // the envelope read per stage
         const double* const venv = POT ? reinterpret_cast<const double*>(uniform64((uint64_t)E.v_env))
                                        : nullptr;
         const bool pot_on = POT && E.v_site != nullptr;
-        unsigned char* const vpart = lds_ptr(2 * kDiagCopy);
+        unsigned char* const vpart = S == 1 ? lds_ptr(2 * kDiagCopy) : xarea;
         if constexpr (POT) {
             const double* const vs = reinterpret_cast<const double*>(uniform64((uint64_t)E.v_site));
-            for (int i = t; i < N; i += NTU)
-                reinterpret_cast<T*>(vpart)[dpos[i]] = pot_on ? (T)vs[i] : (T)0;
+            if constexpr (S == 1) {
+                for (int i = t; i < N; i += NTU)
+                    reinterpret_cast<T*>(vpart)[dpos[i]] = pot_on ? (T)vs[i] : (T)0;
+            } else {
+                for (int i = tid; i < N; i += NTU * UNITS)
+                    *reinterpret_cast<T*>(vpart + (size_t)i * CB) = pot_on ? (T)vs[i] : (T)0;
+            }
         }
         // complex hopping: the prepared ratio tables, [2 n_steps + 1][N][3]
         const unsigned char* const hop_tab =
@@ -911,10 +920,10 @@ void rk4_resident(ResidentArgs A) {
                         const unsigned char* Yd2 =
                             GINT ? xarea + (size_t)(unit * 2 + s) * N * CB
                                  : Yunit + (1 - s) * Pb * CB;
-                        k = element_rhs_sel<T, false, T1, DT, false, HOP>(u < GE, Yb, Yd2, d, tw,
-                                                                          GINT ? (T)1 : Uw,
-                                                                          hold[s][u], nullptr,
-                                                                          (T)0, false, Wt);
+                        k = element_rhs_sel<T, false, T1, DT, POT, HOP>(u < GE, Yb, Yd2, d, tw,
+                                                                        GINT ? (T)1 : Uw,
+                                                                        hold[s][u], vpart, Aw,
+                                                                        pot_on, Wt);
                     }
                     hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(hold[s][u]);
@@ -1678,17 +1687,16 @@ constexpr const void* unit_hop_fn() {
         return nullptr;
 }
 
+// the potential variant: spin split (FP32) and shared blocks (FP32 and FP64;
+// t = 1: FP32)
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
 constexpr const void* potential_fn() {
-    if constexpr (std::is_same<T, float>::value && S == 1)
-        return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false, true>;
-    else
-        return nullptr;
+    return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, false, true>;
 }
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO>
 constexpr const void* potential_t1_fn() {
-    if constexpr (std::is_same<T, float>::value && S == 1)
+    if constexpr (std::is_same<T, float>::value)
         return (const void*)&rk4_resident<T, S, NTU, UNITS, UE, UO, GE, GO, true, true>;
     else
         return nullptr;
@@ -1854,16 +1862,19 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             if ((int64_t)c.NTU * c.GE < tab.n_gen_even || (int64_t)c.NTU * c.GO < tab.n_gen_odd)
                 continue;
             lds = lds_bytes(c, N, P);
-            // the potential's profile, the general interaction's D and two
-            // site-ordered copies of the partner's diagonal, or the first
-            // kHopLds places of the complex-hopping stage table
+            // spin split: the potential's profile, the general interaction's
+            // D and two site-ordered copies of the partner's diagonal, or the
+            // first kHopLds places of the complex-hopping stage table; shared
+            // blocks: D of every unit and spin or the profile (one value per
+            // site at the element stride), or the whole ratio table
             const size_t tb = c.dtype == FTWA_F64 ? 8 : 4;
             const size_t cbb = 2 * tb;
             if (need_interaction)
                 lds += c.S == 1 ? 3 * 256 * tb : ((size_t)c.UNITS * 2 * N * cbb + 15) / 16 * 16;
             else if (need_hop)
                 lds += c.S == 1 ? (size_t)kHopLds * 6 * tb : ((size_t)N * 3 * cbb + 15) / 16 * 16;
-            else if (need_potential) lds += 256 * tb;
+            else if (need_potential)
+                lds += c.S == 1 ? 256 * tb : ((size_t)N * cbb + 15) / 16 * 16;
         }
         if (lds > kMaxLds) continue;
         plan->config = k;

@@ -2,8 +2,9 @@
 term of Eq. (6) for an external potential, Sec. III) through the C ABI: the
 stream kernels against the oracle bitwise (same operation order: a = U(d_i -
 d_j), then a + A(v_i - v_j), A and v rounded once), batches mixing instances
-with and without a potential, trajectory chunks, graph replays, and the paths
-that refuse it."""
+with and without a potential, trajectory chunks, graph replays, the resident
+variants (spin split, shared blocks, split kernel), and the paths that refuse
+it."""
 import numpy as np
 import pytest
 
@@ -66,7 +67,7 @@ def test_potential_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps, 
     olat, lat, rho0, prob, v, cdt = _setup(ft, orc, kind, a, b, M, dtype, 7, profile=profile)
     env = _pulse(steps, dt)
     _attach(prob, v, env)
-    ft.evolve(prob, dt, steps, re)  # automatic path: the stream kernels
+    ft.evolve(prob, dt, steps, re, path="stream")
     y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype,
                                  vsite=v, env=env)
     got = unpack(_host(prob.rho), lat.N)
@@ -131,6 +132,41 @@ def test_resident_launch_mixing_entries_with_and_without_a_potential(ft, orc):
     y2, _, _ = orc.evolve(o2, 2.0, r2, dt, steps, re, precision="f32")
     assert np.array_equal(unpack(_host(p1.rho), l1.N), y1.astype(np.complex64))
     assert np.array_equal(unpack(_host(p2.rho), l2.N), y2.astype(np.complex64))
+
+
+@pytest.mark.parametrize("dtype,kind,a,b,config,t", [
+    ("f32", "torus", 2, 3, -1, 1.0), ("f64", "torus", 2, 3, -1, 1.0),
+    ("f32", "torus", 3, 9, -1, 1.0), ("f64", "torus", 3, 9, -1, 1.0),
+    ("f32", "torus", 3, 9, 6, 1.0),    # every slot general
+    ("f64", "torus", 3, 9, 2, 1.0),
+    ("f32", "torus", 3, 9, -1, 0.8),   # t != 1: the general-hopping variant
+    ("f32", "hex", 4, 0, -1, 1.0), ("f64", "hex", 4, 0, -1, 1.0),
+])
+def test_potential_on_the_shared_block_tiles(ft, orc, dtype, kind, a, b, config, t):
+    """The shared-block tiles' potential variant (the profile in LDS after the
+    blocks, one value per site at the element stride, indexed by the
+    descriptors' diagonal offsets) bitwise equal to the oracle, states and
+    moments."""
+    import torch
+    dt, steps, re = 0.01, 12, 4
+    olat = orc.Lattice(kind, a, b, t)
+    lat = ft.Lattice(kind, a, b, t)
+    n0 = orc.fock_start(olat, "random", 23)
+    rho0 = orc.sample(olat, n0, 23, 13)
+    prob = ft.Problem.allocate(lat, 3.3, 13, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    v = np.random.default_rng(23).uniform(-1, 1, lat.N)
+    env = _pulse(steps, dt, t0=0.04)
+    _attach(prob, v, env)
+    ft.evolve(prob, dt, steps, re, path="resident", config=config)
+    y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype,
+                                 vsite=v, env=env)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
+    assert np.allclose(_host(prob.S2), S2r, rtol=1e-12, atol=1e-12)
 
 
 @pytest.mark.parametrize("kind,a,b,config", [("hex", 5, 0, 19), ("hex", 5, 0, 20), ("hex", 5, 0, 21), ("hex", 5, 0, 22),
@@ -200,7 +236,7 @@ def test_batch_chunks_and_mixed_instances(ft, orc):
     p2.instance = 1
     env = _pulse(steps, dt, A0=0.8, t0=0.05)
     _attach(p1, v1, env)
-    ft.evolve([p1, p2], dt, steps, re, traj_chunk=16)
+    ft.evolve([p1, p2], dt, steps, re, traj_chunk=16, path="stream")
     y1, _, _ = orc.evolve(o1, 2.0, r1, dt, steps, re, vsite=v1, env=env)
     y2, _, _ = orc.evolve(o2, 1.0, r2, dt, steps, re)
     assert np.array_equal(unpack(_host(p1.rho), l1.N), y1)
@@ -209,7 +245,9 @@ def test_batch_chunks_and_mixed_instances(ft, orc):
 
 
 def test_graph_replays_with_a_potential(ft, orc):
-    """A captured run with a potential replayed twice equals two direct runs."""
+    """A captured run with a potential (12 sites: the shared-block tile's
+    variant) replayed twice equals two direct runs; the first replay also
+    equals the oracle."""
     import torch
     dt, steps, re = 0.01, 10, 5
     olat, lat, rho0, prob, v, _ = _setup(ft, orc, "torus", 2, 3, 40, "f32", 13)
@@ -219,12 +257,15 @@ def test_graph_replays_with_a_potential(ft, orc):
     ref.rho.copy_(prob.rho)
     ref.v_site, ref.v_env = prob.v_site, prob.v_env
     g = ft.EvolveGraph([prob], dt, steps, re)
-    for _ in range(2):
+    y_ref, _, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision="f32", vsite=v, env=env)
+    for r in range(2):
         g.launch()
         g.check()
         ft.evolve(ref, dt, steps, re)
         torch.cuda.synchronize()
         assert torch.equal(prob.rho, ref.rho)
+        if r == 0:
+            assert np.array_equal(unpack(_host(prob.rho), lat.N), y_ref.astype(np.complex64))
     g.close()
 
 
@@ -232,10 +273,6 @@ def test_paths_that_refuse_a_potential(ft, orc):
     import torch
     olat, lat, rho0, prob, v, _ = _setup(ft, orc, "torus", 2, 3, 8, "f32", 14)
     _attach(prob, v, _pulse(4, 0.01))
-    with pytest.raises(ft.FtwaError):
-        ft.evolve(prob, 0.01, 4, 2, path="resident")
-    with pytest.raises(ft.FtwaError):
-        ft.evolve(prob, 0.01, 4, 2, config=4)
     w = torch.zeros((2, 2 * lat.N), dtype=torch.float64, device="cuda")
     with pytest.raises(ft.FtwaError):
         ft.adjoint(prob, 0.01, 4, 4, 4, w)

@@ -1,4 +1,4 @@
-"""One automatic resident call mixing every Hamiltonian variant at 198 sites
+"""One resident call mixing every Hamiltonian variant at 198 sites
 (a general interaction, complex hopping, an external potential) with an
 on-site 150-site instance: each instance forms a launch group of its own, with
 its own LDS layout (FP32: the spin-split kernels; FP64: the split kernel), and
@@ -80,6 +80,42 @@ def test_every_variant_in_one_resident_call(ft, orc, dtype):
     pc.v_env = torch.from_numpy(env).cuda()
     # on-site, another size
     od, ld, rd, pd, _ = _problem(ft, orc, "hex", 5, 0, 1.5, 6, dtype, 64, 3)
+
+    ft.evolve([pa, pb, pc, pd], dt, steps, re, path="resident")
+    refs = [
+        orc.evolve(oa, 0.0, ra, dt, steps, re, precision=dtype, umat=u)[0],
+        orc.evolve(ob, 3.3, rb, dt, steps, re, precision=dtype, hop=w)[0],
+        orc.evolve(oc, 2.0, rc, dt, steps, re, precision=dtype, vsite=v, env=env)[0],
+        orc.evolve(od, 1.5, rd, dt, steps, re, precision=dtype)[0],
+    ]
+    for p, lat, y in zip((pa, pb, pc, pd), (la, lb, lc, ld), refs):
+        got = unpack(_host(p.rho), lat.N)
+        assert np.array_equal(got, y.astype(cdt)), np.max(np.abs(got - y))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_every_variant_on_the_shared_block_tiles_in_one_call(ft, orc, dtype):
+    """The same at 54 sites (the 3x9 torus: shared-block tiles, both spin
+    blocks of a trajectory in one workgroup) with an on-site 12-site instance:
+    four launch groups of the shared-block kernel, each equal to the oracle
+    bitwise."""
+    import torch
+    dt, steps, re = 0.01, 8, 4
+    oa, la, ra, pa, cdt = _problem(ft, orc, "torus", 3, 9, 0.0, 7, dtype, 71, 0)
+    idx = np.arange(oa.N)
+    u = 0.4 * np.exp(-np.abs(idx[:, None] - idx[None, :]) / 3.0)
+    np.fill_diagonal(u, 2.5)
+    pa.u_mat = torch.from_numpy(u).cuda()
+    ob, lb, rb, pb, _ = _problem(ft, orc, "torus", 3, 9, 3.3, 9, dtype, 72, 1)
+    w = _ratios(ob, 2 * steps + 1, dt, 0.0)
+    pb.hop_w = torch.from_numpy(_ratios(ob, 2 * steps + 1, dt, np.nan)).cuda()
+    oc, lc, rc, pc, _ = _problem(ft, orc, "torus", 3, 9, 2.0, 5, dtype, 73, 2)
+    v = np.array([(-1.0) ** s for s in oc.sub])
+    tau = np.arange(2 * steps + 1) * dt / 2
+    env = 0.9 * np.sin(7.0 * tau)
+    pc.v_site = torch.from_numpy(v).cuda()
+    pc.v_env = torch.from_numpy(env).cuda()
+    od, ld, rd, pd, _ = _problem(ft, orc, "torus", 2, 3, 1.5, 21, dtype, 74, 3)
 
     ft.evolve([pa, pb, pc, pd], dt, steps, re, path="resident")
     refs = [
