@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--paths", default=None,
                     help="pulse, longrange, peierls: the paths to run (comma list; default "
                          "resident,stream for pulse, stream,auto for the others)")
+    ap.add_argument("--lattice", default="flake198", choices=sorted(VARIANT_LATTICES),
+                    help="pulse, longrange, peierls: the lattice (flake198: the 198-site flake, "
+                         "4096 trajectories by default; torus54: the 3x9 torus, 16384)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a "
                          "known-size reference dispatch for HBM byte counters)")
@@ -574,19 +577,32 @@ def run_thermal(args):
                    "occupations": "uniform on [0.2, 0.8], seeded", "dtype": "f32"}}))
 
 
+# Lattices of the pulse, longrange and peierls workloads: (kind, a, b), the
+# default trajectory count, and a name for the metric.
+VARIANT_LATTICES = {
+    "flake198": (("armchair", 10, 20), 4096, "198-site flake"),
+    "torus54": (("torus", 3, 9), 16384, "54-site torus"),
+}
+
+
+def variant_lattice(ft, args):
+    (kind, a, b), m, name = VARIANT_LATTICES[args.lattice]
+    return ft.Lattice(kind, a, b), args.traj or m, name
+
+
 def run_pulse(args):
     """A time-dependent staggered potential on the 198-site flake (the
     external-potential term of Eq. (6)): V_i(t) = A(t) (+1 on one sublattice,
     -1 on the other), A a Gaussian pulse with a carrier; 4096 trajectories x
-    400 steps, FP32 and FP64 on the spin-split resident kernels (FP64: the
+    400 steps, FP32 and FP64 on the resident kernels (FP32 spin split, FP64
     split kernel) and on the stream kernels, each with and without the
-    potential (the cost of the term)."""
+    potential (the cost of the term).  --lattice torus54: the same on the
+    3x9 torus (16384 trajectories; the shared-block tiles' variant)."""
     import numpy as np
     import torch
     import paper_2212_04352_amd as ft
-    lat = ft.Lattice("armchair", 10, 20)
+    lat, M, lname = variant_lattice(ft, args)
     N = lat.N
-    M = args.traj or 4096
     steps = args.horizon_steps or 400
     dt = 0.005
     tau = np.arange(2 * steps + 1) * dt / 2
@@ -623,9 +639,9 @@ def run_pulse(args):
             log(f"pulse: {dtype} {path} potential={with_pot}: {M * steps / el:.3e} traj-steps/s")
             del p, ws
     print(json.dumps({
-        "metric": "trajectory*RK4-steps/s with a time-dependent staggered potential, 198-site flake",
+        "metric": f"trajectory*RK4-steps/s with a time-dependent staggered potential, {lname}",
         "unit": "trajectory*RK4-steps/s", "rows": rows,
-        "config": {"workload": "flake198_pulse", "trajectories": M, "rk4_steps": steps, "dt": dt,
+        "config": {"workload": f"{args.lattice}_pulse", "trajectories": M, "rk4_steps": steps, "dt": dt,
                    "envelope": "exp(-((t-0.5)/0.2)^2) cos(6t)",
                    "profile": "+1 / -1 by sublattice"}}))
 
@@ -636,12 +652,13 @@ def run_longrange(args):
     tail), FP32 and FP64, 4096 trajectories x 400 steps, on the stream kernels
     and on the automatic path (the general-interaction variants of the FP32
     spin-split and FP64 split resident kernels), next to the on-site run of
-    the same paths."""
+    the same paths.  --lattice torus54: the same on the 3x9 torus (16384
+    trajectories; the shared-block tiles' variant)."""
     import numpy as np
     import torch
     from collections import deque
     import paper_2212_04352_amd as ft
-    lat = ft.Lattice("armchair", 10, 20)
+    lat, M, lname = variant_lattice(ft, args)
     N = lat.N
     dist = np.full((N, N), np.inf)
     for r in range(N):  # breadth-first graph distances
@@ -655,7 +672,6 @@ def run_longrange(args):
                     q.append(y)
     u = 0.5 * np.exp(-dist)
     np.fill_diagonal(u, 3.3)
-    M = args.traj or 4096
     steps = args.horizon_steps or 400
     rows = []
     for dtype in args.dtypes.split(","):
@@ -681,9 +697,9 @@ def run_longrange(args):
                     f"traj-steps/s")
                 del p, ws
     print(json.dumps({
-        "metric": "trajectory*RK4-steps/s with a general density-density interaction, 198-site flake",
+        "metric": f"trajectory*RK4-steps/s with a general density-density interaction, {lname}",
         "unit": "trajectory*RK4-steps/s", "rows": rows,
-        "config": {"workload": "flake198_longrange", "trajectories": M, "rk4_steps": steps,
+        "config": {"workload": f"{args.lattice}_longrange", "trajectories": M, "rk4_steps": steps,
                    "dt": 0.005, "paths": ["stream", "auto"],
                    "interaction": "u_ii = 3.3, u_ij = exp(-graph distance) / 2"}}))
 
@@ -695,12 +711,13 @@ def run_peierls(args):
     tables at half steps; FP32 and FP64, 4096 trajectories x 400 steps, on the
     stream kernels and on the automatic path (the complex-hopping variants of
     the FP32 spin-split and FP64 split resident kernels), next to real
-    hopping on the same paths."""
+    hopping on the same paths.  --lattice torus54: the same on the 3x9 torus
+    (16384 trajectories; the shared-block tiles' variant)."""
     import numpy as np
     import torch
     from collections import deque
     import paper_2212_04352_amd as ft
-    lat = ft.Lattice("armchair", 10, 20)
+    lat, M, lname = variant_lattice(ft, args)
     N = lat.N
     x = np.full(N, -1.0)
     x[0] = 0
@@ -711,7 +728,6 @@ def run_peierls(args):
             if x[b] < 0:
                 x[b] = x[a] + 1
                 q.append(b)
-    M = args.traj or 4096
     steps = args.horizon_steps or 400
     dt = 0.005
     Bh = 0.5 * np.sin(2.0 * 0.5 * dt * np.arange(2 * steps + 1))
@@ -745,9 +761,9 @@ def run_peierls(args):
                 log(f"peierls: {dtype} {path} complex={peierls}: {M * steps / el:.3e} traj-steps/s")
                 del p, ws
     print(json.dumps({
-        "metric": "trajectory*RK4-steps/s with complex time-dependent hopping, 198-site flake",
+        "metric": f"trajectory*RK4-steps/s with complex time-dependent hopping, {lname}",
         "unit": "trajectory*RK4-steps/s", "rows": rows,
-        "config": {"workload": "flake198_peierls", "trajectories": M, "rk4_steps": steps,
+        "config": {"workload": f"{args.lattice}_peierls", "trajectories": M, "rk4_steps": steps,
                    "dt": dt, "paths": ["stream", "auto"], "U": 3.3,
                    "hopping": "t exp(i (x_k - x_i) 0.5 sin(2 tau)), x = graph distance"}}))
 

@@ -176,11 +176,13 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        its first Runge-Kutta stage, v_env[2n+1] in the second and third,
  *        v_env[2n+2] in the fourth.  Arithmetic: a = U (d_i - d_j), then
  *        a = a + A (v_i - v_j), A and v rounded once to the working precision.
- *        Integrated by the spin-split resident kernels (FP32 one workgroup
- *        per spin block, FP64 split over several) where the automatic choice
- *        is one of them, else by the stream kernels (a forced
- *        resident path or configuration without the potential variant gives
- *        FTWA_ENOTSUP); ftwa_adjoint refuses it.
+ *        Integrated by the potential variants of the resident kernels (the
+ *        shared-block tiles holding both spin blocks of a trajectory in one
+ *        workgroup, FP32 and FP64; FP32 one workgroup per spin block; FP64
+ *        split over several) where the automatic choice is one of them, else
+ *        by the stream kernels (a forced resident path or configuration
+ *        without the potential variant gives FTWA_ENOTSUP); ftwa_adjoint
+ *        refuses it.
  *        v_env must hold 2 n_steps + 1 values (not checked: device memory).
  *   u_mat [N][N] FP64 or NULL  a general density-density interaction u_ij
  *        between opposite spins (Eq. (1); symmetric) in place of the on-site
@@ -188,11 +190,11 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        D_i - D_j, D_i = sum_k u_ki (rho_kk,sbar + 1/2), accumulated as
  *        D = fma(u_ki, d_k + 1/2, D) over ascending k in the working precision
  *        (u rounded once).  Integrated by the general-interaction variants
- *        of the FP32 spin-split resident kernels and the FP64 split kernel
- *        where the automatic choice is one of them and the instance has
- *        neither v_site nor hop_w (u, rounded once, is staged by a kernel into
- *        the workspace; each stage forms D in LDS before the elements), else
- *        by the stream kernels (a
+ *        of the resident kernels (shared-block tiles in FP32 and FP64, the
+ *        FP32 spin split, the FP64 split kernel) where the automatic choice
+ *        is one of them and the instance has neither v_site nor hop_w (u,
+ *        rounded once, is staged by a kernel into the workspace; each stage
+ *        forms D in LDS before the elements), else by the stream kernels (a
  *        per-stage kernel forms D for every site and trajectory); a forced
  *        resident path or configuration without the variant, or with v_site
  *        or hop_w, gives FTWA_ENOTSUP.  Invariant monitors (inv: their energy
@@ -211,14 +213,15 @@ ftwa_status ftwa_fock_start(ftwa_lattice lat, ftwa_start kind, uint64_t seed,
  *        (fma(wr, xr, -(wi xi)), fma(wr, xi, wi xr)) with w rounded once to
  *        the working precision, slots summed in ascending order; slots
  *        n >= deg(i) are ignored (any finite or non-finite value).
- *        Integrated by the complex-hopping variants of the FP32 spin-split
- *        resident kernels and the FP64 split kernel where the automatic
- *        choice is one of them and the instance has no v_site (the ratios,
- *        rounded once and with unused slots zeroed, are staged by a kernel
- *        into the workspace; each stage keeps the ratios of up to 152 sites
- *        in LDS in FP32, of all sites in FP64), else by the stream kernels; a forced
- *        resident path or configuration without the
- *        variant, or with v_site, gives FTWA_ENOTSUP.  Invariant monitors
+ *        Integrated by the complex-hopping variants of the resident kernels
+ *        (shared-block tiles in FP32 and FP64, the FP32 spin split, the FP64
+ *        split kernel) where the automatic choice is one of them and the
+ *        instance has no v_site (the ratios, rounded once and with unused
+ *        slots zeroed, are staged by a kernel into the workspace; each stage
+ *        keeps the ratios of up to 152 sites in LDS in the FP32 spin split,
+ *        of all sites in the others), else by the stream kernels; a forced
+ *        resident path or configuration without the variant, or with v_site,
+ *        gives FTWA_ENOTSUP.  Invariant monitors
  *        (FTWA_EINVAL) and ftwa_adjoint (FTWA_ENOTSUP) refuse it.  Combines
  *        with v_site and u_mat on the stream kernels.  hop_w must hold
  *        (2 n_steps + 1) N 3 complex values (not checked: device memory).
