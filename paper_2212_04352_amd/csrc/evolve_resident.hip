@@ -256,7 +256,7 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // POT: an external on-site potential adds A (v_i - v_j) to the U factor (Vd:
 // the profile v in the layout of the diagonal array, Aw: the envelope at the
 // stage time; only when `pot_on`).
-// HOP (spin split): complex hopping j_ik = t w_ik: col = sum_n w_jn x_n over
+// HOP: complex hopping j_ik = t w_ik: col = sum_n w_jn x_n over
 // the column neighbours x_n = rho_ik, row = sum_n conj(w_in) rho_kj, each
 // product as (fma(wr, xr, -(wi xi)), fma(wr, xi, wi xr)), slots summed in
 // order; Wt: this stage's ratio table in global memory, three complex ratios
@@ -306,15 +306,48 @@ __device__ __forceinline__ cplx_t<T> hop_mul(cplx_t<T> w, cplx_t<T> x) {
     return r;
 }
 
-template <typename T, bool OWN_REG, bool GEN, bool T1, bool POT = false, bool HOP = false>
+// The six ratios of an element from a ratio table held whole in LDS (the
+// shared-block tiles): j's triple, then i's, unconjugated.
+template <typename T>
+__device__ __forceinline__ void ratios_lds(const HopTab& Wt, uint32_t di, uint32_t dj,
+                                           cplx_t<T>* w) {
+    const cplx_t<T>* a = reinterpret_cast<const cplx_t<T>*>(Wt.lds + __umul24(dj, Wt.mul));
+    const cplx_t<T>* b = reinterpret_cast<const cplx_t<T>*>(Wt.lds + __umul24(di, Wt.mul));
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+        w[n] = a[n];
+        w[n + 3] = b[n];
+    }
+}
+
+// WPRE (with HOP): the element's six ratios come in `wpre` (ratios_lds), read
+// once for both spin blocks of a shared-block tile, which share them.
+template <typename T, bool OWN_REG, bool GEN, bool T1, bool POT = false, bool HOP = false,
+          bool WPRE = false>
 __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const unsigned char* Yd,
                                                  const Stencil& e, T t, T U, cplx_t<T> own,
                                                  const unsigned char* Vd = nullptr, T Aw = 0,
                                                  bool pot_on = false,
-                                                 HopTab Wt = {}) {
+                                                 HopTab Wt = {}, const cplx_t<T>* wpre = nullptr) {
     using C = cplx_t<T>;
     C col, row;
-    if constexpr (HOP) {
+    if constexpr (HOP && WPRE) {
+        C x[6];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            x[n] = GEN ? lds_at<T>(Yb, e.n[n]) : *reinterpret_cast<const C*>(Yb + e.n[n]);
+            if constexpr (GEN) x[n].y = conj_sign<T>(e.n[n]) * x[n].y;
+        }
+        C p[6];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            C w = wpre[n];
+            if (n >= 3) w.y = -w.y;
+            p[n] = hop_mul<T>(w, x[n]);
+        }
+        col = cadd(cadd(p[0], p[1]), p[2]);
+        row = cadd(cadd(p[3], p[4]), p[5]);
+    } else if constexpr (HOP) {
         // Ratios of the element's sites: j's for the column sums, i's
         // (conjugated) for the row sums.  A ratio triple is 3 sizeof(C) =
         // 6 sizeof(T); the diagonal offsets are site places x sizeof(T) (spin
@@ -396,19 +429,28 @@ __device__ __forceinline__ cplx_t<T> element_rhs(const unsigned char* Yb, const 
 // The element's own slot offset from its descriptor.
 __device__ __forceinline__ uint32_t own_off(const ResDesc& d) { return d.a.w; }
 __device__ __forceinline__ uint32_t own_off(const uint4& w) { return lo16x8(w.w); }
+// Its two diagonal offsets (i's and j's; the wide descriptors of the shared
+// blocks only, where they do not depend on the general form).
+__device__ __forceinline__ uint32_t own_di(const ResDesc& d) { return d.b.w & 0xffffu; }
+__device__ __forceinline__ uint32_t own_dj(const ResDesc& d) { return d.b.w >> 16; }
+__device__ __forceinline__ uint32_t own_di(const uint4&) { return 0; }
+__device__ __forceinline__ uint32_t own_dj(const uint4&) { return 0; }
 
 // The same with the variant chosen by a (compile-time) slot condition.
-template <typename T, bool OWN_REG, bool T1, typename DT, bool POT = false, bool HOP = false>
+template <typename T, bool OWN_REG, bool T1, typename DT, bool POT = false, bool HOP = false,
+          bool WPRE = false>
 __device__ __forceinline__ cplx_t<T> element_rhs_sel(bool gen, const unsigned char* Yb,
                                                      const unsigned char* Yd, const DT& d,
                                                      T t, T U, cplx_t<T> own,
                                                      const unsigned char* Vd = nullptr, T Aw = 0,
                                                      bool pot_on = false,
-                                                     HopTab Wt = {}) {
-    return gen ? element_rhs<T, OWN_REG, true, T1, POT, HOP>(Yb, Yd, decode<true>(d), t, U, own,
-                                                              Vd, Aw, pot_on, Wt)
-               : element_rhs<T, OWN_REG, false, T1, POT, HOP>(Yb, Yd, decode<false>(d), t, U,
-                                                               own, Vd, Aw, pot_on, Wt);
+                                                     HopTab Wt = {},
+                                                     const cplx_t<T>* wpre = nullptr) {
+    return gen ? element_rhs<T, OWN_REG, true, T1, POT, HOP, WPRE>(Yb, Yd, decode<true>(d), t, U,
+                                                                    own, Vd, Aw, pot_on, Wt, wpre)
+               : element_rhs<T, OWN_REG, false, T1, POT, HOP, WPRE>(Yb, Yd, decode<false>(d), t,
+                                                                     U, own, Vd, Aw, pot_on, Wt,
+                                                                     wpre);
 }
 
 // One Runge-Kutta stage update of an element from its slope k:
@@ -902,6 +944,10 @@ void rk4_resident(ResidentArgs A) {
             for (int u = 0; u < UE; ++u) {
                 const DT d = dq[u % KP];
                 if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<DT>(drs, entry_of(u + KP), toff);
+                // shared blocks with complex hopping: the element's ratios,
+                // the same for both spins, read once
+                C wsh[HOP && S == 2 ? 6 : 1];
+                if constexpr (HOP && S == 2) ratios_lds<T>(Wt, own_di(d), own_dj(d), wsh);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
@@ -920,10 +966,9 @@ void rk4_resident(ResidentArgs A) {
                         const unsigned char* Yd2 =
                             GINT ? xarea + (size_t)(unit * 2 + s) * N * CB
                                  : Yunit + (1 - s) * Pb * CB;
-                        k = element_rhs_sel<T, false, T1, DT, POT, HOP>(u < GE, Yb, Yd2, d, tw,
-                                                                        GINT ? (T)1 : Uw,
-                                                                        hold[s][u], vpart, Aw,
-                                                                        pot_on, Wt);
+                        k = element_rhs_sel<T, false, T1, DT, POT, HOP, HOP>(
+                            u < GE, Yb, Yd2, d, tw, GINT ? (T)1 : Uw, hold[s][u], vpart, Aw,
+                            pot_on, Wt, wsh);
                     }
                     hold[s][u] = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(hold[s][u]);
@@ -952,6 +997,8 @@ void rk4_resident(ResidentArgs A) {
             for (int u = UE; u < UE + UO; ++u) {
                 const DT d = dq[u % KP];
                 if (u + KP < UE + UO) dq[u % KP] = slot_desc_buf<DT>(drs, entry_of(u + KP), toff);
+                C wsh[HOP && S == 2 ? 6 : 1];
+                if constexpr (HOP && S == 2) ratios_lds<T>(Wt, own_di(d), own_dj(d), wsh);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     unsigned char* Yb = Yunit + s * Pb * CB;
@@ -962,13 +1009,14 @@ void rk4_resident(ResidentArgs A) {
                     const T Us = S == 1 ? Uu : (GINT ? (T)1 : Uw);
                     // stage 1 reads the element's own value from y (the
                     // stage input of a full step is its base point)
+                    constexpr bool WP = HOP && S == 2;
                     const C k = STAGE == 1
-                        ? element_rhs_sel<T, true, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
-                                                                      Us, y[s][u], vpart, Aw,
-                                                                      pot_on, Wt)
-                        : element_rhs_sel<T, false, T1, DT, POT, HOP>(u - UE < GO, Yb, Yd, d, tw,
-                                                                       Us, y[s][u], vpart, Aw,
-                                                                       pot_on, Wt);
+                        ? element_rhs_sel<T, true, T1, DT, POT, HOP, WP>(u - UE < GO, Yb, Yd, d,
+                                                                          tw, Us, y[s][u], vpart,
+                                                                          Aw, pot_on, Wt, wsh)
+                        : element_rhs_sel<T, false, T1, DT, POT, HOP, WP>(u - UE < GO, Yb, Yd, d,
+                                                                           tw, Us, y[s][u], vpart,
+                                                                           Aw, pot_on, Wt, wsh);
                     *reinterpret_cast<C*>(Yb + own_off(d)) = rk_update<STAGE, T>(c, k, y[s][u], acc[s][u]);
                     pin(acc[s][u]);
                     if constexpr (STAGE == 4) pin(y[s][u]);
