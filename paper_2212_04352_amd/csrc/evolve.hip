@@ -422,6 +422,7 @@ ftwa_status build_table(Plan& p, const ftwa_instance* inst, char* ws) {
                 e.v_env = inst[k].v_env;
                 e.hop = inst[k].hop_w ? ws + ip.off_hop : nullptr;
                 e.umat = inst[k].u_mat ? ws + ip.off_umat : nullptr;
+                e.u_lds = inst[k].u_mat && ip.res.u_lds ? 1 : 0;
                 p.table.push_back(e);
             }
         }

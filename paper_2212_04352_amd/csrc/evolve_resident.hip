@@ -306,6 +306,26 @@ __device__ __forceinline__ cplx_t<T> hop_mul(cplx_t<T> w, cplx_t<T> x) {
     return r;
 }
 
+// Four consecutive values of T from LDS (16-byte aligned): one 16-byte read
+// in FP32, two in FP64.
+template <typename T>
+__device__ __forceinline__ void quad_lds(const unsigned char* p, T* out) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        out[0] = v.x;
+        out[1] = v.y;
+        out[2] = v.z;
+        out[3] = v.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 16);
+        out[0] = a.x;
+        out[1] = a.y;
+        out[2] = b.x;
+        out[3] = b.y;
+    }
+}
+
 // The six ratios of an element from a ratio table held whole in LDS (the
 // shared-block tiles): j's triple, then i's, unconjugated.
 template <typename T>
@@ -611,6 +631,13 @@ void rk4_resident(ResidentArgs A) {
         // site order (HOP) or the potential's profile (POT, [site] at the
         // element stride)
         unsigned char* const xarea = lds_ptr(((uint32_t)(UNITS * S * Pb * CB) + 15u) & ~15u);
+        // S = 2 with a general interaction: then a copy of u in its staged
+        // layout and h = d + 1/2 of every unit's two diagonals in site order
+        // ([unit][spin][k], zero from N up to u's padded row count KU), where
+        // the plan made room for them (E.u_lds)
+        unsigned char* const uarea = xarea + ((UNITS * 2 * N * CB + 15) & ~15);
+        const int KU = umat_rows(N);
+        T* const hsv = reinterpret_cast<T*>(uarea + (size_t)KU * N * TB);
         // GINT: h_k = d_k + 1/2 of the partner's diagonal in site order, copy c
         // (stage parity), zero from N up to the u table's padded row count
         auto dsite = [&](int c) { return reinterpret_cast<T*>(lds_ptr((3 + c) * kDiagCopy)); };
@@ -709,6 +736,24 @@ void rk4_resident(ResidentArgs A) {
             HOP ? reinterpret_cast<const unsigned char*>(uniform64((uint64_t)E.hop)) : nullptr;
         // general interaction: u in T, [k][i]; D goes where the profile would
         const T* const utab = GINT ? reinterpret_cast<const T*>(uniform64((uint64_t)E.umat)) : nullptr;
+        const bool u_lds = GINT && S == 2 && E.u_lds != 0;
+        if constexpr (GINT && S == 2) {
+            // u into LDS once per item (16-byte words; visible after the
+            // barrier that follows the first record)
+            if (u_lds) {
+                const uint4* src = reinterpret_cast<const uint4*>(utab);
+                const int n16 = KU * N * TB / 16;
+                for (int k = tid; k < n16; k += NTU * UNITS)
+                    reinterpret_cast<uint4*>(uarea)[k] = src[k];
+                // h of the first stage input (slot 0 of thread t < N holds
+                // site t's diagonal)
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    if (t < N) hsv[(unit * 2 + s) * KU + t] = y[s][0].x + (T)0.5;
+                    for (int k = N + t; k < KU; k += NTU) hsv[(unit * 2 + s) * KU + k] = (T)0;
+                }
+            }
+        }
         if constexpr (S == 1) {
             // the partner's diagonal in two alternating copies (stage parity),
             // reals in sublattice-major order; the current one from HBM
@@ -892,9 +937,34 @@ void rk4_resident(ResidentArgs A) {
                     const int s = cs >= N ? 1 : 0;
                     const int i = cs - s * N;
                     const unsigned char* const dsrc = Yunit + (1 - s) * Pb * CB;
+                    T accD = 0;
+                    if (u_lds) {
+                        // u and h from their LDS copies, four terms per 16
+                        // (FP32) or 32 (FP64) bytes (u: a wave's lanes on
+                        // consecutive sites; h: the same address on every
+                        // lane), in batches of 16 terms whose reads are all
+                        // issued before the chain uses them; up to the padded
+                        // row count KU the terms k >= N are fma(0, 0, D) =
+                        // D + 0 (exact: the chain starts at +0 and never holds
+                        // -0)
+                        const unsigned char* const ui = uarea + (size_t)i * 4 * TB;
+                        const T* const hp = hsv + (unit * 2 + (1 - s)) * KU;
+                        for (int k0 = 0; k0 < KU; k0 += 16) {
+                            T ub[16], hb[16];
+#pragma unroll
+                            for (int b = 0; b < 4; ++b) {
+                                quad_lds<T>(ui + (size_t)(k0 / 4 + b) * N * 4 * TB, ub + 4 * b);
+                                quad_lds<T>(reinterpret_cast<const unsigned char*>(hp + k0 + 4 * b),
+                                            hb + 4 * b);
+                            }
+#pragma unroll
+                            for (int q = 0; q < 16; ++q) accD = fma_rn<T>(ub[q], hb[q], accD);
+                        }
+                        *reinterpret_cast<T*>(xarea + ((unit * 2 + s) * N + i) * CB) = accD;
+                        continue;
+                    }
                     const __amdgpu_buffer_rsrc_t urs = __builtin_amdgcn_make_buffer_rsrc(
                         (void*)utab, (short)0, (int)(umat_rows(N) * N * TB), 0x00020000);
-                    T accD = 0;
 #pragma unroll 2
                     for (int k0 = 0; k0 < N; k0 += 4) {
                         T ub[4];
@@ -1061,6 +1131,14 @@ void rk4_resident(ResidentArgs A) {
 #pragma unroll
                     for (int s = 0; s < S; ++s)
                         *reinterpret_cast<C*>(Yunit + s * Pb * CB + own) = hold[s][u];
+                }
+                if constexpr (GINT) {
+                    // the next stage input's h (read after the barrier)
+                    if (u_lds && t < N) {
+#pragma unroll
+                        for (int s = 0; s < S; ++s)
+                            hsv[(unit * 2 + s) * KU + t] = hold[s][0].x + (T)0.5;
+                    }
                 }
             }
             __syncthreads();
@@ -1883,6 +1961,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         const int k = kPreference[o];
         if (force_config >= 0 && k != force_config) continue;
         const Config& c = kConfigs[k];
+        bool u_lds = false;
         if (c.dtype != dtype) continue;
         if (!c.auto_pick && force_config < 0) continue;
         if (need_potential && !c.fn_pot) continue;
@@ -1917,8 +1996,18 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
             // site at the element stride), or the whole ratio table
             const size_t tb = c.dtype == FTWA_F64 ? 8 : 4;
             const size_t cbb = 2 * tb;
-            if (need_interaction)
+            if (need_interaction) {
                 lds += c.S == 1 ? 3 * 256 * tb : ((size_t)c.UNITS * 2 * N * cbb + 15) / 16 * 16;
+                // shared blocks: a copy of u and the units' h = d + 1/2 in
+                // site order beside D where they fit (read there by the
+                // per-stage chains instead of from L2 and the blocks)
+                const size_t ub = (size_t)umat_rows(N) * N * tb +  // multiples of 16
+                                  (size_t)c.UNITS * 2 * umat_rows(N) * tb;
+                if (c.S == 2 && lds + ub <= kMaxLds) {
+                    lds += ub;
+                    u_lds = true;
+                }
+            }
             else if (need_hop)
                 lds += c.S == 1 ? (size_t)kHopLds * 6 * tb : ((size_t)N * 3 * cbb + 15) / 16 * 16;
             else if (need_potential)
@@ -1933,6 +2022,7 @@ bool resident_plan(int N, ftwa_dtype dtype, const DeviceTables& tab, ResidentPla
         plan->odd_slots = (int64_t)c.NTU * c.UO;
         plan->lds = lds;
         plan->bnd_entry = (int64_t)c.NTU * c.UB;
+        plan->u_lds = u_lds;
         return true;
     }
     return false;

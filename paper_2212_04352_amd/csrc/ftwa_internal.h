@@ -290,6 +290,8 @@ struct ResidentPlan {
     int64_t odd_slots = 0;
     int64_t bnd_entry = 0;   // split configurations: first boundary entry of the even class
     size_t lds = 0;
+    bool u_lds = false;      // shared blocks with a general interaction: lds includes a copy
+                             // of u (umat_table's layout), which the kernel reads there
 };
 // One entry of a resident launch's table: a window of trajectories of one
 // instance (device memory, read by the kernel).
@@ -317,6 +319,7 @@ struct ResidentInst {
     const double* v_env;   // its envelope at half steps from the start of the run
     const void* hop;       // NULL or the complex-hopping ratio table (hop_table)
     const void* umat;      // NULL or the general interaction in the working precision (umat_table)
+    int u_lds;             // nonzero: the shared-block kernel copies umat into LDS per item
 };
 struct ResidentLaunch {
     int config;
