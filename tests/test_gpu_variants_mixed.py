@@ -127,3 +127,49 @@ def test_every_variant_on_the_shared_block_tiles_in_one_call(ft, orc, dtype):
     for p, lat, y in zip((pa, pb, pc, pd), (la, lb, lc, ld), refs):
         got = unpack(_host(p.rho), lat.N)
         assert np.array_equal(got, y.astype(cdt)), np.max(np.abs(got - y))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_shared_block_variants_in_graph_replays(ft, orc, dtype):
+    """The three shared-block variants at 54 sites captured in one graph (the
+    staging kernels of u and of the ratio tables inside it) and replayed
+    twice: every replay equals a direct run, the first also the oracle."""
+    import torch
+    dt, steps, re = 0.01, 6, 3
+    oa, la, ra, pa, cdt = _problem(ft, orc, "torus", 3, 9, 0.0, 6, dtype, 81, 0)
+    idx = np.arange(oa.N)
+    u = 0.4 * np.exp(-np.abs(idx[:, None] - idx[None, :]) / 3.0)
+    np.fill_diagonal(u, 2.5)
+    pa.u_mat = torch.from_numpy(u).cuda()
+    ob, lb, rb, pb, _ = _problem(ft, orc, "torus", 3, 9, 3.3, 5, dtype, 82, 1)
+    w = _ratios(ob, 2 * steps + 1, dt, 0.0)
+    pb.hop_w = torch.from_numpy(_ratios(ob, 2 * steps + 1, dt, np.nan)).cuda()
+    oc, lc, rc, pc, _ = _problem(ft, orc, "torus", 3, 9, 2.0, 7, dtype, 83, 2)
+    v = np.array([(-1.0) ** s for s in oc.sub])
+    env = 0.9 * np.sin(7.0 * np.arange(2 * steps + 1) * dt / 2)
+    pc.v_site = torch.from_numpy(v).cuda()
+    pc.v_env = torch.from_numpy(env).cuda()
+    probs = [pa, pb, pc]
+    refs = []
+    for p in probs:
+        q = ft.Problem.allocate(p.lat, p.U, p.n_traj, p.n0.cpu().numpy(), dtype,
+                                instance=p.instance)
+        q.rho.copy_(p.rho)
+        q.u_mat, q.hop_w, q.v_site, q.v_env = p.u_mat, p.hop_w, p.v_site, p.v_env
+        refs.append(q)
+    ys = [
+        orc.evolve(oa, 0.0, ra, dt, steps, re, precision=dtype, umat=u)[0],
+        orc.evolve(ob, 3.3, rb, dt, steps, re, precision=dtype, hop=w)[0],
+        orc.evolve(oc, 2.0, rc, dt, steps, re, precision=dtype, vsite=v, env=env)[0],
+    ]
+    g = ft.EvolveGraph(probs, dt, steps, re, path="resident")
+    for r in range(2):
+        g.launch()
+        g.check()
+        ft.evolve(refs, dt, steps, re, path="resident")
+        torch.cuda.synchronize()
+        for p, q, lat, y in zip(probs, refs, (la, lb, lc), ys):
+            assert torch.equal(p.rho, q.rho)
+            if r == 0:
+                assert np.array_equal(unpack(_host(p.rho), lat.N), y.astype(cdt))
+    g.close()
