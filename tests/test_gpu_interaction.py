@@ -58,10 +58,11 @@ def _setup(ft, orc, kind, a, b, M, dtype, seed):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("kind,a,b,M,steps", [("torus", 2, 3, 70, 50), ("hex", 2, 0, 33, 30),
                                               ("armchair", 10, 20, 5, 8)])
-def test_interaction_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps):
+@pytest.mark.parametrize("path", ["stream", "auto"])
+def test_interaction_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps, path):
     dt, re = 0.01, 5
     olat, lat, rho0, prob, u, cdt = _setup(ft, orc, kind, a, b, M, dtype, 3)
-    ft.evolve(prob, dt, steps, re)
+    ft.evolve(prob, dt, steps, re, path=path)  # auto: resident variants where they fit
     y_ref, X_ref, _ = orc.evolve(olat, 0.0, rho0, dt, steps, re, precision=dtype, umat=u)
     got = unpack(_host(prob.rho), lat.N)
     assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))

@@ -75,10 +75,11 @@ def _setup(ft, orc, kind, a, b, M, U, dtype, seed, steps, dt):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("kind,a,b,M,steps", [("torus", 2, 3, 70, 40), ("hex", 2, 0, 33, 30),
                                               ("armchair", 10, 20, 5, 6)])
-def test_peierls_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps):
+@pytest.mark.parametrize("path", ["stream", "auto"])
+def test_peierls_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps, path):
     dt, re = 0.01, 5
     olat, lat, rho0, prob, w, cdt = _setup(ft, orc, kind, a, b, M, 3.3, dtype, 4, steps, dt)
-    ft.evolve(prob, dt, steps, re)
+    ft.evolve(prob, dt, steps, re, path=path)  # auto: resident variants where they fit
     y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype, hop=w)
     got = unpack(_host(prob.rho), lat.N)
     assert np.all(np.isfinite(got))

@@ -62,12 +62,13 @@ def _attach(prob, v, env):
     ("hex", 2, 0, 33, 40, "random"),        # degree-2 edge sites
     ("armchair", 10, 20, 5, 12, "random"),  # 198 sites
 ])
-def test_potential_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps, profile):
+@pytest.mark.parametrize("path", ["stream", "auto"])
+def test_potential_matches_oracle_bitwise(ft, orc, dtype, kind, a, b, M, steps, profile, path):
     dt, re = 0.01, 4
     olat, lat, rho0, prob, v, cdt = _setup(ft, orc, kind, a, b, M, dtype, 7, profile=profile)
     env = _pulse(steps, dt)
     _attach(prob, v, env)
-    ft.evolve(prob, dt, steps, re, path="stream")
+    ft.evolve(prob, dt, steps, re, path=path)  # auto: resident variants where they fit
     y_ref, X_ref, _ = orc.evolve(olat, 3.3, rho0, dt, steps, re, precision=dtype,
                                  vsite=v, env=env)
     got = unpack(_host(prob.rho), lat.N)
