@@ -180,7 +180,7 @@ ftwa_status plan_evolve(const ftwa_instance* inst, int n_inst, double dt, int64_
             }
         }
         // an external potential: the stream kernels, or a resident configuration
-        // with the potential variant (spin split)
+        // with the potential variant
         const bool pot = inst[k].v_site != nullptr;
         // a general interaction: the stream kernels, or a resident configuration
         // with the general-interaction variant (alone)

@@ -259,13 +259,14 @@ __device__ __forceinline__ cplx_t<T> lds_at(const unsigned char* base, uint32_t 
 // HOP: complex hopping j_ik = t w_ik: col = sum_n w_jn x_n over
 // the column neighbours x_n = rho_ik, row = sum_n conj(w_in) rho_kj, each
 // product as (fma(wr, xr, -(wi xi)), fma(wr, xi, wi xr)), slots summed in
-// order; Wt: this stage's ratio table in global memory, three complex ratios
-// per site at the site's place in the diagonal array (zero for a missing
-// neighbour), so that the diagonal offsets of the descriptor index it.
-// The ratio table of one stage: base and size in bytes (read through a
-// buffer resource: 32-bit offsets, its own wait counter), and its copy of the
-// first places in LDS (`lds`; places below lds_end / 4, lds_end in diagonal
-// offset units, are read there).
+// order; Wt: this stage's ratio table, three complex ratios per site at the
+// site's position in the diagonal array that the descriptors index (spin
+// split: its place; shared blocks: the site), zero for a missing neighbour.
+// The ratio table of one stage: base and size in bytes in global memory (read
+// through a buffer resource: 32-bit offsets, its own wait counter), and its
+// copy in LDS (`lds`): the triples whose diagonal offset is below lds_end
+// (spin split: the first kHopLds places; otherwise the whole table) are read
+// there.
 struct HopTab {
     const unsigned char* p = nullptr;
     int bytes = 0;
@@ -525,13 +526,18 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 // LDS in the layout of the diagonal that the descriptors index (spin split:
 // after the partner's diagonal copies; shared blocks: after the blocks, site
 // i at i sizeof(C)).
-// HOP (spin split only): every entry carries complex hopping (ResidentInst::hop:
-// the ratio table hop_table_kernel prepared, read from global memory).
-// GINT (spin split only): every entry carries a general interaction u_ij
-// (ResidentInst::umat, u rounded to T, [k][i]): each stage starts with
-// D_i = sum_k u_ki (d_k + 1/2) over the partner's diagonal, one ascending
-// fused chain per site, into LDS after the diagonal copies (in their
-// layout), and the U factor of an element is D_i - D_j (U = 1 exactly).
+// HOP: every entry carries complex hopping (ResidentInst::hop: the ratio
+// table hop_table_kernel prepared; spin split: each stage's first kHopLds
+// places copied into LDS, the rest read from global memory; shared blocks:
+// the whole stage table in LDS, an element's ratios read once for both
+// spins).
+// GINT: every entry carries a general interaction u_ij (ResidentInst::umat,
+// u rounded to T, blocked by four along k: [k/4][i][4]): each stage starts
+// with D_i = sum_k u_ki (d_k + 1/2) over the partner's diagonal, one
+// ascending fused chain per site (and spin, shared blocks), into LDS (spin
+// split: after the diagonal copies, in their layout; shared blocks: after
+// the blocks, at the element stride), and the U factor of an element is
+// D_i - D_j (U = 1 exactly).
 // Places whose complex-hopping ratios (three FP32 complex numbers, 24 bytes)
 // a stage keeps in LDS: the most that fit beside a 198-site spin block (its
 // elements, the two diagonal copies and the record sums leave 3,712 bytes of
@@ -734,7 +740,8 @@ void rk4_resident(ResidentArgs A) {
         // complex hopping: the prepared ratio tables, [2 n_steps + 1][N][3]
         const unsigned char* const hop_tab =
             HOP ? reinterpret_cast<const unsigned char*>(uniform64((uint64_t)E.hop)) : nullptr;
-        // general interaction: u in T, [k][i]; D goes where the profile would
+        // general interaction: u in T, blocked [k/4][i][4] (spin split: D goes
+        // where the profile would)
         const T* const utab = GINT ? reinterpret_cast<const T*>(uniform64((uint64_t)E.umat)) : nullptr;
         const bool u_lds = GINT && S == 2 && E.u_lds != 0;
         if constexpr (GINT && S == 2) {
@@ -943,13 +950,13 @@ void rk4_resident(ResidentArgs A) {
                         // (FP32) or 32 (FP64) bytes (u: a wave's lanes on
                         // consecutive sites; h: the same address on every
                         // lane), in batches of 16 terms whose reads are all
-                        // issued before the chain uses them; up to the padded
-                        // row count KU the terms k >= N are fma(0, 0, D) =
+                        // issued before the chain uses them; up to N rounded
+                        // up to 16 (<= KU) the terms k >= N are fma(0, 0, D) =
                         // D + 0 (exact: the chain starts at +0 and never holds
                         // -0)
                         const unsigned char* const ui = uarea + (size_t)i * 4 * TB;
                         const T* const hp = hsv + (unit * 2 + (1 - s)) * KU;
-                        for (int k0 = 0; k0 < KU; k0 += 16) {
+                        for (int k0 = 0; k0 < N; k0 += 16) {
                             T ub[16], hb[16];
 #pragma unroll
                             for (int b = 0; b < 4; ++b) {
