@@ -88,7 +88,8 @@ def parse():
                          "resident,stream for pulse, stream,auto for the others)")
     ap.add_argument("--lattice", default="flake198", choices=sorted(VARIANT_LATTICES),
                     help="pulse, longrange, peierls: the lattice (flake198: the 198-site flake, "
-                         "4096 trajectories by default; torus54: the 3x9 torus, 16384)")
+                         "4096 trajectories by default; torus54: the 3x9 torus, 16384; torus12: "
+                         "the 2x3 torus, 65536)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a "
                          "known-size reference dispatch for HBM byte counters)")
@@ -582,6 +583,7 @@ def run_thermal(args):
 VARIANT_LATTICES = {
     "flake198": (("armchair", 10, 20), 4096, "198-site flake"),
     "torus54": (("torus", 3, 9), 16384, "54-site torus"),
+    "torus12": (("torus", 2, 3), 65536, "12-site torus"),
 }
 
 

@@ -548,17 +548,19 @@ constexpr int kHopLds = 152;
 // 16 units of 64 threads (lattices up to 15 sites) holds little state per
 // thread: at 64 registers two 1024-thread workgroups share a CU (8 waves per
 // SIMD instead of 4; 10 % faster at 12 sites with eight scratch accesses per
-// lane and RK4 step).  Every other tile keeps the register file for its state
-// (the same hint spills FP64 and larger tiles and makes them 2-5x slower).
-template <typename T, int S, int NTU, int UNITS>
+// lane and RK4 step).  Its Hamiltonian variants (VAR) spill two to three times
+// as much there and keep four waves.  Every other tile keeps the register
+// file for its state (the same hint spills FP64 and larger tiles and makes
+// them 2-5x slower).
+template <typename T, int S, int NTU, int UNITS, bool VAR>
 constexpr int resident_min_waves() {
-    return std::is_same<T, float>::value && S == 2 && NTU == 64 && UNITS == 16 ? 8 : 1;
+    return std::is_same<T, float>::value && S == 2 && NTU == 64 && UNITS == 16 && !VAR ? 8 : 1;
 }
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1,
           bool POT = false, bool HOP = false, bool GINT = false>
 __global__ __launch_bounds__(NTU * UNITS)
-__attribute__((amdgpu_waves_per_eu(resident_min_waves<T, S, NTU, UNITS>(), 8)))
+__attribute__((amdgpu_waves_per_eu(resident_min_waves<T, S, NTU, UNITS, POT || HOP || GINT>(), 8)))
 void rk4_resident(ResidentArgs A) {
     using C = cplx_t<T>;
     // descriptor form: compact for the spin split, wide otherwise
