@@ -120,3 +120,59 @@ def test_largest_lattice(ft, orc, dtype):
     """A 9 x 14 torus, 252 sites (the library takes up to 255): the stream path
     in both precisions (no resident tile holds a block this large)."""
     _run(ft, orc, ("torus", 9, 14), dtype, "auto", M=3, steps=3, re=1)
+
+
+@pytest.mark.parametrize("variant", ["potential", "interaction", "hopping"])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("spec", [CHAIN7, COMB], ids=["chain7", "comb"])
+def test_variants_on_irregular_graphs(ft, orc, spec, dtype, variant):
+    """The shared-block tiles' Hamiltonian variants on graphs with degree-1
+    sites (unused ratio slots, NaN on the device side) and far fewer sites
+    than the interaction table's padded rows, bitwise equal to the oracle."""
+    import torch
+    dt, steps, re = 0.01, 16, 4
+    lat, olat = _lattices(ft, orc, spec)
+    N = olat.N
+    rng = np.random.default_rng(12)
+    sub = np.array(spec[3], dtype=float)
+    n0 = np.array([1.0 - sub, sub])  # Neel-like start (odd site counts)
+    M = 19
+    rho0 = orc.sample(olat, n0, 12, M)
+    U = 0.0 if variant == "interaction" else 2.7
+    prob = ft.Problem.allocate(lat, U, M, n0, dtype)
+    cdt = np.complex128 if dtype == "f64" else np.complex64
+    prob.rho.copy_(torch.from_numpy(pack(rho0.astype(cdt))))
+    if variant == "potential":
+        v = rng.uniform(-1, 1, N)
+        env = 1.2 * np.cos(3.0 * np.arange(2 * steps + 1) * dt / 2)
+        prob.v_site = torch.from_numpy(v).cuda()
+        prob.v_env = torch.from_numpy(env).cuda()
+        kw = dict(vsite=v, env=env)
+    elif variant == "interaction":
+        idx = np.arange(N)
+        u = 0.6 * np.exp(-np.abs(idx[:, None] - idx[None, :]))
+        np.fill_diagonal(u, 2.9)
+        prob.u_mat = torch.from_numpy(u).cuda()
+        kw = dict(umat=u)
+    else:
+        th = rng.uniform(-np.pi, np.pi, (N, N))
+
+        def table(nbr, deg, fill):
+            w = np.full((2 * steps + 1, N, 3), fill, dtype=np.complex128)
+            for i in range(N):
+                for n in range(int(deg[i])):
+                    k = int(nbr[i][n])
+                    a, b = (i, k) if i < k else (k, i)
+                    for h in range(2 * steps + 1):
+                        z = np.exp(1j * (th[a, b] + 0.3 * h * dt))
+                        w[h, i, n] = z if i < k else np.conj(z)
+            return w
+
+        prob.hop_w = torch.from_numpy(table(lat.nbr, lat.deg, np.nan)).cuda()
+        kw = dict(hop=table(olat.nbr, olat.deg, 0.0))
+    ft.evolve(prob, dt, steps, re, path="resident")
+    y_ref, X_ref, _ = orc.evolve(olat, U, rho0, dt, steps, re, precision=dtype, **kw)
+    got = unpack(_host(prob.rho), lat.N)
+    assert np.array_equal(got, y_ref.astype(cdt)), np.max(np.abs(got - y_ref))
+    S1r, S2r = orc.moments(X_ref)
+    assert np.allclose(_host(prob.S1), S1r, rtol=1e-12, atol=1e-12)
