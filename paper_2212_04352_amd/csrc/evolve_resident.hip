@@ -544,17 +544,17 @@ __device__ __forceinline__ unsigned char* lds_ptr(uint32_t a) {
 // the 160 KB); the table's later places are read from global memory.
 constexpr int kHopLds = 152;
 
-// Minimum waves per SIMD the compiler must leave room for.  The FP32 tile of
-// 16 units of 64 threads (lattices up to 15 sites) holds little state per
-// thread: at 64 registers two 1024-thread workgroups share a CU (8 waves per
-// SIMD instead of 4; 10 % faster at 12 sites with eight scratch accesses per
-// lane and RK4 step).  Its Hamiltonian variants (VAR) spill two to three times
+// Minimum waves per SIMD the compiler must leave room for.  The FP32 tiles of
+// units of 64 threads (lattices up to 15 sites) hold little state per
+// thread: at 64 registers eight waves share a SIMD instead of four (with 16
+// units: 10 % faster at 12 sites with eight scratch accesses per lane and
+// RK4 step).  Its Hamiltonian variants (VAR) spill two to three times
 // as much there and keep four waves.  Every other tile keeps the register
 // file for its state (the same hint spills FP64 and larger tiles and makes
 // them 2-5x slower).
 template <typename T, int S, int NTU, int UNITS, bool VAR>
 constexpr int resident_min_waves() {
-    return std::is_same<T, float>::value && S == 2 && NTU == 64 && UNITS == 16 && !VAR ? 8 : 1;
+    return std::is_same<T, float>::value && S == 2 && NTU == 64 && !VAR ? 8 : 1;
 }
 
 template <typename T, int S, int NTU, int UNITS, int UE, int UO, int GE, int GO, bool T1,
@@ -1920,12 +1920,32 @@ const Config kConfigs[] = {
     // registers per thread (the wider tiles spill in FP64)
     FTWA_RES_CFG(double, FTWA_F64, 2, 384, 2, 2, 2, 1, 1),
     FTWA_RES_CFG(double, FTWA_F64, 2, 384, 2, 2, 2, 2, 2),
+    // fewer units per workgroup: the per-stage barriers span fewer waves and
+    // more workgroups share a CU, so one workgroup's barrier wait overlaps
+    // the others' work (a single-wave workgroup's barrier is nearly free):
+    // 12 sites FP32 6.1e8 -> 1.06e9 (64 x 1), 24 sites 1.6e8 -> 2.5e8
+    // (128 x 1), 54 sites 4.7e7 -> 5.9e7 (256 x 1); FP64 12 sites 4.3e8 ->
+    // 5.8e8, 24 sites 7.9e7 -> 1.26e8 (FP64 384 x 1 is slower than 384 x 2)
+    FTWA_RES_CFG(double, FTWA_F64, 2, 64, 8, 1, 1, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 64, 8, 1, 1, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 64, 4, 1, 1, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 64, 4, 1, 1, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 64, 2, 1, 1, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 64, 2, 1, 1, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 64, 1, 1, 1, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 64, 1, 1, 1, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 128, 1, 2, 2, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 128, 1, 2, 2, 1, 1),
+    FTWA_RES_CFG(double, FTWA_F64, 2, 384, 1, 2, 2, 1, 1),
+    FTWA_RES_CFG(float, FTWA_F32, 2, 256, 1, 3, 3, 1, 1),
 };
 
-// Order of preference of the first-fit choice (a tile with fewer general
-// slots before the same tile with more; indices are those of kConfigs).
-const int kPreference[] = {0, 13, 1, 23, 24, 14, 2, 15, 3, 4, 16, 5, 17, 6, 18, 7, 8, 9, 10, 11,
-                           12, 22, 19, 20, 21};
+// Order of preference of the first-fit choice (of tiles with the same slots,
+// fewer units per workgroup first, then fewer general slots; indices are
+// those of kConfigs).
+const int kPreference[] = {31, 29, 27, 25, 0, 33, 13, 1, 23, 24, 35, 14, 2, 15, 3,
+                           32, 30, 28, 26, 4, 34, 16, 5, 36, 17, 6, 18, 7,
+                           8, 9, 10, 11, 12, 22, 19, 20, 21};
 static_assert(sizeof(kPreference) == sizeof(kConfigs) / sizeof(kConfigs[0]) * sizeof(int),
               "every configuration has a place in the preference order");
 

@@ -182,11 +182,23 @@ def test_errors_are_reported(ft):
 
 # ----------------------------------------------------------------- resident path
 @pytest.mark.parametrize("dtype,kind,a,b,U,M,steps,config,t", [
-    ("f64", "torus", 2, 3, 3.3, 130, 200, -1, 1.0),    # 16 trajectories per workgroup, ragged
+    ("f64", "torus", 2, 3, 3.3, 130, 200, -1, 1.0),    # one 64-thread unit per workgroup
     ("f32", "torus", 2, 3, 3.3, 130, 200, -1, 1.0),
+    ("f64", "torus", 2, 3, 3.3, 130, 200, 0, 1.0),     # 16 trajectories per workgroup, ragged
+    ("f32", "torus", 2, 3, 3.3, 130, 200, 4, 1.0),
+    ("f64", "torus", 2, 3, 3.3, 130, 40, 25, 1.0),     # 8, 4 and 2 units per workgroup
+    ("f32", "torus", 2, 3, 3.3, 130, 40, 26, 1.0),
+    ("f64", "torus", 2, 3, 3.3, 130, 40, 27, 1.0),
+    ("f32", "torus", 2, 3, 3.3, 130, 40, 28, 1.0),
+    ("f64", "torus", 2, 3, 3.3, 130, 40, 29, 1.0),
+    ("f32", "torus", 2, 3, 3.3, 130, 40, 30, 1.0),
+    ("f64", "hex", 2, 0, 1.7, 33, 40, 1, 1.0),         # 128 x 8 tiles, ragged
+    ("f32", "hex", 2, 0, 1.7, 33, 40, 5, 1.0),
+    ("f64", "torus", 3, 9, 3.3, 70, 60, 35, 1.0),      # 384 x 1 (FP64), 256 x 4 (FP32)
+    ("f32", "torus", 3, 9, 3.3, 70, 60, 17, 1.0),
     ("f64", "hex", 2, 0, 1.7, 33, 40, -1, 1.0),        # degree-2 edge sites
     ("f32", "hex", 2, 0, 1.7, 33, 40, -1, 1.0),
-    ("f64", "torus", 3, 9, 3.3, 70, 60, -1, 1.0),      # 54 sites, 3 trajectories per workgroup
+    ("f64", "torus", 3, 9, 3.3, 70, 60, -1, 1.0),      # 54 sites
     ("f32", "torus", 3, 9, 3.3, 70, 60, -1, 1.0),
     ("f64", "hex", 4, 0, 2.0, 10, 20, -1, 1.0),        # 96 sites, one trajectory per workgroup
     ("f32", "hex", 4, 0, 2.0, 10, 20, -1, 1.0),
