@@ -673,6 +673,21 @@ ftwa_status evolve_stored(const ftwa_instance& in, double dt, int64_t n_steps, i
     std::memset(&tune, 0, sizeof(tune));
     tune.path = FTWA_PATH_RESIDENT;
     tune.resident_config = -1;
+    // These runs store the whole state at every record, so the shared-block
+    // tiles with several trajectories per workgroup come first (their stores
+    // of neighbouring trajectories share cache lines; the single-unit tiles
+    // that ordinary runs prefer took the 54-site checkpoint run from 0.24 to
+    // 0.38 s); otherwise the usual first fit (spin split, split kernel).
+    static const int kStoredPreference[] = {0, 13, 1, 23, 24, 14, 2, 15, 3,
+                                            4, 16, 5, 17, 6, 18, 7};
+    const DeviceTables& tab = host_tables(in.lat);
+    for (int c : kStoredPreference) {
+        ResidentPlan rp;
+        if (resident_plan(in.lat->N, dtype, tab, &rp, c, in.inv == nullptr)) {
+            tune.resident_config = c;
+            break;
+        }
+    }
     Plan plan;
     ftwa_status st = plan_evolve(&in, 1, dt, n_steps, record_every, dtype, &tune, &plan);
     if (st != FTWA_OK) return st;
